@@ -1,0 +1,348 @@
+"""Packed homomorphic convolution layers (test infrastructure; see package doc).
+
+DensePack (Section 3.2, Fig. 1, Table I): the input tensor X[h][w][c] is laid
+out in the slots of one ciphertext at slot c*H*W + h*W + w (channel slowest,
+then rows; zeros elsewhere).  A tensor with more than N/2 values is split by
+channel blocks over M ciphertexts.  Each output value (o, i, j) is one
+homomorphic dot product: the filter, zero-padded to the input size, is placed
+at the patch anchor a = (s*i - pad)*W + (s*j - pad), multiplied slot-wise with
+the input (MulPC), and all slots are summed by R = log2(N/2) rotate-and-add
+steps (Rot, AddCC).  The shifted filter is an exact slot rotation (Galois
+permutation, rotation right by a) of one base filter plaintext per output
+channel and border class; a border class is the set of filter taps that fall
+inside the image, so the client never pads.  The result of each dot product
+is left replicated in every slot, one ciphertext per output value.
+
+Scale rule: a plaintext multiply that is followed by a rescale dropping q_l is
+encoded at scale q_l * target / current, so the rescale lands exactly on the
+target.  The rescale happens after the rotate-and-sum.
+
+FFConv (Section 4, Eq. 2; DP-HI2C-CP of Section 4.2 and Table IX): W1 (d x d,
+O'_c filters) runs under DensePack; the O'_c*S replicated results are gathered
+into one ConvPack ciphertext per channel by multiplying each with a one-hot
+mask moved to slot p = i*O_w + j (the DP->CP transition of Table III with
+d = 1, written with masks instead of rotations because the DensePack outputs
+are replicated); W2 (1 x 1) is then a ConvPack layer (Table II): output
+channel o is sum_c round(W2[c,o] * 2^k) * G_c with exact integer scalars.
+One rescale follows, so the factorized layer has depth 2.
+
+CP->DP combine (Table III, CP-HI2C-DP): channel ciphertexts holding S values
+at slots 0..S-1 are rotated right by (o mod B)*S and summed into dense
+ciphertexts of B channels each.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import scheme
+from .encoding import encode, round_half_away
+from .ring import automorph_ntt, galois_for_rotation
+
+
+@dataclass(frozen=True)
+class ConvGeom:
+    h: int
+    w: int
+    c_in: int
+    d: int
+    stride: int = 1
+    pad: int = 0
+
+    @property
+    def out_h(self) -> int:
+        return (self.h + 2 * self.pad - self.d) // self.stride + 1
+
+    @property
+    def out_w(self) -> int:
+        return (self.w + 2 * self.pad - self.d) // self.stride + 1
+
+    @property
+    def spatial(self) -> int:
+        return self.out_h * self.out_w
+
+    def channels_per_ct(self, slots: int) -> int:
+        per = slots // (self.h * self.w)
+        assert per >= 1, "one channel plane must fit in the slots"
+        return min(per, self.c_in)
+
+    def n_cts(self, slots: int) -> int:
+        return math.ceil(self.c_in / self.channels_per_ct(slots))
+
+    def tap_range(self, pos: int, size: int):
+        """Valid filter taps [lo, hi) along one axis for output coordinate pos."""
+        start = self.stride * pos - self.pad
+        return max(0, -start), min(self.d, size - start)
+
+    def border_classes(self):
+        """(row_ranges, col_ranges, class_of_output[i][j]).
+
+        Row (column) ranges are numbered in order of first appearance as the
+        output row (column) index increases; class = row_class * n_cols + col_class.
+        """
+        rows, row_id = [], []
+        for i in range(self.out_h):
+            r = self.tap_range(i, self.h)
+            if r not in rows:
+                rows.append(r)
+            row_id.append(rows.index(r))
+        cols, col_id = [], []
+        for j in range(self.out_w):
+            c = self.tap_range(j, self.w)
+            if c not in cols:
+                cols.append(c)
+            col_id.append(cols.index(c))
+        cls = [[row_id[i] * len(cols) + col_id[j] for j in range(self.out_w)] for i in range(self.out_h)]
+        return rows, cols, cls
+
+    def anchor(self, i: int, j: int) -> int:
+        return (self.stride * i - self.pad) * self.w + (self.stride * j - self.pad)
+
+
+@dataclass
+class Counts:
+    mulpc: int = 0
+    addcc: int = 0
+    rot: int = 0
+    rescale: int = 0
+    square: int = 0
+    scalar_mul: int = 0
+    extra: dict = field(default_factory=dict)
+
+    def merge(self, other: "Counts") -> "Counts":
+        return Counts(
+            self.mulpc + other.mulpc, self.addcc + other.addcc, self.rot + other.rot,
+            self.rescale + other.rescale, self.square + other.square,
+            self.scalar_mul + other.scalar_mul,
+        )
+
+
+# ---- DensePack ---------------------------------------------------------------
+
+def densepack_slots(x: np.ndarray, geom: ConvGeom, slots: int) -> list[np.ndarray]:
+    """Slot vectors (one per input ciphertext) of X[h][w][c]: slot c*H*W + h*W + w."""
+    per = geom.channels_per_ct(slots)
+    out = []
+    for m in range(geom.n_cts(slots)):
+        v = np.zeros(slots)
+        for cl in range(per):
+            c = m * per + cl
+            if c >= geom.c_in:
+                break
+            v[cl * geom.h * geom.w: (cl + 1) * geom.h * geom.w] = x[:, :, c].reshape(-1)
+        out.append(v)
+    return out
+
+
+def base_filter_slots(weights: np.ndarray, geom: ConvGeom, slots: int, o: int, cls: int, m: int) -> np.ndarray:
+    """Slot vector of the base filter for output channel o, border class cls, input ct m."""
+    rows, cols, _ = geom.border_classes()
+    (kh_lo, kh_hi) = rows[cls // len(cols)]
+    (kw_lo, kw_hi) = cols[cls % len(cols)]
+    per = geom.channels_per_ct(slots)
+    v = np.zeros(slots)
+    for cl in range(per):
+        c = m * per + cl
+        if c >= geom.c_in:
+            break
+        for kh in range(kh_lo, kh_hi):
+            for kw in range(kw_lo, kw_hi):
+                v[cl * geom.h * geom.w + kh * geom.w + kw] = weights[kh, kw, c, o]
+    return v
+
+
+def densepack_pt_scale(params, level: int, in_scale: float, target_scale: float) -> float:
+    return params.q[level - 1] * target_scale / in_scale
+
+
+def densepack_base_filters(params, weights, geom: ConvGeom, level: int, pt_scale: float) -> np.ndarray:
+    """Encoded base filters, uint64 array [O_c][classes][M][level][N] (NTT domain)."""
+    rows, cols, _ = geom.border_classes()
+    n_cls = len(rows) * len(cols)
+    m_cts = geom.n_cts(params.slots)
+    o_c = weights.shape[3]
+    out = np.empty((o_c, n_cls, m_cts, level, params.n), dtype=np.uint64)
+    for o in range(o_c):
+        for b in range(n_cls):
+            for m in range(m_cts):
+                out[o, b, m] = encode(base_filter_slots(weights, geom, params.slots, o, b, m), params, level, pt_scale)
+    return out
+
+
+def rotate_and_sum(params, keys, t: scheme.Ciphertext, r_steps: int, counts: Counts) -> scheme.Ciphertext:
+    """t <- t + Rot(t, 2^j) for j < r_steps (all slots end up holding the total)."""
+    for j in range(r_steps):
+        t = scheme.add(params, t, scheme.rotate(params, keys, t, 1 << j))
+        counts.rot += int(np.prod(t.c.shape[:-3], dtype=np.int64))
+        counts.addcc += int(np.prod(t.c.shape[:-3], dtype=np.int64))
+    return t
+
+
+def output_list(geom: ConvGeom, o_c: int):
+    """All (o, i, j) in output order index = o*S + i*O_w + j."""
+    return [(o, i, j) for o in range(o_c) for i in range(geom.out_h) for j in range(geom.out_w)]
+
+
+def conv_densepack(params, keys, x: scheme.Ciphertext, geom: ConvGeom, base_filters: np.ndarray,
+                   pt_scale: float, outputs=None, r_steps: int | None = None, counts: Counts | None = None):
+    """DensePack conv (Table I): returns (ciphertexts of the requested outputs, rescaled)."""
+    counts = counts if counts is not None else Counts()
+    o_c = base_filters.shape[0]
+    outputs = output_list(geom, o_c) if outputs is None else outputs
+    r_steps = int(math.log2(params.slots)) if r_steps is None else r_steps
+    _, _, cls = geom.border_classes()
+    xc = x.c if x.c.ndim == 4 else x.c[None]  # (M, 2, level, N)
+    m_cts = xc.shape[0]
+    level = xc.shape[-2]
+    acc = np.empty((len(outputs), 2, level, params.n), dtype=np.uint64)
+    for idx, (o, i, j) in enumerate(outputs):
+        g = galois_for_rotation(-geom.anchor(i, j), params.n)
+        term = None
+        for m in range(m_cts):
+            f = automorph_ntt(base_filters[o, cls[i][j], m, :level], g)
+            prod = scheme.mul_plain(params, scheme.Ciphertext(xc[m], x.scale), f, pt_scale)
+            counts.mulpc += 1
+            if term is None:
+                term = prod
+            else:
+                term = scheme.add(params, term, prod)
+                counts.addcc += 1
+        acc[idx] = term.c
+    t = scheme.Ciphertext(acc, x.scale * pt_scale)
+    t = rotate_and_sum(params, keys, t, r_steps, counts)
+    t = scheme.rescale(params, t)
+    counts.rescale += len(outputs)
+    return t, counts
+
+
+# ---- DP -> CP gather and the 1x1 ConvPack -------------------------------------
+
+def gather_mask_scale(params, level: int, y_scale: float, target_scale: float, k_bits: int) -> float:
+    return params.q[level - 1] * target_scale / (y_scale * 2.0**k_bits)
+
+
+def encode_onehot(params, level: int, scale: float) -> np.ndarray:
+    z = np.zeros(params.slots)
+    z[0] = 1.0
+    return encode(z, params, level, scale)
+
+
+def w2_integers(w2: np.ndarray, k_bits: int) -> np.ndarray:
+    """round-half-away(W2 * 2^k) as int64 (the exact integer scalars of the 1x1 conv)."""
+    return round_half_away(np.asarray(w2, dtype=np.float64) * 2.0**k_bits).astype(np.int64)
+
+
+def gather_convpack(params, y: scheme.Ciphertext, spatial: int, w2: np.ndarray, k_bits: int,
+                    mask_pt: np.ndarray, mask_scale: float, counts: Counts | None = None):
+    """y: (r*S) replicated DensePack outputs, index c*S + p.  Returns O_c ConvPack cts (rescaled)."""
+    counts = counts if counts is not None else Counts()
+    r, o_c = w2.shape
+    level = y.level
+    gathered = []
+    for c in range(r):
+        acc = None
+        for p in range(spatial):
+            e = automorph_ntt(mask_pt[:level], galois_for_rotation(-p, params.n))
+            prod = scheme.mul_plain(params, scheme.Ciphertext(y.c[c * spatial + p], y.scale), e, mask_scale)
+            counts.mulpc += 1
+            if acc is None:
+                acc = prod
+            else:
+                acc = scheme.add(params, acc, prod)
+                counts.addcc += 1
+        gathered.append(acc)
+    wint = w2_integers(w2, k_bits)
+    outs = []
+    for o in range(o_c):
+        z = None
+        for c in range(r):
+            term = scheme.mul_int(params, gathered[c], int(wint[c, o]))
+            counts.scalar_mul += 1
+            if z is None:
+                z = term
+            else:
+                z = scheme.add(params, z, term)
+                counts.addcc += 1
+        outs.append(z.c)
+    z = scheme.Ciphertext(np.stack(outs), gathered[0].scale * 2.0**k_bits)
+    z = scheme.rescale(params, z)
+    counts.rescale += o_c
+    return z, counts
+
+
+def convpack(params, cts: scheme.Ciphertext, w: np.ndarray, target_scale: float,
+             counts: Counts | None = None):
+    """Standalone ConvPack layer (Table II): K input cts, weights (K, O_c) as integers.
+
+    Each weight is round-half-away(w * D_w) with D_w = q_l * target / input scale,
+    so the rescale that follows lands on `target_scale`.
+    """
+    counts = counts if counts is not None else Counts()
+    k_in, o_c = w.shape
+    level = cts.level
+    dw = params.q[level - 1] * target_scale / cts.scale
+    wint = round_half_away(np.asarray(w, np.float64) * dw)
+    outs = []
+    for o in range(o_c):
+        z = None
+        for k in range(k_in):
+            term = scheme.mul_int(params, scheme.Ciphertext(cts.c[k], cts.scale), int(wint[k, o]))
+            counts.mulpc += 1
+            if z is None:
+                z = term
+            else:
+                z = scheme.add(params, z, term)
+                counts.addcc += 1
+        outs.append(z.c)
+    z = scheme.Ciphertext(np.stack(outs), cts.scale * dw)
+    z = scheme.rescale(params, z)
+    counts.rescale += o_c
+    return z, counts
+
+
+def square_rescale(params, keys, x: scheme.Ciphertext, counts: Counts | None = None):
+    counts = counts if counts is not None else Counts()
+    y = scheme.rescale(params, scheme.square(params, keys, x))
+    n = int(np.prod(x.c.shape[:-3], dtype=np.int64))
+    counts.square += n
+    counts.rescale += n
+    return y, counts
+
+
+def pre_square_target(params, level_after_rescale: int, scale: float) -> float:
+    """Scale to aim for before a square so that square + rescale returns to `scale`."""
+    return math.sqrt(params.q[level_after_rescale - 1] * scale)
+
+
+def combine_cp_to_dp(params, keys, z: scheme.Ciphertext, spatial: int, per_dense: int,
+                     counts: Counts | None = None):
+    """CP->DP: dense_m = sum_{o in block m} Rot(Z_o, -(o mod B)*S)."""
+    counts = counts if counts is not None else Counts()
+    o_c = z.c.shape[0]
+    dense = []
+    for m in range(math.ceil(o_c / per_dense)):
+        acc = None
+        for o in range(m * per_dense, min(o_c, (m + 1) * per_dense)):
+            zo = scheme.Ciphertext(z.c[o], z.scale)
+            shift = (o % per_dense) * spatial
+            if shift:
+                zo = scheme.rotate(params, keys, zo, -shift)
+                counts.rot += 1
+            if acc is None:
+                acc = zo
+            else:
+                acc = scheme.add(params, acc, zo)
+                counts.addcc += 1
+        dense.append(acc.c)
+    return scheme.Ciphertext(np.stack(dense), z.scale), counts
+
+
+def combine_offsets(o_c: int, spatial: int, per_dense: int) -> list[int]:
+    """Rotation amounts the combine step needs keys for (left rotations)."""
+    return sorted({-(o % per_dense) * spatial for o in range(o_c) if o % per_dense})
+
+
+def rotate_and_sum_steps(params) -> list[int]:
+    return [1 << j for j in range(int(math.log2(params.slots)))]

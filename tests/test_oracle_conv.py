@@ -1,0 +1,188 @@
+"""Pins for the FP64 reference, the packed HE conv layers of the oracle and the count model.
+
+* conv2d (Eq. 1, im2col + one matrix product) equals a direct six-loop
+  convolution; W1 followed by the 1x1 W2 equals the conv with W1 W2 (Eq. 2 is
+  an exact identity at full rank); the truncated SVD residual equals the tail
+  of the spectrum computed from eigenvalues of W^T W (Eckart-Young-Mirsky).
+* The HE layers decrypt to the FP64 reference within 1e-3 absolute: an
+  all-ones rotate-and-sum gives N/2 in every slot; a single-tap filter returns
+  the shifted input; DensePack with padding (several border classes) and with
+  the input split over several ciphertexts; gather + 1x1 ConvPack with an
+  identity W2 returns the gathered channels; the full FFConv layer with x^2;
+  the CP->DP combine lays channels out exactly as DensePack does.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import conv as C
+from oracle import encoding as E
+from oracle import params as P
+from oracle import reference as R
+from oracle import scheme as S
+from oracle import workloads as Wk
+
+W = "unit"
+
+
+def direct_conv(x, w, stride, pad):
+    h, wd, c = x.shape
+    d, _, _, o = w.shape
+    oh = (h + 2 * pad - d) // stride + 1
+    ow = (wd + 2 * pad - d) // stride + 1
+    out = np.zeros((oh, ow, o))
+    for i in range(oh):
+        for j in range(ow):
+            for oc in range(o):
+                s = 0.0
+                for kh in range(d):
+                    for kw in range(d):
+                        for ch in range(c):
+                            y, xx = stride * i - pad + kh, stride * j - pad + kw
+                            if 0 <= y < h and 0 <= xx < wd:
+                                s += x[y, xx, ch] * w[kh, kw, ch, oc]
+                out[i, j, oc] = s
+    return out
+
+
+@pytest.mark.parametrize("shape,d,stride,pad", [((7, 6, 2), 3, 1, 1), ((9, 9, 1), 5, 2, 0), ((8, 8, 3), 3, 2, 1)])
+def test_conv2d_matches_direct(shape, d, stride, pad):
+    rng = np.random.default_rng(1)
+    x = rng.random(shape)
+    w = rng.normal(0, 0.1, (d, d, shape[2], 4))
+    assert np.abs(R.conv2d(x, w, stride, pad) - direct_conv(x, w, stride, pad)).max() < 1e-12
+
+
+def test_factorisation_identities():
+    rng = np.random.default_rng(2)
+    x = rng.random((8, 8, 3))
+    w1 = rng.normal(0, 0.1, (3, 3, 3, 2))
+    w2 = rng.normal(0, 0.1, (2, 5))
+    lhs = R.ffconv_reference(x, w1, w2, 1, 1)
+    rhs = R.conv2d(x, R.compose_factors(w1, w2), 1, 1)
+    assert np.abs(lhs - rhs).max() < 1e-12
+    wm = rng.normal(0, 1, (27, 6))
+    ev = np.sort(np.linalg.eigvalsh(wm.T @ wm))[::-1]
+    for r in (1, 3, 5):
+        a, b = R.truncated_svd_factors(wm, r)
+        assert abs(np.linalg.norm(wm - a @ b) ** 2 - ev[r:].sum()) < 1e-8
+        for _ in range(5):  # no random rank-r factorisation does better
+            u = rng.normal(size=(27, r))
+            v = np.linalg.lstsq(u, wm, rcond=None)[0]
+            assert np.linalg.norm(wm - u @ v) >= np.linalg.norm(wm - a @ b) - 1e-9
+
+
+def _ctx(n, rotations, relin=False, levels=3, scale=2.0**25):
+    p = P.Params(n, (30,) * levels, 36, scale)
+    return p, Wk.make_context(p, W, rotations=rotations, relin=relin)
+
+
+def test_rotate_and_sum_of_ones():
+    p, ctx = _ctx(256, C.rotate_and_sum_steps(P.Params(256, (30,), 36, 1.0)))
+    ct = Wk.encrypt_slots(ctx, np.ones(p.slots), 3, p.scale, W, 0)
+    out = C.rotate_and_sum(p, ctx, ct, int(math.log2(p.slots)), C.Counts())
+    assert np.abs(ctx.decrypt(out) - p.slots).max() < 1e-3
+
+
+def _run_densepack(p, ctx, x, w, geom, level, outputs=None):
+    cts = [Wk.encrypt_slots(ctx, v, level, p.scale, W, m) for m, v in enumerate(C.densepack_slots(x, geom, p.slots))]
+    xin = S.Ciphertext(np.stack([c.c for c in cts]), p.scale)
+    pts = C.densepack_pt_scale(p, level, p.scale, p.scale)
+    bf = C.densepack_base_filters(p, w, geom, level, pts)
+    return C.conv_densepack(p, ctx, xin, geom, bf, pts, outputs=outputs)
+
+
+def test_single_tap_filter_shifts_input():
+    p, ctx = _ctx(256, C.rotate_and_sum_steps(P.Params(256, (30,), 36, 1.0)))
+    geom = C.ConvGeom(6, 6, 2, 3, 1, 1)
+    x = synth.image(W, (6, 6, 2))
+    w = np.zeros((3, 3, 2, 1))
+    w[2, 0, 1, 0] = 1.0  # picks x[i+1][j-1][1]
+    y, cnt = _run_densepack(p, ctx, x, w, geom, 3)
+    for idx, (o, i, j) in enumerate(C.output_list(geom, 1)):
+        want = x[i + 1, j - 1, 1] if (i + 1 < 6 and j - 1 >= 0) else 0.0
+        got = ctx.decrypt(S.Ciphertext(y.c[idx], y.scale))
+        assert abs(got[0] - want) < 1e-3 and abs(got[77] - want) < 1e-3
+    assert cnt.rot == 36 * 7 and cnt.mulpc == 36
+
+
+@pytest.mark.parametrize("shape,d,stride,pad,o_c,n", [
+    ((6, 6, 3), 3, 1, 1, 2, 256),   # one ciphertext, 9 border classes
+    ((4, 4, 8), 3, 1, 1, 2, 128),   # 128 values over 64 slots: two input ciphertexts
+    ((7, 7, 1), 3, 2, 0, 3, 128),   # stride 2, no padding, one class
+])
+def test_densepack_matches_fp64(shape, d, stride, pad, o_c, n):
+    p, ctx = _ctx(n, C.rotate_and_sum_steps(P.Params(n, (30,), 36, 1.0)))
+    geom = C.ConvGeom(shape[0], shape[1], shape[2], d, stride, pad)
+    x = synth.image(W, shape)
+    w = synth.weights(W, 7, (d, d, shape[2], o_c), 0.1)
+    y, cnt = _run_densepack(p, ctx, x, w, geom, 3)
+    ref = R.conv2d(x, w, stride, pad)
+    for idx, (o, i, j) in enumerate(C.output_list(geom, o_c)):
+        got = ctx.decrypt(S.Ciphertext(y.c[idx], y.scale))
+        assert np.abs(got - ref[i, j, o]).max() < 1e-3
+    m = geom.n_cts(p.slots)
+    assert cnt.mulpc == geom.spatial * o_c * m
+    assert cnt.rot == geom.spatial * o_c * int(math.log2(p.slots))
+
+
+def _ffconv(p, ctx, geom, x, w1, w2, square, k_bits=12):
+    level = p.max_level
+    ct = Wk.encrypt_slots(ctx, C.densepack_slots(x, geom, p.slots)[0], level, p.scale, W, 0)
+    pts = C.densepack_pt_scale(p, level, p.scale, p.scale)
+    bf = C.densepack_base_filters(p, w1, geom, level, pts)
+    y, cnt = C.conv_densepack(p, ctx, ct, geom, bf, pts)
+    target = C.pre_square_target(p, level - 2, p.scale) if square else p.scale
+    ms = C.gather_mask_scale(p, y.level, y.scale, target, k_bits)
+    mask = C.encode_onehot(p, y.level, ms)
+    z, cnt = C.gather_convpack(p, y, geom.spatial, w2, k_bits, mask, ms, cnt)
+    if square:
+        z, cnt = C.square_rescale(p, ctx, z, cnt)
+    return z, cnt
+
+
+def test_gather_identity_w2_returns_channels():
+    p, ctx = _ctx(256, C.rotate_and_sum_steps(P.Params(256, (30,), 36, 1.0)), levels=3)
+    geom = C.ConvGeom(5, 5, 1, 3, 1, 0)
+    x = synth.image(W, (5, 5, 1))
+    w1 = synth.weights(W, 8, (3, 3, 1, 2), 0.3)
+    z, _ = _ffconv(p, ctx, geom, x, w1, np.eye(2), square=False)
+    y = R.conv2d(x, w1, 1, 0)
+    for c in range(2):
+        got = ctx.decrypt(S.Ciphertext(z.c[c], z.scale))
+        assert np.abs(got[: geom.spatial] - y[:, :, c].reshape(-1)).max() < 1e-3
+        assert np.abs(got[geom.spatial:]).max() < 1e-3  # zeros outside the S compact slots
+
+
+def test_ffconv_with_square_matches_fp64():
+    p, ctx = _ctx(512, C.rotate_and_sum_steps(P.Params(512, (30,), 36, 1.0)), relin=True, levels=4)
+    geom = C.ConvGeom(8, 8, 2, 3, 1, 1)
+    x = synth.image(W, (8, 8, 2))
+    w1 = synth.weights(W, 9, (3, 3, 2, 2), 0.3)
+    w2 = synth.weights(W, 10, (2, 3), 0.5)
+    z, cnt = _ffconv(p, ctx, geom, x, w1, w2, square=True)
+    ref = R.ffconv_reference(x, w1, w2, 1, 1, square=True)
+    assert z.level == 1 and abs(z.scale / p.scale - 1) < 1e-9
+    for o in range(3):
+        got = ctx.decrypt(S.Ciphertext(z.c[o], z.scale))
+        assert np.abs(got[: geom.spatial] - ref[:, :, o].reshape(-1)).max() < 1e-3
+    assert cnt.rot == 64 * 2 * 8 and cnt.scalar_mul == 6 and cnt.square == 3
+
+
+def test_combine_cp_to_dp_layout():
+    n = 256
+    geom_next = C.ConvGeom(4, 4, 3, 1)
+    p = P.Params(n, (30, 30), 36, 2.0**25)
+    offsets = C.combine_offsets(3, 16, 8)
+    ctx = Wk.make_context(p, W, rotations=offsets)
+    vals = synth.message(W, 48)
+    chans = [Wk.encrypt_slots(ctx, np.concatenate([vals[16 * o: 16 * o + 16], np.zeros(p.slots - 16)]), 2, p.scale, W, o)
+             for o in range(3)]
+    z = S.Ciphertext(np.stack([c.c for c in chans]), p.scale)
+    dense, cnt = C.combine_cp_to_dp(p, ctx, z, 16, 8)
+    tensor = vals.reshape(3, 4, 4).transpose(1, 2, 0)  # [h][w][c]
+    want = C.densepack_slots(tensor, geom_next, p.slots)[0]
+    assert np.abs(ctx.decrypt(S.Ciphertext(dense.c[0], dense.scale)) - want).max() < 1e-4
+    assert cnt.rot == 2
