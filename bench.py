@@ -1,0 +1,261 @@
+#!/usr/bin/env python3
+"""Encrypted conv-layer latency and rotations/s on one MI355X: FFConv vs plain.
+
+Workload (the 28x28 MNIST-shaped layer, synthetic): a 28x28x1 image with
+pixels uniform in [0, 1), client-encrypted under DensePack in one ciphertext
+at N = 8192 (4 x 30-bit primes + a 40-bit special prime, scale 2^25).
+  * FFConv layer (the step that is timed): 5x5 stride-2 low-rank conv 1 -> 2
+    channels under DensePack (288 dot products, 12 rotate-and-add steps each),
+    the DP->CP gather and a 1x1 conv 2 -> 5 under ConvPack, then x^2 and
+    rescale -- one ffconv_layer call;
+  * plain comparator: the 5x5 stride-2 conv 1 -> 5 with the composed weights
+    W1 W2 under DensePack (720 dot products), then x^2 and rescale.
+Weights are N(0, 0.1^2).  Inputs, keys and plaintext weights are resident in
+HBM before the timed region.  One step = one FFConv layer on one encrypted
+image; `value` is executed rotations per second of the timed steps.
+
+Extra fields: the plain layer's latency and rotations/s, HMA/s, decrypted
+max error of both against the FP64 convolution, executed operation counts,
+the roofline of the dominant kernel (timed with HIP events around each of its
+launches inside the timed region), and the CPU oracle timed on a bounded
+sample of the same DensePack dot products.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+WORKLOAD = "ffconv_n8192"
+N, Q_BITS, P_BITS, SCALE = 8192, (30, 30, 30, 30), 40, 2.0**25
+K_BITS = 12
+HBM_PEAK_GBS = 8000.0
+# 32-bit VALU lane operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
+DOMINANT = "ks_modup_ip"
+
+# Operation-cost model (32-bit VALU lane ops) used for the ALU roofline of the
+# key-switch kernels; see DESIGN.md ("Rooflines").
+COST = {
+    "bfly_narrow": 12, "bfly_wide": 34,   # CT butterfly with a Shoup twiddle product
+    "mac_narrow": 11, "mac_wide": 40,     # Barrett product + modular add
+    "lift_narrow": 8, "lift_wide": 12,    # centred lift of one coefficient
+}
+
+
+def modup_ip_ops(count: int, level: int, n: int, narrow) -> float:
+    """Algorithmic VALU ops of one k_ks_modup_ip launch over `count` ciphertexts."""
+    bfly = (n // 2) * int(math.log2(n))
+    ops = 0.0
+    for t in range(level + 1):
+        nar = narrow[t] if t < level else narrow[-1]
+        n_ntt = level - 1 if t < level else level
+        ops += n_ntt * (bfly * COST["bfly_narrow" if nar else "bfly_wide"] +
+                        n * COST["lift_narrow" if nar else "lift_wide"])
+        ops += 2 * level * n * COST["mac_narrow" if nar else "mac_wide"]
+    return ops * count
+
+
+def modup_ip_bytes(count: int, level: int, n: int) -> float:
+    """Algorithmic HBM bytes of one k_ks_modup_ip launch: digits (+ own limb),
+    outputs, and the key once."""
+    limb = 8 * n
+    return count * ((level + 1) * level * limb + 2 * (level + 1) * limb) + 2 * level * (level + 1) * limb
+
+
+def setup(ctx, client, x, w1, w2):
+    from paper_2102_03494_amd import layers as Ly
+    from paper_2102_03494_amd.he import Ct
+
+    geom = Ly.Geometry(28, 28, 1, 5, 2, 0)
+    level = len(Q_BITS)
+    slots = N // 2
+    ct = client.encrypt(Ly.densepack_layout(x, geom, slots)[0], level, SCALE, index=0)
+    steps = Ly.rot_steps(ctx)
+    desc_ff = ctx.conv_desc(28, 28, 1, 5, 2, 0, w1.shape[3], len(steps))
+    pts1 = Ly.pt_scale_for(ctx, level, SCALE, SCALE)
+    f1 = Ly.encode_filters(client, w1, geom, level, pts1)
+    y_scale = SCALE * pts1 / ctx.q[level - 1]
+    target = Ly.pre_square_target(ctx, level - 2, SCALE)
+    ms = Ly.mask_scale_for(ctx, level - 1, y_scale, target, K_BITS)
+    mask = Ly.onehot_mask(client, level - 1, ms)
+    w_plain = Ly.compose_factors(w1, w2)
+    desc_pl = ctx.conv_desc(28, 28, 1, 5, 2, 0, w_plain.shape[3], len(steps))
+    target_pl = Ly.pre_square_target(ctx, level - 1, SCALE)
+    pts_pl = Ly.pt_scale_for(ctx, level, SCALE, target_pl)
+    f_pl = Ly.encode_filters(client, w_plain, geom, level, pts_pl)
+
+    def ffconv_step():
+        return ctx.ffconv_layer(ct, desc_ff, f1, pts1, mask, ms, w2, K_BITS, True)
+
+    def plain_step():
+        y = ctx.conv_densepack(ct, desc_pl, f_pl, pts_pl)
+        return ctx.rescale(ctx.square(y))
+
+    return geom, ct, ffconv_step, plain_step, w_plain
+
+
+def timed(fn, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, out
+
+
+def cpu_baseline(x, w1, n_outputs: int):
+    """The oracle's DensePack dot products (HMA + 12 rotate-and-add + rescale)
+    on a sample of W1 outputs of the same workload, single process."""
+    import synth  # noqa: F401
+    from oracle import conv as C
+    from oracle import params as P
+    from oracle import workloads as Wk
+
+    p = P.ffconv_n8192()
+    ctx = Wk.make_context(p, WORKLOAD, rotations=C.rotate_and_sum_steps(p))
+    geom = C.ConvGeom(28, 28, 1, 5, 2, 0)
+    ct = Wk.encrypt_slots(ctx, C.densepack_slots(x, geom, p.slots)[0], p.max_level, p.scale, WORKLOAD, 0)
+    pts = C.densepack_pt_scale(p, p.max_level, p.scale, p.scale)
+    bf = C.densepack_base_filters(p, w1, geom, p.max_level, pts)
+    outs = C.output_list(geom, w1.shape[3])
+    sample = [outs[i] for i in range(0, len(outs), max(1, len(outs) // n_outputs))][:n_outputs]
+    t0 = time.perf_counter()
+    _, cnt = C.conv_densepack(p, ctx, ct, geom, bf, pts, outputs=sample)
+    dt = time.perf_counter() - t0
+    return {"value": cnt.rot / dt, "unit": "rotations/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(sample)} of the {len(outs)} W1 DensePack dot products (HMA, 12 rotate-and-add, "
+                      f"rescale) at N=8192, {dt:.1f} s single-threaded numpy"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--plain-steps", type=int, default=4)
+    ap.add_argument("--cpu-sample", type=int, default=12, help="oracle dot products timed (0 = skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); "
+              "the multi-GPU sharding is a design note, not a built path", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2102_03494_amd import layers as Ly
+    from paper_2102_03494_amd.client import Client
+    from paper_2102_03494_amd.he import HEContext
+
+    torch.cuda.set_device(0)
+    x = synth.image(WORKLOAD, (28, 28, 1))
+    w1 = synth.weights(WORKLOAD, 1, (5, 5, 1, 2), 0.1)
+    w2 = synth.weights(WORKLOAD, 2, (2, 5), 0.1)
+
+    ctx = HEContext(N, Q_BITS, P_BITS)
+    ctx.reserve(ctx.workspace_need(720, len(Q_BITS)) + (1 << 28))
+    client = Client(ctx, WORKLOAD)
+    client.gen_rotation_keys(Ly.rot_steps(ctx))
+    client.gen_relin_key()
+    geom, ct, ffconv_step, plain_step, w_plain = setup(ctx, client, x, w1, w2)
+    print(f"# setup done: N={N}, moduli={ctx.moduli}", file=sys.stderr, flush=True)
+
+    # ---- timed FFConv steps (dominant kernel bracketed by HIP events) ----------
+    for _ in range(args.warmup):
+        ffconv_step()
+    torch.cuda.synchronize()
+    ctx.prof_select(DOMINANT)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        z = ffconv_step()
+    torch.cuda.synchronize()
+    t_ff = (time.perf_counter() - t0) / args.steps
+    dom_ms, dom_launches = ctx.prof_read()
+    ctx.prof_select(None)
+    counts_ff = ctx.last_counts()
+    print(f"# ffconv: {t_ff * 1e3:.3f} ms/layer", file=sys.stderr, flush=True)
+
+    # ---- plain comparator -------------------------------------------------------
+    t_pl, zp = timed(plain_step, args.plain_steps, 1, torch)
+    counts_pl = ctx.last_counts()
+    print(f"# plain: {t_pl * 1e3:.3f} ms/layer", file=sys.stderr, flush=True)
+
+    # ---- decrypted accuracy vs FP64 ------------------------------------------------
+    ref_y = Ly.reference_conv2d(x, w1, 2, 0)
+    ref_ff = (ref_y @ w2) ** 2
+    err_ff = 0.0
+    for o in range(w2.shape[1]):
+        v = client.decrypt(z.data[o], z.scale, geom.spatial, limbs=1)
+        err_ff = max(err_ff, float(np.abs(v - ref_ff[:, :, o].ravel()).max()))
+    ref_pl = Ly.reference_conv2d(x, w_plain, 2, 0) ** 2
+    err_pl = 0.0
+    for idx in range(zp.data.shape[0]):
+        o, rem = divmod(idx, geom.spatial)
+        i, j = divmod(rem, geom.out_w)
+        v = client.decrypt(zp.data[idx], zp.scale, 1, limbs=1)
+        err_pl = max(err_pl, abs(float(v[0]) - ref_pl[i, j, o]))
+
+    rot_ff = 288 * 12
+    rot_pl = 720 * 12
+    hma_ff = counts_ff["mulpc"] + counts_ff["scalar_mul"]
+    level = len(Q_BITS)
+    narrow = [q < (1 << 31) for q in ctx.moduli]
+    avg_ms = dom_ms / max(1, dom_launches)
+    per_launch_count = 288  # one rotate-and-add step of all W1 dot products per launch
+    ops = modup_ip_ops(per_launch_count, level, N, narrow)
+    achieved_ops = ops / (avg_ms * 1e-3)
+    roofline = {
+        "kernel": "k_ks_modup_ip (ModUp NTTs + key inner product of one rotate-and-add step, 288 ciphertexts, level 4)",
+        "bound": "alu", "achieved": achieved_ops / 1e12, "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s (32-bit VALU)",
+        "frac": achieved_ops / VALU_PEAK_OPS, "traffic": None,
+        "avg_launch_ms": avg_ms, "launches": dom_launches,
+        "hbm_gbs_algorithmic": modup_ip_bytes(per_launch_count, level, N) / (avg_ms * 1e-3) / 1e9,
+    }
+
+    cpu = None
+    if args.cpu_sample > 0:
+        print("# timing the CPU oracle sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(x, w1, args.cpu_sample)
+
+    line = {
+        "metric": "encrypted conv-layer latency (ms) + rotations/s; FFConv batched vs plain",
+        "value": rot_ff / t_ff,
+        "unit": "rotations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_ff * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64 (exact RNS residues, 30/40-bit primes)",
+        "data": "synthetic (seeded U[0,1) 28x28x1 image, N(0,0.1^2) weights; no dataset)",
+        "config": {"workload": "FFConv layer 28x28x1, 5x5 s2 1->2 DensePack + 1x1 2->5 ConvPack + x^2, "
+                               "N=8192, 4x30-bit + 40-bit P, scale 2^25",
+                   "global_batch": 1, "parallelism": "none (1 GPU)"},
+        "ffconv_layer_ms": t_ff * 1e3,
+        "plain_layer_ms": t_pl * 1e3,
+        "speedup_vs_plain": t_pl / t_ff,
+        "plain_rotations_per_s": rot_pl / t_pl,
+        "hma_per_s": hma_ff / t_ff,
+        "counts_ffconv": counts_ff,
+        "counts_plain_conv": counts_pl,
+        "decrypted_max_abs_err": {"ffconv": err_ff, "plain": err_pl},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,260 @@
+/*
+ * ffconv_he.h -- C ABI of the MI355X (gfx950) homomorphic convolution library.
+ *
+ * The library evaluates convolution layers on packed RLWE ciphertexts of an
+ * RNS CKKS-style scheme, in the two forms of the FFConv paper (arXiv
+ * 2102.03494): a plain d x d convolution under DensePack (Section 3.2,
+ * Fig. 1, Table I) and the FFConv factorisation (Section 4, Eq. 2): a
+ * low-rank d x d convolution under DensePack, the DP->CP transition
+ * (Table III, d = 1) and a 1 x 1 convolution under ConvPack (Table II).
+ * The setting is the paper's (Section 1 and Section 3): the client encrypts
+ * an image, the server holds plaintext weights and returns an encrypted
+ * prediction.  Every step runs in hand-written HIP kernels.
+ *
+ * Conventions shared by all calls
+ * -------------------------------
+ * Ring: Z[X]/(X^N + 1), N a power of two in [2^10, 2^16].  Moduli: the
+ * ciphertext primes q_0 > ... > q_{L-1} (ordered as generated) followed by the
+ * special prime P; "modulus index" t < L means q_t and t = L means P.  Every
+ * prime is 1 mod 2N and below 2^62.
+ *
+ * Polynomials are stored limb-major as uint64 residues in [0, q):
+ *   poly  = [n_limbs][N], limb t reduced mod modulus index t;
+ *   ct    = [2][level][N]   (c0 then c1; decryption is c0 + c1*s);
+ *   batch = [count][2][level][N], contiguous.
+ * Ciphertexts and plaintexts are in the NTT domain: entry i holds the value
+ * at psi^(2*brv(i)+1), with psi = x^((q-1)/2N) for x the smallest quadratic
+ * non-residue mod q and brv the log2(N)-bit reversal.  Slot j of a CKKS
+ * vector is the evaluation at zeta^(5^j), zeta = exp(i pi / N); the Galois
+ * element 5^k mod 2N rotates the slot vector left by k.
+ *
+ * Memory: every data pointer named d_* is device memory owned by the caller
+ * (e.g. torch tensors).  Host pointers are named h_*.  The library owns the
+ * context tables, the switching keys and the workspace it is given by
+ * he_ctx_reserve (the only call that allocates device memory besides
+ * he_ctx_create and he_keygen_switch).
+ *
+ * Errors: each call returns HE_OK (0) or a negative code.  Argument, level
+ * and key errors are detected before any launch and leave outputs untouched;
+ * he_last_error gives the message.  Launch failures return HE_EDEVICE.
+ * Calls enqueue work on the given stream (hipStream_t as void*, NULL = the
+ * default stream) and return without synchronising, except where stated.
+ * A context is not thread safe: use one per host thread or serialise.
+ */
+#ifndef FFCONV_HE_H
+#define FFCONV_HE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HE_OK = 0,
+  HE_EINVAL = -1,       /* bad argument or shape */
+  HE_ELEVEL = -2,       /* level too low/high for the operation */
+  HE_ENOKEY = -4,       /* a needed switching key is missing */
+  HE_ENOMEM = -5,       /* workspace or device allocation too small / failed */
+  HE_EDEVICE = -6,      /* HIP runtime or launch error */
+  HE_EUNSUPPORTED = -7  /* parameter combination not built */
+};
+
+typedef struct he_ctx he_ctx;
+
+#define HE_MAX_PRIMES 16
+
+typedef struct {
+  int32_t n;                      /* ring degree N */
+  int32_t n_q;                    /* number of ciphertext primes L (1..15) */
+  int32_t q_bits[HE_MAX_PRIMES];  /* bit size of each ciphertext prime (20..61) */
+  int32_t p_bits;                 /* bit size of the special prime (20..61) */
+} he_params;
+
+/* ---- parameters (host only; no device needed) ----------------------------
+ * he_params_moduli: the primes the context would use, written to
+ * h_out[0..n_q] (ciphertext primes then P).  A prime of b bits is the
+ * largest prime below 2^b that is 1 mod 2N; primes of equal size follow each
+ * other downward.  Returns HE_EINVAL for unsupported sizes. */
+int he_params_moduli(const he_params *p, uint64_t *h_out);
+
+/* ---- context ---------------------------------------------------------------
+ * he_ctx_create builds the prime chain, roots and twiddle tables on the
+ * current device.  he_ctx_reserve makes sure the workspace holds `bytes`
+ * (device allocation; call it outside timed regions).  he_ctx_workspace_need
+ * returns the bytes the heaviest call on `count` ciphertexts at `level` needs
+ * (0 on error). */
+int he_ctx_create(const he_params *p, he_ctx **out);
+int he_ctx_destroy(he_ctx *ctx);
+int he_ctx_reserve(he_ctx *ctx, size_t bytes);
+size_t he_ctx_workspace_need(const he_ctx *ctx, int count, int level);
+int he_ctx_moduli(const he_ctx *ctx, uint64_t *h_out);   /* n_q + 1 values */
+const char *he_last_error(const he_ctx *ctx);
+
+/* ---- ring transforms (the negacyclic NTT that sits inside every Rot and
+ * Square) ---------------------------------------------------------------------
+ * In place on d_polys = [n_polys][n_limbs][N]; limb t of each poly uses
+ * modulus index first_mod + t.  he_ntt maps coefficients to evaluations,
+ * he_intt maps back.  Inputs must be reduced (< modulus). */
+int he_ntt(he_ctx *ctx, uint64_t *d_polys, int n_polys, int n_limbs, int first_mod, void *stream);
+int he_intt(he_ctx *ctx, uint64_t *d_polys, int n_polys, int n_limbs, int first_mod, void *stream);
+
+/* ---- elementwise operations (AddCC and MulPC of Table I) -------------------
+ * he_add:  d_out[i] = d_a[i] + d_b[i] for `count` ciphertexts at `level`
+ *          (d_out may alias d_a or d_b).
+ * he_hma_plain: one accumulator ciphertext d_acc ([2][level][N]) gets
+ *          (accumulate ? d_acc : 0) + sum_{i<k} d_cts[i] * sigma_{g_i}(pt_i),
+ *          where pt_i = d_pts + i * pt_stride limbs-of-N (pt_stride = 0 reuses
+ *          one plaintext), each plaintext has pt_limbs >= level limbs, and
+ *          g_i = h_galois[i] (h_galois NULL: no permutation).  This is MulPC
+ *          with the plaintext slot rotation folded into its load.
+ * he_hma_scalar: d_acc = (accumulate ? d_acc : 0) + sum_{i<k} w_i * d_cts[i]
+ *          with exact signed integers h_w[i] (|w| < 2^62). */
+int he_add(he_ctx *ctx, uint64_t *d_out, const uint64_t *d_a, const uint64_t *d_b,
+           int count, int level, void *stream);
+int he_hma_plain(he_ctx *ctx, uint64_t *d_acc, const uint64_t *d_cts, int k,
+                 const uint64_t *d_pts, int pt_stride, int pt_limbs,
+                 const int32_t *h_galois, int level, int accumulate, void *stream);
+int he_hma_scalar(he_ctx *ctx, uint64_t *d_acc, const uint64_t *d_cts, int k,
+                  const int64_t *h_w, int level, int accumulate, void *stream);
+
+/* ---- rescale -----------------------------------------------------------------
+ * d_out[i] ([2][level-1][N]) = round(d_in[i] / q_{level-1}) for `count`
+ * ciphertexts: c_t <- (c_t - centred(c mod q_{level-1})) * q_{level-1}^-1.
+ * The caller divides its scale by q_{level-1}.  level >= 2; d_out must not
+ * alias d_in. */
+int he_rescale(he_ctx *ctx, uint64_t *d_out, const uint64_t *d_in, int count, int level, void *stream);
+
+/* ---- keys ------------------------------------------------------------------
+ * Switching keys live in the context (device memory owned by the library).
+ * he_keygen_switch computes and stores the key for Galois element `galois`
+ * (odd, < 2N), or the relinearisation key when galois == 0, from client data:
+ *   d_s     secret in the NTT domain, [L+1][N] (all moduli),
+ *   d_a     uniform residues, NTT domain, [L][L+1][N] (one row per digit),
+ *   d_e     signed error coefficients, int64 [L][N].
+ * For digit j and modulus index t:  b = -a*s + e + [t == j] (P mod q_t) s'
+ * with s' = sigma_galois(s) (or s^2), stored with a as [L][2][L+1][N].
+ * This is a client-side call (it needs the secret); it synchronises. */
+int he_keygen_switch(he_ctx *ctx, int32_t galois, const uint64_t *d_s,
+                     const uint64_t *d_a, const int64_t *d_e, void *stream);
+int he_has_key(const he_ctx *ctx, int32_t galois);
+int he_drop_keys(he_ctx *ctx);
+
+/* ---- client helpers (not on the server path) -------------------------------
+ * he_from_signed: d_out [n_limbs][N] = d_coeffs (int64 [N]) mod modulus index
+ *          first_mod + t, coefficient domain (follow with he_ntt).
+ * he_encrypt_sk: d_ct ([2][level][N]) = (-a*s + e + pt, a) with d_pt
+ *          [level][N] (NTT), d_a [level][N] (NTT), d_e int64 [N], d_s [L+1][N].
+ * he_decrypt: d_out [level][N] (NTT) = c0 + c1*s.
+ * he_encode_coeffs: host FP64 encoder; h_out[N] (int64) =
+ *          round-half-away(scale * m_k) for the real slot vector h_z
+ *          (n_values <= N/2, zero padded); returns HE_EINVAL if any value
+ *          reaches 2^62.
+ * he_decode_coeffs: host decoder; h_z[n_values] = real slot values of the
+ *          real coefficient vector h_m (already divided by the scale). */
+int he_from_signed(he_ctx *ctx, uint64_t *d_out, const int64_t *d_coeffs, int n_limbs, int first_mod, void *stream);
+int he_encrypt_sk(he_ctx *ctx, uint64_t *d_ct, const uint64_t *d_pt, const uint64_t *d_a,
+                  const int64_t *d_e, const uint64_t *d_s, int level, void *stream);
+int he_decrypt(he_ctx *ctx, uint64_t *d_out, const uint64_t *d_ct, const uint64_t *d_s, int level, void *stream);
+int he_encode_coeffs(int n, const double *h_z, int n_values, double scale, int64_t *h_out);
+int he_decode_coeffs(int n, const double *h_m, int n_values, double *h_z);
+
+/* ---- rotations (Rot of Table I) --------------------------------------------
+ * he_rotate: d_out[i] = Rot(d_in[i], k) (slot rotation left by k) for
+ *          `count` ciphertexts at `level`, all with the key of 5^k mod 2N;
+ *          one key switch each: digits of sigma_g(c1) centred per prime,
+ *          lifted to every prime and P, inner product with the key, ModDown.
+ *          d_out may alias d_in.
+ * he_rotate_hoisted: m rotations of ONE ciphertext d_in by h_steps[0..m)
+ *          sharing one digit decomposition (the Galois permutation is applied
+ *          to the lifted digits); d_outs = [m][2][level][N].  Results are
+ *          bit-identical to he_rotate.
+ * he_rotsum: in place, for j < r_steps: t <- t + Rot(t, 2^j), for `count`
+ *          ciphertexts (the DensePack dot-product sum, Fig. 1b). */
+int he_rotate(he_ctx *ctx, uint64_t *d_out, const uint64_t *d_in, int count, int level, int k, void *stream);
+int he_rotate_hoisted(he_ctx *ctx, const uint64_t *d_in, int level, const int32_t *h_steps, int m,
+                      uint64_t *d_outs, void *stream);
+int he_rotsum(he_ctx *ctx, uint64_t *d_cts, int count, int level, int r_steps, void *stream);
+
+/* ---- square (the x^2 activation, Section 2.1) ------------------------------
+ * d_out[i] = relinearised (c0^2, 2 c0 c1) + KeySwitch(c1^2) under the key for
+ * s^2, for `count` ciphertexts; the scale squares (no rescale). */
+int he_square(he_ctx *ctx, uint64_t *d_out, const uint64_t *d_in, int count, int level, void *stream);
+
+/* ---- convolution layers ----------------------------------------------------
+ * Geometry: input X[h][w][c], filters [kh][kw][c][o], output [i][j][o] with
+ * out_h = (h + 2 pad - d) / stride + 1 (same for w); S = out_h * out_w.
+ * DensePack layout (Section 3.2): X value (h, w, c) sits at slot
+ * (c mod B) * H * W + h * W + w of input ciphertext c / B, where
+ * B = min(c_in, floor((N/2) / (H*W))) channels fit one ciphertext;
+ * M = ceil(c_in / B) input ciphertexts.
+ * Border classes: the valid filter-row ranges [lo, hi) are numbered in order
+ * of first appearance over output rows 0..out_h-1, likewise columns; class =
+ * row_class * n_col_classes + col_class.  Base filter plaintext
+ * (o, class, m) carries W[kh][kw][c][o] at slot (c mod B)*H*W + kh*W + kw for
+ * the taps valid in that class (zero elsewhere).
+ */
+typedef struct {
+  int32_t h, w, c_in;   /* input tensor */
+  int32_t d, stride, pad;
+  int32_t o_c;          /* output channels of this DensePack layer */
+  int32_t r_steps;      /* rotate-and-sum steps (log2(N/2) sums every slot) */
+} he_conv_desc;
+
+/* he_conv_densepack (Table I): for every output value (o, i, j), index
+ * o*S + i*out_w + j, computes sum_m x_m * sigma_{g}(F[o][class(i,j)][m]) with
+ * g = 5^(-anchor) (rotation right by anchor = (stride i - pad) W +
+ * (stride j - pad)), then r_steps rotate-and-add steps, then one rescale.
+ *   d_in:   [M][2][level][N]
+ *   d_filt: [o_c][n_classes][M][level][N] base filters (NTT domain)
+ *   d_out:  [o_c * S][2][level-1][N]: each output replicated in every slot.
+ * Needs rotation keys for 2^j, j < r_steps, and workspace for o_c*S
+ * ciphertexts at `level` (see he_ctx_workspace_need). */
+int he_conv_densepack(he_ctx *ctx, const uint64_t *d_in, int level, const he_conv_desc *desc,
+                      const uint64_t *d_filt, uint64_t *d_out, void *stream);
+
+/* he_conv_convpack (Table II): K channel ciphertexts in, O_c out:
+ * d_out[o] = rescale(sum_k round-half-away(h_w[k*o_c + o] * w_scale) * d_in[k]).
+ * d_in [K][2][level][N], d_out [o_c][2][level-1][N].  The caller picks
+ * w_scale = q_{level-1} * target / input_scale so the rescale lands on
+ * target. */
+int he_conv_convpack(he_ctx *ctx, const uint64_t *d_in, int k, int level, const double *h_w,
+                     int o_c, double w_scale, uint64_t *d_out, void *stream);
+
+/* ffconv_layer (Section 4, DP-HI2C-CP of Table IX):
+ *   1. W1 under DensePack exactly as he_conv_densepack (desc->o_c = rank r),
+ *      giving r*S replicated ciphertexts at level-1;
+ *   2. DP->CP gather: G_c = sum_p y_{c,p} * sigma_{5^-p}(E), E = d_mask (the
+ *      one-hot slot-0 plaintext, [level-1][N]), p = i*out_w + j;
+ *   3. 1x1 ConvPack: Z_o = sum_c round-half-away(h_w2[c*o_c2 + o] * 2^k_bits) G_c;
+ *   4. rescale; 5. if square: Z <- rescale(relinearised Z^2).
+ * d_out: [o_c2][2][level-2 (-1 more if square)][N].  The mask is encoded by
+ * the caller at scale q_{level-2} * target / (y_scale * 2^k_bits). */
+int ffconv_layer(he_ctx *ctx, const uint64_t *d_in, int level, const he_conv_desc *desc,
+                 const uint64_t *d_w1_filt, const uint64_t *d_mask, const double *h_w2, int o_c2,
+                 int k_bits, int square, uint64_t *d_out, void *stream);
+
+/* Executed operation counters of the last layer call (he_conv_densepack,
+ * he_conv_convpack, ffconv_layer): MulPC, AddCC, Rot, rescaled ciphertexts,
+ * squares, integer-scalar products. */
+typedef struct {
+  int64_t mulpc, addcc, rot, rescale, square, scalar_mul;
+} he_counts;
+int he_last_counts(const he_ctx *ctx, he_counts *out);
+
+/* ---- instrumentation (not part of the evaluated path) ---------------------
+ * he_prof_select: from now on every launch of the kernel named `kernel`
+ * ("ntt", "ks_digits", "ks_modup_ip", "intt_last", "drop_last", "dp_hma",
+ * "hma_perm", "scalar_mac", "tensor_sq", "modup_store", "ip_perm", "add") is
+ * bracketed by two HIP events recorded on the stream it is launched on; NULL
+ * or "" stops recording.  he_prof_read waits for the recorded events and
+ * returns the summed kernel time (ms) and the number of launches since the
+ * last select or read, then clears them. */
+int he_prof_select(he_ctx *ctx, const char *kernel);
+int he_prof_read(he_ctx *ctx, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FFCONV_HE_H */

@@ -1,0 +1,108 @@
+"""Client side of the protocol (the party that holds the secret key).
+
+In the paper's setting (Section 1; Section 3, MLaaS scenario) the client
+encrypts its image, the server evaluates the network with plaintext weights
+and the client decrypts the prediction.  This module generates the secret and
+the switching keys from the seeded draws of ``synth``, encodes and encrypts
+slot vectors and decrypts results, calling the library for every ring
+operation (encoding's FFT and the CRT of decryption run on the host).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+import synth
+
+from .he import Ct, HEContext, galois_for_rotation, to_device, to_host
+
+
+class Client:
+    def __init__(self, ctx: HEContext, workload, secret_index: int = 0):
+        self.ctx = ctx
+        self.workload = workload
+        n, big_l = ctx.n, ctx.L
+        s = synth.ternary_secret(workload, n, secret_index)
+        self.s_coeff = torch.from_numpy(s).cuda()
+        s_ntt = ctx.from_signed(self.s_coeff, big_l + 1, 0)
+        ctx.ntt(s_ntt.view(1, big_l + 1, n))
+        self.s_ntt = s_ntt
+
+    # ---- keys ------------------------------------------------------------------
+    def _switch_key(self, key_index: int):
+        c = self.ctx
+        a, e = synth.switch_key_draws(self.workload, key_index, c.moduli, c.n, c.L)
+        c.keygen_switch(key_index, self.s_ntt, to_device(a), torch.from_numpy(e).cuda())
+
+    def gen_rotation_keys(self, steps):
+        for k in steps:
+            g = galois_for_rotation(int(k), self.ctx.n)
+            if g != 1 and not self.ctx.has_key(g):
+                self._switch_key(g)
+
+    def gen_relin_key(self):
+        if not self.ctx.has_key(synth.RELIN_INDEX):
+            self._switch_key(synth.RELIN_INDEX)
+
+    # ---- plaintexts -----------------------------------------------------------------
+    def encode(self, z, level: int, scale: float) -> torch.Tensor:
+        """NTT-domain plaintext [level][N] of real slot values z."""
+        coeffs = torch.from_numpy(self.ctx.encode_coeffs(z, scale)).cuda()
+        pt = self.ctx.from_signed(coeffs, level, 0)
+        self.ctx.ntt(pt.view(1, level, self.ctx.n))
+        return pt
+
+    def encrypt_pt(self, pt: torch.Tensor, scale: float, index: int) -> Ct:
+        c = self.ctx
+        level = pt.shape[-2]
+        a, e = synth.encryption_draws(self.workload, index, c.q[:level], c.n)
+        ct = c.encrypt_sk(pt, to_device(a), torch.from_numpy(e).cuda(), self.s_ntt)
+        return Ct(ct.view(1, 2, level, c.n), scale)
+
+    def encrypt(self, z, level: int, scale: float, index: int) -> Ct:
+        return self.encrypt_pt(self.encode(z, level, scale), scale, index)
+
+    # ---- decryption -----------------------------------------------------------------
+    def decrypt_coeffs(self, ct_one: torch.Tensor) -> list[int]:
+        """Centred integer coefficients of c0 + c1*s (exact CRT over the limbs)."""
+        c = self.ctx
+        m = c.decrypt(ct_one.contiguous(), self.s_ntt)
+        level = m.shape[0]
+        c.intt(m.view(1, level, c.n))
+        limbs = to_host(m)
+        moduli = c.q[:level]
+        big_q = 1
+        for q in moduli:
+            big_q *= q
+        parts = []
+        for t, q in enumerate(moduli):
+            qhat = big_q // q
+            parts.append((qhat, pow(qhat % q, -1, q), q, limbs[t]))
+        out = []
+        for k in range(c.n):
+            x = 0
+            for qhat, qinv, q, col in parts:
+                x += (int(col[k]) * qinv % q) * qhat
+            x %= big_q
+            out.append(x - big_q if x > big_q // 2 else x)
+        return out
+
+    def decrypt(self, ct_one: torch.Tensor, scale: float, n_values: int | None = None,
+                limbs: int | None = None) -> np.ndarray:
+        """Real slot values.  `limbs` keeps only the first limbs (modulus drop),
+        valid when |message * scale| < q_0 / 2; with one limb the centring is
+        vectorised."""
+        n_values = self.ctx.n // 2 if n_values is None else n_values
+        if limbs is not None:
+            ct_one = ct_one[:, :limbs]
+        if ct_one.shape[-2] == 1:
+            c = self.ctx
+            m = c.decrypt(ct_one.contiguous(), self.s_ntt)
+            c.intt(m.view(1, 1, c.n))
+            v = to_host(m)[0].astype(np.int64)
+            q = c.q[0]
+            v = np.where(v > q // 2, v - q, v).astype(np.float64)
+            return self.ctx.decode_coeffs(v / scale, n_values)
+        coeffs = self.decrypt_coeffs(ct_one)
+        m = np.array([float(x) for x in coeffs]) / scale
+        return self.ctx.decode_coeffs(m, n_values)

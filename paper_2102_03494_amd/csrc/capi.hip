@@ -1,0 +1,924 @@
+// C-ABI of the homomorphic convolution library: context, keys, workspace,
+// argument checks and kernel orchestration.  See include/ffconv_he.h for the
+// contract of every entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdarg>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/ffconv_he.h"
+#include "host_params.h"
+#include "kernels.h"
+
+using namespace he;
+
+struct he_ctx {
+  int n = 0, logn = 0, big_l = 0;
+  std::vector<u64> moduli;  // q_0..q_{L-1}, P
+  Mods mods{};
+  u64* d_tw = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::map<int, u64*> keys;  // Galois element (0 = relinearisation) -> [L][2][L+1][N]
+  std::string err;
+  he_counts counts{};
+  int device = 0;
+  // instrumentation: events around launches of one selected kernel
+  std::string prof_kernel;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
+  std::vector<hipEvent_t> prof_pool;
+};
+
+namespace {
+
+int fail(he_ctx* c, int code, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return code;
+}
+
+int check_launch(he_ctx* c, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, HE_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+  return HE_OK;
+}
+
+hipStream_t S(void* s) { return (hipStream_t)s; }
+
+hipEvent_t prof_event(he_ctx* c) {
+  if (!c->prof_pool.empty()) {
+    hipEvent_t e = c->prof_pool.back();
+    c->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets the launches in its scope with events when `name` is selected.
+struct Prof {
+  he_ctx* c;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  Prof(he_ctx* ctx, const char* name, hipStream_t st) : c(ctx), s(st) {
+    if (!c->prof_kernel.empty() && c->prof_kernel == name) {
+      a = prof_event(c);
+      if (a) hipEventRecord(a, s);
+    }
+  }
+  ~Prof() {
+    if (!a) return;
+    hipEvent_t b = prof_event(c);
+    if (!b) return;
+    hipEventRecord(b, s);
+    c->prof_events.push_back({a, b});
+  }
+};
+
+// Bump allocator over the context workspace (one per call).
+struct Arena {
+  char* base;
+  size_t cap, used = 0;
+  Arena(he_ctx* c) : base(c->ws), cap(c->ws_bytes) {}
+  template <typename T>
+  T* take(size_t count) {
+    size_t bytes = (count * sizeof(T) + 255) & ~(size_t)255;
+    if (used + bytes > cap) return nullptr;
+    T* p = (T*)(base + used);
+    used += bytes;
+    return p;
+  }
+  size_t left() const { return cap - used; }
+};
+
+u32 galois_of(int k, int n) {
+  const int slots = n / 2;
+  int e = k % slots;
+  if (e < 0) e += slots;
+  return (u32)powmod(5, (u64)e, 2 * (u64)n);
+}
+
+template <template <int> class F, typename... A>
+int dispatch_logn(int logn, A&&... args) {
+  switch (logn) {
+    case 10: F<10>::run(args...); return 0;
+    case 11: F<11>::run(args...); return 0;
+    case 12: F<12>::run(args...); return 0;
+    case 13: F<13>::run(args...); return 0;
+    case 14: F<14>::run(args...); return 0;
+    default: return -1;
+  }
+}
+
+// ---- launch wrappers (templated on log2 N) ---------------------------------
+
+template <int LOGN>
+struct LNtt {
+  static void run(he_ctx* c, u64* d, int n_polys, int n_limbs, int first_mod, bool fwd, hipStream_t s) {
+    dim3 grid(n_limbs, n_polys);
+    Prof pr(c, "ntt", s);
+    if (fwd)
+      k_ntt<LOGN, true><<<grid, NttGeom<LOGN>::T, 0, s>>>(d, n_limbs, first_mod, c->mods, c->d_tw);
+    else
+      k_ntt<LOGN, false><<<grid, NttGeom<LOGN>::T, 0, s>>>(d, n_limbs, first_mod, c->mods, c->d_tw);
+  }
+};
+
+// Key switch of `count` polynomials: input c1 (NTT domain, permuted by g
+// before decomposition), result (u0, u1) in u, P limb INTT in rcoef.
+template <int LOGN>
+struct LKeySwitchCore {
+  static void run(he_ctx* c, const u64* c1, size_t cstride, u32 ginv, const u64* key, int count, int level,
+                  u64* dcoef, u64* u, u64* rcoef, hipStream_t s) {
+    constexpr int T = NttGeom<LOGN>::T;
+    constexpr size_t N = (size_t)1 << LOGN;
+    {
+      Prof pr(c, "ks_digits", s);
+      k_ks_digits<LOGN><<<dim3(level, count), T, 0, s>>>(c1, cstride, ginv, dcoef, level, c->mods, c->d_tw);
+    }
+    {
+      Prof pr(c, "ks_modup_ip", s);
+      k_ks_modup_ip<LOGN><<<dim3(level + 1, count), T, 0, s>>>(dcoef, c1, cstride, ginv, key, u, level, c->big_l,
+                                                                c->mods, c->d_tw);
+    }
+    Prof pr(c, "intt_last", s);
+    k_intt_last<LOGN><<<dim3(2 * count), T, 0, s>>>(u, (size_t)(level + 1) * N, level, c->big_l, rcoef, c->mods,
+                                                     c->d_tw);
+  }
+};
+
+template <int LOGN>
+struct LDropLast {
+  static void run(he_ctx* c, int epi, const u64* src, size_t pstride, const u64* rcoef, int div_mi, int keep,
+                  int n_polys, EpiArgs ea, hipStream_t s) {
+    constexpr int T = NttGeom<LOGN>::T;
+    ConstTable inv{};
+    const u64 d = c->moduli[div_mi];
+    for (int t = 0; t < keep; ++t) {
+      inv.v[t] = inv_mod(d % c->moduli[t], c->moduli[t]);
+      inv.sh[t] = shoup_companion(inv.v[t], c->moduli[t]);
+    }
+    dim3 grid(keep, n_polys);
+    Prof pr(c, "drop_last", s);
+    switch (epi) {
+      case EPI_STORE:
+        k_drop_last<LOGN, EPI_STORE><<<grid, T, 0, s>>>(src, pstride, rcoef, div_mi, inv, ea, c->mods, c->d_tw);
+        break;
+      case EPI_ROT:
+        k_drop_last<LOGN, EPI_ROT><<<grid, T, 0, s>>>(src, pstride, rcoef, div_mi, inv, ea, c->mods, c->d_tw);
+        break;
+      case EPI_ROTSUM:
+        k_drop_last<LOGN, EPI_ROTSUM><<<grid, T, 0, s>>>(src, pstride, rcoef, div_mi, inv, ea, c->mods, c->d_tw);
+        break;
+      default:
+        k_drop_last<LOGN, EPI_RELIN><<<grid, T, 0, s>>>(src, pstride, rcoef, div_mi, inv, ea, c->mods, c->d_tw);
+        break;
+    }
+  }
+};
+
+template <int LOGN>
+struct LIntt1 {
+  static void run(he_ctx* c, const u64* src, size_t pstride, int limb, int mi, u64* rcoef, int n_polys,
+                  hipStream_t s) {
+    Prof pr(c, "intt_last", s);
+    k_intt_last<LOGN><<<dim3(n_polys), NttGeom<LOGN>::T, 0, s>>>(src, pstride, limb, mi, rcoef, c->mods, c->d_tw);
+  }
+};
+
+template <int LOGN>
+struct LDpHma {
+  static void run(he_ctx* c, const u64* x, const u64* filt, u64* out, int level, int out_base, int n_out,
+                  const DPGeom& geo, hipStream_t s) {
+    Prof pr(c, "dp_hma", s);
+    k_dp_hma<LOGN><<<dim3(level, n_out), NttGeom<LOGN>::T, 0, s>>>(x, filt, out, level, out_base, geo, c->mods);
+  }
+};
+
+template <int LOGN>
+struct LHmaPerm {
+  static void run(he_ctx* c, u64* acc, const u64* cts, int K, const u64* pts, int pt_stride, int pt_limbs,
+                  const int32_t* gal, u32 g_step, int level, int accumulate, int n_acc, hipStream_t s) {
+    constexpr int N = 1 << LOGN;
+    Prof pr(c, "hma_perm", s);
+    k_hma_perm<LOGN><<<dim3(N / 256, level, n_acc), 256, 0, s>>>(acc, cts, K, pts, pt_stride, pt_limbs, gal, g_step,
+                                                                   level, accumulate, c->mods);
+  }
+};
+
+template <int LOGN>
+struct LKeygen {
+  static void run(he_ctx* c, u64* key, const u64* sk, const u64* a, const u64* ehat, u32 g, ConstTable pm,
+                  hipStream_t s) {
+    constexpr int N = 1 << LOGN;
+    k_keygen<LOGN><<<dim3(N / 256, c->big_l + 1, c->big_l), 256, 0, s>>>(key, sk, a, ehat, g, c->big_l, pm,
+                                                                          c->mods);
+  }
+};
+
+// ---- shared orchestration ----------------------------------------------------
+
+size_t ks_elems(int count, int level, int n) { return (size_t)count * (3 * (size_t)level + 4) * n; }
+
+// Rotation (EPI_ROT into out) or rotate-and-add (EPI_ROTSUM in place) of
+// `count` ciphertexts by k, chunked to the workspace.
+int rotate_batch(he_ctx* c, u64* out, const u64* in, int count, int level, int k, int epi, Arena& ar,
+                 hipStream_t s) {
+  const int n = c->n;
+  const u32 g = galois_of(k, n);
+  if (g == 1) {  // rotation by a multiple of N/2 slots: identity
+    if (epi == EPI_ROT) {
+      if (out != in) hipMemcpyAsync(out, in, (size_t)count * 2 * level * n * 8, hipMemcpyDeviceToDevice, s);
+      return HE_OK;
+    }
+    // t + t
+    dim3 grid(n / 256, level, count);
+    k_add<<<grid, 256, 0, s>>>(out, in, in, level, n, c->mods);
+    return check_launch(c, "add");
+  }
+  auto it = c->keys.find((int)g);
+  if (it == c->keys.end()) return fail(c, HE_ENOKEY, "no rotation key for step %d (Galois element %u)", k, g);
+  const u32 ginv = galois_of(-k, n);
+  const size_t per = ks_elems(1, level, n);
+  size_t avail = ar.left() / 8;
+  int chunk = (int)std::min<size_t>((size_t)count, avail / (per + 64));
+  chunk = std::min(chunk, 32000);
+  if (chunk < 1) return fail(c, HE_ENOMEM, "workspace too small for one key switch at level %d", level);
+  Arena sub = ar;
+  u64* dcoef = sub.take<u64>((size_t)chunk * level * n);
+  u64* u = sub.take<u64>((size_t)chunk * 2 * (level + 1) * n);
+  u64* rc = sub.take<u64>((size_t)chunk * 2 * n);
+  if (!dcoef || !u || !rc) return fail(c, HE_ENOMEM, "workspace too small");
+  const size_t cstride = (size_t)2 * level * n;
+  for (int b0 = 0; b0 < count; b0 += chunk) {
+    const int cn = std::min(chunk, count - b0);
+    const u64* cin = in + (size_t)b0 * cstride;
+    u64* cout = out + (size_t)b0 * cstride;
+    dispatch_logn<LKeySwitchCore>(c->logn, c, cin + (size_t)level * n, cstride, ginv, it->second, cn, level, dcoef,
+                                  u, rc, s);
+    EpiArgs ea{cout, (size_t)level * n, cin, (size_t)level * n, g, ginv, nullptr};
+    dispatch_logn<LDropLast>(c->logn, c, epi, (const u64*)u, (size_t)(level + 1) * n, (const u64*)rc, c->big_l,
+                             level, 2 * cn, ea, s);
+  }
+  return check_launch(c, "rotate");
+}
+
+int rescale_batch(he_ctx* c, u64* out, const u64* in, int count, int level, Arena& ar, hipStream_t s) {
+  const int n = c->n;
+  size_t avail = ar.left() / 8;
+  int chunk = (int)std::min<size_t>((size_t)count, avail / (2 * (size_t)n + 64));
+  chunk = std::min(chunk, 32000);
+  if (chunk < 1) return fail(c, HE_ENOMEM, "workspace too small for rescale");
+  Arena sub = ar;
+  u64* rc = sub.take<u64>((size_t)chunk * 2 * n);
+  for (int b0 = 0; b0 < count; b0 += chunk) {
+    const int cn = std::min(chunk, count - b0);
+    const u64* cin = in + (size_t)b0 * 2 * level * n;
+    u64* cout = out + (size_t)b0 * 2 * (level - 1) * n;
+    dispatch_logn<LIntt1>(c->logn, c, cin, (size_t)level * n, level - 1, level - 1, rc, 2 * cn, s);
+    EpiArgs ea{cout, (size_t)(level - 1) * n, nullptr, 0, 1u, 1u, nullptr};
+    dispatch_logn<LDropLast>(c->logn, c, EPI_STORE, cin, (size_t)level * n, (const u64*)rc, level - 1, level - 1,
+                             2 * cn, ea, s);
+  }
+  return check_launch(c, "rescale");
+}
+
+int square_batch(he_ctx* c, u64* out, const u64* in, int count, int level, Arena& ar, hipStream_t s) {
+  const int n = c->n;
+  auto it = c->keys.find(0);
+  if (it == c->keys.end()) return fail(c, HE_ENOKEY, "no relinearisation key");
+  const size_t per = ks_elems(1, level, n) + 3 * (size_t)level * n;
+  int chunk = (int)std::min<size_t>((size_t)count, (ar.left() / 8) / (per + 128));
+  chunk = std::min(chunk, 32000);
+  if (chunk < 1) return fail(c, HE_ENOMEM, "workspace too small for square");
+  Arena sub = ar;
+  u64* d01 = sub.take<u64>((size_t)chunk * 2 * level * n);
+  u64* d2 = sub.take<u64>((size_t)chunk * level * n);
+  u64* dcoef = sub.take<u64>((size_t)chunk * level * n);
+  u64* u = sub.take<u64>((size_t)chunk * 2 * (level + 1) * n);
+  u64* rc = sub.take<u64>((size_t)chunk * 2 * n);
+  if (!d01 || !d2 || !dcoef || !u || !rc) return fail(c, HE_ENOMEM, "workspace too small");
+  for (int b0 = 0; b0 < count; b0 += chunk) {
+    const int cn = std::min(chunk, count - b0);
+    const u64* cin = in + (size_t)b0 * 2 * level * n;
+    u64* cout = out + (size_t)b0 * 2 * level * n;
+    {
+      Prof pr(c, "tensor_sq", s);
+      k_tensor_sq<<<dim3(n / 256, level, cn), 256, 0, s>>>(d01, d2, cin, level, n, c->mods);
+    }
+    dispatch_logn<LKeySwitchCore>(c->logn, c, (const u64*)d2, (size_t)level * n, 1u, it->second, cn, level, dcoef,
+                                  u, rc, s);
+    EpiArgs ea{cout, (size_t)level * n, d01, (size_t)level * n, 1u, 1u, nullptr};
+    dispatch_logn<LDropLast>(c->logn, c, EPI_RELIN, (const u64*)u, (size_t)(level + 1) * n, (const u64*)rc,
+                             c->big_l, level, 2 * cn, ea, s);
+  }
+  return check_launch(c, "square");
+}
+
+bool build_geom(he_ctx* c, const he_conv_desc* d, DPGeom& g, int& n_cls) {
+  if (!d || d->h < 1 || d->w < 1 || d->c_in < 1 || d->d < 1 || d->stride < 1 || d->pad < 0 || d->o_c < 1)
+    return false;
+  g = DPGeom{};
+  g.h = d->h; g.w = d->w; g.c_in = d->c_in; g.d = d->d; g.stride = d->stride; g.pad = d->pad; g.o_c = d->o_c;
+  g.out_h = (d->h + 2 * d->pad - d->d) / d->stride + 1;
+  g.out_w = (d->w + 2 * d->pad - d->d) / d->stride + 1;
+  if (g.out_h < 1 || g.out_w < 1 || g.out_h > 64 || g.out_w > 64) return false;
+  const int slots = c->n / 2;
+  const int plane = d->h * d->w;
+  if (plane > slots) return false;
+  const int per = std::min(d->c_in, slots / plane);
+  g.m_cts = (d->c_in + per - 1) / per;
+  auto ranges = [&](int out, int size, int* cls, int& n_cls_axis) {
+    std::vector<std::pair<int, int>> seen;
+    for (int i = 0; i < out; ++i) {
+      int start = d->stride * i - d->pad;
+      std::pair<int, int> r(std::max(0, -start), std::min(d->d, size - start));
+      auto f = std::find(seen.begin(), seen.end(), r);
+      if (f == seen.end()) {
+        seen.push_back(r);
+        cls[i] = (int)seen.size() - 1;
+      } else {
+        cls[i] = (int)(f - seen.begin());
+      }
+    }
+    n_cls_axis = (int)seen.size();
+  };
+  ranges(g.out_h, d->h, g.row_cls, g.n_row_cls);
+  ranges(g.out_w, d->w, g.col_cls, g.n_col_cls);
+  n_cls = g.n_row_cls * g.n_col_cls;
+  return true;
+}
+
+// DensePack conv (HMA + rotate-and-sum + rescale) into d_out, chunked over
+// outputs so that any workspace holding one output's temporaries works.
+int densepack_run(he_ctx* c, const u64* d_in, int level, const he_conv_desc* desc, const u64* d_filt, u64* d_out,
+                  Arena& ar, hipStream_t s) {
+  DPGeom geo;
+  int n_cls = 0;
+  if (!build_geom(c, desc, geo, n_cls)) return fail(c, HE_EINVAL, "bad convolution geometry");
+  if (level < 2 || level > c->big_l) return fail(c, HE_ELEVEL, "DensePack needs 2 <= level <= L (got %d)", level);
+  const int n = c->n;
+  const int spatial = geo.out_h * geo.out_w;
+  const int total = spatial * geo.o_c;
+  for (int j = 0; j < desc->r_steps; ++j) {
+    u32 g = galois_of(1 << j, n);
+    if (g != 1 && !c->keys.count((int)g)) return fail(c, HE_ENOKEY, "missing rotation key for step %d", 1 << j);
+  }
+  // per output: accumulator (2 level N) + key switch temporaries
+  const size_t per = (size_t)2 * level * n + ks_elems(1, level, n) + 2 * (size_t)n;
+  int chunk = (int)std::min<size_t>((size_t)total, (ar.left() / 8) / (per + 128));
+  chunk = std::min(chunk, 16000);
+  if (chunk < 1) return fail(c, HE_ENOMEM, "workspace too small for DensePack");
+  for (int o0 = 0; o0 < total; o0 += chunk) {
+    const int cn = std::min(chunk, total - o0);
+    Arena sub = ar;
+    u64* acc = sub.take<u64>((size_t)cn * 2 * level * n);
+    if (!acc) return fail(c, HE_ENOMEM, "workspace too small");
+    dispatch_logn<LDpHma>(c->logn, c, d_in, d_filt, acc, level, o0, cn, geo, s);
+    for (int j = 0; j < desc->r_steps; ++j) {
+      int e = rotate_batch(c, acc, acc, cn, level, 1 << j, EPI_ROTSUM, sub, s);
+      if (e) return e;
+    }
+    int e = rescale_batch(c, d_out + (size_t)o0 * 2 * (level - 1) * n, acc, cn, level, sub, s);
+    if (e) return e;
+  }
+  c->counts.mulpc += (int64_t)total * geo.m_cts;
+  c->counts.addcc += (int64_t)total * (geo.m_cts - 1) + (int64_t)total * desc->r_steps;
+  c->counts.rot += (int64_t)total * desc->r_steps;
+  c->counts.rescale += total;
+  return check_launch(c, "densepack");
+}
+
+}  // namespace
+
+// ---- staging of small host tables (double-buffered pinned memory) ------------
+
+struct Stage {
+  char* host[2] = {nullptr, nullptr};
+  size_t cap[2] = {0, 0};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  bool pending[2] = {false, false};
+  int next = 0;
+};
+static std::map<const he_ctx*, Stage> g_stage;
+
+namespace {
+
+// Copies `bytes` from host to the device pointer `dst` on stream s, through a
+// pinned buffer whose previous copy is waited for first.
+int upload(he_ctx* c, void* dst, const void* src, size_t bytes, hipStream_t s) {
+  Stage& st = g_stage[c];
+  const int k = st.next;
+  st.next ^= 1;
+  if (st.pending[k]) {
+    if (hipEventSynchronize(st.ev[k]) != hipSuccess) return fail(c, HE_EDEVICE, "staging event wait failed");
+    st.pending[k] = false;
+  }
+  if (st.cap[k] < bytes) {
+    if (st.host[k]) hipHostFree(st.host[k]);
+    size_t cap = std::max<size_t>(bytes, 1 << 20);
+    if (hipHostMalloc((void**)&st.host[k], cap, hipHostMallocDefault) != hipSuccess) {
+      st.host[k] = nullptr;
+      st.cap[k] = 0;
+      return fail(c, HE_ENOMEM, "pinned staging allocation failed");
+    }
+    st.cap[k] = cap;
+  }
+  if (!st.ev[k] && hipEventCreateWithFlags(&st.ev[k], hipEventDisableTiming) != hipSuccess)
+    return fail(c, HE_EDEVICE, "event create failed");
+  std::memcpy(st.host[k], src, bytes);
+  if (hipMemcpyAsync(dst, st.host[k], bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+    return fail(c, HE_EDEVICE, "staging copy failed");
+  hipEventRecord(st.ev[k], s);
+  st.pending[k] = true;
+  return HE_OK;
+}
+
+bool level_ok(he_ctx* c, int level) { return level >= 1 && level <= c->big_l; }
+
+// Residue table of signed integer scalars w (count values) for limbs < level,
+// laid out [count][level] followed by the Shoup companions.
+std::vector<u64> scalar_table(he_ctx* c, const std::vector<int64_t>& w, int level) {
+  std::vector<u64> tab(2 * w.size() * level);
+  for (size_t k = 0; k < w.size(); ++k) {
+    for (int t = 0; t < level; ++t) {
+      const u64 r = from_signed(w[k], c->mods.m[t]);
+      tab[k * level + t] = r;
+      tab[w.size() * level + k * level + t] = shoup_companion(r, c->moduli[t]);
+    }
+  }
+  return tab;
+}
+
+int64_t round_half_away(double x) {
+  double r = std::floor(std::fabs(x) + 0.5);
+  return (int64_t)(x < 0 ? -r : r);
+}
+
+// out[o] = sum_k w[k][o] * in[k] for integer weights (no rescale).
+int scalar_mac(he_ctx* c, u64* out, const u64* in, int k, const std::vector<int64_t>& w, int o_c, int level,
+               Arena& ar, hipStream_t s) {
+  std::vector<u64> tab = scalar_table(c, w, level);
+  u64* d_tab = ar.take<u64>(tab.size());
+  if (!d_tab) return fail(c, HE_ENOMEM, "workspace too small for weight table");
+  int e = upload(c, d_tab, tab.data(), tab.size() * 8, s);
+  if (e) return e;
+  Prof pr(c, "scalar_mac", s);
+  k_scalar_mac<<<dim3(c->n / 256, level, o_c), 256, 0, s>>>(out, in, k, o_c, d_tab, d_tab + w.size() * level, level,
+                                                            c->n, c->mods);
+  return check_launch(c, "scalar_mac");
+}
+
+}  // namespace
+
+template <int LOGN>
+struct LHoisted {
+  static void run(he_ctx* c, const u64* in, int level, int m, const u64* const* d_keys, const u32* d_gp, u64* dcoef,
+                  u64* dhat, u64* u, u64* rc, u64* outs, hipStream_t s) {
+    constexpr int T = NttGeom<LOGN>::T;
+    constexpr int N = 1 << LOGN;
+    const u64* c1 = in + (size_t)level * N;
+    k_ks_digits<LOGN><<<dim3(level, 1), T, 0, s>>>(c1, 0, 1u, dcoef, level, c->mods, c->d_tw);
+    {
+      Prof pr(c, "modup_store", s);
+      k_modup_store<LOGN><<<dim3(level + 1, level), T, 0, s>>>(dcoef, c1, dhat, level, c->big_l, c->mods, c->d_tw);
+    }
+    {
+      Prof pr(c, "ip_perm", s);
+      k_ip_perm<LOGN><<<dim3(N / 256, level + 1, m), 256, 0, s>>>(dhat, d_keys, d_gp, u, level, c->big_l, c->mods);
+    }
+    k_intt_last<LOGN><<<dim3(2 * m), T, 0, s>>>(u, (size_t)(level + 1) * N, level, c->big_l, rc, c->mods, c->d_tw);
+    EpiArgs ea{outs, (size_t)level * N, in, 0, 1u, 1u, d_gp};
+    LDropLast<LOGN>::run(c, EPI_ROT, u, (size_t)(level + 1) * N, rc, c->big_l, level, 2 * m, ea, s);
+  }
+};
+
+// =============================================================================
+// Public entry points
+// =============================================================================
+
+extern "C" {
+
+int he_params_moduli(const he_params* p, uint64_t* h_out) {
+  if (!p || !h_out) return HE_EINVAL;
+  return gen_moduli(p->n, p->n_q, p->q_bits, p->p_bits, h_out) ? HE_EINVAL : HE_OK;
+}
+
+int he_ctx_create(const he_params* p, he_ctx** out) {
+  if (!p || !out) return HE_EINVAL;
+  *out = nullptr;
+  int logn = 0;
+  while ((1 << logn) < p->n) ++logn;
+  if ((1 << logn) != p->n || logn < 10 || logn > 14) return HE_EUNSUPPORTED;
+  if (p->n_q < 1 || p->n_q >= HE_MAXM) return HE_EINVAL;
+  std::vector<u64> mods(p->n_q + 1);
+  if (gen_moduli(p->n, p->n_q, p->q_bits, p->p_bits, mods.data())) return HE_EINVAL;
+  he_ctx* c = new he_ctx();
+  c->n = p->n;
+  c->logn = logn;
+  c->big_l = p->n_q;
+  c->moduli = mods;
+  hipGetDevice(&c->device);
+  for (int i = 0; i <= p->n_q; ++i) c->mods.m[i] = make_modconst(mods[i], p->n);
+  const size_t n = p->n;
+  std::vector<u64> tw(mods.size() * 4 * n);
+  for (size_t i = 0; i < mods.size(); ++i) {
+    u64* b = tw.data() + i * 4 * n;
+    make_twiddles(mods[i], p->n, b, b + n, b + 2 * n, b + 3 * n);
+  }
+  if (hipMalloc((void**)&c->d_tw, tw.size() * 8) != hipSuccess ||
+      hipMemcpy(c->d_tw, tw.data(), tw.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+    hipFree(c->d_tw);
+    delete c;
+    return HE_EDEVICE;
+  }
+  *out = c;
+  return HE_OK;
+}
+
+int he_ctx_destroy(he_ctx* c) {
+  if (!c) return HE_EINVAL;
+  hipDeviceSynchronize();
+  for (auto& pr : c->prof_events) c->prof_pool.insert(c->prof_pool.end(), {pr.first, pr.second});
+  for (hipEvent_t e : c->prof_pool) hipEventDestroy(e);
+  for (auto& kv : c->keys) hipFree(kv.second);
+  hipFree(c->d_tw);
+  hipFree(c->ws);
+  auto it = g_stage.find(c);
+  if (it != g_stage.end()) {
+    for (int k = 0; k < 2; ++k) {
+      if (it->second.host[k]) hipHostFree(it->second.host[k]);
+      if (it->second.ev[k]) hipEventDestroy(it->second.ev[k]);
+    }
+    g_stage.erase(it);
+  }
+  delete c;
+  return HE_OK;
+}
+
+int he_ctx_reserve(he_ctx* c, size_t bytes) {
+  if (!c) return HE_EINVAL;
+  if (bytes <= c->ws_bytes) return HE_OK;
+  hipDeviceSynchronize();
+  hipFree(c->ws);
+  c->ws = nullptr;
+  c->ws_bytes = 0;
+  if (hipMalloc((void**)&c->ws, bytes) != hipSuccess) return fail(c, HE_ENOMEM, "workspace allocation of %zu bytes failed", bytes);
+  c->ws_bytes = bytes;
+  return HE_OK;
+}
+
+size_t he_ctx_workspace_need(const he_ctx* c, int count, int level) {
+  if (!c || count < 1 || level < 1) return 0;
+  // accumulators (2 level), a second batch of that size (layer intermediates),
+  // key switch temporaries (3 level + 4) and staging tables, in limbs of N.
+  const size_t per = (size_t)(4 * level) + (3 * (size_t)level + 4) + 2;
+  return (size_t)count * per * c->n * 8 + ((size_t)16 << 20);
+}
+
+int he_ctx_moduli(const he_ctx* c, uint64_t* h_out) {
+  if (!c || !h_out) return HE_EINVAL;
+  for (size_t i = 0; i < c->moduli.size(); ++i) h_out[i] = c->moduli[i];
+  return HE_OK;
+}
+
+const char* he_last_error(const he_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int he_ntt(he_ctx* c, uint64_t* d, int n_polys, int n_limbs, int first_mod, void* stream) {
+  if (!c || !d || n_polys < 1 || n_limbs < 1 || n_polys > 65535 || first_mod < 0 || first_mod + n_limbs > c->big_l + 1)
+    return fail(c, HE_EINVAL, "he_ntt: bad arguments");
+  dispatch_logn<LNtt>(c->logn, c, d, n_polys, n_limbs, first_mod, true, S(stream));
+  return check_launch(c, "he_ntt");
+}
+
+int he_intt(he_ctx* c, uint64_t* d, int n_polys, int n_limbs, int first_mod, void* stream) {
+  if (!c || !d || n_polys < 1 || n_limbs < 1 || n_polys > 65535 || first_mod < 0 || first_mod + n_limbs > c->big_l + 1)
+    return fail(c, HE_EINVAL, "he_intt: bad arguments");
+  dispatch_logn<LNtt>(c->logn, c, d, n_polys, n_limbs, first_mod, false, S(stream));
+  return check_launch(c, "he_intt");
+}
+
+int he_add(he_ctx* c, uint64_t* out, const uint64_t* a, const uint64_t* b, int count, int level, void* stream) {
+  if (!c || !out || !a || !b || count < 1 || count > 65535 || !level_ok(c, level)) return fail(c, HE_EINVAL, "he_add: bad arguments");
+  k_add<<<dim3(c->n / 256, level, count), 256, 0, S(stream)>>>(out, a, b, level, c->n, c->mods);
+  return check_launch(c, "he_add");
+}
+
+int he_hma_plain(he_ctx* c, uint64_t* acc, const uint64_t* cts, int k, const uint64_t* pts, int pt_stride, int pt_limbs,
+                 const int32_t* h_galois, int level, int accumulate, void* stream) {
+  if (!c || !acc || !cts || !pts || k < 1 || pt_stride < 0 || pt_limbs < level || !level_ok(c, level))
+    return fail(c, HE_EINVAL, "he_hma_plain: bad arguments");
+  Arena ar(c);
+  const int32_t* d_gal = nullptr;
+  if (h_galois) {
+    for (int i = 0; i < k; ++i)
+      if (h_galois[i] <= 0 || h_galois[i] >= 2 * c->n || !(h_galois[i] & 1))
+        return fail(c, HE_EINVAL, "he_hma_plain: Galois element %d invalid", h_galois[i]);
+    int32_t* g = ar.take<int32_t>(k);
+    if (!g) return fail(c, HE_ENOMEM, "workspace too small");
+    int e = upload(c, g, h_galois, (size_t)k * 4, S(stream));
+    if (e) return e;
+    d_gal = g;
+  }
+  dispatch_logn<LHmaPerm>(c->logn, c, acc, cts, k, pts, pt_stride, pt_limbs, d_gal, 1u, level, accumulate, 1, S(stream));
+  return check_launch(c, "he_hma_plain");
+}
+
+int he_hma_scalar(he_ctx* c, uint64_t* acc, const uint64_t* cts, int k, const int64_t* h_w, int level, int accumulate,
+                  void* stream) {
+  if (!c || !acc || !cts || !h_w || k < 1 || !level_ok(c, level)) return fail(c, HE_EINVAL, "he_hma_scalar: bad arguments");
+  Arena ar(c);
+  std::vector<int64_t> w(h_w, h_w + k);
+  if (!accumulate) return scalar_mac(c, acc, cts, k, w, 1, level, ar, S(stream));
+  u64* tmp = ar.take<u64>((size_t)2 * level * c->n);
+  if (!tmp) return fail(c, HE_ENOMEM, "workspace too small");
+  int e = scalar_mac(c, tmp, cts, k, w, 1, level, ar, S(stream));
+  if (e) return e;
+  return he_add(c, acc, acc, tmp, 1, level, stream);
+}
+
+int he_rescale(he_ctx* c, uint64_t* out, const uint64_t* in, int count, int level, void* stream) {
+  if (!c || !out || !in || count < 1 || level < 2 || level > c->big_l || out == in)
+    return fail(c, HE_EINVAL, "he_rescale: bad arguments");
+  Arena ar(c);
+  return rescale_batch(c, out, in, count, level, ar, S(stream));
+}
+
+int he_keygen_switch(he_ctx* c, int32_t galois, const uint64_t* d_s, const uint64_t* d_a, const int64_t* d_e,
+                     void* stream) {
+  if (!c || !d_s || !d_a || !d_e) return fail(c, HE_EINVAL, "he_keygen_switch: null argument");
+  if (galois != 0 && (galois < 1 || galois >= 2 * c->n || !(galois & 1)))
+    return fail(c, HE_EINVAL, "he_keygen_switch: bad Galois element %d", galois);
+  const int L = c->big_l;
+  const size_t n = c->n;
+  hipStream_t s = S(stream);
+  // ehat[j][t] = NTT(e_j mod m_t)
+  u64* ehat = nullptr;
+  if (hipMalloc((void**)&ehat, (size_t)L * (L + 1) * n * 8) != hipSuccess) return fail(c, HE_ENOMEM, "keygen temp");
+  for (int j = 0; j < L; ++j)
+    k_from_signed<<<dim3(n / 256, L + 1), 256, 0, s>>>(ehat + (size_t)j * (L + 1) * n, d_e + (size_t)j * n, 0, (int)n,
+                                                       c->mods);
+  dispatch_logn<LNtt>(c->logn, c, ehat, L, L + 1, 0, true, s);
+  u64* key = nullptr;
+  auto it = c->keys.find(galois);
+  if (it != c->keys.end()) {
+    key = it->second;
+  } else if (hipMalloc((void**)&key, (size_t)L * 2 * (L + 1) * n * 8) != hipSuccess) {
+    hipFree(ehat);
+    return fail(c, HE_ENOMEM, "key allocation failed");
+  }
+  ConstTable pm{};
+  for (int t = 0; t < L; ++t) {
+    pm.v[t] = c->moduli[L] % c->moduli[t];
+    pm.sh[t] = shoup_companion(pm.v[t], c->moduli[t]);
+  }
+  dispatch_logn<LKeygen>(c->logn, c, key, d_s, d_a, (const u64*)ehat, (u32)galois, pm, s);
+  int e = check_launch(c, "keygen");
+  hipStreamSynchronize(s);
+  hipFree(ehat);
+  if (e) {
+    if (it == c->keys.end()) hipFree(key);
+    return e;
+  }
+  c->keys[galois] = key;
+  return HE_OK;
+}
+
+int he_has_key(const he_ctx* c, int32_t galois) { return c && c->keys.count(galois) ? 1 : 0; }
+
+int he_drop_keys(he_ctx* c) {
+  if (!c) return HE_EINVAL;
+  hipDeviceSynchronize();
+  for (auto& kv : c->keys) hipFree(kv.second);
+  c->keys.clear();
+  return HE_OK;
+}
+
+int he_from_signed(he_ctx* c, uint64_t* d_out, const int64_t* d_coeffs, int n_limbs, int first_mod, void* stream) {
+  if (!c || !d_out || !d_coeffs || n_limbs < 1 || first_mod < 0 || first_mod + n_limbs > c->big_l + 1)
+    return fail(c, HE_EINVAL, "he_from_signed: bad arguments");
+  k_from_signed<<<dim3(c->n / 256, n_limbs), 256, 0, S(stream)>>>(d_out, d_coeffs, first_mod, c->n, c->mods);
+  return check_launch(c, "he_from_signed");
+}
+
+int he_encrypt_sk(he_ctx* c, uint64_t* d_ct, const uint64_t* d_pt, const uint64_t* d_a, const int64_t* d_e,
+                  const uint64_t* d_s, int level, void* stream) {
+  if (!c || !d_ct || !d_pt || !d_a || !d_e || !d_s || !level_ok(c, level)) return fail(c, HE_EINVAL, "he_encrypt_sk: bad arguments");
+  Arena ar(c);
+  u64* ehat = ar.take<u64>((size_t)level * c->n);
+  if (!ehat) return fail(c, HE_ENOMEM, "workspace too small");
+  hipStream_t s = S(stream);
+  k_from_signed<<<dim3(c->n / 256, level), 256, 0, s>>>(ehat, d_e, 0, c->n, c->mods);
+  dispatch_logn<LNtt>(c->logn, c, ehat, 1, level, 0, true, s);
+  k_encrypt<<<dim3(c->n / 256, level), 256, 0, s>>>(d_ct, d_pt, d_a, ehat, d_s, level, c->n, c->mods);
+  return check_launch(c, "he_encrypt_sk");
+}
+
+int he_decrypt(he_ctx* c, uint64_t* d_out, const uint64_t* d_ct, const uint64_t* d_s, int level, void* stream) {
+  if (!c || !d_out || !d_ct || !d_s || !level_ok(c, level)) return fail(c, HE_EINVAL, "he_decrypt: bad arguments");
+  k_decrypt<<<dim3(c->n / 256, level), 256, 0, S(stream)>>>(d_out, d_ct, d_s, level, c->n, c->mods);
+  return check_launch(c, "he_decrypt");
+}
+
+int he_encode_coeffs(int n, const double* h_z, int n_values, double scale, int64_t* h_out) {
+  if (!h_z || !h_out) return HE_EINVAL;
+  return encode_coeffs(n, h_z, n_values, scale, h_out) ? HE_EINVAL : HE_OK;
+}
+
+int he_decode_coeffs(int n, const double* h_m, int n_values, double* h_z) {
+  if (!h_m || !h_z) return HE_EINVAL;
+  return decode_coeffs(n, h_m, n_values, h_z) ? HE_EINVAL : HE_OK;
+}
+
+int he_rotate(he_ctx* c, uint64_t* d_out, const uint64_t* d_in, int count, int level, int k, void* stream) {
+  if (!c || !d_out || !d_in || count < 1 || !level_ok(c, level)) return fail(c, HE_EINVAL, "he_rotate: bad arguments");
+  Arena ar(c);
+  return rotate_batch(c, d_out, d_in, count, level, k, EPI_ROT, ar, S(stream));
+}
+
+int he_rotsum(he_ctx* c, uint64_t* d_cts, int count, int level, int r_steps, void* stream) {
+  if (!c || !d_cts || count < 1 || r_steps < 0 || r_steps > 20 || !level_ok(c, level))
+    return fail(c, HE_EINVAL, "he_rotsum: bad arguments");
+  Arena ar(c);
+  for (int j = 0; j < r_steps; ++j) {
+    int e = rotate_batch(c, d_cts, d_cts, count, level, 1 << j, EPI_ROTSUM, ar, S(stream));
+    if (e) return e;
+  }
+  return HE_OK;
+}
+
+int he_rotate_hoisted(he_ctx* c, const uint64_t* d_in, int level, const int32_t* h_steps, int m, uint64_t* d_outs,
+                      void* stream) {
+  if (!c || !d_in || !h_steps || !d_outs || m < 1 || m > 32000 || !level_ok(c, level))
+    return fail(c, HE_EINVAL, "he_rotate_hoisted: bad arguments");
+  const int n = c->n;
+  std::vector<const u64*> kp(m);
+  std::vector<u32> gp(2 * m);
+  for (int r = 0; r < m; ++r) {
+    const u32 g = galois_of(h_steps[r], n);
+    auto it = c->keys.find((int)g);
+    if (g == 1 || it == c->keys.end())
+      return fail(c, g == 1 ? HE_EINVAL : HE_ENOKEY, "he_rotate_hoisted: no key for step %d", h_steps[r]);
+    kp[r] = it->second;
+    gp[2 * r] = g;
+    gp[2 * r + 1] = galois_of(-h_steps[r], n);
+  }
+  Arena ar(c);
+  u64* dcoef = ar.take<u64>((size_t)level * n);
+  u64* dhat = ar.take<u64>((size_t)level * (level + 1) * n);
+  const u64** d_keys = ar.take<const u64*>(m);
+  u32* d_gp = ar.take<u32>(2 * m);
+  const size_t per = (size_t)2 * (level + 1) * n + 2 * (size_t)n;
+  int chunk = (int)std::min<size_t>((size_t)m, (ar.left() / 8) / (per + 64));
+  if (!dcoef || !dhat || !d_keys || !d_gp || chunk < 1) return fail(c, HE_ENOMEM, "workspace too small for hoisted rotation");
+  u64* u = ar.take<u64>((size_t)chunk * 2 * (level + 1) * n);
+  u64* rc = ar.take<u64>((size_t)chunk * 2 * n);
+  hipStream_t s = S(stream);
+  // one staging copy: key pointers then Galois pairs (both tables are 8-byte aligned)
+  std::vector<char> blob(m * sizeof(u64*) + 2 * m * sizeof(u32));
+  std::memcpy(blob.data(), kp.data(), m * sizeof(u64*));
+  std::memcpy(blob.data() + m * sizeof(u64*), gp.data(), 2 * m * sizeof(u32));
+  // d_keys and d_gp were taken back to back; copy each part to its place
+  int e = upload(c, (void*)d_keys, kp.data(), m * sizeof(u64*), s);
+  if (!e) e = upload(c, d_gp, gp.data(), 2 * m * sizeof(u32), s);
+  if (e) return e;
+  for (int r0 = 0; r0 < m; r0 += chunk) {
+    const int cm = std::min(chunk, m - r0);
+    dispatch_logn<LHoisted>(c->logn, c, d_in, level, cm, (const u64* const*)(d_keys + r0), (const u32*)(d_gp + 2 * r0),
+                            dcoef, dhat, u, rc, d_outs + (size_t)r0 * 2 * level * n, s);
+  }
+  return check_launch(c, "he_rotate_hoisted");
+}
+
+int he_square(he_ctx* c, uint64_t* d_out, const uint64_t* d_in, int count, int level, void* stream) {
+  if (!c || !d_out || !d_in || count < 1 || !level_ok(c, level)) return fail(c, HE_EINVAL, "he_square: bad arguments");
+  Arena ar(c);
+  return square_batch(c, d_out, d_in, count, level, ar, S(stream));
+}
+
+int he_conv_densepack(he_ctx* c, const uint64_t* d_in, int level, const he_conv_desc* desc, const uint64_t* d_filt,
+                      uint64_t* d_out, void* stream) {
+  if (!c || !d_in || !desc || !d_filt || !d_out) return fail(c, HE_EINVAL, "he_conv_densepack: null argument");
+  c->counts = he_counts{};
+  Arena ar(c);
+  return densepack_run(c, d_in, level, desc, d_filt, d_out, ar, S(stream));
+}
+
+int he_conv_convpack(he_ctx* c, const uint64_t* d_in, int k, int level, const double* h_w, int o_c, double w_scale,
+                     uint64_t* d_out, void* stream) {
+  if (!c || !d_in || !h_w || !d_out || k < 1 || o_c < 1 || o_c > 65535 || level < 2 || level > c->big_l)
+    return fail(c, HE_EINVAL, "he_conv_convpack: bad arguments");
+  c->counts = he_counts{};
+  std::vector<int64_t> w((size_t)k * o_c);
+  for (size_t i = 0; i < w.size(); ++i) {
+    const double x = h_w[i] * w_scale;
+    if (!(std::fabs(x) < 4.0e18)) return fail(c, HE_EINVAL, "he_conv_convpack: weight too large for the scale");
+    w[i] = round_half_away(x);
+  }
+  Arena ar(c);
+  u64* z = ar.take<u64>((size_t)o_c * 2 * level * c->n);
+  if (!z) return fail(c, HE_ENOMEM, "workspace too small");
+  hipStream_t s = S(stream);
+  int e = scalar_mac(c, z, d_in, k, w, o_c, level, ar, s);
+  if (!e) e = rescale_batch(c, d_out, z, o_c, level, ar, s);
+  c->counts.mulpc = (int64_t)k * o_c;
+  c->counts.addcc = (int64_t)(k - 1) * o_c;
+  c->counts.rescale = o_c;
+  return e;
+}
+
+int ffconv_layer(he_ctx* c, const uint64_t* d_in, int level, const he_conv_desc* desc, const uint64_t* d_w1_filt,
+                 const uint64_t* d_mask, const double* h_w2, int o_c2, int k_bits, int square, uint64_t* d_out,
+                 void* stream) {
+  if (!c || !d_in || !desc || !d_w1_filt || !d_mask || !h_w2 || !d_out) return fail(c, HE_EINVAL, "ffconv_layer: null argument");
+  const int need = square ? 4 : 3;
+  if (level < need || level > c->big_l) return fail(c, HE_ELEVEL, "ffconv_layer needs level >= %d (got %d)", need, level);
+  if (o_c2 < 1 || k_bits < 0 || k_bits > 40) return fail(c, HE_EINVAL, "ffconv_layer: bad W2 shape or k_bits");
+  c->counts = he_counts{};
+  DPGeom geo;
+  int n_cls = 0;
+  if (!build_geom(c, desc, geo, n_cls)) return fail(c, HE_EINVAL, "bad convolution geometry");
+  const int n = c->n;
+  const int r = desc->o_c;
+  const int spatial = geo.out_h * geo.out_w;
+  const int l1 = level - 1, l2 = level - 2;
+  hipStream_t s = S(stream);
+  Arena ar(c);
+  u64* y = ar.take<u64>((size_t)r * spatial * 2 * l1 * n);
+  u64* g = ar.take<u64>((size_t)r * 2 * l1 * n);
+  u64* z = ar.take<u64>((size_t)o_c2 * 2 * l1 * n);
+  u64* zr = square ? ar.take<u64>((size_t)o_c2 * 2 * l2 * n) : nullptr;
+  u64* sq = square ? ar.take<u64>((size_t)o_c2 * 2 * l2 * n) : nullptr;
+  if (!y || !g || !z || (square && (!zr || !sq))) return fail(c, HE_ENOMEM, "workspace too small for ffconv_layer");
+  // 1. W1 under DensePack (HMA, rotate-and-sum, rescale)
+  int e = densepack_run(c, d_in, level, desc, d_w1_filt, y, ar, s);
+  if (e) return e;
+  // 2. DP->CP gather: G_c = sum_p y_{c,p} * sigma_{5^-p}(E)
+  const u32 g5inv = galois_of(-1, n);  // 5^-1 in the group of odd residues mod 2N
+  dispatch_logn<LHmaPerm>(c->logn, c, g, (const u64*)y, spatial, d_mask, 0, l1, (const int32_t*)nullptr, g5inv, l1, 0, r, s);
+  if ((e = check_launch(c, "gather"))) return e;
+  // 3. 1x1 ConvPack with exact integer weights round(W2 * 2^k)
+  std::vector<int64_t> w((size_t)r * o_c2);
+  for (size_t i = 0; i < w.size(); ++i) w[i] = round_half_away(std::ldexp(h_w2[i], k_bits));
+  if ((e = scalar_mac(c, z, g, r, w, o_c2, l1, ar, s))) return e;
+  // 4. rescale; 5. optional square + relinearise + rescale
+  if (!square) {
+    e = rescale_batch(c, d_out, z, o_c2, l1, ar, s);
+  } else {
+    e = rescale_batch(c, zr, z, o_c2, l1, ar, s);
+    if (!e) e = square_batch(c, sq, zr, o_c2, l2, ar, s);
+    if (!e) e = rescale_batch(c, d_out, sq, o_c2, l2, ar, s);
+  }
+  c->counts.mulpc += (int64_t)r * spatial;      // gather masks
+  c->counts.addcc += (int64_t)r * (spatial - 1) + (int64_t)o_c2 * (r - 1);
+  c->counts.scalar_mul += (int64_t)r * o_c2;
+  c->counts.rescale += o_c2 * (square ? 2 : 1);
+  c->counts.square += square ? o_c2 : 0;
+  return e;
+}
+
+int he_prof_select(he_ctx* c, const char* kernel) {
+  if (!c) return HE_EINVAL;
+  c->prof_kernel = kernel ? kernel : "";
+  double ms;
+  int64_t n;
+  return he_prof_read(c, &ms, &n);
+}
+
+int he_prof_read(he_ctx* c, double* total_ms, int64_t* launches) {
+  if (!c || !total_ms || !launches) return HE_EINVAL;
+  double sum = 0;
+  for (auto& pr : c->prof_events) {
+    float ms = 0;
+    if (hipEventSynchronize(pr.second) != hipSuccess || hipEventElapsedTime(&ms, pr.first, pr.second) != hipSuccess)
+      return fail(c, HE_EDEVICE, "he_prof_read: event failure");
+    sum += ms;
+    c->prof_pool.push_back(pr.first);
+    c->prof_pool.push_back(pr.second);
+  }
+  *total_ms = sum;
+  *launches = (int64_t)c->prof_events.size();
+  c->prof_events.clear();
+  return HE_OK;
+}
+
+int he_last_counts(const he_ctx* c, he_counts* out) {
+  if (!c || !out) return HE_EINVAL;
+  *out = c->counts;
+  return HE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,132 @@
+// Modular arithmetic for RNS limbs on gfx950 (and the host).
+//
+// Residues are uint64 in [0, q).  Each prime is one of two width classes,
+// chosen per limb and uniform across a workgroup:
+//   narrow  q < 2^31 : products fit 64 bits; reductions use 32-bit multiplies
+//                      (v_mul_hi_u32 / v_mad_u64_u32);
+//   wide    q < 2^62 : 128-bit products from __umul64hi.
+// Products with a fixed operand (twiddles, inverses) use Shoup's method with a
+// precomputed companion w' = floor(w * 2^32 / q) (narrow) or
+// floor(w * 2^64 / q) (wide).  Products of two data operands use Barrett
+// reduction with s = bitlen(q) and mu = floor(2^(2s) / q): the quotient
+// estimate floor(floor(x / 2^(s-1)) * mu / 2^(s+1)) is at most 2 below the
+// true quotient, so two conditional subtractions finish.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace he {
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+
+struct ModConst {
+  u64 q;
+  u64 mu64;    // floor((2^64 - 1) / q): Barrett for any 64-bit input
+  u64 bmu;     // floor(2^(2s) / q): Barrett for products of residues
+  u32 s;       // bit length of q
+  u32 narrow;  // q < 2^31
+  u64 n_inv;   // N^-1 mod q
+  u64 n_inv_sh;
+};
+
+__host__ __device__ inline u64 mulhi64(u64 a, u64 b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __umul64hi(a, b);
+#else
+  return (u64)(((unsigned __int128)a * b) >> 64);
+#endif
+}
+
+__host__ __device__ inline u64 add_mod(u64 a, u64 b, u64 q) {
+  u64 s = a + b;
+  return s >= q ? s - q : s;
+}
+
+__host__ __device__ inline u64 sub_mod(u64 a, u64 b, u64 q) {
+  return a >= b ? a - b : a + (q - b);
+}
+
+// a * w mod q with Shoup companion wsh; a < 2^32 (narrow) or any a (wide).
+__host__ __device__ inline u64 mul_shoup(u64 a, u64 w, u64 wsh, u64 q, bool narrow) {
+  if (narrow) {
+    u32 a32 = (u32)a;
+    u32 qh = (u32)(((u64)a32 * (u32)wsh) >> 32);
+    u32 r = a32 * (u32)w - qh * (u32)q;
+    return r >= (u32)q ? r - (u32)q : r;
+  }
+  u64 qh = mulhi64(a, wsh);
+  u64 r = a * w - qh * q;
+  return r >= q ? r - q : r;
+}
+
+// a * b mod q for residues a, b < q.
+__host__ __device__ inline u64 mul_mod(u64 a, u64 b, const ModConst& m) {
+  const u64 q = m.q;
+  const u32 s = m.s;
+  if (m.narrow) {
+    u64 x = (u64)(u32)a * (u32)b;                    // < 2^62
+    u32 t = (u32)(x >> (s - 1));                     // < 2^(s+1) <= 2^32
+    u64 qh = ((u64)t * (u32)m.bmu) >> (s + 1);       // quotient estimate
+    u64 r = x - qh * q;                              // < 3q
+    if (r >= q) r -= q;
+    if (r >= q) r -= q;
+    return r;
+  }
+  u64 lo = a * b, hi = mulhi64(a, b);                // x < 2^(2s)
+  u64 t = (hi << (65 - s)) | (lo >> (s - 1));        // x >> (s-1) < 2^(s+1)
+  u64 plo = t * m.bmu, phi = mulhi64(t, m.bmu);
+  u64 qh = (phi << (63 - s)) | (plo >> (s + 1));     // (t * mu) >> (s+1)
+  u64 r = lo - qh * q;                               // < 3q, exact mod 2^64
+  if (r >= q) r -= q;
+  if (r >= q) r -= q;
+  return r;
+}
+
+// v mod q for any 64-bit v.
+__host__ __device__ inline u64 reduce64(u64 v, const ModConst& m) {
+  u64 qh = mulhi64(v, m.mu64);
+  u64 r = v - qh * m.q;
+  return r >= m.q ? r - m.q : r;
+}
+
+// Centred representative of v (a residue mod qs, qs odd) reduced mod m.
+__host__ __device__ inline u64 lift_centered(u64 v, u64 qs, const ModConst& m) {
+  if (v <= (qs - 1) / 2) return reduce64(v, m);
+  u64 r = reduce64(qs - v, m);
+  return r ? m.q - r : 0;
+}
+
+// Signed integer (|x| < 2^63) reduced mod m.
+__host__ __device__ inline u64 from_signed(int64_t x, const ModConst& m) {
+  if (x >= 0) return reduce64((u64)x, m);
+  u64 r = reduce64((u64)(-(x + 1)) + 1, m);  // |x| without overflow at INT64_MIN+1
+  return r ? m.q - r : 0;
+}
+
+// Compile-time width class variants (the class is uniform per workgroup).
+template <bool NARROW>
+__host__ __device__ inline u64 mul_mod_t(u64 a, u64 b, const ModConst& m) {
+  const u64 q = m.q;
+  const u32 s = m.s;
+  if constexpr (NARROW) {
+    u64 x = (u64)(u32)a * (u32)b;
+    u32 t = (u32)(x >> (s - 1));
+    u64 qh = ((u64)t * (u32)m.bmu) >> (s + 1);
+    u64 r = x - qh * q;
+    if (r >= q) r -= q;
+    if (r >= q) r -= q;
+    return r;
+  } else {
+    u64 lo = a * b, hi = mulhi64(a, b);
+    u64 t = (hi << (65 - s)) | (lo >> (s - 1));
+    u64 plo = t * m.bmu, phi = mulhi64(t, m.bmu);
+    u64 qh = (phi << (63 - s)) | (plo >> (s + 1));
+    u64 r = lo - qh * q;
+    if (r >= q) r -= q;
+    if (r >= q) r -= q;
+    return r;
+  }
+}
+
+}  // namespace he

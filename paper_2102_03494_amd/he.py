@@ -1,0 +1,318 @@
+"""Thin Python binding of the C ABI (include/ffconv_he.h).
+
+Argument marshalling only: device buffers are torch tensors (dtype int64
+holding the uint64 residues bit for bit) whose data pointers are handed to
+the library together with torch's current HIP stream.  Every computation runs
+in the library's HIP kernels.  Scale bookkeeping (a float per ciphertext) is
+kept here, on the host, with the same IEEE operations as the layer contract
+documents.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import HeConvDesc, HeCounts, HeParams
+
+
+class HEError(RuntimeError):
+    pass
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    if not t.is_cuda:
+        raise HEError("expected a device tensor")
+    if not t.is_contiguous():
+        raise HEError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def to_device(a: np.ndarray, device="cuda") -> torch.Tensor:
+    """uint64 numpy array -> int64 device tensor with the same bits."""
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint64:
+        a = a.view(np.int64)
+    return torch.from_numpy(a.copy()).to(device)
+
+
+def to_host(t: torch.Tensor) -> np.ndarray:
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+def galois_for_rotation(k: int, n: int) -> int:
+    slots = n // 2
+    return pow(5, k % slots, 2 * n)
+
+
+@dataclass
+class Ct:
+    """A batch of ciphertexts [count][2][level][N] on the device plus its scale."""
+    data: torch.Tensor
+    scale: float
+
+    @property
+    def level(self) -> int:
+        return self.data.shape[-2]
+
+    @property
+    def count(self) -> int:
+        return int(np.prod(self.data.shape[:-3], dtype=np.int64)) if self.data.dim() > 3 else 1
+
+
+class HEContext:
+    def __init__(self, n: int, q_bits, p_bits: int, workspace_bytes: int = 0):
+        self.lib = _lib.lib()
+        self.n = int(n)
+        self.q_bits = tuple(int(b) for b in q_bits)
+        self.p_bits = int(p_bits)
+        self.L = len(self.q_bits)
+        prm = HeParams()
+        prm.n = self.n
+        prm.n_q = self.L
+        for i, b in enumerate(self.q_bits):
+            prm.q_bits[i] = b
+        prm.p_bits = self.p_bits
+        self._params = prm
+        h = ctypes.c_void_p()
+        self._check(self.lib.he_ctx_create(ctypes.byref(prm), ctypes.byref(h)), "he_ctx_create", ctx=None)
+        self.h = h
+        out = (ctypes.c_uint64 * (self.L + 1))()
+        self._check(self.lib.he_ctx_moduli(self.h, out), "he_ctx_moduli")
+        self.moduli = [int(v) for v in out]
+        self.q = self.moduli[: self.L]
+        self.p = self.moduli[self.L]
+        if workspace_bytes:
+            self.reserve(workspace_bytes)
+
+    # ---- plumbing --------------------------------------------------------
+    def _check(self, rc: int, what: str, ctx="self"):
+        if rc != 0:
+            msg = ""
+            if ctx == "self" and getattr(self, "h", None) is not None:
+                msg = self.lib.he_last_error(self.h).decode()
+            raise HEError(f"{what} failed with code {rc}: {msg}")
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            self.lib.he_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def params_moduli(n, q_bits, p_bits) -> list[int]:
+        lib = _lib.lib()
+        prm = HeParams()
+        prm.n = n
+        prm.n_q = len(q_bits)
+        for i, b in enumerate(q_bits):
+            prm.q_bits[i] = b
+        prm.p_bits = p_bits
+        out = (ctypes.c_uint64 * (len(q_bits) + 1))()
+        rc = lib.he_params_moduli(ctypes.byref(prm), out)
+        if rc != 0:
+            raise HEError(f"he_params_moduli failed with code {rc}")
+        return [int(v) for v in out]
+
+    def reserve(self, nbytes: int):
+        self._check(self.lib.he_ctx_reserve(self.h, ctypes.c_size_t(int(nbytes))), "he_ctx_reserve")
+
+    def workspace_need(self, count: int, level: int) -> int:
+        return int(self.lib.he_ctx_workspace_need(self.h, count, level))
+
+    def empty_ct(self, count: int, level: int) -> torch.Tensor:
+        return torch.empty((count, 2, level, self.n), dtype=torch.int64, device="cuda")
+
+    def last_counts(self) -> dict:
+        c = HeCounts()
+        self._check(self.lib.he_last_counts(self.h, ctypes.byref(c)), "he_last_counts")
+        return {k: int(getattr(c, k)) for k, _ in HeCounts._fields_}
+
+    def prof_select(self, kernel: str | None):
+        """Record HIP events around every launch of `kernel` (None stops)."""
+        self._check(self.lib.he_prof_select(self.h, (kernel or "").encode()), "he_prof_select")
+
+    def prof_read(self) -> tuple[float, int]:
+        """(summed kernel milliseconds, launches) since the last select/read."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._check(self.lib.he_prof_read(self.h, ctypes.byref(ms), ctypes.byref(n)), "he_prof_read")
+        return float(ms.value), int(n.value)
+
+    # ---- transforms ----------------------------------------------------------
+    def ntt(self, polys: torch.Tensor, first_mod: int = 0):
+        n_limbs = polys.shape[-2]
+        n_polys = polys.numel() // (n_limbs * self.n)
+        self._check(self.lib.he_ntt(self.h, _ptr(polys), n_polys, n_limbs, first_mod, _stream()), "he_ntt")
+
+    def intt(self, polys: torch.Tensor, first_mod: int = 0):
+        n_limbs = polys.shape[-2]
+        n_polys = polys.numel() // (n_limbs * self.n)
+        self._check(self.lib.he_intt(self.h, _ptr(polys), n_polys, n_limbs, first_mod, _stream()), "he_intt")
+
+    # ---- elementwise -----------------------------------------------------------
+    def add(self, out: torch.Tensor, a: torch.Tensor, b: torch.Tensor):
+        level = a.shape[-2]
+        count = a.numel() // (2 * level * self.n)
+        self._check(self.lib.he_add(self.h, _ptr(out), _ptr(a), _ptr(b), count, level, _stream()), "he_add")
+
+    def hma_plain(self, acc: torch.Tensor, cts: torch.Tensor, pts: torch.Tensor, pt_stride: int,
+                  galois=None, accumulate: bool = False):
+        level = acc.shape[-2]
+        k = cts.numel() // (2 * level * self.n)
+        pt_limbs = pts.shape[-2]
+        gal = None
+        if galois is not None:
+            gal = (ctypes.c_int32 * k)(*[int(g) for g in galois])
+        self._check(self.lib.he_hma_plain(self.h, _ptr(acc), _ptr(cts), k, _ptr(pts), pt_stride, pt_limbs, gal,
+                                          level, int(accumulate), _stream()), "he_hma_plain")
+
+    def hma_scalar(self, acc: torch.Tensor, cts: torch.Tensor, weights, accumulate: bool = False):
+        level = acc.shape[-2]
+        k = len(weights)
+        w = (ctypes.c_int64 * k)(*[int(x) for x in weights])
+        self._check(self.lib.he_hma_scalar(self.h, _ptr(acc), _ptr(cts), k, w, level, int(accumulate), _stream()),
+                    "he_hma_scalar")
+
+    def rescale(self, ct: Ct) -> Ct:
+        level = ct.level
+        count = ct.data.numel() // (2 * level * self.n)
+        out = torch.empty(ct.data.shape[:-2] + (level - 1, self.n), dtype=torch.int64, device="cuda")
+        self._check(self.lib.he_rescale(self.h, _ptr(out), _ptr(ct.data), count, level, _stream()), "he_rescale")
+        return Ct(out, ct.scale / self.q[level - 1])
+
+    # ---- keys / client -----------------------------------------------------------
+    def keygen_switch(self, galois: int, s_ntt: torch.Tensor, a: torch.Tensor, e: torch.Tensor):
+        self._check(self.lib.he_keygen_switch(self.h, int(galois), _ptr(s_ntt), _ptr(a), _ptr(e), _stream()),
+                    "he_keygen_switch")
+
+    def has_key(self, galois: int) -> bool:
+        return bool(self.lib.he_has_key(self.h, int(galois)))
+
+    def drop_keys(self):
+        self._check(self.lib.he_drop_keys(self.h), "he_drop_keys")
+
+    def from_signed(self, coeffs: torch.Tensor, n_limbs: int, first_mod: int = 0) -> torch.Tensor:
+        out = torch.empty((n_limbs, self.n), dtype=torch.int64, device="cuda")
+        self._check(self.lib.he_from_signed(self.h, _ptr(out), _ptr(coeffs), n_limbs, first_mod, _stream()),
+                    "he_from_signed")
+        return out
+
+    def encrypt_sk(self, pt: torch.Tensor, a: torch.Tensor, e: torch.Tensor, s_ntt: torch.Tensor) -> torch.Tensor:
+        level = pt.shape[-2]
+        ct = torch.empty((2, level, self.n), dtype=torch.int64, device="cuda")
+        self._check(self.lib.he_encrypt_sk(self.h, _ptr(ct), _ptr(pt), _ptr(a), _ptr(e), _ptr(s_ntt), level,
+                                           _stream()), "he_encrypt_sk")
+        return ct
+
+    def decrypt(self, ct: torch.Tensor, s_ntt: torch.Tensor) -> torch.Tensor:
+        level = ct.shape[-2]
+        out = torch.empty((level, self.n), dtype=torch.int64, device="cuda")
+        self._check(self.lib.he_decrypt(self.h, _ptr(out), _ptr(ct), _ptr(s_ntt), level, _stream()), "he_decrypt")
+        return out
+
+    def encode_coeffs(self, z, scale: float) -> np.ndarray:
+        z = np.ascontiguousarray(np.asarray(z, dtype=np.float64))
+        out = np.empty(self.n, dtype=np.int64)
+        rc = self.lib.he_encode_coeffs(self.n, z.ctypes.data_as(_lib.DP), len(z), float(scale),
+                                       out.ctypes.data_as(_lib.I64P))
+        if rc != 0:
+            raise HEError("he_encode_coeffs failed (value too large for the scale?)")
+        return out
+
+    def decode_coeffs(self, m, n_values: int) -> np.ndarray:
+        m = np.ascontiguousarray(np.asarray(m, dtype=np.float64))
+        out = np.empty(n_values, dtype=np.float64)
+        rc = self.lib.he_decode_coeffs(self.n, m.ctypes.data_as(_lib.DP), n_values, out.ctypes.data_as(_lib.DP))
+        if rc != 0:
+            raise HEError("he_decode_coeffs failed")
+        return out
+
+    # ---- rotations / square --------------------------------------------------------
+    def rotate(self, ct: Ct, k: int, out: torch.Tensor | None = None) -> Ct:
+        level = ct.level
+        count = ct.data.numel() // (2 * level * self.n)
+        out = torch.empty_like(ct.data) if out is None else out
+        self._check(self.lib.he_rotate(self.h, _ptr(out), _ptr(ct.data), count, level, int(k), _stream()),
+                    "he_rotate")
+        return Ct(out, ct.scale)
+
+    def rotate_hoisted(self, ct: Ct, steps) -> Ct:
+        level = ct.level
+        m = len(steps)
+        arr = (ctypes.c_int32 * m)(*[int(k) for k in steps])
+        out = torch.empty((m, 2, level, self.n), dtype=torch.int64, device="cuda")
+        self._check(self.lib.he_rotate_hoisted(self.h, _ptr(ct.data), level, arr, m, _ptr(out), _stream()),
+                    "he_rotate_hoisted")
+        return Ct(out, ct.scale)
+
+    def rotsum(self, ct: Ct, r_steps: int):
+        level = ct.level
+        count = ct.data.numel() // (2 * level * self.n)
+        self._check(self.lib.he_rotsum(self.h, _ptr(ct.data), count, level, int(r_steps), _stream()), "he_rotsum")
+
+    def square(self, ct: Ct) -> Ct:
+        level = ct.level
+        count = ct.data.numel() // (2 * level * self.n)
+        out = torch.empty_like(ct.data)
+        self._check(self.lib.he_square(self.h, _ptr(out), _ptr(ct.data), count, level, _stream()), "he_square")
+        return Ct(out, ct.scale * ct.scale)
+
+    # ---- layers ----------------------------------------------------------------------
+    @staticmethod
+    def conv_desc(h, w, c_in, d, stride, pad, o_c, r_steps) -> HeConvDesc:
+        desc = HeConvDesc()
+        for k, v in dict(h=h, w=w, c_in=c_in, d=d, stride=stride, pad=pad, o_c=o_c, r_steps=r_steps).items():
+            setattr(desc, k, int(v))
+        return desc
+
+    def conv_densepack(self, x: Ct, desc: HeConvDesc, filt: torch.Tensor, pt_scale: float,
+                       out: torch.Tensor | None = None) -> Ct:
+        level = x.level
+        oh = (desc.h + 2 * desc.pad - desc.d) // desc.stride + 1
+        ow = (desc.w + 2 * desc.pad - desc.d) // desc.stride + 1
+        total = oh * ow * desc.o_c
+        if out is None:
+            out = torch.empty((total, 2, level - 1, self.n), dtype=torch.int64, device="cuda")
+        self._check(self.lib.he_conv_densepack(self.h, _ptr(x.data), level, ctypes.byref(desc), _ptr(filt),
+                                               _ptr(out), _stream()), "he_conv_densepack")
+        return Ct(out, x.scale * pt_scale / self.q[level - 1])
+
+    def conv_convpack(self, x: Ct, w: np.ndarray, w_scale: float) -> Ct:
+        level = x.level
+        k, o_c = w.shape
+        wf = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
+        out = torch.empty((o_c, 2, level - 1, self.n), dtype=torch.int64, device="cuda")
+        self._check(self.lib.he_conv_convpack(self.h, _ptr(x.data), k, level, wf.ctypes.data_as(_lib.DP), o_c,
+                                              float(w_scale), _ptr(out), _stream()), "he_conv_convpack")
+        return Ct(out, x.scale * w_scale / self.q[level - 1])
+
+    def ffconv_layer(self, x: Ct, desc: HeConvDesc, w1_filt: torch.Tensor, w1_pt_scale: float,
+                     mask: torch.Tensor, mask_scale: float, w2: np.ndarray, k_bits: int, square: bool,
+                     out: torch.Tensor | None = None) -> Ct:
+        level = x.level
+        r, o_c2 = w2.shape
+        wf = np.ascontiguousarray(np.asarray(w2, dtype=np.float64))
+        lvl_out = level - 2 - (1 if square else 0)
+        if out is None:
+            out = torch.empty((o_c2, 2, lvl_out, self.n), dtype=torch.int64, device="cuda")
+        self._check(self.lib.ffconv_layer(self.h, _ptr(x.data), level, ctypes.byref(desc), _ptr(w1_filt),
+                                          _ptr(mask), wf.ctypes.data_as(_lib.DP), o_c2, int(k_bits), int(square),
+                                          _ptr(out), _stream()), "ffconv_layer")
+        y_scale = x.scale * w1_pt_scale / self.q[level - 1]
+        z_scale = y_scale * mask_scale * 2.0**k_bits / self.q[level - 2]
+        if square:
+            z_scale = z_scale * z_scale / self.q[level - 3]
+        return Ct(out, z_scale)

@@ -1,0 +1,155 @@
+"""Server-side layer set-up: packing layouts, plaintext weights and scales.
+
+The weights stay in plaintext on the server (Section 3, MLaaS scenario).
+This module lays them out in slots as the C ABI expects (DensePack, Section
+3.2 and Fig. 1; the DP->CP mask of FFConv, Section 4.2), encodes them with the
+client-library encoder into NTT-domain plaintexts on the device, and computes
+the plaintext scales.  The evaluation itself is one library call.
+
+Scale rule: a plaintext multiply followed by a rescale that drops q_l is
+encoded at q_l * target / current so the rescale lands on `target`; before a
+square the target is sqrt(q_next * scale) so that square + rescale returns to
+`scale`.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from .he import HEContext
+
+
+@dataclass(frozen=True)
+class Geometry:
+    h: int
+    w: int
+    c_in: int
+    d: int
+    stride: int = 1
+    pad: int = 0
+
+    @property
+    def out_h(self):
+        return (self.h + 2 * self.pad - self.d) // self.stride + 1
+
+    @property
+    def out_w(self):
+        return (self.w + 2 * self.pad - self.d) // self.stride + 1
+
+    @property
+    def spatial(self):
+        return self.out_h * self.out_w
+
+    def per_ct(self, slots):
+        return min(self.c_in, slots // (self.h * self.w))
+
+    def n_cts(self, slots):
+        return -(-self.c_in // self.per_ct(slots))
+
+    def _axis_classes(self, out, size):
+        seen, ids = [], []
+        for i in range(out):
+            start = self.stride * i - self.pad
+            r = (max(0, -start), min(self.d, size - start))
+            if r not in seen:
+                seen.append(r)
+            ids.append(seen.index(r))
+        return seen, ids
+
+    def classes(self):
+        """(row tap ranges, column tap ranges); class = row_class * n_cols + col_class."""
+        rows, _ = self._axis_classes(self.out_h, self.h)
+        cols, _ = self._axis_classes(self.out_w, self.w)
+        return rows, cols
+
+
+def densepack_layout(x: np.ndarray, g: Geometry, slots: int) -> list[np.ndarray]:
+    """Slot vectors of X[h][w][c]: value (h, w, c) at slot (c mod B)*H*W + h*W + w of ct c // B."""
+    per = g.per_ct(slots)
+    vecs = []
+    for m in range(g.n_cts(slots)):
+        v = np.zeros(slots)
+        for cl in range(per):
+            c = m * per + cl
+            if c < g.c_in:
+                v[cl * g.h * g.w:(cl + 1) * g.h * g.w] = x[:, :, c].ravel()
+        vecs.append(v)
+    return vecs
+
+
+def filter_layout(weights: np.ndarray, g: Geometry, slots: int, o: int, cls: int, m: int) -> np.ndarray:
+    rows, cols = g.classes()
+    kh0, kh1 = rows[cls // len(cols)]
+    kw0, kw1 = cols[cls % len(cols)]
+    per = g.per_ct(slots)
+    v = np.zeros(slots)
+    for cl in range(per):
+        c = m * per + cl
+        if c >= g.c_in:
+            break
+        for kh in range(kh0, kh1):
+            for kw in range(kw0, kw1):
+                v[cl * g.h * g.w + kh * g.w + kw] = weights[kh, kw, c, o]
+    return v
+
+
+def encode_filters(client, weights: np.ndarray, g: Geometry, level: int, pt_scale: float) -> torch.Tensor:
+    """Base filter plaintexts [O_c][classes][M][level][N] on the device."""
+    ctx = client.ctx
+    rows, cols = g.classes()
+    n_cls = len(rows) * len(cols)
+    m_cts = g.n_cts(ctx.n // 2)
+    o_c = weights.shape[3]
+    out = torch.empty((o_c, n_cls, m_cts, level, ctx.n), dtype=torch.int64, device="cuda")
+    for o in range(o_c):
+        for b in range(n_cls):
+            for m in range(m_cts):
+                out[o, b, m] = client.encode(filter_layout(weights, g, ctx.n // 2, o, b, m), level, pt_scale)
+    return out
+
+
+def pt_scale_for(ctx: HEContext, level: int, in_scale: float, target: float) -> float:
+    return ctx.q[level - 1] * target / in_scale
+
+
+def pre_square_target(ctx: HEContext, level_after_rescale: int, scale: float) -> float:
+    return math.sqrt(ctx.q[level_after_rescale - 1] * scale)
+
+
+def mask_scale_for(ctx: HEContext, level: int, y_scale: float, target: float, k_bits: int) -> float:
+    return ctx.q[level - 1] * target / (y_scale * 2.0**k_bits)
+
+
+def onehot_mask(client, level: int, scale: float) -> torch.Tensor:
+    z = np.zeros(client.ctx.n // 2)
+    z[0] = 1.0
+    return client.encode(z, level, scale)
+
+
+def rot_steps(ctx: HEContext) -> list[int]:
+    return [1 << j for j in range(int(math.log2(ctx.n // 2)))]
+
+
+def reference_conv2d(x: np.ndarray, weights: np.ndarray, stride: int = 1, pad: int = 0) -> np.ndarray:
+    """FP64 plaintext convolution (for accuracy reports): Z[i][j][o]."""
+    h, w, c = x.shape
+    d = weights.shape[0]
+    oh = (h + 2 * pad - d) // stride + 1
+    ow = (w + 2 * pad - d) // stride + 1
+    xp = np.zeros((h + 2 * pad, w + 2 * pad, c))
+    xp[pad:pad + h, pad:pad + w] = x
+    out = np.zeros((oh, ow, weights.shape[3]))
+    for kh in range(d):
+        for kw in range(d):
+            patch = xp[kh:kh + stride * oh:stride, kw:kw + stride * ow:stride, :]  # (oh, ow, c)
+            out += np.tensordot(patch, weights[kh, kw], axes=([2], [0]))
+    return out
+
+
+def compose_factors(w1: np.ndarray, w2: np.ndarray) -> np.ndarray:
+    """d x d x I_c x O_c filters of W1 followed by the 1x1 W2 (O'_c x O_c)."""
+    d1, d2, c, r = w1.shape
+    return (w1.reshape(d1 * d2 * c, r) @ w2).reshape(d1, d2, c, w2.shape[1])

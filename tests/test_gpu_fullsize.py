@@ -1,0 +1,129 @@
+"""GPU parity at the evaluated sizes, in the launch configuration bench.py times.
+
+* Plain 28x28x1 conv, 5x5 stride 2, 5 channels at N = 4096 (2 x 30-bit +
+  36-bit P): all 720 DensePack outputs on the GPU; a sample (first, last and
+  spread, covering every output channel) is recomputed by the oracle and must
+  match bit for bit; every output decrypts to within 1e-3 of the FP64 conv.
+* FFConv 1 -> 2 -> 5 with x^2 at N = 8192 (4 x 30-bit + 40-bit P): the W1
+  DensePack outputs are checked bit for bit on a sample; the whole layer and
+  the plain comparator (W1 W2 composed, then x^2) decrypt to within 1e-3.
+Inputs and plaintexts come from the oracle; the GPU generates its own keys.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import synth  # noqa: E402
+from oracle import conv as C  # noqa: E402
+from oracle import params as P  # noqa: E402
+from oracle import reference as R  # noqa: E402
+from oracle import scheme as S  # noqa: E402
+from oracle import workloads as Wk  # noqa: E402
+
+
+def _he():
+    from paper_2102_03494_amd import he
+    return he
+
+
+def _setup(p, workload, relin=False):
+    he = _he()
+    from paper_2102_03494_amd.client import Client
+    steps = C.rotate_and_sum_steps(p)
+    octx = Wk.make_context(p, workload, rotations=steps, relin=relin)
+    gctx = he.HEContext(p.n, p.q_bits, p.p_bits)
+    gctx.reserve(gctx.workspace_need(720, p.max_level) + (1 << 28))
+    assert gctx.moduli == p.q + [p.p]
+    cl = Client(gctx, workload)
+    cl.gen_rotation_keys(steps)
+    if relin:
+        cl.gen_relin_key()
+    return octx, gctx, cl, len(steps)
+
+
+def _sample(total, spatial, k=6):
+    idx = {0, total - 1}
+    for o in range(total // spatial):
+        idx.add(o * spatial + (7 * o + 3) % spatial)
+    return sorted(idx)[:k + total // spatial]
+
+
+def test_plain_n4096_full_layer():
+    wl = "plain_n4096"
+    p = P.plain_n4096()
+    octx, gctx, cl, r = _setup(p, wl)
+    geom = C.ConvGeom(28, 28, 1, 5, 2, 0)
+    x = synth.image(wl, (28, 28, 1))
+    w = synth.weights(wl, 1, (5, 5, 1, 5), 0.1)
+    ct = Wk.encrypt_slots(octx, C.densepack_slots(x, geom, p.slots)[0], 2, p.scale, wl, 0)
+    pts = C.densepack_pt_scale(p, 2, p.scale, p.scale)
+    bf = C.densepack_base_filters(p, w, geom, 2, pts)
+    he = _he()
+    desc = he.HEContext.conv_desc(28, 28, 1, 5, 2, 0, 5, r)
+    got = gctx.conv_densepack(he.Ct(he.to_device(ct.c[None]), p.scale), desc, he.to_device(bf), pts)
+    torch.cuda.synchronize()
+    assert tuple(got.data.shape) == (720, 2, 1, p.n)
+    outs = C.output_list(geom, 5)
+    sample = _sample(720, geom.spatial)
+    want, _ = C.conv_densepack(p, octx, ct, geom, bf, pts, outputs=[outs[i] for i in sample])
+    bits = he.to_host(got.data)
+    for k, i in enumerate(sample):
+        assert np.array_equal(bits[i], want.c[k]), i
+    ref = R.conv2d(x, w, 2, 0)
+    errs = []
+    for idx, (o, i, j) in enumerate(outs):
+        v = cl.decrypt(got.data[idx], got.scale, 1, limbs=1)
+        errs.append(abs(v[0] - ref[i, j, o]))
+    assert max(errs) < 1e-3
+
+
+def test_ffconv_n8192_full_layer_and_plain_comparator():
+    wl = "ffconv_n8192"
+    p = P.ffconv_n8192()
+    octx, gctx, cl, r = _setup(p, wl, relin=True)
+    geom = C.ConvGeom(28, 28, 1, 5, 2, 0)
+    x = synth.image(wl, (28, 28, 1))
+    w1 = synth.weights(wl, 1, (5, 5, 1, 2), 0.1)
+    w2 = synth.weights(wl, 2, (2, 5), 0.1)
+    level = 4
+    ct = Wk.encrypt_slots(octx, C.densepack_slots(x, geom, p.slots)[0], level, p.scale, wl, 0)
+    he = _he()
+    xin = he.Ct(he.to_device(ct.c[None]), p.scale)
+    pts = C.densepack_pt_scale(p, level, p.scale, p.scale)
+    bf = C.densepack_base_filters(p, w1, geom, level, pts)
+    desc = he.HEContext.conv_desc(28, 28, 1, 5, 2, 0, 2, r)
+    # W1 DensePack, sampled bit-exact
+    y = gctx.conv_densepack(xin, desc, he.to_device(bf), pts)
+    outs = C.output_list(geom, 2)
+    sample = _sample(288, geom.spatial, k=3)
+    want, _ = C.conv_densepack(p, octx, ct, geom, bf, pts, outputs=[outs[i] for i in sample])
+    bits = he.to_host(y.data)
+    for k, i in enumerate(sample):
+        assert np.array_equal(bits[i], want.c[k]), i
+    # whole FFConv layer with x^2: decrypted accuracy for all 5 x 144 values
+    target = C.pre_square_target(p, level - 2, p.scale)
+    ms = C.gather_mask_scale(p, level - 1, y.scale, target, 12)
+    mask = C.encode_onehot(p, level - 1, ms)
+    z = gctx.ffconv_layer(xin, desc, he.to_device(bf), pts, he.to_device(mask), ms, w2, 12, True)
+    counts = gctx.last_counts()
+    assert counts["rot"] == 288 * 12 and counts["scalar_mul"] == 10 and counts["square"] == 5
+    ref = R.ffconv_reference(x, w1, w2, 2, 0, square=True)
+    for o in range(5):
+        v = cl.decrypt(z.data[o], z.scale, geom.spatial, limbs=1)
+        assert np.abs(v - ref[:, :, o].ravel()).max() < 1e-3
+    # plain comparator: W1 W2 composed, DensePack, x^2
+    wp = R.compose_factors(w1, w2)
+    target_pl = C.pre_square_target(p, level - 1, p.scale)
+    pts_pl = C.densepack_pt_scale(p, level, p.scale, target_pl)
+    bfp = C.densepack_base_filters(p, wp, geom, level, pts_pl)
+    descp = he.HEContext.conv_desc(28, 28, 1, 5, 2, 0, 5, r)
+    yp = gctx.conv_densepack(xin, descp, he.to_device(bfp), pts_pl)
+    zp = gctx.rescale(gctx.square(yp))
+    refp = R.conv2d(x, wp, 2, 0) ** 2
+    for idx, (o, i, j) in enumerate(C.output_list(geom, 5)):
+        v = cl.decrypt(zp.data[idx], zp.scale, 1, limbs=1)
+        assert abs(v[0] - refp[i, j, o]) < 1e-3

@@ -1,0 +1,255 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+Ring-level results must match the oracle bit for bit (integer work); decrypted
+layer outputs must be within 1e-3 absolute of the FP64 convolution (Eq. 1).
+Inputs (ciphertexts, plaintexts) are produced by the oracle from the seeded
+`synth` draws and uploaded; the GPU side generates its own switching keys from
+the same draws, so any key-generation mistake shows up as a rotation mismatch.
+Small rings (N = 1024) span many workgroups and ragged output counts; the
+full-size layers are checked on sampled outputs and by decrypted accuracy.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import synth  # noqa: E402
+from oracle import conv as C  # noqa: E402
+from oracle import encoding as E  # noqa: E402
+from oracle import params as P  # noqa: E402
+from oracle import reference as R  # noqa: E402
+from oracle import scheme as S  # noqa: E402
+from oracle import workloads as Wk  # noqa: E402
+from oracle.ntt import intt as o_intt  # noqa: E402
+from oracle.ntt import ntt as o_ntt  # noqa: E402
+
+W = "unit"
+
+
+def _he():
+    from paper_2102_03494_amd import he
+    return he
+
+
+def _ctx(p, ws=1 << 28):
+    he = _he()
+    c = he.HEContext(p.n, p.q_bits, p.p_bits, workspace_bytes=ws)
+    assert c.moduli == p.q + [p.p]
+    return c
+
+
+def _client(ctx, rotations=(), relin=False):
+    from paper_2102_03494_amd.client import Client
+    cl = Client(ctx, W)
+    cl.gen_rotation_keys(rotations)
+    if relin:
+        cl.gen_relin_key()
+    return cl
+
+
+def _dev(a):
+    return _he().to_device(a)
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return _he().to_host(t)
+
+
+SMALL = dict(n=1024, q_bits=(30, 30, 30, 30), p_bits=40)
+
+
+@pytest.mark.parametrize("n,q_bits,p_bits", [
+    (1024, (30, 30, 30), 36), (4096, (30, 30), 36), (8192, (30, 30, 30, 30), 40), (16384, (40,) * 6, 60),
+])
+def test_ntt_intt_bit_exact(n, q_bits, p_bits):
+    p = P.Params(n, q_bits, p_bits, 1.0)
+    ctx = _ctx(p, ws=1 << 20)
+    mods = p.q + [p.p]
+    rng = np.random.default_rng(n)
+    a = np.stack([np.stack([rng.integers(0, m, n, dtype=np.uint64) for m in mods]) for _ in range(3)])
+    d = _dev(a)
+    ctx.ntt(d)
+    got = _host(d)
+    for t, m in enumerate(mods):
+        assert np.array_equal(got[:, t], o_ntt(a[:, t], m, p.psi[m])), (t, m)
+    ctx.intt(d)
+    assert np.array_equal(_host(d), a)
+
+
+def _small_setup(rotations=(), relin=False, n=1024):
+    p = P.Params(n, SMALL["q_bits"], SMALL["p_bits"], 2.0**25)
+    octx = Wk.make_context(p, W, rotations=rotations, relin=relin)
+    gctx = _ctx(p)
+    cl = _client(gctx, rotations, relin)
+    return p, octx, gctx, cl
+
+
+def test_encrypt_and_decrypt_bit_exact():
+    p, octx, gctx, cl = _small_setup()
+    z = synth.message(W, p.slots)
+    pt = E.encode(z, p, 4, p.scale)
+    a, e = synth.encryption_draws(W, 0, p.q, p.n)
+    oct_ = octx.encrypt(pt, p.scale, a, e)
+    gct = cl.encrypt_pt(_dev(pt), p.scale, 0)
+    assert np.array_equal(_host(gct.data)[0], oct_.c)
+    dec = _host(gctx.decrypt(gct.data[0], cl.s_ntt))
+    assert np.array_equal(dec, octx.decrypt_poly(oct_))
+    vals = cl.decrypt(gct.data[0], p.scale)
+    assert np.abs(vals - z).max() < 1e-5
+
+
+def _enc_batch(octx, p, count, level=4, index0=0):
+    cts = []
+    for i in range(count):
+        z = synth.message(W, p.slots, index=index0 + i)
+        cts.append(Wk.encrypt_slots(octx, z, level, p.scale, W, index0 + i).c)
+    return np.stack(cts)
+
+
+def test_rotate_batch_bit_exact():
+    steps = (1, 3, -7, 100)
+    p, octx, gctx, cl = _small_setup(rotations=steps)
+    batch = _enc_batch(octx, p, 5)
+    he = _he()
+    for k in steps:
+        got = _host(gctx.rotate(he.Ct(_dev(batch), p.scale), k).data)
+        want = S.rotate(p, octx, S.Ciphertext(batch, p.scale), k).c
+        assert np.array_equal(got, want), k
+    # in place (out aliases in) and at a lower level
+    low = np.ascontiguousarray(batch[:, :, :2])
+    d = _dev(low)
+    gctx.rotate(he.Ct(d, p.scale), 3, out=d)
+    assert np.array_equal(_host(d), S.rotate(p, octx, S.Ciphertext(low, p.scale), 3).c)
+
+
+def test_rotate_hoisted_bit_exact():
+    steps = [1, 2, 5, 17, 255, -3]
+    p, octx, gctx, cl = _small_setup(rotations=steps)
+    ct = _enc_batch(octx, p, 1)[0]
+    got = _host(gctx.rotate_hoisted(_he().Ct(_dev(ct), p.scale), steps).data)
+    for r, k in enumerate(steps):
+        assert np.array_equal(got[r], S.rotate(p, octx, S.Ciphertext(ct, p.scale), k).c), k
+
+
+def test_rotsum_rescale_add_bit_exact():
+    p, octx, gctx, cl = _small_setup(rotations=[1 << j for j in range(9)])
+    batch = _enc_batch(octx, p, 3)
+    he = _he()
+    d = _dev(batch)
+    gctx.rotsum(he.Ct(d, p.scale), 9)
+    want = C.rotate_and_sum(p, octx, S.Ciphertext(batch, p.scale), 9, C.Counts())
+    assert np.array_equal(_host(d), want.c)
+    r = gctx.rescale(he.Ct(d, p.scale))
+    assert np.array_equal(_host(r.data), S.rescale(p, want).c)
+    out = torch.empty_like(d)
+    gctx.add(out, d, _dev(batch))
+    assert np.array_equal(_host(out), S.add(p, want, S.Ciphertext(batch, p.scale)).c)
+
+
+def test_square_bit_exact():
+    p, octx, gctx, cl = _small_setup(relin=True)
+    batch = _enc_batch(octx, p, 3, level=3)
+    got = _host(gctx.square(_he().Ct(_dev(batch), p.scale)).data)
+    assert np.array_equal(got, S.square(p, octx, S.Ciphertext(batch, p.scale)).c)
+
+
+def test_hma_plain_and_scalar_bit_exact():
+    p, octx, gctx, cl = _small_setup()
+    batch = _enc_batch(octx, p, 4, level=3)
+    pts = np.stack([E.encode(synth.message(W, p.slots, index=40 + i), p, 4, 2.0**20) for i in range(4)])
+    gal = [1, 5, 25, 2 * p.n - 5]
+    acc = torch.empty((2, 3, p.n), dtype=torch.int64, device="cuda")
+    gctx.hma_plain(acc, _dev(batch), _dev(pts), 1, galois=gal)
+    want = None
+    from oracle.ring import automorph_ntt
+    for i in range(4):
+        prod = S.mul_plain(p, S.Ciphertext(batch[i], 1.0), automorph_ntt(pts[i], gal[i]), 1.0)
+        want = prod if want is None else S.add(p, want, prod)
+    assert np.array_equal(_host(acc), want.c)
+    w = [3, -7, 1 << 40, -(1 << 35) + 11]
+    gctx.hma_scalar(acc, _dev(batch), w)
+    want = None
+    for i in range(4):
+        prod = S.mul_int(p, S.Ciphertext(batch[i], 1.0), w[i])
+        want = prod if want is None else S.add(p, want, prod)
+    assert np.array_equal(_host(acc), want.c)
+
+
+def _densepack_case(p, octx, gctx, geom, o_c, level, outputs=None, std=0.1, wid=7):
+    x = synth.image(W, (geom.h, geom.w, geom.c_in))
+    w = synth.weights(W, wid, (geom.d, geom.d, geom.c_in, o_c), std)
+    cts = [Wk.encrypt_slots(octx, v, level, p.scale, W, m).c for m, v in enumerate(C.densepack_slots(x, geom, p.slots))]
+    xin = np.stack(cts)
+    pts = C.densepack_pt_scale(p, level, p.scale, p.scale)
+    bf = C.densepack_base_filters(p, w, geom, level, pts)
+    he = _he()
+    desc = he.HEContext.conv_desc(geom.h, geom.w, geom.c_in, geom.d, geom.stride, geom.pad, o_c,
+                                  int(math.log2(p.slots)))
+    gout = gctx.conv_densepack(he.Ct(_dev(xin), p.scale), desc, _dev(bf), pts)
+    return x, w, xin, bf, pts, gout
+
+
+@pytest.mark.parametrize("shape,d,stride,pad,o_c", [
+    ((6, 6, 3), 3, 1, 1, 3),    # 9 border classes, 108 outputs (ragged vs the chunking)
+    ((5, 5, 8), 3, 2, 1, 2),    # 200 values over 512 slots -> 1 ct; stride 2 with padding
+    ((8, 8, 12), 3, 1, 0, 1),   # 768 values over 512 slots: two input ciphertexts
+])
+def test_densepack_bit_exact_small(shape, d, stride, pad, o_c):
+    p, octx, gctx, cl = _small_setup(rotations=[1 << j for j in range(9)])
+    geom = C.ConvGeom(shape[0], shape[1], shape[2], d, stride, pad)
+    x, w, xin, bf, pts, gout = _densepack_case(p, octx, gctx, geom, o_c, 3)
+    got = _host(gout.data)
+    want, _ = C.conv_densepack(p, octx, S.Ciphertext(xin, p.scale), geom, bf, pts)
+    assert got.shape == want.c.shape
+    assert np.array_equal(got, want.c)
+    cnt = gctx.last_counts()
+    assert cnt["rot"] == geom.spatial * o_c * 9 and cnt["mulpc"] == geom.spatial * o_c * geom.n_cts(p.slots)
+    ref = R.conv2d(x, w, stride, pad)
+    for idx in (0, len(got) // 2, len(got) - 1):
+        o, rem = divmod(idx, geom.spatial)
+        i, j = divmod(rem, geom.out_w)
+        v = cl.decrypt(gout.data[idx], gout.scale, 4)
+        assert np.abs(v - ref[i, j, o]).max() < 1e-3
+
+
+def test_convpack_bit_exact():
+    p, octx, gctx, cl = _small_setup()
+    batch = _enc_batch(octx, p, 3, level=3)
+    wts = synth.weights(W, 11, (3, 4), 0.2)
+    want, _ = C.convpack(p, S.Ciphertext(batch, p.scale), wts, p.scale)
+    dw = p.q[2] * p.scale / p.scale
+    got = gctx.conv_convpack(_he().Ct(_dev(batch), p.scale), wts, dw)
+    assert np.array_equal(_host(got.data), want.c)
+    assert got.scale == want.scale
+
+
+def test_ffconv_layer_bit_exact_small():
+    """Whole FFConv layer (W1 DensePack, gather, 1x1 ConvPack, x^2) on a small ring."""
+    p, octx, gctx, cl = _small_setup(rotations=[1 << j for j in range(9)], relin=True)
+    geom = C.ConvGeom(7, 7, 2, 3, 2, 1)
+    x = synth.image(W, (7, 7, 2))
+    w1 = synth.weights(W, 21, (3, 3, 2, 2), 0.3)
+    w2 = synth.weights(W, 22, (2, 3), 0.4)
+    level = 4
+    ct = Wk.encrypt_slots(octx, C.densepack_slots(x, geom, p.slots)[0], level, p.scale, W, 0)
+    pts = C.densepack_pt_scale(p, level, p.scale, p.scale)
+    bf = C.densepack_base_filters(p, w1, geom, level, pts)
+    y, _ = C.conv_densepack(p, octx, ct, geom, bf, pts)
+    target = C.pre_square_target(p, level - 2, p.scale)
+    ms = C.gather_mask_scale(p, y.level, y.scale, target, 12)
+    mask = C.encode_onehot(p, y.level, ms)
+    z, _ = C.gather_convpack(p, y, geom.spatial, w2, 12, mask, ms)
+    want, _ = C.square_rescale(p, octx, z)
+    he = _he()
+    desc = he.HEContext.conv_desc(7, 7, 2, 3, 2, 1, 2, 9)
+    got = gctx.ffconv_layer(he.Ct(_dev(ct.c[None]), p.scale), desc, _dev(bf), pts, _dev(mask), ms, w2, 12, True)
+    assert np.array_equal(_host(got.data), want.c)
+    assert abs(got.scale - want.scale) <= 1e-12 * want.scale
+    ref = R.ffconv_reference(x, w1, w2, 2, 1, square=True)
+    for o in range(3):
+        v = cl.decrypt(got.data[o], got.scale, geom.spatial)
+        assert np.abs(v - ref[:, :, o].reshape(-1)).max() < 1e-3
