@@ -22,7 +22,9 @@ struct he_ctx {
   int n = 0, logn = 0, big_l = 0;
   std::vector<u64> moduli;  // q_0..q_{L-1}, P
   Mods mods{};
-  u64* d_tw = nullptr;
+  u64* d_tw = nullptr;    // [L+1][4][N] 64-bit twiddles + Shoup companions
+  u32* d_tw32 = nullptr;  // 32-bit copies for the narrow moduli
+  Tables tb() const { return Tables{d_tw, d_tw32}; }
   char* ws = nullptr;
   size_t ws_bytes = 0;
   std::map<int, u64*> keys;  // Galois element (0 = relinearisation) -> [L][2][L+1][N]
@@ -33,6 +35,10 @@ struct he_ctx {
   std::string prof_kernel;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
   std::vector<hipEvent_t> prof_pool;
+  // second stream (default priority) for the wide-modulus share of a launch
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  TargetList narrow_t[HE_MAXM + 1], wide_t[HE_MAXM + 1];  // per level: ModUp targets by class
 };
 
 namespace {
@@ -131,9 +137,9 @@ struct LNtt {
     dim3 grid(n_limbs, n_polys);
     Prof pr(c, "ntt", s);
     if (fwd)
-      k_ntt<LOGN, true><<<grid, NttGeom<LOGN>::T, 0, s>>>(d, n_limbs, first_mod, c->mods, c->d_tw);
+      k_ntt<LOGN, true><<<grid, NttGeom<LOGN>::T, 0, s>>>(d, n_limbs, first_mod, c->mods, c->tb());
     else
-      k_ntt<LOGN, false><<<grid, NttGeom<LOGN>::T, 0, s>>>(d, n_limbs, first_mod, c->mods, c->d_tw);
+      k_ntt<LOGN, false><<<grid, NttGeom<LOGN>::T, 0, s>>>(d, n_limbs, first_mod, c->mods, c->tb());
   }
 };
 
@@ -147,16 +153,34 @@ struct LKeySwitchCore {
     constexpr size_t N = (size_t)1 << LOGN;
     {
       Prof pr(c, "ks_digits", s);
-      k_ks_digits<LOGN><<<dim3(level, count), T, 0, s>>>(c1, cstride, ginv, dcoef, level, c->mods, c->d_tw);
+      k_ks_digits<LOGN><<<dim3(level, count), T, 0, s>>>(c1, cstride, ginv, dcoef, level, c->mods, c->tb());
     }
     {
+      // narrow targets on the caller's stream, wide targets (e.g. P) on the
+      // side stream, joined before the ModDown
+      const TargetList& nt = c->narrow_t[level];
+      const TargetList& wt = c->wide_t[level];
       Prof pr(c, "ks_modup_ip", s);
-      k_ks_modup_ip<LOGN><<<dim3(level + 1, count), T, 0, s>>>(dcoef, c1, cstride, ginv, key, u, level, c->big_l,
-                                                                c->mods, c->d_tw);
+      if (wt.n && nt.n) {
+        hipEventRecord(c->fork_ev, s);
+        hipStreamWaitEvent(c->side, c->fork_ev, 0);
+        k_ks_modup_ip<LOGN, false><<<dim3(wt.n, count), T, 0, c->side>>>(dcoef, c1, cstride, ginv, key, u, level,
+                                                                          c->big_l, wt, c->mods, c->tb());
+        k_ks_modup_ip<LOGN, true><<<dim3(nt.n, count), T, 0, s>>>(dcoef, c1, cstride, ginv, key, u, level, c->big_l,
+                                                                   nt, c->mods, c->tb());
+        hipEventRecord(c->join_ev, c->side);
+        hipStreamWaitEvent(s, c->join_ev, 0);
+      } else if (nt.n) {
+        k_ks_modup_ip<LOGN, true><<<dim3(nt.n, count), T, 0, s>>>(dcoef, c1, cstride, ginv, key, u, level, c->big_l,
+                                                                   nt, c->mods, c->tb());
+      } else {
+        k_ks_modup_ip<LOGN, false><<<dim3(wt.n, count), T, 0, s>>>(dcoef, c1, cstride, ginv, key, u, level,
+                                                                    c->big_l, wt, c->mods, c->tb());
+      }
     }
     Prof pr(c, "intt_last", s);
     k_intt_last<LOGN><<<dim3(2 * count), T, 0, s>>>(u, (size_t)(level + 1) * N, level, c->big_l, rcoef, c->mods,
-                                                     c->d_tw);
+                                                     c->tb());
   }
 };
 
@@ -175,16 +199,16 @@ struct LDropLast {
     Prof pr(c, "drop_last", s);
     switch (epi) {
       case EPI_STORE:
-        k_drop_last<LOGN, EPI_STORE><<<grid, T, 0, s>>>(src, pstride, rcoef, div_mi, inv, ea, c->mods, c->d_tw);
+        k_drop_last<LOGN, EPI_STORE><<<grid, T, 0, s>>>(src, pstride, rcoef, div_mi, inv, ea, c->mods, c->tb());
         break;
       case EPI_ROT:
-        k_drop_last<LOGN, EPI_ROT><<<grid, T, 0, s>>>(src, pstride, rcoef, div_mi, inv, ea, c->mods, c->d_tw);
+        k_drop_last<LOGN, EPI_ROT><<<grid, T, 0, s>>>(src, pstride, rcoef, div_mi, inv, ea, c->mods, c->tb());
         break;
       case EPI_ROTSUM:
-        k_drop_last<LOGN, EPI_ROTSUM><<<grid, T, 0, s>>>(src, pstride, rcoef, div_mi, inv, ea, c->mods, c->d_tw);
+        k_drop_last<LOGN, EPI_ROTSUM><<<grid, T, 0, s>>>(src, pstride, rcoef, div_mi, inv, ea, c->mods, c->tb());
         break;
       default:
-        k_drop_last<LOGN, EPI_RELIN><<<grid, T, 0, s>>>(src, pstride, rcoef, div_mi, inv, ea, c->mods, c->d_tw);
+        k_drop_last<LOGN, EPI_RELIN><<<grid, T, 0, s>>>(src, pstride, rcoef, div_mi, inv, ea, c->mods, c->tb());
         break;
     }
   }
@@ -195,7 +219,7 @@ struct LIntt1 {
   static void run(he_ctx* c, const u64* src, size_t pstride, int limb, int mi, u64* rcoef, int n_polys,
                   hipStream_t s) {
     Prof pr(c, "intt_last", s);
-    k_intt_last<LOGN><<<dim3(n_polys), NttGeom<LOGN>::T, 0, s>>>(src, pstride, limb, mi, rcoef, c->mods, c->d_tw);
+    k_intt_last<LOGN><<<dim3(n_polys), NttGeom<LOGN>::T, 0, s>>>(src, pstride, limb, mi, rcoef, c->mods, c->tb());
   }
 };
 
@@ -491,16 +515,16 @@ struct LHoisted {
     constexpr int T = NttGeom<LOGN>::T;
     constexpr int N = 1 << LOGN;
     const u64* c1 = in + (size_t)level * N;
-    k_ks_digits<LOGN><<<dim3(level, 1), T, 0, s>>>(c1, 0, 1u, dcoef, level, c->mods, c->d_tw);
+    k_ks_digits<LOGN><<<dim3(level, 1), T, 0, s>>>(c1, 0, 1u, dcoef, level, c->mods, c->tb());
     {
       Prof pr(c, "modup_store", s);
-      k_modup_store<LOGN><<<dim3(level + 1, level), T, 0, s>>>(dcoef, c1, dhat, level, c->big_l, c->mods, c->d_tw);
+      k_modup_store<LOGN><<<dim3(level + 1, level), T, 0, s>>>(dcoef, c1, dhat, level, c->big_l, c->mods, c->tb());
     }
     {
       Prof pr(c, "ip_perm", s);
       k_ip_perm<LOGN><<<dim3(N / 256, level + 1, m), 256, 0, s>>>(dhat, d_keys, d_gp, u, level, c->big_l, c->mods);
     }
-    k_intt_last<LOGN><<<dim3(2 * m), T, 0, s>>>(u, (size_t)(level + 1) * N, level, c->big_l, rc, c->mods, c->d_tw);
+    k_intt_last<LOGN><<<dim3(2 * m), T, 0, s>>>(u, (size_t)(level + 1) * N, level, c->big_l, rc, c->mods, c->tb());
     EpiArgs ea{outs, (size_t)level * N, in, 0, 1u, 1u, d_gp};
     LDropLast<LOGN>::run(c, EPI_ROT, u, (size_t)(level + 1) * N, rc, c->big_l, level, 2 * m, ea, s);
   }
@@ -539,10 +563,33 @@ int he_ctx_create(const he_params* p, he_ctx** out) {
     u64* b = tw.data() + i * 4 * n;
     make_twiddles(mods[i], p->n, b, b + n, b + 2 * n, b + 3 * n);
   }
+  std::vector<u32> tw32(tw.size(), 0);
+  for (size_t i = 0; i < mods.size(); ++i)
+    if (is_narrow(mods[i]))
+      for (size_t k = 0; k < 4 * n; ++k) tw32[i * 4 * n + k] = (u32)tw[i * 4 * n + k];
   if (hipMalloc((void**)&c->d_tw, tw.size() * 8) != hipSuccess ||
-      hipMemcpy(c->d_tw, tw.data(), tw.size() * 8, hipMemcpyHostToDevice) != hipSuccess) {
+      hipMemcpy(c->d_tw, tw.data(), tw.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMalloc((void**)&c->d_tw32, tw32.size() * 4) != hipSuccess ||
+      hipMemcpy(c->d_tw32, tw32.data(), tw32.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
     hipFree(c->d_tw);
+    hipFree(c->d_tw32);
     delete c;
+    return HE_EDEVICE;
+  }
+  for (int level = 1; level <= c->big_l; ++level) {
+    TargetList& nt = c->narrow_t[level];
+    TargetList& wt = c->wide_t[level];
+    nt.n = wt.n = 0;
+    for (int t = 0; t <= level; ++t) {
+      const int mi = t < level ? t : c->big_l;
+      if (c->mods.m[mi].narrow) nt.t[nt.n++] = t;
+      else wt.t[wt.n++] = t;
+    }
+  }
+  if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess) {
+    he_ctx_destroy(c);
     return HE_EDEVICE;
   }
   *out = c;
@@ -556,7 +603,11 @@ int he_ctx_destroy(he_ctx* c) {
   for (hipEvent_t e : c->prof_pool) hipEventDestroy(e);
   for (auto& kv : c->keys) hipFree(kv.second);
   hipFree(c->d_tw);
+  hipFree(c->d_tw32);
   hipFree(c->ws);
+  if (c->side) hipStreamDestroy(c->side);
+  if (c->fork_ev) hipEventDestroy(c->fork_ev);
+  if (c->join_ev) hipEventDestroy(c->join_ev);
   auto it = g_stage.find(c);
   if (it != g_stage.end()) {
     for (int k = 0; k < 2; ++k) {

@@ -107,7 +107,7 @@ static u32 bitlen(u64 q) {
 }
 
 u64 shoup_companion(u64 w, u64 q) {
-  if (q < ((u64)1 << 31)) return (u64)(((u128)w << 32) / q);
+  if (is_narrow(q)) return (u64)(((u128)w << 32) / q);
   return (u64)(((u128)w << 64) / q);
 }
 
@@ -117,7 +117,7 @@ ModConst make_modconst(u64 q, int n) {
   m.mu64 = (u64)(~(u64)0) / q;
   m.s = bitlen(q);
   m.bmu = (u64)(((u128)1 << (2 * m.s)) / q);
-  m.narrow = q < ((u64)1 << 31) ? 1u : 0u;
+  m.narrow = is_narrow(q) ? 1u : 0u;
   m.n_inv = inv_mod((u64)n % q, q);
   m.n_inv_sh = shoup_companion(m.n_inv, q);
   return m;

@@ -5,8 +5,9 @@
 // 8N-byte run and every kernel reads and writes whole limbs with unit-stride
 // (coalesced) accesses.  Kernels that need a transform hold one limb per
 // workgroup in LDS (ntt_lds.h); elementwise kernels use one thread per
-// coefficient.  The width class of each prime (narrow < 2^31, wide < 2^62) is
-// uniform per workgroup and selects a compile-time specialisation.
+// coefficient.  The width class of each prime (narrow < 2^30, wide < 2^62) is
+// uniform per workgroup; each transform kernel branches once on it into a
+// body compiled for that class (32-bit words for narrow limbs).
 //
 // Key switching of a batch of ciphertexts (rotation or relinearisation) runs
 // as four kernels, each batched over every ciphertext of the call:
@@ -37,26 +38,60 @@ struct ConstTable {  // one constant per modulus index with its Shoup companion
   u64 sh[HE_MAXM];
 };
 
-// Twiddle tables: [n_mods][4][N] = fwd, fwd_shoup, inv, inv_shoup.
-template <int LOGN>
-__device__ __forceinline__ const u64* tw_ptr(const u64* tw, int mi, int which) {
-  return tw + ((size_t)mi * 4 + which) * ((size_t)1 << LOGN);
+// Twiddle tables [n_mods][4][N] (fwd, fwd_shoup, inv, inv_shoup): 64-bit for
+// every modulus, 32-bit copies for the narrow ones.
+struct Tables {
+  const u64* tw64;
+  const u32* tw32;
+};
+
+template <int LOGN, bool NARROW>
+__device__ __forceinline__ Tw<NARROW> tw_of(const Tables& tb, int mi, int which) {
+  constexpr size_t N = (size_t)1 << LOGN;
+  if constexpr (NARROW)
+    return {tb.tw32 + ((size_t)mi * 4 + which) * N, tb.tw32 + ((size_t)mi * 4 + which + 1) * N};
+  else
+    return {tb.tw64 + ((size_t)mi * 4 + which) * N, tb.tw64 + ((size_t)mi * 4 + which + 1) * N};
+}
+
+// An opaque copy of the thread index (see ntt_lds.h): defined where it is
+// used so that address arithmetic is not hoisted out of enclosing loops.
+__device__ __forceinline__ int opaque_tid() {
+  int tid = (int)threadIdx.x;
+  asm volatile("" : "+v"(tid));
+  return tid;
 }
 
 template <int LOGN, bool NARROW>
-__device__ __forceinline__ void fwd_lds(u64* lds, const u64* tw, int mi, u64 q) {
-  ntt_fwd_lds<LOGN, NARROW>(lds, tw_ptr<LOGN>(tw, mi, 0), tw_ptr<LOGN>(tw, mi, 1), q);
+__device__ __forceinline__ void fwd_lds(u64* lds, const Tables& tb, int mi, u64 q) {
+  ntt_fwd_lds<LOGN, NARROW>(lds, tw_of<LOGN, NARROW>(tb, mi, 0), (word_t<NARROW>)q, opaque_tid());
 }
 
 template <int LOGN, bool NARROW>
-__device__ __forceinline__ void inv_lds(u64* lds, const u64* tw, int mi, u64 q) {
-  ntt_inv_lds<LOGN, NARROW>(lds, tw_ptr<LOGN>(tw, mi, 2), tw_ptr<LOGN>(tw, mi, 3), q);
+__device__ __forceinline__ void inv_lds(u64* lds, const Tables& tb, int mi, u64 q) {
+  ntt_inv_lds<LOGN, NARROW>(lds, tw_of<LOGN, NARROW>(tb, mi, 2), (word_t<NARROW>)q, opaque_tid());
+}
+
+template <bool NARROW>
+__device__ __forceinline__ u64 addm(u64 a, u64 b, u64 q) {
+  if constexpr (NARROW) return add32((u32)a, (u32)b, (u32)q);
+  else return add_mod(a, b, q);
+}
+template <bool NARROW>
+__device__ __forceinline__ u64 subm(u64 a, u64 b, u64 q) {
+  if constexpr (NARROW) return sub32((u32)a, (u32)b, (u32)q);
+  else return sub_mod(a, b, q);
+}
+template <bool NARROW>
+__device__ __forceinline__ u64 shoupm(u64 a, u64 w, u64 wsh, u64 q) {
+  if constexpr (NARROW) return shoup32((u32)a, (u32)w, (u32)wsh, (u32)q);
+  else return mul_shoup(a, w, wsh, q, false);
 }
 
 // Coalesced limb load into LDS, optionally through the Galois permutation
 // sigma_g: afterwards lds[i] = src[galois_src(i, g)].  ginv = g^-1 mod 2N
 // (the scatter position of source entry idx is galois_src(idx, ginv)).
-template <int LOGN>
+template <int LOGN, bool NARROW>
 __device__ __forceinline__ void load_limb_perm(u64* lds, const u64* __restrict__ src, u32 ginv) {
   constexpr int T = NttGeom<LOGN>::T;
 #pragma unroll
@@ -64,35 +99,43 @@ __device__ __forceinline__ void load_limb_perm(u64* lds, const u64* __restrict__
     const int idx = (int)threadIdx.x + r * T;
     const u64 v = src[idx];
     const int dst = (ginv == 1u) ? idx : galois_src<LOGN>(idx, ginv);
-    lds[lds_idx(dst)] = v;
+    lds_put<NARROW>(lds, dst, v);
+  }
+}
+
+// Store the LDS limb, optionally scaled by N^-1 (after an inverse transform).
+template <int LOGN, bool NARROW>
+__device__ __forceinline__ void store_limb(u64* __restrict__ dst, const u64* lds, const ModConst& m, bool scale) {
+  constexpr int T = NttGeom<LOGN>::T;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = (int)threadIdx.x + r * T;
+    u64 v = lds_get<NARROW>(lds, i);
+    if (scale) v = shoupm<NARROW>(v, m.n_inv, m.n_inv_sh, m.q);
+    dst[i] = v;
   }
 }
 
 // ---------------------------------------------------------------------------
 // Standalone transforms: blockIdx.x = limb, blockIdx.y = polynomial.
+template <int LOGN, bool FWD, bool NARROW>
+__device__ __forceinline__ void ntt_body(u64* lds, u64* p, int mi, const ModConst& m, const Tables& tb) {
+  load_limb_perm<LOGN, NARROW>(lds, p, 1u);
+  if (FWD) fwd_lds<LOGN, NARROW>(lds, tb, mi, m.q); else inv_lds<LOGN, NARROW>(lds, tb, mi, m.q);
+  store_limb<LOGN, NARROW>(p, lds, m, !FWD);
+}
+
 template <int LOGN, bool FWD>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
-k_ntt(u64* data, int n_limbs, int first_mod, Mods mods, const u64* __restrict__ tw) {
+k_ntt(u64* data, int n_limbs, int first_mod, Mods mods, Tables tb) {
   constexpr int N = 1 << LOGN;
-  constexpr int T = NttGeom<LOGN>::T;
   __shared__ u64 lds[NttGeom<LOGN>::LDS];
   const int limb = blockIdx.x;
   const int mi = first_mod + limb;
   const ModConst m = mods.m[mi];
   u64* p = data + ((size_t)blockIdx.y * n_limbs + limb) * N;
-  load_limb_perm<LOGN>(lds, p, 1u);
-  if (m.narrow) {
-    if (FWD) fwd_lds<LOGN, true>(lds, tw, mi, m.q); else inv_lds<LOGN, true>(lds, tw, mi, m.q);
-  } else {
-    if (FWD) fwd_lds<LOGN, false>(lds, tw, mi, m.q); else inv_lds<LOGN, false>(lds, tw, mi, m.q);
-  }
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int i = (int)threadIdx.x + r * T;
-    u64 v = lds[lds_idx(i)];
-    if (!FWD) v = mul_shoup(v, m.n_inv, m.n_inv_sh, m.q, m.narrow);
-    p[i] = v;
-  }
+  if (m.narrow) ntt_body<LOGN, FWD, true>(lds, p, mi, m, tb);
+  else ntt_body<LOGN, FWD, false>(lds, p, mi, m, tb);
 }
 
 // ---------------------------------------------------------------------------
@@ -100,67 +143,76 @@ k_ntt(u64* data, int n_limbs, int first_mod, Mods mods, const u64* __restrict__ 
 // blockIdx.x = digit j (< level), blockIdx.y = ciphertext b.
 // c1 points at limb 0 of component 1 of ciphertext 0; cstride = elements
 // between ciphertexts.  dcoef = [count][level][N].
+template <int LOGN, bool NARROW>
+__device__ __forceinline__ void digits_body(u64* lds, const u64* src, u32 ginv, u64* out, int j, const ModConst& m,
+                                            const Tables& tb) {
+  load_limb_perm<LOGN, NARROW>(lds, src, ginv);
+  inv_lds<LOGN, NARROW>(lds, tb, j, m.q);
+  store_limb<LOGN, NARROW>(out, lds, m, true);
+}
+
 template <int LOGN>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
 k_ks_digits(const u64* __restrict__ c1, size_t cstride, u32 ginv, u64* __restrict__ dcoef, int level,
-            Mods mods, const u64* __restrict__ tw) {
+            Mods mods, Tables tb) {
   constexpr int N = 1 << LOGN;
-  constexpr int T = NttGeom<LOGN>::T;
   __shared__ u64 lds[NttGeom<LOGN>::LDS];
   const int j = blockIdx.x;
   const size_t b = blockIdx.y;
   const ModConst m = mods.m[j];
-  load_limb_perm<LOGN>(lds, c1 + b * cstride + (size_t)j * N, ginv);
-  if (m.narrow) inv_lds<LOGN, true>(lds, tw, j, m.q); else inv_lds<LOGN, false>(lds, tw, j, m.q);
+  const u64* src = c1 + b * cstride + (size_t)j * N;
   u64* out = dcoef + (b * level + j) * N;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int i = (int)threadIdx.x + r * T;
-    out[i] = mul_shoup(lds[lds_idx(i)], m.n_inv, m.n_inv_sh, m.q, m.narrow);
-  }
+  if (m.narrow) digits_body<LOGN, true>(lds, src, ginv, out, j, m, tb);
+  else digits_body<LOGN, false>(lds, src, ginv, out, j, m, tb);
 }
 
-// Key switch, step 2: ModUp + inner product for one target modulus.
-// blockIdx.x = target t in [0, level]: t < level is q_t, t == level is P
-// (modulus index big_l); blockIdx.y = ciphertext b.
+// Key switch, step 2: ModUp + inner product for one target modulus t in
+// [0, level]: t < level is q_t, t == level is P (modulus index big_l);
+// blockIdx.y = ciphertext b.
 // key = [big_l][2][big_l+1][N]; u = [count][2][level+1][N].
 template <int LOGN, bool NARROW>
 __device__ __forceinline__ void modup_ip_body(u64* lds, const u64* __restrict__ dcoef, const u64* __restrict__ c1,
                                               size_t cstride, u32 ginv, const u64* __restrict__ key,
-                                              u64* __restrict__ u, int level, int big_l, const Mods& mods,
-                                              const u64* __restrict__ tw) {
+                                              u64* __restrict__ u, int level, int big_l, int t, const Mods& mods,
+                                              const Tables& tb) {
+  typedef word_t<NARROW> W;
   constexpr int N = 1 << LOGN;
   constexpr int T = NttGeom<LOGN>::T;
-  const int t = blockIdx.x;
   const size_t b = blockIdx.y;
   const int mi = (t < level) ? t : big_l;
   const ModConst m = mods.m[mi];
-  u64 acc0[16], acc1[16];
+  W acc0[16], acc1[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0;
   for (int j = 0; j < level; ++j) {
     if (j == t) {
       // the digit reduced mod its own prime is the (permuted) input limb itself
-      load_limb_perm<LOGN>(lds, c1 + b * cstride + (size_t)j * N, ginv);
+      load_limb_perm<LOGN, NARROW>(lds, c1 + b * cstride + (size_t)j * N, ginv);
       __syncthreads();
     } else {
       const u64 qj = mods.m[j].q;
       const u64* d = dcoef + (b * level + j) * N;
+      const int tid = opaque_tid();
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int i = (int)threadIdx.x + r * T;
-        lds[lds_idx(i)] = lift_centered(d[i], qj, m);
+        const int i = tid + r * T;
+        lds_put<NARROW>(lds, i, lift_centered(d[i], qj, m));
       }
-      fwd_lds<LOGN, NARROW>(lds, tw, mi, m.q);
+      fwd_lds<LOGN, NARROW>(lds, tb, mi, m.q);
     }
     const u64* kb = key + (((size_t)j * 2 + 0) * (big_l + 1) + mi) * N;
     const u64* ka = key + (((size_t)j * 2 + 1) * (big_l + 1) + mi) * N;
+    const int tid = opaque_tid();
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int i = (int)threadIdx.x + r * T;
-      const u64 dv = lds[lds_idx(i)];
-      acc0[r] = add_mod(acc0[r], mul_mod_t<NARROW>(dv, kb[i], m), m.q);
-      acc1[r] = add_mod(acc1[r], mul_mod_t<NARROW>(dv, ka[i], m), m.q);
+      const int i = tid + r * T;
+      const u64 dv = lds_get<NARROW>(lds, i);
+      // narrow key residues fit the low word of their u64 slot
+      const u64 kbv = NARROW ? (u64)reinterpret_cast<const u32*>(kb)[2 * i] : kb[i];
+      const u64 kav = NARROW ? (u64)reinterpret_cast<const u32*>(ka)[2 * i] : ka[i];
+      acc0[r] = (W)addm<NARROW>(acc0[r], mul_mod_t<NARROW>(dv, kbv, m), m.q);
+      acc1[r] = (W)addm<NARROW>(acc1[r], mul_mod_t<NARROW>(dv, kav, m), m.q);
+      if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bound the load hoisting
     }
     __syncthreads();
   }
@@ -174,38 +226,37 @@ __device__ __forceinline__ void modup_ip_body(u64* lds, const u64* __restrict__ 
   }
 }
 
-template <int LOGN>
+// Target moduli of one width class: blockIdx.x indexes tl.t[] (values in
+// [0, level], level meaning P).  Each class is its own kernel so the 32-bit
+// body gets a register allocation of its own.
+struct TargetList {
+  int n;
+  int t[HE_MAXM];
+};
+
+template <int LOGN, bool NARROW>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
 k_ks_modup_ip(const u64* __restrict__ dcoef, const u64* __restrict__ c1, size_t cstride, u32 ginv,
-              const u64* __restrict__ key, u64* __restrict__ u, int level, int big_l, Mods mods,
-              const u64* __restrict__ tw) {
+              const u64* __restrict__ key, u64* __restrict__ u, int level, int big_l, TargetList tl, Mods mods,
+              Tables tb) {
   __shared__ u64 lds[NttGeom<LOGN>::LDS];
-  const int mi = ((int)blockIdx.x < level) ? (int)blockIdx.x : big_l;
-  if (mods.m[mi].narrow)
-    modup_ip_body<LOGN, true>(lds, dcoef, c1, cstride, ginv, key, u, level, big_l, mods, tw);
-  else
-    modup_ip_body<LOGN, false>(lds, dcoef, c1, cstride, ginv, key, u, level, big_l, mods, tw);
+  modup_ip_body<LOGN, NARROW>(lds, dcoef, c1, cstride, ginv, key, u, level, big_l, tl.t[blockIdx.x], mods, tb);
 }
 
 // INTT of one limb of each polynomial: blockIdx.x = polynomial p.
 // src + p * pstride + limb * N  ->  rcoef[p] (coefficient domain).
 template <int LOGN>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
-k_intt_last(const u64* __restrict__ src, size_t pstride, int limb, int mi, u64* __restrict__ rcoef,
-            Mods mods, const u64* __restrict__ tw) {
+k_intt_last(const u64* __restrict__ src, size_t pstride, int limb, int mi, u64* __restrict__ rcoef, Mods mods,
+            Tables tb) {
   constexpr int N = 1 << LOGN;
-  constexpr int T = NttGeom<LOGN>::T;
   __shared__ u64 lds[NttGeom<LOGN>::LDS];
   const size_t p = blockIdx.x;
   const ModConst m = mods.m[mi];
-  load_limb_perm<LOGN>(lds, src + p * pstride + (size_t)limb * N, 1u);
-  if (m.narrow) inv_lds<LOGN, true>(lds, tw, mi, m.q); else inv_lds<LOGN, false>(lds, tw, mi, m.q);
+  const u64* s = src + p * pstride + (size_t)limb * N;
   u64* out = rcoef + p * N;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int i = (int)threadIdx.x + r * T;
-    out[i] = mul_shoup(lds[lds_idx(i)], m.n_inv, m.n_inv_sh, m.q, m.narrow);
-  }
+  if (m.narrow) digits_body<LOGN, true>(lds, s, 1u, out, mi, m, tb);
+  else digits_body<LOGN, false>(lds, s, 1u, out, mi, m, tb);
 }
 
 enum { EPI_STORE = 0, EPI_ROT = 1, EPI_ROTSUM = 2, EPI_RELIN = 3 };
@@ -227,7 +278,8 @@ template <int LOGN, int EPI, bool NARROW>
 __device__ __forceinline__ void drop_last_body(u64* lds, const u64* __restrict__ src, size_t pstride,
                                                const u64* __restrict__ rcoef, int div_mi,
                                                const ConstTable& inv, EpiArgs ea, const Mods& mods,
-                                               const u64* __restrict__ tw) {
+                                               const Tables& tb) {
+  typedef word_t<NARROW> W;
   constexpr int N = 1 << LOGN;
   constexpr int T = NttGeom<LOGN>::T;
   const int t = blockIdx.x;
@@ -238,15 +290,15 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const u64* __restrict__
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int i = (int)threadIdx.x + r * T;
-    lds[lds_idx(i)] = lift_centered(rc[i], qd, m);
+    lds_put<NARROW>(lds, i, lift_centered(rc[i], qd, m));
   }
-  fwd_lds<LOGN, NARROW>(lds, tw, t, m.q);
+  fwd_lds<LOGN, NARROW>(lds, tb, t, m.q);
   const u64* s = src + p * pstride + (size_t)t * N;
-  u64 val[16];
+  W val[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int i = (int)threadIdx.x + r * T;
-    val[r] = mul_shoup(sub_mod(s[i], lds[lds_idx(i)], m.q), inv.v[t], inv.sh[t], m.q, NARROW);
+    val[r] = (W)shoupm<NARROW>(subm<NARROW>(s[i], lds_get<NARROW>(lds, i), m.q), inv.v[t], inv.sh[t], m.q);
   }
   const int comp = (int)(p & 1);
   u64* o = ea.out + p * ea.out_pstride + (size_t)t * N;
@@ -258,27 +310,27 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const u64* __restrict__
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int i = (int)threadIdx.x + r * T;
-      o[i] = add_mod(d[i], val[r], m.q);
+      o[i] = addm<NARROW>(d[i], val[r], m.q);
     }
   } else {  // EPI_ROT / EPI_ROTSUM
     if (comp == 0) {
       const u32 ginv = ea.gpairs ? ea.gpairs[2 * (p >> 1) + 1] : ea.ginv;
       __syncthreads();  // everyone is done reading the lifted limb
       const u64* c0 = ea.c0 + p * ea.c0_pstride + (size_t)t * N;
-      u64 own[16];
+      W own[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int idx = (int)threadIdx.x + r * T;
         const u64 v = c0[idx];
-        own[r] = v;
-        lds[lds_idx(galois_src<LOGN>(idx, ginv))] = v;
+        own[r] = (W)v;
+        lds_put<NARROW>(lds, galois_src<LOGN>(idx, ginv), v);
       }
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int i = (int)threadIdx.x + r * T;
-        u64 x = add_mod(lds[lds_idx(i)], val[r], m.q);  // sigma_g(c0) + u0
-        if constexpr (EPI == EPI_ROTSUM) x = add_mod(x, own[r], m.q);
+        u64 x = addm<NARROW>(lds_get<NARROW>(lds, i), val[r], m.q);  // sigma_g(c0) + u0
+        if constexpr (EPI == EPI_ROTSUM) x = addm<NARROW>(x, own[r], m.q);
         o[i] = x;
       }
     } else {
@@ -286,7 +338,7 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const u64* __restrict__
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int i = (int)threadIdx.x + r * T;
-          o[i] = add_mod(o[i], val[r], m.q);
+          o[i] = addm<NARROW>(o[i], val[r], m.q);
         }
       } else {
 #pragma unroll
@@ -299,12 +351,12 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const u64* __restrict__
 template <int LOGN, int EPI>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
 k_drop_last(const u64* __restrict__ src, size_t pstride, const u64* __restrict__ rcoef, int div_mi,
-            ConstTable inv, EpiArgs ea, Mods mods, const u64* __restrict__ tw) {
+            ConstTable inv, EpiArgs ea, Mods mods, Tables tb) {
   __shared__ u64 lds[NttGeom<LOGN>::LDS];
   if (mods.m[blockIdx.x].narrow)
-    drop_last_body<LOGN, EPI, true>(lds, src, pstride, rcoef, div_mi, inv, ea, mods, tw);
+    drop_last_body<LOGN, EPI, true>(lds, src, pstride, rcoef, div_mi, inv, ea, mods, tb);
   else
-    drop_last_body<LOGN, EPI, false>(lds, src, pstride, rcoef, div_mi, inv, ea, mods, tw);
+    drop_last_body<LOGN, EPI, false>(lds, src, pstride, rcoef, div_mi, inv, ea, mods, tb);
 }
 
 // ---------------------------------------------------------------------------
@@ -314,7 +366,7 @@ k_drop_last(const u64* __restrict__ src, size_t pstride, const u64* __restrict__
 template <int LOGN, bool NARROW>
 __device__ __forceinline__ void modup_store_body(u64* lds, const u64* __restrict__ dcoef, const u64* __restrict__ c1,
                                                  u64* __restrict__ dhat, int level, int big_l, const Mods& mods,
-                                                 const u64* __restrict__ tw) {
+                                                 const Tables& tb) {
   constexpr int N = 1 << LOGN;
   constexpr int T = NttGeom<LOGN>::T;
   const int t = blockIdx.x;
@@ -333,26 +385,22 @@ __device__ __forceinline__ void modup_store_body(u64* lds, const u64* __restrict
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int i = (int)threadIdx.x + r * T;
-    lds[lds_idx(i)] = lift_centered(d[i], qj, m);
+    lds_put<NARROW>(lds, i, lift_centered(d[i], qj, m));
   }
-  fwd_lds<LOGN, NARROW>(lds, tw, mi, m.q);
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int i = (int)threadIdx.x + r * T;
-    out[i] = lds[lds_idx(i)];
-  }
+  fwd_lds<LOGN, NARROW>(lds, tb, mi, m.q);
+  store_limb<LOGN, NARROW>(out, lds, m, false);
 }
 
 template <int LOGN>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
 k_modup_store(const u64* __restrict__ dcoef, const u64* __restrict__ c1, u64* __restrict__ dhat, int level, int big_l,
-              Mods mods, const u64* __restrict__ tw) {
+              Mods mods, Tables tb) {
   __shared__ u64 lds[NttGeom<LOGN>::LDS];
   const int mi = ((int)blockIdx.x < level) ? (int)blockIdx.x : big_l;
   if (mods.m[mi].narrow)
-    modup_store_body<LOGN, true>(lds, dcoef, c1, dhat, level, big_l, mods, tw);
+    modup_store_body<LOGN, true>(lds, dcoef, c1, dhat, level, big_l, mods, tb);
   else
-    modup_store_body<LOGN, false>(lds, dcoef, c1, dhat, level, big_l, mods, tw);
+    modup_store_body<LOGN, false>(lds, dcoef, c1, dhat, level, big_l, mods, tb);
 }
 
 // Inner product of the shared lifted digits, permuted per rotation, with
@@ -415,10 +463,11 @@ struct DPGeom {
   int row_cls[64], col_cls[64];  // class id of every output row / column
 };
 
-template <int LOGN>
+template <int LOGN, bool NARROW>
 __device__ __forceinline__ void dp_hma_body(const u64* __restrict__ x, const u64* __restrict__ filt,
                                             u64* __restrict__ out, int level, int out_base, const DPGeom& geo,
-                                            const Mods& mods, u64* lds) {
+                                            const ModConst& m, u64* lds) {
+  typedef word_t<NARROW> W;
   constexpr int N = 1 << LOGN;
   constexpr int T = NttGeom<LOGN>::T;
   const int t = blockIdx.x;
@@ -429,29 +478,28 @@ __device__ __forceinline__ void dp_hma_body(const u64* __restrict__ x, const u64
   const int i = pidx / geo.out_w, j = pidx % geo.out_w;
   const int cls = geo.row_cls[i] * geo.n_col_cls + geo.col_cls[j];
   const int slots = N / 2;
-  int anchor = (geo.stride * i - geo.pad) * geo.w + (geo.stride * j - geo.pad);
+  const int anchor = (geo.stride * i - geo.pad) * geo.w + (geo.stride * j - geo.pad);
   // rotation right by anchor: g = 5^(-anchor mod slots); its inverse is 5^(anchor mod slots)
   int a_mod = anchor % slots;
   if (a_mod < 0) a_mod += slots;
   const u32 mask2n = (2u << LOGN) - 1u;
   const u32 ginv = pow_mod_2n(5u, (u32)a_mod, mask2n);
-  const ModConst m = mods.m[t];
-  u64 acc0[16], acc1[16];
+  W acc0[16], acc1[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0;
   const int n_cls = geo.n_row_cls * geo.n_col_cls;
   for (int mc = 0; mc < geo.m_cts; ++mc) {
     const u64* f = filt + ((((size_t)o * n_cls + cls) * geo.m_cts + mc) * level + t) * N;
-    load_limb_perm<LOGN>(lds, f, ginv);
+    load_limb_perm<LOGN, NARROW>(lds, f, ginv);
     __syncthreads();
     const u64* x0 = x + (((size_t)mc * 2 + 0) * level + t) * N;
     const u64* x1 = x + (((size_t)mc * 2 + 1) * level + t) * N;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int k = (int)threadIdx.x + r * T;
-      const u64 fv = lds[lds_idx(k)];
-      acc0[r] = add_mod(acc0[r], mul_mod(x0[k], fv, m), m.q);
-      acc1[r] = add_mod(acc1[r], mul_mod(x1[k], fv, m), m.q);
+      const u64 fv = lds_get<NARROW>(lds, k);
+      acc0[r] = (W)addm<NARROW>(acc0[r], mul_mod_t<NARROW>(x0[k], fv, m), m.q);
+      acc1[r] = (W)addm<NARROW>(acc1[r], mul_mod_t<NARROW>(x1[k], fv, m), m.q);
     }
     __syncthreads();
   }
@@ -467,10 +515,12 @@ __device__ __forceinline__ void dp_hma_body(const u64* __restrict__ x, const u64
 
 template <int LOGN>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
-k_dp_hma(const u64* __restrict__ x, const u64* __restrict__ filt, u64* __restrict__ out, int level,
-         int out_base, DPGeom geo, Mods mods) {
+k_dp_hma(const u64* __restrict__ x, const u64* __restrict__ filt, u64* __restrict__ out, int level, int out_base,
+         DPGeom geo, Mods mods) {
   __shared__ u64 lds[NttGeom<LOGN>::LDS];
-  dp_hma_body<LOGN>(x, filt, out, level, out_base, geo, mods, lds);
+  const ModConst m = mods.m[blockIdx.x];
+  if (m.narrow) dp_hma_body<LOGN, true>(x, filt, out, level, out_base, geo, m, lds);
+  else dp_hma_body<LOGN, false>(x, filt, out, level, out_base, geo, m, lds);
 }
 
 // Sum of permuted-plaintext products into one accumulator per blockIdx.z:

@@ -2,8 +2,9 @@
 //
 // Residues are uint64 in [0, q).  Each prime is one of two width classes,
 // chosen per limb and uniform across a workgroup:
-//   narrow  q < 2^31 : products fit 64 bits; reductions use 32-bit multiplies
-//                      (v_mul_hi_u32 / v_mad_u64_u32);
+//   narrow  q < 2^30 : residues fit 32-bit words with headroom (4q < 2^32);
+//                      reductions use 32-bit multiplies (v_mul_hi_u32,
+//                      v_mad_u64_u32) and min-based conditional subtraction;
 //   wide    q < 2^62 : 128-bit products from __umul64hi.
 // Products with a fixed operand (twiddles, inverses) use Shoup's method with a
 // precomputed companion w' = floor(w * 2^32 / q) (narrow) or
@@ -25,7 +26,7 @@ struct ModConst {
   u64 mu64;    // floor((2^64 - 1) / q): Barrett for any 64-bit input
   u64 bmu;     // floor(2^(2s) / q): Barrett for products of residues
   u32 s;       // bit length of q
-  u32 narrow;  // q < 2^31
+  u32 narrow;  // q < 2^30
   u64 n_inv;   // N^-1 mod q
   u64 n_inv_sh;
 };
@@ -47,6 +48,9 @@ __host__ __device__ inline u64 sub_mod(u64 a, u64 b, u64 q) {
   return a >= b ? a - b : a + (q - b);
 }
 
+constexpr u64 NARROW_LIMIT = (u64)1 << 30;
+__host__ __device__ inline bool is_narrow(u64 q) { return q < NARROW_LIMIT; }
+
 // a * w mod q with Shoup companion wsh; a < 2^32 (narrow) or any a (wide).
 __host__ __device__ inline u64 mul_shoup(u64 a, u64 w, u64 wsh, u64 q, bool narrow) {
   if (narrow) {
@@ -65,12 +69,12 @@ __host__ __device__ inline u64 mul_mod(u64 a, u64 b, const ModConst& m) {
   const u64 q = m.q;
   const u32 s = m.s;
   if (m.narrow) {
-    u64 x = (u64)(u32)a * (u32)b;                    // < 2^62
-    u32 t = (u32)(x >> (s - 1));                     // < 2^(s+1) <= 2^32
-    u64 qh = ((u64)t * (u32)m.bmu) >> (s + 1);       // quotient estimate
-    u64 r = x - qh * q;                              // < 3q
-    if (r >= q) r -= q;
-    if (r >= q) r -= q;
+    const u64 x = (u64)(u32)a * (u32)b;              // < 2^60
+    const u32 t = (u32)(x >> (s - 1));               // < 2^(s+1) <= 2^31
+    const u32 qh = (u32)(((u64)t * (u32)m.bmu) >> (s + 1));  // quotient estimate
+    u32 r = (u32)x - qh * (u32)q;                    // true remainder < 3q < 2^32
+    r = r >= (u32)q ? r - (u32)q : r;
+    r = r >= (u32)q ? r - (u32)q : r;
     return r;
   }
   u64 lo = a * b, hi = mulhi64(a, b);                // x < 2^(2s)
@@ -110,12 +114,17 @@ __host__ __device__ inline u64 mul_mod_t(u64 a, u64 b, const ModConst& m) {
   const u64 q = m.q;
   const u32 s = m.s;
   if constexpr (NARROW) {
-    u64 x = (u64)(u32)a * (u32)b;
-    u32 t = (u32)(x >> (s - 1));
-    u64 qh = ((u64)t * (u32)m.bmu) >> (s + 1);
-    u64 r = x - qh * q;
-    if (r >= q) r -= q;
-    if (r >= q) r -= q;
+    const u64 x = (u64)(u32)a * (u32)b;
+    const u32 t = (u32)(x >> (s - 1));
+    const u32 qh = (u32)(((u64)t * (u32)m.bmu) >> (s + 1));
+    u32 r = (u32)x - qh * (u32)q;
+#if defined(__HIP_DEVICE_COMPILE__)
+    r = min(r, r - (u32)q);
+    r = min(r, r - (u32)q);
+#else
+    r = r >= (u32)q ? r - (u32)q : r;
+    r = r >= (u32)q ? r - (u32)q : r;
+#endif
     return r;
   } else {
     u64 lo = a * b, hi = mulhi64(a, b);
