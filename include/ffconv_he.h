@@ -245,7 +245,8 @@ int he_last_counts(const he_ctx *ctx, he_counts *out);
 
 /* ---- instrumentation (not part of the evaluated path) ---------------------
  * he_prof_select: from now on every launch of the kernel named `kernel`
- * ("ntt", "ks_digits", "ks_modup_ip", "intt_last", "drop_last", "dp_hma",
+ * ("ntt", "ks_digits", "ks_modup_ip" (30-bit targets), "ks_modup_ip_wide"
+ * (wider targets, launched on a second stream), "intt_last", "drop_last", "dp_hma",
  * "hma_perm", "scalar_mac", "tensor_sq", "modup_store", "ip_perm", "add") is
  * bracketed by two HIP events recorded on the stream it is launched on; NULL
  * or "" stops recording.  he_prof_read waits for the recorded events and

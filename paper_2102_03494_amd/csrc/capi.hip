@@ -160,20 +160,27 @@ struct LKeySwitchCore {
       // side stream, joined before the ModDown
       const TargetList& nt = c->narrow_t[level];
       const TargetList& wt = c->wide_t[level];
-      Prof pr(c, "ks_modup_ip", s);
       if (wt.n && nt.n) {
         hipEventRecord(c->fork_ev, s);
         hipStreamWaitEvent(c->side, c->fork_ev, 0);
-        k_ks_modup_ip<LOGN, false><<<dim3(wt.n, count), T, 0, c->side>>>(dcoef, c1, cstride, ginv, key, u, level,
-                                                                          c->big_l, wt, c->mods, c->tb());
-        k_ks_modup_ip<LOGN, true><<<dim3(nt.n, count), T, 0, s>>>(dcoef, c1, cstride, ginv, key, u, level, c->big_l,
-                                                                   nt, c->mods, c->tb());
+        {
+          Prof pw(c, "ks_modup_ip_wide", c->side);
+          k_ks_modup_ip<LOGN, false><<<dim3(wt.n, count), T, 0, c->side>>>(dcoef, c1, cstride, ginv, key, u, level,
+                                                                            c->big_l, wt, c->mods, c->tb());
+        }
+        {
+          Prof pn(c, "ks_modup_ip", s);
+          k_ks_modup_ip<LOGN, true><<<dim3(nt.n, count), T, 0, s>>>(dcoef, c1, cstride, ginv, key, u, level,
+                                                                     c->big_l, nt, c->mods, c->tb());
+        }
         hipEventRecord(c->join_ev, c->side);
         hipStreamWaitEvent(s, c->join_ev, 0);
       } else if (nt.n) {
+        Prof pn(c, "ks_modup_ip", s);
         k_ks_modup_ip<LOGN, true><<<dim3(nt.n, count), T, 0, s>>>(dcoef, c1, cstride, ginv, key, u, level, c->big_l,
                                                                    nt, c->mods, c->tb());
       } else {
+        Prof pw(c, "ks_modup_ip_wide", s);
         k_ks_modup_ip<LOGN, false><<<dim3(wt.n, count), T, 0, s>>>(dcoef, c1, cstride, ginv, key, u, level,
                                                                     c->big_l, wt, c->mods, c->tb());
       }

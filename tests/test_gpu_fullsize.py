@@ -127,3 +127,76 @@ def test_ffconv_n8192_full_layer_and_plain_comparator():
     for idx, (o, i, j) in enumerate(C.output_list(geom, 5)):
         v = cl.decrypt(zp.data[idx], zp.scale, 1, limbs=1)
         assert abs(v[0] - refp[i, j, o]) < 1e-3
+
+
+def test_cifar_n16384_ffconv_layer():
+    """CIFAR-shaped layer, N = 16384, 6 x 40-bit + 60-bit P (every prime wide).
+
+    FFConv 3x3 pad 1, 3 -> 8 (DensePack) -> 64 (1x1 ConvPack): the whole layer
+    on the GPU (8192 W1 dot products, 13 rotate-and-add steps each); two W1
+    outputs (interior and corner border classes) bit-exact against the
+    oracle; all 64 x 1024 outputs within 1e-3 of FP64 after decryption.
+    """
+    wl = "cifar_n16384"
+    p = P.cifar_n16384()
+    he = _he()
+    from paper_2102_03494_amd.client import Client
+    steps = C.rotate_and_sum_steps(p)
+    gctx = he.HEContext(p.n, p.q_bits, p.p_bits)
+    gctx.reserve(24 << 30)
+    assert gctx.moduli == p.q + [p.p]
+    cl = Client(gctx, wl)
+    cl.gen_rotation_keys(steps)
+    geom = C.ConvGeom(32, 32, 3, 3, 1, 1)
+    x = synth.image(wl, (32, 32, 3))
+    w1 = synth.weights(wl, 1, (3, 3, 3, 8), 0.05)
+    w2 = synth.weights(wl, 2, (8, 64), 0.05)
+    level = 6
+    octx = Wk.make_context(p, wl, rotations=steps)
+    ct = Wk.encrypt_slots(octx, C.densepack_slots(x, geom, p.slots)[0], level, p.scale, wl, 0)
+    xin = he.Ct(he.to_device(ct.c[None]), p.scale)
+    pts = C.densepack_pt_scale(p, level, p.scale, p.scale)
+    bf = C.densepack_base_filters(p, w1, geom, level, pts)
+    desc = he.HEContext.conv_desc(32, 32, 3, 3, 1, 1, 8, len(steps))
+    ms = C.gather_mask_scale(p, level - 1, p.scale * pts / p.q[level - 1], p.scale, 12)
+    mask = C.encode_onehot(p, level - 1, ms)
+    z = gctx.ffconv_layer(xin, desc, he.to_device(bf), pts, he.to_device(mask), ms, w2, 12, False)
+    torch.cuda.synchronize()
+    ref = R.ffconv_reference(x, w1, w2, 1, 1)
+    worst = 0.0
+    for o in range(64):
+        v = cl.decrypt(z.data[o], z.scale, geom.spatial, limbs=1)
+        worst = max(worst, float(np.abs(v - ref[:, :, o].ravel()).max()))
+    assert worst < 1e-3, worst
+    del z
+    # sampled W1 dot products, bit for bit (corner class and an interior output)
+    y = gctx.conv_densepack(xin, desc, he.to_device(bf), pts)
+    sample = [0, 5 * 1024 + 17 * 32 + 9]
+    outs = C.output_list(geom, 8)
+    want, _ = C.conv_densepack(p, octx, ct, geom, bf, pts, outputs=[outs[i] for i in sample])
+    for k, i in enumerate(sample):
+        assert np.array_equal(he.to_host(y.data[i]), want.c[k]), i
+
+
+def test_hoisted_256_rotations_n16384():
+    """One L = 6 ciphertext rotated by 256 seeded amounts with one shared ModUp."""
+    wl = "batched_n16384"
+    p = P.cifar_n16384()
+    he = _he()
+    from paper_2102_03494_amd.client import Client
+    amounts = [int(k) for k in synth.rotation_amounts(wl, 256, p.slots)]
+    gctx = he.HEContext(p.n, p.q_bits, p.p_bits)
+    gctx.reserve(2 << 30)
+    cl = Client(gctx, wl)
+    cl.gen_rotation_keys(amounts)
+    sample = [amounts[0], amounts[137], amounts[-1]]
+    octx = Wk.make_context(p, wl, rotations=sample)
+    z = synth.message(wl, p.slots)
+    ct = Wk.encrypt_slots(octx, z, 6, p.scale, wl, 0)
+    outs = gctx.rotate_hoisted(he.Ct(he.to_device(ct.c), p.scale), amounts)
+    for k in sample:
+        r = amounts.index(k)
+        assert np.array_equal(he.to_host(outs.data[r]), S.rotate(p, octx, ct, k).c), k
+    for r in (3, 200):
+        v = cl.decrypt(outs.data[r], outs.scale, 64, limbs=1)
+        assert np.abs(v - np.roll(z, -amounts[r])[:64]).max() < 1e-4
