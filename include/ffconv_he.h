@@ -177,6 +177,35 @@ int he_rotate_hoisted(he_ctx *ctx, const uint64_t *d_in, int level, const int32_
                       uint64_t *d_outs, void *stream);
 int he_rotsum(he_ctx *ctx, uint64_t *d_cts, int count, int level, int r_steps, void *stream);
 
+/* ---- batched calls over ragged batches --------------------------------------
+ * Each item has its own device pointers and level (host arrays of `count`
+ * entries); all items of a call run in one launch per kernel, so work from
+ * different layers, requests or levels shares launches.
+ * he_batch_rotate: d_outs[b] ([2][level_b][N]) = Rot(d_ins[b], h_steps[b])
+ *          (step 0 copies), or d_ins[b] + Rot(d_ins[b], step) when
+ *          accumulate != 0; d_outs[b] may alias d_ins[b].
+ * he_batch_rescale: d_outs[b] = rescale of d_ins[b] from level_b to
+ *          level_b - 1 (level_b >= 2, no aliasing).
+ * he_batch_mul_plain: d_outs[b] = d_cts[b] * d_pts[b] slot-wise (MulPC),
+ *          d_pts[b] = [level_b][N] NTT-domain plaintext. */
+int he_batch_rotate(he_ctx *ctx, uint64_t *const *h_outs, const uint64_t *const *h_ins, const int32_t *h_levels,
+                    const int32_t *h_steps, int count, int accumulate, void *stream);
+int he_batch_rescale(he_ctx *ctx, uint64_t *const *h_outs, const uint64_t *const *h_ins, const int32_t *h_levels,
+                     int count, void *stream);
+int he_batch_mul_plain(he_ctx *ctx, uint64_t *const *h_outs, const uint64_t *const *h_cts,
+                       const uint64_t *const *h_pts, const int32_t *h_levels, int count, void *stream);
+
+/* ---- CP -> DP combine (Table III, CP-HI2C-DP) ------------------------------
+ * O_c channel ciphertexts in ConvPack form (channel o holds its S values in
+ * slots 0..S-1, zeros elsewhere), d_in = [o_c][2][level][N], are packed into
+ * ceil(O_c / B) DensePack ciphertexts (B = per_dense channels each):
+ * dense_m = sum_{o in block m} Rot(Z_o, -(o mod B) * S), so channel o lands
+ * at slots (o mod B) * S .. + S - 1 of dense ciphertext o / B.  Needs the
+ * rotation keys of -k*S, 0 < k < B; B*S <= N/2.
+ * d_out = [ceil(o_c / B)][2][level][N]. */
+int he_combine_cp_dp(he_ctx *ctx, const uint64_t *d_in, int o_c, int level, int spatial, int per_dense,
+                     uint64_t *d_out, void *stream);
+
 /* ---- square (the x^2 activation, Section 2.1) ------------------------------
  * d_out[i] = relinearised (c0^2, 2 c0 c1) + KeySwitch(c1^2) under the key for
  * s^2, for `count` ciphertexts; the scale squares (no rescale). */

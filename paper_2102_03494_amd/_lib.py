@@ -68,6 +68,10 @@ SIGNATURES = {
     "he_rotate_hoisted": (I, [P, P, I, I32P, I, P, P]),
     "he_rotsum": (I, [P, P, I, I, I, P]),
     "he_square": (I, [P, P, P, I, I, P]),
+    "he_batch_rotate": (I, [P, ctypes.POINTER(P), ctypes.POINTER(P), I32P, I32P, I, I, P]),
+    "he_batch_rescale": (I, [P, ctypes.POINTER(P), ctypes.POINTER(P), I32P, I, P]),
+    "he_batch_mul_plain": (I, [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), I32P, I, P]),
+    "he_combine_cp_dp": (I, [P, P, I, I, I, I, P, P]),
     "he_conv_densepack": (I, [P, P, I, ctypes.POINTER(HeConvDesc), P, P, P]),
     "he_conv_convpack": (I, [P, P, I, I, DP, I, ctypes.c_double, P, P]),
     "ffconv_layer": (I, [P, P, I, ctypes.POINTER(HeConvDesc), P, P, DP, I, I, I, P, P]),

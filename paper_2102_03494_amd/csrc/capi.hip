@@ -5,8 +5,8 @@
 
 #include <algorithm>
 #include <cmath>
-#include <cstdio>
 #include <cstdarg>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <string>
@@ -18,12 +18,25 @@
 
 using namespace he;
 
+namespace {
+// Pinned staging ring for small host tables (job tables, weight residues).
+struct StageSlot {
+  char* host = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  bool pending = false;
+};
+constexpr int STAGE_SLOTS = 64;
+}  // namespace
+
 struct he_ctx {
   int n = 0, logn = 0, big_l = 0;
   std::vector<u64> moduli;  // q_0..q_{L-1}, P
   Mods mods{};
+  bool has_narrow = false, has_wide = false;
   u64* d_tw = nullptr;    // [L+1][4][N] 64-bit twiddles + Shoup companions
   u32* d_tw32 = nullptr;  // 32-bit copies for the narrow moduli
+  u64* d_inv = nullptr;   // [2][HE_MAXM][HE_MAXM]: m_div^-1 mod q_t and Shoup companions
   Tables tb() const { return Tables{d_tw, d_tw32}; }
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -38,7 +51,8 @@ struct he_ctx {
   // second stream (default priority) for the wide-modulus share of a launch
   hipStream_t side = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
-  TargetList narrow_t[HE_MAXM + 1], wide_t[HE_MAXM + 1];  // per level: ModUp targets by class
+  StageSlot stage[STAGE_SLOTS];
+  int stage_next = 0;
 };
 
 namespace {
@@ -82,14 +96,14 @@ struct Prof {
   Prof(he_ctx* ctx, const char* name, hipStream_t st) : c(ctx), s(st) {
     if (!c->prof_kernel.empty() && c->prof_kernel == name) {
       a = prof_event(c);
-      if (a) hipEventRecord(a, s);
+      if (a) (void)hipEventRecord(a, s);
     }
   }
   ~Prof() {
     if (!a) return;
     hipEvent_t b = prof_event(c);
     if (!b) return;
-    hipEventRecord(b, s);
+    (void)hipEventRecord(b, s);
     c->prof_events.push_back({a, b});
   }
 };
@@ -129,6 +143,35 @@ int dispatch_logn(int logn, A&&... args) {
   }
 }
 
+// Copies `bytes` from host to device memory `dst` on stream s through a ring
+// of pinned buffers; a slot is reused only after its previous copy finished.
+int upload(he_ctx* c, void* dst, const void* src, size_t bytes, hipStream_t s) {
+  StageSlot& st = c->stage[c->stage_next];
+  c->stage_next = (c->stage_next + 1) % STAGE_SLOTS;
+  if (st.pending) {
+    if (hipEventSynchronize(st.ev) != hipSuccess) return fail(c, HE_EDEVICE, "staging event wait failed");
+    st.pending = false;
+  }
+  if (st.cap < bytes) {
+    if (st.host) (void)hipHostFree(st.host);
+    size_t cap = std::max<size_t>(bytes, 1 << 16);
+    if (hipHostMalloc((void**)&st.host, cap, hipHostMallocDefault) != hipSuccess) {
+      st.host = nullptr;
+      st.cap = 0;
+      return fail(c, HE_ENOMEM, "pinned staging allocation failed");
+    }
+    st.cap = cap;
+  }
+  if (!st.ev && hipEventCreateWithFlags(&st.ev, hipEventDisableTiming) != hipSuccess)
+    return fail(c, HE_EDEVICE, "event create failed");
+  std::memcpy(st.host, src, bytes);
+  if (hipMemcpyAsync(dst, st.host, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+    return fail(c, HE_EDEVICE, "staging copy failed");
+  (void)hipEventRecord(st.ev, s);
+  st.pending = true;
+  return HE_OK;
+}
+
 // ---- launch wrappers (templated on log2 N) ---------------------------------
 
 template <int LOGN>
@@ -143,90 +186,74 @@ struct LNtt {
   }
 };
 
-// Key switch of `count` polynomials: input c1 (NTT domain, permuted by g
-// before decomposition), result (u0, u1) in u, P limb INTT in rcoef.
+// Key switch of a job batch: digits -> ModUp + inner product -> INTT of P.
 template <int LOGN>
-struct LKeySwitchCore {
-  static void run(he_ctx* c, const u64* c1, size_t cstride, u32 ginv, const u64* key, int count, int level,
-                  u64* dcoef, u64* u, u64* rcoef, hipStream_t s) {
+struct LKsCore {
+  static void run(he_ctx* c, const KsJob* jobs, int count, int lmax, u64* dcoef, u64* u, u64* rc, hipStream_t s) {
     constexpr int T = NttGeom<LOGN>::T;
-    constexpr size_t N = (size_t)1 << LOGN;
     {
       Prof pr(c, "ks_digits", s);
-      k_ks_digits<LOGN><<<dim3(level, count), T, 0, s>>>(c1, cstride, ginv, dcoef, level, c->mods, c->tb());
+      k_ks_digits<LOGN><<<dim3(lmax, count), T, 0, s>>>(jobs, dcoef, lmax, c->mods, c->tb());
     }
-    {
+    const dim3 grid(lmax + 1, count);
+    if (c->has_narrow && c->has_wide) {
       // narrow targets on the caller's stream, wide targets (e.g. P) on the
       // side stream, joined before the ModDown
-      const TargetList& nt = c->narrow_t[level];
-      const TargetList& wt = c->wide_t[level];
-      if (wt.n && nt.n) {
-        hipEventRecord(c->fork_ev, s);
-        hipStreamWaitEvent(c->side, c->fork_ev, 0);
-        {
-          Prof pw(c, "ks_modup_ip_wide", c->side);
-          k_ks_modup_ip<LOGN, false><<<dim3(wt.n, count), T, 0, c->side>>>(dcoef, c1, cstride, ginv, key, u, level,
-                                                                            c->big_l, wt, c->mods, c->tb());
-        }
-        {
-          Prof pn(c, "ks_modup_ip", s);
-          k_ks_modup_ip<LOGN, true><<<dim3(nt.n, count), T, 0, s>>>(dcoef, c1, cstride, ginv, key, u, level,
-                                                                     c->big_l, nt, c->mods, c->tb());
-        }
-        hipEventRecord(c->join_ev, c->side);
-        hipStreamWaitEvent(s, c->join_ev, 0);
-      } else if (nt.n) {
-        Prof pn(c, "ks_modup_ip", s);
-        k_ks_modup_ip<LOGN, true><<<dim3(nt.n, count), T, 0, s>>>(dcoef, c1, cstride, ginv, key, u, level, c->big_l,
-                                                                   nt, c->mods, c->tb());
-      } else {
-        Prof pw(c, "ks_modup_ip_wide", s);
-        k_ks_modup_ip<LOGN, false><<<dim3(wt.n, count), T, 0, s>>>(dcoef, c1, cstride, ginv, key, u, level,
-                                                                    c->big_l, wt, c->mods, c->tb());
+      (void)hipEventRecord(c->fork_ev, s);
+      (void)hipStreamWaitEvent(c->side, c->fork_ev, 0);
+      {
+        Prof pw(c, "ks_modup_ip_wide", c->side);
+        k_ks_modup_ip<LOGN, false><<<grid, T, 0, c->side>>>(jobs, dcoef, u, lmax, c->big_l, c->mods, c->tb());
       }
+      {
+        Prof pn(c, "ks_modup_ip", s);
+        k_ks_modup_ip<LOGN, true><<<grid, T, 0, s>>>(jobs, dcoef, u, lmax, c->big_l, c->mods, c->tb());
+      }
+      (void)hipEventRecord(c->join_ev, c->side);
+      (void)hipStreamWaitEvent(s, c->join_ev, 0);
+    } else if (c->has_narrow) {
+      Prof pn(c, "ks_modup_ip", s);
+      k_ks_modup_ip<LOGN, true><<<grid, T, 0, s>>>(jobs, dcoef, u, lmax, c->big_l, c->mods, c->tb());
+    } else {
+      Prof pw(c, "ks_modup_ip_wide", s);
+      k_ks_modup_ip<LOGN, false><<<grid, T, 0, s>>>(jobs, dcoef, u, lmax, c->big_l, c->mods, c->tb());
     }
     Prof pr(c, "intt_last", s);
-    k_intt_last<LOGN><<<dim3(2 * count), T, 0, s>>>(u, (size_t)(level + 1) * N, level, c->big_l, rcoef, c->mods,
-                                                     c->tb());
+    k_intt_last<LOGN, MODE_P><<<dim3(2 * count), T, 0, s>>>(jobs, u, lmax, c->big_l, rc, c->mods, c->tb());
   }
 };
 
 template <int LOGN>
-struct LDropLast {
-  static void run(he_ctx* c, int epi, const u64* src, size_t pstride, const u64* rcoef, int div_mi, int keep,
-                  int n_polys, EpiArgs ea, hipStream_t s) {
+struct LDrop {
+  static void run(he_ctx* c, int mode, int epi, const KsJob* jobs, int count, int lmax, const u64* u, const u64* rc,
+                  hipStream_t s) {
     constexpr int T = NttGeom<LOGN>::T;
-    ConstTable inv{};
-    const u64 d = c->moduli[div_mi];
-    for (int t = 0; t < keep; ++t) {
-      inv.v[t] = inv_mod(d % c->moduli[t], c->moduli[t]);
-      inv.sh[t] = shoup_companion(inv.v[t], c->moduli[t]);
-    }
-    dim3 grid(keep, n_polys);
+    const int keep = mode == MODE_P ? lmax : lmax - 1;
+    const dim3 grid(keep, 2 * count);
     Prof pr(c, "drop_last", s);
-    switch (epi) {
-      case EPI_STORE:
-        k_drop_last<LOGN, EPI_STORE><<<grid, T, 0, s>>>(src, pstride, rcoef, div_mi, inv, ea, c->mods, c->tb());
-        break;
-      case EPI_ROT:
-        k_drop_last<LOGN, EPI_ROT><<<grid, T, 0, s>>>(src, pstride, rcoef, div_mi, inv, ea, c->mods, c->tb());
-        break;
-      case EPI_ROTSUM:
-        k_drop_last<LOGN, EPI_ROTSUM><<<grid, T, 0, s>>>(src, pstride, rcoef, div_mi, inv, ea, c->mods, c->tb());
-        break;
-      default:
-        k_drop_last<LOGN, EPI_RELIN><<<grid, T, 0, s>>>(src, pstride, rcoef, div_mi, inv, ea, c->mods, c->tb());
-        break;
+#define HE_DROP(MD, EP) \
+  k_drop_last<LOGN, MD, EP><<<grid, T, 0, s>>>(jobs, u, lmax, c->big_l, rc, c->d_inv, c->mods, c->tb())
+    if (mode == MODE_LAST) {
+      HE_DROP(MODE_LAST, EPI_STORE);
+    } else if (epi == EPI_ROT) {
+      HE_DROP(MODE_P, EPI_ROT);
+    } else if (epi == EPI_ROTSUM) {
+      HE_DROP(MODE_P, EPI_ROTSUM);
+    } else if (epi == EPI_RELIN) {
+      HE_DROP(MODE_P, EPI_RELIN);
+    } else {
+      HE_DROP(MODE_P, EPI_STORE);
     }
+#undef HE_DROP
   }
 };
 
 template <int LOGN>
 struct LIntt1 {
-  static void run(he_ctx* c, const u64* src, size_t pstride, int limb, int mi, u64* rcoef, int n_polys,
-                  hipStream_t s) {
+  static void run(he_ctx* c, const KsJob* jobs, int count, int lmax, u64* rc, hipStream_t s) {
     Prof pr(c, "intt_last", s);
-    k_intt_last<LOGN><<<dim3(n_polys), NttGeom<LOGN>::T, 0, s>>>(src, pstride, limb, mi, rcoef, c->mods, c->tb());
+    k_intt_last<LOGN, MODE_LAST><<<dim3(2 * count), NttGeom<LOGN>::T, 0, s>>>(jobs, nullptr, lmax, c->big_l, rc,
+                                                                              c->mods, c->tb());
   }
 };
 
@@ -260,69 +287,114 @@ struct LKeygen {
   }
 };
 
+// Hoisted rotations: digits of c1 and the lifted digits, computed once ...
+template <int LOGN>
+struct LHoistUp {
+  static void run(he_ctx* c, const KsJob* job1, const u64* c1, int level, u64* dcoef, u64* dhat, hipStream_t s) {
+    constexpr int T = NttGeom<LOGN>::T;
+    k_ks_digits<LOGN><<<dim3(level, 1), T, 0, s>>>(job1, dcoef, level, c->mods, c->tb());
+    Prof pr(c, "modup_store", s);
+    k_modup_store<LOGN><<<dim3(level + 1, level), T, 0, s>>>(dcoef, c1, dhat, level, c->big_l, c->mods, c->tb());
+  }
+};
+
+// ... then, per chunk of rotations: inner product with each key, ModDown.
+template <int LOGN>
+struct LHoisted {
+  static void run(he_ctx* c, const KsJob* jobs, int m, int level, const u64* dhat, u64* u, u64* rc, hipStream_t s) {
+    constexpr int T = NttGeom<LOGN>::T;
+    constexpr int N = 1 << LOGN;
+    {
+      Prof pr(c, "ip_perm", s);
+      k_ip_perm<LOGN><<<dim3(N / 256, level + 1, m), 256, 0, s>>>(dhat, jobs, u, level, c->big_l, c->mods);
+    }
+    {
+      Prof pr(c, "intt_last", s);
+      k_intt_last<LOGN, MODE_P><<<dim3(2 * m), T, 0, s>>>(jobs, u, level, c->big_l, rc, c->mods, c->tb());
+    }
+    LDrop<LOGN>::run(c, MODE_P, EPI_ROT, jobs, m, level, u, rc, s);
+  }
+};
+
 // ---- shared orchestration ----------------------------------------------------
 
-size_t ks_elems(int count, int level, int n) { return (size_t)count * (3 * (size_t)level + 4) * n; }
+size_t ks_elems_per_job(int lmax, int n) { return (3 * (size_t)lmax + 4) * n; }
 
-// Rotation (EPI_ROT into out) or rotate-and-add (EPI_ROTSUM in place) of
-// `count` ciphertexts by k, chunked to the workspace.
+struct KsScratch {
+  KsJob* jobs = nullptr;
+  u64 *dcoef = nullptr, *u = nullptr, *rc = nullptr;
+};
+
+bool take_scratch(Arena& ar, int count, int lmax, int n, KsScratch& ks) {
+  ks.jobs = ar.take<KsJob>(count);
+  ks.dcoef = ar.take<u64>((size_t)count * lmax * n);
+  ks.u = ar.take<u64>((size_t)count * 2 * (lmax + 1) * n);
+  ks.rc = ar.take<u64>((size_t)count * 2 * n);
+  return ks.jobs && ks.dcoef && ks.u && ks.rc;
+}
+
+// Jobs that fit the arena with key-switch scratch at lmax (+ extra per job).
+int chunk_for(Arena& ar, int count, int lmax, int n, size_t extra_per_job_elems = 0) {
+  const size_t per = ks_elems_per_job(lmax, n) + extra_per_job_elems + 128;
+  return (int)std::min<size_t>({(size_t)count, ar.left() / 8 / per, (size_t)32000});
+}
+
+void make_jobs(he_ctx* c, KsJob* jobs, int count, const u64* d_base, size_t d_stride, const u64* c_base,
+               size_t c_stride, u64* out_base, size_t out_stride, const u64* key, u32 g, u32 ginv, int level,
+               hipStream_t s) {
+  (void)c;
+  k_make_jobs<<<(count + 255) / 256, 256, 0, s>>>(jobs, count, d_base, d_stride, c_base, c_stride, out_base,
+                                                  out_stride, key, g, ginv, level);
+}
+
+// Rotation (EPI_ROT into out) or rotate-and-add (EPI_ROTSUM, may be in place)
+// of `count` ciphertexts at one level by k, chunked to the workspace.
 int rotate_batch(he_ctx* c, u64* out, const u64* in, int count, int level, int k, int epi, Arena& ar,
                  hipStream_t s) {
   const int n = c->n;
   const u32 g = galois_of(k, n);
-  if (g == 1) {  // rotation by a multiple of N/2 slots: identity
-    if (epi == EPI_ROT) {
-      if (out != in) hipMemcpyAsync(out, in, (size_t)count * 2 * level * n * 8, hipMemcpyDeviceToDevice, s);
-      return HE_OK;
-    }
-    // t + t
-    dim3 grid(n / 256, level, count);
-    k_add<<<grid, 256, 0, s>>>(out, in, in, level, n, c->mods);
-    return check_launch(c, "add");
+  const u64* key = nullptr;
+  if (g != 1) {
+    auto it = c->keys.find((int)g);
+    if (it == c->keys.end()) return fail(c, HE_ENOKEY, "no rotation key for step %d (Galois element %u)", k, g);
+    key = it->second;
   }
-  auto it = c->keys.find((int)g);
-  if (it == c->keys.end()) return fail(c, HE_ENOKEY, "no rotation key for step %d (Galois element %u)", k, g);
   const u32 ginv = galois_of(-k, n);
-  const size_t per = ks_elems(1, level, n);
-  size_t avail = ar.left() / 8;
-  int chunk = (int)std::min<size_t>((size_t)count, avail / (per + 64));
-  chunk = std::min(chunk, 32000);
+  const int chunk = chunk_for(ar, count, level, n);
   if (chunk < 1) return fail(c, HE_ENOMEM, "workspace too small for one key switch at level %d", level);
   Arena sub = ar;
-  u64* dcoef = sub.take<u64>((size_t)chunk * level * n);
-  u64* u = sub.take<u64>((size_t)chunk * 2 * (level + 1) * n);
-  u64* rc = sub.take<u64>((size_t)chunk * 2 * n);
-  if (!dcoef || !u || !rc) return fail(c, HE_ENOMEM, "workspace too small");
+  KsScratch ks;
+  if (!take_scratch(sub, chunk, level, n, ks)) return fail(c, HE_ENOMEM, "workspace too small");
   const size_t cstride = (size_t)2 * level * n;
   for (int b0 = 0; b0 < count; b0 += chunk) {
     const int cn = std::min(chunk, count - b0);
     const u64* cin = in + (size_t)b0 * cstride;
     u64* cout = out + (size_t)b0 * cstride;
-    dispatch_logn<LKeySwitchCore>(c->logn, c, cin + (size_t)level * n, cstride, ginv, it->second, cn, level, dcoef,
-                                  u, rc, s);
-    EpiArgs ea{cout, (size_t)level * n, cin, (size_t)level * n, g, ginv, nullptr};
-    dispatch_logn<LDropLast>(c->logn, c, epi, (const u64*)u, (size_t)(level + 1) * n, (const u64*)rc, c->big_l,
-                             level, 2 * cn, ea, s);
+    make_jobs(c, ks.jobs, cn, cin + (size_t)level * n, cstride, cin, cstride, cout, cstride, key, g, ginv, level, s);
+    if (key) dispatch_logn<LKsCore>(c->logn, c, (const KsJob*)ks.jobs, cn, level, ks.dcoef, ks.u, ks.rc, s);
+    dispatch_logn<LDrop>(c->logn, c, (int)MODE_P, epi, (const KsJob*)ks.jobs, cn, level, (const u64*)ks.u,
+                         (const u64*)ks.rc, s);
   }
   return check_launch(c, "rotate");
 }
 
 int rescale_batch(he_ctx* c, u64* out, const u64* in, int count, int level, Arena& ar, hipStream_t s) {
   const int n = c->n;
-  size_t avail = ar.left() / 8;
-  int chunk = (int)std::min<size_t>((size_t)count, avail / (2 * (size_t)n + 64));
-  chunk = std::min(chunk, 32000);
+  const int chunk = (int)std::min<size_t>({(size_t)count, ar.left() / 8 / (2 * (size_t)n + 64), (size_t)32000});
   if (chunk < 1) return fail(c, HE_ENOMEM, "workspace too small for rescale");
   Arena sub = ar;
+  KsJob* jobs = sub.take<KsJob>(chunk);
   u64* rc = sub.take<u64>((size_t)chunk * 2 * n);
+  if (!jobs || !rc) return fail(c, HE_ENOMEM, "workspace too small for rescale");
   for (int b0 = 0; b0 < count; b0 += chunk) {
     const int cn = std::min(chunk, count - b0);
     const u64* cin = in + (size_t)b0 * 2 * level * n;
     u64* cout = out + (size_t)b0 * 2 * (level - 1) * n;
-    dispatch_logn<LIntt1>(c->logn, c, cin, (size_t)level * n, level - 1, level - 1, rc, 2 * cn, s);
-    EpiArgs ea{cout, (size_t)(level - 1) * n, nullptr, 0, 1u, 1u, nullptr};
-    dispatch_logn<LDropLast>(c->logn, c, EPI_STORE, cin, (size_t)level * n, (const u64*)rc, level - 1, level - 1,
-                             2 * cn, ea, s);
+    make_jobs(c, jobs, cn, cin, (size_t)2 * level * n, cin, (size_t)2 * level * n, cout,
+              (size_t)2 * (level - 1) * n, nullptr, 1u, 1u, level, s);
+    dispatch_logn<LIntt1>(c->logn, c, (const KsJob*)jobs, cn, level, rc, s);
+    dispatch_logn<LDrop>(c->logn, c, (int)MODE_LAST, (int)EPI_STORE, (const KsJob*)jobs, cn, level,
+                         (const u64*)nullptr, (const u64*)rc, s);
   }
   return check_launch(c, "rescale");
 }
@@ -331,17 +403,13 @@ int square_batch(he_ctx* c, u64* out, const u64* in, int count, int level, Arena
   const int n = c->n;
   auto it = c->keys.find(0);
   if (it == c->keys.end()) return fail(c, HE_ENOKEY, "no relinearisation key");
-  const size_t per = ks_elems(1, level, n) + 3 * (size_t)level * n;
-  int chunk = (int)std::min<size_t>((size_t)count, (ar.left() / 8) / (per + 128));
-  chunk = std::min(chunk, 32000);
+  const int chunk = chunk_for(ar, count, level, n, 3 * (size_t)level * n);
   if (chunk < 1) return fail(c, HE_ENOMEM, "workspace too small for square");
   Arena sub = ar;
   u64* d01 = sub.take<u64>((size_t)chunk * 2 * level * n);
   u64* d2 = sub.take<u64>((size_t)chunk * level * n);
-  u64* dcoef = sub.take<u64>((size_t)chunk * level * n);
-  u64* u = sub.take<u64>((size_t)chunk * 2 * (level + 1) * n);
-  u64* rc = sub.take<u64>((size_t)chunk * 2 * n);
-  if (!d01 || !d2 || !dcoef || !u || !rc) return fail(c, HE_ENOMEM, "workspace too small");
+  KsScratch ks;
+  if (!d01 || !d2 || !take_scratch(sub, chunk, level, n, ks)) return fail(c, HE_ENOMEM, "workspace too small");
   for (int b0 = 0; b0 < count; b0 += chunk) {
     const int cn = std::min(chunk, count - b0);
     const u64* cin = in + (size_t)b0 * 2 * level * n;
@@ -350,17 +418,18 @@ int square_batch(he_ctx* c, u64* out, const u64* in, int count, int level, Arena
       Prof pr(c, "tensor_sq", s);
       k_tensor_sq<<<dim3(n / 256, level, cn), 256, 0, s>>>(d01, d2, cin, level, n, c->mods);
     }
-    dispatch_logn<LKeySwitchCore>(c->logn, c, (const u64*)d2, (size_t)level * n, 1u, it->second, cn, level, dcoef,
-                                  u, rc, s);
-    EpiArgs ea{cout, (size_t)level * n, d01, (size_t)level * n, 1u, 1u, nullptr};
-    dispatch_logn<LDropLast>(c->logn, c, EPI_RELIN, (const u64*)u, (size_t)(level + 1) * n, (const u64*)rc,
-                             c->big_l, level, 2 * cn, ea, s);
+    make_jobs(c, ks.jobs, cn, d2, (size_t)level * n, d01, (size_t)2 * level * n, cout, (size_t)2 * level * n,
+              it->second, 1u, 1u, level, s);
+    dispatch_logn<LKsCore>(c->logn, c, (const KsJob*)ks.jobs, cn, level, ks.dcoef, ks.u, ks.rc, s);
+    dispatch_logn<LDrop>(c->logn, c, (int)MODE_P, (int)EPI_RELIN, (const KsJob*)ks.jobs, cn, level,
+                         (const u64*)ks.u, (const u64*)ks.rc, s);
   }
   return check_launch(c, "square");
 }
 
 bool build_geom(he_ctx* c, const he_conv_desc* d, DPGeom& g, int& n_cls) {
-  if (!d || d->h < 1 || d->w < 1 || d->c_in < 1 || d->d < 1 || d->stride < 1 || d->pad < 0 || d->o_c < 1)
+  if (!d || d->h < 1 || d->w < 1 || d->c_in < 1 || d->d < 1 || d->stride < 1 || d->pad < 0 || d->o_c < 1 ||
+      d->r_steps < 0 || d->r_steps > 20)
     return false;
   g = DPGeom{};
   g.h = d->h; g.w = d->w; g.c_in = d->c_in; g.d = d->d; g.stride = d->stride; g.pad = d->pad; g.o_c = d->o_c;
@@ -409,9 +478,7 @@ int densepack_run(he_ctx* c, const u64* d_in, int level, const he_conv_desc* des
     if (g != 1 && !c->keys.count((int)g)) return fail(c, HE_ENOKEY, "missing rotation key for step %d", 1 << j);
   }
   // per output: accumulator (2 level N) + key switch temporaries
-  const size_t per = (size_t)2 * level * n + ks_elems(1, level, n) + 2 * (size_t)n;
-  int chunk = (int)std::min<size_t>((size_t)total, (ar.left() / 8) / (per + 128));
-  chunk = std::min(chunk, 16000);
+  const int chunk = std::min(chunk_for(ar, total, level, n, (size_t)2 * level * n + 2 * (size_t)n), 16000);
   if (chunk < 1) return fail(c, HE_ENOMEM, "workspace too small for DensePack");
   for (int o0 = 0; o0 < total; o0 += chunk) {
     const int cn = std::min(chunk, total - o0);
@@ -431,51 +498,6 @@ int densepack_run(he_ctx* c, const u64* d_in, int level, const he_conv_desc* des
   c->counts.rot += (int64_t)total * desc->r_steps;
   c->counts.rescale += total;
   return check_launch(c, "densepack");
-}
-
-}  // namespace
-
-// ---- staging of small host tables (double-buffered pinned memory) ------------
-
-struct Stage {
-  char* host[2] = {nullptr, nullptr};
-  size_t cap[2] = {0, 0};
-  hipEvent_t ev[2] = {nullptr, nullptr};
-  bool pending[2] = {false, false};
-  int next = 0;
-};
-static std::map<const he_ctx*, Stage> g_stage;
-
-namespace {
-
-// Copies `bytes` from host to the device pointer `dst` on stream s, through a
-// pinned buffer whose previous copy is waited for first.
-int upload(he_ctx* c, void* dst, const void* src, size_t bytes, hipStream_t s) {
-  Stage& st = g_stage[c];
-  const int k = st.next;
-  st.next ^= 1;
-  if (st.pending[k]) {
-    if (hipEventSynchronize(st.ev[k]) != hipSuccess) return fail(c, HE_EDEVICE, "staging event wait failed");
-    st.pending[k] = false;
-  }
-  if (st.cap[k] < bytes) {
-    if (st.host[k]) hipHostFree(st.host[k]);
-    size_t cap = std::max<size_t>(bytes, 1 << 20);
-    if (hipHostMalloc((void**)&st.host[k], cap, hipHostMallocDefault) != hipSuccess) {
-      st.host[k] = nullptr;
-      st.cap[k] = 0;
-      return fail(c, HE_ENOMEM, "pinned staging allocation failed");
-    }
-    st.cap[k] = cap;
-  }
-  if (!st.ev[k] && hipEventCreateWithFlags(&st.ev[k], hipEventDisableTiming) != hipSuccess)
-    return fail(c, HE_EDEVICE, "event create failed");
-  std::memcpy(st.host[k], src, bytes);
-  if (hipMemcpyAsync(dst, st.host[k], bytes, hipMemcpyHostToDevice, s) != hipSuccess)
-    return fail(c, HE_EDEVICE, "staging copy failed");
-  hipEventRecord(st.ev[k], s);
-  st.pending[k] = true;
-  return HE_OK;
 }
 
 bool level_ok(he_ctx* c, int level) { return level >= 1 && level <= c->big_l; }
@@ -513,29 +535,32 @@ int scalar_mac(he_ctx* c, u64* out, const u64* in, int k, const std::vector<int6
   return check_launch(c, "scalar_mac");
 }
 
-}  // namespace
-
-template <int LOGN>
-struct LHoisted {
-  static void run(he_ctx* c, const u64* in, int level, int m, const u64* const* d_keys, const u32* d_gp, u64* dcoef,
-                  u64* dhat, u64* u, u64* rc, u64* outs, hipStream_t s) {
-    constexpr int T = NttGeom<LOGN>::T;
-    constexpr int N = 1 << LOGN;
-    const u64* c1 = in + (size_t)level * N;
-    k_ks_digits<LOGN><<<dim3(level, 1), T, 0, s>>>(c1, 0, 1u, dcoef, level, c->mods, c->tb());
-    {
-      Prof pr(c, "modup_store", s);
-      k_modup_store<LOGN><<<dim3(level + 1, level), T, 0, s>>>(dcoef, c1, dhat, level, c->big_l, c->mods, c->tb());
-    }
-    {
-      Prof pr(c, "ip_perm", s);
-      k_ip_perm<LOGN><<<dim3(N / 256, level + 1, m), 256, 0, s>>>(dhat, d_keys, d_gp, u, level, c->big_l, c->mods);
-    }
-    k_intt_last<LOGN><<<dim3(2 * m), T, 0, s>>>(u, (size_t)(level + 1) * N, level, c->big_l, rc, c->mods, c->tb());
-    EpiArgs ea{outs, (size_t)level * N, in, 0, 1u, 1u, d_gp};
-    LDropLast<LOGN>::run(c, EPI_ROT, u, (size_t)(level + 1) * N, rc, c->big_l, level, 2 * m, ea, s);
+// Ragged rotation batch from host job descriptions (each job its own level,
+// input, output, key and Galois element; identity jobs copy).
+int rotate_jobs(he_ctx* c, std::vector<KsJob>& jobs, int epi, Arena& ar, hipStream_t s) {
+  const int n = c->n;
+  const int count = (int)jobs.size();
+  int lmax = 1;
+  for (auto& j : jobs) lmax = std::max(lmax, j.level);
+  const int chunk = chunk_for(ar, count, lmax, n);
+  if (chunk < 1) return fail(c, HE_ENOMEM, "workspace too small for a batched rotation");
+  Arena sub = ar;
+  KsScratch ks;
+  if (!take_scratch(sub, chunk, lmax, n, ks)) return fail(c, HE_ENOMEM, "workspace too small");
+  for (int b0 = 0; b0 < count; b0 += chunk) {
+    const int cn = std::min(chunk, count - b0);
+    int e = upload(c, ks.jobs, jobs.data() + b0, (size_t)cn * sizeof(KsJob), s);
+    if (e) return e;
+    bool any_key = false;
+    for (int b = b0; b < b0 + cn; ++b) any_key |= jobs[b].key != nullptr;
+    if (any_key) dispatch_logn<LKsCore>(c->logn, c, (const KsJob*)ks.jobs, cn, lmax, ks.dcoef, ks.u, ks.rc, s);
+    dispatch_logn<LDrop>(c->logn, c, (int)MODE_P, epi, (const KsJob*)ks.jobs, cn, lmax, (const u64*)ks.u,
+                         (const u64*)ks.rc, s);
   }
-};
+  return check_launch(c, "batched rotation");
+}
+
+}  // namespace
 
 // =============================================================================
 // Public entry points
@@ -562,8 +587,12 @@ int he_ctx_create(const he_params* p, he_ctx** out) {
   c->logn = logn;
   c->big_l = p->n_q;
   c->moduli = mods;
-  hipGetDevice(&c->device);
-  for (int i = 0; i <= p->n_q; ++i) c->mods.m[i] = make_modconst(mods[i], p->n);
+  (void)hipGetDevice(&c->device);
+  for (int i = 0; i <= p->n_q; ++i) {
+    c->mods.m[i] = make_modconst(mods[i], p->n);
+    if (c->mods.m[i].narrow) c->has_narrow = true;
+    else c->has_wide = true;
+  }
   const size_t n = p->n;
   std::vector<u64> tw(mods.size() * 4 * n);
   for (size_t i = 0; i < mods.size(); ++i) {
@@ -574,28 +603,25 @@ int he_ctx_create(const he_params* p, he_ctx** out) {
   for (size_t i = 0; i < mods.size(); ++i)
     if (is_narrow(mods[i]))
       for (size_t k = 0; k < 4 * n; ++k) tw32[i * 4 * n + k] = (u32)tw[i * 4 * n + k];
-  if (hipMalloc((void**)&c->d_tw, tw.size() * 8) != hipSuccess ||
-      hipMemcpy(c->d_tw, tw.data(), tw.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMalloc((void**)&c->d_tw32, tw32.size() * 4) != hipSuccess ||
-      hipMemcpy(c->d_tw32, tw32.data(), tw32.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
-    hipFree(c->d_tw);
-    hipFree(c->d_tw32);
-    delete c;
-    return HE_EDEVICE;
-  }
-  for (int level = 1; level <= c->big_l; ++level) {
-    TargetList& nt = c->narrow_t[level];
-    TargetList& wt = c->wide_t[level];
-    nt.n = wt.n = 0;
-    for (int t = 0; t <= level; ++t) {
-      const int mi = t < level ? t : c->big_l;
-      if (c->mods.m[mi].narrow) nt.t[nt.n++] = t;
-      else wt.t[wt.n++] = t;
+  // inverse table: inv[div][t] = m_div^-1 mod q_t for divisors 0..L (L = P)
+  std::vector<u64> inv(2 * HE_MAXM * HE_MAXM, 0);
+  for (int dv = 0; dv <= p->n_q; ++dv)
+    for (int t = 0; t < p->n_q; ++t) {
+      if (t == dv) continue;
+      const u64 v = inv_mod(mods[dv] % mods[t], mods[t]);
+      inv[dv * HE_MAXM + t] = v;
+      inv[HE_MAXM * HE_MAXM + dv * HE_MAXM + t] = shoup_companion(v, mods[t]);
     }
-  }
-  if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) != hipSuccess) {
+  const bool ok = hipMalloc((void**)&c->d_tw, tw.size() * 8) == hipSuccess &&
+                  hipMemcpy(c->d_tw, tw.data(), tw.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMalloc((void**)&c->d_tw32, tw32.size() * 4) == hipSuccess &&
+                  hipMemcpy(c->d_tw32, tw32.data(), tw32.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMalloc((void**)&c->d_inv, inv.size() * 8) == hipSuccess &&
+                  hipMemcpy(c->d_inv, inv.data(), inv.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
+                  hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess &&
+                  hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
     he_ctx_destroy(c);
     return HE_EDEVICE;
   }
@@ -605,23 +631,20 @@ int he_ctx_create(const he_params* p, he_ctx** out) {
 
 int he_ctx_destroy(he_ctx* c) {
   if (!c) return HE_EINVAL;
-  hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();
   for (auto& pr : c->prof_events) c->prof_pool.insert(c->prof_pool.end(), {pr.first, pr.second});
-  for (hipEvent_t e : c->prof_pool) hipEventDestroy(e);
-  for (auto& kv : c->keys) hipFree(kv.second);
-  hipFree(c->d_tw);
-  hipFree(c->d_tw32);
-  hipFree(c->ws);
-  if (c->side) hipStreamDestroy(c->side);
-  if (c->fork_ev) hipEventDestroy(c->fork_ev);
-  if (c->join_ev) hipEventDestroy(c->join_ev);
-  auto it = g_stage.find(c);
-  if (it != g_stage.end()) {
-    for (int k = 0; k < 2; ++k) {
-      if (it->second.host[k]) hipHostFree(it->second.host[k]);
-      if (it->second.ev[k]) hipEventDestroy(it->second.ev[k]);
-    }
-    g_stage.erase(it);
+  for (hipEvent_t e : c->prof_pool) (void)hipEventDestroy(e);
+  for (auto& kv : c->keys) (void)hipFree(kv.second);
+  (void)hipFree(c->d_tw);
+  (void)hipFree(c->d_tw32);
+  (void)hipFree(c->d_inv);
+  (void)hipFree(c->ws);
+  if (c->side) (void)hipStreamDestroy(c->side);
+  if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
+  if (c->join_ev) (void)hipEventDestroy(c->join_ev);
+  for (auto& st : c->stage) {
+    if (st.host) (void)hipHostFree(st.host);
+    if (st.ev) (void)hipEventDestroy(st.ev);
   }
   delete c;
   return HE_OK;
@@ -630,11 +653,12 @@ int he_ctx_destroy(he_ctx* c) {
 int he_ctx_reserve(he_ctx* c, size_t bytes) {
   if (!c) return HE_EINVAL;
   if (bytes <= c->ws_bytes) return HE_OK;
-  hipDeviceSynchronize();
-  hipFree(c->ws);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(c->ws);
   c->ws = nullptr;
   c->ws_bytes = 0;
-  if (hipMalloc((void**)&c->ws, bytes) != hipSuccess) return fail(c, HE_ENOMEM, "workspace allocation of %zu bytes failed", bytes);
+  if (hipMalloc((void**)&c->ws, bytes) != hipSuccess)
+    return fail(c, HE_ENOMEM, "workspace allocation of %zu bytes failed", bytes);
   c->ws_bytes = bytes;
   return HE_OK;
 }
@@ -642,7 +666,7 @@ int he_ctx_reserve(he_ctx* c, size_t bytes) {
 size_t he_ctx_workspace_need(const he_ctx* c, int count, int level) {
   if (!c || count < 1 || level < 1) return 0;
   // accumulators (2 level), a second batch of that size (layer intermediates),
-  // key switch temporaries (3 level + 4) and staging tables, in limbs of N.
+  // key switch temporaries (3 level + 4) and tables, in limbs of N.
   const size_t per = (size_t)(4 * level) + (3 * (size_t)level + 4) + 2;
   return (size_t)count * per * c->n * 8 + ((size_t)16 << 20);
 }
@@ -670,7 +694,9 @@ int he_intt(he_ctx* c, uint64_t* d, int n_polys, int n_limbs, int first_mod, voi
 }
 
 int he_add(he_ctx* c, uint64_t* out, const uint64_t* a, const uint64_t* b, int count, int level, void* stream) {
-  if (!c || !out || !a || !b || count < 1 || count > 65535 || !level_ok(c, level)) return fail(c, HE_EINVAL, "he_add: bad arguments");
+  if (!c || !out || !a || !b || count < 1 || count > 65535 || !level_ok(c, level))
+    return fail(c, HE_EINVAL, "he_add: bad arguments");
+  Prof pr(c, "add", S(stream));
   k_add<<<dim3(c->n / 256, level, count), 256, 0, S(stream)>>>(out, a, b, level, c->n, c->mods);
   return check_launch(c, "he_add");
 }
@@ -691,7 +717,8 @@ int he_hma_plain(he_ctx* c, uint64_t* acc, const uint64_t* cts, int k, const uin
     if (e) return e;
     d_gal = g;
   }
-  dispatch_logn<LHmaPerm>(c->logn, c, acc, cts, k, pts, pt_stride, pt_limbs, d_gal, 1u, level, accumulate, 1, S(stream));
+  dispatch_logn<LHmaPerm>(c->logn, c, acc, cts, k, pts, pt_stride, pt_limbs, d_gal, 1u, level, accumulate, 1,
+                          S(stream));
   return check_launch(c, "he_hma_plain");
 }
 
@@ -735,7 +762,7 @@ int he_keygen_switch(he_ctx* c, int32_t galois, const uint64_t* d_s, const uint6
   if (it != c->keys.end()) {
     key = it->second;
   } else if (hipMalloc((void**)&key, (size_t)L * 2 * (L + 1) * n * 8) != hipSuccess) {
-    hipFree(ehat);
+    (void)hipFree(ehat);
     return fail(c, HE_ENOMEM, "key allocation failed");
   }
   ConstTable pm{};
@@ -745,10 +772,10 @@ int he_keygen_switch(he_ctx* c, int32_t galois, const uint64_t* d_s, const uint6
   }
   dispatch_logn<LKeygen>(c->logn, c, key, d_s, d_a, (const u64*)ehat, (u32)galois, pm, s);
   int e = check_launch(c, "keygen");
-  hipStreamSynchronize(s);
-  hipFree(ehat);
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(ehat);
   if (e) {
-    if (it == c->keys.end()) hipFree(key);
+    if (it == c->keys.end()) (void)hipFree(key);
     return e;
   }
   c->keys[galois] = key;
@@ -759,8 +786,8 @@ int he_has_key(const he_ctx* c, int32_t galois) { return c && c->keys.count(galo
 
 int he_drop_keys(he_ctx* c) {
   if (!c) return HE_EINVAL;
-  hipDeviceSynchronize();
-  for (auto& kv : c->keys) hipFree(kv.second);
+  (void)hipDeviceSynchronize();
+  for (auto& kv : c->keys) (void)hipFree(kv.second);
   c->keys.clear();
   return HE_OK;
 }
@@ -774,7 +801,8 @@ int he_from_signed(he_ctx* c, uint64_t* d_out, const int64_t* d_coeffs, int n_li
 
 int he_encrypt_sk(he_ctx* c, uint64_t* d_ct, const uint64_t* d_pt, const uint64_t* d_a, const int64_t* d_e,
                   const uint64_t* d_s, int level, void* stream) {
-  if (!c || !d_ct || !d_pt || !d_a || !d_e || !d_s || !level_ok(c, level)) return fail(c, HE_EINVAL, "he_encrypt_sk: bad arguments");
+  if (!c || !d_ct || !d_pt || !d_a || !d_e || !d_s || !level_ok(c, level))
+    return fail(c, HE_EINVAL, "he_encrypt_sk: bad arguments");
   Arena ar(c);
   u64* ehat = ar.take<u64>((size_t)level * c->n);
   if (!ehat) return fail(c, HE_ENOMEM, "workspace too small");
@@ -818,45 +846,157 @@ int he_rotsum(he_ctx* c, uint64_t* d_cts, int count, int level, int r_steps, voi
   return HE_OK;
 }
 
+int he_batch_rotate(he_ctx* c, uint64_t* const* h_outs, const uint64_t* const* h_ins, const int32_t* h_levels,
+                    const int32_t* h_steps, int count, int accumulate, void* stream) {
+  if (!c || !h_outs || !h_ins || !h_levels || !h_steps || count < 1)
+    return fail(c, HE_EINVAL, "he_batch_rotate: null argument");
+  std::vector<KsJob> jobs(count);
+  for (int b = 0; b < count; ++b) {
+    const int level = h_levels[b];
+    if (!level_ok(c, level) || !h_outs[b] || !h_ins[b]) return fail(c, HE_EINVAL, "he_batch_rotate: bad item %d", b);
+    const u32 g = galois_of(h_steps[b], c->n);
+    const u64* key = nullptr;
+    if (g != 1) {
+      auto it = c->keys.find((int)g);
+      if (it == c->keys.end()) return fail(c, HE_ENOKEY, "he_batch_rotate: no key for step %d", h_steps[b]);
+      key = it->second;
+    }
+    jobs[b] = KsJob{h_ins[b] + (size_t)level * c->n, h_ins[b], h_outs[b], key, g, galois_of(-h_steps[b], c->n),
+                    level, 0};
+  }
+  Arena ar(c);
+  return rotate_jobs(c, jobs, accumulate ? EPI_ROTSUM : EPI_ROT, ar, S(stream));
+}
+
+int he_batch_rescale(he_ctx* c, uint64_t* const* h_outs, const uint64_t* const* h_ins, const int32_t* h_levels,
+                     int count, void* stream) {
+  if (!c || !h_outs || !h_ins || !h_levels || count < 1) return fail(c, HE_EINVAL, "he_batch_rescale: null argument");
+  std::vector<KsJob> jobs(count);
+  int lmax = 2;
+  for (int b = 0; b < count; ++b) {
+    const int level = h_levels[b];
+    if (level < 2 || level > c->big_l || !h_outs[b] || !h_ins[b] || h_outs[b] == h_ins[b])
+      return fail(c, HE_EINVAL, "he_batch_rescale: bad item %d", b);
+    jobs[b] = KsJob{h_ins[b], h_ins[b], h_outs[b], nullptr, 1u, 1u, level, 0};
+    lmax = std::max(lmax, level);
+  }
+  const int n = c->n;
+  hipStream_t s = S(stream);
+  Arena ar(c);
+  const int chunk = (int)std::min<size_t>({(size_t)count, ar.left() / 8 / (2 * (size_t)n + 64), (size_t)32000});
+  if (chunk < 1) return fail(c, HE_ENOMEM, "workspace too small for rescale");
+  KsJob* d_jobs = ar.take<KsJob>(chunk);
+  u64* rc = ar.take<u64>((size_t)chunk * 2 * n);
+  if (!d_jobs || !rc) return fail(c, HE_ENOMEM, "workspace too small for rescale");
+  for (int b0 = 0; b0 < count; b0 += chunk) {
+    const int cn = std::min(chunk, count - b0);
+    int e = upload(c, d_jobs, jobs.data() + b0, (size_t)cn * sizeof(KsJob), s);
+    if (e) return e;
+    dispatch_logn<LIntt1>(c->logn, c, (const KsJob*)d_jobs, cn, lmax, rc, s);
+    dispatch_logn<LDrop>(c->logn, c, (int)MODE_LAST, (int)EPI_STORE, (const KsJob*)d_jobs, cn, lmax,
+                         (const u64*)nullptr, (const u64*)rc, s);
+  }
+  return check_launch(c, "he_batch_rescale");
+}
+
+int he_batch_mul_plain(he_ctx* c, uint64_t* const* h_outs, const uint64_t* const* h_cts, const uint64_t* const* h_pts,
+                       const int32_t* h_levels, int count, void* stream) {
+  if (!c || !h_outs || !h_cts || !h_pts || !h_levels || count < 1 || count > 65535)
+    return fail(c, HE_EINVAL, "he_batch_mul_plain: bad arguments");
+  std::vector<KsJob> jobs(count);
+  int lmax = 1;
+  for (int b = 0; b < count; ++b) {
+    if (!level_ok(c, h_levels[b]) || !h_outs[b] || !h_cts[b] || !h_pts[b])
+      return fail(c, HE_EINVAL, "he_batch_mul_plain: bad item %d", b);
+    jobs[b] = KsJob{h_cts[b], h_pts[b], h_outs[b], nullptr, 1u, 1u, h_levels[b], 0};
+    lmax = std::max(lmax, h_levels[b]);
+  }
+  hipStream_t s = S(stream);
+  Arena ar(c);
+  KsJob* d_jobs = ar.take<KsJob>(count);
+  if (!d_jobs) return fail(c, HE_ENOMEM, "workspace too small");
+  int e = upload(c, d_jobs, jobs.data(), (size_t)count * sizeof(KsJob), s);
+  if (e) return e;
+  Prof pr(c, "batch_mul_plain", s);
+  k_batch_mul_plain<<<dim3(c->n / 256, lmax, count), 256, 0, s>>>(d_jobs, c->n, c->mods);
+  return check_launch(c, "he_batch_mul_plain");
+}
+
+int he_combine_cp_dp(he_ctx* c, const uint64_t* d_in, int o_c, int level, int spatial, int per_dense,
+                     uint64_t* d_out, void* stream) {
+  if (!c || !d_in || !d_out || o_c < 1 || spatial < 1 || per_dense < 1 || !level_ok(c, level) ||
+      (long long)per_dense * spatial > c->n / 2)
+    return fail(c, HE_EINVAL, "he_combine_cp_dp: bad arguments");
+  const int n = c->n;
+  const size_t cstride = (size_t)2 * level * n;
+  hipStream_t s = S(stream);
+  Arena ar(c);
+  u64* rot = ar.take<u64>((size_t)o_c * cstride);
+  if (!rot) return fail(c, HE_ENOMEM, "workspace too small for combine");
+  std::vector<KsJob> jobs(o_c);
+  int64_t n_rot = 0;
+  for (int o = 0; o < o_c; ++o) {
+    const int step = -(o % per_dense) * spatial;
+    const u32 g = galois_of(step, n);
+    const u64* key = nullptr;
+    if (g != 1) {
+      auto it = c->keys.find((int)g);
+      if (it == c->keys.end()) return fail(c, HE_ENOKEY, "he_combine_cp_dp: no key for step %d", step);
+      key = it->second;
+      ++n_rot;
+    }
+    const u64* in = d_in + (size_t)o * cstride;
+    jobs[o] = KsJob{in + (size_t)level * n, in, rot + (size_t)o * cstride, key, g, galois_of(-step, n), level, 0};
+  }
+  int e = rotate_jobs(c, jobs, EPI_ROT, ar, s);
+  if (e) return e;
+  const int n_dense = (o_c + per_dense - 1) / per_dense;
+  {
+    Prof pr(c, "block_sum", s);
+    k_block_sum<<<dim3(n / 256, level, n_dense), 256, 0, s>>>(d_out, rot, o_c, per_dense, level, n, c->mods);
+  }
+  c->counts = he_counts{};
+  c->counts.rot = n_rot;
+  c->counts.addcc = o_c - n_dense;
+  return check_launch(c, "he_combine_cp_dp");
+}
+
 int he_rotate_hoisted(he_ctx* c, const uint64_t* d_in, int level, const int32_t* h_steps, int m, uint64_t* d_outs,
                       void* stream) {
   if (!c || !d_in || !h_steps || !d_outs || m < 1 || m > 32000 || !level_ok(c, level))
     return fail(c, HE_EINVAL, "he_rotate_hoisted: bad arguments");
   const int n = c->n;
-  std::vector<const u64*> kp(m);
-  std::vector<u32> gp(2 * m);
+  std::vector<KsJob> jobs(m);
   for (int r = 0; r < m; ++r) {
     const u32 g = galois_of(h_steps[r], n);
     auto it = c->keys.find((int)g);
     if (g == 1 || it == c->keys.end())
       return fail(c, g == 1 ? HE_EINVAL : HE_ENOKEY, "he_rotate_hoisted: no key for step %d", h_steps[r]);
-    kp[r] = it->second;
-    gp[2 * r] = g;
-    gp[2 * r + 1] = galois_of(-h_steps[r], n);
+    jobs[r] = KsJob{d_in + (size_t)level * n, d_in, d_outs + (size_t)r * 2 * level * n, it->second, g,
+                    galois_of(-h_steps[r], n), level, 0};
   }
+  hipStream_t s = S(stream);
   Arena ar(c);
+  KsJob* job1 = ar.take<KsJob>(1);
   u64* dcoef = ar.take<u64>((size_t)level * n);
   u64* dhat = ar.take<u64>((size_t)level * (level + 1) * n);
-  const u64** d_keys = ar.take<const u64*>(m);
-  u32* d_gp = ar.take<u32>(2 * m);
+  KsJob* d_jobs = ar.take<KsJob>(m);
   const size_t per = (size_t)2 * (level + 1) * n + 2 * (size_t)n;
-  int chunk = (int)std::min<size_t>((size_t)m, (ar.left() / 8) / (per + 64));
-  if (!dcoef || !dhat || !d_keys || !d_gp || chunk < 1) return fail(c, HE_ENOMEM, "workspace too small for hoisted rotation");
+  const int chunk = (int)std::min<size_t>((size_t)m, ar.left() / 8 / (per + 64));
+  if (!job1 || !dcoef || !dhat || !d_jobs || chunk < 1)
+    return fail(c, HE_ENOMEM, "workspace too small for hoisted rotation");
   u64* u = ar.take<u64>((size_t)chunk * 2 * (level + 1) * n);
   u64* rc = ar.take<u64>((size_t)chunk * 2 * n);
-  hipStream_t s = S(stream);
-  // one staging copy: key pointers then Galois pairs (both tables are 8-byte aligned)
-  std::vector<char> blob(m * sizeof(u64*) + 2 * m * sizeof(u32));
-  std::memcpy(blob.data(), kp.data(), m * sizeof(u64*));
-  std::memcpy(blob.data() + m * sizeof(u64*), gp.data(), 2 * m * sizeof(u32));
-  // d_keys and d_gp were taken back to back; copy each part to its place
-  int e = upload(c, (void*)d_keys, kp.data(), m * sizeof(u64*), s);
-  if (!e) e = upload(c, d_gp, gp.data(), 2 * m * sizeof(u32), s);
+  // the digits of c1 itself: a job with no permutation
+  KsJob j1 = jobs[0];
+  j1.g = j1.ginv = 1;
+  int e = upload(c, job1, &j1, sizeof(KsJob), s);
+  if (!e) e = upload(c, d_jobs, jobs.data(), (size_t)m * sizeof(KsJob), s);
   if (e) return e;
+  dispatch_logn<LHoistUp>(c->logn, c, (const KsJob*)job1, d_in + (size_t)level * n, level, dcoef, dhat, s);
   for (int r0 = 0; r0 < m; r0 += chunk) {
     const int cm = std::min(chunk, m - r0);
-    dispatch_logn<LHoisted>(c->logn, c, d_in, level, cm, (const u64* const*)(d_keys + r0), (const u32*)(d_gp + 2 * r0),
-                            dcoef, dhat, u, rc, d_outs + (size_t)r0 * 2 * level * n, s);
+    dispatch_logn<LHoisted>(c->logn, c, (const KsJob*)(d_jobs + r0), cm, level, (const u64*)dhat, u, rc, s);
   }
   return check_launch(c, "he_rotate_hoisted");
 }
@@ -901,7 +1041,8 @@ int he_conv_convpack(he_ctx* c, const uint64_t* d_in, int k, int level, const do
 int ffconv_layer(he_ctx* c, const uint64_t* d_in, int level, const he_conv_desc* desc, const uint64_t* d_w1_filt,
                  const uint64_t* d_mask, const double* h_w2, int o_c2, int k_bits, int square, uint64_t* d_out,
                  void* stream) {
-  if (!c || !d_in || !desc || !d_w1_filt || !d_mask || !h_w2 || !d_out) return fail(c, HE_EINVAL, "ffconv_layer: null argument");
+  if (!c || !d_in || !desc || !d_w1_filt || !d_mask || !h_w2 || !d_out)
+    return fail(c, HE_EINVAL, "ffconv_layer: null argument");
   const int need = square ? 4 : 3;
   if (level < need || level > c->big_l) return fail(c, HE_ELEVEL, "ffconv_layer needs level >= %d (got %d)", need, level);
   if (o_c2 < 1 || k_bits < 0 || k_bits > 40) return fail(c, HE_EINVAL, "ffconv_layer: bad W2 shape or k_bits");
@@ -926,7 +1067,8 @@ int ffconv_layer(he_ctx* c, const uint64_t* d_in, int level, const he_conv_desc*
   if (e) return e;
   // 2. DP->CP gather: G_c = sum_p y_{c,p} * sigma_{5^-p}(E)
   const u32 g5inv = galois_of(-1, n);  // 5^-1 in the group of odd residues mod 2N
-  dispatch_logn<LHmaPerm>(c->logn, c, g, (const u64*)y, spatial, d_mask, 0, l1, (const int32_t*)nullptr, g5inv, l1, 0, r, s);
+  dispatch_logn<LHmaPerm>(c->logn, c, g, (const u64*)y, spatial, d_mask, 0, l1, (const int32_t*)nullptr, g5inv, l1, 0,
+                          r, s);
   if ((e = check_launch(c, "gather"))) return e;
   // 3. 1x1 ConvPack with exact integer weights round(W2 * 2^k)
   std::vector<int64_t> w((size_t)r * o_c2);
@@ -940,7 +1082,7 @@ int ffconv_layer(he_ctx* c, const uint64_t* d_in, int level, const he_conv_desc*
     if (!e) e = square_batch(c, sq, zr, o_c2, l2, ar, s);
     if (!e) e = rescale_batch(c, d_out, sq, o_c2, l2, ar, s);
   }
-  c->counts.mulpc += (int64_t)r * spatial;      // gather masks
+  c->counts.mulpc += (int64_t)r * spatial;  // gather masks
   c->counts.addcc += (int64_t)r * (spatial - 1) + (int64_t)o_c2 * (r - 1);
   c->counts.scalar_mul += (int64_t)r * o_c2;
   c->counts.rescale += o_c2 * (square ? 2 : 1);

@@ -120,6 +120,8 @@ ModConst make_modconst(u64 q, int n) {
   m.narrow = is_narrow(q) ? 1u : 0u;
   m.n_inv = inv_mod((u64)n % q, q);
   m.n_inv_sh = shoup_companion(m.n_inv, q);
+  m.r64 = (u64)(((u128)1 << 64) % q);
+  m.r64_sh = shoup_companion(m.r64, q);
   return m;
 }
 

@@ -139,10 +139,8 @@ k_ntt(u64* data, int n_limbs, int first_mod, Mods mods, Tables tb) {
 }
 
 // ---------------------------------------------------------------------------
-// Key switch, step 1: coefficient-domain digits of sigma_g(c1).
-// blockIdx.x = digit j (< level), blockIdx.y = ciphertext b.
-// c1 points at limb 0 of component 1 of ciphertext 0; cstride = elements
-// between ciphertexts.  dcoef = [count][level][N].
+// Inverse transform of one limb into the coefficient domain (scaled by N^-1),
+// optionally through the Galois permutation on the way into LDS.
 template <int LOGN, bool NARROW>
 __device__ __forceinline__ void digits_body(u64* lds, const u64* src, u32 ginv, u64* out, int j, const ModConst& m,
                                             const Tables& tb) {
@@ -151,47 +149,72 @@ __device__ __forceinline__ void digits_body(u64* lds, const u64* src, u32 ginv, 
   store_limb<LOGN, NARROW>(out, lds, m, true);
 }
 
+// ---------------------------------------------------------------------------
+// Batched key switching and rescaling over per-ciphertext job descriptors.
+//
+// One job per ciphertext: the polynomial to switch (`d`, NTT domain,
+// [level][N]), the ciphertext whose c0 the epilogue uses (`c`), the output,
+// the switching key (nullptr: identity job, the epilogue copies `c` to
+// `out`), the Galois element applied before switching and its inverse, and
+// the job's level.  Jobs of one launch may have different levels, keys and
+// Galois elements (ragged batches, several layers or requests at once);
+// workspace rows are laid out with the launch's largest level Lmax:
+//   dcoef [count][Lmax][N]       coefficient-domain digits
+//   u     [count][2][Lmax+1][N]  inner products, the P limb at index `level`
+//   rc    [count][2][N]          coefficient-domain last limb (ModDown/rescale)
+struct KsJob {
+  const u64* d;    // polynomial to switch / ciphertext to rescale
+  const u64* c;    // EPI_ROT*: source ciphertext (c0 at c); EPI_RELIN: (d0, d1)
+  u64* out;        // output ciphertext
+  const u64* key;  // [big_l][2][big_l+1][N]; nullptr = identity
+  u32 g, ginv;     // Galois element (1 = none) and its inverse mod 2N
+  int level;
+  int pad_;
+};
+
+// Key switch, step 1: coefficient-domain digits of sigma_g(d).
+// grid (Lmax, count): blockIdx.x = digit j.
 template <int LOGN>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
-k_ks_digits(const u64* __restrict__ c1, size_t cstride, u32 ginv, u64* __restrict__ dcoef, int level,
-            Mods mods, Tables tb) {
+k_ks_digits(const KsJob* __restrict__ jobs, u64* __restrict__ dcoef, int lmax, Mods mods, Tables tb) {
   constexpr int N = 1 << LOGN;
   __shared__ u64 lds[NttGeom<LOGN>::LDS];
   const int j = blockIdx.x;
   const size_t b = blockIdx.y;
+  const KsJob jb = jobs[b];
+  if (jb.key == nullptr || j >= jb.level) return;
   const ModConst m = mods.m[j];
-  const u64* src = c1 + b * cstride + (size_t)j * N;
-  u64* out = dcoef + (b * level + j) * N;
-  if (m.narrow) digits_body<LOGN, true>(lds, src, ginv, out, j, m, tb);
-  else digits_body<LOGN, false>(lds, src, ginv, out, j, m, tb);
+  const u64* src = jb.d + (size_t)j * N;
+  u64* out = dcoef + (b * lmax + j) * N;
+  if (m.narrow) digits_body<LOGN, true>(lds, src, jb.ginv, out, j, m, tb);
+  else digits_body<LOGN, false>(lds, src, jb.ginv, out, j, m, tb);
 }
 
 // Key switch, step 2: ModUp + inner product for one target modulus t in
-// [0, level]: t < level is q_t, t == level is P (modulus index big_l);
-// blockIdx.y = ciphertext b.
-// key = [big_l][2][big_l+1][N]; u = [count][2][level+1][N].
+// [0, level]: t < level is q_t, t == level is P (modulus index big_l).
+// Accumulates sum_j NTT(lift(digit_j) mod m_t) * key[j][.][m_t] in registers.
 template <int LOGN, bool NARROW>
-__device__ __forceinline__ void modup_ip_body(u64* lds, const u64* __restrict__ dcoef, const u64* __restrict__ c1,
-                                              size_t cstride, u32 ginv, const u64* __restrict__ key,
-                                              u64* __restrict__ u, int level, int big_l, int t, const Mods& mods,
+__device__ __forceinline__ void modup_ip_body(u64* lds, const u64* __restrict__ dcoef, const KsJob& jb, size_t b,
+                                              u64* __restrict__ u, int lmax, int big_l, int t, const Mods& mods,
                                               const Tables& tb) {
   typedef word_t<NARROW> W;
   constexpr int N = 1 << LOGN;
   constexpr int T = NttGeom<LOGN>::T;
-  const size_t b = blockIdx.y;
+  const int level = jb.level;
   const int mi = (t < level) ? t : big_l;
   const ModConst m = mods.m[mi];
+  const u64* key = jb.key;
   W acc0[16], acc1[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0;
   for (int j = 0; j < level; ++j) {
     if (j == t) {
       // the digit reduced mod its own prime is the (permuted) input limb itself
-      load_limb_perm<LOGN, NARROW>(lds, c1 + b * cstride + (size_t)j * N, ginv);
+      load_limb_perm<LOGN, NARROW>(lds, jb.d + (size_t)j * N, jb.ginv);
       __syncthreads();
     } else {
       const u64 qj = mods.m[j].q;
-      const u64* d = dcoef + (b * level + j) * N;
+      const u64* d = dcoef + (b * lmax + j) * N;
       const int tid = opaque_tid();
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
@@ -216,8 +239,8 @@ __device__ __forceinline__ void modup_ip_body(u64* lds, const u64* __restrict__ 
     }
     __syncthreads();
   }
-  u64* u0 = u + ((b * 2 + 0) * (level + 1) + t) * N;
-  u64* u1 = u + ((b * 2 + 1) * (level + 1) + t) * N;
+  u64* u0 = u + ((b * 2 + 0) * (lmax + 1) + t) * N;
+  u64* u1 = u + ((b * 2 + 1) * (lmax + 1) + t) * N;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int i = (int)threadIdx.x + r * T;
@@ -226,34 +249,52 @@ __device__ __forceinline__ void modup_ip_body(u64* lds, const u64* __restrict__ 
   }
 }
 
-// Target moduli of one width class: blockIdx.x indexes tl.t[] (values in
-// [0, level], level meaning P).  Each class is its own kernel so the 32-bit
-// body gets a register allocation of its own.
-struct TargetList {
-  int n;
-  int t[HE_MAXM];
-};
-
+// grid (Lmax + 1, count): blockIdx.x < Lmax is ciphertext prime blockIdx.x,
+// blockIdx.x == Lmax is P.  Each width class is its own kernel (so the 32-bit
+// body gets a register allocation of its own); blocks of the other class,
+// and primes above a job's level, exit at once.
 template <int LOGN, bool NARROW>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
-k_ks_modup_ip(const u64* __restrict__ dcoef, const u64* __restrict__ c1, size_t cstride, u32 ginv,
-              const u64* __restrict__ key, u64* __restrict__ u, int level, int big_l, TargetList tl, Mods mods,
-              Tables tb) {
+k_ks_modup_ip(const KsJob* __restrict__ jobs, const u64* __restrict__ dcoef, u64* __restrict__ u, int lmax,
+              int big_l, Mods mods, Tables tb) {
   __shared__ u64 lds[NttGeom<LOGN>::LDS];
-  modup_ip_body<LOGN, NARROW>(lds, dcoef, c1, cstride, ginv, key, u, level, big_l, tl.t[blockIdx.x], mods, tb);
+  const size_t b = blockIdx.y;
+  const KsJob jb = jobs[b];
+  if (jb.key == nullptr) return;
+  int t = blockIdx.x;
+  if (t == lmax) t = jb.level;
+  else if (t >= jb.level) return;
+  const int mi = (t < jb.level) ? t : big_l;
+  if ((mods.m[mi].narrow != 0) != NARROW) return;
+  modup_ip_body<LOGN, NARROW>(lds, dcoef, jb, b, u, lmax, big_l, t, mods, tb);
 }
 
-// INTT of one limb of each polynomial: blockIdx.x = polynomial p.
-// src + p * pstride + limb * N  ->  rcoef[p] (coefficient domain).
-template <int LOGN>
+// INTT of the limb that is divided out: for polynomial p = 2 b + comp,
+//   MODE_P:    the P limb of u (ModDown after a key switch);
+//   MODE_LAST: the last limb of the ciphertext jobs[b].d (rescale).
+enum { MODE_P = 0, MODE_LAST = 1 };
+
+template <int LOGN, int MODE>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
-k_intt_last(const u64* __restrict__ src, size_t pstride, int limb, int mi, u64* __restrict__ rcoef, Mods mods,
-            Tables tb) {
+k_intt_last(const KsJob* __restrict__ jobs, const u64* __restrict__ u, int lmax, int big_l, u64* __restrict__ rcoef,
+            Mods mods, Tables tb) {
   constexpr int N = 1 << LOGN;
   __shared__ u64 lds[NttGeom<LOGN>::LDS];
   const size_t p = blockIdx.x;
+  const size_t b = p >> 1;
+  const int comp = (int)(p & 1);
+  const KsJob jb = jobs[b];
+  const u64* s;
+  int mi;
+  if (MODE == MODE_P) {
+    if (jb.key == nullptr) return;
+    s = u + ((b * 2 + comp) * (lmax + 1) + jb.level) * N;
+    mi = big_l;
+  } else {
+    s = jb.d + ((size_t)comp * jb.level + jb.level - 1) * N;
+    mi = jb.level - 1;
+  }
   const ModConst m = mods.m[mi];
-  const u64* s = src + p * pstride + (size_t)limb * N;
   u64* out = rcoef + p * N;
   if (m.narrow) digits_body<LOGN, true>(lds, s, 1u, out, mi, m, tb);
   else digits_body<LOGN, false>(lds, s, 1u, out, mi, m, tb);
@@ -261,69 +302,79 @@ k_intt_last(const u64* __restrict__ src, size_t pstride, int limb, int mi, u64* 
 
 enum { EPI_STORE = 0, EPI_ROT = 1, EPI_ROTSUM = 2, EPI_RELIN = 3 };
 
-struct EpiArgs {
-  u64* out;              // output base (component 0, limb 0 of ciphertext 0)
-  size_t out_pstride;    // elements between output polynomials (2 per ciphertext)
-  const u64* c0;         // EPI_ROT: source ciphertexts (component 0 used); EPI_RELIN: d0/d1 base
-  size_t c0_pstride;     // elements between source polynomials
-  u32 g;                 // Galois element (EPI_ROT / EPI_ROTSUM)
-  u32 ginv;              // its inverse mod 2N
-  const u32* gpairs;     // optional per-ciphertext (g, g^-1) pairs (hoisted rotations)
-};
-
-// Drop the last limb: for polynomial p (blockIdx.y) and kept prime t
-// (blockIdx.x): val = (src[p][t] - NTT(lift(rcoef[p]))) * div^-1 mod q_t,
-// followed by the epilogue.  The divisor modulus is mods.m[div_mi].
-template <int LOGN, int EPI, bool NARROW>
-__device__ __forceinline__ void drop_last_body(u64* lds, const u64* __restrict__ src, size_t pstride,
-                                               const u64* __restrict__ rcoef, int div_mi,
-                                               const ConstTable& inv, EpiArgs ea, const Mods& mods,
-                                               const Tables& tb) {
+// Drop the last limb, for polynomial p = 2 b + comp (blockIdx.y) and kept
+// prime t (blockIdx.x):  val = (src_t - NTT(lift(rc_p))) * div^-1 mod q_t,
+// with (src, div) = (u limb t, P) in MODE_P and (d limb t, q_{level-1}) in
+// MODE_LAST, followed by the epilogue into jobs[b].out:
+//   EPI_STORE   out = val
+//   EPI_ROT     out = (sigma_g(c0) + val, val)        (identity job: out = c)
+//   EPI_ROTSUM  out = c + (sigma_g(c0) + val, val)    (identity job: out = 2c)
+//   EPI_RELIN   out = (d0 + val, d1 + val), (d0, d1) = c
+// inv_tab[div][t] holds q_div^-1 mod q_t (div = big_l for P) and its Shoup
+// companion at inv_tab[HE_MAXM * HE_MAXM + ...].
+template <int LOGN, int MODE, int EPI, bool NARROW>
+__device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t b, int comp, int t,
+                                               const u64* __restrict__ u, int lmax, int big_l,
+                                               const u64* __restrict__ rcoef, const u64* __restrict__ inv_tab,
+                                               const Mods& mods, const Tables& tb) {
   typedef word_t<NARROW> W;
   constexpr int N = 1 << LOGN;
   constexpr int T = NttGeom<LOGN>::T;
-  const int t = blockIdx.x;
-  const size_t p = blockIdx.y;
+  const int level = jb.level;
+  const int keep = (MODE == MODE_P) ? level : level - 1;
+  const int div_mi = (MODE == MODE_P) ? big_l : level - 1;
   const ModConst m = mods.m[t];
+  u64* o = jb.out + ((size_t)comp * keep + t) * N;
+  if (MODE == MODE_P && jb.key == nullptr) {  // identity job
+    const u64* cs = jb.c + ((size_t)comp * level + t) * N;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = (int)threadIdx.x + r * T;
+      u64 x = cs[i];
+      if constexpr (EPI == EPI_ROTSUM) x = addm<NARROW>(x, x, m.q);
+      o[i] = x;
+    }
+    return;
+  }
   const u64 qd = mods.m[div_mi].q;
-  const u64* rc = rcoef + p * N;
+  const u64* rc = rcoef + (b * 2 + comp) * N;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int i = (int)threadIdx.x + r * T;
     lds_put<NARROW>(lds, i, lift_centered(rc[i], qd, m));
   }
   fwd_lds<LOGN, NARROW>(lds, tb, t, m.q);
-  const u64* s = src + p * pstride + (size_t)t * N;
+  const u64* s = (MODE == MODE_P) ? u + ((b * 2 + comp) * (lmax + 1) + t) * N
+                                  : jb.d + ((size_t)comp * level + t) * N;
+  const u64 iv = inv_tab[div_mi * HE_MAXM + t];
+  const u64 ivs = inv_tab[HE_MAXM * HE_MAXM + div_mi * HE_MAXM + t];
   W val[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int i = (int)threadIdx.x + r * T;
-    val[r] = (W)shoupm<NARROW>(subm<NARROW>(s[i], lds_get<NARROW>(lds, i), m.q), inv.v[t], inv.sh[t], m.q);
+    val[r] = (W)shoupm<NARROW>(subm<NARROW>(s[i], lds_get<NARROW>(lds, i), m.q), iv, ivs, m.q);
   }
-  const int comp = (int)(p & 1);
-  u64* o = ea.out + p * ea.out_pstride + (size_t)t * N;
   if constexpr (EPI == EPI_STORE) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) o[(int)threadIdx.x + r * T] = val[r];
   } else if constexpr (EPI == EPI_RELIN) {
-    const u64* d = ea.c0 + p * ea.c0_pstride + (size_t)t * N;
+    const u64* dd = jb.c + ((size_t)comp * level + t) * N;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int i = (int)threadIdx.x + r * T;
-      o[i] = addm<NARROW>(d[i], val[r], m.q);
+      o[i] = addm<NARROW>(dd[i], val[r], m.q);
     }
   } else {  // EPI_ROT / EPI_ROTSUM
+    const u64* cs = jb.c + ((size_t)comp * level + t) * N;
     if (comp == 0) {
-      const u32 ginv = ea.gpairs ? ea.gpairs[2 * (p >> 1) + 1] : ea.ginv;
       __syncthreads();  // everyone is done reading the lifted limb
-      const u64* c0 = ea.c0 + p * ea.c0_pstride + (size_t)t * N;
       W own[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int idx = (int)threadIdx.x + r * T;
-        const u64 v = c0[idx];
+        const u64 v = cs[idx];
         own[r] = (W)v;
-        lds_put<NARROW>(lds, galois_src<LOGN>(idx, ginv), v);
+        lds_put<NARROW>(lds, galois_src<LOGN>(idx, jb.ginv), v);
       }
       __syncthreads();
 #pragma unroll
@@ -338,7 +389,7 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const u64* __restrict__
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int i = (int)threadIdx.x + r * T;
-          o[i] = addm<NARROW>(o[i], val[r], m.q);
+          o[i] = addm<NARROW>(cs[i], val[r], m.q);
         }
       } else {
 #pragma unroll
@@ -348,15 +399,23 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const u64* __restrict__
   }
 }
 
-template <int LOGN, int EPI>
+// grid (Lmax, 2 count)
+template <int LOGN, int MODE, int EPI>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
-k_drop_last(const u64* __restrict__ src, size_t pstride, const u64* __restrict__ rcoef, int div_mi,
-            ConstTable inv, EpiArgs ea, Mods mods, Tables tb) {
+k_drop_last(const KsJob* __restrict__ jobs, const u64* __restrict__ u, int lmax, int big_l,
+            const u64* __restrict__ rcoef, const u64* __restrict__ inv_tab, Mods mods, Tables tb) {
   __shared__ u64 lds[NttGeom<LOGN>::LDS];
-  if (mods.m[blockIdx.x].narrow)
-    drop_last_body<LOGN, EPI, true>(lds, src, pstride, rcoef, div_mi, inv, ea, mods, tb);
+  const int t = blockIdx.x;
+  const size_t p = blockIdx.y;
+  const size_t b = p >> 1;
+  const int comp = (int)(p & 1);
+  const KsJob jb = jobs[b];
+  const int keep = (MODE == MODE_P) ? jb.level : jb.level - 1;
+  if (t >= keep) return;
+  if (mods.m[t].narrow)
+    drop_last_body<LOGN, MODE, EPI, true>(lds, jb, b, comp, t, u, lmax, big_l, rcoef, inv_tab, mods, tb);
   else
-    drop_last_body<LOGN, EPI, false>(lds, src, pstride, rcoef, div_mi, inv, ea, mods, tb);
+    drop_last_body<LOGN, MODE, EPI, false>(lds, jb, b, comp, t, u, lmax, big_l, rcoef, inv_tab, mods, tb);
 }
 
 // ---------------------------------------------------------------------------
@@ -405,27 +464,95 @@ k_modup_store(const u64* __restrict__ dcoef, const u64* __restrict__ c1, u64* __
 
 // Inner product of the shared lifted digits, permuted per rotation, with
 // that rotation's key: u[r][c][t][i] = sum_j dhat[j][t][src_{g_r}(i)] *
-// key_r[j][c][m_t][i].  grid (N / 256, level + 1, m).
+// key_r[j][c][m_t][i], with (key_r, g_r) from jobs[r].  The products are
+// summed at full width (64-bit for narrow primes, 128-bit otherwise) and
+// reduced once.  grid (N / 256, level + 1, m).
 template <int LOGN>
-__global__ void k_ip_perm(const u64* __restrict__ dhat, const u64* const* __restrict__ keys,
-                          const u32* __restrict__ gpairs, u64* __restrict__ u, int level, int big_l, Mods mods) {
+__global__ void k_ip_perm(const u64* __restrict__ dhat, const KsJob* __restrict__ jobs, u64* __restrict__ u,
+                          int level, int big_l, Mods mods) {
   constexpr int N = 1 << LOGN;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int t = blockIdx.y;
   const size_t r = blockIdx.z;
   const int mi = (t < level) ? t : big_l;
   const ModConst m = mods.m[mi];
-  const u32 g = gpairs[2 * r];
-  const int src = galois_src<LOGN>(i, g);
-  const u64* key = keys[r];
-  u64 s0 = 0, s1 = 0;
-  for (int j = 0; j < level; ++j) {
-    const u64 dv = dhat[((size_t)j * (level + 1) + t) * N + src];
-    s0 = add_mod(s0, mul_mod(dv, key[(((size_t)j * 2 + 0) * (big_l + 1) + mi) * N + i], m), m.q);
-    s1 = add_mod(s1, mul_mod(dv, key[(((size_t)j * 2 + 1) * (big_l + 1) + mi) * N + i], m), m.q);
+  const KsJob jb = jobs[r];
+  const int src = galois_src<LOGN>(i, jb.g);
+  const u64* key = jb.key;
+  u64 s0, s1;
+  if (m.narrow) {  // products < 2^60, at most 15 digits: one 64-bit sum each
+    u64 a0 = 0, a1 = 0;
+    for (int j = 0; j < level; ++j) {
+      const u64 dv = dhat[((size_t)j * (level + 1) + t) * N + src];
+      a0 += (u64)(u32)dv * (u32)key[(((size_t)j * 2 + 0) * (big_l + 1) + mi) * N + i];
+      a1 += (u64)(u32)dv * (u32)key[(((size_t)j * 2 + 1) * (big_l + 1) + mi) * N + i];
+    }
+    s0 = reduce64(a0, m);
+    s1 = reduce64(a1, m);
+  } else {  // 128-bit sums of the full products, reduced once
+    Acc128 a0{0, 0}, a1{0, 0};
+    for (int j = 0; j < level; ++j) {
+      const u64 dv = dhat[((size_t)j * (level + 1) + t) * N + src];
+      mac128(a0, dv, key[(((size_t)j * 2 + 0) * (big_l + 1) + mi) * N + i]);
+      mac128(a1, dv, key[(((size_t)j * 2 + 1) * (big_l + 1) + mi) * N + i]);
+    }
+    s0 = reduce128(a0, m);
+    s1 = reduce128(a1, m);
   }
   u[((r * 2 + 0) * (level + 1) + t) * N + i] = s0;
   u[((r * 2 + 1) * (level + 1) + t) * N + i] = s1;
+}
+
+// Job table of a uniform batch: ciphertext b at base + b * stride.
+__global__ void k_make_jobs(KsJob* jobs, int count, const u64* d_base, size_t d_stride, const u64* c_base,
+                            size_t c_stride, u64* out_base, size_t out_stride, const u64* key, u32 g, u32 ginv,
+                            int level) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= count) return;
+  KsJob jb;
+  jb.d = d_base + (size_t)b * d_stride;
+  jb.c = c_base + (size_t)b * c_stride;
+  jb.out = out_base + (size_t)b * out_stride;
+  jb.key = key;
+  jb.g = g;
+  jb.ginv = ginv;
+  jb.level = level;
+  jb.pad_ = 0;
+  jobs[b] = jb;
+}
+
+// CP -> DP combine, summing step: out[m] = sum_{o in block m} rot[o], block
+// m = [m B, min(O_c, (m+1) B)); grid (N / 256, level, n_dense).
+__global__ void k_block_sum(u64* __restrict__ out, const u64* __restrict__ rot, int o_c, int per_dense, int level,
+                            int n, Mods mods) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y;
+  const int mblk = blockIdx.z;
+  const u64 q = mods.m[t].q;
+  const int o_end = min(o_c, (mblk + 1) * per_dense);
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    u64 acc = 0;
+    for (int o = mblk * per_dense; o < o_end; ++o) acc = add_mod(acc, rot[(((size_t)o * 2 + c) * level + t) * n + i], q);
+    out[(((size_t)mblk * 2 + c) * level + t) * n + i] = acc;
+  }
+}
+
+// Batched MulPC over a ragged batch: out_b = ct_b * pt_b (slot-wise), every
+// item with its own level; jobs give (d = ct, c = pt, out).  grid
+// (N / 256, Lmax, count); limbs above an item's level exit.
+__global__ void k_batch_mul_plain(const KsJob* __restrict__ jobs, int n, Mods mods) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y;
+  const KsJob jb = jobs[blockIdx.z];
+  if (t >= jb.level) return;
+  const ModConst m = mods.m[t];
+  const u64 pv = jb.c[(size_t)t * n + i];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const size_t off = ((size_t)c * jb.level + t) * n + i;
+    jb.out[off] = mul_mod(jb.d[off], pv, m);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -29,6 +29,8 @@ struct ModConst {
   u32 narrow;  // q < 2^30
   u64 n_inv;   // N^-1 mod q
   u64 n_inv_sh;
+  u64 r64;     // 2^64 mod q (folds the high word of a 128-bit sum)
+  u64 r64_sh;
 };
 
 __host__ __device__ inline u64 mulhi64(u64 a, u64 b) {
@@ -136,6 +138,25 @@ __host__ __device__ inline u64 mul_mod_t(u64 a, u64 b, const ModConst& m) {
     if (r >= q) r -= q;
     return r;
   }
+}
+
+// Lazily accumulated sums of products, reduced once.
+//  narrow: sum of up to 16 products (< 2^60 each) in one u64;
+//  wide:   sum of up to 15 products (< 2^124 each) in a 128-bit (hi, lo) pair.
+struct Acc128 {
+  u64 lo, hi;
+};
+__host__ __device__ inline void mac128(Acc128& a, u64 x, u64 y) {
+  const u64 plo = x * y, phi = mulhi64(x, y);
+  const u64 lo = a.lo + plo;
+  a.hi += phi + (lo < plo ? 1 : 0);
+  a.lo = lo;
+}
+// (hi * 2^64 + lo) mod q
+__host__ __device__ inline u64 reduce128(const Acc128& a, const ModConst& m) {
+  const u64 h = reduce64(a.hi, m);
+  const u64 l = reduce64(a.lo, m);
+  return add_mod(mul_shoup(h, m.r64, m.r64_sh, m.q, m.narrow), l, m.q);
 }
 
 }  // namespace he

@@ -263,6 +263,43 @@ class HEContext:
         count = ct.data.numel() // (2 * level * self.n)
         self._check(self.lib.he_rotsum(self.h, _ptr(ct.data), count, level, int(r_steps), _stream()), "he_rotsum")
 
+    # ---- batched (ragged) calls --------------------------------------------------
+    @staticmethod
+    def _ptrs(tensors):
+        arr = (ctypes.c_void_p * len(tensors))(*[t.data_ptr() for t in tensors])
+        for t in tensors:
+            if not (t.is_cuda and t.is_contiguous()):
+                raise HEError("batched calls take contiguous device tensors")
+        return arr
+
+    def batch_rotate(self, outs, ins, steps, accumulate: bool = False):
+        """outs[b] = Rot(ins[b], steps[b]) (or ins[b] + Rot(...)), every item its own level."""
+        k = len(ins)
+        levels = (ctypes.c_int32 * k)(*[t.shape[-2] for t in ins])
+        st = (ctypes.c_int32 * k)(*[int(x) for x in steps])
+        self._check(self.lib.he_batch_rotate(self.h, self._ptrs(outs), self._ptrs(ins), levels, st, k,
+                                             int(accumulate), _stream()), "he_batch_rotate")
+
+    def batch_rescale(self, outs, ins):
+        k = len(ins)
+        levels = (ctypes.c_int32 * k)(*[t.shape[-2] for t in ins])
+        self._check(self.lib.he_batch_rescale(self.h, self._ptrs(outs), self._ptrs(ins), levels, k, _stream()),
+                    "he_batch_rescale")
+
+    def batch_mul_plain(self, outs, cts, pts):
+        k = len(cts)
+        levels = (ctypes.c_int32 * k)(*[t.shape[-2] for t in cts])
+        self._check(self.lib.he_batch_mul_plain(self.h, self._ptrs(outs), self._ptrs(cts), self._ptrs(pts), levels,
+                                                k, _stream()), "he_batch_mul_plain")
+
+    def combine_cp_dp(self, z: Ct, spatial: int, per_dense: int) -> Ct:
+        o_c, _, level, n = z.data.shape
+        n_dense = -(-o_c // per_dense)
+        out = torch.empty((n_dense, 2, level, n), dtype=torch.int64, device="cuda")
+        self._check(self.lib.he_combine_cp_dp(self.h, _ptr(z.data), o_c, level, spatial, per_dense, _ptr(out),
+                                              _stream()), "he_combine_cp_dp")
+        return Ct(out, z.scale)
+
     def square(self, ct: Ct) -> Ct:
         level = ct.level
         count = ct.data.numel() // (2 * level * self.n)

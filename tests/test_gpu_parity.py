@@ -253,3 +253,55 @@ def test_ffconv_layer_bit_exact_small():
     for o in range(3):
         v = cl.decrypt(got.data[o], got.scale, geom.spatial)
         assert np.abs(v - ref[:, :, o].reshape(-1)).max() < 1e-3
+
+
+def test_batch_rotate_ragged_levels():
+    """One launch set over items at levels 4, 2, 3, 4, 1 with different steps (0 copies)."""
+    steps = [1, 3, -7, 0, 100]
+    levels = [4, 2, 3, 4, 1]
+    p, octx, gctx, cl = _small_setup(rotations=[k for k in steps if k])
+    cts = [_enc_batch(octx, p, 1, level=lv, index0=20 + i)[0] for i, lv in enumerate(levels)]
+    ins = [_dev(c) for c in cts]
+    outs = [torch.empty_like(t) for t in ins]
+    gctx.batch_rotate(outs, ins, steps)
+
+    def rot(c, k):
+        return c if k == 0 else S.rotate(p, octx, S.Ciphertext(c, p.scale), k).c
+
+    for c, o, k in zip(cts, outs, steps):
+        assert np.array_equal(_host(o), rot(c, k)), k
+    gctx.batch_rotate(ins, ins, steps, accumulate=True)  # in place: t + Rot(t, k)
+    for c, t, k in zip(cts, ins, steps):
+        want = S.add(p, S.Ciphertext(c, p.scale), S.Ciphertext(rot(c, k), p.scale)).c
+        assert np.array_equal(_host(t), want), k
+
+
+def test_batch_rescale_and_mul_plain_ragged():
+    p, octx, gctx, cl = _small_setup()
+    levels = [4, 2, 3, 2]
+    cts = [_enc_batch(octx, p, 1, level=lv, index0=40 + i)[0] for i, lv in enumerate(levels)]
+    pts = [E.encode(synth.message(W, p.slots, index=60 + i), p, lv, 2.0**20) for i, lv in enumerate(levels)]
+    ins = [_dev(c) for c in cts]
+    prods = [torch.empty_like(t) for t in ins]
+    gctx.batch_mul_plain(prods, ins, [_dev(x) for x in pts])
+    for c, pt, o in zip(cts, pts, prods):
+        assert np.array_equal(_host(o), S.mul_plain(p, S.Ciphertext(c, 1.0), pt, 1.0).c)
+    outs = [torch.empty((2, lv - 1, p.n), dtype=torch.int64, device="cuda") for lv in levels]
+    gctx.batch_rescale(outs, ins)
+    for c, o in zip(cts, outs):
+        assert np.array_equal(_host(o), S.rescale(p, S.Ciphertext(c, p.scale)).c)
+
+
+def test_combine_cp_dp_bit_exact():
+    """CP -> DP combine of 5 channel ciphertexts (16 values each) into one dense ciphertext."""
+    offsets = C.combine_offsets(5, 16, 8)
+    p, octx, gctx, cl = _small_setup(rotations=offsets)
+    vals = synth.message(W, 80, index=7)
+    chans = np.stack([Wk.encrypt_slots(octx, np.concatenate([vals[16 * o:16 * o + 16], np.zeros(p.slots - 16)]),
+                                       3, p.scale, W, 70 + o).c for o in range(5)])
+    want, cnt = C.combine_cp_to_dp(p, octx, S.Ciphertext(chans, p.scale), 16, 8)
+    got = gctx.combine_cp_dp(_he().Ct(_dev(chans), p.scale), 16, 8)
+    assert np.array_equal(_host(got.data), want.c)
+    assert gctx.last_counts()["rot"] == cnt.rot == 4
+    dense = cl.decrypt(got.data[0], p.scale, 80)
+    assert np.abs(dense - vals).max() < 1e-4
