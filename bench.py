@@ -38,37 +38,50 @@ K_BITS = 12
 HBM_PEAK_GBS = 8000.0
 # 32-bit VALU lane operations per second: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
-DOMINANT = "ks_modup_ip"
+DOMINANT = "ks_modup_stage"
 
-# Operation-cost model (32-bit VALU lane ops) used for the ALU roofline of the
-# key-switch kernels; see DESIGN.md ("Rooflines").
+# Algorithmic operation counts (VALU lane ops; an FP64 multiply, FMA or add
+# counts as one, as it issues at the 32-bit rate) of the key-switch work per
+# width class: narrow = 30-bit primes in 32-bit words (Harvey butterflies,
+# 64-bit lazy inner-product sums), f64 = primes below 2^42 as exact integers
+# in doubles, wide = 64-bit words.
 COST = {
-    "bfly_narrow": 12, "bfly_wide": 34,   # CT butterfly with a Shoup twiddle product
-    "mac_narrow": 11, "mac_wide": 40,     # Barrett product + modular add
-    "lift_narrow": 8, "lift_wide": 12,    # centred lift of one coefficient
+    "bfly": {"n32": 9, "f64": 9, "u64": 34},   # one butterfly with its twiddle product
+    "mac": {"n32": 1, "f64": 8, "u64": 40},    # one key product accumulated
+    "lift": {"n32": 3, "f64": 3, "u64": 12},   # centred lift of one digit coefficient
+    "fin": {"n32": 10, "f64": 6, "u64": 0},    # final reduction of one output coefficient
 }
 
 
-def modup_ip_ops(count: int, level: int, n: int, narrow) -> float:
-    """Algorithmic VALU ops of one k_ks_modup_ip<30-bit targets> launch over `count` ciphertexts."""
+def width_class(q: int) -> str:
+    return "n32" if q < (1 << 30) else ("f64" if q < (1 << 42) else "u64")
+
+
+def modup_ip_ops(count: int, level: int, n: int, moduli, pg: int) -> float:
+    """Algorithmic VALU ops of the ModUp + inner-product stage (every target
+    prime of every width class, P split over pg digit groups) over `count`
+    ciphertexts at `level`: per target, a lift and an NTT of each digit but
+    its own, one key product per digit and output polynomial, one final
+    reduction per output coefficient."""
     bfly = (n // 2) * int(math.log2(n))
     ops = 0.0
-    for t in range(level + 1):
-        nar = narrow[t] if t < level else narrow[-1]
-        if not nar:
-            continue  # the wide targets run in their own kernel (ks_modup_ip_wide)
-        n_ntt = level - 1 if t < level else level
-        ops += n_ntt * (bfly * COST["bfly_narrow" if nar else "bfly_wide"] +
-                        n * COST["lift_narrow" if nar else "lift_wide"])
-        ops += 2 * level * n * COST["mac_narrow" if nar else "mac_wide"]
+    for t in range(level):
+        c = width_class(moduli[t])
+        ops += (level - 1) * (bfly * COST["bfly"][c] + n * COST["lift"][c])
+        ops += 2 * n * (level * COST["mac"][c] + COST["fin"][c])
+    c = width_class(moduli[-1])
+    groups = -(-level // -(-level // pg))
+    ops += level * (bfly * COST["bfly"][c] + n * COST["lift"][c] + 2 * n * COST["mac"][c])
+    ops += groups * 2 * n * COST["fin"][c]
     return ops * count
 
 
 def modup_ip_bytes(count: int, level: int, n: int) -> float:
-    """Algorithmic HBM bytes of one k_ks_modup_ip launch over the `level`
-    ciphertext-prime targets: digits (+ own limb), outputs, and the key once."""
+    """Algorithmic HBM bytes of the ModUp + inner-product stage: each digit
+    (or own limb) read once per ciphertext, the level + 1 output rows of both
+    polynomials written, the key (2 level (level + 1) limbs) read once."""
     limb = 8 * n
-    return count * (level * level * limb + 2 * level * limb) + 2 * level * level * limb
+    return count * (level * limb + 2 * (level + 1) * limb) + 2 * level * (level + 1) * limb
 
 
 def setup(ctx, client, x, w1, w2):
@@ -195,6 +208,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=4)
     ap.add_argument("--cpu-sample", type=int, default=12, help="oracle dot products timed (0 = skip)")
     ap.add_argument("--no-hoisted", action="store_true", help="skip the N=16384 hoisted-rotation section")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 3 plain device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); "
@@ -203,6 +218,16 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_probe > 0:
+        nbytes = args.copy_probe << 20
+        src = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes, "copies": 3}))
+        return
 
     import synth
     from paper_2102_03494_amd import layers as Ly
@@ -263,18 +288,26 @@ def main():
     rot_pl = 720 * 12
     hma_ff = counts_ff["mulpc"] + counts_ff["scalar_mul"]
     level = len(Q_BITS)
-    narrow = [q < (1 << 31) for q in ctx.moduli]
+    pg = ctx.get_tuning("p_groups", level)
+    # the timed region also holds the 5 relinearisations of x^2 (level 2,
+    # 5 ciphertexts): count their ops with the 12 rotate-and-add steps
+    ops_layer = 12 * modup_ip_ops(288, level, N, ctx.moduli, pg) + \
+        modup_ip_ops(5, 2, N, ctx.moduli[:2] + ctx.moduli[-1:], ctx.get_tuning("p_groups", 2))
+    bytes_layer = 12 * modup_ip_bytes(288, level, N) + modup_ip_bytes(5, 2, N)
+    launches_layer = 13
     avg_ms = dom_ms / max(1, dom_launches)
-    per_launch_count = 288  # one rotate-and-add step of all W1 dot products per launch
-    ops = modup_ip_ops(per_launch_count, level, N, narrow)
+    ops = ops_layer / launches_layer
     achieved_ops = ops / (avg_ms * 1e-3)
     roofline = {
-        "kernel": "k_ks_modup_ip<13, true> (ModUp NTTs + key inner product into the four 30-bit primes, "
-                  "one rotate-and-add step of 288 ciphertexts at level 4)",
-        "bound": "alu", "achieved": achieved_ops / 1e12, "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s (32-bit VALU)",
-        "frac": achieved_ops / VALU_PEAK_OPS, "traffic": None,
-        "avg_launch_ms": avg_ms, "launches": dom_launches,
-        "hbm_gbs_algorithmic": modup_ip_bytes(per_launch_count, level, N) / (avg_ms * 1e-3) / 1e9,
+        "kernel": "ModUp + key inner product stage: k_ks_modup_ip<13, narrow> (the 30-bit targets) and "
+                  "k_ks_modup_ip<13, f64> (P, split over p_groups digit groups) running concurrently on two "
+                  "streams; per launch one rotate-and-add step of 288 ciphertexts at level 4 "
+                  "(plus one relinearisation launch per layer)",
+        "bound": "alu", "achieved": achieved_ops / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+        "unit": "Tops/s (VALU lane ops)", "frac": achieved_ops / VALU_PEAK_OPS, "traffic": None,
+        "avg_launch_ms": avg_ms, "launches": dom_launches, "p_groups": pg,
+        "algorithmic_ops_per_launch": ops,
+        "hbm_gbs_algorithmic": bytes_layer / launches_layer / (avg_ms * 1e-3) / 1e9,
     }
 
     hoisted = None

@@ -92,6 +92,16 @@ size_t he_ctx_workspace_need(const he_ctx *ctx, int count, int level);
 int he_ctx_moduli(const he_ctx *ctx, uint64_t *h_out);   /* n_q + 1 values */
 const char *he_last_error(const he_ctx *ctx);
 
+/* Schedule knobs of the key switch (Sec. III's hybrid key switching as built
+ * here; no effect on any result bit, only on speed).  knob "p_groups": the
+ * number of workgroups (1..min(level, 4)) that share the ModUp + inner
+ * product into the special prime P at key-switch level `level` (1..L);
+ * value 0 restores the built-in cost model.  he_ctx_set_tuning returns
+ * HE_EINVAL for an unknown knob or out-of-range level/value;
+ * he_ctx_get_tuning returns the value in effect (>= 1) or a negative code. */
+int he_ctx_set_tuning(he_ctx *ctx, const char *knob, int level, int value);
+int he_ctx_get_tuning(const he_ctx *ctx, const char *knob, int level);
+
 /* ---- ring transforms (the negacyclic NTT that sits inside every Rot and
  * Square) ---------------------------------------------------------------------
  * In place on d_polys = [n_polys][n_limbs][N]; limb t of each poly uses
@@ -274,11 +284,13 @@ int he_last_counts(const he_ctx *ctx, he_counts *out);
 
 /* ---- instrumentation (not part of the evaluated path) ---------------------
  * he_prof_select: from now on every launch of the kernel named `kernel`
- * ("ntt", "ks_digits", "ks_modup_ip" (30-bit targets), "ks_modup_ip_wide"
- * (wider targets, launched on a second stream), "intt_last", "drop_last", "dp_hma",
- * "hma_perm", "scalar_mac", "tensor_sq", "modup_store", "ip_perm", "add") is
- * bracketed by two HIP events recorded on the stream it is launched on; NULL
- * or "" stops recording.  he_prof_read waits for the recorded events and
+ * ("ntt", "ks_digits", "ks_modup_ip" (narrow targets), "ks_modup_ip_f64" and
+ * "ks_modup_ip_wide" (the other width classes, launched on a second stream
+ * when more than one class is present), "ks_modup_stage" (the ModUp kernels
+ * of all classes together, fork to join), "intt_last", "drop_last",
+ * "dp_hma", "hma_perm", "scalar_mac", "tensor_sq", "modup_store", "ip_perm",
+ * "add") is bracketed by two HIP events recorded on the stream it is launched
+ * on; NULL or "" stops recording.  he_prof_read waits for the recorded events and
  * returns the summed kernel time (ms) and the number of launches since the
  * last select or read, then clears them. */
 int he_prof_select(he_ctx *ctx, const char *kernel);

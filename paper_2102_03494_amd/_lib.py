@@ -50,6 +50,8 @@ SIGNATURES = {
     "he_ctx_workspace_need": (ctypes.c_size_t, [P, I, I]),
     "he_ctx_moduli": (I, [P, U64P]),
     "he_last_error": (ctypes.c_char_p, [P]),
+    "he_ctx_set_tuning": (I, [P, ctypes.c_char_p, I, I]),
+    "he_ctx_get_tuning": (I, [P, ctypes.c_char_p, I]),
     "he_ntt": (I, [P, P, I, I, I, P]),
     "he_intt": (I, [P, P, I, I, I, P]),
     "he_add": (I, [P, P, P, P, I, I, P]),

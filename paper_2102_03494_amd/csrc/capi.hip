@@ -33,11 +33,13 @@ struct he_ctx {
   int n = 0, logn = 0, big_l = 0;
   std::vector<u64> moduli;  // q_0..q_{L-1}, P
   Mods mods{};
-  bool has_narrow = false, has_wide = false;
+  bool has_cls[3] = {false, false, false};  // width classes among q_0..q_{L-1}, P
   u64* d_tw = nullptr;    // [L+1][4][N] 64-bit twiddles + Shoup companions
   u32* d_tw32 = nullptr;  // 32-bit copies for the narrow moduli
-  u64* d_inv = nullptr;   // [2][HE_MAXM][HE_MAXM]: m_div^-1 mod q_t and Shoup companions
-  Tables tb() const { return Tables{d_tw, d_tw32}; }
+  double* d_twf = nullptr;  // (w, w / q) as doubles for the f64 moduli
+  u64* d_inv = nullptr;   // [2][HE_MAXM][HE_MAXM]: m_div^-1 mod q_t and Shoup components
+  Tables tb() const { return Tables{d_tw, d_tw32, d_twf}; }
+  int pg_set[HE_MAXM + 1] = {};  // P groups per key-switch level (0 = cost model)
   char* ws = nullptr;
   size_t ws_bytes = 0;
   std::map<int, u64*> keys;  // Galois element (0 = relinearisation) -> [L][2][L+1][N]
@@ -48,7 +50,7 @@ struct he_ctx {
   std::string prof_kernel;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
   std::vector<hipEvent_t> prof_pool;
-  // second stream (default priority) for the wide-modulus share of a launch
+  // second stream (default priority) for the other width classes of a launch
   hipStream_t side = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   StageSlot stage[STAGE_SLOTS];
@@ -187,52 +189,62 @@ struct LNtt {
 };
 
 // Key switch of a job batch: digits -> ModUp + inner product -> INTT of P.
+// The ModUp kernel of each width class present runs on its own stream (the
+// caller's for the first, the side stream for the others), joined before the
+// P INTT.
 template <int LOGN>
 struct LKsCore {
-  static void run(he_ctx* c, const KsJob* jobs, int count, int lmax, u64* dcoef, u64* u, u64* rc, hipStream_t s) {
+  static void run(he_ctx* c, const KsJob* jobs, int count, int lmax, int pg, u64* dcoef, u64* u, u64* rc,
+                  hipStream_t s) {
     constexpr int T = NttGeom<LOGN>::T;
     {
       Prof pr(c, "ks_digits", s);
       k_ks_digits<LOGN><<<dim3(lmax, count), T, 0, s>>>(jobs, dcoef, lmax, c->mods, c->tb());
     }
-    const dim3 grid(lmax + 1, count);
-    if (c->has_narrow && c->has_wide) {
-      // narrow targets on the caller's stream, wide targets (e.g. P) on the
-      // side stream, joined before the ModDown
-      (void)hipEventRecord(c->fork_ev, s);
-      (void)hipStreamWaitEvent(c->side, c->fork_ev, 0);
-      {
-        Prof pw(c, "ks_modup_ip_wide", c->side);
-        k_ks_modup_ip<LOGN, false><<<grid, T, 0, c->side>>>(jobs, dcoef, u, lmax, c->big_l, c->mods, c->tb());
+    const dim3 grid(lmax + pg, count);
+    static const char* names[3] = {"ks_modup_ip", "ks_modup_ip_f64", "ks_modup_ip_wide"};
+    const bool forked = (int)c->has_cls[0] + (int)c->has_cls[1] + (int)c->has_cls[2] > 1;
+    {
+      Prof stage(c, "ks_modup_stage", s);  // wall time of all classes together
+      if (forked) {  // the side stream starts after the digits, not after the first ModUp kernel
+        (void)hipEventRecord(c->fork_ev, s);
+        (void)hipStreamWaitEvent(c->side, c->fork_ev, 0);
       }
-      {
-        Prof pn(c, "ks_modup_ip", s);
-        k_ks_modup_ip<LOGN, true><<<grid, T, 0, s>>>(jobs, dcoef, u, lmax, c->big_l, c->mods, c->tb());
+      bool first = true;
+      for (int cls = 0; cls < 3; ++cls) {
+        if (!c->has_cls[cls]) continue;
+        const hipStream_t st = first ? s : c->side;
+        first = false;
+        Prof pr(c, names[cls], st);
+        if (cls == CLS_N32)
+          k_ks_modup_ip<LOGN, CLS_N32><<<grid, T, 0, st>>>(jobs, dcoef, u, lmax, pg, c->big_l, c->mods, c->tb());
+        else if (cls == CLS_F64)
+          k_ks_modup_ip<LOGN, CLS_F64><<<grid, T, 0, st>>>(jobs, dcoef, u, lmax, pg, c->big_l, c->mods, c->tb());
+        else
+          k_ks_modup_ip<LOGN, CLS_U64><<<grid, T, 0, st>>>(jobs, dcoef, u, lmax, pg, c->big_l, c->mods, c->tb());
       }
-      (void)hipEventRecord(c->join_ev, c->side);
-      (void)hipStreamWaitEvent(s, c->join_ev, 0);
-    } else if (c->has_narrow) {
-      Prof pn(c, "ks_modup_ip", s);
-      k_ks_modup_ip<LOGN, true><<<grid, T, 0, s>>>(jobs, dcoef, u, lmax, c->big_l, c->mods, c->tb());
-    } else {
-      Prof pw(c, "ks_modup_ip_wide", s);
-      k_ks_modup_ip<LOGN, false><<<grid, T, 0, s>>>(jobs, dcoef, u, lmax, c->big_l, c->mods, c->tb());
+      if (forked) {
+        (void)hipEventRecord(c->join_ev, c->side);
+        (void)hipStreamWaitEvent(s, c->join_ev, 0);
+      }
     }
     Prof pr(c, "intt_last", s);
-    k_intt_last<LOGN, MODE_P><<<dim3(2 * count), T, 0, s>>>(jobs, u, lmax, c->big_l, rc, c->mods, c->tb());
+    k_intt_last<LOGN, MODE_P><<<dim3(2 * count), T, 0, s>>>(jobs, u, lmax, pg, c->big_l, rc, c->mods, c->tb());
   }
 };
 
+// ModDown (MODE_P, u with `urows` rows per polynomial) or rescale
+// (MODE_LAST) of a job batch with the given epilogue.
 template <int LOGN>
 struct LDrop {
-  static void run(he_ctx* c, int mode, int epi, const KsJob* jobs, int count, int lmax, const u64* u, const u64* rc,
-                  hipStream_t s) {
+  static void run(he_ctx* c, int mode, int epi, const KsJob* jobs, int count, int lmax, int urows, const u64* u,
+                  const u64* rc, hipStream_t s) {
     constexpr int T = NttGeom<LOGN>::T;
     const int keep = mode == MODE_P ? lmax : lmax - 1;
     const dim3 grid(keep, 2 * count);
     Prof pr(c, "drop_last", s);
 #define HE_DROP(MD, EP) \
-  k_drop_last<LOGN, MD, EP><<<grid, T, 0, s>>>(jobs, u, lmax, c->big_l, rc, c->d_inv, c->mods, c->tb())
+  k_drop_last<LOGN, MD, EP><<<grid, T, 0, s>>>(jobs, u, urows, c->big_l, rc, c->d_inv, c->mods, c->tb())
     if (mode == MODE_LAST) {
       HE_DROP(MODE_LAST, EPI_STORE);
     } else if (epi == EPI_ROT) {
@@ -252,8 +264,8 @@ template <int LOGN>
 struct LIntt1 {
   static void run(he_ctx* c, const KsJob* jobs, int count, int lmax, u64* rc, hipStream_t s) {
     Prof pr(c, "intt_last", s);
-    k_intt_last<LOGN, MODE_LAST><<<dim3(2 * count), NttGeom<LOGN>::T, 0, s>>>(jobs, nullptr, lmax, c->big_l, rc,
-                                                                              c->mods, c->tb());
+    k_intt_last<LOGN, MODE_LAST><<<dim3(2 * count), NttGeom<LOGN>::T, 0, s>>>(jobs, nullptr, lmax, 1, c->big_l,
+                                                                              rc, c->mods, c->tb());
   }
 };
 
@@ -308,34 +320,56 @@ struct LHoisted {
       Prof pr(c, "ip_perm", s);
       k_ip_perm<LOGN><<<dim3(N / 256, level + 1, m), 256, 0, s>>>(dhat, jobs, u, level, c->big_l, c->mods);
     }
-    {
+    {  // u rows per polynomial: level + 1, P at row level (one P group)
       Prof pr(c, "intt_last", s);
-      k_intt_last<LOGN, MODE_P><<<dim3(2 * m), T, 0, s>>>(jobs, u, level, c->big_l, rc, c->mods, c->tb());
+      k_intt_last<LOGN, MODE_P><<<dim3(2 * m), T, 0, s>>>(jobs, u, level, 1, c->big_l, rc, c->mods, c->tb());
     }
-    LDrop<LOGN>::run(c, MODE_P, EPI_ROT, jobs, m, level, u, rc, s);
+    LDrop<LOGN>::run(c, MODE_P, EPI_ROT, jobs, m, level, level + 1, u, rc, s);
   }
 };
 
 // ---- shared orchestration ----------------------------------------------------
 
-size_t ks_elems_per_job(int lmax, int n) { return (3 * (size_t)lmax + 4) * n; }
+constexpr int PG_MAX = 4;
+
+// Number of groups the P target's digits are split into at key-switch level
+// `level`: set per level through he_ctx_set_tuning, else from a cost model
+// that makes a P workgroup about as long as a ciphertext-prime workgroup
+// (relative transform cost per class: narrow 1, f64 1.3, wide 3).
+int p_groups(const he_ctx* c, int level) {
+  if (level < 2) return 1;
+  const int lim = std::min(level, PG_MAX);
+  if (c->pg_set[level] > 0) return std::min(c->pg_set[level], lim);
+  static const double cost[3] = {1.0, 1.3, 3.0};
+  double cq = 0;
+  for (int t = 0; t < level; ++t) cq += cost[c->mods.m[t].cls];
+  cq /= level;
+  const double p_block = level * cost[c->mods.m[c->big_l].cls];
+  const int pg = (int)std::lround(p_block / ((level - 1) * cq));
+  return std::max(1, std::min(pg, lim));
+}
+
+// Key-switch scratch per job: digits (lmax), u (2 (lmax + pg)), rc (2).
+size_t ks_elems_per_job(int lmax, int pg, int n) { return (3 * (size_t)lmax + 2 * (size_t)pg + 2) * n; }
 
 struct KsScratch {
   KsJob* jobs = nullptr;
   u64 *dcoef = nullptr, *u = nullptr, *rc = nullptr;
+  int pg = 1;
 };
 
-bool take_scratch(Arena& ar, int count, int lmax, int n, KsScratch& ks) {
+bool take_scratch(Arena& ar, int count, int lmax, int pg, int n, KsScratch& ks) {
+  ks.pg = pg;
   ks.jobs = ar.take<KsJob>(count);
   ks.dcoef = ar.take<u64>((size_t)count * lmax * n);
-  ks.u = ar.take<u64>((size_t)count * 2 * (lmax + 1) * n);
+  ks.u = ar.take<u64>((size_t)count * 2 * (lmax + pg) * n);
   ks.rc = ar.take<u64>((size_t)count * 2 * n);
   return ks.jobs && ks.dcoef && ks.u && ks.rc;
 }
 
 // Jobs that fit the arena with key-switch scratch at lmax (+ extra per job).
-int chunk_for(Arena& ar, int count, int lmax, int n, size_t extra_per_job_elems = 0) {
-  const size_t per = ks_elems_per_job(lmax, n) + extra_per_job_elems + 128;
+int chunk_for(Arena& ar, int count, int lmax, int pg, int n, size_t extra_per_job_elems = 0) {
+  const size_t per = ks_elems_per_job(lmax, pg, n) + extra_per_job_elems + 128;
   return (int)std::min<size_t>({(size_t)count, ar.left() / 8 / per, (size_t)32000});
 }
 
@@ -360,20 +394,21 @@ int rotate_batch(he_ctx* c, u64* out, const u64* in, int count, int level, int k
     key = it->second;
   }
   const u32 ginv = galois_of(-k, n);
-  const int chunk = chunk_for(ar, count, level, n);
+  const int pg = p_groups(c, level);
+  const int chunk = chunk_for(ar, count, level, pg, n);
   if (chunk < 1) return fail(c, HE_ENOMEM, "workspace too small for one key switch at level %d", level);
   Arena sub = ar;
   KsScratch ks;
-  if (!take_scratch(sub, chunk, level, n, ks)) return fail(c, HE_ENOMEM, "workspace too small");
+  if (!take_scratch(sub, chunk, level, pg, n, ks)) return fail(c, HE_ENOMEM, "workspace too small");
   const size_t cstride = (size_t)2 * level * n;
   for (int b0 = 0; b0 < count; b0 += chunk) {
     const int cn = std::min(chunk, count - b0);
     const u64* cin = in + (size_t)b0 * cstride;
     u64* cout = out + (size_t)b0 * cstride;
     make_jobs(c, ks.jobs, cn, cin + (size_t)level * n, cstride, cin, cstride, cout, cstride, key, g, ginv, level, s);
-    if (key) dispatch_logn<LKsCore>(c->logn, c, (const KsJob*)ks.jobs, cn, level, ks.dcoef, ks.u, ks.rc, s);
-    dispatch_logn<LDrop>(c->logn, c, (int)MODE_P, epi, (const KsJob*)ks.jobs, cn, level, (const u64*)ks.u,
-                         (const u64*)ks.rc, s);
+    if (key) dispatch_logn<LKsCore>(c->logn, c, (const KsJob*)ks.jobs, cn, level, pg, ks.dcoef, ks.u, ks.rc, s);
+    dispatch_logn<LDrop>(c->logn, c, (int)MODE_P, epi, (const KsJob*)ks.jobs, cn, level, level + pg,
+                         (const u64*)ks.u, (const u64*)ks.rc, s);
   }
   return check_launch(c, "rotate");
 }
@@ -393,7 +428,7 @@ int rescale_batch(he_ctx* c, u64* out, const u64* in, int count, int level, Aren
     make_jobs(c, jobs, cn, cin, (size_t)2 * level * n, cin, (size_t)2 * level * n, cout,
               (size_t)2 * (level - 1) * n, nullptr, 1u, 1u, level, s);
     dispatch_logn<LIntt1>(c->logn, c, (const KsJob*)jobs, cn, level, rc, s);
-    dispatch_logn<LDrop>(c->logn, c, (int)MODE_LAST, (int)EPI_STORE, (const KsJob*)jobs, cn, level,
+    dispatch_logn<LDrop>(c->logn, c, (int)MODE_LAST, (int)EPI_STORE, (const KsJob*)jobs, cn, level, 0,
                          (const u64*)nullptr, (const u64*)rc, s);
   }
   return check_launch(c, "rescale");
@@ -403,13 +438,14 @@ int square_batch(he_ctx* c, u64* out, const u64* in, int count, int level, Arena
   const int n = c->n;
   auto it = c->keys.find(0);
   if (it == c->keys.end()) return fail(c, HE_ENOKEY, "no relinearisation key");
-  const int chunk = chunk_for(ar, count, level, n, 3 * (size_t)level * n);
+  const int pg = p_groups(c, level);
+  const int chunk = chunk_for(ar, count, level, pg, n, 3 * (size_t)level * n);
   if (chunk < 1) return fail(c, HE_ENOMEM, "workspace too small for square");
   Arena sub = ar;
   u64* d01 = sub.take<u64>((size_t)chunk * 2 * level * n);
   u64* d2 = sub.take<u64>((size_t)chunk * level * n);
   KsScratch ks;
-  if (!d01 || !d2 || !take_scratch(sub, chunk, level, n, ks)) return fail(c, HE_ENOMEM, "workspace too small");
+  if (!d01 || !d2 || !take_scratch(sub, chunk, level, pg, n, ks)) return fail(c, HE_ENOMEM, "workspace too small");
   for (int b0 = 0; b0 < count; b0 += chunk) {
     const int cn = std::min(chunk, count - b0);
     const u64* cin = in + (size_t)b0 * 2 * level * n;
@@ -420,8 +456,8 @@ int square_batch(he_ctx* c, u64* out, const u64* in, int count, int level, Arena
     }
     make_jobs(c, ks.jobs, cn, d2, (size_t)level * n, d01, (size_t)2 * level * n, cout, (size_t)2 * level * n,
               it->second, 1u, 1u, level, s);
-    dispatch_logn<LKsCore>(c->logn, c, (const KsJob*)ks.jobs, cn, level, ks.dcoef, ks.u, ks.rc, s);
-    dispatch_logn<LDrop>(c->logn, c, (int)MODE_P, (int)EPI_RELIN, (const KsJob*)ks.jobs, cn, level,
+    dispatch_logn<LKsCore>(c->logn, c, (const KsJob*)ks.jobs, cn, level, pg, ks.dcoef, ks.u, ks.rc, s);
+    dispatch_logn<LDrop>(c->logn, c, (int)MODE_P, (int)EPI_RELIN, (const KsJob*)ks.jobs, cn, level, level + pg,
                          (const u64*)ks.u, (const u64*)ks.rc, s);
   }
   return check_launch(c, "square");
@@ -478,7 +514,8 @@ int densepack_run(he_ctx* c, const u64* d_in, int level, const he_conv_desc* des
     if (g != 1 && !c->keys.count((int)g)) return fail(c, HE_ENOKEY, "missing rotation key for step %d", 1 << j);
   }
   // per output: accumulator (2 level N) + key switch temporaries
-  const int chunk = std::min(chunk_for(ar, total, level, n, (size_t)2 * level * n + 2 * (size_t)n), 16000);
+  const int chunk =
+      std::min(chunk_for(ar, total, level, p_groups(c, level), n, (size_t)2 * level * n + 2 * (size_t)n), 16000);
   if (chunk < 1) return fail(c, HE_ENOMEM, "workspace too small for DensePack");
   for (int o0 = 0; o0 < total; o0 += chunk) {
     const int cn = std::min(chunk, total - o0);
@@ -542,20 +579,22 @@ int rotate_jobs(he_ctx* c, std::vector<KsJob>& jobs, int epi, Arena& ar, hipStre
   const int count = (int)jobs.size();
   int lmax = 1;
   for (auto& j : jobs) lmax = std::max(lmax, j.level);
-  const int chunk = chunk_for(ar, count, lmax, n);
+  const int pg = p_groups(c, lmax);
+  const int chunk = chunk_for(ar, count, lmax, pg, n);
   if (chunk < 1) return fail(c, HE_ENOMEM, "workspace too small for a batched rotation");
   Arena sub = ar;
   KsScratch ks;
-  if (!take_scratch(sub, chunk, lmax, n, ks)) return fail(c, HE_ENOMEM, "workspace too small");
+  if (!take_scratch(sub, chunk, lmax, pg, n, ks)) return fail(c, HE_ENOMEM, "workspace too small");
   for (int b0 = 0; b0 < count; b0 += chunk) {
     const int cn = std::min(chunk, count - b0);
     int e = upload(c, ks.jobs, jobs.data() + b0, (size_t)cn * sizeof(KsJob), s);
     if (e) return e;
     bool any_key = false;
     for (int b = b0; b < b0 + cn; ++b) any_key |= jobs[b].key != nullptr;
-    if (any_key) dispatch_logn<LKsCore>(c->logn, c, (const KsJob*)ks.jobs, cn, lmax, ks.dcoef, ks.u, ks.rc, s);
-    dispatch_logn<LDrop>(c->logn, c, (int)MODE_P, epi, (const KsJob*)ks.jobs, cn, lmax, (const u64*)ks.u,
-                         (const u64*)ks.rc, s);
+    if (any_key)
+      dispatch_logn<LKsCore>(c->logn, c, (const KsJob*)ks.jobs, cn, lmax, pg, ks.dcoef, ks.u, ks.rc, s);
+    dispatch_logn<LDrop>(c->logn, c, (int)MODE_P, epi, (const KsJob*)ks.jobs, cn, lmax, lmax + pg,
+                         (const u64*)ks.u, (const u64*)ks.rc, s);
   }
   return check_launch(c, "batched rotation");
 }
@@ -590,8 +629,7 @@ int he_ctx_create(const he_params* p, he_ctx** out) {
   (void)hipGetDevice(&c->device);
   for (int i = 0; i <= p->n_q; ++i) {
     c->mods.m[i] = make_modconst(mods[i], p->n);
-    if (c->mods.m[i].narrow) c->has_narrow = true;
-    else c->has_wide = true;
+    c->has_cls[c->mods.m[i].cls] = true;
   }
   const size_t n = p->n;
   std::vector<u64> tw(mods.size() * 4 * n);
@@ -600,9 +638,20 @@ int he_ctx_create(const he_params* p, he_ctx** out) {
     make_twiddles(mods[i], p->n, b, b + n, b + 2 * n, b + 3 * n);
   }
   std::vector<u32> tw32(tw.size(), 0);
-  for (size_t i = 0; i < mods.size(); ++i)
+  std::vector<double> twf(tw.size(), 0.0);
+  for (size_t i = 0; i < mods.size(); ++i) {
+    const u64* b = tw.data() + i * 4 * n;
     if (is_narrow(mods[i]))
-      for (size_t k = 0; k < 4 * n; ++k) tw32[i * 4 * n + k] = (u32)tw[i * 4 * n + k];
+      for (size_t k = 0; k < 4 * n; ++k) tw32[i * 4 * n + k] = (u32)b[k];
+    if (width_class(mods[i]) == CLS_F64)
+      for (size_t k = 0; k < n; ++k) {  // (w, w / q) for the forward and inverse tables
+        double* f = twf.data() + i * 4 * n;
+        f[k] = (double)b[k];
+        f[n + k] = (double)b[k] / (double)mods[i];
+        f[2 * n + k] = (double)b[2 * n + k];
+        f[3 * n + k] = (double)b[2 * n + k] / (double)mods[i];
+      }
+  }
   // inverse table: inv[div][t] = m_div^-1 mod q_t for divisors 0..L (L = P)
   std::vector<u64> inv(2 * HE_MAXM * HE_MAXM, 0);
   for (int dv = 0; dv <= p->n_q; ++dv)
@@ -616,6 +665,8 @@ int he_ctx_create(const he_params* p, he_ctx** out) {
                   hipMemcpy(c->d_tw, tw.data(), tw.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
                   hipMalloc((void**)&c->d_tw32, tw32.size() * 4) == hipSuccess &&
                   hipMemcpy(c->d_tw32, tw32.data(), tw32.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMalloc((void**)&c->d_twf, twf.size() * 8) == hipSuccess &&
+                  hipMemcpy(c->d_twf, twf.data(), twf.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
                   hipMalloc((void**)&c->d_inv, inv.size() * 8) == hipSuccess &&
                   hipMemcpy(c->d_inv, inv.data(), inv.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
                   hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess &&
@@ -637,6 +688,7 @@ int he_ctx_destroy(he_ctx* c) {
   for (auto& kv : c->keys) (void)hipFree(kv.second);
   (void)hipFree(c->d_tw);
   (void)hipFree(c->d_tw32);
+  (void)hipFree(c->d_twf);
   (void)hipFree(c->d_inv);
   (void)hipFree(c->ws);
   if (c->side) (void)hipStreamDestroy(c->side);
@@ -666,8 +718,9 @@ int he_ctx_reserve(he_ctx* c, size_t bytes) {
 size_t he_ctx_workspace_need(const he_ctx* c, int count, int level) {
   if (!c || count < 1 || level < 1) return 0;
   // accumulators (2 level), a second batch of that size (layer intermediates),
-  // key switch temporaries (3 level + 4) and tables, in limbs of N.
-  const size_t per = (size_t)(4 * level) + (3 * (size_t)level + 4) + 2;
+  // key switch temporaries (3 level + 2 pg + 2, pg <= PG_MAX) and tables, in
+  // limbs of N.
+  const size_t per = (size_t)(4 * level) + (3 * (size_t)level + 2 * PG_MAX + 2) + 2;
   return (size_t)count * per * c->n * 8 + ((size_t)16 << 20);
 }
 
@@ -678,6 +731,20 @@ int he_ctx_moduli(const he_ctx* c, uint64_t* h_out) {
 }
 
 const char* he_last_error(const he_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int he_ctx_set_tuning(he_ctx* c, const char* knob, int level, int value) {
+  if (!c || !knob) return HE_EINVAL;
+  if (std::strcmp(knob, "p_groups") != 0) return fail(c, HE_EINVAL, "he_ctx_set_tuning: unknown knob '%s'", knob);
+  if (level < 1 || level > c->big_l || value < 0 || value > std::min(level, PG_MAX))
+    return fail(c, HE_EINVAL, "he_ctx_set_tuning: p_groups %d out of range at level %d", value, level);
+  c->pg_set[level] = value;
+  return HE_OK;
+}
+
+int he_ctx_get_tuning(const he_ctx* c, const char* knob, int level) {
+  if (!c || !knob || std::strcmp(knob, "p_groups") != 0 || level < 1 || level > c->big_l) return HE_EINVAL;
+  return p_groups(c, level);
+}
 
 int he_ntt(he_ctx* c, uint64_t* d, int n_polys, int n_limbs, int first_mod, void* stream) {
   if (!c || !d || n_polys < 1 || n_limbs < 1 || n_polys > 65535 || first_mod < 0 || first_mod + n_limbs > c->big_l + 1)
@@ -893,7 +960,7 @@ int he_batch_rescale(he_ctx* c, uint64_t* const* h_outs, const uint64_t* const* 
     int e = upload(c, d_jobs, jobs.data() + b0, (size_t)cn * sizeof(KsJob), s);
     if (e) return e;
     dispatch_logn<LIntt1>(c->logn, c, (const KsJob*)d_jobs, cn, lmax, rc, s);
-    dispatch_logn<LDrop>(c->logn, c, (int)MODE_LAST, (int)EPI_STORE, (const KsJob*)d_jobs, cn, lmax,
+    dispatch_logn<LDrop>(c->logn, c, (int)MODE_LAST, (int)EPI_STORE, (const KsJob*)d_jobs, cn, lmax, 0,
                          (const u64*)nullptr, (const u64*)rc, s);
   }
   return check_launch(c, "he_batch_rescale");

@@ -122,6 +122,11 @@ ModConst make_modconst(u64 q, int n) {
   m.n_inv_sh = shoup_companion(m.n_inv, q);
   m.r64 = (u64)(((u128)1 << 64) % q);
   m.r64_sh = shoup_companion(m.r64, q);
+  m.cls = (u32)width_class(q);
+  m.pad_ = 0;
+  m.qd = (double)q;
+  m.qinv = 1.0 / (double)q;
+  m.n_inv_q = (double)m.n_inv / (double)q;
   return m;
 }
 

@@ -5,17 +5,19 @@
 // 8N-byte run and every kernel reads and writes whole limbs with unit-stride
 // (coalesced) accesses.  Kernels that need a transform hold one limb per
 // workgroup in LDS (ntt_lds.h); elementwise kernels use one thread per
-// coefficient.  The width class of each prime (narrow < 2^30, wide < 2^62) is
-// uniform per workgroup; each transform kernel branches once on it into a
-// body compiled for that class (32-bit words for narrow limbs).
+// coefficient.  The width class of each prime (modarith.h: narrow < 2^30,
+// f64 < 2^42, wide < 2^62) is uniform per workgroup; each transform kernel
+// branches once on it into a body compiled for that class (32-bit words for
+// narrow limbs, exact integers in doubles for f64 limbs).
 //
 // Key switching of a batch of ciphertexts (rotation or relinearisation) runs
 // as four kernels, each batched over every ciphertext of the call:
 //   k_ks_digits    INTT of each limb of sigma_g(c1)  -> coefficient digits
 //   k_ks_modup_ip  per target modulus: centred lift of each digit, NTT, and
 //                  the inner product with the key, accumulated in registers
-//                  (the lifted digits never go to memory)
-//   k_intt_last    INTT of the P limb of (u0, u1)
+//                  (the lifted digits never go to memory); the P target is
+//                  split over `pg` groups of digits, each its own workgroup
+//   k_intt_last    sum of the P partials, INTT of the P limb of (u0, u1)
 //   k_drop_last    per target prime: centred lift of that limb, NTT,
 //                  (u - lift) * P^-1, fused with the operation's epilogue
 //                  (rotation, rotate-and-add, relinearisation, or plain store)
@@ -38,21 +40,32 @@ struct ConstTable {  // one constant per modulus index with its Shoup companion
   u64 sh[HE_MAXM];
 };
 
-// Twiddle tables [n_mods][4][N] (fwd, fwd_shoup, inv, inv_shoup): 64-bit for
-// every modulus, 32-bit copies for the narrow ones.
+// Twiddle tables [n_mods][4][N] (fwd, fwd companion, inv, inv companion):
+// 64-bit with Shoup companions for every modulus, 32-bit copies for the
+// narrow ones, and doubles (w, w / q) for the f64 ones.
 struct Tables {
   const u64* tw64;
   const u32* tw32;
+  const double* twf;
 };
 
-template <int LOGN, bool NARROW>
-__device__ __forceinline__ Tw<NARROW> tw_of(const Tables& tb, int mi, int which) {
+template <int LOGN, int CLS>
+__device__ __forceinline__ Tw<CLS> tw_of(const Tables& tb, int mi, int which) {
   constexpr size_t N = (size_t)1 << LOGN;
-  if constexpr (NARROW)
-    return {tb.tw32 + ((size_t)mi * 4 + which) * N, tb.tw32 + ((size_t)mi * 4 + which + 1) * N};
-  else
-    return {tb.tw64 + ((size_t)mi * 4 + which) * N, tb.tw64 + ((size_t)mi * 4 + which + 1) * N};
+  const size_t o = ((size_t)mi * 4 + which) * N;
+  if constexpr (CLS == CLS_N32) return {tb.tw32 + o, tb.tw32 + o + N};
+  else if constexpr (CLS == CLS_F64) return {tb.twf + o, tb.twf + o + N};
+  else return {tb.tw64 + o, tb.tw64 + o + N};
 }
+
+// Expands BODY with the compile-time constant CLS set to the width class of
+// m (uniform per workgroup).
+#define HE_BY_CLASS(m, BODY)                          \
+  do {                                                \
+    if ((m).cls == CLS_N32) { constexpr int CLS = CLS_N32; BODY; } \
+    else if ((m).cls == CLS_F64) { constexpr int CLS = CLS_F64; BODY; } \
+    else { constexpr int CLS = CLS_U64; BODY; }      \
+  } while (0)
 
 // An opaque copy of the thread index (see ntt_lds.h): defined where it is
 // used so that address arithmetic is not hoisted out of enclosing loops.
@@ -62,14 +75,14 @@ __device__ __forceinline__ int opaque_tid() {
   return tid;
 }
 
-template <int LOGN, bool NARROW>
-__device__ __forceinline__ void fwd_lds(u64* lds, const Tables& tb, int mi, u64 q) {
-  ntt_fwd_lds<LOGN, NARROW>(lds, tw_of<LOGN, NARROW>(tb, mi, 0), (word_t<NARROW>)q, opaque_tid());
+template <int LOGN, int CLS>
+__device__ __forceinline__ void fwd_lds(u64* lds, const Tables& tb, int mi, const ModConst& m) {
+  ntt_fwd_lds<LOGN, CLS>(lds, tw_of<LOGN, CLS>(tb, mi, 0), mview<CLS>(m), opaque_tid());
 }
 
-template <int LOGN, bool NARROW>
-__device__ __forceinline__ void inv_lds(u64* lds, const Tables& tb, int mi, u64 q) {
-  ntt_inv_lds<LOGN, NARROW>(lds, tw_of<LOGN, NARROW>(tb, mi, 2), (word_t<NARROW>)q, opaque_tid());
+template <int LOGN, int CLS>
+__device__ __forceinline__ void inv_lds(u64* lds, const Tables& tb, int mi, const ModConst& m) {
+  ntt_inv_lds<LOGN, CLS>(lds, tw_of<LOGN, CLS>(tb, mi, 2), mview<CLS>(m), opaque_tid());
 }
 
 template <bool NARROW>
@@ -91,7 +104,7 @@ __device__ __forceinline__ u64 shoupm(u64 a, u64 w, u64 wsh, u64 q) {
 // Coalesced limb load into LDS, optionally through the Galois permutation
 // sigma_g: afterwards lds[i] = src[galois_src(i, g)].  ginv = g^-1 mod 2N
 // (the scatter position of source entry idx is galois_src(idx, ginv)).
-template <int LOGN, bool NARROW>
+template <int LOGN, int CLS>
 __device__ __forceinline__ void load_limb_perm(u64* lds, const u64* __restrict__ src, u32 ginv) {
   constexpr int T = NttGeom<LOGN>::T;
 #pragma unroll
@@ -99,30 +112,68 @@ __device__ __forceinline__ void load_limb_perm(u64* lds, const u64* __restrict__
     const int idx = (int)threadIdx.x + r * T;
     const u64 v = src[idx];
     const int dst = (ginv == 1u) ? idx : galois_src<LOGN>(idx, ginv);
-    lds_put<NARROW>(lds, dst, v);
+    lds_put<CLS>(lds, dst, v);
   }
 }
 
-// Store the LDS limb, optionally scaled by N^-1 (after an inverse transform).
-template <int LOGN, bool NARROW>
+// Store the LDS limb as canonical residues, optionally scaled by N^-1 (after
+// an inverse transform).
+template <int LOGN, int CLS>
 __device__ __forceinline__ void store_limb(u64* __restrict__ dst, const u64* lds, const ModConst& m, bool scale) {
   constexpr int T = NttGeom<LOGN>::T;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int i = (int)threadIdx.x + r * T;
-    u64 v = lds_get<NARROW>(lds, i);
-    if (scale) v = shoupm<NARROW>(v, m.n_inv, m.n_inv_sh, m.q);
-    dst[i] = v;
+    if constexpr (CLS == CLS_F64) {
+      double v = lds_getw<CLS>(lds, i);
+      if (scale) v = f64_mulc(v, f64_from_u64(m.n_inv), m.n_inv_q, m.qd);
+      dst[i] = to_canon<CLS>(v, m);
+    } else {
+      u64 v = lds_get<CLS>(lds, i, m);
+      if (scale) v = shoupm<CLS == CLS_N32>(v, m.n_inv, m.n_inv_sh, m.q);
+      dst[i] = v;
+    }
+  }
+}
+
+// Centred lift of a residue v mod qs (odd) into the word of target m's
+// class.  f64 targets take small sources (qs < 2^43) as signed values
+// without a reduction; the transforms accept them as they are.  Narrow
+// targets take a narrow source with qs < 2 q_t by one conditional add
+// (both halves of the centred range then land in [0, q_t)), and a source
+// below 2^43 by an exact FP64 reduction of the signed value.
+template <int CLS>
+__device__ __forceinline__ word_t<CLS> lift_word(u64 v, u64 qs, const ModConst& m) {
+  if constexpr (CLS == CLS_F64) {
+    if (qs < ((u64)1 << 43)) {
+      const double x = f64_from_u64(v);
+      return v > (qs - 1) / 2 ? x - f64_from_u64(qs) : x;
+    }
+    return f64_from_u64(lift_centered(v, qs, m));
+  } else if constexpr (CLS == CLS_N32) {
+    if (qs < 2 * m.q) {
+      const u32 x = (u32)v;
+      return x > (u32)((qs - 1) / 2) ? x + (u32)(m.q - qs) : x;
+    }
+    if (qs < ((u64)1 << 43)) {
+      double x = f64_from_u64(v);
+      if (v > (qs - 1) / 2) x -= f64_from_u64(qs);
+      const double r = f64_canon(x, m.qd, m.qinv);
+      return (u32)r;
+    }
+    return (u32)lift_centered(v, qs, m);
+  } else {
+    return (word_t<CLS>)lift_centered(v, qs, m);
   }
 }
 
 // ---------------------------------------------------------------------------
 // Standalone transforms: blockIdx.x = limb, blockIdx.y = polynomial.
-template <int LOGN, bool FWD, bool NARROW>
+template <int LOGN, bool FWD, int CLS>
 __device__ __forceinline__ void ntt_body(u64* lds, u64* p, int mi, const ModConst& m, const Tables& tb) {
-  load_limb_perm<LOGN, NARROW>(lds, p, 1u);
-  if (FWD) fwd_lds<LOGN, NARROW>(lds, tb, mi, m.q); else inv_lds<LOGN, NARROW>(lds, tb, mi, m.q);
-  store_limb<LOGN, NARROW>(p, lds, m, !FWD);
+  load_limb_perm<LOGN, CLS>(lds, p, 1u);
+  if (FWD) fwd_lds<LOGN, CLS>(lds, tb, mi, m); else inv_lds<LOGN, CLS>(lds, tb, mi, m);
+  store_limb<LOGN, CLS>(p, lds, m, !FWD);
 }
 
 template <int LOGN, bool FWD>
@@ -134,19 +185,18 @@ k_ntt(u64* data, int n_limbs, int first_mod, Mods mods, Tables tb) {
   const int mi = first_mod + limb;
   const ModConst m = mods.m[mi];
   u64* p = data + ((size_t)blockIdx.y * n_limbs + limb) * N;
-  if (m.narrow) ntt_body<LOGN, FWD, true>(lds, p, mi, m, tb);
-  else ntt_body<LOGN, FWD, false>(lds, p, mi, m, tb);
+  HE_BY_CLASS(m, (ntt_body<LOGN, FWD, CLS>(lds, p, mi, m, tb)));
 }
 
 // ---------------------------------------------------------------------------
 // Inverse transform of one limb into the coefficient domain (scaled by N^-1),
 // optionally through the Galois permutation on the way into LDS.
-template <int LOGN, bool NARROW>
+template <int LOGN, int CLS>
 __device__ __forceinline__ void digits_body(u64* lds, const u64* src, u32 ginv, u64* out, int j, const ModConst& m,
                                             const Tables& tb) {
-  load_limb_perm<LOGN, NARROW>(lds, src, ginv);
-  inv_lds<LOGN, NARROW>(lds, tb, j, m.q);
-  store_limb<LOGN, NARROW>(out, lds, m, true);
+  load_limb_perm<LOGN, CLS>(lds, src, ginv);
+  inv_lds<LOGN, CLS>(lds, tb, j, m);
+  store_limb<LOGN, CLS>(out, lds, m, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -158,10 +208,12 @@ __device__ __forceinline__ void digits_body(u64* lds, const u64* src, u32 ginv, 
 // `out`), the Galois element applied before switching and its inverse, and
 // the job's level.  Jobs of one launch may have different levels, keys and
 // Galois elements (ragged batches, several layers or requests at once);
-// workspace rows are laid out with the launch's largest level Lmax:
-//   dcoef [count][Lmax][N]       coefficient-domain digits
-//   u     [count][2][Lmax+1][N]  inner products, the P limb at index `level`
-//   rc    [count][2][N]          coefficient-domain last limb (ModDown/rescale)
+// workspace rows are laid out with the launch's largest level Lmax and the
+// number pg of P groups:
+//   dcoef [count][Lmax][N]        coefficient-domain digits
+//   u     [count][2][Lmax+pg][N]  inner products: q_t at row t < level, the
+//                                 partial sum of P group k at row Lmax + k
+//   rc    [count][2][N]           coefficient-domain last limb (ModDown/rescale)
 struct KsJob {
   const u64* d;    // polynomial to switch / ciphertext to rescale
   const u64* c;    // EPI_ROT*: source ciphertext (c0 at c); EPI_RELIN: (d0, d1)
@@ -186,31 +238,40 @@ k_ks_digits(const KsJob* __restrict__ jobs, u64* __restrict__ dcoef, int lmax, M
   const ModConst m = mods.m[j];
   const u64* src = jb.d + (size_t)j * N;
   u64* out = dcoef + (b * lmax + j) * N;
-  if (m.narrow) digits_body<LOGN, true>(lds, src, jb.ginv, out, j, m, tb);
-  else digits_body<LOGN, false>(lds, src, jb.ginv, out, j, m, tb);
+  HE_BY_CLASS(m, (digits_body<LOGN, CLS>(lds, src, jb.ginv, out, j, m, tb)));
 }
 
-// Key switch, step 2: ModUp + inner product for one target modulus t in
-// [0, level]: t < level is q_t, t == level is P (modulus index big_l).
-// Accumulates sum_j NTT(lift(digit_j) mod m_t) * key[j][.][m_t] in registers.
-template <int LOGN, bool NARROW>
+// P groups: with pg groups a job at `level` gives group k the digits
+// [k G, min((k + 1) G, level)), G = ceil(level / pg); groups past the last
+// digit are empty and have no partial.
+__host__ __device__ inline int pgroup_size(int level, int pg) { return (level + pg - 1) / pg; }
+__host__ __device__ inline int pgroup_count(int level, int pg) {
+  const int g = pgroup_size(level, pg);
+  return (level + g - 1) / g;
+}
+
+// Key switch, step 2: ModUp + inner product for one target: a ciphertext
+// prime t over all digits, or one group of digits [j0, j1) for P.
+// Accumulates sum_j NTT(lift(digit_j) mod m) * key[j][.][m] in registers and
+// writes it to u row `row` (canonical residues).
+template <int LOGN, int CLS>
 __device__ __forceinline__ void modup_ip_body(u64* lds, const u64* __restrict__ dcoef, const KsJob& jb, size_t b,
-                                              u64* __restrict__ u, int lmax, int big_l, int t, const Mods& mods,
-                                              const Tables& tb) {
-  typedef word_t<NARROW> W;
+                                              u64* __restrict__ u, int lmax, int urows, int big_l, int t, int mi,
+                                              int j0, int j1, int row, const Mods& mods, const Tables& tb) {
+  // accumulators: 64-bit sums of products of canonical narrow residues
+  // (each < 2^60, at most 15 digits), centred doubles (f64), residues (wide)
+  typedef std::conditional_t<CLS == CLS_N32, u64, word_t<CLS>> A;
   constexpr int N = 1 << LOGN;
   constexpr int T = NttGeom<LOGN>::T;
-  const int level = jb.level;
-  const int mi = (t < level) ? t : big_l;
   const ModConst m = mods.m[mi];
   const u64* key = jb.key;
-  W acc0[16], acc1[16];
+  A acc0[16], acc1[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0;
-  for (int j = 0; j < level; ++j) {
+  for (int j = j0; j < j1; ++j) {
     if (j == t) {
       // the digit reduced mod its own prime is the (permuted) input limb itself
-      load_limb_perm<LOGN, NARROW>(lds, jb.d + (size_t)j * N, jb.ginv);
+      load_limb_perm<LOGN, CLS>(lds, jb.d + (size_t)j * N, jb.ginv);
       __syncthreads();
     } else {
       const u64 qj = mods.m[j].q;
@@ -219,9 +280,9 @@ __device__ __forceinline__ void modup_ip_body(u64* lds, const u64* __restrict__ 
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int i = tid + r * T;
-        lds_put<NARROW>(lds, i, lift_centered(d[i], qj, m));
+        lds_putw<CLS>(lds, i, lift_word<CLS>(d[i], qj, m));
       }
-      fwd_lds<LOGN, NARROW>(lds, tb, mi, m.q);
+      fwd_lds<LOGN, CLS>(lds, tb, mi, m);
     }
     const u64* kb = key + (((size_t)j * 2 + 0) * (big_l + 1) + mi) * N;
     const u64* ka = key + (((size_t)j * 2 + 1) * (big_l + 1) + mi) * N;
@@ -229,44 +290,75 @@ __device__ __forceinline__ void modup_ip_body(u64* lds, const u64* __restrict__ 
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int i = tid + r * T;
-      const u64 dv = lds_get<NARROW>(lds, i);
-      // narrow key residues fit the low word of their u64 slot
-      const u64 kbv = NARROW ? (u64)reinterpret_cast<const u32*>(kb)[2 * i] : kb[i];
-      const u64 kav = NARROW ? (u64)reinterpret_cast<const u32*>(ka)[2 * i] : ka[i];
-      acc0[r] = (W)addm<NARROW>(acc0[r], mul_mod_t<NARROW>(dv, kbv, m), m.q);
-      acc1[r] = (W)addm<NARROW>(acc1[r], mul_mod_t<NARROW>(dv, kav, m), m.q);
+      if constexpr (CLS == CLS_N32) {
+        const u32 dv = (u32)lds_get<CLS>(lds, i, m);
+        // narrow key residues fit the low word of their u64 slot
+        acc0[r] += (u64)dv * reinterpret_cast<const u32*>(kb)[2 * i];
+        acc1[r] += (u64)dv * reinterpret_cast<const u32*>(ka)[2 * i];
+      } else if constexpr (CLS == CLS_F64) {
+        const double dv = lds_getw<CLS>(lds, i);
+        // centred products, summed unreduced (|sum| < 8.2 q for <= 15 digits)
+        acc0[r] += f64_mulmod(dv, f64_from_u64(kb[i]), m.qd, m.qinv);
+        acc1[r] += f64_mulmod(dv, f64_from_u64(ka[i]), m.qd, m.qinv);
+      } else {
+        const u64 dv = lds_getw<CLS>(lds, i);
+        acc0[r] = add_mod(acc0[r], mul_mod_t<false>(dv, kb[i], m), m.q);
+        acc1[r] = add_mod(acc1[r], mul_mod_t<false>(dv, ka[i], m), m.q);
+      }
       if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bound the load hoisting
     }
     __syncthreads();
   }
-  u64* u0 = u + ((b * 2 + 0) * (lmax + 1) + t) * N;
-  u64* u1 = u + ((b * 2 + 1) * (lmax + 1) + t) * N;
+  u64* u0 = u + ((b * 2 + 0) * urows + row) * N;
+  u64* u1 = u + ((b * 2 + 1) * urows + row) * N;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int i = (int)threadIdx.x + r * T;
-    u0[i] = acc0[r];
-    u1[i] = acc1[r];
+    if constexpr (CLS == CLS_N32) {
+      u0[i] = reduce64(acc0[r], m);
+      u1[i] = reduce64(acc1[r], m);
+    } else if constexpr (CLS == CLS_F64) {
+      u0[i] = to_canon<CLS>(acc0[r], m);
+      u1[i] = to_canon<CLS>(acc1[r], m);
+    } else {
+      u0[i] = acc0[r];
+      u1[i] = acc1[r];
+    }
   }
 }
 
-// grid (Lmax + 1, count): blockIdx.x < Lmax is ciphertext prime blockIdx.x,
-// blockIdx.x == Lmax is P.  Each width class is its own kernel (so the 32-bit
-// body gets a register allocation of its own); blocks of the other class,
-// and primes above a job's level, exit at once.
-template <int LOGN, bool NARROW>
+// grid (Lmax + pg, count): blockIdx.x < Lmax is ciphertext prime blockIdx.x,
+// blockIdx.x = Lmax + k is group k of P's digits.  Each width class is its
+// own kernel (so each body gets a register allocation of its own); blocks of
+// the other classes, primes above a job's level and empty P groups exit at
+// once.
+template <int LOGN, int CLS>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
-k_ks_modup_ip(const KsJob* __restrict__ jobs, const u64* __restrict__ dcoef, u64* __restrict__ u, int lmax,
+k_ks_modup_ip(const KsJob* __restrict__ jobs, const u64* __restrict__ dcoef, u64* __restrict__ u, int lmax, int pg,
               int big_l, Mods mods, Tables tb) {
   __shared__ u64 lds[NttGeom<LOGN>::LDS];
   const size_t b = blockIdx.y;
   const KsJob jb = jobs[b];
   if (jb.key == nullptr) return;
-  int t = blockIdx.x;
-  if (t == lmax) t = jb.level;
-  else if (t >= jb.level) return;
-  const int mi = (t < jb.level) ? t : big_l;
-  if ((mods.m[mi].narrow != 0) != NARROW) return;
-  modup_ip_body<LOGN, NARROW>(lds, dcoef, jb, b, u, lmax, big_l, t, mods, tb);
+  const int x = blockIdx.x;
+  const int level = jb.level;
+  int t, mi, j0, j1, row;
+  if (x < lmax) {
+    if (x >= level) return;
+    t = mi = row = x;
+    j0 = 0;
+    j1 = level;
+  } else {
+    const int g = pgroup_size(level, pg);
+    j0 = (x - lmax) * g;
+    if (j0 >= level) return;
+    j1 = min(j0 + g, level);
+    t = -1;
+    mi = big_l;
+    row = x;
+  }
+  if ((int)mods.m[mi].cls != CLS) return;
+  modup_ip_body<LOGN, CLS>(lds, dcoef, jb, b, u, lmax, lmax + pg, big_l, t, mi, j0, j1, row, mods, tb);
 }
 
 // INTT of the limb that is divided out: for polynomial p = 2 b + comp,
@@ -274,50 +366,73 @@ k_ks_modup_ip(const KsJob* __restrict__ jobs, const u64* __restrict__ dcoef, u64
 //   MODE_LAST: the last limb of the ciphertext jobs[b].d (rescale).
 enum { MODE_P = 0, MODE_LAST = 1 };
 
+// Coefficient-domain copy of the P limb of u: the sum of its group partials
+// (rows lmax .. lmax + groups - 1, each canonical mod P), INTT, N^-1.
+template <int LOGN, int CLS>
+__device__ __forceinline__ void intt_p_body(u64* lds, const u64* __restrict__ urow, int groups, u64* out, int mi,
+                                            const ModConst& m, const Tables& tb) {
+  constexpr int N = 1 << LOGN;
+  constexpr int T = NttGeom<LOGN>::T;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = (int)threadIdx.x + r * T;
+    u64 v = urow[i];
+    for (int k = 1; k < groups; ++k) v = add_mod(v, urow[(size_t)k * N + i], m.q);
+    lds_put<CLS>(lds, i, v);
+  }
+  inv_lds<LOGN, CLS>(lds, tb, mi, m);
+  store_limb<LOGN, CLS>(out, lds, m, true);
+}
+
+// INTT of the limb that is divided out: for polynomial p = 2 b + comp,
+//   MODE_P:    the P limb of u, i.e. the sum of its group partials (ModDown
+//              after a key switch; u rows per polynomial lmax + pg);
+//   MODE_LAST: the last limb of the ciphertext jobs[b].d (rescale).
 template <int LOGN, int MODE>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
-k_intt_last(const KsJob* __restrict__ jobs, const u64* __restrict__ u, int lmax, int big_l, u64* __restrict__ rcoef,
-            Mods mods, Tables tb) {
+k_intt_last(const KsJob* __restrict__ jobs, const u64* __restrict__ u, int lmax, int pg, int big_l,
+            u64* __restrict__ rcoef, Mods mods, Tables tb) {
   constexpr int N = 1 << LOGN;
   __shared__ u64 lds[NttGeom<LOGN>::LDS];
   const size_t p = blockIdx.x;
   const size_t b = p >> 1;
   const int comp = (int)(p & 1);
   const KsJob jb = jobs[b];
-  const u64* s;
-  int mi;
+  u64* out = rcoef + p * N;
   if (MODE == MODE_P) {
     if (jb.key == nullptr) return;
-    s = u + ((b * 2 + comp) * (lmax + 1) + jb.level) * N;
-    mi = big_l;
+    const u64* s = u + ((b * 2 + comp) * (lmax + pg) + lmax) * N;
+    const int groups = pgroup_count(jb.level, pg);
+    const ModConst m = mods.m[big_l];
+    HE_BY_CLASS(m, (intt_p_body<LOGN, CLS>(lds, s, groups, out, big_l, m, tb)));
   } else {
-    s = jb.d + ((size_t)comp * jb.level + jb.level - 1) * N;
-    mi = jb.level - 1;
+    const u64* s = jb.d + ((size_t)comp * jb.level + jb.level - 1) * N;
+    const int mi = jb.level - 1;
+    const ModConst m = mods.m[mi];
+    HE_BY_CLASS(m, (digits_body<LOGN, CLS>(lds, s, 1u, out, mi, m, tb)));
   }
-  const ModConst m = mods.m[mi];
-  u64* out = rcoef + p * N;
-  if (m.narrow) digits_body<LOGN, true>(lds, s, 1u, out, mi, m, tb);
-  else digits_body<LOGN, false>(lds, s, 1u, out, mi, m, tb);
 }
 
 enum { EPI_STORE = 0, EPI_ROT = 1, EPI_ROTSUM = 2, EPI_RELIN = 3 };
 
 // Drop the last limb, for polynomial p = 2 b + comp (blockIdx.y) and kept
 // prime t (blockIdx.x):  val = (src_t - NTT(lift(rc_p))) * div^-1 mod q_t,
-// with (src, div) = (u limb t, P) in MODE_P and (d limb t, q_{level-1}) in
+// with (src, div) = (u row t, P) in MODE_P and (d limb t, q_{level-1}) in
 // MODE_LAST, followed by the epilogue into jobs[b].out:
 //   EPI_STORE   out = val
 //   EPI_ROT     out = (sigma_g(c0) + val, val)        (identity job: out = c)
 //   EPI_ROTSUM  out = c + (sigma_g(c0) + val, val)    (identity job: out = 2c)
 //   EPI_RELIN   out = (d0 + val, d1 + val), (d0, d1) = c
 // inv_tab[div][t] holds q_div^-1 mod q_t (div = big_l for P) and its Shoup
-// companion at inv_tab[HE_MAXM * HE_MAXM + ...].
-template <int LOGN, int MODE, int EPI, bool NARROW>
+// companion at inv_tab[HE_MAXM * HE_MAXM + ...].  u has `urows` rows per
+// polynomial.
+template <int LOGN, int MODE, int EPI, int CLS>
 __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t b, int comp, int t,
-                                               const u64* __restrict__ u, int lmax, int big_l,
+                                               const u64* __restrict__ u, int urows, int big_l,
                                                const u64* __restrict__ rcoef, const u64* __restrict__ inv_tab,
                                                const Mods& mods, const Tables& tb) {
-  typedef word_t<NARROW> W;
+  constexpr bool NW = CLS == CLS_N32;  // canonical values in 32-bit words
+  typedef std::conditional_t<NW, u32, u64> V;
   constexpr int N = 1 << LOGN;
   constexpr int T = NttGeom<LOGN>::T;
   const int level = jb.level;
@@ -331,7 +446,7 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
     for (int r = 0; r < 16; ++r) {
       const int i = (int)threadIdx.x + r * T;
       u64 x = cs[i];
-      if constexpr (EPI == EPI_ROTSUM) x = addm<NARROW>(x, x, m.q);
+      if constexpr (EPI == EPI_ROTSUM) x = addm<NW>(x, x, m.q);
       o[i] = x;
     }
     return;
@@ -341,18 +456,23 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int i = (int)threadIdx.x + r * T;
-    lds_put<NARROW>(lds, i, lift_centered(rc[i], qd, m));
+    lds_putw<CLS>(lds, i, lift_word<CLS>(rc[i], qd, m));
   }
-  fwd_lds<LOGN, NARROW>(lds, tb, t, m.q);
-  const u64* s = (MODE == MODE_P) ? u + ((b * 2 + comp) * (lmax + 1) + t) * N
+  fwd_lds<LOGN, CLS>(lds, tb, t, m);
+  const u64* s = (MODE == MODE_P) ? u + ((b * 2 + comp) * urows + t) * N
                                   : jb.d + ((size_t)comp * level + t) * N;
   const u64 iv = inv_tab[div_mi * HE_MAXM + t];
   const u64 ivs = inv_tab[HE_MAXM * HE_MAXM + div_mi * HE_MAXM + t];
-  W val[16];
+  V val[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int i = (int)threadIdx.x + r * T;
-    val[r] = (W)shoupm<NARROW>(subm<NARROW>(s[i], lds_get<NARROW>(lds, i), m.q), iv, ivs, m.q);
+    if constexpr (CLS == CLS_F64) {
+      const double dlt = f64_from_u64(s[i]) - lds_getw<CLS>(lds, i);
+      val[r] = to_canon<CLS>(f64_mulmod(dlt, f64_from_u64(iv), m.qd, m.qinv), m);
+    } else {
+      val[r] = (V)shoupm<NW>(subm<NW>(s[i], lds_get<CLS>(lds, i, m), m.q), iv, ivs, m.q);
+    }
   }
   if constexpr (EPI == EPI_STORE) {
 #pragma unroll
@@ -362,26 +482,28 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int i = (int)threadIdx.x + r * T;
-      o[i] = addm<NARROW>(dd[i], val[r], m.q);
+      o[i] = addm<NW>(dd[i], val[r], m.q);
     }
   } else {  // EPI_ROT / EPI_ROTSUM
     const u64* cs = jb.c + ((size_t)comp * level + t) * N;
     if (comp == 0) {
+      // sigma_g(c0) through LDS, in canonical 32-bit (narrow) or 64-bit words
+      constexpr int PC = NW ? CLS_N32 : CLS_U64;
       __syncthreads();  // everyone is done reading the lifted limb
-      W own[16];
+      V own[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int idx = (int)threadIdx.x + r * T;
         const u64 v = cs[idx];
-        own[r] = (W)v;
-        lds_put<NARROW>(lds, galois_src<LOGN>(idx, jb.ginv), v);
+        own[r] = (V)v;
+        lds_put<PC>(lds, galois_src<LOGN>(idx, jb.ginv), v);
       }
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int i = (int)threadIdx.x + r * T;
-        u64 x = addm<NARROW>(lds_get<NARROW>(lds, i), val[r], m.q);  // sigma_g(c0) + u0
-        if constexpr (EPI == EPI_ROTSUM) x = addm<NARROW>(x, own[r], m.q);
+        u64 x = addm<NW>(lds_get<PC>(lds, i, m), val[r], m.q);  // sigma_g(c0) + u0
+        if constexpr (EPI == EPI_ROTSUM) x = addm<NW>(x, own[r], m.q);
         o[i] = x;
       }
     } else {
@@ -389,7 +511,7 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int i = (int)threadIdx.x + r * T;
-          o[i] = addm<NARROW>(cs[i], val[r], m.q);
+          o[i] = addm<NW>(cs[i], val[r], m.q);
         }
       } else {
 #pragma unroll
@@ -402,7 +524,7 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
 // grid (Lmax, 2 count)
 template <int LOGN, int MODE, int EPI>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
-k_drop_last(const KsJob* __restrict__ jobs, const u64* __restrict__ u, int lmax, int big_l,
+k_drop_last(const KsJob* __restrict__ jobs, const u64* __restrict__ u, int urows, int big_l,
             const u64* __restrict__ rcoef, const u64* __restrict__ inv_tab, Mods mods, Tables tb) {
   __shared__ u64 lds[NttGeom<LOGN>::LDS];
   const int t = blockIdx.x;
@@ -412,17 +534,16 @@ k_drop_last(const KsJob* __restrict__ jobs, const u64* __restrict__ u, int lmax,
   const KsJob jb = jobs[b];
   const int keep = (MODE == MODE_P) ? jb.level : jb.level - 1;
   if (t >= keep) return;
-  if (mods.m[t].narrow)
-    drop_last_body<LOGN, MODE, EPI, true>(lds, jb, b, comp, t, u, lmax, big_l, rcoef, inv_tab, mods, tb);
-  else
-    drop_last_body<LOGN, MODE, EPI, false>(lds, jb, b, comp, t, u, lmax, big_l, rcoef, inv_tab, mods, tb);
+  const ModConst& m = mods.m[t];
+  HE_BY_CLASS(m, (drop_last_body<LOGN, MODE, EPI, CLS>(lds, jb, b, comp, t, u, urows, big_l, rcoef, inv_tab, mods,
+                                                       tb)));
 }
 
 // ---------------------------------------------------------------------------
 // Hoisted rotations of one ciphertext.
 // ModUp once: dhat[j][t] = NTT(lift(digit_j) mod m_t) for j < level,
 // t <= level (t == level is P).  blockIdx.x = t, blockIdx.y = j.
-template <int LOGN, bool NARROW>
+template <int LOGN, int CLS>
 __device__ __forceinline__ void modup_store_body(u64* lds, const u64* __restrict__ dcoef, const u64* __restrict__ c1,
                                                  u64* __restrict__ dhat, int level, int big_l, const Mods& mods,
                                                  const Tables& tb) {
@@ -444,10 +565,10 @@ __device__ __forceinline__ void modup_store_body(u64* lds, const u64* __restrict
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int i = (int)threadIdx.x + r * T;
-    lds_put<NARROW>(lds, i, lift_centered(d[i], qj, m));
+    lds_putw<CLS>(lds, i, lift_word<CLS>(d[i], qj, m));
   }
-  fwd_lds<LOGN, NARROW>(lds, tb, mi, m.q);
-  store_limb<LOGN, NARROW>(out, lds, m, false);
+  fwd_lds<LOGN, CLS>(lds, tb, mi, m);
+  store_limb<LOGN, CLS>(out, lds, m, false);
 }
 
 template <int LOGN>
@@ -456,10 +577,8 @@ k_modup_store(const u64* __restrict__ dcoef, const u64* __restrict__ c1, u64* __
               Mods mods, Tables tb) {
   __shared__ u64 lds[NttGeom<LOGN>::LDS];
   const int mi = ((int)blockIdx.x < level) ? (int)blockIdx.x : big_l;
-  if (mods.m[mi].narrow)
-    modup_store_body<LOGN, true>(lds, dcoef, c1, dhat, level, big_l, mods, tb);
-  else
-    modup_store_body<LOGN, false>(lds, dcoef, c1, dhat, level, big_l, mods, tb);
+  const ModConst& m = mods.m[mi];
+  HE_BY_CLASS(m, (modup_store_body<LOGN, CLS>(lds, dcoef, c1, dhat, level, big_l, mods, tb)));
 }
 
 // Inner product of the shared lifted digits, permuted per rotation, with
@@ -594,7 +713,7 @@ template <int LOGN, bool NARROW>
 __device__ __forceinline__ void dp_hma_body(const u64* __restrict__ x, const u64* __restrict__ filt,
                                             u64* __restrict__ out, int level, int out_base, const DPGeom& geo,
                                             const ModConst& m, u64* lds) {
-  typedef word_t<NARROW> W;
+  typedef std::conditional_t<NARROW, u32, u64> W;
   constexpr int N = 1 << LOGN;
   constexpr int T = NttGeom<LOGN>::T;
   const int t = blockIdx.x;
@@ -617,14 +736,14 @@ __device__ __forceinline__ void dp_hma_body(const u64* __restrict__ x, const u64
   const int n_cls = geo.n_row_cls * geo.n_col_cls;
   for (int mc = 0; mc < geo.m_cts; ++mc) {
     const u64* f = filt + ((((size_t)o * n_cls + cls) * geo.m_cts + mc) * level + t) * N;
-    load_limb_perm<LOGN, NARROW>(lds, f, ginv);
+    load_limb_perm<LOGN, NARROW ? CLS_N32 : CLS_U64>(lds, f, ginv);
     __syncthreads();
     const u64* x0 = x + (((size_t)mc * 2 + 0) * level + t) * N;
     const u64* x1 = x + (((size_t)mc * 2 + 1) * level + t) * N;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int k = (int)threadIdx.x + r * T;
-      const u64 fv = lds_get<NARROW>(lds, k);
+      const u64 fv = lds_get<NARROW ? CLS_N32 : CLS_U64>(lds, k, m);
       acc0[r] = (W)addm<NARROW>(acc0[r], mul_mod_t<NARROW>(x0[k], fv, m), m.q);
       acc1[r] = (W)addm<NARROW>(acc1[r], mul_mod_t<NARROW>(x1[k], fv, m), m.q);
     }

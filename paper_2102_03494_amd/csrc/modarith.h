@@ -1,10 +1,14 @@
 // Modular arithmetic for RNS limbs on gfx950 (and the host).
 //
-// Residues are uint64 in [0, q).  Each prime is one of two width classes,
-// chosen per limb and uniform across a workgroup:
+// Residues are uint64 in [0, q) in memory.  Each prime is one of three
+// width classes, chosen per limb and uniform across a workgroup:
 //   narrow  q < 2^30 : residues fit 32-bit words with headroom (4q < 2^32);
 //                      reductions use 32-bit multiplies (v_mul_hi_u32,
 //                      v_mad_u64_u32) and min-based conditional subtraction;
+//   f64     q < 2^42 : inside the transform kernels residues are exact
+//                      integers held in FP64 registers, signed and only
+//                      lazily reduced; products use the exact FMA splitting
+//                      below (all full-rate FP64 instructions on gfx950);
 //   wide    q < 2^62 : 128-bit products from __umul64hi.
 // Products with a fixed operand (twiddles, inverses) use Shoup's method with a
 // precomputed companion w' = floor(w * 2^32 / q) (narrow) or
@@ -31,7 +35,15 @@ struct ModConst {
   u64 n_inv_sh;
   u64 r64;     // 2^64 mod q (folds the high word of a 128-bit sum)
   u64 r64_sh;
+  u32 cls;     // width class (CLS_*)
+  u32 pad_;
+  double qd;       // q as a double (exact for q < 2^53)
+  double qinv;     // 1 / q rounded to double
+  double n_inv_q;  // n_inv / q rounded to double (f64 Shoup-style companion)
 };
+
+enum { CLS_N32 = 0, CLS_F64 = 1, CLS_U64 = 2 };
+constexpr u64 F64_LIMIT = (u64)1 << 42;
 
 __host__ __device__ inline u64 mulhi64(u64 a, u64 b) {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -52,6 +64,50 @@ __host__ __device__ inline u64 sub_mod(u64 a, u64 b, u64 q) {
 
 constexpr u64 NARROW_LIMIT = (u64)1 << 30;
 __host__ __device__ inline bool is_narrow(u64 q) { return q < NARROW_LIMIT; }
+__host__ __device__ inline int width_class(u64 q) {
+  return q < NARROW_LIMIT ? CLS_N32 : (q < F64_LIMIT ? CLS_F64 : CLS_U64);
+}
+
+// ---- f64 class ---------------------------------------------------------------
+// Values are integers |a| < 2^46 held exactly in doubles.  For a multiplier
+// w < q with wq ~ w / q (rounded, or formed as fl(w * fl(1/q))) the product
+// a * w is split exactly as h + l with h = fl(a w) and l = fma(a, w, -h);
+// the quotient estimate t = rint(a * wq) is within 1/2 + 2^-5 of a w / q
+// (relative error of a * wq below 3 * 2^-53 and |a w / q| < 2^46), so
+// r = (h - t q) + l lies in (-0.54 q, 0.54 q).  h - t q is an integer below 2^44 in magnitude, hence
+// fma(-t, q, h) is exact, and so is the final sum with |l| <= ulp(h) / 2.
+// The result is congruent to a w mod q but only "centred", not canonical.
+__host__ __device__ inline double f64_mulc(double a, double w, double wq, double q) {
+  const double h = a * w;
+  const double l = fma(a, w, -h);
+  const double t = rint(a * wq);
+  return fma(-t, q, h) + l;
+}
+// a * b mod q (centred) for two data operands: wq computed on the fly.
+__host__ __device__ inline double f64_mulmod(double a, double b, double q, double qinv) {
+  return f64_mulc(a, b, b * qinv, q);
+}
+// Centred representative in [-q/2 - 2^-6 q, q/2 + 2^-6 q] of any |a| < 2^46.
+__host__ __device__ inline double f64_centre(double a, double q, double qinv) {
+  return fma(-rint(a * qinv), q, a);
+}
+// Canonical residue in [0, q) of any |a| < 2^46.
+__host__ __device__ inline double f64_canon(double a, double q, double qinv) {
+  const double r = f64_centre(a, q, qinv);
+  return r < 0.0 ? r + q : r;
+}
+// Exact conversions between integers in [0, 2^52) and doubles: with the
+// exponent of 2^52 fixed, the mantissa field of 2^52 + v is v itself.
+__host__ __device__ inline double f64_from_u64(u64 v) {
+  union { u64 u; double d; } x;
+  x.u = v | 0x4330000000000000ull;
+  return x.d - 4503599627370496.0;
+}
+__host__ __device__ inline u64 f64_to_u64(double v) {  // v an integer in [0, 2^52)
+  union { u64 u; double d; } x;
+  x.d = v + 4503599627370496.0;
+  return x.u & 0x000FFFFFFFFFFFFFull;
+}
 
 // a * w mod q with Shoup companion wsh; a < 2^32 (narrow) or any a (wide).
 __host__ __device__ inline u64 mul_shoup(u64 a, u64 w, u64 wsh, u64 q, bool narrow) {

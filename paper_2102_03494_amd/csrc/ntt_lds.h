@@ -23,10 +23,14 @@
 // pre-processing such as a Galois permutation or a centred lift) and read the
 // result back out of LDS in a coalesced pattern.
 //
-// Word size: limbs of a narrow prime (q < 2^30) are held as 32-bit words in
-// registers and LDS and use 32-bit twiddle tables, so every butterfly is pure
-// 32-bit integer work (three 32-bit multiplies for the Shoup product, min-based
-// conditional subtractions); wide primes use 64-bit words.
+// Word size per width class (modarith.h): narrow limbs are 32-bit words in
+// registers and LDS with 32-bit twiddle tables and Harvey's lazy butterflies
+// (forward values kept in [0, 4q), inverse values in [0, 2q), which 4q < 2^32
+// allows; three 32-bit multiplies per Shoup product, min-based conditional
+// subtractions); f64 limbs are exact
+// integers in doubles, left unreduced through the forward butterflies
+// (|value| grows by at most 0.54 q per stage, below 8.6 q after 14 stages)
+// and centred after each inverse sum; wide limbs are 64-bit words.
 #pragma once
 #include <type_traits>
 
@@ -34,8 +38,20 @@
 
 namespace he {
 
-template <bool NARROW>
-using word_t = std::conditional_t<NARROW, u32, u64>;
+template <int CLS>
+struct Word {
+  typedef u64 W;
+};
+template <>
+struct Word<CLS_N32> {
+  typedef u32 W;
+};
+template <>
+struct Word<CLS_F64> {
+  typedef double W;
+};
+template <int CLS>
+using word_t = typename Word<CLS>::W;
 
 __device__ __forceinline__ int lds_idx(int i) { return i + (i >> 5); }
 
@@ -44,19 +60,66 @@ struct NttGeom {
   static constexpr int N = 1 << LOGN;
   static constexpr int E = 16;           // entries per thread per pass
   static constexpr int T = N / E;        // threads per workgroup
-  static constexpr int LDS = N + (N >> 5);  // u64 words reserved (narrow limbs use half)
+  static constexpr int LDS = N + (N >> 5);  // 64-bit words reserved (narrow limbs use half)
 };
 
-// LDS accessors in the word size of the width class.
-template <bool NARROW>
-__device__ __forceinline__ void lds_put(u64* lds, int i, u64 v) {
-  if constexpr (NARROW) reinterpret_cast<u32*>(lds)[lds_idx(i)] = (u32)v;
-  else lds[lds_idx(i)] = v;
+// Modulus as seen by the butterflies of one class.
+template <int CLS>
+struct MV {
+  u64 q;
+};
+template <>
+struct MV<CLS_N32> {
+  u32 q;
+};
+template <>
+struct MV<CLS_F64> {
+  double q, qinv;
+};
+template <int CLS>
+__device__ __forceinline__ MV<CLS> mview(const ModConst& m) {
+  if constexpr (CLS == CLS_N32) return MV<CLS>{(u32)m.q};
+  else if constexpr (CLS == CLS_F64) return MV<CLS>{m.qd, m.qinv};
+  else return MV<CLS>{m.q};
 }
-template <bool NARROW>
-__device__ __forceinline__ u64 lds_get(const u64* lds, int i) {
-  if constexpr (NARROW) return reinterpret_cast<const u32*>(lds)[lds_idx(i)];
-  else return lds[lds_idx(i)];
+
+// Canonical residue (u64 in [0, q)) <-> word of the class.
+template <int CLS>
+__device__ __forceinline__ word_t<CLS> to_word(u64 v) {
+  if constexpr (CLS == CLS_F64) return f64_from_u64(v);
+  else return (word_t<CLS>)v;
+}
+// Canonical residue of a transform output (narrow: from [0, 4q)).
+template <int CLS>
+__device__ __forceinline__ u64 to_canon(word_t<CLS> v, const ModConst& m) {
+  if constexpr (CLS == CLS_F64) {
+    return f64_to_u64(f64_canon(v, m.qd, m.qinv));
+  } else if constexpr (CLS == CLS_N32) {
+    const u32 q = (u32)m.q;
+    v = min(v, v - 2 * q);
+    return (u64)min(v, v - q);
+  } else {
+    return (u64)v;
+  }
+}
+
+// LDS accessors in the word size of the class: raw words, and canonical
+// residues in and out.
+template <int CLS>
+__device__ __forceinline__ void lds_putw(u64* lds, int i, word_t<CLS> v) {
+  reinterpret_cast<word_t<CLS>*>(lds)[lds_idx(i)] = v;
+}
+template <int CLS>
+__device__ __forceinline__ word_t<CLS> lds_getw(const u64* lds, int i) {
+  return reinterpret_cast<const word_t<CLS>*>(lds)[lds_idx(i)];
+}
+template <int CLS>
+__device__ __forceinline__ void lds_put(u64* lds, int i, u64 v) {
+  lds_putw<CLS>(lds, i, to_word<CLS>(v));
+}
+template <int CLS>
+__device__ __forceinline__ u64 lds_get(const u64* lds, int i, const ModConst& m) {
+  return to_canon<CLS>(lds_getw<CLS>(lds, i), m);
 }
 
 // ---- butterfly arithmetic ------------------------------------------------------
@@ -74,37 +137,69 @@ __device__ __forceinline__ u32 shoup32(u32 a, u32 w, u32 wsh, u32 q) {
   return min(r, r - q);
 }
 
-template <bool NARROW>
+// Butterfly pieces.  Forward (Cooley-Tukey): x = fwd_x(a), y = mulc(b),
+// outputs (add(x, y), sub(x, y)).  Inverse (Gentleman-Sande): outputs
+// (add_inv(a, b), mulc(sub_inv(a, b))).  mulc is the product with a table
+// constant (w, companion wsh).
+template <int CLS>
 struct Arith;
 
 template <>
-struct Arith<true> {
+struct Arith<CLS_N32> {  // Harvey: forward in [0, 4q), inverse in [0, 2q)
   typedef u32 W;
-  static __device__ __forceinline__ W add(W a, W b, W q) { return add32(a, b, q); }
-  static __device__ __forceinline__ W sub(W a, W b, W q) { return sub32(a, b, q); }
-  static __device__ __forceinline__ W mulc(W a, W w, W wsh, W q) { return shoup32(a, w, wsh, q); }
+  static __device__ __forceinline__ W fwd_x(W a, MV<CLS_N32> m) { return min(a, a - 2 * m.q); }
+  static __device__ __forceinline__ W add(W a, W b, MV<CLS_N32>) { return a + b; }
+  static __device__ __forceinline__ W sub(W a, W b, MV<CLS_N32> m) { return a - b + 2 * m.q; }
+  static __device__ __forceinline__ W add_inv(W a, W b, MV<CLS_N32> m) {
+    const W s = a + b;
+    return min(s, s - 2 * m.q);
+  }
+  static __device__ __forceinline__ W sub_inv(W a, W b, MV<CLS_N32> m) { return a - b + 2 * m.q; }
+  // lazy Shoup product in [0, 2q) of any a < 2^32
+  static __device__ __forceinline__ W mulc(W a, W w, W wsh, MV<CLS_N32> m) {
+    return a * w - __umulhi(a, wsh) * m.q;
+  }
 };
 
 template <>
-struct Arith<false> {
-  typedef u64 W;
-  static __device__ __forceinline__ W add(W a, W b, W q) { return add_mod(a, b, q); }
-  static __device__ __forceinline__ W sub(W a, W b, W q) { return sub_mod(a, b, q); }
-  static __device__ __forceinline__ W mulc(W a, W w, W wsh, W q) { return mul_shoup(a, w, wsh, q, false); }
+struct Arith<CLS_F64> {
+  typedef double W;
+  static __device__ __forceinline__ W fwd_x(W a, MV<CLS_F64>) { return a; }
+  static __device__ __forceinline__ W add(W a, W b, MV<CLS_F64>) { return a + b; }
+  static __device__ __forceinline__ W sub(W a, W b, MV<CLS_F64>) { return a - b; }
+  static __device__ __forceinline__ W add_inv(W a, W b, MV<CLS_F64> m) { return f64_centre(a + b, m.q, m.qinv); }
+  static __device__ __forceinline__ W sub_inv(W a, W b, MV<CLS_F64>) { return a - b; }
+  // the companion w / q is formed on the fly (one multiply instead of a
+  // second table load and two registers per twiddle)
+  static __device__ __forceinline__ W mulc(W a, W w, W, MV<CLS_F64> m) { return f64_mulc(a, w, w * m.qinv, m.q); }
 };
 
-// Twiddle table view: narrow primes read the 32-bit tables.
-template <bool NARROW>
+template <>
+struct Arith<CLS_U64> {
+  typedef u64 W;
+  static __device__ __forceinline__ W fwd_x(W a, MV<CLS_U64>) { return a; }
+  static __device__ __forceinline__ W add(W a, W b, MV<CLS_U64> m) { return add_mod(a, b, m.q); }
+  static __device__ __forceinline__ W sub(W a, W b, MV<CLS_U64> m) { return sub_mod(a, b, m.q); }
+  static __device__ __forceinline__ W add_inv(W a, W b, MV<CLS_U64> m) { return add_mod(a, b, m.q); }
+  static __device__ __forceinline__ W sub_inv(W a, W b, MV<CLS_U64> m) { return sub_mod(a, b, m.q); }
+  static __device__ __forceinline__ W mulc(W a, W w, W wsh, MV<CLS_U64> m) {
+    return mul_shoup(a, w, wsh, m.q, false);
+  }
+};
+
+// Twiddle table view in the class's word type: w and its Shoup companion
+// (integer classes; the f64 class reads w only).
+template <int CLS>
 struct Tw {
-  const word_t<NARROW>* w;
-  const word_t<NARROW>* sh;
+  const word_t<CLS>* w;
+  const word_t<CLS>* sh;
 };
 
 // One forward pass: stages s0 .. s0+K-1.
-template <int LOGN, int K, bool NARROW>
-__device__ __forceinline__ void fwd_pass(u64* lds_raw, int s0, Tw<NARROW> tw, word_t<NARROW> q, int tid) {
-  typedef word_t<NARROW> W;
-  typedef Arith<NARROW> A;
+template <int LOGN, int K, int CLS>
+__device__ __forceinline__ void fwd_pass(u64* lds_raw, int s0, Tw<CLS> tw, MV<CLS> q, int tid) {
+  typedef word_t<CLS> W;
+  typedef Arith<CLS> A;
   W* lds = reinterpret_cast<W*>(lds_raw);
   constexpr int N = 1 << LOGN;
   constexpr int R = 1 << K;
@@ -130,8 +225,8 @@ __device__ __forceinline__ void fwd_pass(u64* lds_raw, int s0, Tw<NARROW> tw, wo
       for (int r = 0; r < R; ++r) {
         if (r & half) continue;
         const int ti = m + (blk << u) + (r >> (K - u));
-        const W x = v[r];
-        const W y = A::mulc(v[r + half], tw.w[ti], tw.sh[ti], q);
+        const W x = A::fwd_x(v[r], q);
+        const W y = A::mulc(v[r + half], tw.w[ti], CLS == CLS_F64 ? W(0) : tw.sh[ti], q);
         v[r] = A::add(x, y, q);
         v[r + half] = A::sub(x, y, q);
       }
@@ -142,10 +237,10 @@ __device__ __forceinline__ void fwd_pass(u64* lds_raw, int s0, Tw<NARROW> tw, wo
 }
 
 // One inverse pass: stages s0+K-1 down to s0.
-template <int LOGN, int K, bool NARROW>
-__device__ __forceinline__ void inv_pass(u64* lds_raw, int s0, Tw<NARROW> tw, word_t<NARROW> q, int tid) {
-  typedef word_t<NARROW> W;
-  typedef Arith<NARROW> A;
+template <int LOGN, int K, int CLS>
+__device__ __forceinline__ void inv_pass(u64* lds_raw, int s0, Tw<CLS> tw, MV<CLS> q, int tid) {
+  typedef word_t<CLS> W;
+  typedef Arith<CLS> A;
   W* lds = reinterpret_cast<W*>(lds_raw);
   constexpr int N = 1 << LOGN;
   constexpr int R = 1 << K;
@@ -173,8 +268,8 @@ __device__ __forceinline__ void inv_pass(u64* lds_raw, int s0, Tw<NARROW> tw, wo
         const int ti = m + (blk << u) + (r >> (K - u));
         const W x = v[r];
         const W y = v[r + half];
-        v[r] = A::add(x, y, q);
-        v[r + half] = A::mulc(A::sub(x, y, q), tw.w[ti], tw.sh[ti], q);
+        v[r] = A::add_inv(x, y, q);
+        v[r + half] = A::mulc(A::sub_inv(x, y, q), tw.w[ti], CLS == CLS_F64 ? W(0) : tw.sh[ti], q);
       }
     }
 #pragma unroll
@@ -183,36 +278,36 @@ __device__ __forceinline__ void inv_pass(u64* lds_raw, int s0, Tw<NARROW> tw, wo
 }
 
 // Forward transform of the limb held in LDS (all threads of the workgroup).
-template <int LOGN, bool NARROW>
-__device__ __forceinline__ void ntt_fwd_lds(u64* lds, Tw<NARROW> tw, word_t<NARROW> q, int tid) {
+template <int LOGN, int CLS>
+__device__ __forceinline__ void ntt_fwd_lds(u64* lds, Tw<CLS> tw, MV<CLS> q, int tid) {
   constexpr int FULL = LOGN / 4;
   constexpr int REM = LOGN % 4;
   __syncthreads();
 #pragma unroll
   for (int p = 0; p < FULL; ++p) {
-    fwd_pass<LOGN, 4, NARROW>(lds, 4 * p, tw, q, tid);
+    fwd_pass<LOGN, 4, CLS>(lds, 4 * p, tw, q, tid);
     __syncthreads();
   }
   if constexpr (REM > 0) {
-    fwd_pass<LOGN, REM, NARROW>(lds, 4 * FULL, tw, q, tid);
+    fwd_pass<LOGN, REM, CLS>(lds, 4 * FULL, tw, q, tid);
     __syncthreads();
   }
 }
 
 // Inverse transform of the limb held in LDS, without the N^-1 factor (the
 // caller folds it into its store).
-template <int LOGN, bool NARROW>
-__device__ __forceinline__ void ntt_inv_lds(u64* lds, Tw<NARROW> tw, word_t<NARROW> q, int tid) {
+template <int LOGN, int CLS>
+__device__ __forceinline__ void ntt_inv_lds(u64* lds, Tw<CLS> tw, MV<CLS> q, int tid) {
   constexpr int FULL = LOGN / 4;
   constexpr int REM = LOGN % 4;
   __syncthreads();
   if constexpr (REM > 0) {
-    inv_pass<LOGN, REM, NARROW>(lds, 4 * FULL, tw, q, tid);
+    inv_pass<LOGN, REM, CLS>(lds, 4 * FULL, tw, q, tid);
     __syncthreads();
   }
 #pragma unroll
   for (int p = FULL - 1; p >= 0; --p) {
-    inv_pass<LOGN, 4, NARROW>(lds, 4 * p, tw, q, tid);
+    inv_pass<LOGN, 4, CLS>(lds, 4 * p, tw, q, tid);
     __syncthreads();
   }
 }

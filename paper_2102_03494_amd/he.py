@@ -132,6 +132,15 @@ class HEContext:
     def workspace_need(self, count: int, level: int) -> int:
         return int(self.lib.he_ctx_workspace_need(self.h, count, level))
 
+    def set_tuning(self, knob: str, level: int, value: int):
+        self._check(self.lib.he_ctx_set_tuning(self.h, knob.encode(), level, value), "he_ctx_set_tuning")
+
+    def get_tuning(self, knob: str, level: int) -> int:
+        v = int(self.lib.he_ctx_get_tuning(self.h, knob.encode(), level))
+        if v < 0:
+            self._check(v, "he_ctx_get_tuning")
+        return v
+
     def empty_ct(self, count: int, level: int) -> torch.Tensor:
         return torch.empty((count, 2, level, self.n), dtype=torch.int64, device="cuda")
 

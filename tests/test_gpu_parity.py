@@ -64,6 +64,7 @@ SMALL = dict(n=1024, q_bits=(30, 30, 30, 30), p_bits=40)
 
 @pytest.mark.parametrize("n,q_bits,p_bits", [
     (1024, (30, 30, 30), 36), (4096, (30, 30), 36), (8192, (30, 30, 30, 30), 40), (16384, (40,) * 6, 60),
+    (2048, (42, 41), 40),  # f64 class at its largest primes (2^42 limit)
 ])
 def test_ntt_intt_bit_exact(n, q_bits, p_bits):
     p = P.Params(n, q_bits, p_bits, 1.0)
@@ -124,6 +125,25 @@ def test_rotate_batch_bit_exact():
     d = _dev(low)
     gctx.rotate(he.Ct(d, p.scale), 3, out=d)
     assert np.array_equal(_host(d), S.rotate(p, octx, S.Ciphertext(low, p.scale), 3).c)
+
+
+def test_p_groups_do_not_change_bits():
+    """Every split of the P target's digits (1..4 groups) gives the oracle's bits."""
+    p, octx, gctx, cl = _small_setup(rotations=(5,))
+    batch = _enc_batch(octx, p, 3)
+    want = S.rotate(p, octx, S.Ciphertext(batch, p.scale), 5).c
+    he = _he()
+    default = gctx.get_tuning("p_groups", 4)
+    assert 1 <= default <= 4
+    for pg in (1, 2, 3, 4):
+        gctx.set_tuning("p_groups", 4, pg)
+        assert gctx.get_tuning("p_groups", 4) == pg
+        got = _host(gctx.rotate(he.Ct(_dev(batch), p.scale), 5).data)
+        assert np.array_equal(got, want), pg
+    gctx.set_tuning("p_groups", 4, 0)
+    assert gctx.get_tuning("p_groups", 4) == default
+    with pytest.raises(he.HEError):
+        gctx.set_tuning("p_groups", 4, 5)
 
 
 def test_rotate_hoisted_bit_exact():
