@@ -176,6 +176,152 @@ def hoisted_section(torch, steps: int):
     }
 
 
+def batched_layers_section(torch, ctx, client, n_layers: int, reps: int):
+    """n_layers independent FFConv layers of the timed workload's shape (each
+    with its own seeded image, W1 and W2), three ways: n_layers sequential
+    ffconv_layer calls, one ffconv_layer_batch call, and that call captured
+    once in a HIP graph and replayed."""
+    import numpy as np
+
+    import synth
+    from paper_2102_03494_amd import layers as Ly
+    from paper_2102_03494_amd.he import Ct
+
+    geom = Ly.Geometry(28, 28, 1, 5, 2, 0)
+    level = len(Q_BITS)
+    steps = Ly.rot_steps(ctx)
+    desc = ctx.conv_desc(28, 28, 1, 5, 2, 0, 2, len(steps))
+    pts = Ly.pt_scale_for(ctx, level, SCALE, SCALE)
+    y_scale = SCALE * pts / ctx.q[level - 1]
+    ms = Ly.mask_scale_for(ctx, level - 1, y_scale, Ly.pre_square_target(ctx, level - 2, SCALE), K_BITS)
+    mask = Ly.onehot_mask(client, level - 1, ms)
+    xs, filts, tabs, w1s, w2s, imgs = [], [], [], [], [], []
+    for li in range(n_layers):
+        x = synth.image(WORKLOAD, (28, 28, 1), index=1000 + li)
+        w1 = synth.weights(WORKLOAD, 1000 + 2 * li, (5, 5, 1, 2), 0.1)
+        w2 = synth.weights(WORKLOAD, 1001 + 2 * li, (2, 5), 0.1)
+        xs.append(client.encrypt(Ly.densepack_layout(x, geom, N // 2)[0], level, SCALE, index=1000 + li).data[0])
+        filts.append(Ly.encode_filters(client, w1, geom, level, pts))
+        tabs.append(ctx.int_weight_table(w2, K_BITS, level - 1))
+        imgs.append(x)
+        w1s.append(w1)
+        w2s.append(w2)
+    xs = torch.stack(xs).contiguous()
+    filts = torch.stack(filts).contiguous()
+    tabs = torch.stack(tabs).contiguous()
+    ctx.reserve(ctx.ffconv_workspace_need(n_layers, level, desc, 5, True))
+    out = torch.empty((n_layers, 5, 2, level - 3, N), dtype=torch.int64, device="cuda")
+    print(f"# batched layers: {n_layers} layers set up", file=sys.stderr, flush=True)
+
+    def sequential():
+        for li in range(n_layers):
+            ctx.ffconv_layer(Ct(xs[li:li + 1], SCALE), desc, filts[li], pts, mask, ms, w2s[li], K_BITS, True,
+                             out=out[li])
+
+    def batched():
+        return ctx.ffconv_layer_batch(xs, SCALE, desc, filts, pts, mask, ms, tabs, 5, K_BITS, True, out=out)
+
+    t_seq, _ = timed(sequential, 1, 1, torch)
+    seq_bits = out.cpu().clone()
+    t_bat, z = timed(batched, reps, 1, torch)
+    bat_bits = out.cpu().clone()
+    graph, _ = ctx.capture(batched)
+    out.zero_()
+    t_gr, _ = timed(graph.launch, reps, 1, torch)
+    gr_bits = out.cpu().clone()
+    graph.close()
+    same = bool(torch.equal(seq_bits, bat_bits) and torch.equal(bat_bits, gr_bits))
+    err = 0.0
+    for li in (0, n_layers // 2, n_layers - 1):
+        ref = (Ly.reference_conv2d(imgs[li], w1s[li], 2, 0) @ w2s[li]) ** 2
+        for o in range(5):
+            v = client.decrypt(out[li, o], z.scale, geom.spatial, limbs=1)
+            err = max(err, float(np.abs(v - ref[:, :, o].ravel()).max()))
+    rot = n_layers * 288 * 12
+    return {
+        "workload": f"{n_layers} independent FFConv layers 28x28x1, 5x5 s2 1->2 + 1x1 2->5 + x^2, N=8192, "
+                    "each with its own seeded image, W1 and W2",
+        "sequential_ms_per_layer": t_seq * 1e3 / n_layers,
+        "batched_ms_per_layer": t_bat * 1e3 / n_layers,
+        "graph_ms_per_layer": t_gr * 1e3 / n_layers,
+        "graph_rotations_per_s": rot / t_gr,
+        "speedup_graph_vs_sequential": t_seq / t_gr,
+        "outputs_identical_sequential_batched_graph": same,
+        "decrypted_max_abs_err_sampled_layers": err,
+        "p_groups": ctx.get_tuning("p_groups", level),
+    }
+
+
+def ragged_section(torch, reps: int):
+    """64 ciphertexts at N = 16384 (6 x 40-bit + 60-bit P), ciphertext i at
+    level 2 + (i mod 5): one batched MulPC, one batched rescale and the 13
+    rotate-and-add steps (each one batched key switch over all 64, every item
+    at its own level), against the same work issued per ciphertext."""
+    import numpy as np
+
+    import synth
+    from paper_2102_03494_amd.client import Client
+    from paper_2102_03494_amd.he import Ct, HEContext
+
+    wl = "batched_n16384"
+    n = 16384
+    ctx = HEContext(n, (40,) * 6, 60)
+    ctx.reserve(4 << 30)
+    cl = Client(ctx, wl)
+    r_steps = 13
+    cl.gen_rotation_keys([1 << j for j in range(r_steps)])
+    levels = [2 + (i % 5) for i in range(64)]
+    msgs = [synth.message(wl, n // 2, index=100 + i) for i in range(64)]
+    cts = [cl.encrypt(msgs[i], levels[i], 2.0**30, index=100 + i).data[0] for i in range(64)]
+    pts = [cl.encode(synth.message(wl, n // 2, index=300 + i), levels[i], 2.0**30) for i in range(64)]
+    prod = [torch.empty_like(c) for c in cts]
+    resc = [torch.empty((2, lv - 1, n), dtype=torch.int64, device="cuda") for lv in levels]
+    acc = [c.clone() for c in cts]
+
+    def b_mul():
+        ctx.batch_mul_plain(prod, cts, pts)
+
+    def u_mul():
+        for i in range(64):
+            ctx.batch_mul_plain(prod[i:i + 1], cts[i:i + 1], pts[i:i + 1])
+
+    def b_resc():
+        ctx.batch_rescale(resc, prod)
+
+    def u_resc():
+        for i in range(64):
+            ctx.batch_rescale(resc[i:i + 1], prod[i:i + 1])
+
+    def b_rot():
+        for j in range(r_steps):
+            ctx.batch_rotate(acc, acc, [1 << j] * 64, accumulate=True)
+
+    def u_rot():
+        for j in range(r_steps):
+            for i in range(64):
+                ctx.batch_rotate(acc[i:i + 1], acc[i:i + 1], [1 << j], accumulate=True)
+
+    res = {}
+    for name, fb, fu in (("mulpc", b_mul, u_mul), ("rescale", b_resc, u_resc), ("rotate_and_sum", b_rot, u_rot)):
+        tb, _ = timed(fb, reps, 1, torch)
+        tu, _ = timed(fu, reps, 1, torch)
+        res[name] = {"batched_ms": tb * 1e3, "per_ciphertext_ms": tu * 1e3, "speedup": tu / tb}
+    res["rotate_and_sum"]["rotations_per_s"] = 64 * r_steps / (res["rotate_and_sum"]["batched_ms"] * 1e-3)
+    # check: rotate-and-sum of a fresh copy sums all slots
+    for i in (0, 1, 4):
+        acc[i].copy_(cts[i])
+    for j in range(r_steps):
+        ctx.batch_rotate(acc[:5], acc[:5], [1 << j] * 5, accumulate=True)
+    err = 0.0
+    for i in (0, 1, 4):
+        v = cl.decrypt(acc[i], 2.0**30, 4)
+        err = max(err, float(np.abs(v - msgs[i].sum()).max()))
+    res["workload"] = ("64 ciphertexts, N=16384 (6x40-bit + 60-bit P), levels 2 + (i mod 5); MulPC, rescale and "
+                       "13 rotate-and-add steps, each one batched launch chain over all 64 vs per-ciphertext calls")
+    res["rotate_and_sum_decrypted_max_abs_err"] = err
+    return res
+
+
 def cpu_baseline(x, w1, n_outputs: int):
     """The oracle's DensePack dot products (HMA + 12 rotate-and-add + rescale)
     on a sample of W1 outputs of the same workload, single process."""
@@ -208,6 +354,9 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=4)
     ap.add_argument("--cpu-sample", type=int, default=12, help="oracle dot products timed (0 = skip)")
     ap.add_argument("--no-hoisted", action="store_true", help="skip the N=16384 hoisted-rotation section")
+    ap.add_argument("--batched-layers", type=int, default=128,
+                    help="independent layers in the batched/graph section (0 = skip)")
+    ap.add_argument("--no-ragged", action="store_true", help="skip the ragged 64-ciphertext batch section")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -310,12 +459,23 @@ def main():
         "hbm_gbs_algorithmic": bytes_layer / launches_layer / (avg_ms * 1e-3) / 1e9,
     }
 
+    batched = None
+    if args.batched_layers > 0:
+        print("# batched layers and graph", file=sys.stderr, flush=True)
+        batched = batched_layers_section(torch, ctx, client, args.batched_layers, max(1, min(args.steps, 3)))
+
     hoisted = None
     if not args.no_hoisted:
         del ctx, client
         torch.cuda.empty_cache()
         print("# hoisted rotations at N=16384", file=sys.stderr, flush=True)
         hoisted = hoisted_section(torch, max(1, min(args.steps, 5)))
+
+    ragged = None
+    if not args.no_ragged:
+        torch.cuda.empty_cache()
+        print("# ragged batch at N=16384", file=sys.stderr, flush=True)
+        ragged = ragged_section(torch, max(1, min(args.steps, 3)))
 
     cpu = None
     if args.cpu_sample > 0:
@@ -347,6 +507,8 @@ def main():
         "counts_plain_conv": counts_pl,
         "decrypted_max_abs_err": {"ffconv": err_ff, "plain": err_pl},
         "roofline": roofline,
+        "batched_layers_graph": batched,
+        "ragged_batch": ragged,
         "hoisted_rotations": hoisted,
         "cpu_baseline": cpu,
     }

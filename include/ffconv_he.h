@@ -274,6 +274,56 @@ int ffconv_layer(he_ctx *ctx, const uint64_t *d_in, int level, const he_conv_des
                  const uint64_t *d_w1_filt, const uint64_t *d_mask, const double *h_w2, int o_c2,
                  int k_bits, int square, uint64_t *d_out, void *stream);
 
+/* he_int_weight_table: the exact integer weights round-half-away(h_w[i] *
+ * 2^k_bits), i < count, as residues for limbs < level followed by their
+ * Shoup companions, written to caller-owned device memory d_tab
+ * (2 * count * level uint64, laid out [2][count][level]).  The 1x1 ConvPack
+ * weights of ffconv_layer_batch (W2 of one layer, count = r * o_c2, row-major
+ * [r][o_c2], at level - 1) use this form.  Copies through pinned host memory
+ * on `stream`; not capturable in a graph. */
+int he_int_weight_table(he_ctx *ctx, const double *h_w, int count, int k_bits, int level, uint64_t *d_tab,
+                        void *stream);
+
+/* ffconv_layer_batch: n_layers independent FFConv layers of one geometry
+ * (batched serving, and Sec. 4's layer run many times), as ffconv_layer on
+ * each, with every key switch batched over all layers' ciphertexts (one
+ * Galois key read per rotate-and-add step for all of them).  Layer l reads
+ * its input ciphertext at d_in + l * in_stride, its W1 base filters at
+ * d_w1_filt + l * filt_stride and its W2 table (he_int_weight_table) at
+ * d_w2_tab + l * 2 * r * o_c2 * (level - 1) (strides in uint64); the mask is
+ * shared.  d_out: [n_layers][o_c2][2][..][N].  n_layers * max(r, o_c2) <=
+ * 65535.  Makes no host-to-device copies, so it can be captured in a graph.
+ * Workspace: he_ffconv_workspace_need. */
+int ffconv_layer_batch(he_ctx *ctx, int n_layers, const uint64_t *d_in, size_t in_stride, int level,
+                       const he_conv_desc *desc, const uint64_t *d_w1_filt, size_t filt_stride,
+                       const uint64_t *d_mask, const uint64_t *d_w2_tab, int o_c2, int square, uint64_t *d_out,
+                       void *stream);
+
+/* Workspace bytes ffconv_layer / ffconv_layer_batch need for n_layers layers
+ * (0 on bad arguments); the batch runs in a smaller workspace too, in more
+ * chunks, down to one ciphertext's temporaries. */
+size_t he_ffconv_workspace_need(const he_ctx *ctx, int n_layers, int level, const he_conv_desc *desc, int o_c2,
+                                int square);
+
+/* ---- graphs (HIP graphs instead of per-call launches) ---------------------
+ * he_graph_begin starts capturing `stream` (a non-default stream; thread-local
+ * capture mode); the library calls made on it until he_graph_end are
+ * recorded, not run, and he_graph_end instantiates them.  he_graph_launch
+ * replays the whole recorded sequence on `stream` in one launch, with the
+ * same device pointers (inputs, outputs, workspace, keys): write new inputs
+ * into the same buffers between replays.  It returns HE_EINVAL if the
+ * workspace was reallocated or keys were dropped since the capture.
+ * Calls that copy host tables (he_int_weight_table, ffconv_layer with host
+ * W2, he_batch_*), reserve, key generation and key dropping fail with
+ * HE_EUNSUPPORTED while capturing.  Replays of one graph must not overlap
+ * with each other or with other calls on the context (they share its
+ * workspace). */
+typedef struct he_graph he_graph;
+int he_graph_begin(he_ctx *ctx, void *stream);
+int he_graph_end(he_ctx *ctx, void *stream, he_graph **out);
+int he_graph_launch(he_graph *graph, void *stream);
+int he_graph_destroy(he_graph *graph);
+
 /* Executed operation counters of the last layer call (he_conv_densepack,
  * he_conv_convpack, ffconv_layer): MulPC, AddCC, Rot, rescaled ciphertexts,
  * squares, integer-scalar products. */

@@ -77,6 +77,14 @@ SIGNATURES = {
     "he_conv_densepack": (I, [P, P, I, ctypes.POINTER(HeConvDesc), P, P, P]),
     "he_conv_convpack": (I, [P, P, I, I, DP, I, ctypes.c_double, P, P]),
     "ffconv_layer": (I, [P, P, I, ctypes.POINTER(HeConvDesc), P, P, DP, I, I, I, P, P]),
+    "he_int_weight_table": (I, [P, DP, I, I, I, P, P]),
+    "ffconv_layer_batch": (I, [P, I, P, ctypes.c_size_t, I, ctypes.POINTER(HeConvDesc), P, ctypes.c_size_t, P, P,
+                               I, I, P, P]),
+    "he_ffconv_workspace_need": (ctypes.c_size_t, [P, I, I, ctypes.POINTER(HeConvDesc), I, I]),
+    "he_graph_begin": (I, [P, P]),
+    "he_graph_end": (I, [P, P, ctypes.POINTER(P)]),
+    "he_graph_launch": (I, [P, P]),
+    "he_graph_destroy": (I, [P]),
     "he_last_counts": (I, [P, ctypes.POINTER(HeCounts)]),
     "he_prof_select": (I, [P, ctypes.c_char_p]),
     "he_prof_read": (I, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),

@@ -55,6 +55,17 @@ struct he_ctx {
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   StageSlot stage[STAGE_SLOTS];
   int stage_next = 0;
+  // graph capture: set between he_graph_begin and he_graph_end; epoch counts
+  // changes that move memory a captured graph refers to (workspace, keys)
+  bool capturing = false;
+  uint64_t epoch = 0;
+};
+
+struct he_graph {
+  he_ctx* ctx = nullptr;
+  uint64_t epoch = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -96,7 +107,7 @@ struct Prof {
   hipStream_t s;
   hipEvent_t a = nullptr;
   Prof(he_ctx* ctx, const char* name, hipStream_t st) : c(ctx), s(st) {
-    if (!c->prof_kernel.empty() && c->prof_kernel == name) {
+    if (!c->capturing && !c->prof_kernel.empty() && c->prof_kernel == name) {
       a = prof_event(c);
       if (a) (void)hipEventRecord(a, s);
     }
@@ -148,6 +159,9 @@ int dispatch_logn(int logn, A&&... args) {
 // Copies `bytes` from host to device memory `dst` on stream s through a ring
 // of pinned buffers; a slot is reused only after its previous copy finished.
 int upload(he_ctx* c, void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (c->capturing)
+    return fail(c, HE_EUNSUPPORTED, "this call copies host tables and cannot be captured in a graph "
+                                    "(use the device-table form, e.g. ffconv_layer_batch)");
   StageSlot& st = c->stage[c->stage_next];
   c->stage_next = (c->stage_next + 1) % STAGE_SLOTS;
   if (st.pending) {
@@ -495,20 +509,28 @@ bool build_geom(he_ctx* c, const he_conv_desc* d, DPGeom& g, int& n_cls) {
   ranges(g.out_h, d->h, g.row_cls, g.n_row_cls);
   ranges(g.out_w, d->w, g.col_cls, g.n_col_cls);
   n_cls = g.n_row_cls * g.n_col_cls;
+  g.per_layer = g.out_h * g.out_w * g.o_c;
+  g.x_stride = g.f_stride = 0;
   return true;
 }
 
 // DensePack conv (HMA + rotate-and-sum + rescale) into d_out, chunked over
 // outputs so that any workspace holding one output's temporaries works.
+// n_layers independent layers of one geometry: layer l reads its input at
+// d_in + l x_stride and its filters at d_filt + l f_stride; the outputs of
+// all layers are one batch (layer-major) for every key switch.
 int densepack_run(he_ctx* c, const u64* d_in, int level, const he_conv_desc* desc, const u64* d_filt, u64* d_out,
-                  Arena& ar, hipStream_t s) {
+                  Arena& ar, hipStream_t s, int n_layers = 1, size_t x_stride = 0, size_t f_stride = 0) {
   DPGeom geo;
   int n_cls = 0;
   if (!build_geom(c, desc, geo, n_cls)) return fail(c, HE_EINVAL, "bad convolution geometry");
   if (level < 2 || level > c->big_l) return fail(c, HE_ELEVEL, "DensePack needs 2 <= level <= L (got %d)", level);
   const int n = c->n;
   const int spatial = geo.out_h * geo.out_w;
-  const int total = spatial * geo.o_c;
+  if ((long long)n_layers * geo.per_layer > (1ll << 30)) return fail(c, HE_EINVAL, "too many outputs");
+  geo.x_stride = x_stride;
+  geo.f_stride = f_stride;
+  const int total = spatial * geo.o_c * n_layers;
   for (int j = 0; j < desc->r_steps; ++j) {
     u32 g = galois_of(1 << j, n);
     if (g != 1 && !c->keys.count((int)g)) return fail(c, HE_ENOKEY, "missing rotation key for step %d", 1 << j);
@@ -558,7 +580,21 @@ int64_t round_half_away(double x) {
   return (int64_t)(x < 0 ? -r : r);
 }
 
-// out[o] = sum_k w[k][o] * in[k] for integer weights (no rescale).
+// out[l][o] = sum_k w_l[k][o] * in[l][k] for integer weights (no rescale),
+// n_layers independent layers: layer l reads K ciphertexts at in + l in_stride
+// and its device table (scalar_table layout, 2 K o_c level u64) at
+// d_tab + l 2 K o_c level.
+int scalar_mac_dev(he_ctx* c, u64* out, const u64* in, int k, const u64* d_tab, int o_c, int level, int n_layers,
+                   size_t in_stride, hipStream_t s) {
+  if ((long long)n_layers * o_c > 65535) return fail(c, HE_EINVAL, "too many output ciphertexts for one launch");
+  const size_t tab = (size_t)k * o_c * level;
+  Prof pr(c, "scalar_mac", s);
+  k_scalar_mac<<<dim3(c->n / 256, level, n_layers * o_c), 256, 0, s>>>(out, in, k, o_c, d_tab, d_tab + tab, level,
+                                                                       c->n, in_stride, 2 * tab, c->mods);
+  return check_launch(c, "scalar_mac");
+}
+
+// out[o] = sum_k w[k][o] * in[k] for host integer weights (no rescale).
 int scalar_mac(he_ctx* c, u64* out, const u64* in, int k, const std::vector<int64_t>& w, int o_c, int level,
                Arena& ar, hipStream_t s) {
   std::vector<u64> tab = scalar_table(c, w, level);
@@ -566,10 +602,7 @@ int scalar_mac(he_ctx* c, u64* out, const u64* in, int k, const std::vector<int6
   if (!d_tab) return fail(c, HE_ENOMEM, "workspace too small for weight table");
   int e = upload(c, d_tab, tab.data(), tab.size() * 8, s);
   if (e) return e;
-  Prof pr(c, "scalar_mac", s);
-  k_scalar_mac<<<dim3(c->n / 256, level, o_c), 256, 0, s>>>(out, in, k, o_c, d_tab, d_tab + w.size() * level, level,
-                                                            c->n, c->mods);
-  return check_launch(c, "scalar_mac");
+  return scalar_mac_dev(c, out, in, k, d_tab, o_c, level, 1, 0, s);
 }
 
 // Ragged rotation batch from host job descriptions (each job its own level,
@@ -597,6 +630,75 @@ int rotate_jobs(he_ctx* c, std::vector<KsJob>& jobs, int epi, Arena& ar, hipStre
                          (const u64*)ks.u, (const u64*)ks.rc, s);
   }
   return check_launch(c, "batched rotation");
+}
+
+// Workspace bytes of an FFConv run over n_layers layers (layer buffers plus
+// the DensePack chunk temporaries at the largest chunk).
+size_t ffconv_need(const he_ctx* c, int n_layers, int level, int spatial, int r, int o_c2, bool square) {
+  auto al = [](size_t elems) { return ((elems * 8 + 255) & ~(size_t)255); };
+  const size_t n = c->n;
+  const int l1 = level - 1, l2 = level - 2;
+  const size_t total = (size_t)n_layers * r * spatial;
+  size_t need = al(total * 2 * l1 * n) + al((size_t)n_layers * r * 2 * l1 * n) +
+                al((size_t)n_layers * o_c2 * 2 * l1 * n) + (square ? 2 * al((size_t)n_layers * o_c2 * 2 * l2 * n) : 0);
+  const size_t chunk = std::min<size_t>(total, 16000);
+  const int pg = p_groups(c, level);
+  need += al(chunk * 2 * level * n) + chunk * 8 * (ks_elems_per_job(level, pg, n) + 2 * (size_t)n + 128 + 256);
+  return need + ((size_t)64 << 20);
+}
+
+// FFConv over n_layers independent layers of one geometry (layer l: input at
+// d_in + l in_stride, W1 base filters at d_w1 + l f_stride, W2 integer table
+// at d_w2tab + l 2 r o_c2 (level - 1)): W1 DensePack, DP->CP gather with the
+// one-hot mask, 1x1 ConvPack with exact integer weights, rescale, optional
+// square + relinearise + rescale.  Outputs d_out [n_layers][o_c2][2][..][N].
+int ffconv_run(he_ctx* c, int n_layers, const u64* d_in, size_t in_stride, int level, const he_conv_desc* desc,
+               const u64* d_w1, size_t f_stride, const u64* d_mask, const u64* d_w2tab, int o_c2, int square,
+               u64* d_out, Arena& ar, hipStream_t s) {
+  const int need = square ? 4 : 3;
+  if (level < need || level > c->big_l) return fail(c, HE_ELEVEL, "ffconv needs level >= %d (got %d)", need, level);
+  c->counts = he_counts{};
+  DPGeom geo;
+  int n_cls = 0;
+  if (!build_geom(c, desc, geo, n_cls)) return fail(c, HE_EINVAL, "bad convolution geometry");
+  const int n = c->n;
+  const int r = desc->o_c;
+  const int spatial = geo.out_h * geo.out_w;
+  const int l1 = level - 1, l2 = level - 2;
+  if ((long long)n_layers * r > 65535 || (long long)n_layers * o_c2 > 65535)
+    return fail(c, HE_EINVAL, "too many layers for one call");
+  const size_t B = (size_t)n_layers;
+  u64* y = ar.take<u64>(B * r * spatial * 2 * l1 * n);
+  u64* g = ar.take<u64>(B * r * 2 * l1 * n);
+  u64* z = ar.take<u64>(B * o_c2 * 2 * l1 * n);
+  u64* zr = square ? ar.take<u64>(B * o_c2 * 2 * l2 * n) : nullptr;
+  u64* sq = square ? ar.take<u64>(B * o_c2 * 2 * l2 * n) : nullptr;
+  if (!y || !g || !z || (square && (!zr || !sq))) return fail(c, HE_ENOMEM, "workspace too small for the FFConv layer");
+  // 1. W1 under DensePack (HMA, rotate-and-sum, rescale), all layers in one batch
+  int e = densepack_run(c, d_in, level, desc, d_w1, y, ar, s, n_layers, in_stride, f_stride);
+  if (e) return e;
+  // 2. DP->CP gather: G_c = sum_p y_{c,p} * sigma_{5^-p}(E), one accumulator per (layer, c)
+  const u32 g5inv = galois_of(-1, n);  // 5^-1 in the group of odd residues mod 2N
+  dispatch_logn<LHmaPerm>(c->logn, c, g, (const u64*)y, spatial, d_mask, 0, l1, (const int32_t*)nullptr, g5inv, l1, 0,
+                          n_layers * r, s);
+  if ((e = check_launch(c, "gather"))) return e;
+  // 3. 1x1 ConvPack with exact integer weights round(W2 * 2^k)
+  if ((e = scalar_mac_dev(c, z, g, r, d_w2tab, o_c2, l1, n_layers, (size_t)r * 2 * l1 * n, s))) return e;
+  // 4. rescale; 5. optional square + relinearise + rescale
+  const int nz = n_layers * o_c2;
+  if (!square) {
+    e = rescale_batch(c, d_out, z, nz, l1, ar, s);
+  } else {
+    e = rescale_batch(c, zr, z, nz, l1, ar, s);
+    if (!e) e = square_batch(c, sq, zr, nz, l2, ar, s);
+    if (!e) e = rescale_batch(c, d_out, sq, nz, l2, ar, s);
+  }
+  c->counts.mulpc += (int64_t)n_layers * r * spatial;  // gather masks
+  c->counts.addcc += (int64_t)n_layers * (r * (spatial - 1) + o_c2 * (r - 1));
+  c->counts.scalar_mul += (int64_t)n_layers * r * o_c2;
+  c->counts.rescale += (int64_t)nz * (square ? 2 : 1);
+  c->counts.square += square ? nz : 0;
+  return e;
 }
 
 }  // namespace
@@ -705,6 +807,8 @@ int he_ctx_destroy(he_ctx* c) {
 int he_ctx_reserve(he_ctx* c, size_t bytes) {
   if (!c) return HE_EINVAL;
   if (bytes <= c->ws_bytes) return HE_OK;
+  if (c->capturing) return fail(c, HE_EUNSUPPORTED, "he_ctx_reserve: not allowed during graph capture");
+  ++c->epoch;
   (void)hipDeviceSynchronize();
   (void)hipFree(c->ws);
   c->ws = nullptr;
@@ -812,6 +916,7 @@ int he_rescale(he_ctx* c, uint64_t* out, const uint64_t* in, int count, int leve
 int he_keygen_switch(he_ctx* c, int32_t galois, const uint64_t* d_s, const uint64_t* d_a, const int64_t* d_e,
                      void* stream) {
   if (!c || !d_s || !d_a || !d_e) return fail(c, HE_EINVAL, "he_keygen_switch: null argument");
+  if (c->capturing) return fail(c, HE_EUNSUPPORTED, "he_keygen_switch: not allowed during graph capture");
   if (galois != 0 && (galois < 1 || galois >= 2 * c->n || !(galois & 1)))
     return fail(c, HE_EINVAL, "he_keygen_switch: bad Galois element %d", galois);
   const int L = c->big_l;
@@ -853,6 +958,8 @@ int he_has_key(const he_ctx* c, int32_t galois) { return c && c->keys.count(galo
 
 int he_drop_keys(he_ctx* c) {
   if (!c) return HE_EINVAL;
+  if (c->capturing) return fail(c, HE_EUNSUPPORTED, "he_drop_keys: not allowed during graph capture");
+  ++c->epoch;
   (void)hipDeviceSynchronize();
   for (auto& kv : c->keys) (void)hipFree(kv.second);
   c->keys.clear();
@@ -1110,51 +1217,103 @@ int ffconv_layer(he_ctx* c, const uint64_t* d_in, int level, const he_conv_desc*
                  void* stream) {
   if (!c || !d_in || !desc || !d_w1_filt || !d_mask || !h_w2 || !d_out)
     return fail(c, HE_EINVAL, "ffconv_layer: null argument");
-  const int need = square ? 4 : 3;
-  if (level < need || level > c->big_l) return fail(c, HE_ELEVEL, "ffconv_layer needs level >= %d (got %d)", need, level);
-  if (o_c2 < 1 || k_bits < 0 || k_bits > 40) return fail(c, HE_EINVAL, "ffconv_layer: bad W2 shape or k_bits");
-  c->counts = he_counts{};
+  if (o_c2 < 1 || k_bits < 0 || k_bits > 40 || desc->o_c < 1) return fail(c, HE_EINVAL, "ffconv_layer: bad W2 shape or k_bits");
+  if (level < 3 || level > c->big_l) return fail(c, HE_ELEVEL, "ffconv_layer needs level >= 3 (got %d)", level);
+  std::vector<int64_t> w((size_t)desc->o_c * o_c2);
+  for (size_t i = 0; i < w.size(); ++i) w[i] = round_half_away(std::ldexp(h_w2[i], k_bits));
+  std::vector<u64> tab = scalar_table(c, w, level - 1);
+  Arena ar(c);
+  u64* d_tab = ar.take<u64>(tab.size());
+  if (!d_tab) return fail(c, HE_ENOMEM, "workspace too small for ffconv_layer");
+  hipStream_t s = S(stream);
+  int e = upload(c, d_tab, tab.data(), tab.size() * 8, s);
+  if (e) return e;
+  return ffconv_run(c, 1, d_in, 0, level, desc, d_w1_filt, 0, d_mask, d_tab, o_c2, square, d_out, ar, s);
+}
+
+int he_int_weight_table(he_ctx* c, const double* h_w, int count, int k_bits, int level, uint64_t* d_tab,
+                        void* stream) {
+  if (!c || !h_w || !d_tab || count < 1 || k_bits < 0 || k_bits > 40 || !level_ok(c, level))
+    return fail(c, HE_EINVAL, "he_int_weight_table: bad arguments");
+  std::vector<int64_t> w(count);
+  for (int i = 0; i < count; ++i) {
+    const double x = std::ldexp(h_w[i], k_bits);
+    if (!(std::fabs(x) < 4.0e18)) return fail(c, HE_EINVAL, "he_int_weight_table: weight too large");
+    w[i] = round_half_away(x);
+  }
+  std::vector<u64> tab = scalar_table(c, w, level);
+  return upload(c, d_tab, tab.data(), tab.size() * 8, S(stream));
+}
+
+int ffconv_layer_batch(he_ctx* c, int n_layers, const uint64_t* d_in, size_t in_stride, int level,
+                       const he_conv_desc* desc, const uint64_t* d_w1_filt, size_t filt_stride, const uint64_t* d_mask,
+                       const uint64_t* d_w2_tab, int o_c2, int square, uint64_t* d_out, void* stream) {
+  if (!c || !d_in || !desc || !d_w1_filt || !d_mask || !d_w2_tab || !d_out || n_layers < 1)
+    return fail(c, HE_EINVAL, "ffconv_layer_batch: bad arguments");
+  if (o_c2 < 1 || desc->o_c < 1) return fail(c, HE_EINVAL, "ffconv_layer_batch: bad W2 shape");
+  if (level < 3 || level > c->big_l) return fail(c, HE_ELEVEL, "ffconv_layer_batch needs level >= 3 (got %d)", level);
+  Arena ar(c);
+  return ffconv_run(c, n_layers, d_in, in_stride, level, desc, d_w1_filt, filt_stride, d_mask, d_w2_tab, o_c2, square,
+                    d_out, ar, S(stream));
+}
+
+size_t he_ffconv_workspace_need(const he_ctx* c, int n_layers, int level, const he_conv_desc* desc, int o_c2,
+                                int square) {
   DPGeom geo;
   int n_cls = 0;
-  if (!build_geom(c, desc, geo, n_cls)) return fail(c, HE_EINVAL, "bad convolution geometry");
-  const int n = c->n;
-  const int r = desc->o_c;
-  const int spatial = geo.out_h * geo.out_w;
-  const int l1 = level - 1, l2 = level - 2;
-  hipStream_t s = S(stream);
-  Arena ar(c);
-  u64* y = ar.take<u64>((size_t)r * spatial * 2 * l1 * n);
-  u64* g = ar.take<u64>((size_t)r * 2 * l1 * n);
-  u64* z = ar.take<u64>((size_t)o_c2 * 2 * l1 * n);
-  u64* zr = square ? ar.take<u64>((size_t)o_c2 * 2 * l2 * n) : nullptr;
-  u64* sq = square ? ar.take<u64>((size_t)o_c2 * 2 * l2 * n) : nullptr;
-  if (!y || !g || !z || (square && (!zr || !sq))) return fail(c, HE_ENOMEM, "workspace too small for ffconv_layer");
-  // 1. W1 under DensePack (HMA, rotate-and-sum, rescale)
-  int e = densepack_run(c, d_in, level, desc, d_w1_filt, y, ar, s);
-  if (e) return e;
-  // 2. DP->CP gather: G_c = sum_p y_{c,p} * sigma_{5^-p}(E)
-  const u32 g5inv = galois_of(-1, n);  // 5^-1 in the group of odd residues mod 2N
-  dispatch_logn<LHmaPerm>(c->logn, c, g, (const u64*)y, spatial, d_mask, 0, l1, (const int32_t*)nullptr, g5inv, l1, 0,
-                          r, s);
-  if ((e = check_launch(c, "gather"))) return e;
-  // 3. 1x1 ConvPack with exact integer weights round(W2 * 2^k)
-  std::vector<int64_t> w((size_t)r * o_c2);
-  for (size_t i = 0; i < w.size(); ++i) w[i] = round_half_away(std::ldexp(h_w2[i], k_bits));
-  if ((e = scalar_mac(c, z, g, r, w, o_c2, l1, ar, s))) return e;
-  // 4. rescale; 5. optional square + relinearise + rescale
-  if (!square) {
-    e = rescale_batch(c, d_out, z, o_c2, l1, ar, s);
-  } else {
-    e = rescale_batch(c, zr, z, o_c2, l1, ar, s);
-    if (!e) e = square_batch(c, sq, zr, o_c2, l2, ar, s);
-    if (!e) e = rescale_batch(c, d_out, sq, o_c2, l2, ar, s);
+  if (!c || !desc || n_layers < 1 || o_c2 < 1 || level < 3 || level > c->big_l ||
+      !build_geom(const_cast<he_ctx*>(c), desc, geo, n_cls))
+    return 0;
+  return ffconv_need(c, n_layers, level, geo.out_h * geo.out_w, desc->o_c, o_c2, square != 0);
+}
+
+// ---- graphs ---------------------------------------------------------------------
+
+int he_graph_begin(he_ctx* c, void* stream) {
+  if (!c || !stream) return fail(c, HE_EINVAL, "he_graph_begin: needs a context and a non-default stream");
+  if (c->capturing) return fail(c, HE_EINVAL, "he_graph_begin: already capturing");
+  if (hipStreamBeginCapture(S(stream), hipStreamCaptureModeThreadLocal) != hipSuccess)
+    return fail(c, HE_EDEVICE, "he_graph_begin: hipStreamBeginCapture failed");
+  c->capturing = true;
+  return HE_OK;
+}
+
+int he_graph_end(he_ctx* c, void* stream, he_graph** out) {
+  if (!c || !stream || !out) return fail(c, HE_EINVAL, "he_graph_end: bad arguments");
+  *out = nullptr;
+  if (!c->capturing) return fail(c, HE_EINVAL, "he_graph_end: not capturing");
+  c->capturing = false;
+  hipGraph_t g = nullptr;
+  if (hipStreamEndCapture(S(stream), &g) != hipSuccess || !g)
+    return fail(c, HE_EDEVICE, "he_graph_end: capture failed (a call inside it was not capturable)");
+  hipGraphExec_t ex = nullptr;
+  if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(c, HE_EDEVICE, "he_graph_end: instantiation failed");
   }
-  c->counts.mulpc += (int64_t)r * spatial;  // gather masks
-  c->counts.addcc += (int64_t)r * (spatial - 1) + (int64_t)o_c2 * (r - 1);
-  c->counts.scalar_mul += (int64_t)r * o_c2;
-  c->counts.rescale += o_c2 * (square ? 2 : 1);
-  c->counts.square += square ? o_c2 : 0;
-  return e;
+  he_graph* gr = new he_graph();
+  gr->ctx = c;
+  gr->epoch = c->epoch;
+  gr->graph = g;
+  gr->exec = ex;
+  *out = gr;
+  return HE_OK;
+}
+
+int he_graph_launch(he_graph* g, void* stream) {
+  if (!g || !g->ctx) return HE_EINVAL;
+  if (g->epoch != g->ctx->epoch)
+    return fail(g->ctx, HE_EINVAL, "he_graph_launch: workspace or keys changed since the capture");
+  if (hipGraphLaunch(g->exec, S(stream)) != hipSuccess) return fail(g->ctx, HE_EDEVICE, "hipGraphLaunch failed");
+  return HE_OK;
+}
+
+int he_graph_destroy(he_graph* g) {
+  if (!g) return HE_EINVAL;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+  return HE_OK;
 }
 
 int he_prof_select(he_ctx* c, const char* kernel) {

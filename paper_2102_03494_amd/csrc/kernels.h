@@ -707,6 +707,11 @@ struct DPGeom {
   int h, w, c_in, d, stride, pad, o_c;
   int out_h, out_w, n_row_cls, n_col_cls, m_cts;
   int row_cls[64], col_cls[64];  // class id of every output row / column
+  // several independent layers of this geometry in one launch: output index
+  // oi = layer * per_layer + o * S + p; layer l reads x + l x_stride and its
+  // base filters at filt + l f_stride (u64 elements)
+  int per_layer;
+  size_t x_stride, f_stride;
 };
 
 template <int LOGN, bool NARROW>
@@ -717,7 +722,11 @@ __device__ __forceinline__ void dp_hma_body(const u64* __restrict__ x, const u64
   constexpr int N = 1 << LOGN;
   constexpr int T = NttGeom<LOGN>::T;
   const int t = blockIdx.x;
-  const int oi = out_base + (int)blockIdx.y;  // absolute output index o*S + p
+  const int oall = out_base + (int)blockIdx.y;  // absolute output index over all layers
+  const int layer = oall / geo.per_layer;
+  const int oi = oall - layer * geo.per_layer;  // o*S + p within the layer
+  x += (size_t)layer * geo.x_stride;
+  filt += (size_t)layer * geo.f_stride;
   const int spatial = geo.out_h * geo.out_w;
   const int o = oi / spatial;
   const int pidx = oi % spatial;
@@ -801,12 +810,19 @@ __global__ void k_hma_perm(u64* __restrict__ acc, const u64* __restrict__ cts, i
 
 // Integer-scalar MAC (ConvPack, Table II): out[o] = sum_k w[k][o] * in[k],
 // with w given per limb as residues + Shoup companions: wres[(k*o_c + o)*level + t].
+// blockIdx.z = layer * o_c + o over independent layers: layer l reads
+// in + l in_stride and its table at wres / wsh + l tab_stride; out[z].
 __global__ void k_scalar_mac(u64* __restrict__ out, const u64* __restrict__ in, int K, int o_c,
                              const u64* __restrict__ wres, const u64* __restrict__ wsh, int level, int n,
-                             Mods mods) {
+                             size_t in_stride, size_t tab_stride, Mods mods) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int t = blockIdx.y;
-  const size_t o = blockIdx.z;
+  const size_t z = blockIdx.z;
+  const size_t layer = z / o_c;
+  const size_t o = z - layer * o_c;
+  in += layer * in_stride;
+  wres += layer * tab_stride;
+  wsh += layer * tab_stride;
   const ModConst m = mods.m[t];
   u64 s0 = 0, s1 = 0;
   for (int k = 0; k < K; ++k) {
@@ -815,8 +831,8 @@ __global__ void k_scalar_mac(u64* __restrict__ out, const u64* __restrict__ in, 
     s0 = add_mod(s0, mul_shoup(in[(((size_t)k * 2 + 0) * level + t) * n + i], w, ws, m.q, m.narrow), m.q);
     s1 = add_mod(s1, mul_shoup(in[(((size_t)k * 2 + 1) * level + t) * n + i], w, ws, m.q, m.narrow), m.q);
   }
-  out[((o * 2 + 0) * level + t) * n + i] = s0;
-  out[((o * 2 + 1) * level + t) * n + i] = s1;
+  out[((z * 2 + 0) * level + t) * n + i] = s0;
+  out[((z * 2 + 1) * level + t) * n + i] = s1;
 }
 
 // Square tensor: d0 = c0^2, d1 = 2 c0 c1 (both into d01 = [count][2][level][N])

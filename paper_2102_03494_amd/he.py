@@ -67,6 +67,28 @@ class Ct:
         return int(np.prod(self.data.shape[:-3], dtype=np.int64)) if self.data.dim() > 3 else 1
 
 
+class Graph:
+    """An instantiated HIP graph of library calls (HEContext.capture)."""
+
+    def __init__(self, ctx, handle: ctypes.c_void_p):
+        self.ctx = ctx
+        self.h = handle
+
+    def launch(self):
+        self.ctx._check(self.ctx.lib.he_graph_launch(self.h, _stream()), "he_graph_launch")
+
+    def close(self):
+        if self.h:
+            self.ctx.lib.he_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class HEContext:
     def __init__(self, n: int, q_bits, p_bits: int, workspace_bytes: int = 0):
         self.lib = _lib.lib()
@@ -362,3 +384,58 @@ class HEContext:
         if square:
             z_scale = z_scale * z_scale / self.q[level - 3]
         return Ct(out, z_scale)
+
+    def int_weight_table(self, w: np.ndarray, k_bits: int, level: int, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Device table of round(w * 2^k_bits) (row-major w) for limbs < level."""
+        wf = np.ascontiguousarray(np.asarray(w, dtype=np.float64).ravel())
+        if out is None:
+            out = torch.empty((2 * wf.size * level,), dtype=torch.int64, device="cuda")
+        self._check(self.lib.he_int_weight_table(self.h, wf.ctypes.data_as(_lib.DP), wf.size, int(k_bits), level,
+                                                 _ptr(out), _stream()), "he_int_weight_table")
+        return out
+
+    def ffconv_workspace_need(self, n_layers: int, level: int, desc: HeConvDesc, o_c2: int, square: bool) -> int:
+        return int(self.lib.he_ffconv_workspace_need(self.h, n_layers, level, ctypes.byref(desc), o_c2,
+                                                      int(square)))
+
+    def ffconv_layer_batch(self, xs: torch.Tensor, scale: float, desc: HeConvDesc, w1_filts: torch.Tensor,
+                           w1_pt_scale: float, mask: torch.Tensor, mask_scale: float, w2_tabs: torch.Tensor,
+                           o_c2: int, k_bits: int, square: bool, out: torch.Tensor | None = None) -> Ct:
+        """len(xs) independent FFConv layers (inputs xs[l], all at `scale`, with
+        filters w1_filts[l] and W2 tables w2_tabs[l]) in one call."""
+        n_layers = xs.shape[0]
+        level = xs.shape[-2]
+        assert w1_filts.shape[0] == n_layers and w2_tabs.shape[0] == n_layers
+        assert xs.is_contiguous() and w1_filts.is_contiguous() and w2_tabs.is_contiguous()
+        lvl_out = level - 2 - (1 if square else 0)
+        if out is None:
+            out = torch.empty((n_layers, o_c2, 2, lvl_out, self.n), dtype=torch.int64, device="cuda")
+        in_stride = xs[0].numel()
+        f_stride = w1_filts[0].numel()
+        self._check(self.lib.ffconv_layer_batch(self.h, n_layers, _ptr(xs), in_stride, level, ctypes.byref(desc),
+                                                _ptr(w1_filts), f_stride, _ptr(mask), _ptr(w2_tabs), o_c2,
+                                                int(square), _ptr(out), _stream()), "ffconv_layer_batch")
+        y_scale = scale * w1_pt_scale / self.q[level - 1]
+        z_scale = y_scale * mask_scale * 2.0**k_bits / self.q[level - 2]
+        if square:
+            z_scale = z_scale * z_scale / self.q[level - 3]
+        return Ct(out, z_scale)
+
+    def capture(self, fn):
+        """Records the library calls fn() makes into a HIP graph (on a side
+        stream) and returns (Graph, fn's result).  fn must allocate nothing:
+        pass preallocated outputs."""
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        g = ctypes.c_void_p()
+        with torch.cuda.stream(side):
+            self._check(self.lib.he_graph_begin(self.h, _stream()), "he_graph_begin")
+            try:
+                res = fn()
+            except BaseException:
+                if self.lib.he_graph_end(self.h, _stream(), ctypes.byref(g)) == 0 and g:
+                    self.lib.he_graph_destroy(g)
+                raise
+            self._check(self.lib.he_graph_end(self.h, _stream(), ctypes.byref(g)), "he_graph_end")
+        torch.cuda.current_stream().wait_stream(side)
+        return Graph(self, g), res
