@@ -272,6 +272,32 @@ def gather_convpack(params, y: scheme.Ciphertext, spatial: int, w2: np.ndarray, 
     return z, counts
 
 
+def gather_onehot(params, y: scheme.Ciphertext, k: int, mask_pt: np.ndarray, mask_scale: float,
+                  counts: Counts | None = None):
+    """Output arrangement of replicated DensePack outputs (the step Table I
+    leaves uncounted, Sec. 3.2): for each group of k ciphertexts, the sum over
+    j of y_j times the one-hot plaintext E shifted right by j, i.e.
+    sigma_{5^-j}(E); the value of ciphertext j lands in slot j.  y.c holds
+    (groups * k, 2, level, N); returns (groups, 2, level, N), not rescaled."""
+    counts = counts if counts is not None else Counts()
+    level = y.level
+    groups = y.c.shape[0] // k
+    out = []
+    for z in range(groups):
+        acc = None
+        for j in range(k):
+            e = automorph_ntt(mask_pt[:level], galois_for_rotation(-j, params.n))
+            prod = scheme.mul_plain(params, scheme.Ciphertext(y.c[z * k + j], y.scale), e, mask_scale)
+            counts.mulpc += 1
+            if acc is None:
+                acc = prod
+            else:
+                acc = scheme.add(params, acc, prod)
+                counts.addcc += 1
+        out.append(acc.c)
+    return scheme.Ciphertext(np.stack(out), y.scale * mask_scale), counts
+
+
 def convpack(params, cts: scheme.Ciphertext, w: np.ndarray, target_scale: float,
              counts: Counts | None = None):
     """Standalone ConvPack layer (Table II): K input cts, weights (K, O_c) as integers.

@@ -9,7 +9,8 @@
   the shifted input; DensePack with padding (several border classes) and with
   the input split over several ciphertexts; gather + 1x1 ConvPack with an
   identity W2 returns the gathered channels; the full FFConv layer with x^2;
-  the CP->DP combine lays channels out exactly as DensePack does.
+  the CP->DP combine lays channels out exactly as DensePack does; the
+  one-hot arrangement puts replicated value j in slot j and zeros elsewhere.
 """
 import math
 
@@ -186,3 +187,22 @@ def test_combine_cp_to_dp_layout():
     want = C.densepack_slots(tensor, geom_next, p.slots)[0]
     assert np.abs(ctx.decrypt(S.Ciphertext(dense.c[0], dense.scale)) - want).max() < 1e-4
     assert cnt.rot == 2
+
+
+def test_gather_onehot_places_value_j_in_slot_j():
+    n = 256
+    p = P.Params(n, (30, 30), 36, 2.0**25)
+    ctx = Wk.make_context(p, W)
+    k = 10
+    vals = synth.message(W, 2 * k, index=5)
+    reps = np.stack([Wk.encrypt_slots(ctx, np.full(p.slots, v), 2, p.scale, W, 60 + i).c for i, v in enumerate(vals)])
+    ms = p.q[1] * p.scale / p.scale  # the rescale lands back on the input scale
+    mask = C.encode_onehot(p, 2, ms)
+    g, cnt = C.gather_onehot(p, S.Ciphertext(reps, p.scale), k, mask, ms)
+    g = S.rescale(p, g)
+    assert g.c.shape[0] == 2 and cnt.mulpc == 2 * k and cnt.addcc == 2 * (k - 1)
+    for z in range(2):
+        got = ctx.decrypt(S.Ciphertext(g.c[z], g.scale))
+        want = np.zeros(p.slots)
+        want[:k] = vals[z * k:(z + 1) * k]
+        assert np.abs(got - want).max() < 1e-4
