@@ -322,6 +322,28 @@ def ragged_section(torch, reps: int):
     return res
 
 
+def serving_section(window: float, cap: float):
+    """The MNIST-shaped share of the serving stream (Poisson, 200 requests/s,
+    70% MNIST-shaped) over a short window, served by the FFConv net and by the
+    plain-conv comparator net; serial shortest-class-first batching."""
+    from paper_2102_03494_amd import serve
+    out = {}
+    for variant in ("ffconv", "plain"):
+        args = serve.parse_args(["--window", str(window), "--cap", str(cap), "--classes", "mnist",
+                                 "--variant", variant])
+        rep = serve.run(args)
+        c = rep["classes"]["mnist"]
+        out[variant] = {k: c[k] for k in ("offered", "completed", "batches", "deferrals", "p50_latency_s",
+                                          "p99_latency_s")}
+        out[variant].update(makespan_s=rep["makespan_s"], peak_backlog=rep["peak_backlog"],
+                            backlog_at_end=rep["backlog_at_end"], ms_per_request=1e3 * rep["cost_per_request_s"]["mnist"],
+                            decrypted_max_abs_err=rep["decrypted_max_abs_err"]["mnist"])
+    out["workload"] = (f"MNIST-shaped requests of a {window:g} s Poisson window at 200 requests/s (70% MNIST): "
+                       "FFConv 5x5 s2 pad 1 1->2->5 + x^2, combine, FC 845->10 at N=8192, 5x30-bit + 40-bit P; "
+                       "batches of up to 32 requests")
+    return out
+
+
 def cpu_baseline(x, w1, n_outputs: int):
     """The oracle's DensePack dot products (HMA + 12 rotate-and-add + rescale)
     on a sample of W1 outputs of the same workload, single process."""
@@ -357,6 +379,8 @@ def main():
     ap.add_argument("--batched-layers", type=int, default=128,
                     help="independent layers in the batched/graph section (0 = skip)")
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged 64-ciphertext batch section")
+    ap.add_argument("--serve-window", type=float, default=1.0,
+                    help="arrival window (s) of the serving section (0 = skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 3 plain device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -477,6 +501,12 @@ def main():
         print("# ragged batch at N=16384", file=sys.stderr, flush=True)
         ragged = ragged_section(torch, max(1, min(args.steps, 3)))
 
+    serving = None
+    if args.serve_window > 0:
+        torch.cuda.empty_cache()
+        print("# serving section", file=sys.stderr, flush=True)
+        serving = serving_section(args.serve_window, 30.0)
+
     cpu = None
     if args.cpu_sample > 0:
         print("# timing the CPU oracle sample", file=sys.stderr, flush=True)
@@ -509,6 +539,7 @@ def main():
         "roofline": roofline,
         "batched_layers_graph": batched,
         "ragged_batch": ragged,
+        "serving_mnist": serving,
         "hoisted_rotations": hoisted,
         "cpu_baseline": cpu,
     }

@@ -215,6 +215,19 @@ int he_batch_mul_plain(he_ctx *ctx, uint64_t *const *h_outs, const uint64_t *con
  * d_out = [ceil(o_c / B)][2][level][N]. */
 int he_combine_cp_dp(he_ctx *ctx, const uint64_t *d_in, int o_c, int level, int spatial, int per_dense,
                      uint64_t *d_out, void *stream);
+/* The same for `count` independent items in one batched key switch:
+ * d_in [count][o_c][2][level][N] -> d_out [count][ceil(o_c/B)][2][level][N]. */
+int he_combine_cp_dp_batch(he_ctx *ctx, int count, const uint64_t *d_in, int o_c, int level, int spatial,
+                           int per_dense, uint64_t *d_out, void *stream);
+
+/* ---- one-hot gather (the DP->CP step of Table III, and the arrangement of
+ * DensePack's replicated outputs into one DensePack ciphertext) ---------------
+ * d_out[z] = sum_{k < K} d_cts[z*K + k] * sigma_{5^-k}(E) for z < count,
+ * where E = d_mask is a plaintext [level][N] that is one-hot at slot 0:
+ * ciphertext k of each group lands at slot k.  d_cts [count*K][2][level][N],
+ * d_out [count][2][level][N]; K <= N/2.  No rescale. */
+int he_gather_onehot(he_ctx *ctx, int count, const uint64_t *d_cts, int k, const uint64_t *d_mask, int level,
+                     uint64_t *d_out, void *stream);
 
 /* ---- square (the x^2 activation, Section 2.1) ------------------------------
  * d_out[i] = relinearised (c0^2, 2 c0 c1) + KeySwitch(c1^2) under the key for
@@ -252,6 +265,13 @@ typedef struct {
  * ciphertexts at `level` (see he_ctx_workspace_need). */
 int he_conv_densepack(he_ctx *ctx, const uint64_t *d_in, int level, const he_conv_desc *desc,
                       const uint64_t *d_filt, uint64_t *d_out, void *stream);
+/* The same layer on n_layers independent inputs in one batch (every key
+ * switch over all of them): input l at d_in + l * in_stride, its base
+ * filters at d_filt + l * filt_stride (0: one filter set shared by all, as
+ * when many requests run one model); d_out [n_layers * o_c * S][2][level-1][N]. */
+int he_conv_densepack_batch(he_ctx *ctx, int n_layers, const uint64_t *d_in, size_t in_stride, int level,
+                            const he_conv_desc *desc, const uint64_t *d_filt, size_t filt_stride, uint64_t *d_out,
+                            void *stream);
 
 /* he_conv_convpack (Table II): K channel ciphertexts in, O_c out:
  * d_out[o] = rescale(sum_k round-half-away(h_w[k*o_c + o] * w_scale) * d_in[k]).

@@ -81,6 +81,10 @@ SIGNATURES = {
     "ffconv_layer_batch": (I, [P, I, P, ctypes.c_size_t, I, ctypes.POINTER(HeConvDesc), P, ctypes.c_size_t, P, P,
                                I, I, P, P]),
     "he_ffconv_workspace_need": (ctypes.c_size_t, [P, I, I, ctypes.POINTER(HeConvDesc), I, I]),
+    "he_combine_cp_dp_batch": (I, [P, I, P, I, I, I, I, P, P]),
+    "he_gather_onehot": (I, [P, I, P, I, P, I, P, P]),
+    "he_conv_densepack_batch": (I, [P, I, P, ctypes.c_size_t, I, ctypes.POINTER(HeConvDesc), P, ctypes.c_size_t, P,
+                                    P]),
     "he_graph_begin": (I, [P, P]),
     "he_graph_end": (I, [P, P, ctypes.POINTER(P)]),
     "he_graph_launch": (I, [P, P]),

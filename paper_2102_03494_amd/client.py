@@ -47,10 +47,8 @@ class Client:
     # ---- plaintexts -----------------------------------------------------------------
     def encode(self, z, level: int, scale: float) -> torch.Tensor:
         """NTT-domain plaintext [level][N] of real slot values z."""
-        coeffs = torch.from_numpy(self.ctx.encode_coeffs(z, scale)).cuda()
-        pt = self.ctx.from_signed(coeffs, level, 0)
-        self.ctx.ntt(pt.view(1, level, self.ctx.n))
-        return pt
+        from .layers import PlainEncoder
+        return PlainEncoder(self.ctx).encode(z, level, scale)
 
     def encrypt_pt(self, pt: torch.Tensor, scale: float, index: int) -> Ct:
         c = self.ctx

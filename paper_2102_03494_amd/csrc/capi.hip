@@ -1096,18 +1096,21 @@ int he_batch_mul_plain(he_ctx* c, uint64_t* const* h_outs, const uint64_t* const
   return check_launch(c, "he_batch_mul_plain");
 }
 
-int he_combine_cp_dp(he_ctx* c, const uint64_t* d_in, int o_c, int level, int spatial, int per_dense,
-                     uint64_t* d_out, void* stream) {
-  if (!c || !d_in || !d_out || o_c < 1 || spatial < 1 || per_dense < 1 || !level_ok(c, level) ||
+int he_combine_cp_dp_batch(he_ctx* c, int count, const uint64_t* d_in, int o_c, int level, int spatial,
+                           int per_dense, uint64_t* d_out, void* stream) {
+  if (!c || !d_in || !d_out || count < 1 || o_c < 1 || spatial < 1 || per_dense < 1 || !level_ok(c, level) ||
       (long long)per_dense * spatial > c->n / 2)
     return fail(c, HE_EINVAL, "he_combine_cp_dp: bad arguments");
   const int n = c->n;
+  const int n_dense = (o_c + per_dense - 1) / per_dense;
+  if ((long long)count * n_dense > 65535) return fail(c, HE_EINVAL, "he_combine_cp_dp: too many items");
   const size_t cstride = (size_t)2 * level * n;
   hipStream_t s = S(stream);
   Arena ar(c);
-  u64* rot = ar.take<u64>((size_t)o_c * cstride);
+  const size_t total = (size_t)count * o_c;
+  u64* rot = ar.take<u64>(total * cstride);
   if (!rot) return fail(c, HE_ENOMEM, "workspace too small for combine");
-  std::vector<KsJob> jobs(o_c);
+  std::vector<KsJob> jobs(total);
   int64_t n_rot = 0;
   for (int o = 0; o < o_c; ++o) {
     const int step = -(o % per_dense) * spatial;
@@ -1117,22 +1120,43 @@ int he_combine_cp_dp(he_ctx* c, const uint64_t* d_in, int o_c, int level, int sp
       auto it = c->keys.find((int)g);
       if (it == c->keys.end()) return fail(c, HE_ENOKEY, "he_combine_cp_dp: no key for step %d", step);
       key = it->second;
-      ++n_rot;
+      n_rot += count;
     }
-    const u64* in = d_in + (size_t)o * cstride;
-    jobs[o] = KsJob{in + (size_t)level * n, in, rot + (size_t)o * cstride, key, g, galois_of(-step, n), level, 0};
+    for (int b = 0; b < count; ++b) {
+      const size_t idx = (size_t)b * o_c + o;
+      const u64* in = d_in + idx * cstride;
+      jobs[idx] = KsJob{in + (size_t)level * n, in, rot + idx * cstride, key, g, galois_of(-step, n), level, 0};
+    }
   }
   int e = rotate_jobs(c, jobs, EPI_ROT, ar, s);
   if (e) return e;
-  const int n_dense = (o_c + per_dense - 1) / per_dense;
   {
     Prof pr(c, "block_sum", s);
-    k_block_sum<<<dim3(n / 256, level, n_dense), 256, 0, s>>>(d_out, rot, o_c, per_dense, level, n, c->mods);
+    k_block_sum<<<dim3(n / 256, level, count * n_dense), 256, 0, s>>>(d_out, rot, o_c, per_dense, n_dense, level, n,
+                                                                      c->mods);
   }
   c->counts = he_counts{};
   c->counts.rot = n_rot;
-  c->counts.addcc = o_c - n_dense;
+  c->counts.addcc = (int64_t)count * (o_c - n_dense);
   return check_launch(c, "he_combine_cp_dp");
+}
+
+int he_combine_cp_dp(he_ctx* c, const uint64_t* d_in, int o_c, int level, int spatial, int per_dense,
+                     uint64_t* d_out, void* stream) {
+  return he_combine_cp_dp_batch(c, 1, d_in, o_c, level, spatial, per_dense, d_out, stream);
+}
+
+int he_gather_onehot(he_ctx* c, int count, const uint64_t* d_cts, int k, const uint64_t* d_mask, int level,
+                     uint64_t* d_out, void* stream) {
+  if (!c || !d_cts || !d_mask || !d_out || count < 1 || count > 65535 || k < 1 || k > c->n / 2 || !level_ok(c, level))
+    return fail(c, HE_EINVAL, "he_gather_onehot: bad arguments");
+  const u32 g5inv = galois_of(-1, c->n);
+  dispatch_logn<LHmaPerm>(c->logn, c, d_out, d_cts, k, d_mask, 0, level, (const int32_t*)nullptr, g5inv, level, 0,
+                          count, S(stream));
+  c->counts = he_counts{};
+  c->counts.mulpc = (int64_t)count * k;
+  c->counts.addcc = (int64_t)count * (k - 1);
+  return check_launch(c, "he_gather_onehot");
 }
 
 int he_rotate_hoisted(he_ctx* c, const uint64_t* d_in, int level, const int32_t* h_steps, int m, uint64_t* d_outs,
@@ -1187,6 +1211,16 @@ int he_conv_densepack(he_ctx* c, const uint64_t* d_in, int level, const he_conv_
   c->counts = he_counts{};
   Arena ar(c);
   return densepack_run(c, d_in, level, desc, d_filt, d_out, ar, S(stream));
+}
+
+int he_conv_densepack_batch(he_ctx* c, int n_layers, const uint64_t* d_in, size_t in_stride, int level,
+                            const he_conv_desc* desc, const uint64_t* d_filt, size_t filt_stride, uint64_t* d_out,
+                            void* stream) {
+  if (!c || !d_in || !desc || !d_filt || !d_out || n_layers < 1)
+    return fail(c, HE_EINVAL, "he_conv_densepack_batch: bad arguments");
+  c->counts = he_counts{};
+  Arena ar(c);
+  return densepack_run(c, d_in, level, desc, d_filt, d_out, ar, S(stream), n_layers, in_stride, filt_stride);
 }
 
 int he_conv_convpack(he_ctx* c, const uint64_t* d_in, int k, int level, const double* h_w, int o_c, double w_scale,

@@ -642,18 +642,23 @@ __global__ void k_make_jobs(KsJob* jobs, int count, const u64* d_base, size_t d_
 
 // CP -> DP combine, summing step: out[m] = sum_{o in block m} rot[o], block
 // m = [m B, min(O_c, (m+1) B)); grid (N / 256, level, n_dense).
-__global__ void k_block_sum(u64* __restrict__ out, const u64* __restrict__ rot, int o_c, int per_dense, int level,
-                            int n, Mods mods) {
+__global__ void k_block_sum(u64* __restrict__ out, const u64* __restrict__ rot, int o_c, int per_dense, int n_dense,
+                            int level, int n, Mods mods) {
+  // blockIdx.z = item * n_dense + m: out[z] = sum of item's ciphertexts
+  // m * per_dense .. (m + 1) * per_dense - 1 (rot holds o_c per item)
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int t = blockIdx.y;
-  const int mblk = blockIdx.z;
+  const size_t z = blockIdx.z;
+  const size_t item = z / n_dense;
+  const int mblk = (int)(z - item * n_dense);
   const u64 q = mods.m[t].q;
   const int o_end = min(o_c, (mblk + 1) * per_dense);
+  rot += item * o_c * 2 * level * (size_t)n;
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
     u64 acc = 0;
     for (int o = mblk * per_dense; o < o_end; ++o) acc = add_mod(acc, rot[(((size_t)o * 2 + c) * level + t) * n + i], q);
-    out[(((size_t)mblk * 2 + c) * level + t) * n + i] = acc;
+    out[((z * 2 + c) * level + t) * n + i] = acc;
   }
 }
 

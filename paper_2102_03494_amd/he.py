@@ -358,6 +358,41 @@ class HEContext:
                                                _ptr(out), _stream()), "he_conv_densepack")
         return Ct(out, x.scale * pt_scale / self.q[level - 1])
 
+    def conv_densepack_batch(self, xs: torch.Tensor, scale: float, desc: HeConvDesc, filt: torch.Tensor,
+                             pt_scale: float, shared_filters: bool = True, out: torch.Tensor | None = None) -> Ct:
+        """DensePack layer on xs[l] (each [M][2][level][N] or [2][level][N]) for every l, one batch.
+        filt: one filter set (shared_filters) or one per input stacked on dim 0."""
+        n_layers = xs.shape[0]
+        level = xs.shape[-2]
+        oh = (desc.h + 2 * desc.pad - desc.d) // desc.stride + 1
+        ow = (desc.w + 2 * desc.pad - desc.d) // desc.stride + 1
+        total = oh * ow * desc.o_c
+        if out is None:
+            out = torch.empty((n_layers, total, 2, level - 1, self.n), dtype=torch.int64, device="cuda")
+        f_stride = 0 if shared_filters else filt[0].numel()
+        self._check(self.lib.he_conv_densepack_batch(self.h, n_layers, _ptr(xs), xs[0].numel(), level,
+                                                     ctypes.byref(desc), _ptr(filt), f_stride, _ptr(out), _stream()),
+                    "he_conv_densepack_batch")
+        return Ct(out, scale * pt_scale / self.q[level - 1])
+
+    def combine_cp_dp_batch(self, z: Ct, spatial: int, per_dense: int) -> Ct:
+        """z.data [count][o_c][2][level][N] -> [count][n_dense][2][level][N]."""
+        count, o_c, _, level, n = z.data.shape
+        n_dense = -(-o_c // per_dense)
+        out = torch.empty((count, n_dense, 2, level, n), dtype=torch.int64, device="cuda")
+        self._check(self.lib.he_combine_cp_dp_batch(self.h, count, _ptr(z.data), o_c, level, spatial, per_dense,
+                                                    _ptr(out), _stream()), "he_combine_cp_dp_batch")
+        return Ct(out, z.scale)
+
+    def gather_onehot(self, y: Ct, k: int, mask: torch.Tensor, mask_scale: float) -> Ct:
+        """y.data [count*k][2][level][N] -> [count][2][level][N]: item j of each group to slot j."""
+        level = y.level
+        count = y.data.numel() // (k * 2 * level * self.n)
+        out = torch.empty((count, 2, level, self.n), dtype=torch.int64, device="cuda")
+        self._check(self.lib.he_gather_onehot(self.h, count, _ptr(y.data), k, _ptr(mask), level, _ptr(out),
+                                              _stream()), "he_gather_onehot")
+        return Ct(out, y.scale * mask_scale)
+
     def conv_convpack(self, x: Ct, w: np.ndarray, w_scale: float) -> Ct:
         level = x.level
         k, o_c = w.shape
@@ -400,18 +435,21 @@ class HEContext:
 
     def ffconv_layer_batch(self, xs: torch.Tensor, scale: float, desc: HeConvDesc, w1_filts: torch.Tensor,
                            w1_pt_scale: float, mask: torch.Tensor, mask_scale: float, w2_tabs: torch.Tensor,
-                           o_c2: int, k_bits: int, square: bool, out: torch.Tensor | None = None) -> Ct:
+                           o_c2: int, k_bits: int, square: bool, out: torch.Tensor | None = None,
+                           shared_w1: bool = False) -> Ct:
         """len(xs) independent FFConv layers (inputs xs[l], all at `scale`, with
-        filters w1_filts[l] and W2 tables w2_tabs[l]) in one call."""
+        filters w1_filts[l] -- or one filter set for all when shared_w1 -- and
+        W2 tables w2_tabs[l]) in one call."""
         n_layers = xs.shape[0]
         level = xs.shape[-2]
-        assert w1_filts.shape[0] == n_layers and w2_tabs.shape[0] == n_layers
+        assert shared_w1 or w1_filts.shape[0] == n_layers
+        assert w2_tabs.shape[0] == n_layers
         assert xs.is_contiguous() and w1_filts.is_contiguous() and w2_tabs.is_contiguous()
         lvl_out = level - 2 - (1 if square else 0)
         if out is None:
             out = torch.empty((n_layers, o_c2, 2, lvl_out, self.n), dtype=torch.int64, device="cuda")
         in_stride = xs[0].numel()
-        f_stride = w1_filts[0].numel()
+        f_stride = 0 if shared_w1 else w1_filts[0].numel()
         self._check(self.lib.ffconv_layer_batch(self.h, n_layers, _ptr(xs), in_stride, level, ctypes.byref(desc),
                                                 _ptr(w1_filts), f_stride, _ptr(mask), _ptr(w2_tabs), o_c2,
                                                 int(square), _ptr(out), _stream()), "ffconv_layer_batch")

@@ -96,6 +96,21 @@ def filter_layout(weights: np.ndarray, g: Geometry, slots: int, o: int, cls: int
     return v
 
 
+class PlainEncoder:
+    """Keyless encoder for the server's plaintext weights: slot values to an
+    NTT-domain plaintext [level][N] on the device (the client's encoding:
+    host FFT of the canonical embedding, then the library's NTT)."""
+
+    def __init__(self, ctx: HEContext):
+        self.ctx = ctx
+
+    def encode(self, z, level: int, scale: float) -> torch.Tensor:
+        coeffs = torch.from_numpy(self.ctx.encode_coeffs(z, scale)).cuda()
+        pt = self.ctx.from_signed(coeffs, level, 0)
+        self.ctx.ntt(pt.view(1, level, self.ctx.n))
+        return pt
+
+
 def encode_filters(client, weights: np.ndarray, g: Geometry, level: int, pt_scale: float) -> torch.Tensor:
     """Base filter plaintexts [O_c][classes][M][level][N] on the device."""
     ctx = client.ctx
