@@ -483,6 +483,9 @@ def main():
         "hbm_gbs_algorithmic": bytes_layer / launches_layer / (avg_ms * 1e-3) / 1e9,
     }
 
+    tuning = {"source": ctx.tuning_source,
+              "p_groups": {lv: ctx.get_tuning("p_groups", lv) for lv in range(1, len(Q_BITS) + 1)}}
+
     batched = None
     if args.batched_layers > 0:
         print("# batched layers and graph", file=sys.stderr, flush=True)
@@ -537,6 +540,7 @@ def main():
         "counts_plain_conv": counts_pl,
         "decrypted_max_abs_err": {"ffconv": err_ff, "plain": err_pl},
         "roofline": roofline,
+        "tuning": tuning,
         "batched_layers_graph": batched,
         "ragged_batch": ragged,
         "serving_mnist": serving,

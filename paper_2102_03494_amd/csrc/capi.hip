@@ -34,6 +34,8 @@ struct he_ctx {
   std::vector<u64> moduli;  // q_0..q_{L-1}, P
   Mods mods{};
   bool has_cls[3] = {false, false, false};  // width classes among q_0..q_{L-1}, P
+  unsigned q_mask = 0;                       // bit c: a ciphertext prime of class c exists
+  int p_cls = 0;                             // class of P
   u64* d_tw = nullptr;    // [L+1][4][N] 64-bit twiddles + Shoup companions
   u32* d_tw32 = nullptr;  // 32-bit copies for the narrow moduli
   double* d_twf = nullptr;  // (w, w / q) as doubles for the f64 moduli
@@ -156,6 +158,30 @@ int dispatch_logn(int logn, A&&... args) {
   }
 }
 
+// Runs LAUNCH with the constant CLS bound to every width class in `mask`
+// (transform kernels are instantiated per class).
+#define HE_FOR_CLASSES(mask, LAUNCH)               \
+  do {                                             \
+    if ((mask)&1u) {                               \
+      constexpr int CLS = CLS_N32;                 \
+      LAUNCH;                                      \
+    }                                              \
+    if ((mask)&2u) {                               \
+      constexpr int CLS = CLS_F64;                 \
+      LAUNCH;                                      \
+    }                                              \
+    if ((mask)&4u) {                               \
+      constexpr int CLS = CLS_U64;                 \
+      LAUNCH;                                      \
+    }                                              \
+  } while (0)
+
+unsigned cls_mask(const he_ctx* c, int first, int count) {
+  unsigned m = 0;
+  for (int i = first; i < first + count; ++i) m |= 1u << c->mods.m[i].cls;
+  return m;
+}
+
 // Copies `bytes` from host to device memory `dst` on stream s through a ring
 // of pinned buffers; a slot is reused only after its previous copy finished.
 int upload(he_ctx* c, void* dst, const void* src, size_t bytes, hipStream_t s) {
@@ -195,10 +221,13 @@ struct LNtt {
   static void run(he_ctx* c, u64* d, int n_polys, int n_limbs, int first_mod, bool fwd, hipStream_t s) {
     dim3 grid(n_limbs, n_polys);
     Prof pr(c, "ntt", s);
+    const unsigned mask = cls_mask(c, first_mod, n_limbs);
     if (fwd)
-      k_ntt<LOGN, true><<<grid, NttGeom<LOGN>::T, 0, s>>>(d, n_limbs, first_mod, c->mods, c->tb());
+      HE_FOR_CLASSES(mask, (k_ntt<LOGN, true, CLS><<<grid, NttGeom<LOGN>::T, 0, s>>>(d, n_limbs, first_mod, c->mods,
+                                                                                      c->tb())));
     else
-      k_ntt<LOGN, false><<<grid, NttGeom<LOGN>::T, 0, s>>>(d, n_limbs, first_mod, c->mods, c->tb());
+      HE_FOR_CLASSES(mask, (k_ntt<LOGN, false, CLS><<<grid, NttGeom<LOGN>::T, 0, s>>>(d, n_limbs, first_mod, c->mods,
+                                                                                       c->tb())));
   }
 };
 
@@ -213,7 +242,8 @@ struct LKsCore {
     constexpr int T = NttGeom<LOGN>::T;
     {
       Prof pr(c, "ks_digits", s);
-      k_ks_digits<LOGN><<<dim3(lmax, count), T, 0, s>>>(jobs, dcoef, lmax, c->mods, c->tb());
+      HE_FOR_CLASSES(c->q_mask, (k_ks_digits<LOGN, CLS><<<dim3(lmax, count), T, 0, s>>>(jobs, dcoef, lmax, c->mods,
+                                                                                        c->tb())));
     }
     const dim3 grid(lmax + pg, count);
     static const char* names[3] = {"ks_modup_ip", "ks_modup_ip_f64", "ks_modup_ip_wide"};
@@ -243,7 +273,8 @@ struct LKsCore {
       }
     }
     Prof pr(c, "intt_last", s);
-    k_intt_last<LOGN, MODE_P><<<dim3(2 * count), T, 0, s>>>(jobs, u, lmax, pg, c->big_l, rc, c->mods, c->tb());
+    HE_FOR_CLASSES(1u << c->p_cls, (k_intt_last<LOGN, MODE_P, CLS><<<dim3(2 * count), T, 0, s>>>(
+                                       jobs, u, lmax, pg, c->big_l, rc, c->mods, c->tb())));
   }
 };
 
@@ -257,8 +288,9 @@ struct LDrop {
     const int keep = mode == MODE_P ? lmax : lmax - 1;
     const dim3 grid(keep, 2 * count);
     Prof pr(c, "drop_last", s);
-#define HE_DROP(MD, EP) \
-  k_drop_last<LOGN, MD, EP><<<grid, T, 0, s>>>(jobs, u, urows, c->big_l, rc, c->d_inv, c->mods, c->tb())
+#define HE_DROP(MD, EP)                                                                                    \
+  HE_FOR_CLASSES(c->q_mask, (k_drop_last<LOGN, MD, EP, CLS><<<grid, T, 0, s>>>(jobs, u, urows, c->big_l, rc, \
+                                                                               c->d_inv, c->mods, c->tb())))
     if (mode == MODE_LAST) {
       HE_DROP(MODE_LAST, EPI_STORE);
     } else if (epi == EPI_ROT) {
@@ -278,8 +310,8 @@ template <int LOGN>
 struct LIntt1 {
   static void run(he_ctx* c, const KsJob* jobs, int count, int lmax, u64* rc, hipStream_t s) {
     Prof pr(c, "intt_last", s);
-    k_intt_last<LOGN, MODE_LAST><<<dim3(2 * count), NttGeom<LOGN>::T, 0, s>>>(jobs, nullptr, lmax, 1, c->big_l,
-                                                                              rc, c->mods, c->tb());
+    HE_FOR_CLASSES(c->q_mask, (k_intt_last<LOGN, MODE_LAST, CLS><<<dim3(2 * count), NttGeom<LOGN>::T, 0, s>>>(
+                                   jobs, nullptr, lmax, 1, c->big_l, rc, c->mods, c->tb())));
   }
 };
 
@@ -318,9 +350,12 @@ template <int LOGN>
 struct LHoistUp {
   static void run(he_ctx* c, const KsJob* job1, const u64* c1, int level, u64* dcoef, u64* dhat, hipStream_t s) {
     constexpr int T = NttGeom<LOGN>::T;
-    k_ks_digits<LOGN><<<dim3(level, 1), T, 0, s>>>(job1, dcoef, level, c->mods, c->tb());
+    HE_FOR_CLASSES(c->q_mask, (k_ks_digits<LOGN, CLS><<<dim3(level, 1), T, 0, s>>>(job1, dcoef, level, c->mods,
+                                                                                     c->tb())));
     Prof pr(c, "modup_store", s);
-    k_modup_store<LOGN><<<dim3(level + 1, level), T, 0, s>>>(dcoef, c1, dhat, level, c->big_l, c->mods, c->tb());
+    HE_FOR_CLASSES(c->q_mask | (1u << c->p_cls),
+                   (k_modup_store<LOGN, CLS><<<dim3(level + 1, level), T, 0, s>>>(dcoef, c1, dhat, level, c->big_l,
+                                                                                  c->mods, c->tb())));
   }
 };
 
@@ -336,7 +371,8 @@ struct LHoisted {
     }
     {  // u rows per polynomial: level + 1, P at row level (one P group)
       Prof pr(c, "intt_last", s);
-      k_intt_last<LOGN, MODE_P><<<dim3(2 * m), T, 0, s>>>(jobs, u, level, 1, c->big_l, rc, c->mods, c->tb());
+      HE_FOR_CLASSES(1u << c->p_cls, (k_intt_last<LOGN, MODE_P, CLS><<<dim3(2 * m), T, 0, s>>>(
+                                         jobs, u, level, 1, c->big_l, rc, c->mods, c->tb())));
     }
     LDrop<LOGN>::run(c, MODE_P, EPI_ROT, jobs, m, level, level + 1, u, rc, s);
   }
@@ -732,7 +768,9 @@ int he_ctx_create(const he_params* p, he_ctx** out) {
   for (int i = 0; i <= p->n_q; ++i) {
     c->mods.m[i] = make_modconst(mods[i], p->n);
     c->has_cls[c->mods.m[i].cls] = true;
+    if (i < p->n_q) c->q_mask |= 1u << c->mods.m[i].cls;
   }
+  c->p_cls = (int)c->mods.m[p->n_q].cls;
   const size_t n = p->n;
   std::vector<u64> tw(mods.size() * 4 * n);
   for (size_t i = 0; i < mods.size(); ++i) {

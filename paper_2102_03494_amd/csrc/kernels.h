@@ -58,14 +58,11 @@ __device__ __forceinline__ Tw<CLS> tw_of(const Tables& tb, int mi, int which) {
   else return {tb.tw64 + o, tb.tw64 + o + N};
 }
 
-// Expands BODY with the compile-time constant CLS set to the width class of
-// m (uniform per workgroup).
-#define HE_BY_CLASS(m, BODY)                          \
-  do {                                                \
-    if ((m).cls == CLS_N32) { constexpr int CLS = CLS_N32; BODY; } \
-    else if ((m).cls == CLS_F64) { constexpr int CLS = CLS_F64; BODY; } \
-    else { constexpr int CLS = CLS_U64; BODY; }      \
-  } while (0)
+// Transform kernels are templated on the width class CLS: the host launches
+// one instance per class present among the primes a launch touches (in every
+// configuration here that is one launch), and workgroups whose prime is of
+// another class exit at once.  One class per kernel keeps its register
+// allocation to what that class needs.
 
 // An opaque copy of the thread index (see ntt_lds.h): defined where it is
 // used so that address arithmetic is not hoisted out of enclosing loops.
@@ -176,7 +173,7 @@ __device__ __forceinline__ void ntt_body(u64* lds, u64* p, int mi, const ModCons
   store_limb<LOGN, CLS>(p, lds, m, !FWD);
 }
 
-template <int LOGN, bool FWD>
+template <int LOGN, bool FWD, int CLS>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
 k_ntt(u64* data, int n_limbs, int first_mod, Mods mods, Tables tb) {
   constexpr int N = 1 << LOGN;
@@ -185,7 +182,8 @@ k_ntt(u64* data, int n_limbs, int first_mod, Mods mods, Tables tb) {
   const int mi = first_mod + limb;
   const ModConst m = mods.m[mi];
   u64* p = data + ((size_t)blockIdx.y * n_limbs + limb) * N;
-  HE_BY_CLASS(m, (ntt_body<LOGN, FWD, CLS>(lds, p, mi, m, tb)));
+  if ((int)m.cls != CLS) return;
+  ntt_body<LOGN, FWD, CLS>(lds, p, mi, m, tb);
 }
 
 // ---------------------------------------------------------------------------
@@ -226,7 +224,7 @@ struct KsJob {
 
 // Key switch, step 1: coefficient-domain digits of sigma_g(d).
 // grid (Lmax, count): blockIdx.x = digit j.
-template <int LOGN>
+template <int LOGN, int CLS>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
 k_ks_digits(const KsJob* __restrict__ jobs, u64* __restrict__ dcoef, int lmax, Mods mods, Tables tb) {
   constexpr int N = 1 << LOGN;
@@ -238,7 +236,8 @@ k_ks_digits(const KsJob* __restrict__ jobs, u64* __restrict__ dcoef, int lmax, M
   const ModConst m = mods.m[j];
   const u64* src = jb.d + (size_t)j * N;
   u64* out = dcoef + (b * lmax + j) * N;
-  HE_BY_CLASS(m, (digits_body<LOGN, CLS>(lds, src, jb.ginv, out, j, m, tb)));
+  if ((int)m.cls != CLS) return;
+  digits_body<LOGN, CLS>(lds, src, jb.ginv, out, j, m, tb);
 }
 
 // P groups: with pg groups a job at `level` gives group k the digits
@@ -388,7 +387,7 @@ __device__ __forceinline__ void intt_p_body(u64* lds, const u64* __restrict__ ur
 //   MODE_P:    the P limb of u, i.e. the sum of its group partials (ModDown
 //              after a key switch; u rows per polynomial lmax + pg);
 //   MODE_LAST: the last limb of the ciphertext jobs[b].d (rescale).
-template <int LOGN, int MODE>
+template <int LOGN, int MODE, int CLS>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
 k_intt_last(const KsJob* __restrict__ jobs, const u64* __restrict__ u, int lmax, int pg, int big_l,
             u64* __restrict__ rcoef, Mods mods, Tables tb) {
@@ -404,12 +403,14 @@ k_intt_last(const KsJob* __restrict__ jobs, const u64* __restrict__ u, int lmax,
     const u64* s = u + ((b * 2 + comp) * (lmax + pg) + lmax) * N;
     const int groups = pgroup_count(jb.level, pg);
     const ModConst m = mods.m[big_l];
-    HE_BY_CLASS(m, (intt_p_body<LOGN, CLS>(lds, s, groups, out, big_l, m, tb)));
+    if ((int)m.cls != CLS) return;
+    intt_p_body<LOGN, CLS>(lds, s, groups, out, big_l, m, tb);
   } else {
     const u64* s = jb.d + ((size_t)comp * jb.level + jb.level - 1) * N;
     const int mi = jb.level - 1;
     const ModConst m = mods.m[mi];
-    HE_BY_CLASS(m, (digits_body<LOGN, CLS>(lds, s, 1u, out, mi, m, tb)));
+    if ((int)m.cls != CLS) return;
+    digits_body<LOGN, CLS>(lds, s, 1u, out, mi, m, tb);
   }
 }
 
@@ -522,7 +523,7 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
 }
 
 // grid (Lmax, 2 count)
-template <int LOGN, int MODE, int EPI>
+template <int LOGN, int MODE, int EPI, int CLS>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
 k_drop_last(const KsJob* __restrict__ jobs, const u64* __restrict__ u, int urows, int big_l,
             const u64* __restrict__ rcoef, const u64* __restrict__ inv_tab, Mods mods, Tables tb) {
@@ -534,9 +535,8 @@ k_drop_last(const KsJob* __restrict__ jobs, const u64* __restrict__ u, int urows
   const KsJob jb = jobs[b];
   const int keep = (MODE == MODE_P) ? jb.level : jb.level - 1;
   if (t >= keep) return;
-  const ModConst& m = mods.m[t];
-  HE_BY_CLASS(m, (drop_last_body<LOGN, MODE, EPI, CLS>(lds, jb, b, comp, t, u, urows, big_l, rcoef, inv_tab, mods,
-                                                       tb)));
+  if ((int)mods.m[t].cls != CLS) return;
+  drop_last_body<LOGN, MODE, EPI, CLS>(lds, jb, b, comp, t, u, urows, big_l, rcoef, inv_tab, mods, tb);
 }
 
 // ---------------------------------------------------------------------------
@@ -571,14 +571,14 @@ __device__ __forceinline__ void modup_store_body(u64* lds, const u64* __restrict
   store_limb<LOGN, CLS>(out, lds, m, false);
 }
 
-template <int LOGN>
+template <int LOGN, int CLS>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
 k_modup_store(const u64* __restrict__ dcoef, const u64* __restrict__ c1, u64* __restrict__ dhat, int level, int big_l,
               Mods mods, Tables tb) {
   __shared__ u64 lds[NttGeom<LOGN>::LDS];
   const int mi = ((int)blockIdx.x < level) ? (int)blockIdx.x : big_l;
-  const ModConst& m = mods.m[mi];
-  HE_BY_CLASS(m, (modup_store_body<LOGN, CLS>(lds, dcoef, c1, dhat, level, big_l, mods, tb)));
+  if ((int)mods.m[mi].cls != CLS) return;
+  modup_store_body<LOGN, CLS>(lds, dcoef, c1, dhat, level, big_l, mods, tb);
 }
 
 // Inner product of the shared lifted digits, permuted per rotation, with

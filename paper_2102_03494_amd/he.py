@@ -90,7 +90,11 @@ class Graph:
 
 
 class HEContext:
-    def __init__(self, n: int, q_bits, p_bits: int, workspace_bytes: int = 0):
+    def __init__(self, n: int, q_bits, p_bits: int, workspace_bytes: int = 0, tuned: bool = True):
+        """A library context for ring dimension n, ciphertext primes of the
+        given bit sizes and a special prime of p_bits.  With `tuned`, the
+        autotuner's cached schedule for this ring (tune.py) is applied;
+        tuning_source tells whether it came from the cache or the cost model."""
         self.lib = _lib.lib()
         self.n = int(n)
         self.q_bits = tuple(int(b) for b in q_bits)
@@ -111,6 +115,10 @@ class HEContext:
         self.moduli = [int(v) for v in out]
         self.q = self.moduli[: self.L]
         self.p = self.moduli[self.L]
+        self.tuning_source = "cost model"
+        if tuned:
+            from .tune import apply
+            self.tuning_source = apply(self)
         if workspace_bytes:
             self.reserve(workspace_bytes)
 
