@@ -242,10 +242,10 @@ struct LKsCore {
     constexpr int T = NttGeom<LOGN>::T;
     {
       Prof pr(c, "ks_digits", s);
-      HE_FOR_CLASSES(c->q_mask, (k_ks_digits<LOGN, CLS><<<dim3(lmax, count), T, 0, s>>>(jobs, dcoef, lmax, c->mods,
-                                                                                        c->tb())));
+      HE_FOR_CLASSES(c->q_mask, (k_ks_digits<LOGN, CLS><<<xcd_grid(lmax, count), T, 0, s>>>(jobs, count, dcoef, lmax,
+                                                                                            c->mods, c->tb())));
     }
-    const dim3 grid(lmax + pg, count);
+    const unsigned grid = xcd_grid(lmax + pg, count);
     static const char* names[3] = {"ks_modup_ip", "ks_modup_ip_f64", "ks_modup_ip_wide"};
     const bool forked = (int)c->has_cls[0] + (int)c->has_cls[1] + (int)c->has_cls[2] > 1;
     {
@@ -261,11 +261,14 @@ struct LKsCore {
         first = false;
         Prof pr(c, names[cls], st);
         if (cls == CLS_N32)
-          k_ks_modup_ip<LOGN, CLS_N32><<<grid, T, 0, st>>>(jobs, dcoef, u, lmax, pg, c->big_l, c->mods, c->tb());
+          k_ks_modup_ip<LOGN, CLS_N32><<<grid, T, 0, st>>>(jobs, count, dcoef, u, lmax, pg, c->big_l, c->mods,
+                                                            c->tb());
         else if (cls == CLS_F64)
-          k_ks_modup_ip<LOGN, CLS_F64><<<grid, T, 0, st>>>(jobs, dcoef, u, lmax, pg, c->big_l, c->mods, c->tb());
+          k_ks_modup_ip<LOGN, CLS_F64><<<grid, T, 0, st>>>(jobs, count, dcoef, u, lmax, pg, c->big_l, c->mods,
+                                                            c->tb());
         else
-          k_ks_modup_ip<LOGN, CLS_U64><<<grid, T, 0, st>>>(jobs, dcoef, u, lmax, pg, c->big_l, c->mods, c->tb());
+          k_ks_modup_ip<LOGN, CLS_U64><<<grid, T, 0, st>>>(jobs, count, dcoef, u, lmax, pg, c->big_l, c->mods,
+                                                            c->tb());
       }
       if (forked) {
         (void)hipEventRecord(c->join_ev, c->side);
@@ -273,8 +276,8 @@ struct LKsCore {
       }
     }
     Prof pr(c, "intt_last", s);
-    HE_FOR_CLASSES(1u << c->p_cls, (k_intt_last<LOGN, MODE_P, CLS><<<dim3(2 * count), T, 0, s>>>(
-                                       jobs, u, lmax, pg, c->big_l, rc, c->mods, c->tb())));
+    HE_FOR_CLASSES(1u << c->p_cls, (k_intt_last<LOGN, MODE_P, CLS><<<xcd_grid(2, count), T, 0, s>>>(
+                                       jobs, count, u, lmax, pg, c->big_l, rc, c->mods, c->tb())));
   }
 };
 
@@ -286,11 +289,12 @@ struct LDrop {
                   const u64* rc, hipStream_t s) {
     constexpr int T = NttGeom<LOGN>::T;
     const int keep = mode == MODE_P ? lmax : lmax - 1;
-    const dim3 grid(keep, 2 * count);
+    const unsigned grid = xcd_grid(2 * keep, count);
     Prof pr(c, "drop_last", s);
 #define HE_DROP(MD, EP)                                                                                    \
-  HE_FOR_CLASSES(c->q_mask, (k_drop_last<LOGN, MD, EP, CLS><<<grid, T, 0, s>>>(jobs, u, urows, c->big_l, rc, \
-                                                                               c->d_inv, c->mods, c->tb())))
+  HE_FOR_CLASSES(c->q_mask, (k_drop_last<LOGN, MD, EP, CLS><<<grid, T, 0, s>>>(jobs, count, keep, u, urows,  \
+                                                                               c->big_l, rc, c->d_inv, c->mods, \
+                                                                               c->tb())))
     if (mode == MODE_LAST) {
       HE_DROP(MODE_LAST, EPI_STORE);
     } else if (epi == EPI_ROT) {
@@ -310,8 +314,8 @@ template <int LOGN>
 struct LIntt1 {
   static void run(he_ctx* c, const KsJob* jobs, int count, int lmax, u64* rc, hipStream_t s) {
     Prof pr(c, "intt_last", s);
-    HE_FOR_CLASSES(c->q_mask, (k_intt_last<LOGN, MODE_LAST, CLS><<<dim3(2 * count), NttGeom<LOGN>::T, 0, s>>>(
-                                   jobs, nullptr, lmax, 1, c->big_l, rc, c->mods, c->tb())));
+    HE_FOR_CLASSES(c->q_mask, (k_intt_last<LOGN, MODE_LAST, CLS><<<xcd_grid(2, count), NttGeom<LOGN>::T, 0, s>>>(
+                                   jobs, count, nullptr, lmax, 1, c->big_l, rc, c->mods, c->tb())));
   }
 };
 
@@ -350,8 +354,8 @@ template <int LOGN>
 struct LHoistUp {
   static void run(he_ctx* c, const KsJob* job1, const u64* c1, int level, u64* dcoef, u64* dhat, hipStream_t s) {
     constexpr int T = NttGeom<LOGN>::T;
-    HE_FOR_CLASSES(c->q_mask, (k_ks_digits<LOGN, CLS><<<dim3(level, 1), T, 0, s>>>(job1, dcoef, level, c->mods,
-                                                                                     c->tb())));
+    HE_FOR_CLASSES(c->q_mask, (k_ks_digits<LOGN, CLS><<<xcd_grid(level, 1), T, 0, s>>>(job1, 1, dcoef, level,
+                                                                                         c->mods, c->tb())));
     Prof pr(c, "modup_store", s);
     HE_FOR_CLASSES(c->q_mask | (1u << c->p_cls),
                    (k_modup_store<LOGN, CLS><<<dim3(level + 1, level), T, 0, s>>>(dcoef, c1, dhat, level, c->big_l,
@@ -371,8 +375,8 @@ struct LHoisted {
     }
     {  // u rows per polynomial: level + 1, P at row level (one P group)
       Prof pr(c, "intt_last", s);
-      HE_FOR_CLASSES(1u << c->p_cls, (k_intt_last<LOGN, MODE_P, CLS><<<dim3(2 * m), T, 0, s>>>(
-                                         jobs, u, level, 1, c->big_l, rc, c->mods, c->tb())));
+      HE_FOR_CLASSES(1u << c->p_cls, (k_intt_last<LOGN, MODE_P, CLS><<<xcd_grid(2, m), T, 0, s>>>(
+                                         jobs, m, u, level, 1, c->big_l, rc, c->mods, c->tb())));
     }
     LDrop<LOGN>::run(c, MODE_P, EPI_ROT, jobs, m, level, level + 1, u, rc, s);
   }

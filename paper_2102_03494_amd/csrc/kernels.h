@@ -212,6 +212,24 @@ __device__ __forceinline__ void digits_body(u64* lds, const u64* src, u32 ginv, 
 //   u     [count][2][Lmax+pg][N]  inner products: q_t at row t < level, the
 //                                 partial sum of P group k at row Lmax + k
 //   rc    [count][2][N]           coefficient-domain last limb (ModDown/rescale)
+// Workgroup placement of the key-switch kernels.  The dispatcher hands
+// workgroup i of a 1-D grid to XCD i mod 8, and each XCD has its own L2.  The
+// kernels below run on grids of per * round8(count) workgroups mapped
+// job-major per XCD: all `per` workgroups of job b run on XCD b mod 8, one
+// after another, so the targets of a ciphertext share its digits in one L2 and
+// what one kernel writes for a job (digits, inner products, the P limb) the
+// next reads from that L2.  Slots past `count` exit.
+struct XcdSlot {
+  int job;  // job index (may be >= count: exit)
+  int sub;  // workgroup within the job, 0 .. per-1
+};
+__device__ __forceinline__ XcdSlot xcd_slot(int per) {
+  const unsigned i = blockIdx.x;
+  const unsigned local = i >> 3;
+  return XcdSlot{(int)((local / per) * 8 + (i & 7u)), (int)(local % per)};
+}
+__host__ __device__ inline unsigned xcd_grid(int per, int count) { return (unsigned)per * ((count + 7) & ~7); }
+
 struct KsJob {
   const u64* d;    // polynomial to switch / ciphertext to rescale
   const u64* c;    // EPI_ROT*: source ciphertext (c0 at c); EPI_RELIN: (d0, d1)
@@ -223,14 +241,16 @@ struct KsJob {
 };
 
 // Key switch, step 1: coefficient-domain digits of sigma_g(d).
-// grid (Lmax, count): blockIdx.x = digit j.
+// grid xcd_grid(Lmax, count): workgroup = (job b, digit j).
 template <int LOGN, int CLS>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
-k_ks_digits(const KsJob* __restrict__ jobs, u64* __restrict__ dcoef, int lmax, Mods mods, Tables tb) {
+k_ks_digits(const KsJob* __restrict__ jobs, int count, u64* __restrict__ dcoef, int lmax, Mods mods, Tables tb) {
   constexpr int N = 1 << LOGN;
   __shared__ u64 lds[NttGeom<LOGN>::LDS];
-  const int j = blockIdx.x;
-  const size_t b = blockIdx.y;
+  const XcdSlot sl = xcd_slot(lmax);
+  if (sl.job >= count) return;
+  const int j = sl.sub;
+  const size_t b = sl.job;
   const KsJob jb = jobs[b];
   if (jb.key == nullptr || j >= jb.level) return;
   const ModConst m = mods.m[j];
@@ -326,20 +346,22 @@ __device__ __forceinline__ void modup_ip_body(u64* lds, const u64* __restrict__ 
   }
 }
 
-// grid (Lmax + pg, count): blockIdx.x < Lmax is ciphertext prime blockIdx.x,
-// blockIdx.x = Lmax + k is group k of P's digits.  Each width class is its
+// grid xcd_grid(Lmax + pg, count): workgroup (job b, x), x < Lmax is
+// ciphertext prime x, x = Lmax + k is group k of P's digits.  Each width class is its
 // own kernel (so each body gets a register allocation of its own); blocks of
 // the other classes, primes above a job's level and empty P groups exit at
 // once.
 template <int LOGN, int CLS>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
-k_ks_modup_ip(const KsJob* __restrict__ jobs, const u64* __restrict__ dcoef, u64* __restrict__ u, int lmax, int pg,
-              int big_l, Mods mods, Tables tb) {
+k_ks_modup_ip(const KsJob* __restrict__ jobs, int count, const u64* __restrict__ dcoef, u64* __restrict__ u, int lmax,
+              int pg, int big_l, Mods mods, Tables tb) {
   __shared__ u64 lds[NttGeom<LOGN>::LDS];
-  const size_t b = blockIdx.y;
+  const XcdSlot sl = xcd_slot(lmax + pg);
+  if (sl.job >= count) return;
+  const size_t b = sl.job;
   const KsJob jb = jobs[b];
   if (jb.key == nullptr) return;
-  const int x = blockIdx.x;
+  const int x = sl.sub;
   const int level = jb.level;
   int t, mi, j0, j1, row;
   if (x < lmax) {
@@ -389,13 +411,15 @@ __device__ __forceinline__ void intt_p_body(u64* lds, const u64* __restrict__ ur
 //   MODE_LAST: the last limb of the ciphertext jobs[b].d (rescale).
 template <int LOGN, int MODE, int CLS>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
-k_intt_last(const KsJob* __restrict__ jobs, const u64* __restrict__ u, int lmax, int pg, int big_l,
+k_intt_last(const KsJob* __restrict__ jobs, int count, const u64* __restrict__ u, int lmax, int pg, int big_l,
             u64* __restrict__ rcoef, Mods mods, Tables tb) {
   constexpr int N = 1 << LOGN;
   __shared__ u64 lds[NttGeom<LOGN>::LDS];
-  const size_t p = blockIdx.x;
-  const size_t b = p >> 1;
-  const int comp = (int)(p & 1);
+  const XcdSlot sl = xcd_slot(2);  // grid xcd_grid(2, count): workgroup (job b, polynomial comp)
+  if (sl.job >= count) return;
+  const size_t b = sl.job;
+  const int comp = sl.sub;
+  const size_t p = 2 * b + comp;
   const KsJob jb = jobs[b];
   u64* out = rcoef + p * N;
   if (MODE == MODE_P) {
@@ -522,16 +546,18 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
   }
 }
 
-// grid (Lmax, 2 count)
+// grid xcd_grid(2 Kmax, count), Kmax the largest number of kept limbs:
+// workgroup (job b, polynomial comp, kept prime t).
 template <int LOGN, int MODE, int EPI, int CLS>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
-k_drop_last(const KsJob* __restrict__ jobs, const u64* __restrict__ u, int urows, int big_l,
+k_drop_last(const KsJob* __restrict__ jobs, int count, int kmax, const u64* __restrict__ u, int urows, int big_l,
             const u64* __restrict__ rcoef, const u64* __restrict__ inv_tab, Mods mods, Tables tb) {
   __shared__ u64 lds[NttGeom<LOGN>::LDS];
-  const int t = blockIdx.x;
-  const size_t p = blockIdx.y;
-  const size_t b = p >> 1;
-  const int comp = (int)(p & 1);
+  const XcdSlot sl = xcd_slot(2 * kmax);
+  if (sl.job >= count) return;
+  const size_t b = sl.job;
+  const int comp = sl.sub / kmax;
+  const int t = sl.sub - comp * kmax;
   const KsJob jb = jobs[b];
   const int keep = (MODE == MODE_P) ? jb.level : jb.level - 1;
   if (t >= keep) return;
