@@ -118,49 +118,100 @@ __device__ __forceinline__ void load_limb_perm(u64* lds, const u64* __restrict__
 template <int LOGN, int CLS>
 __device__ __forceinline__ void store_limb(u64* __restrict__ dst, const u64* lds, const ModConst& m, bool scale) {
   constexpr int T = NttGeom<LOGN>::T;
+  const int i0 = lds_idx((int)threadIdx.x);
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int i = (int)threadIdx.x + r * T;
+    const int li = lds_step(i0, r, T);
     if constexpr (CLS == CLS_F64) {
-      double v = lds_getw<CLS>(lds, i);
+      double v = lds_getw_at<CLS>(lds, li);
       if (scale) v = f64_mulc(v, f64_from_u64(m.n_inv), m.n_inv_q, m.qd);
       dst[i] = to_canon<CLS>(v, m);
     } else {
-      u64 v = lds_get<CLS>(lds, i, m);
+      u64 v = to_canon<CLS>(lds_getw_at<CLS>(lds, li), m);
       if (scale) v = shoupm<CLS == CLS_N32>(v, m.n_inv, m.n_inv_sh, m.q);
       dst[i] = v;
     }
   }
 }
 
-// Centred lift of a residue v mod qs (odd) into the word of target m's
-// class.  f64 targets take small sources (qs < 2^43) as signed values
-// without a reduction; the transforms accept them as they are.  Narrow
-// targets take a narrow source with qs < 2 q_t by one conditional add
-// (both halves of the centred range then land in [0, q_t)), and a source
-// below 2^43 by an exact FP64 reduction of the signed value.
-template <int CLS>
-__device__ __forceinline__ word_t<CLS> lift_word(u64 v, u64 qs, const ModConst& m) {
-  if constexpr (CLS == CLS_F64) {
-    if (qs < ((u64)1 << 43)) {
-      const double x = f64_from_u64(v);
-      return v > (qs - 1) / 2 ? x - f64_from_u64(qs) : x;
+// Centred lift into LDS of one limb of residues mod qs (odd), the 16 entries
+// tid + r T of this thread, in the word of target m's class.  All loads are
+// issued before any is used, and the method is chosen once (it is uniform
+// per workgroup):
+//   narrow target, narrow source with qs < 2 q_t: one conditional add (both
+//     halves of the centred range then land in [0, q_t));
+//   f64 target, source below 2^43: the signed value itself (the transforms
+//     take it unreduced);
+//   narrow target, source below 2^43: an exact FP64 reduction of the signed
+//     value;
+//   otherwise: lift_centered (64-bit Barrett).
+// Narrow sources are read as the low 32-bit words of their slots.
+template <int LOGN, int CLS>
+__device__ __forceinline__ void lift_limb(u64* lds, const u64* __restrict__ src, u64 qs, const ModConst& m, int tid) {
+  constexpr int T = NttGeom<LOGN>::T;
+  const int i0 = lds_idx(tid);
+  if (qs < NARROW_LIMIT) {
+    const u32* s32 = reinterpret_cast<const u32*>(src);
+    u32 v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = s32[2 * (tid + r * T)];
+    const u32 half = (u32)((qs - 1) / 2);
+    if constexpr (CLS == CLS_N32) {
+      if (qs < 2 * m.q) {
+        const u32 add = (u32)(m.q - qs);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) lds_putw_at<CLS>(lds, lds_step(i0, r, T), v[r] > half ? v[r] + add : v[r]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) lds_putw_at<CLS>(lds, lds_step(i0, r, T), (u32)lift_centered(v[r], qs, m));
+      }
+    } else if constexpr (CLS == CLS_F64) {
+      const double qsd = (double)(u32)qs;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const double x = (double)v[r];
+        lds_putw_at<CLS>(lds, lds_step(i0, r, T), v[r] > half ? x - qsd : x);
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) lds_putw_at<CLS>(lds, lds_step(i0, r, T), lift_centered(v[r], qs, m));
     }
-    return f64_from_u64(lift_centered(v, qs, m));
-  } else if constexpr (CLS == CLS_N32) {
-    if (qs < 2 * m.q) {
-      const u32 x = (u32)v;
-      return x > (u32)((qs - 1) / 2) ? x + (u32)(m.q - qs) : x;
-    }
-    if (qs < ((u64)1 << 43)) {
-      double x = f64_from_u64(v);
-      if (v > (qs - 1) / 2) x -= f64_from_u64(qs);
-      const double r = f64_canon(x, m.qd, m.qinv);
-      return (u32)r;
-    }
-    return (u32)lift_centered(v, qs, m);
   } else {
-    return (word_t<CLS>)lift_centered(v, qs, m);
+    u64 v[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = src[tid + r * T];
+    const u64 half = (qs - 1) / 2;
+    if constexpr (CLS == CLS_F64) {
+      if (qs < ((u64)1 << 43)) {
+        const double qsd = f64_from_u64(qs);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const double x = f64_from_u64(v[r]);
+          lds_putw_at<CLS>(lds, lds_step(i0, r, T), v[r] > half ? x - qsd : x);
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          lds_putw_at<CLS>(lds, lds_step(i0, r, T), f64_from_u64(lift_centered(v[r], qs, m)));
+      }
+    } else if constexpr (CLS == CLS_N32) {
+      if (qs < ((u64)1 << 43)) {
+        const double qsd = f64_from_u64(qs);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          double x = f64_from_u64(v[r]);
+          if (v[r] > half) x -= qsd;
+          lds_putw_at<CLS>(lds, lds_step(i0, r, T), (u32)f64_canon(x, m.qd, m.qinv));
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) lds_putw_at<CLS>(lds, lds_step(i0, r, T), (u32)lift_centered(v[r], qs, m));
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) lds_putw_at<CLS>(lds, lds_step(i0, r, T), lift_centered(v[r], qs, m));
+    }
   }
 }
 
@@ -177,7 +228,7 @@ template <int LOGN, bool FWD, int CLS>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
 k_ntt(u64* data, int n_limbs, int first_mod, Mods mods, Tables tb) {
   constexpr int N = 1 << LOGN;
-  __shared__ u64 lds[NttGeom<LOGN>::LDS];
+  __shared__ u64 lds[lds_words<LOGN, CLS>()];
   const int limb = blockIdx.x;
   const int mi = first_mod + limb;
   const ModConst m = mods.m[mi];
@@ -246,7 +297,7 @@ template <int LOGN, int CLS>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
 k_ks_digits(const KsJob* __restrict__ jobs, int count, u64* __restrict__ dcoef, int lmax, Mods mods, Tables tb) {
   constexpr int N = 1 << LOGN;
-  __shared__ u64 lds[NttGeom<LOGN>::LDS];
+  __shared__ u64 lds[lds_words<LOGN, CLS>()];
   const XcdSlot sl = xcd_slot(lmax);
   if (sl.job >= count) return;
   const int j = sl.sub;
@@ -293,34 +344,29 @@ __device__ __forceinline__ void modup_ip_body(u64* lds, const u64* __restrict__ 
       load_limb_perm<LOGN, CLS>(lds, jb.d + (size_t)j * N, jb.ginv);
       __syncthreads();
     } else {
-      const u64 qj = mods.m[j].q;
-      const u64* d = dcoef + (b * lmax + j) * N;
-      const int tid = opaque_tid();
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int i = tid + r * T;
-        lds_putw<CLS>(lds, i, lift_word<CLS>(d[i], qj, m));
-      }
+      lift_limb<LOGN, CLS>(lds, dcoef + (b * lmax + j) * N, mods.m[j].q, m, opaque_tid());
       fwd_lds<LOGN, CLS>(lds, tb, mi, m);
     }
     const u64* kb = key + (((size_t)j * 2 + 0) * (big_l + 1) + mi) * N;
     const u64* ka = key + (((size_t)j * 2 + 1) * (big_l + 1) + mi) * N;
     const int tid = opaque_tid();
+    const int i0 = lds_idx(tid);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int i = tid + r * T;
+      const int li = lds_step(i0, r, T);
       if constexpr (CLS == CLS_N32) {
-        const u32 dv = (u32)lds_get<CLS>(lds, i, m);
+        const u32 dv = (u32)to_canon<CLS>(lds_getw_at<CLS>(lds, li), m);
         // narrow key residues fit the low word of their u64 slot
         acc0[r] += (u64)dv * reinterpret_cast<const u32*>(kb)[2 * i];
         acc1[r] += (u64)dv * reinterpret_cast<const u32*>(ka)[2 * i];
       } else if constexpr (CLS == CLS_F64) {
-        const double dv = lds_getw<CLS>(lds, i);
+        const double dv = lds_getw_at<CLS>(lds, li);
         // centred products, summed unreduced (|sum| < 8.2 q for <= 15 digits)
         acc0[r] += f64_mulmod(dv, f64_from_u64(kb[i]), m.qd, m.qinv);
         acc1[r] += f64_mulmod(dv, f64_from_u64(ka[i]), m.qd, m.qinv);
       } else {
-        const u64 dv = lds_getw<CLS>(lds, i);
+        const u64 dv = lds_getw_at<CLS>(lds, li);
         acc0[r] = add_mod(acc0[r], mul_mod_t<false>(dv, kb[i], m), m.q);
         acc1[r] = add_mod(acc1[r], mul_mod_t<false>(dv, ka[i], m), m.q);
       }
@@ -355,7 +401,7 @@ template <int LOGN, int CLS>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
 k_ks_modup_ip(const KsJob* __restrict__ jobs, int count, const u64* __restrict__ dcoef, u64* __restrict__ u, int lmax,
               int pg, int big_l, Mods mods, Tables tb) {
-  __shared__ u64 lds[NttGeom<LOGN>::LDS];
+  __shared__ u64 lds[lds_words<LOGN, CLS>()];
   const XcdSlot sl = xcd_slot(lmax + pg);
   if (sl.job >= count) return;
   const size_t b = sl.job;
@@ -414,7 +460,7 @@ __global__ void __launch_bounds__(NttGeom<LOGN>::T)
 k_intt_last(const KsJob* __restrict__ jobs, int count, const u64* __restrict__ u, int lmax, int pg, int big_l,
             u64* __restrict__ rcoef, Mods mods, Tables tb) {
   constexpr int N = 1 << LOGN;
-  __shared__ u64 lds[NttGeom<LOGN>::LDS];
+  __shared__ u64 lds[lds_words<LOGN, CLS>()];
   const XcdSlot sl = xcd_slot(2);  // grid xcd_grid(2, count): workgroup (job b, polynomial comp)
   if (sl.job >= count) return;
   const size_t b = sl.job;
@@ -476,27 +522,23 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
     }
     return;
   }
-  const u64 qd = mods.m[div_mi].q;
-  const u64* rc = rcoef + (b * 2 + comp) * N;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int i = (int)threadIdx.x + r * T;
-    lds_putw<CLS>(lds, i, lift_word<CLS>(rc[i], qd, m));
-  }
+  lift_limb<LOGN, CLS>(lds, rcoef + (b * 2 + comp) * N, mods.m[div_mi].q, m, (int)threadIdx.x);
   fwd_lds<LOGN, CLS>(lds, tb, t, m);
   const u64* s = (MODE == MODE_P) ? u + ((b * 2 + comp) * urows + t) * N
                                   : jb.d + ((size_t)comp * level + t) * N;
   const u64 iv = inv_tab[div_mi * HE_MAXM + t];
   const u64 ivs = inv_tab[HE_MAXM * HE_MAXM + div_mi * HE_MAXM + t];
   V val[16];
+  const int i0 = lds_idx((int)threadIdx.x);
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int i = (int)threadIdx.x + r * T;
+    const int li = lds_step(i0, r, T);
     if constexpr (CLS == CLS_F64) {
-      const double dlt = f64_from_u64(s[i]) - lds_getw<CLS>(lds, i);
+      const double dlt = f64_from_u64(s[i]) - lds_getw_at<CLS>(lds, li);
       val[r] = to_canon<CLS>(f64_mulmod(dlt, f64_from_u64(iv), m.qd, m.qinv), m);
     } else {
-      val[r] = (V)shoupm<NW>(subm<NW>(s[i], lds_get<CLS>(lds, i, m), m.q), iv, ivs, m.q);
+      val[r] = (V)shoupm<NW>(subm<NW>(s[i], to_canon<CLS>(lds_getw_at<CLS>(lds, li), m), m.q), iv, ivs, m.q);
     }
   }
   if constexpr (EPI == EPI_STORE) {
@@ -527,7 +569,7 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int i = (int)threadIdx.x + r * T;
-        u64 x = addm<NW>(lds_get<PC>(lds, i, m), val[r], m.q);  // sigma_g(c0) + u0
+        u64 x = addm<NW>((u64)lds_getw_at<PC>(lds, lds_step(i0, r, T)), val[r], m.q);  // sigma_g(c0) + u0
         if constexpr (EPI == EPI_ROTSUM) x = addm<NW>(x, own[r], m.q);
         o[i] = x;
       }
@@ -552,7 +594,7 @@ template <int LOGN, int MODE, int EPI, int CLS>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
 k_drop_last(const KsJob* __restrict__ jobs, int count, int kmax, const u64* __restrict__ u, int urows, int big_l,
             const u64* __restrict__ rcoef, const u64* __restrict__ inv_tab, Mods mods, Tables tb) {
-  __shared__ u64 lds[NttGeom<LOGN>::LDS];
+  __shared__ u64 lds[lds_words<LOGN, CLS>()];
   const XcdSlot sl = xcd_slot(2 * kmax);
   if (sl.job >= count) return;
   const size_t b = sl.job;
@@ -586,13 +628,7 @@ __device__ __forceinline__ void modup_store_body(u64* lds, const u64* __restrict
     for (int r = 0; r < 16; ++r) out[(int)threadIdx.x + r * T] = src[(int)threadIdx.x + r * T];
     return;
   }
-  const u64 qj = mods.m[j].q;
-  const u64* d = dcoef + (size_t)j * N;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int i = (int)threadIdx.x + r * T;
-    lds_putw<CLS>(lds, i, lift_word<CLS>(d[i], qj, m));
-  }
+  lift_limb<LOGN, CLS>(lds, dcoef + (size_t)j * N, mods.m[j].q, m, (int)threadIdx.x);
   fwd_lds<LOGN, CLS>(lds, tb, mi, m);
   store_limb<LOGN, CLS>(out, lds, m, false);
 }
@@ -601,7 +637,7 @@ template <int LOGN, int CLS>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
 k_modup_store(const u64* __restrict__ dcoef, const u64* __restrict__ c1, u64* __restrict__ dhat, int level, int big_l,
               Mods mods, Tables tb) {
-  __shared__ u64 lds[NttGeom<LOGN>::LDS];
+  __shared__ u64 lds[lds_words<LOGN, CLS>()];
   const int mi = ((int)blockIdx.x < level) ? (int)blockIdx.x : big_l;
   if ((int)mods.m[mi].cls != CLS) return;
   modup_store_body<LOGN, CLS>(lds, dcoef, c1, dhat, level, big_l, mods, tb);

@@ -55,6 +55,14 @@ using word_t = typename Word<CLS>::W;
 
 __device__ __forceinline__ int lds_idx(int i) { return i + (i >> 5); }
 
+// lds_idx(i0 + r * stride) from lds_idx(i0), for stride a power of two and
+// i0 mod stride + (r * stride) mod 32 < 32 (true for the element sets of a
+// butterfly pass, where i0 mod 32 < stride or stride >= 32, and for the
+// coalesced sets tid + r * T with 32 | T).  The added part is a compile-time
+// constant once r and stride are, so it folds into the LDS instruction's
+// immediate offset.
+__device__ __forceinline__ int lds_step(int idx0, int r, int stride) { return idx0 + r * stride + ((r * stride) >> 5); }
+
 template <int LOGN>
 struct NttGeom {
   static constexpr int N = 1 << LOGN;
@@ -62,6 +70,13 @@ struct NttGeom {
   static constexpr int T = N / E;        // threads per workgroup
   static constexpr int LDS = N + (N >> 5);  // 64-bit words reserved (narrow limbs use half)
 };
+
+// 64-bit words of LDS a transform workgroup of class CLS declares: narrow
+// limbs are 32-bit words, so half (more workgroups fit a CU).
+template <int LOGN, int CLS>
+constexpr int lds_words() {
+  return CLS == CLS_N32 ? NttGeom<LOGN>::LDS / 2 : NttGeom<LOGN>::LDS;
+}
 
 // Modulus as seen by the butterflies of one class.
 template <int CLS>
@@ -112,6 +127,15 @@ __device__ __forceinline__ void lds_putw(u64* lds, int i, word_t<CLS> v) {
 template <int CLS>
 __device__ __forceinline__ word_t<CLS> lds_getw(const u64* lds, int i) {
   return reinterpret_cast<const word_t<CLS>*>(lds)[lds_idx(i)];
+}
+// The same at an already padded index (lds_idx / lds_step).
+template <int CLS>
+__device__ __forceinline__ void lds_putw_at(u64* lds, int idx, word_t<CLS> v) {
+  reinterpret_cast<word_t<CLS>*>(lds)[idx] = v;
+}
+template <int CLS>
+__device__ __forceinline__ word_t<CLS> lds_getw_at(const u64* lds, int idx) {
+  return reinterpret_cast<const word_t<CLS>*>(lds)[idx];
 }
 template <int CLS>
 __device__ __forceinline__ void lds_put(u64* lds, int i, u64 v) {
@@ -214,9 +238,10 @@ __device__ __forceinline__ void fwd_pass(u64* lds_raw, int s0, Tw<CLS> tw, MV<CL
     const int blk = g >> logW;
     const int off = g & (Wd - 1);
     const int base = blk * B0 + off;
+    const int b0 = lds_idx(base);
     W v[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = lds[lds_idx(base + r * Wd)];
+    for (int r = 0; r < R; ++r) v[r] = lds[lds_step(b0, r, Wd)];
 #pragma unroll
     for (int u = 0; u < K; ++u) {
       const int half = R >> (u + 1);
@@ -232,7 +257,7 @@ __device__ __forceinline__ void fwd_pass(u64* lds_raw, int s0, Tw<CLS> tw, MV<CL
       }
     }
 #pragma unroll
-    for (int r = 0; r < R; ++r) lds[lds_idx(base + r * Wd)] = v[r];
+    for (int r = 0; r < R; ++r) lds[lds_step(b0, r, Wd)] = v[r];
   }
 }
 
@@ -255,9 +280,10 @@ __device__ __forceinline__ void inv_pass(u64* lds_raw, int s0, Tw<CLS> tw, MV<CL
     const int blk = g >> logW;
     const int off = g & (Wd - 1);
     const int base = blk * B0 + off;
+    const int b0 = lds_idx(base);
     W v[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[r] = lds[lds_idx(base + r * Wd)];
+    for (int r = 0; r < R; ++r) v[r] = lds[lds_step(b0, r, Wd)];
 #pragma unroll
     for (int u = K - 1; u >= 0; --u) {
       const int half = R >> (u + 1);
@@ -273,7 +299,7 @@ __device__ __forceinline__ void inv_pass(u64* lds_raw, int s0, Tw<CLS> tw, MV<CL
       }
     }
 #pragma unroll
-    for (int r = 0; r < R; ++r) lds[lds_idx(base + r * Wd)] = v[r];
+    for (int r = 0; r < R; ++r) lds[lds_step(b0, r, Wd)] = v[r];
   }
 }
 
