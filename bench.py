@@ -40,6 +40,27 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9
 DOMINANT = "ks_modup_stage"
 
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (each
+# scaled by what the counter reads for a 1 GiB device copy: x2.0 / x1.0),
+# valid only for the kernel sources they were measured on: bench.py reports
+# them when these sources hash to KERNEL_SHA256, else null.
+KERNEL_SOURCES = ("modarith.h", "ntt_lds.h", "kernels.h", "capi.hip")
+KERNEL_SHA256 = None
+TRAFFIC_BYTES = {"ks_modup_stage": None, "ip_perm": None}
+
+
+def kernel_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2102_03494_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    return TRAFFIC_BYTES.get(kernel) if KERNEL_SHA256 is not None and kernel_sha256() == KERNEL_SHA256 else None
+
 # Algorithmic operation counts (VALU lane ops; an FP64 multiply, FMA or add
 # counts as one, as it issues at the 32-bit rate) of the key-switch work per
 # width class: narrow = 30-bit primes in 32-bit words (Harvey butterflies,
@@ -171,7 +192,7 @@ def hoisted_section(torch, steps: int):
         "rotations_per_s": m / t_h,
         "roofline": {"kernel": "k_ip_perm (key inner product of all 256 rotations, one launch)",
                      "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": None, "avg_launch_ms": avg,
+                     "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic("ip_perm"), "avg_launch_ms": avg,
                      "algorithmic_bytes_per_launch": ip_bytes},
     }
 
@@ -477,7 +498,8 @@ def main():
                   "streams; per launch one rotate-and-add step of 288 ciphertexts at level 4 "
                   "(plus one relinearisation launch per layer)",
         "bound": "alu", "achieved": achieved_ops / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-        "unit": "Tops/s (VALU lane ops)", "frac": achieved_ops / VALU_PEAK_OPS, "traffic": None,
+        "unit": "Tops/s (VALU lane ops)", "frac": achieved_ops / VALU_PEAK_OPS,
+        "traffic": measured_traffic("ks_modup_stage"),
         "avg_launch_ms": avg_ms, "launches": dom_launches, "p_groups": pg,
         "algorithmic_ops_per_launch": ops,
         "hbm_gbs_algorithmic": bytes_layer / launches_layer / (avg_ms * 1e-3) / 1e9,

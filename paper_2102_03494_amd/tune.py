@@ -32,7 +32,10 @@ def ring_key(n: int, q_bits, p_bits: int) -> str:
 
 def _device_name() -> str:
     import torch
-    return torch.cuda.get_device_name(0) if torch.cuda.is_available() else "none"
+    if not torch.cuda.is_available():
+        return "none"
+    props = torch.cuda.get_device_properties(0)
+    return f"{torch.cuda.get_device_name(0)} ({getattr(props, 'gcnArchName', '?')})"
 
 
 def load_cache(path: str = CACHE) -> dict:
@@ -61,7 +64,7 @@ def apply(ctx, path: str = CACHE) -> str:
     return "cache"
 
 
-def tune(ctx, batch: int = 288, reps: int = 3, levels=None) -> dict:
+def tune(ctx, batch: int = 288, reps: int = 8, levels=None) -> dict:
     """Fastest p_groups per level for one rotate-and-add step over `batch`
     ciphertexts (uniform random residues: timing does not depend on them)."""
     import numpy as np
@@ -103,13 +106,14 @@ def main(argv=None):
     ap.add_argument("--q", required=True, help="comma-separated prime sizes, e.g. 30,30,30,30")
     ap.add_argument("--p", type=int, required=True)
     ap.add_argument("--batch", type=int, default=288)
+    ap.add_argument("--reps", type=int, default=8)
     ap.add_argument("--write", action="store_true", help="store the result in the cache")
     ap.add_argument("--cache", default=CACHE)
     args = ap.parse_args(argv)
     from .he import HEContext
     q_bits = tuple(int(b) for b in args.q.split(","))
     ctx = HEContext(args.n, q_bits, args.p)
-    res = tune(ctx, args.batch)
+    res = tune(ctx, args.batch, args.reps)
     entry = {"p_groups": {str(k): v["best"] for k, v in res.items()},
              "ms_per_step": {str(k): {str(pg): round(t, 4) for pg, t in v["ms"].items()} for k, v in res.items()},
              "batch": args.batch, "device": _device_name()}
