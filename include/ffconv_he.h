@@ -354,10 +354,11 @@ int he_last_counts(const he_ctx *ctx, he_counts *out);
 
 /* ---- instrumentation (not part of the evaluated path) ---------------------
  * he_prof_select: from now on every launch of the kernel named `kernel`
- * ("ntt", "ks_digits", "ks_modup_ip" (narrow targets), "ks_modup_ip_f64" and
- * "ks_modup_ip_wide" (the other width classes, launched on a second stream
- * when more than one class is present), "ks_modup_stage" (the ModUp kernels
- * of all classes together, fork to join), "intt_last", "drop_last",
+ * ("ntt", "ks_digits", "ks_modup_stage" (the ModUp + inner-product work of
+ * a key switch: one kernel when the ring's primes span one or two width
+ * classes, else one per class on two streams, fork to join),
+ * "ks_modup_ip" / "ks_modup_ip_f64" / "ks_modup_ip_wide" (the per-class
+ * kernels of the three-class case), "intt_last", "drop_last",
  * "dp_hma", "hma_perm", "scalar_mac", "tensor_sq", "modup_store", "ip_perm",
  * "add") is bracketed by two HIP events recorded on the stream it is launched
  * on; NULL or "" stops recording.  he_prof_read waits for the recorded events and

@@ -232,9 +232,10 @@ struct LNtt {
 };
 
 // Key switch of a job batch: digits -> ModUp + inner product -> INTT of P.
-// The ModUp kernel of each width class present runs on its own stream (the
-// caller's for the first, the side stream for the others), joined before the
-// P INTT.
+// ModUp is one launch when the ring's primes span one or two width classes
+// (each workgroup runs its target's class); with all three, the kernel of
+// each class runs on its own stream (the caller's for the first, the side
+// stream for the others), joined before the P INTT.
 template <int LOGN>
 struct LKsCore {
   static void run(he_ctx* c, const KsJob* jobs, int count, int lmax, int pg, u64* dcoef, u64* u, u64* rc,
@@ -247,7 +248,20 @@ struct LKsCore {
     }
     const unsigned grid = xcd_grid(lmax + pg, count);
     static const char* names[3] = {"ks_modup_ip", "ks_modup_ip_f64", "ks_modup_ip_wide"};
-    const bool forked = (int)c->has_cls[0] + (int)c->has_cls[1] + (int)c->has_cls[2] > 1;
+    const int n_cls = (int)c->has_cls[0] + (int)c->has_cls[1] + (int)c->has_cls[2];
+    if (n_cls == 2) {  // one launch, each workgroup in its target's class
+      Prof stage(c, "ks_modup_stage", s);
+      if (!c->has_cls[CLS_U64])
+        k_ks_modup_ip2<LOGN, CLS_N32, CLS_F64><<<grid, T, 0, s>>>(jobs, count, dcoef, u, lmax, pg, c->big_l, c->mods,
+                                                                   c->tb());
+      else if (!c->has_cls[CLS_F64])
+        k_ks_modup_ip2<LOGN, CLS_N32, CLS_U64><<<grid, T, 0, s>>>(jobs, count, dcoef, u, lmax, pg, c->big_l, c->mods,
+                                                                   c->tb());
+      else
+        k_ks_modup_ip2<LOGN, CLS_F64, CLS_U64><<<grid, T, 0, s>>>(jobs, count, dcoef, u, lmax, pg, c->big_l, c->mods,
+                                                                   c->tb());
+    } else {
+    const bool forked = n_cls > 1;
     {
       Prof stage(c, "ks_modup_stage", s);  // wall time of all classes together
       if (forked) {  // the side stream starts after the digits, not after the first ModUp kernel
@@ -274,6 +288,7 @@ struct LKsCore {
         (void)hipEventRecord(c->join_ev, c->side);
         (void)hipStreamWaitEvent(s, c->join_ev, 0);
       }
+    }
     }
     Prof pr(c, "intt_last", s);
     HE_FOR_CLASSES(1u << c->p_cls, (k_intt_last<LOGN, MODE_P, CLS><<<xcd_grid(2, count), T, 0, s>>>(

@@ -431,6 +431,44 @@ k_ks_modup_ip(const KsJob* __restrict__ jobs, int count, const u64* __restrict__
 // INTT of the limb that is divided out: for polynomial p = 2 b + comp,
 //   MODE_P:    the P limb of u (ModDown after a key switch);
 //   MODE_LAST: the last limb of the ciphertext jobs[b].d (rescale).
+// The same for a ring whose primes span two width classes A and B: one
+// launch in which each workgroup runs the body of its target's class (both
+// bodies hold one workgroup per CU anyway), instead of one kernel per class
+// on two streams joined by events.
+template <int LOGN, int CA, int CB>
+__global__ void __launch_bounds__(NttGeom<LOGN>::T)
+k_ks_modup_ip2(const KsJob* __restrict__ jobs, int count, const u64* __restrict__ dcoef, u64* __restrict__ u, int lmax,
+               int pg, int big_l, Mods mods, Tables tb) {
+  constexpr int LW = lds_words<LOGN, CA>() > lds_words<LOGN, CB>() ? lds_words<LOGN, CA>() : lds_words<LOGN, CB>();
+  __shared__ u64 lds[LW];
+  const XcdSlot sl = xcd_slot(lmax + pg);
+  if (sl.job >= count) return;
+  const size_t b = sl.job;
+  const KsJob jb = jobs[b];
+  if (jb.key == nullptr) return;
+  const int x = sl.sub;
+  const int level = jb.level;
+  int t, mi, j0, j1, row;
+  if (x < lmax) {
+    if (x >= level) return;
+    t = mi = row = x;
+    j0 = 0;
+    j1 = level;
+  } else {
+    const int g = pgroup_size(level, pg);
+    j0 = (x - lmax) * g;
+    if (j0 >= level) return;
+    j1 = min(j0 + g, level);
+    t = -1;
+    mi = big_l;
+    row = x;
+  }
+  if ((int)mods.m[mi].cls == CA)
+    modup_ip_body<LOGN, CA>(lds, dcoef, jb, b, u, lmax, lmax + pg, big_l, t, mi, j0, j1, row, mods, tb);
+  else
+    modup_ip_body<LOGN, CB>(lds, dcoef, jb, b, u, lmax, lmax + pg, big_l, t, mi, j0, j1, row, mods, tb);
+}
+
 enum { MODE_P = 0, MODE_LAST = 1 };
 
 // Coefficient-domain copy of the P limb of u: the sum of its group partials

@@ -297,6 +297,9 @@ __device__ __forceinline__ void inv_pass(u64* lds_raw, int s0, Tw<CLS> tw, MV<CL
         v[r] = A::add_inv(x, y, q);
         v[r + half] = A::mulc(A::sub_inv(x, y, q), tw.w[ti], CLS == CLS_F64 ? W(0) : tw.sh[ti], q);
       }
+      // f64: load the next stage's twiddles after this stage, so only one
+      // stage's are live (measured faster for the f64 inverse transform)
+      if constexpr (CLS == CLS_F64) __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) lds[lds_step(b0, r, Wd)] = v[r];
