@@ -96,7 +96,9 @@ const char *he_last_error(const he_ctx *ctx);
  * here; no effect on any result bit, only on speed).  knob "p_groups": the
  * number of workgroups (1..min(level, 4)) that share the ModUp + inner
  * product into the special prime P at key-switch level `level` (1..L);
- * value 0 restores the built-in cost model.  he_ctx_set_tuning returns
+ * value 0 restores the built-in cost model.  knob "split_streams" (level
+ * ignored; 1 by default, 0 or 1): run the rotate-and-sum of a DensePack
+ * layer's outputs as two halves on two streams.  he_ctx_set_tuning returns
  * HE_EINVAL for an unknown knob or out-of-range level/value;
  * he_ctx_get_tuning returns the value in effect (>= 1) or a negative code. */
 int he_ctx_set_tuning(he_ctx *ctx, const char *knob, int level, int value);

@@ -42,6 +42,7 @@ struct he_ctx {
   u64* d_inv = nullptr;   // [2][HE_MAXM][HE_MAXM]: m_div^-1 mod q_t and Shoup components
   Tables tb() const { return Tables{d_tw, d_tw32, d_twf}; }
   int pg_set[HE_MAXM + 1] = {};  // P groups per key-switch level (0 = cost model)
+  int split_streams = 1;         // DensePack rotate-and-sum in two halves on two streams
   char* ws = nullptr;
   size_t ws_bytes = 0;
   std::map<int, u64*> keys;  // Galois element (0 = relinearisation) -> [L][2][L+1][N]
@@ -137,6 +138,14 @@ struct Arena {
     return p;
   }
   size_t left() const { return cap - used; }
+  // The remaining space split into two disjoint arenas of about half each.
+  void halves(Arena& lo, Arena& hi) const {
+    const size_t mid = used + ((left() / 2) & ~(size_t)255);
+    lo = *this;
+    lo.cap = mid;
+    hi = *this;
+    hi.used = mid;
+  }
 };
 
 u32 galois_of(int k, int n) {
@@ -600,12 +609,37 @@ int densepack_run(he_ctx* c, const u64* d_in, int level, const he_conv_desc* des
     u64* acc = sub.take<u64>((size_t)cn * 2 * level * n);
     if (!acc) return fail(c, HE_ENOMEM, "workspace too small");
     dispatch_logn<LDpHma>(c->logn, c, d_in, d_filt, acc, level, o0, cn, geo, s);
-    for (int j = 0; j < desc->r_steps; ++j) {
-      int e = rotate_batch(c, acc, acc, cn, level, 1 << j, EPI_ROTSUM, sub, s);
+    u64* out = d_out + (size_t)o0 * 2 * (level - 1) * n;
+    const int n_cls = (int)c->has_cls[0] + (int)c->has_cls[1] + (int)c->has_cls[2];
+    if (c->split_streams && cn >= 64 && n_cls <= 2) {
+      // The outputs are independent chains through the rotate-and-add steps:
+      // two halves on two streams fill each other's kernel tails; one fork
+      // and one join per chunk, each half with its own scratch.
+      const int h0 = cn / 2, h1 = cn - h0;
+      u64* acc1 = acc + (size_t)h0 * 2 * level * n;
+      u64* out1 = out + (size_t)h0 * 2 * (level - 1) * n;
+      Arena a0 = sub, a1 = sub;
+      sub.halves(a0, a1);
+      (void)hipEventRecord(c->fork_ev, s);
+      (void)hipStreamWaitEvent(c->side, c->fork_ev, 0);
+      int e = HE_OK;
+      for (int j = 0; j < desc->r_steps && !e; ++j) {
+        e = rotate_batch(c, acc, acc, h0, level, 1 << j, EPI_ROTSUM, a0, s);
+        if (!e) e = rotate_batch(c, acc1, acc1, h1, level, 1 << j, EPI_ROTSUM, a1, c->side);
+      }
+      if (!e) e = rescale_batch(c, out, acc, h0, level, a0, s);
+      if (!e) e = rescale_batch(c, out1, acc1, h1, level, a1, c->side);
+      (void)hipEventRecord(c->join_ev, c->side);
+      (void)hipStreamWaitEvent(s, c->join_ev, 0);
+      if (e) return e;
+    } else {
+      for (int j = 0; j < desc->r_steps; ++j) {
+        int e = rotate_batch(c, acc, acc, cn, level, 1 << j, EPI_ROTSUM, sub, s);
+        if (e) return e;
+      }
+      int e = rescale_batch(c, out, acc, cn, level, sub, s);
       if (e) return e;
     }
-    int e = rescale_batch(c, d_out + (size_t)o0 * 2 * (level - 1) * n, acc, cn, level, sub, s);
-    if (e) return e;
   }
   c->counts.mulpc += (int64_t)total * geo.m_cts;
   c->counts.addcc += (int64_t)total * (geo.m_cts - 1) + (int64_t)total * desc->r_steps;
@@ -895,6 +929,11 @@ const char* he_last_error(const he_ctx* c) { return c ? c->err.c_str() : "null c
 
 int he_ctx_set_tuning(he_ctx* c, const char* knob, int level, int value) {
   if (!c || !knob) return HE_EINVAL;
+  if (std::strcmp(knob, "split_streams") == 0) {
+    if (value < 0 || value > 1) return fail(c, HE_EINVAL, "he_ctx_set_tuning: split_streams is 0 or 1");
+    c->split_streams = value;
+    return HE_OK;
+  }
   if (std::strcmp(knob, "p_groups") != 0) return fail(c, HE_EINVAL, "he_ctx_set_tuning: unknown knob '%s'", knob);
   if (level < 1 || level > c->big_l || value < 0 || value > std::min(level, PG_MAX))
     return fail(c, HE_EINVAL, "he_ctx_set_tuning: p_groups %d out of range at level %d", value, level);
@@ -903,7 +942,9 @@ int he_ctx_set_tuning(he_ctx* c, const char* knob, int level, int value) {
 }
 
 int he_ctx_get_tuning(const he_ctx* c, const char* knob, int level) {
-  if (!c || !knob || std::strcmp(knob, "p_groups") != 0 || level < 1 || level > c->big_l) return HE_EINVAL;
+  if (!c || !knob) return HE_EINVAL;
+  if (std::strcmp(knob, "split_streams") == 0) return c->split_streams;
+  if (std::strcmp(knob, "p_groups") != 0 || level < 1 || level > c->big_l) return HE_EINVAL;
   return p_groups(c, level);
 }
 

@@ -147,6 +147,30 @@ def test_p_groups_do_not_change_bits():
         gctx.set_tuning("p_groups", 4, 5)
 
 
+def test_split_streams_do_not_change_bits():
+    """DensePack with its outputs in two halves on two streams gives the one-stream bits."""
+    p, octx, gctx, cl = _small_setup(rotations=[1 << j for j in range(9)])
+    geom = C.ConvGeom(9, 9, 2, 3, 1, 1)
+    x = synth.image(W, (9, 9, 2), index=3)
+    w = synth.weights(W, 31, (3, 3, 2, 2), 0.3)
+    ct = Wk.encrypt_slots(octx, C.densepack_slots(x, geom, p.slots)[0], 3, p.scale, W, 9)
+    pts = C.densepack_pt_scale(p, 3, p.scale, p.scale)
+    bf = C.densepack_base_filters(p, w, geom, 3, pts)
+    he = _he()
+    desc = he.HEContext.conv_desc(9, 9, 2, 3, 1, 1, 2, 9)
+    outs = {}
+    for split in (0, 1):
+        gctx.set_tuning("split_streams", 0, split)
+        assert gctx.get_tuning("split_streams", 0) == split
+        outs[split] = _host(gctx.conv_densepack(he.Ct(_dev(ct.c[None]), p.scale), desc, _dev(bf), pts).data)
+    assert outs[0].shape[0] == 162  # 81 outputs x 2 channels: split into halves of 81
+    assert np.array_equal(outs[0], outs[1])
+    sample = [0, 80, 81, 161]
+    want, _ = C.conv_densepack(p, octx, ct, geom, bf, pts, outputs=[C.output_list(geom, 2)[i] for i in sample])
+    for k, i in enumerate(sample):
+        assert np.array_equal(outs[1][i], want.c[k]), i
+
+
 def test_rotate_hoisted_bit_exact():
     steps = [1, 2, 5, 17, 255, -3]
     p, octx, gctx, cl = _small_setup(rotations=steps)
