@@ -45,8 +45,11 @@ DOMINANT = "ks_modup_stage"
 # valid only for the kernel sources they were measured on: bench.py reports
 # them when these sources hash to KERNEL_SHA256, else null.
 KERNEL_SOURCES = ("modarith.h", "ntt_lds.h", "kernels.h", "capi.hip")
-KERNEL_SHA256 = None
-TRAFFIC_BYTES = {"ks_modup_stage": None, "ip_perm": None}
+KERNEL_SHA256 = "cc482ea255264cc53ca7d1ff2cf37c50832750804e7f8f7f92856b4fa8f03054"
+# ks_modup_stage: mean over one layer's 25 launches (24 of 144 jobs at
+# 268.7 MB, one relinearisation launch of 5 jobs at 8.7 MB); ip_perm: one
+# launch over all 256 rotations
+TRAFFIC_BYTES = {"ks_modup_stage": 258295698, "ip_perm": 4454506709}
 
 
 def kernel_sha256() -> str:
@@ -451,7 +454,7 @@ def main():
         z = ffconv_step()
     torch.cuda.synchronize()
     t_ff = (time.perf_counter() - t0) / args.steps
-    dom_ms, dom_launches = ctx.prof_read()
+    dom_ms, dom_busy_ms, dom_launches = ctx.prof_read_busy()
     ctx.prof_select(None)
     counts_ff = ctx.last_counts()
     print(f"# ffconv: {t_ff * 1e3:.3f} ms/layer", file=sys.stderr, flush=True)
@@ -483,30 +486,38 @@ def main():
     hma_ff = counts_ff["mulpc"] + counts_ff["scalar_mul"]
     level = len(Q_BITS)
     pg = ctx.get_tuning("p_groups", level)
-    # the timed region also holds the 5 relinearisations of x^2 (level 2,
-    # 5 ciphertexts): count their ops with the 12 rotate-and-add steps
+    split = ctx.get_tuning("split_streams", 0)
+    # the timed region holds, per layer, 12 rotate-and-add steps of the 288 W1
+    # outputs (as two launches of 144 on two streams when split) and the 5
+    # relinearisations of x^2 (level 2)
     ops_layer = 12 * modup_ip_ops(288, level, N, ctx.moduli, pg) + \
         modup_ip_ops(5, 2, N, ctx.moduli[:2] + ctx.moduli[-1:], ctx.get_tuning("p_groups", 2))
     bytes_layer = 12 * modup_ip_bytes(288, level, N) + modup_ip_bytes(5, 2, N)
-    launches_layer = 13
+    launches_layer = 12 * (2 if split else 1) + 1
     avg_ms = dom_ms / max(1, dom_launches)
-    ops = ops_layer / launches_layer
-    achieved_ops = ops / (avg_ms * 1e-3)
+    layers = dom_launches / launches_layer
+    ops_per_launch = ops_layer / launches_layer
+    # throughput while the stage runs: all its algorithmic work over the time
+    # at least one of its launches was running (two overlap when split)
+    achieved_ops = ops_layer * layers / (dom_busy_ms * 1e-3)
+    per_launch_ops = ops_per_launch / (avg_ms * 1e-3)
     roofline = {
-        "kernel": "ModUp + key inner product stage: k_ks_modup_ip<13, narrow> (the 30-bit targets) and "
-                  "k_ks_modup_ip<13, f64> (P, split over p_groups digit groups) running concurrently on two "
-                  "streams; per launch one rotate-and-add step of 288 ciphertexts at level 4 "
-                  "(plus one relinearisation launch per layer)",
+        "kernel": "k_ks_modup_ip2<13, narrow, f64>: ModUp NTTs + key inner product into the four 30-bit primes and "
+                  "P (f64, p_groups digit groups), one launch per rotate-and-add step of the 288 W1 outputs at level 4 "
+                  "(two concurrent launches of 144 when split_streams), plus one relinearisation launch per layer",
         "bound": "alu", "achieved": achieved_ops / 1e12, "peak": VALU_PEAK_OPS / 1e12,
         "unit": "Tops/s (VALU lane ops)", "frac": achieved_ops / VALU_PEAK_OPS,
         "traffic": measured_traffic("ks_modup_stage"),
-        "avg_launch_ms": avg_ms, "launches": dom_launches, "p_groups": pg,
-        "algorithmic_ops_per_launch": ops,
-        "hbm_gbs_algorithmic": bytes_layer / launches_layer / (avg_ms * 1e-3) / 1e9,
+        "avg_launch_ms": avg_ms, "launches": dom_launches, "busy_ms": dom_busy_ms,
+        "concurrency": dom_ms / dom_busy_ms if dom_busy_ms > 0 else None,
+        "algorithmic_ops_per_launch": ops_per_launch,
+        "per_launch_achieved": per_launch_ops / 1e12,
+        "p_groups": pg, "split_streams": split,
+        "hbm_gbs_algorithmic": bytes_layer * layers / (dom_busy_ms * 1e-3) / 1e9,
     }
-
     tuning = {"source": ctx.tuning_source,
-              "p_groups": {lv: ctx.get_tuning("p_groups", lv) for lv in range(1, len(Q_BITS) + 1)}}
+              "p_groups": {lv: ctx.get_tuning("p_groups", lv) for lv in range(1, len(Q_BITS) + 1)},
+              "split_streams": split}
 
     batched = None
     if args.batched_layers > 0:

@@ -368,6 +368,10 @@ int he_last_counts(const he_ctx *ctx, he_counts *out);
  * last select or read, then clears them. */
 int he_prof_select(he_ctx *ctx, const char *kernel);
 int he_prof_read(he_ctx *ctx, double *total_ms, int64_t *launches);
+/* he_prof_read_busy: as he_prof_read, plus the time (ms) during which at least
+ * one bracketed launch was running (the union of their intervals; launches on
+ * two streams overlap, so busy_ms <= total_ms). */
+int he_prof_read_busy(he_ctx *ctx, double *total_ms, double *busy_ms, int64_t *launches);
 
 #ifdef __cplusplus
 }

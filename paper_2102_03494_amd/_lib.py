@@ -91,6 +91,7 @@ SIGNATURES = {
     "he_graph_destroy": (I, [P]),
     "he_last_counts": (I, [P, ctypes.POINTER(HeCounts)]),
     "he_prof_select": (I, [P, ctypes.c_char_p]),
+    "he_prof_read_busy": (I, [P, DP, DP, ctypes.POINTER(ctypes.c_int64)]),
     "he_prof_read": (I, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
 }
 

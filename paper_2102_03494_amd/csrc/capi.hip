@@ -1456,6 +1456,42 @@ int he_prof_select(he_ctx* c, const char* kernel) {
   return he_prof_read(c, &ms, &n);
 }
 
+int he_prof_read_busy(he_ctx* c, double* total_ms, double* busy_ms, int64_t* launches) {
+  if (!c || !total_ms || !busy_ms || !launches) return HE_EINVAL;
+  std::vector<std::pair<double, double>> iv;
+  double sum = 0;
+  if (!c->prof_events.empty()) {
+    hipEvent_t ref = c->prof_events.front().first;
+    for (auto& pr : c->prof_events) {
+      float a = 0, b = 0;
+      if (hipEventSynchronize(pr.second) != hipSuccess || hipEventElapsedTime(&a, ref, pr.first) != hipSuccess ||
+          hipEventElapsedTime(&b, ref, pr.second) != hipSuccess)
+        return fail(c, HE_EDEVICE, "he_prof_read_busy: event failure");
+      iv.push_back({a, b});
+      sum += b - a;
+    }
+  }
+  std::sort(iv.begin(), iv.end());
+  double busy = 0, cs = 0, ce = -1;
+  for (auto& x : iv) {
+    if (x.first > ce) {
+      if (ce > cs) busy += ce - cs;
+      cs = x.first;
+      ce = x.second;
+    } else if (x.second > ce) {
+      ce = x.second;
+    }
+  }
+  if (ce > cs) busy += ce - cs;
+  *busy_ms = busy;
+  double total = 0;
+  int64_t n = 0;
+  int e = he_prof_read(c, &total, &n);
+  *total_ms = sum;
+  *launches = n;
+  return e;
+}
+
 int he_prof_read(he_ctx* c, double* total_ms, int64_t* launches) {
   if (!c || !total_ms || !launches) return HE_EINVAL;
   double sum = 0;

@@ -190,6 +190,15 @@ class HEContext:
         self._check(self.lib.he_prof_read(self.h, ctypes.byref(ms), ctypes.byref(n)), "he_prof_read")
         return float(ms.value), int(n.value)
 
+    def prof_read_busy(self) -> tuple[float, float, int]:
+        """(summed kernel ms, ms with at least one bracketed launch running, launches)."""
+        ms = ctypes.c_double()
+        busy = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._check(self.lib.he_prof_read_busy(self.h, ctypes.byref(ms), ctypes.byref(busy), ctypes.byref(n)),
+                    "he_prof_read_busy")
+        return float(ms.value), float(busy.value), int(n.value)
+
     # ---- transforms ----------------------------------------------------------
     def ntt(self, polys: torch.Tensor, first_mod: int = 0):
         n_limbs = polys.shape[-2]
