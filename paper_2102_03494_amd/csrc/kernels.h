@@ -114,8 +114,10 @@ __device__ __forceinline__ void load_limb_perm(u64* lds, const u64* __restrict__
 }
 
 // Store the LDS limb as canonical residues, optionally scaled by N^-1 (after
-// an inverse transform).
-template <int LOGN, int CLS>
+// an inverse transform).  PACK: a narrow limb goes out as N 32-bit words at
+// the start of its row (the layout of coefficient-domain scratch rows, which
+// lift_limb reads); otherwise every residue takes a 64-bit word.
+template <int LOGN, int CLS, bool PACK = false>
 __device__ __forceinline__ void store_limb(u64* __restrict__ dst, const u64* lds, const ModConst& m, bool scale) {
   constexpr int T = NttGeom<LOGN>::T;
   const int i0 = lds_idx((int)threadIdx.x);
@@ -130,7 +132,8 @@ __device__ __forceinline__ void store_limb(u64* __restrict__ dst, const u64* lds
     } else {
       u64 v = to_canon<CLS>(lds_getw_at<CLS>(lds, li), m);
       if (scale) v = shoupm<CLS == CLS_N32>(v, m.n_inv, m.n_inv_sh, m.q);
-      dst[i] = v;
+      if constexpr (PACK && CLS == CLS_N32) reinterpret_cast<u32*>(dst)[i] = (u32)v;
+      else dst[i] = v;
     }
   }
 }
@@ -146,7 +149,7 @@ __device__ __forceinline__ void store_limb(u64* __restrict__ dst, const u64* lds
 //   narrow target, source below 2^43: an exact FP64 reduction of the signed
 //     value;
 //   otherwise: lift_centered (64-bit Barrett).
-// Narrow sources are read as the low 32-bit words of their slots.
+// A narrow source row is packed: N 32-bit words (store_limb<.., true>).
 template <int LOGN, int CLS>
 __device__ __forceinline__ void lift_limb(u64* lds, const u64* __restrict__ src, u64 qs, const ModConst& m, int tid) {
   constexpr int T = NttGeom<LOGN>::T;
@@ -155,7 +158,7 @@ __device__ __forceinline__ void lift_limb(u64* lds, const u64* __restrict__ src,
     const u32* s32 = reinterpret_cast<const u32*>(src);
     u32 v[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = s32[2 * (tid + r * T)];
+    for (int r = 0; r < 16; ++r) v[r] = s32[tid + r * T];
     const u32 half = (u32)((qs - 1) / 2);
     if constexpr (CLS == CLS_N32) {
       if (qs < 2 * m.q) {
@@ -245,7 +248,7 @@ __device__ __forceinline__ void digits_body(u64* lds, const u64* src, u32 ginv, 
                                             const Tables& tb) {
   load_limb_perm<LOGN, CLS>(lds, src, ginv);
   inv_lds<LOGN, CLS>(lds, tb, j, m);
-  store_limb<LOGN, CLS>(out, lds, m, true);
+  store_limb<LOGN, CLS, true>(out, lds, m, true);
 }
 
 // ---------------------------------------------------------------------------
@@ -259,10 +262,14 @@ __device__ __forceinline__ void digits_body(u64* lds, const u64* src, u32 ginv, 
 // Galois elements (ragged batches, several layers or requests at once);
 // workspace rows are laid out with the launch's largest level Lmax and the
 // number pg of P groups:
-//   dcoef [count][Lmax][N]        coefficient-domain digits
+//   dcoef [count][Lmax][N]        coefficient-domain digits (narrow rows packed,
+//                                 N 32-bit words)
 //   u     [count][2][Lmax+pg][N]  inner products: q_t at row t < level, the
 //                                 partial sum of P group k at row Lmax + k
-//   rc    [count][2][N]           coefficient-domain last limb (ModDown/rescale)
+//   rc    [count][2][N]           coefficient-domain last limb (ModDown/rescale;
+//                                 packed when narrow)
+// Switching keys are [L][2][L+1][N] 64-bit words (digit j, component b/a,
+// modulus); a row of a narrow modulus holds N packed 32-bit residues.
 // Workgroup placement of the key-switch kernels.  The dispatcher hands
 // workgroup i of a 1-D grid to XCD i mod 8, and each XCD has its own L2.  The
 // kernels below run on grids of per * round8(count) workgroups mapped
@@ -357,9 +364,9 @@ __device__ __forceinline__ void modup_ip_body(u64* lds, const u64* __restrict__ 
       const int li = lds_step(i0, r, T);
       if constexpr (CLS == CLS_N32) {
         const u32 dv = (u32)to_canon<CLS>(lds_getw_at<CLS>(lds, li), m);
-        // narrow key residues fit the low word of their u64 slot
-        acc0[r] += (u64)dv * reinterpret_cast<const u32*>(kb)[2 * i];
-        acc1[r] += (u64)dv * reinterpret_cast<const u32*>(ka)[2 * i];
+        // narrow key rows are packed 32-bit residues
+        acc0[r] += (u64)dv * reinterpret_cast<const u32*>(kb)[i];
+        acc1[r] += (u64)dv * reinterpret_cast<const u32*>(ka)[i];
       } else if constexpr (CLS == CLS_F64) {
         const double dv = lds_getw_at<CLS>(lds, li);
         // centred products, summed unreduced (|sum| < 8.2 q for <= 15 digits)
@@ -392,11 +399,116 @@ __device__ __forceinline__ void modup_ip_body(u64* lds, const u64* __restrict__ 
   }
 }
 
+// Asynchronous copy of one 32-bit word per lane from global memory into LDS
+// (global_load_lds_dword): lane l of the calling wave writes wave_dst[l], so
+// wave_dst must be the same for all lanes of the wave.  The copy is counted
+// by the wave's vector-memory counter; wait_vm() waits for all of them.
+__device__ __forceinline__ void copy_to_lds(const u32* src, u32* wave_dst) {
+  __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                   (__attribute__((address_space(3))) void*)wave_dst, 4, 0, 0);
+}
+__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
+
+// Largest ring with a staged narrow ModUp (its staging array and transform
+// buffer fit a CU's LDS), and the staging array's size in 32-bit words: the
+// key rows of one digit (2 N), or the transform buffer of the ring's other
+// class when the kernel serves two.
+constexpr int STAGE_MAX_LOGN = 13;
+template <int LOGN>
+constexpr int stage_words() {
+  return (2 << LOGN) > 2 * lds_words<LOGN, CLS_U64>() ? (2 << LOGN) : 2 * lds_words<LOGN, CLS_U64>();
+}
+
+// ModUp + inner product for a narrow target (as modup_ip_body), with the key
+// rows of digit j (both components, packed 32-bit) copied asynchronously
+// into the staging array S = [key b | key a] before the digit itself is
+// loaded: both loads are in flight together, and the products read the key
+// from LDS.  (Vector-memory loads complete in issue order, so the twiddle
+// loads of the transform would wait for copies issued after the digit; the
+// copies go first.)  Each lane reads back only the words it copied, so a
+// wave waits for its own copies and needs no barrier for them.
+template <int LOGN>
+__device__ __forceinline__ void modup_ip_narrow_staged(u64* lds, u32* S, const u64* __restrict__ dcoef,
+                                                       const KsJob& jb, size_t b, u64* __restrict__ u, int lmax,
+                                                       int urows, int big_l, int t, int mi, int j0, int j1, int row,
+                                                       const Mods& mods, const Tables& tb) {
+  constexpr int CLS = CLS_N32;
+  constexpr int N = 1 << LOGN;
+  constexpr int T = NttGeom<LOGN>::T;
+  const ModConst m = mods.m[mi];
+  const u64* key = jb.key;
+  const int tid = opaque_tid();
+  const int wave0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x) & ~63;  // first thread of the wave
+  const int i0 = lds_idx(tid);
+  u64 acc0[16], acc1[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0;
+  for (int j = j0; j < j1; ++j) {
+    const u32* kb = reinterpret_cast<const u32*>(key + (((size_t)j * 2 + 0) * (big_l + 1) + mi) * N);
+    const u32* ka = reinterpret_cast<const u32*>(key + (((size_t)j * 2 + 1) * (big_l + 1) + mi) * N);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      copy_to_lds(kb + tid + r * T, S + r * T + wave0);
+      copy_to_lds(ka + tid + r * T, S + N + r * T + wave0);
+    }
+    __builtin_amdgcn_sched_barrier(0);  // the copies are issued before the digit's loads
+    if (j == t) {
+      // the digit reduced mod its own prime is the (permuted) input limb itself
+      load_limb_perm<LOGN, CLS>(lds, jb.d + (size_t)j * N, jb.ginv);
+      lds_barrier();
+    } else {
+      lift_limb<LOGN, CLS>(lds, dcoef + (b * lmax + j) * N, mods.m[j].q, m, tid);
+      fwd_lds<LOGN, CLS>(lds, tb, mi, m);
+    }
+    wait_vm();
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const u32 dv = (u32)to_canon<CLS>(lds_getw_at<CLS>(lds, lds_step(i0, r, T)), m);
+      acc0[r] += (u64)dv * S[r * T + tid];
+      acc1[r] += (u64)dv * S[N + r * T + tid];
+    }
+    lds_barrier();  // the copies of the next digit overwrite S
+  }
+  u64* u0 = u + ((b * 2 + 0) * urows + row) * N;
+  u64* u1 = u + ((b * 2 + 1) * urows + row) * N;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = (int)threadIdx.x + r * T;
+    u0[i] = reduce64(acc0[r], m);
+    u1[i] = reduce64(acc1[r], m);
+  }
+}
+
+// Target of workgroup x of job jb in the ModUp grid: ciphertext prime x
+// (x < lmax) over all digits, or group x - lmax of P's digits.  False: the
+// workgroup has nothing to do.
+struct ModupTarget {
+  int t, mi, j0, j1, row;
+};
+__device__ __forceinline__ bool modup_target(const KsJob& jb, int x, int lmax, int pg, int big_l, ModupTarget& o) {
+  const int level = jb.level;
+  if (x < lmax) {
+    if (x >= level) return false;
+    o.t = o.mi = o.row = x;
+    o.j0 = 0;
+    o.j1 = level;
+  } else {
+    const int g = pgroup_size(level, pg);
+    o.j0 = (x - lmax) * g;
+    if (o.j0 >= level) return false;
+    o.j1 = min(o.j0 + g, level);
+    o.t = -1;
+    o.mi = big_l;
+    o.row = x;
+  }
+  return true;
+}
+
 // grid xcd_grid(Lmax + pg, count): workgroup (job b, x), x < Lmax is
 // ciphertext prime x, x = Lmax + k is group k of P's digits.  Each width class is its
 // own kernel (so each body gets a register allocation of its own); blocks of
 // the other classes, primes above a job's level and empty P groups exit at
-// once.
+// once.  Narrow targets of rings up to 2^STAGE_MAX_LOGN take the staged body.
 template <int LOGN, int CLS>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
 k_ks_modup_ip(const KsJob* __restrict__ jobs, int count, const u64* __restrict__ dcoef, u64* __restrict__ u, int lmax,
@@ -407,30 +519,18 @@ k_ks_modup_ip(const KsJob* __restrict__ jobs, int count, const u64* __restrict__
   const size_t b = sl.job;
   const KsJob jb = jobs[b];
   if (jb.key == nullptr) return;
-  const int x = sl.sub;
-  const int level = jb.level;
-  int t, mi, j0, j1, row;
-  if (x < lmax) {
-    if (x >= level) return;
-    t = mi = row = x;
-    j0 = 0;
-    j1 = level;
+  ModupTarget o;
+  if (!modup_target(jb, sl.sub, lmax, pg, big_l, o)) return;
+  if ((int)mods.m[o.mi].cls != CLS) return;
+  if constexpr (CLS == CLS_N32 && LOGN <= STAGE_MAX_LOGN) {
+    __shared__ __align__(16) u32 S[stage_words<LOGN>()];
+    modup_ip_narrow_staged<LOGN>(lds, S, dcoef, jb, b, u, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row, mods,
+                                 tb);
   } else {
-    const int g = pgroup_size(level, pg);
-    j0 = (x - lmax) * g;
-    if (j0 >= level) return;
-    j1 = min(j0 + g, level);
-    t = -1;
-    mi = big_l;
-    row = x;
+    modup_ip_body<LOGN, CLS>(lds, dcoef, jb, b, u, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row, mods, tb);
   }
-  if ((int)mods.m[mi].cls != CLS) return;
-  modup_ip_body<LOGN, CLS>(lds, dcoef, jb, b, u, lmax, lmax + pg, big_l, t, mi, j0, j1, row, mods, tb);
 }
 
-// INTT of the limb that is divided out: for polynomial p = 2 b + comp,
-//   MODE_P:    the P limb of u (ModDown after a key switch);
-//   MODE_LAST: the last limb of the ciphertext jobs[b].d (rescale).
 // The same for a ring whose primes span two width classes A and B: one
 // launch in which each workgroup runs the body of its target's class (both
 // bodies hold one workgroup per CU anyway), instead of one kernel per class
@@ -439,34 +539,33 @@ template <int LOGN, int CA, int CB>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
 k_ks_modup_ip2(const KsJob* __restrict__ jobs, int count, const u64* __restrict__ dcoef, u64* __restrict__ u, int lmax,
                int pg, int big_l, Mods mods, Tables tb) {
-  constexpr int LW = lds_words<LOGN, CA>() > lds_words<LOGN, CB>() ? lds_words<LOGN, CA>() : lds_words<LOGN, CB>();
-  __shared__ u64 lds[LW];
   const XcdSlot sl = xcd_slot(lmax + pg);
   if (sl.job >= count) return;
   const size_t b = sl.job;
   const KsJob jb = jobs[b];
   if (jb.key == nullptr) return;
-  const int x = sl.sub;
-  const int level = jb.level;
-  int t, mi, j0, j1, row;
-  if (x < lmax) {
-    if (x >= level) return;
-    t = mi = row = x;
-    j0 = 0;
-    j1 = level;
+  ModupTarget o;
+  if (!modup_target(jb, sl.sub, lmax, pg, big_l, o)) return;
+  const bool is_a = (int)mods.m[o.mi].cls == CA;
+  if constexpr (CA == CLS_N32 && LOGN <= STAGE_MAX_LOGN) {
+    // narrow targets: transform buffer lds + staging S; class-B targets use
+    // S as their transform buffer
+    __shared__ u64 lds[lds_words<LOGN, CA>()];
+    __shared__ __align__(16) u32 S[stage_words<LOGN>()];
+    if (is_a)
+      modup_ip_narrow_staged<LOGN>(lds, S, dcoef, jb, b, u, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row,
+                                   mods, tb);
+    else
+      modup_ip_body<LOGN, CB>(reinterpret_cast<u64*>(S), dcoef, jb, b, u, lmax, lmax + pg, big_l, o.t, o.mi, o.j0,
+                              o.j1, o.row, mods, tb);
   } else {
-    const int g = pgroup_size(level, pg);
-    j0 = (x - lmax) * g;
-    if (j0 >= level) return;
-    j1 = min(j0 + g, level);
-    t = -1;
-    mi = big_l;
-    row = x;
+    constexpr int LW = lds_words<LOGN, CA>() > lds_words<LOGN, CB>() ? lds_words<LOGN, CA>() : lds_words<LOGN, CB>();
+    __shared__ u64 lds[LW];
+    if (is_a)
+      modup_ip_body<LOGN, CA>(lds, dcoef, jb, b, u, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row, mods, tb);
+    else
+      modup_ip_body<LOGN, CB>(lds, dcoef, jb, b, u, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row, mods, tb);
   }
-  if ((int)mods.m[mi].cls == CA)
-    modup_ip_body<LOGN, CA>(lds, dcoef, jb, b, u, lmax, lmax + pg, big_l, t, mi, j0, j1, row, mods, tb);
-  else
-    modup_ip_body<LOGN, CB>(lds, dcoef, jb, b, u, lmax, lmax + pg, big_l, t, mi, j0, j1, row, mods, tb);
 }
 
 enum { MODE_P = 0, MODE_LAST = 1 };
@@ -486,7 +585,7 @@ __device__ __forceinline__ void intt_p_body(u64* lds, const u64* __restrict__ ur
     lds_put<CLS>(lds, i, v);
   }
   inv_lds<LOGN, CLS>(lds, tb, mi, m);
-  store_limb<LOGN, CLS>(out, lds, m, true);
+  store_limb<LOGN, CLS, true>(out, lds, m, true);
 }
 
 // INTT of the limb that is divided out: for polynomial p = 2 b + comp,
@@ -703,8 +802,8 @@ __global__ void k_ip_perm(const u64* __restrict__ dhat, const KsJob* __restrict_
     u64 a0 = 0, a1 = 0;
     for (int j = 0; j < level; ++j) {
       const u64 dv = dhat[((size_t)j * (level + 1) + t) * N + src];
-      a0 += (u64)(u32)dv * (u32)key[(((size_t)j * 2 + 0) * (big_l + 1) + mi) * N + i];
-      a1 += (u64)(u32)dv * (u32)key[(((size_t)j * 2 + 1) * (big_l + 1) + mi) * N + i];
+      a0 += (u64)(u32)dv * reinterpret_cast<const u32*>(key + (((size_t)j * 2 + 0) * (big_l + 1) + mi) * N)[i];
+      a1 += (u64)(u32)dv * reinterpret_cast<const u32*>(key + (((size_t)j * 2 + 1) * (big_l + 1) + mi) * N)[i];
     }
     s0 = reduce64(a0, m);
     s1 = reduce64(a1, m);
@@ -987,8 +1086,15 @@ __global__ void k_keygen(u64* key, const u64* s, const u64* a, const u64* ehat, 
     else sp = s[(size_t)t * N + galois_src<LOGN>(i, g)];
     b = add_mod(b, mul_shoup(sp, p_mod.v[t], p_mod.sh[t], m.q, m.narrow), m.q);
   }
-  key[(((size_t)j * 2 + 0) * (big_l + 1) + t) * N + i] = b;
-  key[(((size_t)j * 2 + 1) * (big_l + 1) + t) * N + i] = av;
+  u64* kb = key + (((size_t)j * 2 + 0) * (big_l + 1) + t) * N;
+  u64* ka = key + (((size_t)j * 2 + 1) * (big_l + 1) + t) * N;
+  if (m.narrow) {  // packed 32-bit residues
+    reinterpret_cast<u32*>(kb)[i] = (u32)b;
+    reinterpret_cast<u32*>(ka)[i] = (u32)av;
+  } else {
+    kb[i] = b;
+    ka[i] = av;
+  }
 }
 
 // Encryption: c0 = pt + ehat - a*s, c1 = a.

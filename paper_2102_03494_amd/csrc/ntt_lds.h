@@ -63,6 +63,13 @@ __device__ __forceinline__ int lds_idx(int i) { return i + (i >> 5); }
 // immediate offset.
 __device__ __forceinline__ int lds_step(int idx0, int r, int stride) { return idx0 + r * stride + ((r * stride) >> 5); }
 
+// Workgroup barrier for LDS traffic only: each wave waits for its own LDS
+// operations, then all waves meet.  __syncthreads also waits for the wave's
+// outstanding global-to-LDS copies; this one lets copies into another LDS
+// array stay in flight across the passes of a transform.  The memory clobber
+// keeps the compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 template <int LOGN>
 struct NttGeom {
   static constexpr int N = 1 << LOGN;
@@ -311,15 +318,15 @@ template <int LOGN, int CLS>
 __device__ __forceinline__ void ntt_fwd_lds(u64* lds, Tw<CLS> tw, MV<CLS> q, int tid) {
   constexpr int FULL = LOGN / 4;
   constexpr int REM = LOGN % 4;
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int p = 0; p < FULL; ++p) {
     fwd_pass<LOGN, 4, CLS>(lds, 4 * p, tw, q, tid);
-    __syncthreads();
+    lds_barrier();
   }
   if constexpr (REM > 0) {
     fwd_pass<LOGN, REM, CLS>(lds, 4 * FULL, tw, q, tid);
-    __syncthreads();
+    lds_barrier();
   }
 }
 
@@ -329,15 +336,15 @@ template <int LOGN, int CLS>
 __device__ __forceinline__ void ntt_inv_lds(u64* lds, Tw<CLS> tw, MV<CLS> q, int tid) {
   constexpr int FULL = LOGN / 4;
   constexpr int REM = LOGN % 4;
-  __syncthreads();
+  lds_barrier();
   if constexpr (REM > 0) {
     inv_pass<LOGN, REM, CLS>(lds, 4 * FULL, tw, q, tid);
-    __syncthreads();
+    lds_barrier();
   }
 #pragma unroll
   for (int p = FULL - 1; p >= 0; --p) {
     inv_pass<LOGN, 4, CLS>(lds, 4 * p, tw, q, tid);
-    __syncthreads();
+    lds_barrier();
   }
 }
 
