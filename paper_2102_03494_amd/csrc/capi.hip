@@ -491,6 +491,51 @@ int rotate_batch(he_ctx* c, u64* out, const u64* in, int count, int level, int k
   return check_launch(c, "rotate");
 }
 
+// Rotate-and-sum chain acc <- acc + rot(acc, 2^j), j = 0 .. steps - 1, in
+// place over `count` ciphertexts at one level, with the job tables of all
+// steps built by one launch (chain_prepare) instead of one per step.
+struct Chain {
+  KsJob* jobs = nullptr;  // [steps][count]
+  KsScratch ks;
+  int count = 0, level = 0, pg = 1, steps = 0;
+};
+
+// False (nothing launched) when the chain does not fit the arena in one
+// chunk or has too many steps; the caller then rotates step by step.
+bool chain_prepare(he_ctx* c, u64* acc, int count, int level, int steps, Arena ar, hipStream_t s, Chain& ch) {
+  const int n = c->n;
+  if (steps < 1 || steps > MAX_CHAIN || count < 1) return false;
+  const int pg = p_groups(c, level);
+  if (chunk_for(ar, count, level, pg, n, (size_t)steps * sizeof(KsJob) / 8 + 1) < count) return false;
+  ch.jobs = ar.take<KsJob>((size_t)steps * count);
+  if (!ch.jobs || !take_scratch(ar, count, level, pg, n, ch.ks)) return false;
+  ChainKeys ck{};
+  for (int j = 0; j < steps; ++j) {
+    const u32 g = galois_of(1 << j, n);
+    auto it = c->keys.find((int)g);
+    if (g != 1 && it == c->keys.end()) return false;
+    ck.key[j] = (g == 1) ? nullptr : it->second;
+    ck.g[j] = g;
+    ck.ginv[j] = galois_of(-(1 << j), n);
+  }
+  ch.count = count;
+  ch.level = level;
+  ch.pg = pg;
+  ch.steps = steps;
+  k_make_chain_jobs<<<dim3((count + 255) / 256, steps), 256, 0, s>>>(ch.jobs, count, acc, (size_t)2 * level * n,
+                                                                    (size_t)level * n, level, ck);
+  return true;
+}
+
+void chain_step(he_ctx* c, const Chain& ch, int j, hipStream_t s) {
+  const KsJob* jobs = ch.jobs + (size_t)j * ch.count;
+  const int g_is_one = galois_of(1 << j, c->n) == 1;
+  if (!g_is_one)
+    dispatch_logn<LKsCore>(c->logn, c, jobs, ch.count, ch.level, ch.pg, ch.ks.dcoef, ch.ks.u, ch.ks.rc, s);
+  dispatch_logn<LDrop>(c->logn, c, (int)MODE_P, (int)EPI_ROTSUM, jobs, ch.count, ch.level, ch.level + ch.pg,
+                       (const u64*)ch.ks.u, (const u64*)ch.ks.rc, s);
+}
+
 int rescale_batch(he_ctx* c, u64* out, const u64* in, int count, int level, Arena& ar, hipStream_t s) {
   const int n = c->n;
   const int chunk = (int)std::min<size_t>({(size_t)count, ar.left() / 8 / (2 * (size_t)n + 64), (size_t)32000});
@@ -623,9 +668,18 @@ int densepack_run(he_ctx* c, const u64* d_in, int level, const he_conv_desc* des
       (void)hipEventRecord(c->fork_ev, s);
       (void)hipStreamWaitEvent(c->side, c->fork_ev, 0);
       int e = HE_OK;
-      for (int j = 0; j < desc->r_steps && !e; ++j) {
-        e = rotate_batch(c, acc, acc, h0, level, 1 << j, EPI_ROTSUM, a0, s);
-        if (!e) e = rotate_batch(c, acc1, acc1, h1, level, 1 << j, EPI_ROTSUM, a1, c->side);
+      Chain ch0, ch1;
+      if (chain_prepare(c, acc, h0, level, desc->r_steps, a0, s, ch0) &&
+          chain_prepare(c, acc1, h1, level, desc->r_steps, a1, c->side, ch1)) {
+        for (int j = 0; j < desc->r_steps; ++j) {
+          chain_step(c, ch0, j, s);
+          chain_step(c, ch1, j, c->side);
+        }
+      } else {
+        for (int j = 0; j < desc->r_steps && !e; ++j) {
+          e = rotate_batch(c, acc, acc, h0, level, 1 << j, EPI_ROTSUM, a0, s);
+          if (!e) e = rotate_batch(c, acc1, acc1, h1, level, 1 << j, EPI_ROTSUM, a1, c->side);
+        }
       }
       if (!e) e = rescale_batch(c, out, acc, h0, level, a0, s);
       if (!e) e = rescale_batch(c, out1, acc1, h1, level, a1, c->side);
@@ -633,9 +687,14 @@ int densepack_run(he_ctx* c, const u64* d_in, int level, const he_conv_desc* des
       (void)hipStreamWaitEvent(s, c->join_ev, 0);
       if (e) return e;
     } else {
-      for (int j = 0; j < desc->r_steps; ++j) {
-        int e = rotate_batch(c, acc, acc, cn, level, 1 << j, EPI_ROTSUM, sub, s);
-        if (e) return e;
+      Chain ch;
+      if (chain_prepare(c, acc, cn, level, desc->r_steps, sub, s, ch)) {
+        for (int j = 0; j < desc->r_steps; ++j) chain_step(c, ch, j, s);
+      } else {
+        for (int j = 0; j < desc->r_steps; ++j) {
+          int e = rotate_batch(c, acc, acc, cn, level, 1 << j, EPI_ROTSUM, sub, s);
+          if (e) return e;
+        }
       }
       int e = rescale_batch(c, out, acc, cn, level, sub, s);
       if (e) return e;

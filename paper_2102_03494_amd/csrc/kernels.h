@@ -266,6 +266,7 @@ __device__ __forceinline__ void digits_body(u64* lds, const u64* src, u32 ginv, 
 //                                 N 32-bit words)
 //   u     [count][2][Lmax+pg][N]  inner products: q_t at row t < level, the
 //                                 partial sum of P group k at row Lmax + k
+//                                 (rows of narrow primes packed)
 //   rc    [count][2][N]           coefficient-domain last limb (ModDown/rescale;
 //                                 packed when narrow)
 // Switching keys are [L][2][L+1][N] 64-bit words (digit j, component b/a,
@@ -386,9 +387,9 @@ __device__ __forceinline__ void modup_ip_body(u64* lds, const u64* __restrict__ 
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int i = (int)threadIdx.x + r * T;
-    if constexpr (CLS == CLS_N32) {
-      u0[i] = reduce64(acc0[r], m);
-      u1[i] = reduce64(acc1[r], m);
+    if constexpr (CLS == CLS_N32) {  // packed row
+      reinterpret_cast<u32*>(u0)[i] = (u32)reduce64(acc0[r], m);
+      reinterpret_cast<u32*>(u1)[i] = (u32)reduce64(acc1[r], m);
     } else if constexpr (CLS == CLS_F64) {
       u0[i] = to_canon<CLS>(acc0[r], m);
       u1[i] = to_canon<CLS>(acc1[r], m);
@@ -474,8 +475,8 @@ __device__ __forceinline__ void modup_ip_narrow_staged(u64* lds, u32* S, const u
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int i = (int)threadIdx.x + r * T;
-    u0[i] = reduce64(acc0[r], m);
-    u1[i] = reduce64(acc1[r], m);
+    reinterpret_cast<u32*>(u0)[i] = (u32)reduce64(acc0[r], m);
+    reinterpret_cast<u32*>(u1)[i] = (u32)reduce64(acc1[r], m);
   }
 }
 
@@ -580,8 +581,14 @@ __device__ __forceinline__ void intt_p_body(u64* lds, const u64* __restrict__ ur
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int i = (int)threadIdx.x + r * T;
-    u64 v = urow[i];
-    for (int k = 1; k < groups; ++k) v = add_mod(v, urow[(size_t)k * N + i], m.q);
+    u64 v;
+    if constexpr (CLS == CLS_N32) {  // packed rows
+      v = reinterpret_cast<const u32*>(urow)[i];
+      for (int k = 1; k < groups; ++k) v = add_mod(v, reinterpret_cast<const u32*>(urow + (size_t)k * N)[i], m.q);
+    } else {
+      v = urow[i];
+      for (int k = 1; k < groups; ++k) v = add_mod(v, urow[(size_t)k * N + i], m.q);
+    }
     lds_put<CLS>(lds, i, v);
   }
   inv_lds<LOGN, CLS>(lds, tb, mi, m);
@@ -671,11 +678,13 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
   for (int r = 0; r < 16; ++r) {
     const int i = (int)threadIdx.x + r * T;
     const int li = lds_step(i0, r, T);
+    // u rows of narrow primes are packed
+    const u64 sv = (MODE == MODE_P && NW) ? (u64)reinterpret_cast<const u32*>(s)[i] : s[i];
     if constexpr (CLS == CLS_F64) {
-      const double dlt = f64_from_u64(s[i]) - lds_getw_at<CLS>(lds, li);
+      const double dlt = f64_from_u64(sv) - lds_getw_at<CLS>(lds, li);
       val[r] = to_canon<CLS>(f64_mulmod(dlt, f64_from_u64(iv), m.qd, m.qinv), m);
     } else {
-      val[r] = (V)shoupm<NW>(subm<NW>(s[i], to_canon<CLS>(lds_getw_at<CLS>(lds, li), m), m.q), iv, ivs, m.q);
+      val[r] = (V)shoupm<NW>(subm<NW>(sv, to_canon<CLS>(lds_getw_at<CLS>(lds, li), m), m.q), iv, ivs, m.q);
     }
   }
   if constexpr (EPI == EPI_STORE) {
@@ -817,8 +826,15 @@ __global__ void k_ip_perm(const u64* __restrict__ dhat, const KsJob* __restrict_
     s0 = reduce128(a0, m);
     s1 = reduce128(a1, m);
   }
-  u[((r * 2 + 0) * (level + 1) + t) * N + i] = s0;
-  u[((r * 2 + 1) * (level + 1) + t) * N + i] = s1;
+  u64* u0 = u + ((r * 2 + 0) * (level + 1) + t) * N;
+  u64* u1 = u + ((r * 2 + 1) * (level + 1) + t) * N;
+  if (m.narrow) {  // packed rows
+    reinterpret_cast<u32*>(u0)[i] = (u32)s0;
+    reinterpret_cast<u32*>(u1)[i] = (u32)s1;
+  } else {
+    u0[i] = s0;
+    u1[i] = s1;
+  }
 }
 
 // Job table of a uniform batch: ciphertext b at base + b * stride.
@@ -837,6 +853,34 @@ __global__ void k_make_jobs(KsJob* jobs, int count, const u64* d_base, size_t d_
   jb.level = level;
   jb.pad_ = 0;
   jobs[b] = jb;
+}
+
+// Keys and Galois elements of the steps of a rotate-and-sum chain.
+constexpr int MAX_CHAIN = 16;
+struct ChainKeys {
+  const u64* key[MAX_CHAIN];
+  u32 g[MAX_CHAIN], ginv[MAX_CHAIN];
+};
+
+// Job tables of all steps of a rotate-and-sum chain over `count` ciphertexts
+// updated in place (ciphertext b at base + b * stride): step j's table at
+// jobs + j * count.  grid (ceil(count / 256), steps).
+__global__ void k_make_chain_jobs(KsJob* jobs, int count, u64* base, size_t stride, size_t c1_off, int level,
+                                  ChainKeys ck) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (b >= count) return;
+  u64* x = base + (size_t)b * stride;
+  KsJob jb;
+  jb.d = x + c1_off;
+  jb.c = x;
+  jb.out = x;
+  jb.key = ck.key[j];
+  jb.g = ck.g[j];
+  jb.ginv = ck.ginv[j];
+  jb.level = level;
+  jb.pad_ = 0;
+  jobs[(size_t)j * count + b] = jb;
 }
 
 // CP -> DP combine, summing step: out[m] = sum_{o in block m} rot[o], block
