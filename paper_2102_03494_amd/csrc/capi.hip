@@ -240,7 +240,8 @@ struct LNtt {
   }
 };
 
-// Key switch of a job batch: digits -> ModUp + inner product -> INTT of P.
+// Key switch of a job batch: digits -> ModUp + inner product -> INTT of P (in
+// the ModUp launch when P is one group).
 // ModUp is one launch when the ring's primes span one or two width classes
 // (each workgroup runs its target's class); with all three, the kernel of
 // each class runs on its own stream (the caller's for the first, the side
@@ -250,6 +251,9 @@ struct LKsCore {
   static void run(he_ctx* c, const KsJob* jobs, int count, int lmax, int pg, u64* dcoef, u64* u, u64* rc,
                   hipStream_t s) {
     constexpr int T = NttGeom<LOGN>::T;
+    // with one P group, ModUp's P workgroups also write the coefficient-domain
+    // P limb (rc), and no separate INTT launch is needed
+    u64* rc1 = pg == 1 ? rc : nullptr;
     {
       Prof pr(c, "ks_digits", s);
       HE_FOR_CLASSES(c->q_mask, (k_ks_digits<LOGN, CLS><<<xcd_grid(lmax, count), T, 0, s>>>(jobs, count, dcoef, lmax,
@@ -261,14 +265,14 @@ struct LKsCore {
     if (n_cls == 2) {  // one launch, each workgroup in its target's class
       Prof stage(c, "ks_modup_stage", s);
       if (!c->has_cls[CLS_U64])
-        k_ks_modup_ip2<LOGN, CLS_N32, CLS_F64><<<grid, T, 0, s>>>(jobs, count, dcoef, u, lmax, pg, c->big_l, c->mods,
-                                                                   c->tb());
+        k_ks_modup_ip2<LOGN, CLS_N32, CLS_F64><<<grid, T, 0, s>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l,
+                                                                   c->mods, c->tb());
       else if (!c->has_cls[CLS_F64])
-        k_ks_modup_ip2<LOGN, CLS_N32, CLS_U64><<<grid, T, 0, s>>>(jobs, count, dcoef, u, lmax, pg, c->big_l, c->mods,
-                                                                   c->tb());
+        k_ks_modup_ip2<LOGN, CLS_N32, CLS_U64><<<grid, T, 0, s>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l,
+                                                                   c->mods, c->tb());
       else
-        k_ks_modup_ip2<LOGN, CLS_F64, CLS_U64><<<grid, T, 0, s>>>(jobs, count, dcoef, u, lmax, pg, c->big_l, c->mods,
-                                                                   c->tb());
+        k_ks_modup_ip2<LOGN, CLS_F64, CLS_U64><<<grid, T, 0, s>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l,
+                                                                   c->mods, c->tb());
     } else {
     const bool forked = n_cls > 1;
     {
@@ -284,13 +288,13 @@ struct LKsCore {
         first = false;
         Prof pr(c, names[cls], st);
         if (cls == CLS_N32)
-          k_ks_modup_ip<LOGN, CLS_N32><<<grid, T, 0, st>>>(jobs, count, dcoef, u, lmax, pg, c->big_l, c->mods,
+          k_ks_modup_ip<LOGN, CLS_N32><<<grid, T, 0, st>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l, c->mods,
                                                             c->tb());
         else if (cls == CLS_F64)
-          k_ks_modup_ip<LOGN, CLS_F64><<<grid, T, 0, st>>>(jobs, count, dcoef, u, lmax, pg, c->big_l, c->mods,
+          k_ks_modup_ip<LOGN, CLS_F64><<<grid, T, 0, st>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l, c->mods,
                                                             c->tb());
         else
-          k_ks_modup_ip<LOGN, CLS_U64><<<grid, T, 0, st>>>(jobs, count, dcoef, u, lmax, pg, c->big_l, c->mods,
+          k_ks_modup_ip<LOGN, CLS_U64><<<grid, T, 0, st>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l, c->mods,
                                                             c->tb());
       }
       if (forked) {
@@ -299,6 +303,7 @@ struct LKsCore {
       }
     }
     }
+    if (rc1) return;
     Prof pr(c, "intt_last", s);
     HE_FOR_CLASSES(1u << c->p_cls, (k_intt_last<LOGN, MODE_P, CLS><<<xcd_grid(2, count), T, 0, s>>>(
                                        jobs, count, u, lmax, pg, c->big_l, rc, c->mods, c->tb())));

@@ -328,14 +328,36 @@ __host__ __device__ inline int pgroup_count(int level, int pg) {
   return (level + g - 1) / g;
 }
 
+// The whole P limb of one inner-product polynomial, held as this thread's 16
+// accumulators (entries tid + r T, as modup_ip_body sums them), to its
+// coefficient-domain copy for ModDown: canonical residues, INTT, N^-1, packed
+// store at out (what k_intt_last computes from a u row).
+template <int LOGN, int CLS, typename A>
+__device__ __forceinline__ void p_limb_to_coeffs(u64* lds, const A (&acc)[16], u64* out, int mi, const ModConst& m,
+                                                 const Tables& tb) {
+  constexpr int T = NttGeom<LOGN>::T;
+  __syncthreads();  // the LDS buffer is free
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    u64 v;
+    if constexpr (CLS == CLS_N32) v = reduce64(acc[r], m);
+    else if constexpr (CLS == CLS_F64) v = to_canon<CLS>(acc[r], m);
+    else v = acc[r];
+    lds_put<CLS>(lds, (int)threadIdx.x + r * T, v);
+  }
+  inv_lds<LOGN, CLS>(lds, tb, mi, m);
+  store_limb<LOGN, CLS, true>(out, lds, m, true);
+}
+
 // Key switch, step 2: ModUp + inner product for one target: a ciphertext
 // prime t over all digits, or one group of digits [j0, j1) for P.
 // Accumulates sum_j NTT(lift(digit_j) mod m) * key[j][.][m] in registers and
 // writes it to u row `row` (canonical residues).
 template <int LOGN, int CLS>
 __device__ __forceinline__ void modup_ip_body(u64* lds, const u64* __restrict__ dcoef, const KsJob& jb, size_t b,
-                                              u64* __restrict__ u, int lmax, int urows, int big_l, int t, int mi,
-                                              int j0, int j1, int row, const Mods& mods, const Tables& tb) {
+                                              u64* __restrict__ u, u64* __restrict__ rc_p, int lmax, int urows,
+                                              int big_l, int t, int mi, int j0, int j1, int row, const Mods& mods,
+                                              const Tables& tb) {
   // accumulators: 64-bit sums of products of canonical narrow residues
   // (each < 2^60, at most 15 digits), centred doubles (f64), residues (wide)
   typedef std::conditional_t<CLS == CLS_N32, u64, word_t<CLS>> A;
@@ -381,6 +403,11 @@ __device__ __forceinline__ void modup_ip_body(u64* lds, const u64* __restrict__ 
       if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);  // bound the load hoisting
     }
     __syncthreads();
+  }
+  if (rc_p) {
+    p_limb_to_coeffs<LOGN, CLS>(lds, acc0, rc_p, mi, m, tb);
+    p_limb_to_coeffs<LOGN, CLS>(lds, acc1, rc_p + N, mi, m, tb);
+    return;
   }
   u64* u0 = u + ((b * 2 + 0) * urows + row) * N;
   u64* u1 = u + ((b * 2 + 1) * urows + row) * N;
@@ -430,9 +457,10 @@ constexpr int stage_words() {
 // wave waits for its own copies and needs no barrier for them.
 template <int LOGN>
 __device__ __forceinline__ void modup_ip_narrow_staged(u64* lds, u32* S, const u64* __restrict__ dcoef,
-                                                       const KsJob& jb, size_t b, u64* __restrict__ u, int lmax,
-                                                       int urows, int big_l, int t, int mi, int j0, int j1, int row,
-                                                       const Mods& mods, const Tables& tb) {
+                                                       const KsJob& jb, size_t b, u64* __restrict__ u,
+                                                       u64* __restrict__ rc_p, int lmax, int urows, int big_l, int t,
+                                                       int mi, int j0, int j1, int row, const Mods& mods,
+                                                       const Tables& tb) {
   constexpr int CLS = CLS_N32;
   constexpr int N = 1 << LOGN;
   constexpr int T = NttGeom<LOGN>::T;
@@ -469,6 +497,11 @@ __device__ __forceinline__ void modup_ip_narrow_staged(u64* lds, u32* S, const u
       acc1[r] += (u64)dv * S[N + r * T + tid];
     }
     lds_barrier();  // the copies of the next digit overwrite S
+  }
+  if (rc_p) {
+    p_limb_to_coeffs<LOGN, CLS>(lds, acc0, rc_p, mi, m, tb);
+    p_limb_to_coeffs<LOGN, CLS>(lds, acc1, rc_p + N, mi, m, tb);
+    return;
   }
   u64* u0 = u + ((b * 2 + 0) * urows + row) * N;
   u64* u1 = u + ((b * 2 + 1) * urows + row) * N;
@@ -512,8 +545,8 @@ __device__ __forceinline__ bool modup_target(const KsJob& jb, int x, int lmax, i
 // once.  Narrow targets of rings up to 2^STAGE_MAX_LOGN take the staged body.
 template <int LOGN, int CLS>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
-k_ks_modup_ip(const KsJob* __restrict__ jobs, int count, const u64* __restrict__ dcoef, u64* __restrict__ u, int lmax,
-              int pg, int big_l, Mods mods, Tables tb) {
+k_ks_modup_ip(const KsJob* __restrict__ jobs, int count, const u64* __restrict__ dcoef, u64* __restrict__ u,
+              u64* __restrict__ rc, int lmax, int pg, int big_l, Mods mods, Tables tb) {
   __shared__ u64 lds[lds_words<LOGN, CLS>()];
   const XcdSlot sl = xcd_slot(lmax + pg);
   if (sl.job >= count) return;
@@ -522,13 +555,16 @@ k_ks_modup_ip(const KsJob* __restrict__ jobs, int count, const u64* __restrict__
   if (jb.key == nullptr) return;
   ModupTarget o;
   if (!modup_target(jb, sl.sub, lmax, pg, big_l, o)) return;
+  // with one P group (rc given) its workgroup also finishes the P limb
+  u64* rc_p = (rc != nullptr && o.t < 0) ? rc + b * 2 * ((size_t)1 << LOGN) : nullptr;
   if ((int)mods.m[o.mi].cls != CLS) return;
   if constexpr (CLS == CLS_N32 && LOGN <= STAGE_MAX_LOGN) {
     __shared__ __align__(16) u32 S[stage_words<LOGN>()];
-    modup_ip_narrow_staged<LOGN>(lds, S, dcoef, jb, b, u, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row, mods,
-                                 tb);
+    modup_ip_narrow_staged<LOGN>(lds, S, dcoef, jb, b, u, rc_p, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row,
+                                 mods, tb);
   } else {
-    modup_ip_body<LOGN, CLS>(lds, dcoef, jb, b, u, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row, mods, tb);
+    modup_ip_body<LOGN, CLS>(lds, dcoef, jb, b, u, rc_p, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row, mods,
+                             tb);
   }
 }
 
@@ -538,8 +574,8 @@ k_ks_modup_ip(const KsJob* __restrict__ jobs, int count, const u64* __restrict__
 // on two streams joined by events.
 template <int LOGN, int CA, int CB>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
-k_ks_modup_ip2(const KsJob* __restrict__ jobs, int count, const u64* __restrict__ dcoef, u64* __restrict__ u, int lmax,
-               int pg, int big_l, Mods mods, Tables tb) {
+k_ks_modup_ip2(const KsJob* __restrict__ jobs, int count, const u64* __restrict__ dcoef, u64* __restrict__ u,
+               u64* __restrict__ rc, int lmax, int pg, int big_l, Mods mods, Tables tb) {
   const XcdSlot sl = xcd_slot(lmax + pg);
   if (sl.job >= count) return;
   const size_t b = sl.job;
@@ -547,6 +583,8 @@ k_ks_modup_ip2(const KsJob* __restrict__ jobs, int count, const u64* __restrict_
   if (jb.key == nullptr) return;
   ModupTarget o;
   if (!modup_target(jb, sl.sub, lmax, pg, big_l, o)) return;
+  // with one P group (rc given) its workgroup also finishes the P limb
+  u64* rc_p = (rc != nullptr && o.t < 0) ? rc + b * 2 * ((size_t)1 << LOGN) : nullptr;
   const bool is_a = (int)mods.m[o.mi].cls == CA;
   if constexpr (CA == CLS_N32 && LOGN <= STAGE_MAX_LOGN) {
     // narrow targets: transform buffer lds + staging S; class-B targets use
@@ -554,18 +592,20 @@ k_ks_modup_ip2(const KsJob* __restrict__ jobs, int count, const u64* __restrict_
     __shared__ u64 lds[lds_words<LOGN, CA>()];
     __shared__ __align__(16) u32 S[stage_words<LOGN>()];
     if (is_a)
-      modup_ip_narrow_staged<LOGN>(lds, S, dcoef, jb, b, u, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row,
+      modup_ip_narrow_staged<LOGN>(lds, S, dcoef, jb, b, u, rc_p, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row,
                                    mods, tb);
     else
-      modup_ip_body<LOGN, CB>(reinterpret_cast<u64*>(S), dcoef, jb, b, u, lmax, lmax + pg, big_l, o.t, o.mi, o.j0,
-                              o.j1, o.row, mods, tb);
+      modup_ip_body<LOGN, CB>(reinterpret_cast<u64*>(S), dcoef, jb, b, u, rc_p, lmax, lmax + pg, big_l, o.t, o.mi,
+                              o.j0, o.j1, o.row, mods, tb);
   } else {
     constexpr int LW = lds_words<LOGN, CA>() > lds_words<LOGN, CB>() ? lds_words<LOGN, CA>() : lds_words<LOGN, CB>();
     __shared__ u64 lds[LW];
     if (is_a)
-      modup_ip_body<LOGN, CA>(lds, dcoef, jb, b, u, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row, mods, tb);
+      modup_ip_body<LOGN, CA>(lds, dcoef, jb, b, u, rc_p, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row, mods,
+                              tb);
     else
-      modup_ip_body<LOGN, CB>(lds, dcoef, jb, b, u, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row, mods, tb);
+      modup_ip_body<LOGN, CB>(lds, dcoef, jb, b, u, rc_p, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row, mods,
+                              tb);
   }
 }
 
