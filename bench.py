@@ -45,11 +45,11 @@ DOMINANT = "ks_modup_stage"
 # valid only for the kernel sources they were measured on: bench.py reports
 # them when these sources hash to KERNEL_SHA256, else null.
 KERNEL_SOURCES = ("modarith.h", "ntt_lds.h", "kernels.h", "capi.hip")
-KERNEL_SHA256 = "cc482ea255264cc53ca7d1ff2cf37c50832750804e7f8f7f92856b4fa8f03054"
+KERNEL_SHA256 = "d52e718f7cb647344864541120b86c9e61abfbeddf5fab9c427c1b0e9292462f"
 # ks_modup_stage: mean over one layer's 25 launches (24 of 144 jobs at
-# 268.7 MB, one relinearisation launch of 5 jobs at 8.7 MB); ip_perm: one
+# 168.5 MB, one relinearisation launch of 5 jobs at 6.9 MB); ip_perm: one
 # launch over all 256 rotations
-TRAFFIC_BYTES = {"ks_modup_stage": 258295698, "ip_perm": 4454506709}
+TRAFFIC_BYTES = {"ks_modup_stage": 162054620, "ip_perm": 4455705045}
 
 
 def kernel_sha256() -> str:
@@ -86,7 +86,8 @@ def modup_ip_ops(count: int, level: int, n: int, moduli, pg: int) -> float:
     prime of every width class, P split over pg digit groups) over `count`
     ciphertexts at `level`: per target, a lift and an NTT of each digit but
     its own, one key product per digit and output polynomial, one final
-    reduction per output coefficient."""
+    reduction per output coefficient; with one P group, the INTT of the P
+    limb (which then runs in the same launch)."""
     bfly = (n // 2) * int(math.log2(n))
     ops = 0.0
     for t in range(level):
@@ -97,15 +98,27 @@ def modup_ip_ops(count: int, level: int, n: int, moduli, pg: int) -> float:
     groups = -(-level // -(-level // pg))
     ops += level * (bfly * COST["bfly"][c] + n * COST["lift"][c] + 2 * n * COST["mac"][c])
     ops += groups * 2 * n * COST["fin"][c]
+    if groups == 1:  # the P workgroup also takes its limb back to the coefficient domain
+        ops += 2 * (bfly * COST["bfly"][c] + n * COST["fin"][c])
     return ops * count
 
 
-def modup_ip_bytes(count: int, level: int, n: int) -> float:
-    """Algorithmic HBM bytes of the ModUp + inner-product stage: each digit
-    (or own limb) read once per ciphertext, the level + 1 output rows of both
-    polynomials written, the key (2 level (level + 1) limbs) read once."""
-    limb = 8 * n
-    return count * (level * limb + 2 * (level + 1) * limb) + 2 * level * (level + 1) * limb
+def modup_ip_bytes(count: int, level: int, n: int, moduli, pg: int) -> float:
+    """Algorithmic HBM bytes of the ModUp + inner-product stage over `count`
+    ciphertexts at `level`: per ciphertext its coefficient-domain digits and
+    its own NTT-domain limbs read once, both output polynomials written once
+    (the level ciphertext-prime rows, and the P limb as its coefficient-domain
+    copy with one P group, else as one partial row per group), and the key
+    (2 level (level + 1) limbs) read once.  Residues of narrow primes are
+    packed 32-bit words, all others 64-bit words."""
+    def width(q):
+        return 4 if q < (1 << 30) else 8
+    qs, p = moduli[:level], moduli[-1]
+    groups = -(-level // -(-level // pg))
+    q_row = sum(width(q) for q in qs) * n
+    per = q_row + 8 * n * level + 2 * (q_row + groups * width(p) * n)
+    key = 2 * level * (q_row + width(p) * n)
+    return count * per + key
 
 
 def setup(ctx, client, x, w1, w2):
@@ -492,7 +505,8 @@ def main():
     # relinearisations of x^2 (level 2)
     ops_layer = 12 * modup_ip_ops(288, level, N, ctx.moduli, pg) + \
         modup_ip_ops(5, 2, N, ctx.moduli[:2] + ctx.moduli[-1:], ctx.get_tuning("p_groups", 2))
-    bytes_layer = 12 * modup_ip_bytes(288, level, N) + modup_ip_bytes(5, 2, N)
+    bytes_layer = 12 * modup_ip_bytes(288, level, N, ctx.moduli, pg) + \
+        modup_ip_bytes(5, 2, N, ctx.moduli[:2] + ctx.moduli[-1:], ctx.get_tuning("p_groups", 2))
     launches_layer = 12 * (2 if split else 1) + 1
     avg_ms = dom_ms / max(1, dom_launches)
     layers = dom_launches / launches_layer

@@ -96,7 +96,10 @@ class Scheduler:
             b -= 1
         return b
 
-    def run(self, requests: list, window_s: float, cap_s: float) -> dict:
+    def run(self, requests: list, window_s: float, cap_s: float, progress_s: float = 0.0) -> dict:
+        """Serve `requests` (arrival times relative to the start); with
+        progress_s > 0, print completed counts and backlog to stderr every
+        progress_s seconds."""
         reqs = sorted(requests, key=lambda r: r.t_arrival)
         queues = {c: deque() for c in self.ex}
         stats = {c: ClassStats() for c in self.ex}
@@ -108,8 +111,14 @@ class Scheduler:
         rejected = 0
         batch_id = 0
         t0 = self.now()
+        next_report = progress_s
         while True:
             t = self.now() - t0
+            if progress_s > 0 and t >= next_report:
+                next_report += progress_s
+                done = {c: st.completed for c, st in stats.items()}
+                print(f"# t={t:.0f}s completed {done} backlog {sum(len(q) for q in queues.values())}",
+                      file=sys.stderr, flush=True)
             while nxt < len(reqs) and reqs[nxt].t_arrival <= min(t, window_s):
                 queues[reqs[nxt].cls].append(reqs[nxt])
                 nxt += 1
@@ -311,7 +320,7 @@ def run(args) -> dict:
     torch.cuda.synchronize()  # the encrypted inputs exist before the clock starts
     sched = Scheduler({c: built[c][4] for c in classes}, args.policy, concurrent=args.concurrent)
     print(f"# serving {len(reqs)} requests over {args.window} s (cap {args.cap} s)", file=sys.stderr, flush=True)
-    rep = sched.run(reqs, args.window, args.cap)
+    rep = sched.run(reqs, args.window, args.cap, progress_s=10.0)
     torch.cuda.synchronize()  # batches still in flight at the cap finish before any decryption
     # accuracy of a few completed requests against the FP64 forward pass
     errs = {}
