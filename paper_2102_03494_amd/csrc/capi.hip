@@ -260,18 +260,19 @@ struct LKsCore {
                                                                                             c->mods, c->tb())));
     }
     const unsigned grid = xcd_grid(lmax + pg, count);
+    constexpr int TM = modup_threads<LOGN>();  // ModUp workgroup size
     static const char* names[3] = {"ks_modup_ip", "ks_modup_ip_f64", "ks_modup_ip_wide"};
     const int n_cls = (int)c->has_cls[0] + (int)c->has_cls[1] + (int)c->has_cls[2];
     if (n_cls == 2) {  // one launch, each workgroup in its target's class
       Prof stage(c, "ks_modup_stage", s);
       if (!c->has_cls[CLS_U64])
-        k_ks_modup_ip2<LOGN, CLS_N32, CLS_F64><<<grid, T, 0, s>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l,
+        k_ks_modup_ip2<LOGN, CLS_N32, CLS_F64><<<grid, TM, 0, s>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l,
                                                                    c->mods, c->tb());
       else if (!c->has_cls[CLS_F64])
-        k_ks_modup_ip2<LOGN, CLS_N32, CLS_U64><<<grid, T, 0, s>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l,
+        k_ks_modup_ip2<LOGN, CLS_N32, CLS_U64><<<grid, TM, 0, s>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l,
                                                                    c->mods, c->tb());
       else
-        k_ks_modup_ip2<LOGN, CLS_F64, CLS_U64><<<grid, T, 0, s>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l,
+        k_ks_modup_ip2<LOGN, CLS_F64, CLS_U64><<<grid, TM, 0, s>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l,
                                                                    c->mods, c->tb());
     } else {
     const bool forked = n_cls > 1;
@@ -288,13 +289,13 @@ struct LKsCore {
         first = false;
         Prof pr(c, names[cls], st);
         if (cls == CLS_N32)
-          k_ks_modup_ip<LOGN, CLS_N32><<<grid, T, 0, st>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l, c->mods,
+          k_ks_modup_ip<LOGN, CLS_N32><<<grid, TM, 0, st>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l, c->mods,
                                                             c->tb());
         else if (cls == CLS_F64)
-          k_ks_modup_ip<LOGN, CLS_F64><<<grid, T, 0, st>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l, c->mods,
+          k_ks_modup_ip<LOGN, CLS_F64><<<grid, TM, 0, st>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l, c->mods,
                                                             c->tb());
         else
-          k_ks_modup_ip<LOGN, CLS_U64><<<grid, T, 0, st>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l, c->mods,
+          k_ks_modup_ip<LOGN, CLS_U64><<<grid, TM, 0, st>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l, c->mods,
                                                             c->tb());
       }
       if (forked) {

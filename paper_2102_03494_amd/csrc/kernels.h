@@ -72,14 +72,26 @@ __device__ __forceinline__ int opaque_tid() {
   return tid;
 }
 
-template <int LOGN, int CLS>
+template <int LOGN, int CLS, int E = 16>
 __device__ __forceinline__ void fwd_lds(u64* lds, const Tables& tb, int mi, const ModConst& m) {
-  ntt_fwd_lds<LOGN, CLS>(lds, tw_of<LOGN, CLS>(tb, mi, 0), mview<CLS>(m), opaque_tid());
+  ntt_fwd_lds<LOGN, CLS, E>(lds, tw_of<LOGN, CLS>(tb, mi, 0), mview<CLS>(m), opaque_tid());
 }
 
-template <int LOGN, int CLS>
+template <int LOGN, int CLS, int E = 16>
 __device__ __forceinline__ void inv_lds(u64* lds, const Tables& tb, int mi, const ModConst& m) {
-  ntt_inv_lds<LOGN, CLS>(lds, tw_of<LOGN, CLS>(tb, mi, 2), mview<CLS>(m), opaque_tid());
+  ntt_inv_lds<LOGN, CLS, E>(lds, tw_of<LOGN, CLS>(tb, mi, 2), mview<CLS>(m), opaque_tid());
+}
+
+// Entries per thread of the ModUp + inner-product kernels: 8 (twice the
+// threads of a transform workgroup, half the registers per thread, so twice
+// the waves per SIMD) while N / 8 threads fit a workgroup.
+template <int LOGN>
+constexpr int modup_e() {
+  return LOGN <= 13 ? 8 : 16;
+}
+template <int LOGN>
+constexpr int modup_threads() {
+  return NttGeom<LOGN, modup_e<LOGN>()>::T;
 }
 
 template <bool NARROW>
@@ -101,11 +113,11 @@ __device__ __forceinline__ u64 shoupm(u64 a, u64 w, u64 wsh, u64 q) {
 // Coalesced limb load into LDS, optionally through the Galois permutation
 // sigma_g: afterwards lds[i] = src[galois_src(i, g)].  ginv = g^-1 mod 2N
 // (the scatter position of source entry idx is galois_src(idx, ginv)).
-template <int LOGN, int CLS>
+template <int LOGN, int CLS, int E = 16>
 __device__ __forceinline__ void load_limb_perm(u64* lds, const u64* __restrict__ src, u32 ginv) {
-  constexpr int T = NttGeom<LOGN>::T;
+  constexpr int T = NttGeom<LOGN, E>::T;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
+  for (int r = 0; r < E; ++r) {
     const int idx = (int)threadIdx.x + r * T;
     const u64 v = src[idx];
     const int dst = (ginv == 1u) ? idx : galois_src<LOGN>(idx, ginv);
@@ -117,12 +129,12 @@ __device__ __forceinline__ void load_limb_perm(u64* lds, const u64* __restrict__
 // an inverse transform).  PACK: a narrow limb goes out as N 32-bit words at
 // the start of its row (the layout of coefficient-domain scratch rows, which
 // lift_limb reads); otherwise every residue takes a 64-bit word.
-template <int LOGN, int CLS, bool PACK = false>
+template <int LOGN, int CLS, bool PACK = false, int E = 16>
 __device__ __forceinline__ void store_limb(u64* __restrict__ dst, const u64* lds, const ModConst& m, bool scale) {
-  constexpr int T = NttGeom<LOGN>::T;
+  constexpr int T = NttGeom<LOGN, E>::T;
   const int i0 = lds_idx((int)threadIdx.x);
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
+  for (int r = 0; r < E; ++r) {
     const int i = (int)threadIdx.x + r * T;
     const int li = lds_step(i0, r, T);
     if constexpr (CLS == CLS_F64) {
@@ -150,70 +162,70 @@ __device__ __forceinline__ void store_limb(u64* __restrict__ dst, const u64* lds
 //     value;
 //   otherwise: lift_centered (64-bit Barrett).
 // A narrow source row is packed: N 32-bit words (store_limb<.., true>).
-template <int LOGN, int CLS>
+template <int LOGN, int CLS, int E = 16>
 __device__ __forceinline__ void lift_limb(u64* lds, const u64* __restrict__ src, u64 qs, const ModConst& m, int tid) {
-  constexpr int T = NttGeom<LOGN>::T;
+  constexpr int T = NttGeom<LOGN, E>::T;
   const int i0 = lds_idx(tid);
   if (qs < NARROW_LIMIT) {
     const u32* s32 = reinterpret_cast<const u32*>(src);
-    u32 v[16];
+    u32 v[E];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = s32[tid + r * T];
+    for (int r = 0; r < E; ++r) v[r] = s32[tid + r * T];
     const u32 half = (u32)((qs - 1) / 2);
     if constexpr (CLS == CLS_N32) {
       if (qs < 2 * m.q) {
         const u32 add = (u32)(m.q - qs);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) lds_putw_at<CLS>(lds, lds_step(i0, r, T), v[r] > half ? v[r] + add : v[r]);
+        for (int r = 0; r < E; ++r) lds_putw_at<CLS>(lds, lds_step(i0, r, T), v[r] > half ? v[r] + add : v[r]);
       } else {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) lds_putw_at<CLS>(lds, lds_step(i0, r, T), (u32)lift_centered(v[r], qs, m));
+        for (int r = 0; r < E; ++r) lds_putw_at<CLS>(lds, lds_step(i0, r, T), (u32)lift_centered(v[r], qs, m));
       }
     } else if constexpr (CLS == CLS_F64) {
       const double qsd = (double)(u32)qs;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
+      for (int r = 0; r < E; ++r) {
         const double x = (double)v[r];
         lds_putw_at<CLS>(lds, lds_step(i0, r, T), v[r] > half ? x - qsd : x);
       }
     } else {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) lds_putw_at<CLS>(lds, lds_step(i0, r, T), lift_centered(v[r], qs, m));
+      for (int r = 0; r < E; ++r) lds_putw_at<CLS>(lds, lds_step(i0, r, T), lift_centered(v[r], qs, m));
     }
   } else {
-    u64 v[16];
+    u64 v[E];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = src[tid + r * T];
+    for (int r = 0; r < E; ++r) v[r] = src[tid + r * T];
     const u64 half = (qs - 1) / 2;
     if constexpr (CLS == CLS_F64) {
       if (qs < ((u64)1 << 43)) {
         const double qsd = f64_from_u64(qs);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
+        for (int r = 0; r < E; ++r) {
           const double x = f64_from_u64(v[r]);
           lds_putw_at<CLS>(lds, lds_step(i0, r, T), v[r] > half ? x - qsd : x);
         }
       } else {
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
+        for (int r = 0; r < E; ++r)
           lds_putw_at<CLS>(lds, lds_step(i0, r, T), f64_from_u64(lift_centered(v[r], qs, m)));
       }
     } else if constexpr (CLS == CLS_N32) {
       if (qs < ((u64)1 << 43)) {
         const double qsd = f64_from_u64(qs);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
+        for (int r = 0; r < E; ++r) {
           double x = f64_from_u64(v[r]);
           if (v[r] > half) x -= qsd;
           lds_putw_at<CLS>(lds, lds_step(i0, r, T), (u32)f64_canon(x, m.qd, m.qinv));
         }
       } else {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) lds_putw_at<CLS>(lds, lds_step(i0, r, T), (u32)lift_centered(v[r], qs, m));
+        for (int r = 0; r < E; ++r) lds_putw_at<CLS>(lds, lds_step(i0, r, T), (u32)lift_centered(v[r], qs, m));
       }
     } else {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) lds_putw_at<CLS>(lds, lds_step(i0, r, T), lift_centered(v[r], qs, m));
+      for (int r = 0; r < E; ++r) lds_putw_at<CLS>(lds, lds_step(i0, r, T), lift_centered(v[r], qs, m));
     }
   }
 }
@@ -328,32 +340,32 @@ __host__ __device__ inline int pgroup_count(int level, int pg) {
   return (level + g - 1) / g;
 }
 
-// The whole P limb of one inner-product polynomial, held as this thread's 16
+// The whole P limb of one inner-product polynomial, held as this thread's E
 // accumulators (entries tid + r T, as modup_ip_body sums them), to its
 // coefficient-domain copy for ModDown: canonical residues, INTT, N^-1, packed
 // store at out (what k_intt_last computes from a u row).
-template <int LOGN, int CLS, typename A>
-__device__ __forceinline__ void p_limb_to_coeffs(u64* lds, const A (&acc)[16], u64* out, int mi, const ModConst& m,
+template <int LOGN, int CLS, int E, typename A>
+__device__ __forceinline__ void p_limb_to_coeffs(u64* lds, const A (&acc)[E], u64* out, int mi, const ModConst& m,
                                                  const Tables& tb) {
-  constexpr int T = NttGeom<LOGN>::T;
+  constexpr int T = NttGeom<LOGN, E>::T;
   __syncthreads();  // the LDS buffer is free
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
+  for (int r = 0; r < E; ++r) {
     u64 v;
     if constexpr (CLS == CLS_N32) v = reduce64(acc[r], m);
     else if constexpr (CLS == CLS_F64) v = to_canon<CLS>(acc[r], m);
     else v = acc[r];
     lds_put<CLS>(lds, (int)threadIdx.x + r * T, v);
   }
-  inv_lds<LOGN, CLS>(lds, tb, mi, m);
-  store_limb<LOGN, CLS, true>(out, lds, m, true);
+  inv_lds<LOGN, CLS, E>(lds, tb, mi, m);
+  store_limb<LOGN, CLS, true, E>(out, lds, m, true);
 }
 
 // Key switch, step 2: ModUp + inner product for one target: a ciphertext
 // prime t over all digits, or one group of digits [j0, j1) for P.
 // Accumulates sum_j NTT(lift(digit_j) mod m) * key[j][.][m] in registers and
 // writes it to u row `row` (canonical residues).
-template <int LOGN, int CLS>
+template <int LOGN, int CLS, int E = 16>
 __device__ __forceinline__ void modup_ip_body(u64* lds, const u64* __restrict__ dcoef, const KsJob& jb, size_t b,
                                               u64* __restrict__ u, u64* __restrict__ rc_p, int lmax, int urows,
                                               int big_l, int t, int mi, int j0, int j1, int row, const Mods& mods,
@@ -362,27 +374,27 @@ __device__ __forceinline__ void modup_ip_body(u64* lds, const u64* __restrict__ 
   // (each < 2^60, at most 15 digits), centred doubles (f64), residues (wide)
   typedef std::conditional_t<CLS == CLS_N32, u64, word_t<CLS>> A;
   constexpr int N = 1 << LOGN;
-  constexpr int T = NttGeom<LOGN>::T;
+  constexpr int T = NttGeom<LOGN, E>::T;
   const ModConst m = mods.m[mi];
   const u64* key = jb.key;
-  A acc0[16], acc1[16];
+  A acc0[E], acc1[E];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0;
+  for (int r = 0; r < E; ++r) acc0[r] = acc1[r] = 0;
   for (int j = j0; j < j1; ++j) {
     if (j == t) {
       // the digit reduced mod its own prime is the (permuted) input limb itself
-      load_limb_perm<LOGN, CLS>(lds, jb.d + (size_t)j * N, jb.ginv);
+      load_limb_perm<LOGN, CLS, E>(lds, jb.d + (size_t)j * N, jb.ginv);
       __syncthreads();
     } else {
-      lift_limb<LOGN, CLS>(lds, dcoef + (b * lmax + j) * N, mods.m[j].q, m, opaque_tid());
-      fwd_lds<LOGN, CLS>(lds, tb, mi, m);
+      lift_limb<LOGN, CLS, E>(lds, dcoef + (b * lmax + j) * N, mods.m[j].q, m, opaque_tid());
+      fwd_lds<LOGN, CLS, E>(lds, tb, mi, m);
     }
     const u64* kb = key + (((size_t)j * 2 + 0) * (big_l + 1) + mi) * N;
     const u64* ka = key + (((size_t)j * 2 + 1) * (big_l + 1) + mi) * N;
     const int tid = opaque_tid();
     const int i0 = lds_idx(tid);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
+    for (int r = 0; r < E; ++r) {
       const int i = tid + r * T;
       const int li = lds_step(i0, r, T);
       if constexpr (CLS == CLS_N32) {
@@ -405,14 +417,14 @@ __device__ __forceinline__ void modup_ip_body(u64* lds, const u64* __restrict__ 
     __syncthreads();
   }
   if (rc_p) {
-    p_limb_to_coeffs<LOGN, CLS>(lds, acc0, rc_p, mi, m, tb);
-    p_limb_to_coeffs<LOGN, CLS>(lds, acc1, rc_p + N, mi, m, tb);
+    p_limb_to_coeffs<LOGN, CLS, E>(lds, acc0, rc_p, mi, m, tb);
+    p_limb_to_coeffs<LOGN, CLS, E>(lds, acc1, rc_p + N, mi, m, tb);
     return;
   }
   u64* u0 = u + ((b * 2 + 0) * urows + row) * N;
   u64* u1 = u + ((b * 2 + 1) * urows + row) * N;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
+  for (int r = 0; r < E; ++r) {
     const int i = (int)threadIdx.x + r * T;
     if constexpr (CLS == CLS_N32) {  // packed row
       reinterpret_cast<u32*>(u0)[i] = (u32)reduce64(acc0[r], m);
@@ -455,7 +467,7 @@ constexpr int stage_words() {
 // loads of the transform would wait for copies issued after the digit; the
 // copies go first.)  Each lane reads back only the words it copied, so a
 // wave waits for its own copies and needs no barrier for them.
-template <int LOGN>
+template <int LOGN, int E>
 __device__ __forceinline__ void modup_ip_narrow_staged(u64* lds, u32* S, const u64* __restrict__ dcoef,
                                                        const KsJob& jb, size_t b, u64* __restrict__ u,
                                                        u64* __restrict__ rc_p, int lmax, int urows, int big_l, int t,
@@ -463,35 +475,35 @@ __device__ __forceinline__ void modup_ip_narrow_staged(u64* lds, u32* S, const u
                                                        const Tables& tb) {
   constexpr int CLS = CLS_N32;
   constexpr int N = 1 << LOGN;
-  constexpr int T = NttGeom<LOGN>::T;
+  constexpr int T = NttGeom<LOGN, E>::T;
   const ModConst m = mods.m[mi];
   const u64* key = jb.key;
   const int tid = opaque_tid();
   const int wave0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x) & ~63;  // first thread of the wave
   const int i0 = lds_idx(tid);
-  u64 acc0[16], acc1[16];
+  u64 acc0[E], acc1[E];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0;
+  for (int r = 0; r < E; ++r) acc0[r] = acc1[r] = 0;
   for (int j = j0; j < j1; ++j) {
     const u32* kb = reinterpret_cast<const u32*>(key + (((size_t)j * 2 + 0) * (big_l + 1) + mi) * N);
     const u32* ka = reinterpret_cast<const u32*>(key + (((size_t)j * 2 + 1) * (big_l + 1) + mi) * N);
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
+    for (int r = 0; r < E; ++r) {
       copy_to_lds(kb + tid + r * T, S + r * T + wave0);
       copy_to_lds(ka + tid + r * T, S + N + r * T + wave0);
     }
     __builtin_amdgcn_sched_barrier(0);  // the copies are issued before the digit's loads
     if (j == t) {
       // the digit reduced mod its own prime is the (permuted) input limb itself
-      load_limb_perm<LOGN, CLS>(lds, jb.d + (size_t)j * N, jb.ginv);
+      load_limb_perm<LOGN, CLS, E>(lds, jb.d + (size_t)j * N, jb.ginv);
       lds_barrier();
     } else {
-      lift_limb<LOGN, CLS>(lds, dcoef + (b * lmax + j) * N, mods.m[j].q, m, tid);
-      fwd_lds<LOGN, CLS>(lds, tb, mi, m);
+      lift_limb<LOGN, CLS, E>(lds, dcoef + (b * lmax + j) * N, mods.m[j].q, m, tid);
+      fwd_lds<LOGN, CLS, E>(lds, tb, mi, m);
     }
     wait_vm();
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
+    for (int r = 0; r < E; ++r) {
       const u32 dv = (u32)to_canon<CLS>(lds_getw_at<CLS>(lds, lds_step(i0, r, T)), m);
       acc0[r] += (u64)dv * S[r * T + tid];
       acc1[r] += (u64)dv * S[N + r * T + tid];
@@ -499,14 +511,14 @@ __device__ __forceinline__ void modup_ip_narrow_staged(u64* lds, u32* S, const u
     lds_barrier();  // the copies of the next digit overwrite S
   }
   if (rc_p) {
-    p_limb_to_coeffs<LOGN, CLS>(lds, acc0, rc_p, mi, m, tb);
-    p_limb_to_coeffs<LOGN, CLS>(lds, acc1, rc_p + N, mi, m, tb);
+    p_limb_to_coeffs<LOGN, CLS, E>(lds, acc0, rc_p, mi, m, tb);
+    p_limb_to_coeffs<LOGN, CLS, E>(lds, acc1, rc_p + N, mi, m, tb);
     return;
   }
   u64* u0 = u + ((b * 2 + 0) * urows + row) * N;
   u64* u1 = u + ((b * 2 + 1) * urows + row) * N;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
+  for (int r = 0; r < E; ++r) {
     const int i = (int)threadIdx.x + r * T;
     reinterpret_cast<u32*>(u0)[i] = (u32)reduce64(acc0[r], m);
     reinterpret_cast<u32*>(u1)[i] = (u32)reduce64(acc1[r], m);
@@ -544,9 +556,10 @@ __device__ __forceinline__ bool modup_target(const KsJob& jb, int x, int lmax, i
 // the other classes, primes above a job's level and empty P groups exit at
 // once.  Narrow targets of rings up to 2^STAGE_MAX_LOGN take the staged body.
 template <int LOGN, int CLS>
-__global__ void __launch_bounds__(NttGeom<LOGN>::T)
+__global__ void __launch_bounds__(modup_threads<LOGN>())
 k_ks_modup_ip(const KsJob* __restrict__ jobs, int count, const u64* __restrict__ dcoef, u64* __restrict__ u,
               u64* __restrict__ rc, int lmax, int pg, int big_l, Mods mods, Tables tb) {
+  constexpr int EM = modup_e<LOGN>();
   __shared__ u64 lds[lds_words<LOGN, CLS>()];
   const XcdSlot sl = xcd_slot(lmax + pg);
   if (sl.job >= count) return;
@@ -560,22 +573,22 @@ k_ks_modup_ip(const KsJob* __restrict__ jobs, int count, const u64* __restrict__
   if ((int)mods.m[o.mi].cls != CLS) return;
   if constexpr (CLS == CLS_N32 && LOGN <= STAGE_MAX_LOGN) {
     __shared__ __align__(16) u32 S[stage_words<LOGN>()];
-    modup_ip_narrow_staged<LOGN>(lds, S, dcoef, jb, b, u, rc_p, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row,
-                                 mods, tb);
+    modup_ip_narrow_staged<LOGN, EM>(lds, S, dcoef, jb, b, u, rc_p, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1,
+                                     o.row, mods, tb);
   } else {
-    modup_ip_body<LOGN, CLS>(lds, dcoef, jb, b, u, rc_p, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row, mods,
-                             tb);
+    modup_ip_body<LOGN, CLS, EM>(lds, dcoef, jb, b, u, rc_p, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row,
+                                 mods, tb);
   }
 }
 
 // The same for a ring whose primes span two width classes A and B: one
-// launch in which each workgroup runs the body of its target's class (both
-// bodies hold one workgroup per CU anyway), instead of one kernel per class
-// on two streams joined by events.
+// launch in which each workgroup runs the body of its target's class,
+// instead of one kernel per class on two streams joined by events.
 template <int LOGN, int CA, int CB>
-__global__ void __launch_bounds__(NttGeom<LOGN>::T)
+__global__ void __launch_bounds__(modup_threads<LOGN>())
 k_ks_modup_ip2(const KsJob* __restrict__ jobs, int count, const u64* __restrict__ dcoef, u64* __restrict__ u,
                u64* __restrict__ rc, int lmax, int pg, int big_l, Mods mods, Tables tb) {
+  constexpr int EM = modup_e<LOGN>();
   const XcdSlot sl = xcd_slot(lmax + pg);
   if (sl.job >= count) return;
   const size_t b = sl.job;
@@ -592,20 +605,20 @@ k_ks_modup_ip2(const KsJob* __restrict__ jobs, int count, const u64* __restrict_
     __shared__ u64 lds[lds_words<LOGN, CA>()];
     __shared__ __align__(16) u32 S[stage_words<LOGN>()];
     if (is_a)
-      modup_ip_narrow_staged<LOGN>(lds, S, dcoef, jb, b, u, rc_p, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row,
-                                   mods, tb);
+      modup_ip_narrow_staged<LOGN, EM>(lds, S, dcoef, jb, b, u, rc_p, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1,
+                                       o.row, mods, tb);
     else
-      modup_ip_body<LOGN, CB>(reinterpret_cast<u64*>(S), dcoef, jb, b, u, rc_p, lmax, lmax + pg, big_l, o.t, o.mi,
-                              o.j0, o.j1, o.row, mods, tb);
+      modup_ip_body<LOGN, CB, EM>(reinterpret_cast<u64*>(S), dcoef, jb, b, u, rc_p, lmax, lmax + pg, big_l, o.t,
+                                  o.mi, o.j0, o.j1, o.row, mods, tb);
   } else {
     constexpr int LW = lds_words<LOGN, CA>() > lds_words<LOGN, CB>() ? lds_words<LOGN, CA>() : lds_words<LOGN, CB>();
     __shared__ u64 lds[LW];
     if (is_a)
-      modup_ip_body<LOGN, CA>(lds, dcoef, jb, b, u, rc_p, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row, mods,
-                              tb);
+      modup_ip_body<LOGN, CA, EM>(lds, dcoef, jb, b, u, rc_p, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row,
+                                  mods, tb);
     else
-      modup_ip_body<LOGN, CB>(lds, dcoef, jb, b, u, rc_p, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row, mods,
-                              tb);
+      modup_ip_body<LOGN, CB, EM>(lds, dcoef, jb, b, u, rc_p, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row,
+                                  mods, tb);
   }
 }
 

@@ -70,11 +70,16 @@ __device__ __forceinline__ int lds_step(int idx0, int r, int stride) { return id
 // keeps the compiler from moving memory accesses across it.
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-template <int LOGN>
+// Transform workgroup geometry: E entries per thread per pass (16, or 8 for
+// twice the threads with half the registers each), T = N / E threads, and
+// radix-E register passes (log2 E stages between barriers).
+template <int LOGN, int E_ = 16>
 struct NttGeom {
+  static_assert(E_ == 16 || E_ == 8, "16 or 8 entries per thread");
   static constexpr int N = 1 << LOGN;
-  static constexpr int E = 16;           // entries per thread per pass
-  static constexpr int T = N / E;        // threads per workgroup
+  static constexpr int E = E_;              // entries per thread per pass
+  static constexpr int T = N / E;           // threads per workgroup
+  static constexpr int KMAX = E == 16 ? 4 : 3;  // stages per register pass
   static constexpr int LDS = N + (N >> 5);  // 64-bit words reserved (narrow limbs use half)
 };
 
@@ -227,15 +232,15 @@ struct Tw {
 };
 
 // One forward pass: stages s0 .. s0+K-1.
-template <int LOGN, int K, int CLS>
+template <int LOGN, int K, int CLS, int E = 16>
 __device__ __forceinline__ void fwd_pass(u64* lds_raw, int s0, Tw<CLS> tw, MV<CLS> q, int tid) {
   typedef word_t<CLS> W;
   typedef Arith<CLS> A;
   W* lds = reinterpret_cast<W*>(lds_raw);
   constexpr int N = 1 << LOGN;
   constexpr int R = 1 << K;
-  constexpr int T = NttGeom<LOGN>::T;
-  constexpr int G = 16 / R;
+  constexpr int T = NttGeom<LOGN, E>::T;
+  constexpr int G = E / R;
   const int B0 = N >> s0;
   const int Wd = B0 >> K;
   const int logW = LOGN - s0 - K;
@@ -269,15 +274,15 @@ __device__ __forceinline__ void fwd_pass(u64* lds_raw, int s0, Tw<CLS> tw, MV<CL
 }
 
 // One inverse pass: stages s0+K-1 down to s0.
-template <int LOGN, int K, int CLS>
+template <int LOGN, int K, int CLS, int E = 16>
 __device__ __forceinline__ void inv_pass(u64* lds_raw, int s0, Tw<CLS> tw, MV<CLS> q, int tid) {
   typedef word_t<CLS> W;
   typedef Arith<CLS> A;
   W* lds = reinterpret_cast<W*>(lds_raw);
   constexpr int N = 1 << LOGN;
   constexpr int R = 1 << K;
-  constexpr int T = NttGeom<LOGN>::T;
-  constexpr int G = 16 / R;
+  constexpr int T = NttGeom<LOGN, E>::T;
+  constexpr int G = E / R;
   const int B0 = N >> s0;
   const int Wd = B0 >> K;
   const int logW = LOGN - s0 - K;
@@ -314,36 +319,38 @@ __device__ __forceinline__ void inv_pass(u64* lds_raw, int s0, Tw<CLS> tw, MV<CL
 }
 
 // Forward transform of the limb held in LDS (all threads of the workgroup).
-template <int LOGN, int CLS>
+template <int LOGN, int CLS, int E = 16>
 __device__ __forceinline__ void ntt_fwd_lds(u64* lds, Tw<CLS> tw, MV<CLS> q, int tid) {
-  constexpr int FULL = LOGN / 4;
-  constexpr int REM = LOGN % 4;
+  constexpr int KM = NttGeom<LOGN, E>::KMAX;
+  constexpr int FULL = LOGN / KM;
+  constexpr int REM = LOGN % KM;
   lds_barrier();
 #pragma unroll
   for (int p = 0; p < FULL; ++p) {
-    fwd_pass<LOGN, 4, CLS>(lds, 4 * p, tw, q, tid);
+    fwd_pass<LOGN, KM, CLS, E>(lds, KM * p, tw, q, tid);
     lds_barrier();
   }
   if constexpr (REM > 0) {
-    fwd_pass<LOGN, REM, CLS>(lds, 4 * FULL, tw, q, tid);
+    fwd_pass<LOGN, REM, CLS, E>(lds, KM * FULL, tw, q, tid);
     lds_barrier();
   }
 }
 
 // Inverse transform of the limb held in LDS, without the N^-1 factor (the
 // caller folds it into its store).
-template <int LOGN, int CLS>
+template <int LOGN, int CLS, int E = 16>
 __device__ __forceinline__ void ntt_inv_lds(u64* lds, Tw<CLS> tw, MV<CLS> q, int tid) {
-  constexpr int FULL = LOGN / 4;
-  constexpr int REM = LOGN % 4;
+  constexpr int KM = NttGeom<LOGN, E>::KMAX;
+  constexpr int FULL = LOGN / KM;
+  constexpr int REM = LOGN % KM;
   lds_barrier();
   if constexpr (REM > 0) {
-    inv_pass<LOGN, REM, CLS>(lds, 4 * FULL, tw, q, tid);
+    inv_pass<LOGN, REM, CLS, E>(lds, KM * FULL, tw, q, tid);
     lds_barrier();
   }
 #pragma unroll
   for (int p = FULL - 1; p >= 0; --p) {
-    inv_pass<LOGN, 4, CLS>(lds, 4 * p, tw, q, tid);
+    inv_pass<LOGN, KM, CLS, E>(lds, KM * p, tw, q, tid);
     lds_barrier();
   }
 }
