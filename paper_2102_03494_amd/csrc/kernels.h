@@ -525,14 +525,18 @@ __device__ __forceinline__ void modup_ip_narrow_staged(u64* lds, u32* S, const u
   }
 }
 
-// Target of workgroup x of job jb in the ModUp grid: ciphertext prime x
-// (x < lmax) over all digits, or group x - lmax of P's digits.  False: the
-// workgroup has nothing to do.
+// Target x of workgroup `sub` of job jb in the ModUp grid: ciphertext prime
+// x (x < lmax) over all digits, or group x - lmax of P's digits, whose
+// partial goes to u row x.  False: the workgroup has nothing to do.
 struct ModupTarget {
   int t, mi, j0, j1, row;
 };
-__device__ __forceinline__ bool modup_target(const KsJob& jb, int x, int lmax, int pg, int big_l, ModupTarget& o) {
+// The P groups come first in a job's run of workgroups (sub < pg): a P
+// workgroup is the longest of its job (costlier width class, and with one
+// group also the INTT of the P limb), so it starts before the short ones.
+__device__ __forceinline__ bool modup_target(const KsJob& jb, int sub, int lmax, int pg, int big_l, ModupTarget& o) {
   const int level = jb.level;
+  const int x = sub < pg ? lmax + sub : sub - pg;
   if (x < lmax) {
     if (x >= level) return false;
     o.t = o.mi = o.row = x;

@@ -273,8 +273,12 @@ __device__ __forceinline__ void fwd_pass(u64* lds_raw, int s0, Tw<CLS> tw, MV<CL
   }
 }
 
-// One inverse pass: stages s0+K-1 down to s0.
-template <int LOGN, int K, int CLS, int E = 16>
+// One inverse pass: stages s0+K-1 down to s0.  f64 sums are centred only at
+// the pass's last stage (and, in a first radix-16 pass, whose input is
+// canonical in [0, q), also after its second stage): a pass's input then
+// stays below 0.54 q in magnitude (q in the first pass), so sums stay below
+// 8.7 q and the products' inputs within the forward transform's range.
+template <int LOGN, int K, int CLS, int E = 16, bool FIRST = false>
 __device__ __forceinline__ void inv_pass(u64* lds_raw, int s0, Tw<CLS> tw, MV<CLS> q, int tid) {
   typedef word_t<CLS> W;
   typedef Arith<CLS> A;
@@ -306,7 +310,12 @@ __device__ __forceinline__ void inv_pass(u64* lds_raw, int s0, Tw<CLS> tw, MV<CL
         const int ti = m + (blk << u) + (r >> (K - u));
         const W x = v[r];
         const W y = v[r + half];
-        v[r] = A::add_inv(x, y, q);
+        if constexpr (CLS == CLS_F64) {
+          const bool centre = u == 0 || (FIRST && K == 4 && u == 2);
+          v[r] = centre ? A::add_inv(x, y, q) : A::add(x, y, q);
+        } else {
+          v[r] = A::add_inv(x, y, q);
+        }
         v[r + half] = A::mulc(A::sub_inv(x, y, q), tw.w[ti], CLS == CLS_F64 ? W(0) : tw.sh[ti], q);
       }
       // f64: load the next stage's twiddles after this stage, so only one
@@ -345,11 +354,14 @@ __device__ __forceinline__ void ntt_inv_lds(u64* lds, Tw<CLS> tw, MV<CLS> q, int
   constexpr int REM = LOGN % KM;
   lds_barrier();
   if constexpr (REM > 0) {
-    inv_pass<LOGN, REM, CLS, E>(lds, KM * FULL, tw, q, tid);
+    inv_pass<LOGN, REM, CLS, E, true>(lds, KM * FULL, tw, q, tid);
+    lds_barrier();
+  } else {
+    inv_pass<LOGN, KM, CLS, E, true>(lds, KM * (FULL - 1), tw, q, tid);
     lds_barrier();
   }
 #pragma unroll
-  for (int p = FULL - 1; p >= 0; --p) {
+  for (int p = (REM > 0 ? FULL : FULL - 1) - 1; p >= 0; --p) {
     inv_pass<LOGN, KM, CLS, E>(lds, KM * p, tw, q, tid);
     lds_barrier();
   }
