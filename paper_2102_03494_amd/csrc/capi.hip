@@ -249,15 +249,19 @@ struct LNtt {
 template <int LOGN>
 struct LKsCore {
   static void run(he_ctx* c, const KsJob* jobs, int count, int lmax, int pg, u64* dcoef, u64* u, u64* rc,
-                  hipStream_t s) {
+                  hipStream_t s, int pk = 0) {
     constexpr int T = NttGeom<LOGN>::T;
     // with one P group, ModUp's P workgroups also write the coefficient-domain
     // P limb (rc), and no separate INTT launch is needed
     u64* rc1 = pg == 1 ? rc : nullptr;
     {
       Prof pr(c, "ks_digits", s);
-      HE_FOR_CLASSES(c->q_mask, (k_ks_digits<LOGN, CLS><<<xcd_grid(lmax, count), T, 0, s>>>(jobs, count, dcoef, lmax,
-                                                                                            c->mods, c->tb())));
+      if (pk & JOB_IN_PACKED)
+        HE_FOR_CLASSES(c->q_mask, (k_ks_digits<LOGN, CLS, true><<<xcd_grid(lmax, count), T, 0, s>>>(
+                                      jobs, count, dcoef, lmax, c->mods, c->tb())));
+      else
+        HE_FOR_CLASSES(c->q_mask, (k_ks_digits<LOGN, CLS, false><<<xcd_grid(lmax, count), T, 0, s>>>(
+                                      jobs, count, dcoef, lmax, c->mods, c->tb())));
     }
     const unsigned grid = xcd_grid(lmax + pg, count);
     constexpr int TM = modup_threads<LOGN>();  // ModUp workgroup size
@@ -316,25 +320,30 @@ struct LKsCore {
 template <int LOGN>
 struct LDrop {
   static void run(he_ctx* c, int mode, int epi, const KsJob* jobs, int count, int lmax, int urows, const u64* u,
-                  const u64* rc, hipStream_t s) {
+                  const u64* rc, hipStream_t s, int pk = 0) {
     constexpr int T = NttGeom<LOGN>::T;
     const int keep = mode == MODE_P ? lmax : lmax - 1;
     const unsigned grid = xcd_grid(2 * keep, count);
     Prof pr(c, "drop_last", s);
-#define HE_DROP(MD, EP)                                                                                    \
-  HE_FOR_CLASSES(c->q_mask, (k_drop_last<LOGN, MD, EP, CLS><<<grid, T, 0, s>>>(jobs, count, keep, u, urows,  \
-                                                                               c->big_l, rc, c->d_inv, c->mods, \
-                                                                               c->tb())))
+#define HE_DROP(MD, EP, PK)                                                                                    \
+  HE_FOR_CLASSES(c->q_mask, (k_drop_last<LOGN, MD, EP, CLS, PK><<<grid, T, 0, s>>>(jobs, count, keep, u, urows,  \
+                                                                                   c->big_l, rc, c->d_inv, c->mods, \
+                                                                                   c->tb())))
+    // packed variants exist where a rotate-and-sum chain uses them: its steps
+    // (ROTSUM, output packed, input packed after the first) and its rescale
     if (mode == MODE_LAST) {
-      HE_DROP(MODE_LAST, EPI_STORE);
+      if (pk & JOB_IN_PACKED) HE_DROP(MODE_LAST, EPI_STORE, JOB_IN_PACKED);
+      else HE_DROP(MODE_LAST, EPI_STORE, 0);
     } else if (epi == EPI_ROT) {
-      HE_DROP(MODE_P, EPI_ROT);
+      HE_DROP(MODE_P, EPI_ROT, 0);
     } else if (epi == EPI_ROTSUM) {
-      HE_DROP(MODE_P, EPI_ROTSUM);
+      if (pk == (JOB_IN_PACKED | JOB_OUT_PACKED)) HE_DROP(MODE_P, EPI_ROTSUM, JOB_IN_PACKED | JOB_OUT_PACKED);
+      else if (pk == JOB_OUT_PACKED) HE_DROP(MODE_P, EPI_ROTSUM, JOB_OUT_PACKED);
+      else HE_DROP(MODE_P, EPI_ROTSUM, 0);
     } else if (epi == EPI_RELIN) {
-      HE_DROP(MODE_P, EPI_RELIN);
+      HE_DROP(MODE_P, EPI_RELIN, 0);
     } else {
-      HE_DROP(MODE_P, EPI_STORE);
+      HE_DROP(MODE_P, EPI_STORE, 0);
     }
 #undef HE_DROP
   }
@@ -342,10 +351,16 @@ struct LDrop {
 
 template <int LOGN>
 struct LIntt1 {
-  static void run(he_ctx* c, const KsJob* jobs, int count, int lmax, u64* rc, hipStream_t s) {
+  static void run(he_ctx* c, const KsJob* jobs, int count, int lmax, u64* rc, hipStream_t s, int pk = 0) {
     Prof pr(c, "intt_last", s);
-    HE_FOR_CLASSES(c->q_mask, (k_intt_last<LOGN, MODE_LAST, CLS><<<xcd_grid(2, count), NttGeom<LOGN>::T, 0, s>>>(
-                                   jobs, count, nullptr, lmax, 1, c->big_l, rc, c->mods, c->tb())));
+    if (pk & JOB_IN_PACKED)
+      HE_FOR_CLASSES(c->q_mask, (k_intt_last<LOGN, MODE_LAST, CLS, true><<<xcd_grid(2, count), NttGeom<LOGN>::T, 0,
+                                                                           s>>>(jobs, count, nullptr, lmax, 1,
+                                                                                c->big_l, rc, c->mods, c->tb())));
+    else
+      HE_FOR_CLASSES(c->q_mask, (k_intt_last<LOGN, MODE_LAST, CLS, false><<<xcd_grid(2, count), NttGeom<LOGN>::T, 0,
+                                                                            s>>>(jobs, count, nullptr, lmax, 1,
+                                                                                 c->big_l, rc, c->mods, c->tb())));
   }
 };
 
@@ -459,10 +474,10 @@ int chunk_for(Arena& ar, int count, int lmax, int pg, int n, size_t extra_per_jo
 
 void make_jobs(he_ctx* c, KsJob* jobs, int count, const u64* d_base, size_t d_stride, const u64* c_base,
                size_t c_stride, u64* out_base, size_t out_stride, const u64* key, u32 g, u32 ginv, int level,
-               hipStream_t s) {
+               hipStream_t s, int flags = 0) {
   (void)c;
   k_make_jobs<<<(count + 255) / 256, 256, 0, s>>>(jobs, count, d_base, d_stride, c_base, c_stride, out_base,
-                                                  out_stride, key, g, ginv, level);
+                                                  out_stride, key, g, ginv, level, flags);
 }
 
 // Rotation (EPI_ROT into out) or rotate-and-add (EPI_ROTSUM, may be in place)
@@ -504,6 +519,7 @@ struct Chain {
   KsJob* jobs = nullptr;  // [steps][count]
   KsScratch ks;
   int count = 0, level = 0, pg = 1, steps = 0;
+  bool packed = false;  // the accumulator leaves the chain packed
 };
 
 // False (nothing launched) when the chain does not fit the arena in one
@@ -528,21 +544,26 @@ bool chain_prepare(he_ctx* c, u64* acc, int count, int level, int steps, Arena a
   ch.level = level;
   ch.pg = pg;
   ch.steps = steps;
+  // between steps the accumulator is kept packed when every ciphertext prime is narrow
+  ch.packed = c->q_mask == (1u << CLS_N32);
   k_make_chain_jobs<<<dim3((count + 255) / 256, steps), 256, 0, s>>>(ch.jobs, count, acc, (size_t)2 * level * n,
-                                                                    (size_t)level * n, level, ck);
+                                                                    (size_t)level * n, level, ck, (int)ch.packed);
   return true;
 }
 
 void chain_step(he_ctx* c, const Chain& ch, int j, hipStream_t s) {
   const KsJob* jobs = ch.jobs + (size_t)j * ch.count;
   const int g_is_one = galois_of(1 << j, c->n) == 1;
+  const int pk = ch.packed ? (JOB_OUT_PACKED | (j > 0 ? JOB_IN_PACKED : 0)) : 0;  // as k_make_chain_jobs sets
   if (!g_is_one)
-    dispatch_logn<LKsCore>(c->logn, c, jobs, ch.count, ch.level, ch.pg, ch.ks.dcoef, ch.ks.u, ch.ks.rc, s);
+    dispatch_logn<LKsCore>(c->logn, c, jobs, ch.count, ch.level, ch.pg, ch.ks.dcoef, ch.ks.u, ch.ks.rc, s, pk);
   dispatch_logn<LDrop>(c->logn, c, (int)MODE_P, (int)EPI_ROTSUM, jobs, ch.count, ch.level, ch.level + ch.pg,
-                       (const u64*)ch.ks.u, (const u64*)ch.ks.rc, s);
+                       (const u64*)ch.ks.u, (const u64*)ch.ks.rc, s, pk);
 }
 
-int rescale_batch(he_ctx* c, u64* out, const u64* in, int count, int level, Arena& ar, hipStream_t s) {
+// in_packed: the input is packed (narrow limbs as 32-bit words, see KsJob).
+int rescale_batch(he_ctx* c, u64* out, const u64* in, int count, int level, Arena& ar, hipStream_t s,
+                  bool in_packed = false) {
   const int n = c->n;
   const int chunk = (int)std::min<size_t>({(size_t)count, ar.left() / 8 / (2 * (size_t)n + 64), (size_t)32000});
   if (chunk < 1) return fail(c, HE_ENOMEM, "workspace too small for rescale");
@@ -555,10 +576,11 @@ int rescale_batch(he_ctx* c, u64* out, const u64* in, int count, int level, Aren
     const u64* cin = in + (size_t)b0 * 2 * level * n;
     u64* cout = out + (size_t)b0 * 2 * (level - 1) * n;
     make_jobs(c, jobs, cn, cin, (size_t)2 * level * n, cin, (size_t)2 * level * n, cout,
-              (size_t)2 * (level - 1) * n, nullptr, 1u, 1u, level, s);
-    dispatch_logn<LIntt1>(c->logn, c, (const KsJob*)jobs, cn, level, rc, s);
+              (size_t)2 * (level - 1) * n, nullptr, 1u, 1u, level, s, in_packed ? JOB_IN_PACKED : 0);
+    const int pk = in_packed ? JOB_IN_PACKED : 0;
+    dispatch_logn<LIntt1>(c->logn, c, (const KsJob*)jobs, cn, level, rc, s, pk);
     dispatch_logn<LDrop>(c->logn, c, (int)MODE_LAST, (int)EPI_STORE, (const KsJob*)jobs, cn, level, 0,
-                         (const u64*)nullptr, (const u64*)rc, s);
+                         (const u64*)nullptr, (const u64*)rc, s, pk);
   }
   return check_launch(c, "rescale");
 }
@@ -675,34 +697,39 @@ int densepack_run(he_ctx* c, const u64* d_in, int level, const he_conv_desc* des
       (void)hipStreamWaitEvent(c->side, c->fork_ev, 0);
       int e = HE_OK;
       Chain ch0, ch1;
+      bool packed0 = false, packed1 = false;
       if (chain_prepare(c, acc, h0, level, desc->r_steps, a0, s, ch0) &&
           chain_prepare(c, acc1, h1, level, desc->r_steps, a1, c->side, ch1)) {
         for (int j = 0; j < desc->r_steps; ++j) {
           chain_step(c, ch0, j, s);
           chain_step(c, ch1, j, c->side);
         }
+        packed0 = ch0.packed;
+        packed1 = ch1.packed;
       } else {
         for (int j = 0; j < desc->r_steps && !e; ++j) {
           e = rotate_batch(c, acc, acc, h0, level, 1 << j, EPI_ROTSUM, a0, s);
           if (!e) e = rotate_batch(c, acc1, acc1, h1, level, 1 << j, EPI_ROTSUM, a1, c->side);
         }
       }
-      if (!e) e = rescale_batch(c, out, acc, h0, level, a0, s);
-      if (!e) e = rescale_batch(c, out1, acc1, h1, level, a1, c->side);
+      if (!e) e = rescale_batch(c, out, acc, h0, level, a0, s, packed0);
+      if (!e) e = rescale_batch(c, out1, acc1, h1, level, a1, c->side, packed1);
       (void)hipEventRecord(c->join_ev, c->side);
       (void)hipStreamWaitEvent(s, c->join_ev, 0);
       if (e) return e;
     } else {
       Chain ch;
+      bool packed = false;
       if (chain_prepare(c, acc, cn, level, desc->r_steps, sub, s, ch)) {
         for (int j = 0; j < desc->r_steps; ++j) chain_step(c, ch, j, s);
+        packed = ch.packed;
       } else {
         for (int j = 0; j < desc->r_steps; ++j) {
           int e = rotate_batch(c, acc, acc, cn, level, 1 << j, EPI_ROTSUM, sub, s);
           if (e) return e;
         }
       }
-      int e = rescale_batch(c, out, acc, cn, level, sub, s);
+      int e = rescale_batch(c, out, acc, cn, level, sub, s, packed);
       if (e) return e;
     }
   }

@@ -72,6 +72,16 @@ __device__ __forceinline__ int opaque_tid() {
   return tid;
 }
 
+// Residue i of a limb row stored as 64-bit words, or packed as 32-bit words
+// (narrow primes).
+__device__ __forceinline__ u64 ld_res(const u64* row, int i, bool packed) {
+  return packed ? (u64) reinterpret_cast<const u32*>(row)[i] : row[i];
+}
+__device__ __forceinline__ void st_res(u64* row, int i, u64 v, bool packed) {
+  if (packed) reinterpret_cast<u32*>(row)[i] = (u32)v;
+  else row[i] = v;
+}
+
 template <int LOGN, int CLS, int E = 16>
 __device__ __forceinline__ void fwd_lds(u64* lds, const Tables& tb, int mi, const ModConst& m) {
   ntt_fwd_lds<LOGN, CLS, E>(lds, tw_of<LOGN, CLS>(tb, mi, 0), mview<CLS>(m), opaque_tid());
@@ -114,12 +124,12 @@ __device__ __forceinline__ u64 shoupm(u64 a, u64 w, u64 wsh, u64 q) {
 // sigma_g: afterwards lds[i] = src[galois_src(i, g)].  ginv = g^-1 mod 2N
 // (the scatter position of source entry idx is galois_src(idx, ginv)).
 template <int LOGN, int CLS, int E = 16>
-__device__ __forceinline__ void load_limb_perm(u64* lds, const u64* __restrict__ src, u32 ginv) {
+__device__ __forceinline__ void load_limb_perm(u64* lds, const u64* __restrict__ src, u32 ginv, bool packed = false) {
   constexpr int T = NttGeom<LOGN, E>::T;
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int idx = (int)threadIdx.x + r * T;
-    const u64 v = src[idx];
+    const u64 v = ld_res(src, idx, packed);
     const int dst = (ginv == 1u) ? idx : galois_src<LOGN>(idx, ginv);
     lds_put<CLS>(lds, dst, v);
   }
@@ -257,8 +267,8 @@ k_ntt(u64* data, int n_limbs, int first_mod, Mods mods, Tables tb) {
 // optionally through the Galois permutation on the way into LDS.
 template <int LOGN, int CLS>
 __device__ __forceinline__ void digits_body(u64* lds, const u64* src, u32 ginv, u64* out, int j, const ModConst& m,
-                                            const Tables& tb) {
-  load_limb_perm<LOGN, CLS>(lds, src, ginv);
+                                            const Tables& tb, bool packed = false) {
+  load_limb_perm<LOGN, CLS>(lds, src, ginv, packed);
   inv_lds<LOGN, CLS>(lds, tb, j, m);
   store_limb<LOGN, CLS, true>(out, lds, m, true);
 }
@@ -308,12 +318,21 @@ struct KsJob {
   const u64* key;  // [big_l][2][big_l+1][N]; nullptr = identity
   u32 g, ginv;     // Galois element (1 = none) and its inverse mod 2N
   int level;
-  int pad_;
+  int flags;       // JOB_IN_PACKED / JOB_OUT_PACKED
 };
+
+// Packed ciphertexts: every limb (all narrow primes) as N 32-bit residues at
+// the start of its 64-bit row, in the usual [2][level][N] layout.  The
+// internal accumulator of a rotate-and-sum chain is kept so between steps:
+// d and c of a job are packed (JOB_IN_PACKED), out is written packed
+// (JOB_OUT_PACKED).  ModUp reads the flag of each job; the digit, P-INTT
+// and ModDown/rescale kernels take the launch's flags as a template
+// parameter (all jobs of a launch share them).
+enum { JOB_IN_PACKED = 1, JOB_OUT_PACKED = 2 };
 
 // Key switch, step 1: coefficient-domain digits of sigma_g(d).
 // grid xcd_grid(Lmax, count): workgroup = (job b, digit j).
-template <int LOGN, int CLS>
+template <int LOGN, int CLS, bool PIN = false>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
 k_ks_digits(const KsJob* __restrict__ jobs, int count, u64* __restrict__ dcoef, int lmax, Mods mods, Tables tb) {
   constexpr int N = 1 << LOGN;
@@ -328,7 +347,7 @@ k_ks_digits(const KsJob* __restrict__ jobs, int count, u64* __restrict__ dcoef, 
   const u64* src = jb.d + (size_t)j * N;
   u64* out = dcoef + (b * lmax + j) * N;
   if ((int)m.cls != CLS) return;
-  digits_body<LOGN, CLS>(lds, src, jb.ginv, out, j, m, tb);
+  digits_body<LOGN, CLS>(lds, src, jb.ginv, out, j, m, tb, PIN);
 }
 
 // P groups: with pg groups a job at `level` gives group k the digits
@@ -383,7 +402,7 @@ __device__ __forceinline__ void modup_ip_body(u64* lds, const u64* __restrict__ 
   for (int j = j0; j < j1; ++j) {
     if (j == t) {
       // the digit reduced mod its own prime is the (permuted) input limb itself
-      load_limb_perm<LOGN, CLS, E>(lds, jb.d + (size_t)j * N, jb.ginv);
+      load_limb_perm<LOGN, CLS, E>(lds, jb.d + (size_t)j * N, jb.ginv, (jb.flags & JOB_IN_PACKED) != 0);
       __syncthreads();
     } else {
       lift_limb<LOGN, CLS, E>(lds, dcoef + (b * lmax + j) * N, mods.m[j].q, m, opaque_tid());
@@ -495,7 +514,7 @@ __device__ __forceinline__ void modup_ip_narrow_staged(u64* lds, u32* S, const u
     __builtin_amdgcn_sched_barrier(0);  // the copies are issued before the digit's loads
     if (j == t) {
       // the digit reduced mod its own prime is the (permuted) input limb itself
-      load_limb_perm<LOGN, CLS, E>(lds, jb.d + (size_t)j * N, jb.ginv);
+      load_limb_perm<LOGN, CLS, E>(lds, jb.d + (size_t)j * N, jb.ginv, (jb.flags & JOB_IN_PACKED) != 0);
       lds_barrier();
     } else {
       lift_limb<LOGN, CLS, E>(lds, dcoef + (b * lmax + j) * N, mods.m[j].q, m, tid);
@@ -656,7 +675,7 @@ __device__ __forceinline__ void intt_p_body(u64* lds, const u64* __restrict__ ur
 //   MODE_P:    the P limb of u, i.e. the sum of its group partials (ModDown
 //              after a key switch; u rows per polynomial lmax + pg);
 //   MODE_LAST: the last limb of the ciphertext jobs[b].d (rescale).
-template <int LOGN, int MODE, int CLS>
+template <int LOGN, int MODE, int CLS, bool PIN = false>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
 k_intt_last(const KsJob* __restrict__ jobs, int count, const u64* __restrict__ u, int lmax, int pg, int big_l,
             u64* __restrict__ rcoef, Mods mods, Tables tb) {
@@ -681,7 +700,7 @@ k_intt_last(const KsJob* __restrict__ jobs, int count, const u64* __restrict__ u
     const int mi = jb.level - 1;
     const ModConst m = mods.m[mi];
     if ((int)m.cls != CLS) return;
-    digits_body<LOGN, CLS>(lds, s, 1u, out, mi, m, tb);
+    digits_body<LOGN, CLS>(lds, s, 1u, out, mi, m, tb, PIN);
   }
 }
 
@@ -698,7 +717,7 @@ enum { EPI_STORE = 0, EPI_ROT = 1, EPI_ROTSUM = 2, EPI_RELIN = 3 };
 // inv_tab[div][t] holds q_div^-1 mod q_t (div = big_l for P) and its Shoup
 // companion at inv_tab[HE_MAXM * HE_MAXM + ...].  u has `urows` rows per
 // polynomial.
-template <int LOGN, int MODE, int EPI, int CLS>
+template <int LOGN, int MODE, int EPI, int CLS, int PK = 0>
 __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t b, int comp, int t,
                                                const u64* __restrict__ u, int urows, int big_l,
                                                const u64* __restrict__ rcoef, const u64* __restrict__ inv_tab,
@@ -712,14 +731,29 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
   const int div_mi = (MODE == MODE_P) ? big_l : level - 1;
   const ModConst m = mods.m[t];
   u64* o = jb.out + ((size_t)comp * keep + t) * N;
+  constexpr bool in_p = (PK & JOB_IN_PACKED) != 0;
+  constexpr bool out_p = (PK & JOB_OUT_PACKED) != 0;
   if (MODE == MODE_P && jb.key == nullptr) {  // identity job
     const u64* cs = jb.c + ((size_t)comp * level + t) * N;
+    if constexpr (in_p != out_p) {
+      // in place with a change of format, the whole row is read before any of it is written
+      u64 xv[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int i = (int)threadIdx.x + r * T;
-      u64 x = cs[i];
-      if constexpr (EPI == EPI_ROTSUM) x = addm<NW>(x, x, m.q);
-      o[i] = x;
+      for (int r = 0; r < 16; ++r) {
+        xv[r] = ld_res(cs, (int)threadIdx.x + r * T, in_p);
+        if constexpr (EPI == EPI_ROTSUM) xv[r] = addm<NW>(xv[r], xv[r], m.q);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 16; ++r) st_res(o, (int)threadIdx.x + r * T, xv[r], out_p);
+    } else {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = (int)threadIdx.x + r * T;
+        u64 x = ld_res(cs, i, in_p);
+        if constexpr (EPI == EPI_ROTSUM) x = addm<NW>(x, x, m.q);
+        st_res(o, i, x, out_p);
+      }
     }
     return;
   }
@@ -735,8 +769,8 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
   for (int r = 0; r < 16; ++r) {
     const int i = (int)threadIdx.x + r * T;
     const int li = lds_step(i0, r, T);
-    // u rows of narrow primes are packed
-    const u64 sv = (MODE == MODE_P && NW) ? (u64)reinterpret_cast<const u32*>(s)[i] : s[i];
+    // u rows of narrow primes are packed; ciphertext limbs as the job says
+    const u64 sv = (MODE == MODE_P) ? (NW ? (u64)reinterpret_cast<const u32*>(s)[i] : s[i]) : ld_res(s, i, in_p);
     if constexpr (CLS == CLS_F64) {
       const double dlt = f64_from_u64(sv) - lds_getw_at<CLS>(lds, li);
       val[r] = to_canon<CLS>(f64_mulmod(dlt, f64_from_u64(iv), m.qd, m.qinv), m);
@@ -746,13 +780,13 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
   }
   if constexpr (EPI == EPI_STORE) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) o[(int)threadIdx.x + r * T] = val[r];
+    for (int r = 0; r < 16; ++r) st_res(o, (int)threadIdx.x + r * T, val[r], out_p);
   } else if constexpr (EPI == EPI_RELIN) {
     const u64* dd = jb.c + ((size_t)comp * level + t) * N;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int i = (int)threadIdx.x + r * T;
-      o[i] = addm<NW>(dd[i], val[r], m.q);
+      st_res(o, i, addm<NW>(ld_res(dd, i, in_p), val[r], m.q), out_p);
     }
   } else {  // EPI_ROT / EPI_ROTSUM
     const u64* cs = jb.c + ((size_t)comp * level + t) * N;
@@ -764,7 +798,7 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int idx = (int)threadIdx.x + r * T;
-        const u64 v = cs[idx];
+        const u64 v = ld_res(cs, idx, in_p);
         own[r] = (V)v;
         lds_put<PC>(lds, galois_src<LOGN>(idx, jb.ginv), v);
       }
@@ -774,18 +808,29 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
         const int i = (int)threadIdx.x + r * T;
         u64 x = addm<NW>((u64)lds_getw_at<PC>(lds, lds_step(i0, r, T)), val[r], m.q);  // sigma_g(c0) + u0
         if constexpr (EPI == EPI_ROTSUM) x = addm<NW>(x, own[r], m.q);
-        o[i] = x;
+        st_res(o, i, x, out_p);
       }
     } else {
-      if constexpr (EPI == EPI_ROTSUM) {
+      if constexpr (EPI == EPI_ROTSUM && in_p != out_p) {
+        // in place with a change of format, the whole row is read before any of it is written
+        V own[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) own[r] = (V)ld_res(cs, (int)threadIdx.x + r * T, in_p);
+        __syncthreads();
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int i = (int)threadIdx.x + r * T;
-          o[i] = addm<NW>(cs[i], val[r], m.q);
+          st_res(o, i, addm<NW>(own[r], val[r], m.q), out_p);
+        }
+      } else if constexpr (EPI == EPI_ROTSUM) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int i = (int)threadIdx.x + r * T;
+          st_res(o, i, addm<NW>(ld_res(cs, i, in_p), val[r], m.q), out_p);
         }
       } else {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) o[(int)threadIdx.x + r * T] = val[r];
+        for (int r = 0; r < 16; ++r) st_res(o, (int)threadIdx.x + r * T, val[r], out_p);
       }
     }
   }
@@ -793,7 +838,7 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
 
 // grid xcd_grid(2 Kmax, count), Kmax the largest number of kept limbs:
 // workgroup (job b, polynomial comp, kept prime t).
-template <int LOGN, int MODE, int EPI, int CLS>
+template <int LOGN, int MODE, int EPI, int CLS, int PK = 0>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
 k_drop_last(const KsJob* __restrict__ jobs, int count, int kmax, const u64* __restrict__ u, int urows, int big_l,
             const u64* __restrict__ rcoef, const u64* __restrict__ inv_tab, Mods mods, Tables tb) {
@@ -807,7 +852,7 @@ k_drop_last(const KsJob* __restrict__ jobs, int count, int kmax, const u64* __re
   const int keep = (MODE == MODE_P) ? jb.level : jb.level - 1;
   if (t >= keep) return;
   if ((int)mods.m[t].cls != CLS) return;
-  drop_last_body<LOGN, MODE, EPI, CLS>(lds, jb, b, comp, t, u, urows, big_l, rcoef, inv_tab, mods, tb);
+  drop_last_body<LOGN, MODE, EPI, CLS, PK>(lds, jb, b, comp, t, u, urows, big_l, rcoef, inv_tab, mods, tb);
 }
 
 // ---------------------------------------------------------------------------
@@ -897,7 +942,7 @@ __global__ void k_ip_perm(const u64* __restrict__ dhat, const KsJob* __restrict_
 // Job table of a uniform batch: ciphertext b at base + b * stride.
 __global__ void k_make_jobs(KsJob* jobs, int count, const u64* d_base, size_t d_stride, const u64* c_base,
                             size_t c_stride, u64* out_base, size_t out_stride, const u64* key, u32 g, u32 ginv,
-                            int level) {
+                            int level, int flags) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= count) return;
   KsJob jb;
@@ -908,7 +953,7 @@ __global__ void k_make_jobs(KsJob* jobs, int count, const u64* d_base, size_t d_
   jb.g = g;
   jb.ginv = ginv;
   jb.level = level;
-  jb.pad_ = 0;
+  jb.flags = flags;
   jobs[b] = jb;
 }
 
@@ -921,9 +966,11 @@ struct ChainKeys {
 
 // Job tables of all steps of a rotate-and-sum chain over `count` ciphertexts
 // updated in place (ciphertext b at base + b * stride): step j's table at
-// jobs + j * count.  grid (ceil(count / 256), steps).
+// jobs + j * count.  With `packed`, every step writes its output packed and
+// every step but the first reads packed input.  grid (ceil(count / 256),
+// steps).
 __global__ void k_make_chain_jobs(KsJob* jobs, int count, u64* base, size_t stride, size_t c1_off, int level,
-                                  ChainKeys ck) {
+                                  ChainKeys ck, int packed) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (b >= count) return;
@@ -936,7 +983,7 @@ __global__ void k_make_chain_jobs(KsJob* jobs, int count, u64* base, size_t stri
   jb.g = ck.g[j];
   jb.ginv = ck.ginv[j];
   jb.level = level;
-  jb.pad_ = 0;
+  jb.flags = packed ? (JOB_OUT_PACKED | (j > 0 ? JOB_IN_PACKED : 0)) : 0;
   jobs[(size_t)j * count + b] = jb;
 }
 

@@ -65,6 +65,7 @@ SMALL = dict(n=1024, q_bits=(30, 30, 30, 30), p_bits=40)
 @pytest.mark.parametrize("n,q_bits,p_bits", [
     (1024, (30, 30, 30), 36), (4096, (30, 30), 36), (8192, (30, 30, 30, 30), 40), (16384, (40,) * 6, 60),
     (2048, (42, 41), 40),  # f64 class at its largest primes (2^42 limit)
+    (4096, (42, 41), 40),  # the same through a first radix-16 inverse pass (canonical input, 16 q sums)
 ])
 def test_ntt_intt_bit_exact(n, q_bits, p_bits):
     p = P.Params(n, q_bits, p_bits, 1.0)
