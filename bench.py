@@ -45,11 +45,11 @@ DOMINANT = "ks_modup_stage"
 # valid only for the kernel sources they were measured on: bench.py reports
 # them when these sources hash to KERNEL_SHA256, else null.
 KERNEL_SOURCES = ("modarith.h", "ntt_lds.h", "kernels.h", "capi.hip")
-KERNEL_SHA256 = "d52e718f7cb647344864541120b86c9e61abfbeddf5fab9c427c1b0e9292462f"
+KERNEL_SHA256 = "f107cc7acd3224cd6177a99afd7561891d14dc4ebe452daec5c0739733b758d4"
 # ks_modup_stage: mean over one layer's 25 launches (24 of 144 jobs at
-# 168.5 MB, one relinearisation launch of 5 jobs at 6.9 MB); ip_perm: one
+# 148.0 MB, one relinearisation launch of 5 jobs at 6.6 MB); ip_perm: one
 # launch over all 256 rotations
-TRAFFIC_BYTES = {"ks_modup_stage": 162054620, "ip_perm": 4455705045}
+TRAFFIC_BYTES = {"ks_modup_stage": 142297719, "ip_perm": 4455420672}
 
 
 def kernel_sha256() -> str:
@@ -103,20 +103,23 @@ def modup_ip_ops(count: int, level: int, n: int, moduli, pg: int) -> float:
     return ops * count
 
 
-def modup_ip_bytes(count: int, level: int, n: int, moduli, pg: int) -> float:
+def modup_ip_bytes(count: int, level: int, n: int, moduli, pg: int, packed_in: bool = False) -> float:
     """Algorithmic HBM bytes of the ModUp + inner-product stage over `count`
     ciphertexts at `level`: per ciphertext its coefficient-domain digits and
     its own NTT-domain limbs read once, both output polynomials written once
     (the level ciphertext-prime rows, and the P limb as its coefficient-domain
     copy with one P group, else as one partial row per group), and the key
     (2 level (level + 1) limbs) read once.  Residues of narrow primes are
-    packed 32-bit words, all others 64-bit words."""
+    packed 32-bit words in the scratch rows and keys, and in the input
+    ciphertext when packed_in (a rotate-and-sum chain after its first step);
+    all others are 64-bit words."""
     def width(q):
         return 4 if q < (1 << 30) else 8
     qs, p = moduli[:level], moduli[-1]
     groups = -(-level // -(-level // pg))
     q_row = sum(width(q) for q in qs) * n
-    per = q_row + 8 * n * level + 2 * (q_row + groups * width(p) * n)
+    own = q_row if packed_in else 8 * n * level
+    per = q_row + own + 2 * (q_row + groups * width(p) * n)
     key = 2 * level * (q_row + width(p) * n)
     return count * per + key
 
@@ -505,7 +508,10 @@ def main():
     # relinearisations of x^2 (level 2)
     ops_layer = 12 * modup_ip_ops(288, level, N, ctx.moduli, pg) + \
         modup_ip_ops(5, 2, N, ctx.moduli[:2] + ctx.moduli[-1:], ctx.get_tuning("p_groups", 2))
-    bytes_layer = 12 * modup_ip_bytes(288, level, N, ctx.moduli, pg) + \
+    # the chain's accumulator is packed after its first step (all primes narrow)
+    packed = all(q < (1 << 30) for q in ctx.moduli[:level])
+    bytes_layer = modup_ip_bytes(288, level, N, ctx.moduli, pg) + \
+        11 * modup_ip_bytes(288, level, N, ctx.moduli, pg, packed_in=packed) + \
         modup_ip_bytes(5, 2, N, ctx.moduli[:2] + ctx.moduli[-1:], ctx.get_tuning("p_groups", 2))
     launches_layer = 12 * (2 if split else 1) + 1
     avg_ms = dom_ms / max(1, dom_launches)
