@@ -249,14 +249,16 @@ struct LNtt {
 template <int LOGN>
 struct LKsCore {
   static void run(he_ctx* c, const KsJob* jobs, int count, int lmax, int pg, u64* dcoef, u64* u, u64* rc,
-                  hipStream_t s, int pk = 0) {
+                  hipStream_t s, int pk = 0, bool digits_done = false) {
     constexpr int T = NttGeom<LOGN>::T;
     // with one P group, ModUp's P workgroups also write the coefficient-domain
     // P limb (rc), and no separate INTT launch is needed
     u64* rc1 = pg == 1 ? rc : nullptr;
     {
       Prof pr(c, "ks_digits", s);
-      if (pk & JOB_IN_PACKED)
+      if (digits_done) {
+        // the previous step's ModDown wrote them
+      } else if (pk & JOB_IN_PACKED)
         HE_FOR_CLASSES(c->q_mask, (k_ks_digits<LOGN, CLS, true><<<xcd_grid(lmax, count), T, 0, s>>>(
                                       jobs, count, dcoef, lmax, c->mods, c->tb())));
       else
@@ -320,7 +322,7 @@ struct LKsCore {
 template <int LOGN>
 struct LDrop {
   static void run(he_ctx* c, int mode, int epi, const KsJob* jobs, int count, int lmax, int urows, const u64* u,
-                  const u64* rc, hipStream_t s, int pk = 0) {
+                  const u64* rc, hipStream_t s, int pk = 0, NextDigits nd = NextDigits{nullptr, 1u, 0}) {
     constexpr int T = NttGeom<LOGN>::T;
     const int keep = mode == MODE_P ? lmax : lmax - 1;
     const unsigned grid = xcd_grid(2 * keep, count);
@@ -328,7 +330,7 @@ struct LDrop {
 #define HE_DROP(MD, EP, PK)                                                                                    \
   HE_FOR_CLASSES(c->q_mask, (k_drop_last<LOGN, MD, EP, CLS, PK><<<grid, T, 0, s>>>(jobs, count, keep, u, urows,  \
                                                                                    c->big_l, rc, c->d_inv, c->mods, \
-                                                                                   c->tb())))
+                                                                                   c->tb(), nd)))
     // packed variants exist where a rotate-and-sum chain uses them: its steps
     // (ROTSUM, output packed, input packed after the first) and its rescale
     if (mode == MODE_LAST) {
@@ -551,14 +553,23 @@ bool chain_prepare(he_ctx* c, u64* acc, int count, int level, int steps, Arena a
   return true;
 }
 
+// Step j of the chain.  When steps j and j + 1 both switch keys, step j's
+// ModDown also writes step j + 1's digits, and step j + 1 launches no digit
+// kernel.
 void chain_step(he_ctx* c, const Chain& ch, int j, hipStream_t s) {
   const KsJob* jobs = ch.jobs + (size_t)j * ch.count;
-  const int g_is_one = galois_of(1 << j, c->n) == 1;
+  auto switches = [&](int k) { return k < ch.steps && galois_of(1 << k, c->n) != 1; };
   const int pk = ch.packed ? (JOB_OUT_PACKED | (j > 0 ? JOB_IN_PACKED : 0)) : 0;  // as k_make_chain_jobs sets
-  if (!g_is_one)
-    dispatch_logn<LKsCore>(c->logn, c, jobs, ch.count, ch.level, ch.pg, ch.ks.dcoef, ch.ks.u, ch.ks.rc, s, pk);
+  if (switches(j))
+    dispatch_logn<LKsCore>(c->logn, c, jobs, ch.count, ch.level, ch.pg, ch.ks.dcoef, ch.ks.u, ch.ks.rc, s, pk,
+                           j > 0 && switches(j - 1));
+  NextDigits nd{nullptr, 1u, ch.level};
+  if (switches(j) && switches(j + 1)) {
+    nd.dcoef = ch.ks.dcoef;
+    nd.ginv = galois_of(-(1 << (j + 1)), c->n);
+  }
   dispatch_logn<LDrop>(c->logn, c, (int)MODE_P, (int)EPI_ROTSUM, jobs, ch.count, ch.level, ch.level + ch.pg,
-                       (const u64*)ch.ks.u, (const u64*)ch.ks.rc, s, pk);
+                       (const u64*)ch.ks.u, (const u64*)ch.ks.rc, s, pk, nd);
 }
 
 // in_packed: the input is packed (narrow limbs as 32-bit words, see KsJob).

@@ -704,6 +704,33 @@ k_intt_last(const KsJob* __restrict__ jobs, int count, const u64* __restrict__ u
   }
 }
 
+// The next rotate-and-add step's digits, produced by this step's ModDown:
+// dcoef rows [count][lmax][N] of the next step, written for limb t by the
+// workgroup that computes limb t of the new c1, through the next step's
+// Galois element (ginv = its inverse).  dcoef == nullptr: none.
+struct NextDigits {
+  u64* dcoef;
+  u32 ginv;
+  int lmax;
+};
+
+// Coefficient-domain digit of limb t from this thread's 16 entries (tid + r
+// T) of an NTT-domain limb held in registers: Galois permutation into LDS,
+// INTT, N^-1, packed store (what k_ks_digits computes from memory).
+template <int LOGN, int CLS, typename V>
+__device__ __forceinline__ void digits_from_regs(u64* lds, const V (&x)[16], u32 ginv, u64* out, int t,
+                                                 const ModConst& m, const Tables& tb) {
+  constexpr int T = NttGeom<LOGN>::T;
+  __syncthreads();  // the LDS buffer is free
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int idx = (int)threadIdx.x + r * T;
+    lds_put<CLS>(lds, ginv == 1u ? idx : galois_src<LOGN>(idx, ginv), (u64)x[r]);
+  }
+  inv_lds<LOGN, CLS>(lds, tb, t, m);
+  store_limb<LOGN, CLS, true>(out, lds, m, true);
+}
+
 enum { EPI_STORE = 0, EPI_ROT = 1, EPI_ROTSUM = 2, EPI_RELIN = 3 };
 
 // Drop the last limb, for polynomial p = 2 b + comp (blockIdx.y) and kept
@@ -721,7 +748,7 @@ template <int LOGN, int MODE, int EPI, int CLS, int PK = 0>
 __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t b, int comp, int t,
                                                const u64* __restrict__ u, int urows, int big_l,
                                                const u64* __restrict__ rcoef, const u64* __restrict__ inv_tab,
-                                               const Mods& mods, const Tables& tb) {
+                                               const Mods& mods, const Tables& tb, const NextDigits& nd) {
   constexpr bool NW = CLS == CLS_N32;  // canonical values in 32-bit words
   typedef std::conditional_t<NW, u32, u64> V;
   constexpr int N = 1 << LOGN;
@@ -811,23 +838,16 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
         st_res(o, i, x, out_p);
       }
     } else {
-      if constexpr (EPI == EPI_ROTSUM && in_p != out_p) {
+      if constexpr (EPI == EPI_ROTSUM) {
+        V xs[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) xs[r] = (V)addm<NW>(ld_res(cs, (int)threadIdx.x + r * T, in_p), val[r], m.q);
         // in place with a change of format, the whole row is read before any of it is written
-        V own[16];
+        if constexpr (in_p != out_p) __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 16; ++r) own[r] = (V)ld_res(cs, (int)threadIdx.x + r * T, in_p);
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int i = (int)threadIdx.x + r * T;
-          st_res(o, i, addm<NW>(own[r], val[r], m.q), out_p);
-        }
-      } else if constexpr (EPI == EPI_ROTSUM) {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int i = (int)threadIdx.x + r * T;
-          st_res(o, i, addm<NW>(ld_res(cs, i, in_p), val[r], m.q), out_p);
-        }
+        for (int r = 0; r < 16; ++r) st_res(o, (int)threadIdx.x + r * T, xs[r], out_p);
+        if (nd.dcoef != nullptr)
+          digits_from_regs<LOGN, CLS>(lds, xs, nd.ginv, nd.dcoef + (b * nd.lmax + t) * N, t, m, tb);
       } else {
 #pragma unroll
         for (int r = 0; r < 16; ++r) st_res(o, (int)threadIdx.x + r * T, val[r], out_p);
@@ -837,11 +857,12 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
 }
 
 // grid xcd_grid(2 Kmax, count), Kmax the largest number of kept limbs:
-// workgroup (job b, polynomial comp, kept prime t).
+// workgroup (job b, polynomial comp, kept prime t).  nd: with EPI_ROTSUM,
+// the c1 workgroups also write the next step's digits.
 template <int LOGN, int MODE, int EPI, int CLS, int PK = 0>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
 k_drop_last(const KsJob* __restrict__ jobs, int count, int kmax, const u64* __restrict__ u, int urows, int big_l,
-            const u64* __restrict__ rcoef, const u64* __restrict__ inv_tab, Mods mods, Tables tb) {
+            const u64* __restrict__ rcoef, const u64* __restrict__ inv_tab, Mods mods, Tables tb, NextDigits nd) {
   __shared__ u64 lds[lds_words<LOGN, CLS>()];
   const XcdSlot sl = xcd_slot(2 * kmax);
   if (sl.job >= count) return;
@@ -852,7 +873,7 @@ k_drop_last(const KsJob* __restrict__ jobs, int count, int kmax, const u64* __re
   const int keep = (MODE == MODE_P) ? jb.level : jb.level - 1;
   if (t >= keep) return;
   if ((int)mods.m[t].cls != CLS) return;
-  drop_last_body<LOGN, MODE, EPI, CLS, PK>(lds, jb, b, comp, t, u, urows, big_l, rcoef, inv_tab, mods, tb);
+  drop_last_body<LOGN, MODE, EPI, CLS, PK>(lds, jb, b, comp, t, u, urows, big_l, rcoef, inv_tab, mods, tb, nd);
 }
 
 // ---------------------------------------------------------------------------
