@@ -714,20 +714,12 @@ struct NextDigits {
   int lmax;
 };
 
-// Coefficient-domain digit of limb t from this thread's 16 entries (tid + r
-// T) of an NTT-domain limb held in registers: Galois permutation into LDS,
-// INTT, N^-1, packed store (what k_ks_digits computes from memory).
-template <int LOGN, int CLS, typename V>
-__device__ __forceinline__ void digits_from_regs(u64* lds, const V (&x)[16], u32 ginv, u64* out, int t,
-                                                 const ModConst& m, const Tables& tb) {
-  constexpr int T = NttGeom<LOGN>::T;
-  __syncthreads();  // the LDS buffer is free
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int idx = (int)threadIdx.x + r * T;
-    lds_put<CLS>(lds, ginv == 1u ? idx : galois_src<LOGN>(idx, ginv), (u64)x[r]);
-  }
-  inv_lds<LOGN, CLS>(lds, tb, t, m);
+// Coefficient-domain digit of limb t from an NTT-domain limb the caller has
+// put into LDS through the Galois permutation: INTT, N^-1, packed store
+// (what k_ks_digits computes from memory).
+template <int LOGN, int CLS>
+__device__ __forceinline__ void digits_from_lds(u64* lds, u64* out, int t, const ModConst& m, const Tables& tb) {
+  inv_lds<LOGN, CLS>(lds, tb, t, m);  // begins with a barrier
   store_limb<LOGN, CLS, true>(out, lds, m, true);
 }
 
@@ -842,12 +834,16 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
         V xs[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) xs[r] = (V)addm<NW>(ld_res(cs, (int)threadIdx.x + r * T, in_p), val[r], m.q);
-        // in place with a change of format, the whole row is read before any of it is written
-        if constexpr (in_p != out_p) __syncthreads();
+        // in place with a change of format the whole row is read before any of it is written;
+        // with the next step's digits the LDS buffer (read above) is free after the barrier
+        if (in_p != out_p || nd.dcoef != nullptr) __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 16; ++r) st_res(o, (int)threadIdx.x + r * T, xs[r], out_p);
-        if (nd.dcoef != nullptr)
-          digits_from_regs<LOGN, CLS>(lds, xs, nd.ginv, nd.dcoef + (b * nd.lmax + t) * N, t, m, tb);
+        for (int r = 0; r < 16; ++r) {
+          const int idx = (int)threadIdx.x + r * T;
+          st_res(o, idx, xs[r], out_p);
+          if (nd.dcoef != nullptr) lds_put<CLS>(lds, nd.ginv == 1u ? idx : galois_src<LOGN>(idx, nd.ginv), (u64)xs[r]);
+        }
+        if (nd.dcoef != nullptr) digits_from_lds<LOGN, CLS>(lds, nd.dcoef + (b * nd.lmax + t) * N, t, m, tb);
       } else {
 #pragma unroll
         for (int r = 0; r < 16; ++r) st_res(o, (int)threadIdx.x + r * T, val[r], out_p);
