@@ -381,8 +381,8 @@ struct LHmaPerm {
                   const int32_t* gal, u32 g_step, int level, int accumulate, int n_acc, hipStream_t s) {
     constexpr int N = 1 << LOGN;
     Prof pr(c, "hma_perm", s);
-    k_hma_perm<LOGN><<<dim3(N / 256, level, n_acc), 256, 0, s>>>(acc, cts, K, pts, pt_stride, pt_limbs, gal, g_step,
-                                                                   level, accumulate, c->mods);
+    k_hma_perm<LOGN><<<dim3(N / 64, level, n_acc), 256, 0, s>>>(acc, cts, K, pts, pt_stride, pt_limbs, gal, g_step,
+                                                                  level, accumulate, c->mods);
   }
 };
 

@@ -1149,32 +1149,71 @@ k_dp_hma(const u64* __restrict__ x, const u64* __restrict__ filt, u64* __restric
 
 // Sum of permuted-plaintext products into one accumulator per blockIdx.z:
 // acc[z] (+)= sum_{k<K} cts[z*K + k] * sigma_{g_k}(pts[k * pt_stride]), with
-// g_k = gal[k] (or g_k = g_step^k when gal == nullptr).
+// g_k = gal[k] (or g_k = g_step^k when gal == nullptr).  grid (N / 64,
+// level, n_acc), 256 threads: 64 coefficients x 4 slices of the k loop
+// (slice s takes k = s, s + 4, ...), whose partial sums meet in LDS.
+// Narrow primes sum up to 15 products (< 2^60 each) before one reduction.
+constexpr int HMA_SLICES = 4;
 template <int LOGN>
-__global__ void k_hma_perm(u64* __restrict__ acc, const u64* __restrict__ cts, int K,
-                           const u64* __restrict__ pts, int pt_stride, int pt_limbs,
-                           const int32_t* __restrict__ gal, u32 g_step, int level, int accumulate, Mods mods) {
+__global__ void __launch_bounds__(256)
+k_hma_perm(u64* __restrict__ acc, const u64* __restrict__ cts, int K, const u64* __restrict__ pts, int pt_stride,
+           int pt_limbs, const int32_t* __restrict__ gal, u32 g_step, int level, int accumulate, Mods mods) {
   constexpr int N = 1 << LOGN;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ u64 part[2][HMA_SLICES][64];
+  const int lane = (int)threadIdx.x & 63;
+  const int sl = (int)threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
   const int t = blockIdx.y;
   const size_t z = blockIdx.z;
   const ModConst m = mods.m[t];
   const u32 mask2n = (2u << LOGN) - 1u;
-  u64* a0 = acc + ((z * 2 + 0) * level + t) * N;
-  u64* a1 = acc + ((z * 2 + 1) * level + t) * N;
-  u64 s0 = accumulate ? a0[i] : 0, s1 = accumulate ? a1[i] : 0;
-  u32 g = 1;
-  for (int k = 0; k < K; ++k) {
-    const u32 gk = gal ? (u32)gal[k] : g;
-    const int src = (gk == 1u) ? i : galois_src<LOGN>(i, gk);
-    const u64 pv = pts[((size_t)k * pt_stride * pt_limbs + t) * N + src];
-    const size_t cbase = (z * K + k) * 2;
-    s0 = add_mod(s0, mul_mod(cts[((cbase + 0) * level + t) * N + i], pv, m), m.q);
-    s1 = add_mod(s1, mul_mod(cts[((cbase + 1) * level + t) * N + i], pv, m), m.q);
-    g = (g * g_step) & mask2n;
+  u32 g = 1, g_stride = 1;  // g_step^sl, g_step^HMA_SLICES
+  for (int e = 0; e < HMA_SLICES; ++e) {
+    if (e < sl) g = (g * g_step) & mask2n;
+    g_stride = (g_stride * g_step) & mask2n;
   }
-  a0[i] = s0;
-  a1[i] = s1;
+  u64 s0 = 0, s1 = 0;
+  if (m.narrow) {
+    u64 l0 = 0, l1 = 0;
+    int n_lazy = 0;
+    for (int k = sl; k < K; k += HMA_SLICES) {
+      const u32 gk = gal ? (u32)gal[k] : g;
+      const int src = (gk == 1u) ? i : galois_src<LOGN>(i, gk);
+      const u32 pv = (u32)pts[((size_t)k * pt_stride * pt_limbs + t) * N + src];
+      const size_t cbase = (z * K + k) * 2;
+      l0 += (u64)(u32)cts[((cbase + 0) * level + t) * N + i] * pv;
+      l1 += (u64)(u32)cts[((cbase + 1) * level + t) * N + i] * pv;
+      if (++n_lazy == 15) {
+        s0 = add_mod(s0, reduce64(l0, m), m.q);
+        s1 = add_mod(s1, reduce64(l1, m), m.q);
+        l0 = l1 = 0;
+        n_lazy = 0;
+      }
+      g = (g * g_stride) & mask2n;
+    }
+    s0 = add_mod(s0, reduce64(l0, m), m.q);
+    s1 = add_mod(s1, reduce64(l1, m), m.q);
+  } else {
+    for (int k = sl; k < K; k += HMA_SLICES) {
+      const u32 gk = gal ? (u32)gal[k] : g;
+      const int src = (gk == 1u) ? i : galois_src<LOGN>(i, gk);
+      const u64 pv = pts[((size_t)k * pt_stride * pt_limbs + t) * N + src];
+      const size_t cbase = (z * K + k) * 2;
+      s0 = add_mod(s0, mul_mod(cts[((cbase + 0) * level + t) * N + i], pv, m), m.q);
+      s1 = add_mod(s1, mul_mod(cts[((cbase + 1) * level + t) * N + i], pv, m), m.q);
+      g = (g * g_stride) & mask2n;
+    }
+  }
+  part[0][sl][lane] = s0;
+  part[1][sl][lane] = s1;
+  __syncthreads();
+  if (sl >= 2) return;  // slice c sums polynomial c
+  const int c = sl;
+  u64* a = acc + ((z * 2 + c) * level + t) * N;
+  u64 v = accumulate ? a[i] : 0;
+#pragma unroll
+  for (int e = 0; e < HMA_SLICES; ++e) v = add_mod(v, part[c][e][lane], m.q);
+  a[i] = v;
 }
 
 // Integer-scalar MAC (ConvPack, Table II): out[o] = sum_k w[k][o] * in[k],
