@@ -1,8 +1,8 @@
 """CKKS slot encoding and decoding (test infrastructure; see package doc).
 
 The paper packs one message per slot (Section 1, packed SIMD encryption;
-Section 3.2, DensePack and ConvPack) but uses BFV's integer slots.  This build
-uses the CKKS canonical embedding over n = N/2 complex slots:
+Section 3.2, DensePack and ConvPack) but uses BFV's integer slots.  Here we
+use the CKKS canonical embedding over n = N/2 complex slots:
   * slot j corresponds to the root zeta^(5^j mod 2N), zeta = exp(i*pi/N);
   * a real vector z (length <= n, zero padded) maps to the real polynomial
     m_k = (2/N) * Re sum_j z_j zeta^(-k*5^j), k < N, i.e. the unique real

@@ -1,6 +1,6 @@
 """Negacyclic number-theoretic transform (test infrastructure; see package doc).
 
-Definition (the convention this build fixes; the paper does not discuss the
+Definition (the convention fixed here; the paper does not discuss the
 transform, which sits inside every rotation and square it times): for a
 polynomial a of degree < N over Z_q and psi a primitive 2N-th root of unity,
 

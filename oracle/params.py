@@ -8,7 +8,7 @@ switching.
 
 The three parameter sets of the evaluated workloads (the paper runs BFV with
 N = 8192 for MNIST and N = 16384 for CIFAR-10, Section 5 "Cryptosystem
-Settings"; this build uses an RNS CKKS-style scheme instead):
+Settings"; here an RNS CKKS-style scheme is used instead):
   * plain 28x28 conv:        N = 4096,  2 x 30-bit + 36-bit P, scale 2^25
   * FFConv 28x28 layer:      N = 8192,  4 x 30-bit + 40-bit P, scale 2^25
     (three 30-bit primes cannot hold the FFConv depth of 2 plus the square
