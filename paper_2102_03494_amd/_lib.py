@@ -1,7 +1,6 @@
 """ctypes loader for libffconv_he.so (the gfx950 HIP library).
 
-The library is built in-tree by ``__graft_entry__.build()`` (or
-``python -m paper_2102_03494_amd.build``).  Importing this module never falls
+The library is built in-tree by ``python -m paper_2102_03494_amd.build``.  Importing this module never falls
 back to anything else: if the shared object is missing or does not load, an
 ImportError says so.
 """
@@ -106,7 +105,7 @@ def header_symbols() -> list[str]:
 def load(path: str = LIB_PATH) -> ctypes.CDLL:
     if not os.path.exists(path):
         raise ImportError(
-            f"{path} is missing: build the HIP library first (python -c 'import __graft_entry__ as g; g.build()')"
+            f"{path} is missing: build the HIP library first (python -m paper_2102_03494_amd.build)"
         )
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
