@@ -521,11 +521,24 @@ __device__ __forceinline__ void modup_ip_narrow_staged(u64* lds, u32* S, const u
       fwd_lds<LOGN, CLS, E>(lds, tb, mi, m);
     }
     wait_vm();
+    if (j1 - j0 <= 8) {
+      // transform outputs (< 4q) brought below 2q only: each product is below
+      // 2^61, so the 64-bit sums of up to 8 digits cannot overflow
+      const u32 q2 = 2u * (u32)m.q;
 #pragma unroll
-    for (int r = 0; r < E; ++r) {
-      const u32 dv = (u32)to_canon<CLS>(lds_getw_at<CLS>(lds, lds_step(i0, r, T)), m);
-      acc0[r] += (u64)dv * S[r * T + tid];
-      acc1[r] += (u64)dv * S[N + r * T + tid];
+      for (int r = 0; r < E; ++r) {
+        const u32 v = lds_getw_at<CLS>(lds, lds_step(i0, r, T));
+        const u32 dv = min(v, v - q2);
+        acc0[r] += (u64)dv * S[r * T + tid];
+        acc1[r] += (u64)dv * S[N + r * T + tid];
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        const u32 dv = (u32)to_canon<CLS>(lds_getw_at<CLS>(lds, lds_step(i0, r, T)), m);
+        acc0[r] += (u64)dv * S[r * T + tid];
+        acc1[r] += (u64)dv * S[N + r * T + tid];
+      }
     }
     lds_barrier();  // the copies of the next digit overwrite S
   }
