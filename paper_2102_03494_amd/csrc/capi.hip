@@ -323,7 +323,7 @@ template <int LOGN>
 struct LDrop {
   static void run(he_ctx* c, int mode, int epi, const KsJob* jobs, int count, int lmax, int urows, const u64* u,
                   const u64* rc, hipStream_t s, int pk = 0, NextDigits nd = NextDigits{nullptr, 1u, 0}) {
-    constexpr int T = NttGeom<LOGN>::T;
+    constexpr int T = drop_threads<LOGN>();
     const int keep = mode == MODE_P ? lmax : lmax - 1;
     const unsigned grid = xcd_grid(2 * keep, count);
     Prof pr(c, "drop_last", s);
@@ -553,18 +553,20 @@ bool chain_prepare(he_ctx* c, u64* acc, int count, int level, int steps, Arena a
   return true;
 }
 
-// Step j of the chain.  When steps j and j + 1 both switch keys, step j's
-// ModDown also writes step j + 1's digits, and step j + 1 launches no digit
-// kernel.
+// Step j of the chain.  When steps j and j + 1 both switch keys (and the
+// ring is at most 2^NEXT_DIGITS_MAX_LOGN), step j's ModDown also writes step
+// j + 1's digits, and step j + 1 launches no digit kernel.
 void chain_step(he_ctx* c, const Chain& ch, int j, hipStream_t s) {
   const KsJob* jobs = ch.jobs + (size_t)j * ch.count;
   auto switches = [&](int k) { return k < ch.steps && galois_of(1 << k, c->n) != 1; };
+  // ModDown writes the next step's digits only where the kernel has them
+  auto fused = [&](int k) { return c->logn <= NEXT_DIGITS_MAX_LOGN && switches(k) && switches(k + 1); };
   const int pk = ch.packed ? (JOB_OUT_PACKED | (j > 0 ? JOB_IN_PACKED : 0)) : 0;  // as k_make_chain_jobs sets
   if (switches(j))
     dispatch_logn<LKsCore>(c->logn, c, jobs, ch.count, ch.level, ch.pg, ch.ks.dcoef, ch.ks.u, ch.ks.rc, s, pk,
-                           j > 0 && switches(j - 1));
+                           j > 0 && fused(j - 1));
   NextDigits nd{nullptr, 1u, ch.level};
-  if (switches(j) && switches(j + 1)) {
+  if (fused(j)) {
     nd.dcoef = ch.ks.dcoef;
     nd.ginv = galois_of(-(1 << (j + 1)), c->n);
   }

@@ -717,6 +717,11 @@ k_intt_last(const KsJob* __restrict__ jobs, int count, const u64* __restrict__ u
   }
 }
 
+// Largest ring whose ModDown also writes the next step's digits: at
+// N = 16384 the transform in the epilogue would make the kernel spill (its
+// 1024 threads get 128 registers each), so the digit kernel runs instead.
+constexpr int NEXT_DIGITS_MAX_LOGN = 13;
+
 // The next rotate-and-add step's digits, produced by this step's ModDown:
 // dcoef rows [count][lmax][N] of the next step, written for limb t by the
 // workgroup that computes limb t of the new c1, through the next step's
@@ -730,10 +735,22 @@ struct NextDigits {
 // Coefficient-domain digit of limb t from an NTT-domain limb the caller has
 // put into LDS through the Galois permutation: INTT, N^-1, packed store
 // (what k_ks_digits computes from memory).
-template <int LOGN, int CLS>
+template <int LOGN, int CLS, int E = 16>
 __device__ __forceinline__ void digits_from_lds(u64* lds, u64* out, int t, const ModConst& m, const Tables& tb) {
-  inv_lds<LOGN, CLS>(lds, tb, t, m);  // begins with a barrier
-  store_limb<LOGN, CLS, true>(out, lds, m, true);
+  inv_lds<LOGN, CLS, E>(lds, tb, t, m);  // begins with a barrier
+  store_limb<LOGN, CLS, true, E>(out, lds, m, true);
+}
+
+// Entries per thread of the ModDown / rescale kernel: 16 (with 8, as ModUp
+// uses, its 1024-thread workgroups measured slower: one workgroup per CU at
+// the same four waves per SIMD).
+template <int LOGN>
+constexpr int drop_e() {
+  return 16;
+}
+template <int LOGN>
+constexpr int drop_threads() {
+  return NttGeom<LOGN, drop_e<LOGN>()>::T;
 }
 
 enum { EPI_STORE = 0, EPI_ROT = 1, EPI_ROTSUM = 2, EPI_RELIN = 3 };
@@ -749,7 +766,7 @@ enum { EPI_STORE = 0, EPI_ROT = 1, EPI_ROTSUM = 2, EPI_RELIN = 3 };
 // inv_tab[div][t] holds q_div^-1 mod q_t (div = big_l for P) and its Shoup
 // companion at inv_tab[HE_MAXM * HE_MAXM + ...].  u has `urows` rows per
 // polynomial.
-template <int LOGN, int MODE, int EPI, int CLS, int PK = 0>
+template <int LOGN, int MODE, int EPI, int CLS, int PK = 0, int E = 16>
 __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t b, int comp, int t,
                                                const u64* __restrict__ u, int urows, int big_l,
                                                const u64* __restrict__ rcoef, const u64* __restrict__ inv_tab,
@@ -757,7 +774,7 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
   constexpr bool NW = CLS == CLS_N32;  // canonical values in 32-bit words
   typedef std::conditional_t<NW, u32, u64> V;
   constexpr int N = 1 << LOGN;
-  constexpr int T = NttGeom<LOGN>::T;
+  constexpr int T = NttGeom<LOGN, E>::T;
   const int level = jb.level;
   const int keep = (MODE == MODE_P) ? level : level - 1;
   const int div_mi = (MODE == MODE_P) ? big_l : level - 1;
@@ -769,18 +786,18 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
     const u64* cs = jb.c + ((size_t)comp * level + t) * N;
     if constexpr (in_p != out_p) {
       // in place with a change of format, the whole row is read before any of it is written
-      u64 xv[16];
+      u64 xv[E];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
+      for (int r = 0; r < E; ++r) {
         xv[r] = ld_res(cs, (int)threadIdx.x + r * T, in_p);
         if constexpr (EPI == EPI_ROTSUM) xv[r] = addm<NW>(xv[r], xv[r], m.q);
       }
       __syncthreads();
 #pragma unroll
-      for (int r = 0; r < 16; ++r) st_res(o, (int)threadIdx.x + r * T, xv[r], out_p);
+      for (int r = 0; r < E; ++r) st_res(o, (int)threadIdx.x + r * T, xv[r], out_p);
     } else {
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
+      for (int r = 0; r < E; ++r) {
         const int i = (int)threadIdx.x + r * T;
         u64 x = ld_res(cs, i, in_p);
         if constexpr (EPI == EPI_ROTSUM) x = addm<NW>(x, x, m.q);
@@ -789,16 +806,16 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
     }
     return;
   }
-  lift_limb<LOGN, CLS>(lds, rcoef + (b * 2 + comp) * N, mods.m[div_mi].q, m, (int)threadIdx.x);
-  fwd_lds<LOGN, CLS>(lds, tb, t, m);
+  lift_limb<LOGN, CLS, E>(lds, rcoef + (b * 2 + comp) * N, mods.m[div_mi].q, m, (int)threadIdx.x);
+  fwd_lds<LOGN, CLS, E>(lds, tb, t, m);
   const u64* s = (MODE == MODE_P) ? u + ((b * 2 + comp) * urows + t) * N
                                   : jb.d + ((size_t)comp * level + t) * N;
   const u64 iv = inv_tab[div_mi * HE_MAXM + t];
   const u64 ivs = inv_tab[HE_MAXM * HE_MAXM + div_mi * HE_MAXM + t];
-  V val[16];
+  V val[E];
   const int i0 = lds_idx((int)threadIdx.x);
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
+  for (int r = 0; r < E; ++r) {
     const int i = (int)threadIdx.x + r * T;
     const int li = lds_step(i0, r, T);
     // u rows of narrow primes are packed; ciphertext limbs as the job says
@@ -812,11 +829,11 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
   }
   if constexpr (EPI == EPI_STORE) {
 #pragma unroll
-    for (int r = 0; r < 16; ++r) st_res(o, (int)threadIdx.x + r * T, val[r], out_p);
+    for (int r = 0; r < E; ++r) st_res(o, (int)threadIdx.x + r * T, val[r], out_p);
   } else if constexpr (EPI == EPI_RELIN) {
     const u64* dd = jb.c + ((size_t)comp * level + t) * N;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
+    for (int r = 0; r < E; ++r) {
       const int i = (int)threadIdx.x + r * T;
       st_res(o, i, addm<NW>(ld_res(dd, i, in_p), val[r], m.q), out_p);
     }
@@ -826,9 +843,9 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
       // sigma_g(c0) through LDS, in canonical 32-bit (narrow) or 64-bit words
       constexpr int PC = NW ? CLS_N32 : CLS_U64;
       __syncthreads();  // everyone is done reading the lifted limb
-      V own[16];
+      V own[E];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
+      for (int r = 0; r < E; ++r) {
         const int idx = (int)threadIdx.x + r * T;
         const u64 v = ld_res(cs, idx, in_p);
         own[r] = (V)v;
@@ -836,7 +853,7 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
       }
       __syncthreads();
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
+      for (int r = 0; r < E; ++r) {
         const int i = (int)threadIdx.x + r * T;
         u64 x = addm<NW>((u64)lds_getw_at<PC>(lds, lds_step(i0, r, T)), val[r], m.q);  // sigma_g(c0) + u0
         if constexpr (EPI == EPI_ROTSUM) x = addm<NW>(x, own[r], m.q);
@@ -844,22 +861,24 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
       }
     } else {
       if constexpr (EPI == EPI_ROTSUM) {
-        V xs[16];
+        V xs[E];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) xs[r] = (V)addm<NW>(ld_res(cs, (int)threadIdx.x + r * T, in_p), val[r], m.q);
+        for (int r = 0; r < E; ++r) xs[r] = (V)addm<NW>(ld_res(cs, (int)threadIdx.x + r * T, in_p), val[r], m.q);
         // in place with a change of format the whole row is read before any of it is written;
         // with the next step's digits the LDS buffer (read above) is free after the barrier
         if (in_p != out_p || nd.dcoef != nullptr) __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
+        for (int r = 0; r < E; ++r) {
           const int idx = (int)threadIdx.x + r * T;
           st_res(o, idx, xs[r], out_p);
           if (nd.dcoef != nullptr) lds_put<CLS>(lds, nd.ginv == 1u ? idx : galois_src<LOGN>(idx, nd.ginv), (u64)xs[r]);
         }
-        if (nd.dcoef != nullptr) digits_from_lds<LOGN, CLS>(lds, nd.dcoef + (b * nd.lmax + t) * N, t, m, tb);
+        if constexpr (LOGN <= NEXT_DIGITS_MAX_LOGN) {
+          if (nd.dcoef != nullptr) digits_from_lds<LOGN, CLS, E>(lds, nd.dcoef + (b * nd.lmax + t) * N, t, m, tb);
+        }
       } else {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) st_res(o, (int)threadIdx.x + r * T, val[r], out_p);
+        for (int r = 0; r < E; ++r) st_res(o, (int)threadIdx.x + r * T, val[r], out_p);
       }
     }
   }
@@ -869,7 +888,7 @@ __device__ __forceinline__ void drop_last_body(u64* lds, const KsJob& jb, size_t
 // workgroup (job b, polynomial comp, kept prime t).  nd: with EPI_ROTSUM,
 // the c1 workgroups also write the next step's digits.
 template <int LOGN, int MODE, int EPI, int CLS, int PK = 0>
-__global__ void __launch_bounds__(NttGeom<LOGN>::T)
+__global__ void __launch_bounds__(drop_threads<LOGN>())
 k_drop_last(const KsJob* __restrict__ jobs, int count, int kmax, const u64* __restrict__ u, int urows, int big_l,
             const u64* __restrict__ rcoef, const u64* __restrict__ inv_tab, Mods mods, Tables tb, NextDigits nd) {
   __shared__ u64 lds[lds_words<LOGN, CLS>()];
@@ -882,7 +901,8 @@ k_drop_last(const KsJob* __restrict__ jobs, int count, int kmax, const u64* __re
   const int keep = (MODE == MODE_P) ? jb.level : jb.level - 1;
   if (t >= keep) return;
   if ((int)mods.m[t].cls != CLS) return;
-  drop_last_body<LOGN, MODE, EPI, CLS, PK>(lds, jb, b, comp, t, u, urows, big_l, rcoef, inv_tab, mods, tb, nd);
+  drop_last_body<LOGN, MODE, EPI, CLS, PK, drop_e<LOGN>()>(lds, jb, b, comp, t, u, urows, big_l, rcoef, inv_tab,
+                                                          mods, tb, nd);
 }
 
 // ---------------------------------------------------------------------------
