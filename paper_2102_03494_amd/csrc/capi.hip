@@ -14,182 +14,12 @@
 
 #include "../../include/ffconv_he.h"
 #include "host_params.h"
-#include "kernels.h"
+#include "ctx.h"
+#include "kernels_elem.h"
 
 using namespace he;
 
 namespace {
-// Pinned staging ring for small host tables (job tables, weight residues).
-struct StageSlot {
-  char* host = nullptr;
-  size_t cap = 0;
-  hipEvent_t ev = nullptr;
-  bool pending = false;
-};
-constexpr int STAGE_SLOTS = 64;
-}  // namespace
-
-struct he_ctx {
-  int n = 0, logn = 0, big_l = 0;
-  std::vector<u64> moduli;  // q_0..q_{L-1}, P
-  Mods mods{};
-  bool has_cls[3] = {false, false, false};  // width classes among q_0..q_{L-1}, P
-  unsigned q_mask = 0;                       // bit c: a ciphertext prime of class c exists
-  int p_cls = 0;                             // class of P
-  u64* d_tw = nullptr;    // [L+1][4][N] 64-bit twiddles + Shoup companions
-  u32* d_tw32 = nullptr;  // 32-bit copies for the narrow moduli
-  double* d_twf = nullptr;  // (w, w / q) as doubles for the f64 moduli
-  u64* d_inv = nullptr;   // [2][HE_MAXM][HE_MAXM]: m_div^-1 mod q_t and Shoup components
-  Tables tb() const { return Tables{d_tw, d_tw32, d_twf}; }
-  int pg_set[HE_MAXM + 1] = {};  // P groups per key-switch level (0 = cost model)
-  int split_streams = 1;         // DensePack rotate-and-sum in two halves on two streams
-  char* ws = nullptr;
-  size_t ws_bytes = 0;
-  std::map<int, u64*> keys;  // Galois element (0 = relinearisation) -> [L][2][L+1][N]
-  std::string err;
-  he_counts counts{};
-  int device = 0;
-  // instrumentation: events around launches of one selected kernel
-  std::string prof_kernel;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
-  std::vector<hipEvent_t> prof_pool;
-  // second stream (default priority) for the other width classes of a launch
-  hipStream_t side = nullptr;
-  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
-  StageSlot stage[STAGE_SLOTS];
-  int stage_next = 0;
-  // graph capture: set between he_graph_begin and he_graph_end; epoch counts
-  // changes that move memory a captured graph refers to (workspace, keys)
-  bool capturing = false;
-  uint64_t epoch = 0;
-};
-
-struct he_graph {
-  he_ctx* ctx = nullptr;
-  uint64_t epoch = 0;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-};
-
-namespace {
-
-int fail(he_ctx* c, int code, const char* fmt, ...) {
-  if (c) {
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
-    va_end(ap);
-    c->err = buf;
-  }
-  return code;
-}
-
-int check_launch(he_ctx* c, const char* what) {
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return fail(c, HE_EDEVICE, "%s: %s", what, hipGetErrorString(e));
-  return HE_OK;
-}
-
-hipStream_t S(void* s) { return (hipStream_t)s; }
-
-hipEvent_t prof_event(he_ctx* c) {
-  if (!c->prof_pool.empty()) {
-    hipEvent_t e = c->prof_pool.back();
-    c->prof_pool.pop_back();
-    return e;
-  }
-  hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
-  return e;
-}
-
-// Brackets the launches in its scope with events when `name` is selected.
-struct Prof {
-  he_ctx* c;
-  hipStream_t s;
-  hipEvent_t a = nullptr;
-  Prof(he_ctx* ctx, const char* name, hipStream_t st) : c(ctx), s(st) {
-    if (!c->capturing && !c->prof_kernel.empty() && c->prof_kernel == name) {
-      a = prof_event(c);
-      if (a) (void)hipEventRecord(a, s);
-    }
-  }
-  ~Prof() {
-    if (!a) return;
-    hipEvent_t b = prof_event(c);
-    if (!b) return;
-    (void)hipEventRecord(b, s);
-    c->prof_events.push_back({a, b});
-  }
-};
-
-// Bump allocator over the context workspace (one per call).
-struct Arena {
-  char* base;
-  size_t cap, used = 0;
-  Arena(he_ctx* c) : base(c->ws), cap(c->ws_bytes) {}
-  template <typename T>
-  T* take(size_t count) {
-    size_t bytes = (count * sizeof(T) + 255) & ~(size_t)255;
-    if (used + bytes > cap) return nullptr;
-    T* p = (T*)(base + used);
-    used += bytes;
-    return p;
-  }
-  size_t left() const { return cap - used; }
-  // The remaining space split into two disjoint arenas of about half each.
-  void halves(Arena& lo, Arena& hi) const {
-    const size_t mid = used + ((left() / 2) & ~(size_t)255);
-    lo = *this;
-    lo.cap = mid;
-    hi = *this;
-    hi.used = mid;
-  }
-};
-
-u32 galois_of(int k, int n) {
-  const int slots = n / 2;
-  int e = k % slots;
-  if (e < 0) e += slots;
-  return (u32)powmod(5, (u64)e, 2 * (u64)n);
-}
-
-template <template <int> class F, typename... A>
-int dispatch_logn(int logn, A&&... args) {
-  switch (logn) {
-    case 10: F<10>::run(args...); return 0;
-    case 11: F<11>::run(args...); return 0;
-    case 12: F<12>::run(args...); return 0;
-    case 13: F<13>::run(args...); return 0;
-    case 14: F<14>::run(args...); return 0;
-    default: return -1;
-  }
-}
-
-// Runs LAUNCH with the constant CLS bound to every width class in `mask`
-// (transform kernels are instantiated per class).
-#define HE_FOR_CLASSES(mask, LAUNCH)               \
-  do {                                             \
-    if ((mask)&1u) {                               \
-      constexpr int CLS = CLS_N32;                 \
-      LAUNCH;                                      \
-    }                                              \
-    if ((mask)&2u) {                               \
-      constexpr int CLS = CLS_F64;                 \
-      LAUNCH;                                      \
-    }                                              \
-    if ((mask)&4u) {                               \
-      constexpr int CLS = CLS_U64;                 \
-      LAUNCH;                                      \
-    }                                              \
-  } while (0)
-
-unsigned cls_mask(const he_ctx* c, int first, int count) {
-  unsigned m = 0;
-  for (int i = first; i < first + count; ++i) m |= 1u << c->mods.m[i].cls;
-  return m;
-}
 
 // Copies `bytes` from host to device memory `dst` on stream s through a ring
 // of pinned buffers; a slot is reused only after its previous copy finished.
@@ -222,212 +52,6 @@ int upload(he_ctx* c, void* dst, const void* src, size_t bytes, hipStream_t s) {
   st.pending = true;
   return HE_OK;
 }
-
-// ---- launch wrappers (templated on log2 N) ---------------------------------
-
-template <int LOGN>
-struct LNtt {
-  static void run(he_ctx* c, u64* d, int n_polys, int n_limbs, int first_mod, bool fwd, hipStream_t s) {
-    dim3 grid(n_limbs, n_polys);
-    Prof pr(c, "ntt", s);
-    const unsigned mask = cls_mask(c, first_mod, n_limbs);
-    if (fwd)
-      HE_FOR_CLASSES(mask, (k_ntt<LOGN, true, CLS><<<grid, NttGeom<LOGN>::T, 0, s>>>(d, n_limbs, first_mod, c->mods,
-                                                                                      c->tb())));
-    else
-      HE_FOR_CLASSES(mask, (k_ntt<LOGN, false, CLS><<<grid, NttGeom<LOGN>::T, 0, s>>>(d, n_limbs, first_mod, c->mods,
-                                                                                       c->tb())));
-  }
-};
-
-// Key switch of a job batch: digits -> ModUp + inner product -> INTT of P (in
-// the ModUp launch when P is one group).
-// ModUp is one launch when the ring's primes span one or two width classes
-// (each workgroup runs its target's class); with all three, the kernel of
-// each class runs on its own stream (the caller's for the first, the side
-// stream for the others), joined before the P INTT.
-template <int LOGN>
-struct LKsCore {
-  static void run(he_ctx* c, const KsJob* jobs, int count, int lmax, int pg, u64* dcoef, u64* u, u64* rc,
-                  hipStream_t s, int pk = 0, bool digits_done = false) {
-    constexpr int T = NttGeom<LOGN>::T;
-    // with one P group, ModUp's P workgroups also write the coefficient-domain
-    // P limb (rc), and no separate INTT launch is needed
-    u64* rc1 = pg == 1 ? rc : nullptr;
-    {
-      Prof pr(c, "ks_digits", s);
-      if (digits_done) {
-        // the previous step's ModDown wrote them
-      } else if (pk & JOB_IN_PACKED)
-        HE_FOR_CLASSES(c->q_mask, (k_ks_digits<LOGN, CLS, true><<<xcd_grid(lmax, count), T, 0, s>>>(
-                                      jobs, count, dcoef, lmax, c->mods, c->tb())));
-      else
-        HE_FOR_CLASSES(c->q_mask, (k_ks_digits<LOGN, CLS, false><<<xcd_grid(lmax, count), T, 0, s>>>(
-                                      jobs, count, dcoef, lmax, c->mods, c->tb())));
-    }
-    const unsigned grid = xcd_grid(lmax + pg, count);
-    constexpr int TM = modup_threads<LOGN>();  // ModUp workgroup size
-    static const char* names[3] = {"ks_modup_ip", "ks_modup_ip_f64", "ks_modup_ip_wide"};
-    const int n_cls = (int)c->has_cls[0] + (int)c->has_cls[1] + (int)c->has_cls[2];
-    if (n_cls == 2) {  // one launch, each workgroup in its target's class
-      Prof stage(c, "ks_modup_stage", s);
-      if (!c->has_cls[CLS_U64])
-        k_ks_modup_ip2<LOGN, CLS_N32, CLS_F64><<<grid, TM, 0, s>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l,
-                                                                   c->mods, c->tb());
-      else if (!c->has_cls[CLS_F64])
-        k_ks_modup_ip2<LOGN, CLS_N32, CLS_U64><<<grid, TM, 0, s>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l,
-                                                                   c->mods, c->tb());
-      else
-        k_ks_modup_ip2<LOGN, CLS_F64, CLS_U64><<<grid, TM, 0, s>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l,
-                                                                   c->mods, c->tb());
-    } else {
-    const bool forked = n_cls > 1;
-    {
-      Prof stage(c, "ks_modup_stage", s);  // wall time of all classes together
-      if (forked) {  // the side stream starts after the digits, not after the first ModUp kernel
-        (void)hipEventRecord(c->fork_ev, s);
-        (void)hipStreamWaitEvent(c->side, c->fork_ev, 0);
-      }
-      bool first = true;
-      for (int cls = 0; cls < 3; ++cls) {
-        if (!c->has_cls[cls]) continue;
-        const hipStream_t st = first ? s : c->side;
-        first = false;
-        Prof pr(c, names[cls], st);
-        if (cls == CLS_N32)
-          k_ks_modup_ip<LOGN, CLS_N32><<<grid, TM, 0, st>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l, c->mods,
-                                                            c->tb());
-        else if (cls == CLS_F64)
-          k_ks_modup_ip<LOGN, CLS_F64><<<grid, TM, 0, st>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l, c->mods,
-                                                            c->tb());
-        else
-          k_ks_modup_ip<LOGN, CLS_U64><<<grid, TM, 0, st>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l, c->mods,
-                                                            c->tb());
-      }
-      if (forked) {
-        (void)hipEventRecord(c->join_ev, c->side);
-        (void)hipStreamWaitEvent(s, c->join_ev, 0);
-      }
-    }
-    }
-    if (rc1) return;
-    Prof pr(c, "intt_last", s);
-    HE_FOR_CLASSES(1u << c->p_cls, (k_intt_last<LOGN, MODE_P, CLS><<<xcd_grid(2, count), T, 0, s>>>(
-                                       jobs, count, u, lmax, pg, c->big_l, rc, c->mods, c->tb())));
-  }
-};
-
-// ModDown (MODE_P, u with `urows` rows per polynomial) or rescale
-// (MODE_LAST) of a job batch with the given epilogue.
-template <int LOGN>
-struct LDrop {
-  static void run(he_ctx* c, int mode, int epi, const KsJob* jobs, int count, int lmax, int urows, const u64* u,
-                  const u64* rc, hipStream_t s, int pk = 0, NextDigits nd = NextDigits{nullptr, 1u, 0}) {
-    constexpr int T = drop_threads<LOGN>();
-    const int keep = mode == MODE_P ? lmax : lmax - 1;
-    const unsigned grid = xcd_grid(2 * keep, count);
-    Prof pr(c, "drop_last", s);
-#define HE_DROP(MD, EP, PK)                                                                                    \
-  HE_FOR_CLASSES(c->q_mask, (k_drop_last<LOGN, MD, EP, CLS, PK><<<grid, T, 0, s>>>(jobs, count, keep, u, urows,  \
-                                                                                   c->big_l, rc, c->d_inv, c->mods, \
-                                                                                   c->tb(), nd)))
-    // packed variants exist where a rotate-and-sum chain uses them: its steps
-    // (ROTSUM, output packed, input packed after the first) and its rescale
-    if (mode == MODE_LAST) {
-      if (pk & JOB_IN_PACKED) HE_DROP(MODE_LAST, EPI_STORE, JOB_IN_PACKED);
-      else HE_DROP(MODE_LAST, EPI_STORE, 0);
-    } else if (epi == EPI_ROT) {
-      HE_DROP(MODE_P, EPI_ROT, 0);
-    } else if (epi == EPI_ROTSUM) {
-      if (pk == (JOB_IN_PACKED | JOB_OUT_PACKED)) HE_DROP(MODE_P, EPI_ROTSUM, JOB_IN_PACKED | JOB_OUT_PACKED);
-      else if (pk == JOB_OUT_PACKED) HE_DROP(MODE_P, EPI_ROTSUM, JOB_OUT_PACKED);
-      else HE_DROP(MODE_P, EPI_ROTSUM, 0);
-    } else if (epi == EPI_RELIN) {
-      HE_DROP(MODE_P, EPI_RELIN, 0);
-    } else {
-      HE_DROP(MODE_P, EPI_STORE, 0);
-    }
-#undef HE_DROP
-  }
-};
-
-template <int LOGN>
-struct LIntt1 {
-  static void run(he_ctx* c, const KsJob* jobs, int count, int lmax, u64* rc, hipStream_t s, int pk = 0) {
-    Prof pr(c, "intt_last", s);
-    if (pk & JOB_IN_PACKED)
-      HE_FOR_CLASSES(c->q_mask, (k_intt_last<LOGN, MODE_LAST, CLS, true><<<xcd_grid(2, count), NttGeom<LOGN>::T, 0,
-                                                                           s>>>(jobs, count, nullptr, lmax, 1,
-                                                                                c->big_l, rc, c->mods, c->tb())));
-    else
-      HE_FOR_CLASSES(c->q_mask, (k_intt_last<LOGN, MODE_LAST, CLS, false><<<xcd_grid(2, count), NttGeom<LOGN>::T, 0,
-                                                                            s>>>(jobs, count, nullptr, lmax, 1,
-                                                                                 c->big_l, rc, c->mods, c->tb())));
-  }
-};
-
-template <int LOGN>
-struct LDpHma {
-  static void run(he_ctx* c, const u64* x, const u64* filt, u64* out, int level, int out_base, int n_out,
-                  const DPGeom& geo, hipStream_t s) {
-    Prof pr(c, "dp_hma", s);
-    k_dp_hma<LOGN><<<dim3(level, n_out), NttGeom<LOGN>::T, 0, s>>>(x, filt, out, level, out_base, geo, c->mods);
-  }
-};
-
-template <int LOGN>
-struct LHmaPerm {
-  static void run(he_ctx* c, u64* acc, const u64* cts, int K, const u64* pts, int pt_stride, int pt_limbs,
-                  const int32_t* gal, u32 g_step, int level, int accumulate, int n_acc, hipStream_t s) {
-    constexpr int N = 1 << LOGN;
-    Prof pr(c, "hma_perm", s);
-    k_hma_perm<LOGN><<<dim3(N / 64, level, n_acc), 256, 0, s>>>(acc, cts, K, pts, pt_stride, pt_limbs, gal, g_step,
-                                                                  level, accumulate, c->mods);
-  }
-};
-
-template <int LOGN>
-struct LKeygen {
-  static void run(he_ctx* c, u64* key, const u64* sk, const u64* a, const u64* ehat, u32 g, ConstTable pm,
-                  hipStream_t s) {
-    constexpr int N = 1 << LOGN;
-    k_keygen<LOGN><<<dim3(N / 256, c->big_l + 1, c->big_l), 256, 0, s>>>(key, sk, a, ehat, g, c->big_l, pm,
-                                                                          c->mods);
-  }
-};
-
-// Hoisted rotations: digits of c1 and the lifted digits, computed once ...
-template <int LOGN>
-struct LHoistUp {
-  static void run(he_ctx* c, const KsJob* job1, const u64* c1, int level, u64* dcoef, u64* dhat, hipStream_t s) {
-    constexpr int T = NttGeom<LOGN>::T;
-    HE_FOR_CLASSES(c->q_mask, (k_ks_digits<LOGN, CLS><<<xcd_grid(level, 1), T, 0, s>>>(job1, 1, dcoef, level,
-                                                                                         c->mods, c->tb())));
-    Prof pr(c, "modup_store", s);
-    HE_FOR_CLASSES(c->q_mask | (1u << c->p_cls),
-                   (k_modup_store<LOGN, CLS><<<dim3(level + 1, level), T, 0, s>>>(dcoef, c1, dhat, level, c->big_l,
-                                                                                  c->mods, c->tb())));
-  }
-};
-
-// ... then, per chunk of rotations: inner product with each key, ModDown.
-template <int LOGN>
-struct LHoisted {
-  static void run(he_ctx* c, const KsJob* jobs, int m, int level, const u64* dhat, u64* u, u64* rc, hipStream_t s) {
-    constexpr int T = NttGeom<LOGN>::T;
-    constexpr int N = 1 << LOGN;
-    {
-      Prof pr(c, "ip_perm", s);
-      k_ip_perm<LOGN><<<dim3(N / 256, level + 1, m), 256, 0, s>>>(dhat, jobs, u, level, c->big_l, c->mods);
-    }
-    {  // u rows per polynomial: level + 1, P at row level (one P group)
-      Prof pr(c, "intt_last", s);
-      HE_FOR_CLASSES(1u << c->p_cls, (k_intt_last<LOGN, MODE_P, CLS><<<xcd_grid(2, m), T, 0, s>>>(
-                                         jobs, m, u, level, 1, c->big_l, rc, c->mods, c->tb())));
-    }
-    LDrop<LOGN>::run(c, MODE_P, EPI_ROT, jobs, m, level, level + 1, u, rc, s);
-  }
-};
 
 // ---- shared orchestration ----------------------------------------------------
 

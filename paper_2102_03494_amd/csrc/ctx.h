@@ -1,0 +1,237 @@
+// Internal state of a library context and the launch wrappers shared by the
+// C-ABI unit (capi.hip) and the per-ring-size launch units (launch_n*.hip,
+// which instantiate the kernels of one log2 N each, so the library builds in
+// parallel).  Not part of the public interface.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/ffconv_he.h"
+#include "host_params.h"
+#include "kernels.h"
+
+namespace he {
+// Pinned staging ring for small host tables (job tables, weight residues).
+struct StageSlot {
+  char* host = nullptr;
+  size_t cap = 0;
+  hipEvent_t ev = nullptr;
+  bool pending = false;
+};
+constexpr int STAGE_SLOTS = 64;
+}  // namespace he
+
+using namespace he;
+
+struct he_ctx {
+  int n = 0, logn = 0, big_l = 0;
+  std::vector<u64> moduli;  // q_0..q_{L-1}, P
+  Mods mods{};
+  bool has_cls[3] = {false, false, false};  // width classes among q_0..q_{L-1}, P
+  unsigned q_mask = 0;                       // bit c: a ciphertext prime of class c exists
+  int p_cls = 0;                             // class of P
+  u64* d_tw = nullptr;    // [L+1][4][N] 64-bit twiddles + Shoup companions
+  u32* d_tw32 = nullptr;  // 32-bit copies for the narrow moduli
+  double* d_twf = nullptr;  // (w, w / q) as doubles for the f64 moduli
+  u64* d_inv = nullptr;   // [2][HE_MAXM][HE_MAXM]: m_div^-1 mod q_t and Shoup components
+  Tables tb() const { return Tables{d_tw, d_tw32, d_twf}; }
+  int pg_set[HE_MAXM + 1] = {};  // P groups per key-switch level (0 = cost model)
+  int split_streams = 1;         // DensePack rotate-and-sum in two halves on two streams
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::map<int, u64*> keys;  // Galois element (0 = relinearisation) -> [L][2][L+1][N]
+  std::string err;
+  he_counts counts{};
+  int device = 0;
+  // instrumentation: events around launches of one selected kernel
+  std::string prof_kernel;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
+  std::vector<hipEvent_t> prof_pool;
+  // second stream (default priority) for the other width classes of a launch
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  StageSlot stage[STAGE_SLOTS];
+  int stage_next = 0;
+  // graph capture: set between he_graph_begin and he_graph_end; epoch counts
+  // changes that move memory a captured graph refers to (workspace, keys)
+  bool capturing = false;
+  uint64_t epoch = 0;
+};
+
+struct he_graph {
+  he_ctx* ctx = nullptr;
+  uint64_t epoch = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace he {
+
+inline int fail(he_ctx* c, int code, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return code;
+}
+
+inline int check_launch(he_ctx* c, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, HE_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+  return HE_OK;
+}
+
+inline hipStream_t S(void* s) { return (hipStream_t)s; }
+
+inline hipEvent_t prof_event(he_ctx* c) {
+  if (!c->prof_pool.empty()) {
+    hipEvent_t e = c->prof_pool.back();
+    c->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets the launches in its scope with events when `name` is selected.
+struct Prof {
+  he_ctx* c;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  Prof(he_ctx* ctx, const char* name, hipStream_t st) : c(ctx), s(st) {
+    if (!c->capturing && !c->prof_kernel.empty() && c->prof_kernel == name) {
+      a = prof_event(c);
+      if (a) (void)hipEventRecord(a, s);
+    }
+  }
+  ~Prof() {
+    if (!a) return;
+    hipEvent_t b = prof_event(c);
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    c->prof_events.push_back({a, b});
+  }
+};
+
+// Bump allocator over the context workspace (one per call).
+struct Arena {
+  char* base;
+  size_t cap, used = 0;
+  Arena(he_ctx* c) : base(c->ws), cap(c->ws_bytes) {}
+  template <typename T>
+  T* take(size_t count) {
+    size_t bytes = (count * sizeof(T) + 255) & ~(size_t)255;
+    if (used + bytes > cap) return nullptr;
+    T* p = (T*)(base + used);
+    used += bytes;
+    return p;
+  }
+  size_t left() const { return cap - used; }
+  // The remaining space split into two disjoint arenas of about half each.
+  void halves(Arena& lo, Arena& hi) const {
+    const size_t mid = used + ((left() / 2) & ~(size_t)255);
+    lo = *this;
+    lo.cap = mid;
+    hi = *this;
+    hi.used = mid;
+  }
+};
+
+inline u32 galois_of(int k, int n) {
+  const int slots = n / 2;
+  int e = k % slots;
+  if (e < 0) e += slots;
+  return (u32)powmod(5, (u64)e, 2 * (u64)n);
+}
+
+template <template <int> class F, typename... A>
+inline int dispatch_logn(int logn, A&&... args) {
+  switch (logn) {
+    case 10: F<10>::run(args...); return 0;
+    case 11: F<11>::run(args...); return 0;
+    case 12: F<12>::run(args...); return 0;
+    case 13: F<13>::run(args...); return 0;
+    case 14: F<14>::run(args...); return 0;
+    default: return -1;
+  }
+}
+
+// Runs LAUNCH with the constant CLS bound to every width class in `mask`
+// (transform kernels are instantiated per class).
+#define HE_FOR_CLASSES(mask, LAUNCH)               \
+  do {                                             \
+    if ((mask)&1u) {                               \
+      constexpr int CLS = CLS_N32;                 \
+      LAUNCH;                                      \
+    }                                              \
+    if ((mask)&2u) {                               \
+      constexpr int CLS = CLS_F64;                 \
+      LAUNCH;                                      \
+    }                                              \
+    if ((mask)&4u) {                               \
+      constexpr int CLS = CLS_U64;                 \
+      LAUNCH;                                      \
+    }                                              \
+  } while (0)
+
+inline unsigned cls_mask(const he_ctx* c, int first, int count) {
+  unsigned m = 0;
+  for (int i = first; i < first + count; ++i) m |= 1u << c->mods.m[i].cls;
+  return m;
+}
+
+// ---- launch wrappers (templated on log2 N; defined in launch.h and
+// instantiated for N = 2^10 .. 2^14 in launch_n10.hip .. launch_n14.hip) ----
+template <int LOGN>
+struct LNtt {
+  static void run(he_ctx* c, u64* d, int n_polys, int n_limbs, int first_mod, bool fwd, hipStream_t s);
+};
+template <int LOGN>
+struct LKsCore {
+  static void run(he_ctx* c, const KsJob* jobs, int count, int lmax, int pg, u64* dcoef, u64* u, u64* rc,
+                  hipStream_t s, int pk = 0, bool digits_done = false);
+};
+template <int LOGN>
+struct LDrop {
+  static void run(he_ctx* c, int mode, int epi, const KsJob* jobs, int count, int lmax, int urows, const u64* u,
+                  const u64* rc, hipStream_t s, int pk = 0, NextDigits nd = NextDigits{nullptr, 1u, 0});
+};
+template <int LOGN>
+struct LIntt1 {
+  static void run(he_ctx* c, const KsJob* jobs, int count, int lmax, u64* rc, hipStream_t s, int pk = 0);
+};
+template <int LOGN>
+struct LDpHma {
+  static void run(he_ctx* c, const u64* x, const u64* filt, u64* out, int level, int out_base, int n_out,
+                  const DPGeom& geo, hipStream_t s);
+};
+template <int LOGN>
+struct LHmaPerm {
+  static void run(he_ctx* c, u64* acc, const u64* cts, int K, const u64* pts, int pt_stride, int pt_limbs,
+                  const int32_t* gal, u32 g_step, int level, int accumulate, int n_acc, hipStream_t s);
+};
+template <int LOGN>
+struct LKeygen {
+  static void run(he_ctx* c, u64* key, const u64* sk, const u64* a, const u64* ehat, u32 g, ConstTable pm,
+                  hipStream_t s);
+};
+template <int LOGN>
+struct LHoistUp {
+  static void run(he_ctx* c, const KsJob* job1, const u64* c1, int level, u64* dcoef, u64* dhat, hipStream_t s);
+};
+template <int LOGN>
+struct LHoisted {
+  static void run(he_ctx* c, const KsJob* jobs, int m, int level, const u64* dhat, u64* u, u64* rc, hipStream_t s);
+};
+
+}  // namespace he

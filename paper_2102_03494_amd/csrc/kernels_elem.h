@@ -1,0 +1,172 @@
+// Elementwise and bookkeeping kernels of the library that do not depend on
+// the ring size (job tables, additions, integer-scalar MACs, the square
+// tensor, client-side helpers).  Included by the C-ABI unit only.
+#pragma once
+#include "kernels.h"
+
+namespace he {
+
+// Job table of a uniform batch: ciphertext b at base + b * stride.
+__global__ void k_make_jobs(KsJob* jobs, int count, const u64* d_base, size_t d_stride, const u64* c_base,
+                            size_t c_stride, u64* out_base, size_t out_stride, const u64* key, u32 g, u32 ginv,
+                            int level, int flags) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= count) return;
+  KsJob jb;
+  jb.d = d_base + (size_t)b * d_stride;
+  jb.c = c_base + (size_t)b * c_stride;
+  jb.out = out_base + (size_t)b * out_stride;
+  jb.key = key;
+  jb.g = g;
+  jb.ginv = ginv;
+  jb.level = level;
+  jb.flags = flags;
+  jobs[b] = jb;
+}
+
+// Job tables of all steps of a rotate-and-sum chain over `count` ciphertexts
+// updated in place (ciphertext b at base + b * stride): step j's table at
+// jobs + j * count.  With `packed`, every step writes its output packed and
+// every step but the first reads packed input.  grid (ceil(count / 256),
+// steps).
+__global__ void k_make_chain_jobs(KsJob* jobs, int count, u64* base, size_t stride, size_t c1_off, int level,
+                                  ChainKeys ck, int packed) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  if (b >= count) return;
+  u64* x = base + (size_t)b * stride;
+  KsJob jb;
+  jb.d = x + c1_off;
+  jb.c = x;
+  jb.out = x;
+  jb.key = ck.key[j];
+  jb.g = ck.g[j];
+  jb.ginv = ck.ginv[j];
+  jb.level = level;
+  jb.flags = packed ? (JOB_OUT_PACKED | (j > 0 ? JOB_IN_PACKED : 0)) : 0;
+  jobs[(size_t)j * count + b] = jb;
+}
+
+// CP -> DP combine, summing step: out[m] = sum_{o in block m} rot[o], block
+// m = [m B, min(O_c, (m+1) B)); grid (N / 256, level, n_dense).
+__global__ void k_block_sum(u64* __restrict__ out, const u64* __restrict__ rot, int o_c, int per_dense, int n_dense,
+                            int level, int n, Mods mods) {
+  // blockIdx.z = item * n_dense + m: out[z] = sum of item's ciphertexts
+  // m * per_dense .. (m + 1) * per_dense - 1 (rot holds o_c per item)
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y;
+  const size_t z = blockIdx.z;
+  const size_t item = z / n_dense;
+  const int mblk = (int)(z - item * n_dense);
+  const u64 q = mods.m[t].q;
+  const int o_end = min(o_c, (mblk + 1) * per_dense);
+  rot += item * o_c * 2 * level * (size_t)n;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    u64 acc = 0;
+    for (int o = mblk * per_dense; o < o_end; ++o) acc = add_mod(acc, rot[(((size_t)o * 2 + c) * level + t) * n + i], q);
+    out[((z * 2 + c) * level + t) * n + i] = acc;
+  }
+}
+
+// Batched MulPC over a ragged batch: out_b = ct_b * pt_b (slot-wise), every
+// item with its own level; jobs give (d = ct, c = pt, out).  grid
+// (N / 256, Lmax, count); limbs above an item's level exit.
+__global__ void k_batch_mul_plain(const KsJob* __restrict__ jobs, int n, Mods mods) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y;
+  const KsJob jb = jobs[blockIdx.z];
+  if (t >= jb.level) return;
+  const ModConst m = mods.m[t];
+  const u64 pv = jb.c[(size_t)t * n + i];
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const size_t off = ((size_t)c * jb.level + t) * n + i;
+    jb.out[off] = mul_mod(jb.d[off], pv, m);
+  }
+}
+
+// out[z] = a[z] + b[z] (ciphertext-sized items).
+__global__ void k_add(u64* out, const u64* a, const u64* b, int level, int n, Mods mods) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y;
+  const size_t z = blockIdx.z;
+  const u64 q = mods.m[t].q;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const size_t off = ((z * 2 + c) * level + t) * (size_t)n + i;
+    out[off] = add_mod(a[off], b[off], q);
+  }
+}
+
+// Integer-scalar MAC (ConvPack, Table II): out[o] = sum_k w[k][o] * in[k],
+// with w given per limb as residues + Shoup companions: wres[(k*o_c + o)*level + t].
+// blockIdx.z = layer * o_c + o over independent layers: layer l reads
+// in + l in_stride and its table at wres / wsh + l tab_stride; out[z].
+__global__ void k_scalar_mac(u64* __restrict__ out, const u64* __restrict__ in, int K, int o_c,
+                             const u64* __restrict__ wres, const u64* __restrict__ wsh, int level, int n,
+                             size_t in_stride, size_t tab_stride, Mods mods) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y;
+  const size_t z = blockIdx.z;
+  const size_t layer = z / o_c;
+  const size_t o = z - layer * o_c;
+  in += layer * in_stride;
+  wres += layer * tab_stride;
+  wsh += layer * tab_stride;
+  const ModConst m = mods.m[t];
+  u64 s0 = 0, s1 = 0;
+  for (int k = 0; k < K; ++k) {
+    const size_t wi = ((size_t)k * o_c + o) * level + t;
+    const u64 w = wres[wi], ws = wsh[wi];
+    s0 = add_mod(s0, mul_shoup(in[(((size_t)k * 2 + 0) * level + t) * n + i], w, ws, m.q, m.narrow), m.q);
+    s1 = add_mod(s1, mul_shoup(in[(((size_t)k * 2 + 1) * level + t) * n + i], w, ws, m.q, m.narrow), m.q);
+  }
+  out[((z * 2 + 0) * level + t) * n + i] = s0;
+  out[((z * 2 + 1) * level + t) * n + i] = s1;
+}
+
+// Square tensor: d0 = c0^2, d1 = 2 c0 c1 (both into d01 = [count][2][level][N])
+// and d2 = c1^2 into [count][level][N].
+__global__ void k_tensor_sq(u64* __restrict__ d01, u64* __restrict__ d2, const u64* __restrict__ in,
+                            int level, int n, Mods mods) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y;
+  const size_t z = blockIdx.z;
+  const ModConst m = mods.m[t];
+  const u64 c0 = in[((z * 2 + 0) * level + t) * n + i];
+  const u64 c1 = in[((z * 2 + 1) * level + t) * n + i];
+  const u64 x01 = mul_mod(c0, c1, m);
+  d01[((z * 2 + 0) * level + t) * n + i] = mul_mod(c0, c0, m);
+  d01[((z * 2 + 1) * level + t) * n + i] = add_mod(x01, x01, m.q);
+  d2[(z * level + t) * n + i] = mul_mod(c1, c1, m);
+}
+
+// out[t] = coeffs mod modulus (first_mod + t), coefficient domain.
+__global__ void k_from_signed(u64* out, const int64_t* coeffs, int first_mod, int n, Mods mods) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y;
+  out[(size_t)t * n + i] = from_signed(coeffs[i], mods.m[first_mod + t]);
+}
+
+// Encryption: c0 = pt + ehat - a*s, c1 = a.
+__global__ void k_encrypt(u64* ct, const u64* pt, const u64* a, const u64* ehat, const u64* s, int level,
+                          int n, Mods mods) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y;
+  const ModConst m = mods.m[t];
+  const size_t k = (size_t)t * n + i;
+  const u64 av = a[k];
+  ct[k] = sub_mod(add_mod(pt[k], ehat[k], m.q), mul_mod(av, s[k], m), m.q);
+  ct[(size_t)level * n + k] = av;
+}
+
+__global__ void k_decrypt(u64* out, const u64* ct, const u64* s, int level, int n, Mods mods) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y;
+  const ModConst m = mods.m[t];
+  const size_t k = (size_t)t * n + i;
+  out[k] = add_mod(ct[k], mul_mod(ct[(size_t)level * n + k], s[k], m), m.q);
+}
+
+}  // namespace he

@@ -1,0 +1,208 @@
+// Definitions of the launch wrappers declared in ctx.h: each picks the
+// kernel instances of its ring size and width classes and enqueues them.
+#pragma once
+#include "ctx.h"
+
+namespace he {
+
+
+template <int LOGN>
+void LNtt<LOGN>::run(he_ctx* c, u64* d, int n_polys, int n_limbs, int first_mod, bool fwd, hipStream_t s) {
+  dim3 grid(n_limbs, n_polys);
+  Prof pr(c, "ntt", s);
+  const unsigned mask = cls_mask(c, first_mod, n_limbs);
+  if (fwd)
+    HE_FOR_CLASSES(mask, (k_ntt<LOGN, true, CLS><<<grid, NttGeom<LOGN>::T, 0, s>>>(d, n_limbs, first_mod, c->mods,
+                                                                                    c->tb())));
+  else
+    HE_FOR_CLASSES(mask, (k_ntt<LOGN, false, CLS><<<grid, NttGeom<LOGN>::T, 0, s>>>(d, n_limbs, first_mod, c->mods,
+                                                                                     c->tb())));
+}
+
+// Key switch of a job batch: digits -> ModUp + inner product -> INTT of P (in
+// the ModUp launch when P is one group).
+// ModUp is one launch when the ring's primes span one or two width classes
+// (each workgroup runs its target's class); with all three, the kernel of
+// each class runs on its own stream (the caller's for the first, the side
+// stream for the others), joined before the P INTT.
+template <int LOGN>
+void LKsCore<LOGN>::run(he_ctx* c, const KsJob* jobs, int count, int lmax, int pg, u64* dcoef, u64* u, u64* rc,
+                  hipStream_t s, int pk, bool digits_done) {
+  constexpr int T = NttGeom<LOGN>::T;
+  // with one P group, ModUp's P workgroups also write the coefficient-domain
+  // P limb (rc), and no separate INTT launch is needed
+  u64* rc1 = pg == 1 ? rc : nullptr;
+  {
+    Prof pr(c, "ks_digits", s);
+    if (digits_done) {
+      // the previous step's ModDown wrote them
+    } else if (pk & JOB_IN_PACKED)
+      HE_FOR_CLASSES(c->q_mask, (k_ks_digits<LOGN, CLS, true><<<xcd_grid(lmax, count), T, 0, s>>>(
+                                    jobs, count, dcoef, lmax, c->mods, c->tb())));
+    else
+      HE_FOR_CLASSES(c->q_mask, (k_ks_digits<LOGN, CLS, false><<<xcd_grid(lmax, count), T, 0, s>>>(
+                                    jobs, count, dcoef, lmax, c->mods, c->tb())));
+  }
+  const unsigned grid = xcd_grid(lmax + pg, count);
+  constexpr int TM = modup_threads<LOGN>();  // ModUp workgroup size
+  static const char* names[3] = {"ks_modup_ip", "ks_modup_ip_f64", "ks_modup_ip_wide"};
+  const int n_cls = (int)c->has_cls[0] + (int)c->has_cls[1] + (int)c->has_cls[2];
+  if (n_cls == 2) {  // one launch, each workgroup in its target's class
+    Prof stage(c, "ks_modup_stage", s);
+    if (!c->has_cls[CLS_U64])
+      k_ks_modup_ip2<LOGN, CLS_N32, CLS_F64><<<grid, TM, 0, s>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l,
+                                                                 c->mods, c->tb());
+    else if (!c->has_cls[CLS_F64])
+      k_ks_modup_ip2<LOGN, CLS_N32, CLS_U64><<<grid, TM, 0, s>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l,
+                                                                 c->mods, c->tb());
+    else
+      k_ks_modup_ip2<LOGN, CLS_F64, CLS_U64><<<grid, TM, 0, s>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l,
+                                                                 c->mods, c->tb());
+  } else {
+  const bool forked = n_cls > 1;
+  {
+    Prof stage(c, "ks_modup_stage", s);  // wall time of all classes together
+    if (forked) {  // the side stream starts after the digits, not after the first ModUp kernel
+      (void)hipEventRecord(c->fork_ev, s);
+      (void)hipStreamWaitEvent(c->side, c->fork_ev, 0);
+    }
+    bool first = true;
+    for (int cls = 0; cls < 3; ++cls) {
+      if (!c->has_cls[cls]) continue;
+      const hipStream_t st = first ? s : c->side;
+      first = false;
+      Prof pr(c, names[cls], st);
+      if (cls == CLS_N32)
+        k_ks_modup_ip<LOGN, CLS_N32><<<grid, TM, 0, st>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l, c->mods,
+                                                          c->tb());
+      else if (cls == CLS_F64)
+        k_ks_modup_ip<LOGN, CLS_F64><<<grid, TM, 0, st>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l, c->mods,
+                                                          c->tb());
+      else
+        k_ks_modup_ip<LOGN, CLS_U64><<<grid, TM, 0, st>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l, c->mods,
+                                                          c->tb());
+    }
+    if (forked) {
+      (void)hipEventRecord(c->join_ev, c->side);
+      (void)hipStreamWaitEvent(s, c->join_ev, 0);
+    }
+  }
+  }
+  if (rc1) return;
+  Prof pr(c, "intt_last", s);
+  HE_FOR_CLASSES(1u << c->p_cls, (k_intt_last<LOGN, MODE_P, CLS><<<xcd_grid(2, count), T, 0, s>>>(
+                                     jobs, count, u, lmax, pg, c->big_l, rc, c->mods, c->tb())));
+}
+
+// ModDown (MODE_P, u with `urows` rows per polynomial) or rescale
+// (MODE_LAST) of a job batch with the given epilogue.
+template <int LOGN>
+void LDrop<LOGN>::run(he_ctx* c, int mode, int epi, const KsJob* jobs, int count, int lmax, int urows, const u64* u,
+                  const u64* rc, hipStream_t s, int pk, NextDigits nd) {
+  constexpr int T = drop_threads<LOGN>();
+  const int keep = mode == MODE_P ? lmax : lmax - 1;
+  const unsigned grid = xcd_grid(2 * keep, count);
+  Prof pr(c, "drop_last", s);
+#define HE_DROP(MD, EP, PK)                                                                                    \
+HE_FOR_CLASSES(c->q_mask, (k_drop_last<LOGN, MD, EP, CLS, PK><<<grid, T, 0, s>>>(jobs, count, keep, u, urows,  \
+                                                                                 c->big_l, rc, c->d_inv, c->mods, \
+                                                                                 c->tb(), nd)))
+  // packed variants exist where a rotate-and-sum chain uses them: its steps
+  // (ROTSUM, output packed, input packed after the first) and its rescale
+  if (mode == MODE_LAST) {
+    if (pk & JOB_IN_PACKED) HE_DROP(MODE_LAST, EPI_STORE, JOB_IN_PACKED);
+    else HE_DROP(MODE_LAST, EPI_STORE, 0);
+  } else if (epi == EPI_ROT) {
+    HE_DROP(MODE_P, EPI_ROT, 0);
+  } else if (epi == EPI_ROTSUM) {
+    if (pk == (JOB_IN_PACKED | JOB_OUT_PACKED)) HE_DROP(MODE_P, EPI_ROTSUM, JOB_IN_PACKED | JOB_OUT_PACKED);
+    else if (pk == JOB_OUT_PACKED) HE_DROP(MODE_P, EPI_ROTSUM, JOB_OUT_PACKED);
+    else HE_DROP(MODE_P, EPI_ROTSUM, 0);
+  } else if (epi == EPI_RELIN) {
+    HE_DROP(MODE_P, EPI_RELIN, 0);
+  } else {
+    HE_DROP(MODE_P, EPI_STORE, 0);
+  }
+#undef HE_DROP
+}
+
+template <int LOGN>
+void LIntt1<LOGN>::run(he_ctx* c, const KsJob* jobs, int count, int lmax, u64* rc, hipStream_t s, int pk) {
+  Prof pr(c, "intt_last", s);
+  if (pk & JOB_IN_PACKED)
+    HE_FOR_CLASSES(c->q_mask, (k_intt_last<LOGN, MODE_LAST, CLS, true><<<xcd_grid(2, count), NttGeom<LOGN>::T, 0,
+                                                                         s>>>(jobs, count, nullptr, lmax, 1,
+                                                                              c->big_l, rc, c->mods, c->tb())));
+  else
+    HE_FOR_CLASSES(c->q_mask, (k_intt_last<LOGN, MODE_LAST, CLS, false><<<xcd_grid(2, count), NttGeom<LOGN>::T, 0,
+                                                                          s>>>(jobs, count, nullptr, lmax, 1,
+                                                                               c->big_l, rc, c->mods, c->tb())));
+}
+
+template <int LOGN>
+void LDpHma<LOGN>::run(he_ctx* c, const u64* x, const u64* filt, u64* out, int level, int out_base, int n_out,
+                  const DPGeom& geo, hipStream_t s) {
+  Prof pr(c, "dp_hma", s);
+  k_dp_hma<LOGN><<<dim3(level, n_out), NttGeom<LOGN>::T, 0, s>>>(x, filt, out, level, out_base, geo, c->mods);
+}
+
+template <int LOGN>
+void LHmaPerm<LOGN>::run(he_ctx* c, u64* acc, const u64* cts, int K, const u64* pts, int pt_stride, int pt_limbs,
+                  const int32_t* gal, u32 g_step, int level, int accumulate, int n_acc, hipStream_t s) {
+  constexpr int N = 1 << LOGN;
+  Prof pr(c, "hma_perm", s);
+  k_hma_perm<LOGN><<<dim3(N / 64, level, n_acc), 256, 0, s>>>(acc, cts, K, pts, pt_stride, pt_limbs, gal, g_step,
+                                                                level, accumulate, c->mods);
+}
+
+template <int LOGN>
+void LKeygen<LOGN>::run(he_ctx* c, u64* key, const u64* sk, const u64* a, const u64* ehat, u32 g, ConstTable pm,
+                  hipStream_t s) {
+  constexpr int N = 1 << LOGN;
+  k_keygen<LOGN><<<dim3(N / 256, c->big_l + 1, c->big_l), 256, 0, s>>>(key, sk, a, ehat, g, c->big_l, pm,
+                                                                        c->mods);
+}
+
+// Hoisted rotations: digits of c1 and the lifted digits, computed once ...
+template <int LOGN>
+void LHoistUp<LOGN>::run(he_ctx* c, const KsJob* job1, const u64* c1, int level, u64* dcoef, u64* dhat, hipStream_t s) {
+  constexpr int T = NttGeom<LOGN>::T;
+  HE_FOR_CLASSES(c->q_mask, (k_ks_digits<LOGN, CLS><<<xcd_grid(level, 1), T, 0, s>>>(job1, 1, dcoef, level,
+                                                                                       c->mods, c->tb())));
+  Prof pr(c, "modup_store", s);
+  HE_FOR_CLASSES(c->q_mask | (1u << c->p_cls),
+                 (k_modup_store<LOGN, CLS><<<dim3(level + 1, level), T, 0, s>>>(dcoef, c1, dhat, level, c->big_l,
+                                                                                c->mods, c->tb())));
+}
+
+// ... then, per chunk of rotations: inner product with each key, ModDown.
+template <int LOGN>
+void LHoisted<LOGN>::run(he_ctx* c, const KsJob* jobs, int m, int level, const u64* dhat, u64* u, u64* rc, hipStream_t s) {
+  constexpr int T = NttGeom<LOGN>::T;
+  constexpr int N = 1 << LOGN;
+  {
+    Prof pr(c, "ip_perm", s);
+    k_ip_perm<LOGN><<<dim3(N / 256, level + 1, m), 256, 0, s>>>(dhat, jobs, u, level, c->big_l, c->mods);
+  }
+  {  // u rows per polynomial: level + 1, P at row level (one P group)
+    Prof pr(c, "intt_last", s);
+    HE_FOR_CLASSES(1u << c->p_cls, (k_intt_last<LOGN, MODE_P, CLS><<<xcd_grid(2, m), T, 0, s>>>(
+                                       jobs, m, u, level, 1, c->big_l, rc, c->mods, c->tb())));
+  }
+  LDrop<LOGN>::run(c, MODE_P, EPI_ROT, jobs, m, level, level + 1, u, rc, s);
+}
+
+}  // namespace he
+
+#define HE_INSTANTIATE_LAUNCHERS(LOGN)    \
+  namespace he {                          \
+  template struct LNtt<LOGN>;             \
+  template struct LKsCore<LOGN>;          \
+  template struct LDrop<LOGN>;            \
+  template struct LIntt1<LOGN>;           \
+  template struct LDpHma<LOGN>;           \
+  template struct LHmaPerm<LOGN>;         \
+  template struct LKeygen<LOGN>;          \
+  template struct LHoistUp<LOGN>;         \
+  template struct LHoisted<LOGN>;         \
+  }
