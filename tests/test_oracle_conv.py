@@ -11,6 +11,9 @@
   identity W2 returns the gathered channels; the full FFConv layer with x^2;
   the CP->DP combine lays channels out exactly as DensePack does; the
   one-hot arrangement puts replicated value j in slot j and zeros elsewhere.
+* The standalone ConvPack layer (Table II) decrypts to the FP64 per-pixel
+  matrix product, counts O_c K MulPC and O_c (K - 1) AddCC, lands on its
+  target scale, returns its inputs for W = I and is linear in W.
 """
 import math
 
@@ -19,6 +22,7 @@ import pytest
 
 import synth
 from oracle import conv as C
+from oracle import counts
 from oracle import encoding as E
 from oracle import params as P
 from oracle import reference as R
@@ -206,3 +210,58 @@ def test_gather_onehot_places_value_j_in_slot_j():
         want = np.zeros(p.slots)
         want[:k] = vals[z * k:(z + 1) * k]
         assert np.abs(got - want).max() < 1e-4
+
+
+def _convpack_inputs(p, ctx, k_in, hw):
+    """K channel ciphertexts in ConvPack form: channel k's hw x hw plane at slots 0..S-1."""
+    x = synth.image(W, (hw, hw, k_in), index=7)
+    s = hw * hw
+    cts = [Wk.encrypt_slots(ctx, np.concatenate([x[:, :, k].ravel(), np.zeros(p.slots - s)]), p.max_level,
+                            p.scale, W, 200 + k) for k in range(k_in)]
+    return x.reshape(s, k_in), S.Ciphertext(np.stack([c.c for c in cts]), p.scale)
+
+
+@pytest.mark.parametrize("k_in,o_c", [(4, 3), (1, 2), (6, 1)])
+def test_convpack_matches_per_pixel_matmul(k_in, o_c):
+    """Standalone ConvPack (Table II): output channel o decrypts to the FP64
+    per-pixel product sum_k W[k, o] x_k in slots 0..S-1 and zeros elsewhere;
+    MulPC = O_c K and AddCC = O_c (K - 1) as Table II counts them; the
+    rescale lands on the target scale (up to rounding of the scale algebra)."""
+    p = P.Params(512, (30, 30, 30), 36, 2.0**25)
+    ctx = Wk.make_context(p, W)
+    pix, cts = _convpack_inputs(p, ctx, k_in, 7)
+    w = synth.weights(W, 40 + k_in, (k_in, o_c), 0.4)
+    target = 2.0**24
+    z, cnt = C.convpack(p, cts, w, target)
+    assert z.level == p.max_level - 1 and z.c.shape[0] == o_c
+    assert abs(z.scale - target) <= 4 * np.spacing(target)
+    want_counts = counts.convpack_lola(o_c, k_in)
+    assert (cnt.mulpc, cnt.addcc, cnt.rot, cnt.rescale) == (want_counts["mulpc"], want_counts["addcc"], 0, o_c)
+    assert want_counts["mulpc"] == o_c * k_in and want_counts["addcc"] == o_c * (k_in - 1)
+    ref = pix @ w  # (S, O_c), plain FP64
+    for o in range(o_c):
+        got = ctx.decrypt(S.Ciphertext(z.c[o], z.scale))
+        assert np.abs(got[: pix.shape[0]] - ref[:, o]).max() < 1e-4
+        assert np.abs(got[pix.shape[0]:]).max() < 1e-4
+
+
+def test_convpack_identity_and_linearity():
+    """ConvPack with W = I returns its inputs (after the rescale), and
+    ConvPack(W_a + W_b) decrypts to ConvPack(W_a) + ConvPack(W_b)."""
+    p = P.Params(512, (30, 30, 30), 36, 2.0**25)
+    ctx = Wk.make_context(p, W)
+    pix, cts = _convpack_inputs(p, ctx, 3, 6)
+    z, _ = C.convpack(p, cts, np.eye(3), p.scale)
+    for k in range(3):
+        got = ctx.decrypt(S.Ciphertext(z.c[k], z.scale))
+        assert np.abs(got[: pix.shape[0]] - pix[:, k]).max() < 1e-4
+    wa = synth.weights(W, 50, (3, 2), 0.3)
+    wb = synth.weights(W, 51, (3, 2), 0.3)
+    za, _ = C.convpack(p, cts, wa, p.scale)
+    zb, _ = C.convpack(p, cts, wb, p.scale)
+    zs, _ = C.convpack(p, cts, wa + wb, p.scale)
+    for o in range(2):
+        da = ctx.decrypt(S.Ciphertext(za.c[o], za.scale))
+        db = ctx.decrypt(S.Ciphertext(zb.c[o], zb.scale))
+        ds = ctx.decrypt(S.Ciphertext(zs.c[o], zs.scale))
+        assert np.abs(ds - (da + db)).max() < 1e-4
