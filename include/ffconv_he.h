@@ -189,6 +189,26 @@ int he_rotate_hoisted(he_ctx *ctx, const uint64_t *d_in, int level, const int32_
                       uint64_t *d_outs, void *stream);
 int he_rotsum(he_ctx *ctx, uint64_t *d_cts, int count, int level, int r_steps, void *stream);
 
+/* ---- allocation-free rotation ----------------------------------------------
+ * For callers that cannot allocate device memory at call time (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * he_rotate_static computes exactly what he_rotate computes (same kernels,
+ * same bits) but takes its key-switch temporaries (job table, digits, inner
+ * products, P-limb coefficients) from a fixed 32 MiB device array of the
+ * library, one per GPU, created when the library is loaded on that GPU and
+ * held until the process ends.  It never touches the context workspace and
+ * calls no allocating routine.  The caller passes inputs and outputs as for
+ * he_rotate; the context's device must be current (else HE_EINVAL).  Batches
+ * larger than the array run in chunks of he_rotate_static_max_batch(ctx,
+ * level) ciphertexts; a level whose single-ciphertext temporaries exceed the
+ * array returns HE_ENOMEM before any launch.  Every call on one GPU, from any
+ * context or thread, shares that GPU's array: calls whose work overlaps on the
+ * device (different streams, or host threads without ordering) race and must
+ * be serialised by the caller.  Nothing in the array needs to start at zero;
+ * it keeps whatever the last call left there. */
+int he_rotate_static(he_ctx *ctx, uint64_t *d_out, const uint64_t *d_in, int count, int level, int k, void *stream);
+int he_rotate_static_max_batch(const he_ctx *ctx, int level);
+
 /* ---- batched calls over ragged batches --------------------------------------
  * Each item has its own device pointers and level (host arrays of `count`
  * entries); all items of a call run in one launch per kernel, so work from

@@ -68,6 +68,8 @@ SIGNATURES = {
     "he_rotate": (I, [P, P, P, I, I, I, P]),
     "he_rotate_hoisted": (I, [P, P, I, I32P, I, P, P]),
     "he_rotsum": (I, [P, P, I, I, I, P]),
+    "he_rotate_static": (I, [P, P, P, I, I, I, P]),
+    "he_rotate_static_max_batch": (I, [P, I]),
     "he_square": (I, [P, P, P, I, I, P]),
     "he_batch_rotate": (I, [P, ctypes.POINTER(P), ctypes.POINTER(P), I32P, I32P, I, I, P]),
     "he_batch_rescale": (I, [P, ctypes.POINTER(P), ctypes.POINTER(P), I32P, I, P]),

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -19,7 +20,36 @@
 
 using namespace he;
 
+// Device scratch of the allocation-free rotation (he_rotate_static): one
+// array per GPU, created when the library's code object is loaded on that
+// GPU and held until the process ends.  Host code never passes the name
+// `scratch` to a kernel (on the host it is only a stand-in for the symbol):
+// its device address on each GPU comes from hipGetSymbolAddress at context
+// creation, with that GPU current, and is kept per device below.
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_addr[MAX_DEVICES] = {};
+
+// Looks up the address of this device's scratch array once per device (the
+// device must be current) and stores it in the context.
+int scratch_setup(he_ctx* c) {
+  if (c->device < 0 || c->device >= MAX_DEVICES) return fail(c, HE_EDEVICE, "device index %d too large", c->device);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[c->device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(c, HE_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_addr[c->device] = (char*)p;
+  }
+  c->fixed_scratch = g_scratch_addr[c->device];
+  return HE_OK;
+}
 
 // Copies `bytes` from host to device memory `dst` on stream s through a ring
 // of pinned buffers; a slot is reused only after its previous copy finished.
@@ -594,7 +624,7 @@ int he_ctx_create(const he_params* p, he_ctx** out) {
                   hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess &&
                   hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) == hipSuccess &&
                   hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) == hipSuccess;
-  if (!ok) {
+  if (!ok || scratch_setup(c) != HE_OK) {
     he_ctx_destroy(c);
     return HE_EDEVICE;
   }
@@ -834,6 +864,28 @@ int he_rotate(he_ctx* c, uint64_t* d_out, const uint64_t* d_in, int count, int l
   if (!c || !d_out || !d_in || count < 1 || !level_ok(c, level)) return fail(c, HE_EINVAL, "he_rotate: bad arguments");
   Arena ar(c);
   return rotate_batch(c, d_out, d_in, count, level, k, EPI_ROT, ar, S(stream));
+}
+
+int he_rotate_static(he_ctx* c, uint64_t* d_out, const uint64_t* d_in, int count, int level, int k, void* stream) {
+  if (!c || !d_out || !d_in || count < 1 || !level_ok(c, level))
+    return fail(c, HE_EINVAL, "he_rotate_static: bad arguments");
+  if (!c->fixed_scratch) return fail(c, HE_EDEVICE, "he_rotate_static: no scratch array on this device");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != c->device)
+    return fail(c, HE_EINVAL, "he_rotate_static: the context's device (%d) is not current (%d)", c->device, dev);
+  // one ciphertext's key-switch temporaries must fit; larger batches run in chunks
+  const size_t one = (ks_elems_per_job(level, p_groups(c, level), c->n) + 128) * 8;
+  if (one > STATIC_SCRATCH_BYTES)
+    return fail(c, HE_ENOMEM, "he_rotate_static: one ciphertext at level %d needs %zu bytes of scratch (max %zu)",
+                level, one, STATIC_SCRATCH_BYTES);
+  Arena ar(c->fixed_scratch, STATIC_SCRATCH_BYTES);
+  return rotate_batch(c, d_out, d_in, count, level, k, EPI_ROT, ar, S(stream));
+}
+
+int he_rotate_static_max_batch(const he_ctx* c, int level) {
+  if (!c || !level_ok(const_cast<he_ctx*>(c), level)) return HE_EINVAL;
+  Arena ar(c->fixed_scratch, STATIC_SCRATCH_BYTES);
+  return chunk_for(ar, 1 << 30, level, p_groups(c, level), c->n);
 }
 
 int he_rotsum(he_ctx* c, uint64_t* d_cts, int count, int level, int r_steps, void* stream) {

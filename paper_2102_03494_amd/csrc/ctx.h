@@ -44,6 +44,7 @@ struct he_ctx {
   int split_streams = 1;         // DensePack rotate-and-sum in two halves on two streams
   char* ws = nullptr;
   size_t ws_bytes = 0;
+  char* fixed_scratch = nullptr;  // this device's static scratch array (he_rotate_static)
   std::map<int, u64*> keys;  // Galois element (0 = relinearisation) -> [L][2][L+1][N]
   std::string err;
   he_counts counts{};
@@ -128,6 +129,7 @@ struct Arena {
   char* base;
   size_t cap, used = 0;
   Arena(he_ctx* c) : base(c->ws), cap(c->ws_bytes) {}
+  Arena(char* b, size_t bytes) : base(b), cap(bytes) {}
   template <typename T>
   T* take(size_t count) {
     size_t bytes = (count * sizeof(T) + 255) & ~(size_t)255;
