@@ -13,7 +13,7 @@
  *
  * Conventions shared by all calls
  * -------------------------------
- * Ring: Z[X]/(X^N + 1), N a power of two in [2^10, 2^16].  Moduli: the
+ * Ring: Z[X]/(X^N + 1), N a power of two in [2^10, 2^14].  Moduli: the
  * ciphertext primes q_0 > ... > q_{L-1} (ordered as generated) followed by the
  * special prime P; "modulus index" t < L means q_t and t = L means P.  Every
  * prime is 1 mod 2N and below 2^62.
@@ -30,13 +30,25 @@
  *
  * Memory: every data pointer named d_* is device memory owned by the caller
  * (e.g. torch tensors).  Host pointers are named h_*.  The library owns the
- * context tables, the switching keys and the workspace it is given by
- * he_ctx_reserve (the only call that allocates device memory besides
- * he_ctx_create and he_keygen_switch).
+ * context tables and the switching keys (he_keys_upload copies client-made
+ * keys into it).  The workspace arena that evaluation calls take their
+ * temporaries from is either the caller's (he_ctx_set_workspace) or the
+ * library's (he_ctx_reserve).  Only he_ctx_create, he_ctx_reserve,
+ * he_keys_upload and the client helper he_keygen_switch allocate device
+ * memory; evaluation calls never do (a call that needs more workspace than
+ * there is returns HE_ENOMEM).
  *
- * Errors: each call returns HE_OK (0) or a negative code.  Argument, level
- * and key errors are detected before any launch and leave outputs untouched;
- * he_last_error gives the message.  Launch failures return HE_EDEVICE.
+ * Scales: a ciphertext's scale is a host double that the caller tracks.
+ * Calls that combine ciphertexts (he_add, he_hma_plain, he_hma_scalar,
+ * he_conv_convpack) take the scales and return HE_ESCALE when they do not
+ * match (two scales match when both are finite and positive and differ by at
+ * most 2^-30 relative; both sides compute them with the same IEEE double
+ * operations).
+ *
+ * Errors: each call returns HE_OK (0) or a negative code.  Argument, level,
+ * scale and key errors are detected before any launch and leave outputs
+ * untouched; he_last_error gives the message.  Launch failures return
+ * HE_EDEVICE.
  * Calls enqueue work on the given stream (hipStream_t as void*, NULL = the
  * default stream) and return without synchronising, except where stated.
  * A context is not thread safe: use one per host thread or serialise.
@@ -55,6 +67,7 @@ enum {
   HE_OK = 0,
   HE_EINVAL = -1,       /* bad argument or shape */
   HE_ELEVEL = -2,       /* level too low/high for the operation */
+  HE_ESCALE = -3,       /* scales of the operands do not match */
   HE_ENOKEY = -4,       /* a needed switching key is missing */
   HE_ENOMEM = -5,       /* workspace or device allocation too small / failed */
   HE_EDEVICE = -6,      /* HIP runtime or launch error */
@@ -81,19 +94,26 @@ int he_params_moduli(const he_params *p, uint64_t *h_out);
 
 /* ---- context ---------------------------------------------------------------
  * he_ctx_create builds the prime chain, roots and twiddle tables on the
- * current device.  he_ctx_reserve makes sure the workspace holds `bytes`
- * (device allocation; call it outside timed regions).  he_ctx_workspace_need
- * returns the bytes the heaviest call on `count` ciphertexts at `level` needs
- * (0 on error). */
+ * current device (N up to 2^14; larger rings return HE_EUNSUPPORTED).
+ * he_ctx_reserve makes sure the workspace holds `bytes` (a library-owned
+ * device allocation, replacing a smaller or caller-owned one; call it
+ * outside timed regions).  he_ctx_set_workspace hands the context a
+ * caller-owned device buffer d_ws of `bytes` (256-byte aligned; NULL and 0
+ * detach it) as its workspace; the caller keeps ownership and must keep it
+ * alive while the context uses it.  Both wait for the device first and
+ * invalidate graphs captured before.  he_ctx_workspace_need returns the bytes
+ * the heaviest call on `count` ciphertexts at `level` needs (0 on error). */
 int he_ctx_create(const he_params *p, he_ctx **out);
 int he_ctx_destroy(he_ctx *ctx);
 int he_ctx_reserve(he_ctx *ctx, size_t bytes);
+int he_ctx_set_workspace(he_ctx *ctx, void *d_ws, size_t bytes);
 size_t he_ctx_workspace_need(const he_ctx *ctx, int count, int level);
 int he_ctx_moduli(const he_ctx *ctx, uint64_t *h_out);   /* n_q + 1 values */
 const char *he_last_error(const he_ctx *ctx);
 
-/* Schedule knobs of the key switch (Sec. III's hybrid key switching as built
- * here; no effect on any result bit, only on speed).  knob "p_groups": the
+/* Schedule knobs of the key switch (the paper does not describe key
+ * switching; this library's is hybrid, one digit per ciphertext prime and one
+ * special prime P).  The knobs change no result bit, only speed.  knob "p_groups": the
  * number of workgroups (1..min(level, 4)) that share the ModUp + inner
  * product into the special prime P at key-switch level `level` (1..L);
  * value 0 restores the built-in cost model.  knob "split_streams" (level
@@ -114,22 +134,33 @@ int he_intt(he_ctx *ctx, uint64_t *d_polys, int n_polys, int n_limbs, int first_
 
 /* ---- elementwise operations (AddCC and MulPC of Table I) -------------------
  * he_add:  d_out[i] = d_a[i] + d_b[i] for `count` ciphertexts at `level`
- *          (d_out may alias d_a or d_b).
+ *          (d_out may alias d_a or d_b); HE_ESCALE unless scale_a and
+ *          scale_b match.  The sum has that scale.
  * he_hma_plain: one accumulator ciphertext d_acc ([2][level][N]) gets
  *          (accumulate ? d_acc : 0) + sum_{i<k} d_cts[i] * sigma_{g_i}(pt_i),
- *          where pt_i = d_pts + i * pt_stride limbs-of-N (pt_stride = 0 reuses
- *          one plaintext), each plaintext has pt_limbs >= level limbs, and
- *          g_i = h_galois[i] (h_galois NULL: no permutation).  This is MulPC
- *          with the plaintext slot rotation folded into its load.
+ *          where d_cts = [k][2][level][N], pt_i starts at
+ *          d_pts + i * pt_stride * pt_limbs * N (pt_stride counts whole
+ *          plaintexts of pt_limbs limbs; 0 reuses one plaintext), each
+ *          plaintext has pt_limbs >= level limbs of which the first `level`
+ *          are used, and g_i = h_galois[i] (h_galois NULL: no permutation).
+ *          This is MulPC with the plaintext slot rotation folded into its
+ *          load.  Scales: every d_cts[i] has ct_scale and every plaintext
+ *          pt_scale; with accumulate, *io_acc_scale (the accumulator's scale)
+ *          must match ct_scale * pt_scale (else HE_ESCALE); on success
+ *          *io_acc_scale = ct_scale * pt_scale.
  * he_hma_scalar: d_acc = (accumulate ? d_acc : 0) + sum_{i<k} w_i * d_cts[i]
- *          with exact signed integers h_w[i] (|w| < 2^62). */
+ *          with exact signed integers h_w[i] (|w| < 2^62, else HE_EINVAL)
+ *          that carry the scale w_scale (e.g. round(x * 2^12) carries 2^12);
+ *          scales as for he_hma_plain with pt_scale = w_scale. */
 int he_add(he_ctx *ctx, uint64_t *d_out, const uint64_t *d_a, const uint64_t *d_b,
-           int count, int level, void *stream);
+           int count, int level, double scale_a, double scale_b, void *stream);
 int he_hma_plain(he_ctx *ctx, uint64_t *d_acc, const uint64_t *d_cts, int k,
                  const uint64_t *d_pts, int pt_stride, int pt_limbs,
-                 const int32_t *h_galois, int level, int accumulate, void *stream);
+                 const int32_t *h_galois, int level, int accumulate,
+                 double ct_scale, double pt_scale, double *io_acc_scale, void *stream);
 int he_hma_scalar(he_ctx *ctx, uint64_t *d_acc, const uint64_t *d_cts, int k,
-                  const int64_t *h_w, int level, int accumulate, void *stream);
+                  const int64_t *h_w, int level, int accumulate,
+                  double ct_scale, double w_scale, double *io_acc_scale, void *stream);
 
 /* ---- rescale -----------------------------------------------------------------
  * d_out[i] ([2][level-1][N]) = round(d_in[i] / q_{level-1}) for `count`
@@ -139,19 +170,39 @@ int he_hma_scalar(he_ctx *ctx, uint64_t *d_acc, const uint64_t *d_cts, int k,
 int he_rescale(he_ctx *ctx, uint64_t *d_out, const uint64_t *d_in, int count, int level, void *stream);
 
 /* ---- keys ------------------------------------------------------------------
- * Switching keys live in the context (device memory owned by the library).
- * he_keygen_switch computes and stores the key for Galois element `galois`
- * (odd, < 2N), or the relinearisation key when galois == 0, from client data:
- *   d_s     secret in the NTT domain, [L+1][N] (all moduli),
- *   d_a     uniform residues, NTT domain, [L][L+1][N] (one row per digit),
- *   d_e     signed error coefficients, int64 [L][N].
- * For digit j and modulus index t:  b = -a*s + e + [t == j] (P mod q_t) s'
- * with s' = sigma_galois(s) (or s^2), stored with a as [L][2][L+1][N].
- * This is a client-side call (it needs the secret); it synchronises. */
-int he_keygen_switch(he_ctx *ctx, int32_t galois, const uint64_t *d_s,
-                     const uint64_t *d_a, const int64_t *d_e, void *stream);
+ * In the paper's setting (Section 1, Section 3) the client keeps the secret
+ * and the server sees only ciphertexts, plaintext weights and the public
+ * switching keys the client sends it.  Key layout (the exchange format):
+ * one key = [L][2][L+1][N] canonical uint64 residues, for digit j < L the
+ * pair (b_j, a_j) over the moduli q_0 .. q_{L-1}, P, in the NTT domain, with
+ *   b_j = -a_j * s + e_j + [t == j] (P mod q_t) s'   (mod modulus t),
+ * s' = sigma_g(s) for Galois element g (odd, 1 < g < 2N; rotation left by k
+ * uses g = 5^k mod 2N) or s^2 for the relinearisation key (g = 0).
+ *
+ * he_keys_upload (server side): copies n_keys such keys, keys =
+ *          [n_keys][L][2][L+1][N] (host memory, or device memory when
+ *          keys_on_device != 0), for Galois elements h_galois[0..n_keys)
+ *          into the context's device-resident key store (replacing keys of
+ *          the same elements, which invalidates graphs captured before).
+ *          Returns HE_EINVAL for a bad or repeated element or a residue not
+ *          below its modulus (the store is then unchanged).  Synchronises.
+ * he_keys_free: drops the keys of h_galois[0..n_keys) (n_keys == 0: all);
+ *          HE_ENOKEY, dropping none, if one is missing.  Waits for the device;
+ *          invalidates graphs captured before.
+ * he_has_key: 1 if the key of `galois` is stored, else 0.
+ * he_keygen_switch (client side, needs the secret; any context with the same
+ *          parameters): writes the key of `galois` in the exchange layout to
+ *          caller memory d_key ([L][2][L+1][N]) from
+ *            d_s  the secret in the NTT domain, [L+1][N] (all moduli),
+ *            d_a  uniform residues, NTT domain, [L][L+1][N] (one row per digit),
+ *            d_e  signed error coefficients, int64 [L][N].
+ *          It stores nothing in the context; synchronises. */
+int he_keys_upload(he_ctx *ctx, const int32_t *h_galois, int n_keys, const uint64_t *keys, int keys_on_device,
+                   void *stream);
+int he_keys_free(he_ctx *ctx, const int32_t *h_galois, int n_keys);
 int he_has_key(const he_ctx *ctx, int32_t galois);
-int he_drop_keys(he_ctx *ctx);
+int he_keygen_switch(he_ctx *ctx, int32_t galois, const uint64_t *d_s, const uint64_t *d_a, const int64_t *d_e,
+                     uint64_t *d_key, void *stream);
 
 /* ---- client helpers (not on the server path) -------------------------------
  * he_from_signed: d_out [n_limbs][N] = d_coeffs (int64 [N]) mod modulus index
@@ -296,12 +347,17 @@ int he_conv_densepack_batch(he_ctx *ctx, int n_layers, const uint64_t *d_in, siz
                             void *stream);
 
 /* he_conv_convpack (Table II): K channel ciphertexts in, O_c out:
- * d_out[o] = rescale(sum_k round-half-away(h_w[k*o_c + o] * w_scale) * d_in[k]).
- * d_in [K][2][level][N], d_out [o_c][2][level-1][N].  The caller picks
- * w_scale = q_{level-1} * target / input_scale so the rescale lands on
- * target. */
+ * d_out[o] = rescale(sum_k round-half-away(h_w[k*o_c + o] * w_scale) * d_in[k])
+ * with w_scale = q_{level-1} * target_scale / in_scale (IEEE double, in that
+ * order), so the rescale lands on the target: *out_scale = in_scale *
+ * w_scale / q_{level-1}.  d_in [K][2][level][N] all at in_scale, d_out
+ * [o_c][2][level-1][N].  HE_ELEVEL unless 2 <= level <= L; HE_ESCALE when a
+ * scale is not finite and positive or w_scale < 1; HE_EINVAL when a weight
+ * times w_scale is not finite or reaches 4e18.  Counts: O_c K MulPC and
+ * O_c (K - 1) AddCC. */
 int he_conv_convpack(he_ctx *ctx, const uint64_t *d_in, int k, int level, const double *h_w,
-                     int o_c, double w_scale, uint64_t *d_out, void *stream);
+                     int o_c, double in_scale, double target_scale, uint64_t *d_out, double *out_scale,
+                     void *stream);
 
 /* ffconv_layer (Section 4, DP-HI2C-CP of Table IX):
  *   1. W1 under DensePack exactly as he_conv_densepack (desc->o_c = rank r),
@@ -311,7 +367,9 @@ int he_conv_convpack(he_ctx *ctx, const uint64_t *d_in, int k, int level, const 
  *   3. 1x1 ConvPack: Z_o = sum_c round-half-away(h_w2[c*o_c2 + o] * 2^k_bits) G_c;
  *   4. rescale; 5. if square: Z <- rescale(relinearised Z^2).
  * d_out: [o_c2][2][level-2 (-1 more if square)][N].  The mask is encoded by
- * the caller at scale q_{level-2} * target / (y_scale * 2^k_bits). */
+ * the caller at scale q_{level-2} * target / (y_scale * 2^k_bits).  A W2
+ * weight times 2^k_bits that is not finite or reaches 4e18 returns HE_EINVAL
+ * before any launch. */
 int ffconv_layer(he_ctx *ctx, const uint64_t *d_in, int level, const he_conv_desc *desc,
                  const uint64_t *d_w1_filt, const uint64_t *d_mask, const double *h_w2, int o_c2,
                  int k_bits, int square, uint64_t *d_out, void *stream);
@@ -354,9 +412,9 @@ size_t he_ffconv_workspace_need(const he_ctx *ctx, int n_layers, int level, cons
  * replays the whole recorded sequence on `stream` in one launch, with the
  * same device pointers (inputs, outputs, workspace, keys): write new inputs
  * into the same buffers between replays.  It returns HE_EINVAL if the
- * workspace was reallocated or keys were dropped since the capture.
+ * workspace was reallocated or keys were replaced or freed since the capture.
  * Calls that copy host tables (he_int_weight_table, ffconv_layer with host
- * W2, he_batch_*), reserve, key generation and key dropping fail with
+ * W2, he_batch_*), workspace changes, key upload and key freeing fail with
  * HE_EUNSUPPORTED while capturing.  Replays of one graph must not overlap
  * with each other or with other calls on the context (they share its
  * workspace). */

@@ -46,6 +46,7 @@ SIGNATURES = {
     "he_ctx_create": (I, [ctypes.POINTER(HeParams), ctypes.POINTER(P)]),
     "he_ctx_destroy": (I, [P]),
     "he_ctx_reserve": (I, [P, ctypes.c_size_t]),
+    "he_ctx_set_workspace": (I, [P, P, ctypes.c_size_t]),
     "he_ctx_workspace_need": (ctypes.c_size_t, [P, I, I]),
     "he_ctx_moduli": (I, [P, U64P]),
     "he_last_error": (ctypes.c_char_p, [P]),
@@ -53,13 +54,14 @@ SIGNATURES = {
     "he_ctx_get_tuning": (I, [P, ctypes.c_char_p, I]),
     "he_ntt": (I, [P, P, I, I, I, P]),
     "he_intt": (I, [P, P, I, I, I, P]),
-    "he_add": (I, [P, P, P, P, I, I, P]),
-    "he_hma_plain": (I, [P, P, P, I, P, I, I, I32P, I, I, P]),
-    "he_hma_scalar": (I, [P, P, P, I, I64P, I, I, P]),
+    "he_add": (I, [P, P, P, P, I, I, ctypes.c_double, ctypes.c_double, P]),
+    "he_hma_plain": (I, [P, P, P, I, P, I, I, I32P, I, I, ctypes.c_double, ctypes.c_double, DP, P]),
+    "he_hma_scalar": (I, [P, P, P, I, I64P, I, I, ctypes.c_double, ctypes.c_double, DP, P]),
     "he_rescale": (I, [P, P, P, I, I, P]),
-    "he_keygen_switch": (I, [P, ctypes.c_int32, P, P, P, P]),
+    "he_keygen_switch": (I, [P, ctypes.c_int32, P, P, P, P, P]),
+    "he_keys_upload": (I, [P, I32P, I, P, I, P]),
+    "he_keys_free": (I, [P, I32P, I]),
     "he_has_key": (I, [P, ctypes.c_int32]),
-    "he_drop_keys": (I, [P]),
     "he_from_signed": (I, [P, P, P, I, I, P]),
     "he_encrypt_sk": (I, [P, P, P, P, P, P, I, P]),
     "he_decrypt": (I, [P, P, P, P, I, P]),
@@ -76,7 +78,7 @@ SIGNATURES = {
     "he_batch_mul_plain": (I, [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P), I32P, I, P]),
     "he_combine_cp_dp": (I, [P, P, I, I, I, I, P, P]),
     "he_conv_densepack": (I, [P, P, I, ctypes.POINTER(HeConvDesc), P, P, P]),
-    "he_conv_convpack": (I, [P, P, I, I, DP, I, ctypes.c_double, P, P]),
+    "he_conv_convpack": (I, [P, P, I, I, DP, I, ctypes.c_double, ctypes.c_double, P, DP, P]),
     "ffconv_layer": (I, [P, P, I, ctypes.POINTER(HeConvDesc), P, P, DP, I, I, I, P, P]),
     "he_int_weight_table": (I, [P, DP, I, I, I, P, P]),
     "ffconv_layer_batch": (I, [P, I, P, ctypes.c_size_t, I, ctypes.POINTER(HeConvDesc), P, ctypes.c_size_t, P, P,

@@ -6,6 +6,10 @@ and the client decrypts the prediction.  This module generates the secret and
 the switching keys from the seeded draws of ``synth``, encodes and encrypts
 slot vectors and decrypts results, calling the library for every ring
 operation (encoding's FFT and the CRT of decryption run on the host).
+
+The client works in a library context of its own.  The server's context
+never sees the secret: it receives only the switching keys, through
+``he_keys_upload`` in the exchange layout, and the ciphertexts.
 """
 from __future__ import annotations
 
@@ -18,8 +22,11 @@ from .he import Ct, HEContext, galois_for_rotation, to_device, to_host
 
 
 class Client:
-    def __init__(self, ctx: HEContext, workload, secret_index: int = 0):
-        self.ctx = ctx
+    def __init__(self, server: HEContext, workload, secret_index: int = 0):
+        """`server` is the evaluating party's context: it only ever receives keys."""
+        self.server = server
+        self.ctx = HEContext(server.n, server.q_bits, server.p_bits, workspace_bytes=16 << 20, tuned=False)
+        ctx = self.ctx
         self.workload = workload
         n, big_l = ctx.n, ctx.L
         s = synth.ternary_secret(workload, n, secret_index)
@@ -29,20 +36,29 @@ class Client:
         self.s_ntt = s_ntt
 
     # ---- keys ------------------------------------------------------------------
-    def _switch_key(self, key_index: int):
+    def switch_key(self, key_index: int) -> torch.Tensor:
+        """The key for Galois element key_index (0: relinearisation), exchange
+        layout [L][2][L+1][N], made in the client's own context."""
         c = self.ctx
         a, e = synth.switch_key_draws(self.workload, key_index, c.moduli, c.n, c.L)
-        c.keygen_switch(key_index, self.s_ntt, to_device(a), torch.from_numpy(e).cuda())
+        return c.keygen_switch(key_index, self.s_ntt, to_device(a), torch.from_numpy(e).cuda())
 
-    def gen_rotation_keys(self, steps):
+    def _send(self, key_index: int, server: HEContext | None):
+        server = self.server if server is None else server
+        if not server.has_key(key_index):
+            key = self.switch_key(key_index)
+            server.upload_keys([key_index], key.view(1, *key.shape))
+            del key
+
+    def gen_rotation_keys(self, steps, server: HEContext | None = None):
+        """Make the rotation keys of `steps` and upload them to the server."""
         for k in steps:
             g = galois_for_rotation(int(k), self.ctx.n)
-            if g != 1 and not self.ctx.has_key(g):
-                self._switch_key(g)
+            if g != 1:
+                self._send(g, server)
 
-    def gen_relin_key(self):
-        if not self.ctx.has_key(synth.RELIN_INDEX):
-            self._switch_key(synth.RELIN_INDEX)
+    def gen_relin_key(self, server: HEContext | None = None):
+        self._send(synth.RELIN_INDEX, server)
 
     # ---- plaintexts -----------------------------------------------------------------
     def encode(self, z, level: int, scale: float) -> torch.Tensor:

@@ -409,6 +409,14 @@ int densepack_run(he_ctx* c, const u64* d_in, int level, const he_conv_desc* des
 
 bool level_ok(he_ctx* c, int level) { return level >= 1 && level <= c->big_l; }
 
+// Scales are host doubles that caller and library compute with the same IEEE
+// operations; two scales agree when both are finite and positive and differ
+// by at most 2^-30 relative.
+bool scale_ok(double a) { return std::isfinite(a) && a > 0; }
+bool scales_agree(double a, double b) {
+  return scale_ok(a) && scale_ok(b) && std::fabs(a - b) <= std::ldexp(std::max(a, b), -30);
+}
+
 // Residue table of signed integer scalars w (count values) for limbs < level,
 // laid out [count][level] followed by the Shoup companions.
 std::vector<u64> scalar_table(he_ctx* c, const std::vector<int64_t>& w, int level) {
@@ -604,6 +612,31 @@ int he_ctx_create(const he_params* p, he_ctx** out) {
         f[3 * n + k] = (double)b[2 * n + k] / (double)mods[i];
       }
   }
+  // Half-ring forward twiddles: after the first stage (pairs i, i + N/2 with
+  // w[1]) the two halves are independent transforms of N/2 points; stage s'
+  // of half h uses, for block k' < 2^s', the full table's w[2^(s'+1) + h 2^s'
+  // + k'], stored at index 2^s' + k' of that half's table.
+  const size_t nh = n / 2;
+  std::vector<u64> twh(mods.size() * 4 * nh, 0);
+  for (size_t i = 0; i < mods.size(); ++i)
+    for (int h = 0; h < 2; ++h) {
+      const u64* fw = tw.data() + i * 4 * n;
+      u64* dst = twh.data() + (i * 2 + h) * 2 * nh;
+      for (size_t mp = 1; mp < nh; mp <<= 1)
+        for (size_t k = 0; k < mp; ++k) {
+          dst[mp + k] = fw[2 * mp + h * mp + k];
+          dst[nh + mp + k] = fw[n + 2 * mp + h * mp + k];
+        }
+    }
+  std::vector<u32> twh32(twh.size(), 0);
+  std::vector<double> twhf(twh.size(), 0.0);
+  for (size_t i = 0; i < mods.size(); ++i) {
+    const size_t o = i * 4 * nh;
+    if (is_narrow(mods[i]))
+      for (size_t k = 0; k < 4 * nh; ++k) twh32[o + k] = (u32)twh[o + k];
+    if (width_class(mods[i]) == CLS_F64)
+      for (size_t k = 0; k < 4 * nh; ++k) twhf[o + k] = (double)twh[o + k];
+  }
   // inverse table: inv[div][t] = m_div^-1 mod q_t for divisors 0..L (L = P)
   std::vector<u64> inv(2 * HE_MAXM * HE_MAXM, 0);
   for (int dv = 0; dv <= p->n_q; ++dv)
@@ -619,6 +652,12 @@ int he_ctx_create(const he_params* p, he_ctx** out) {
                   hipMemcpy(c->d_tw32, tw32.data(), tw32.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
                   hipMalloc((void**)&c->d_twf, twf.size() * 8) == hipSuccess &&
                   hipMemcpy(c->d_twf, twf.data(), twf.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMalloc((void**)&c->d_twh, twh.size() * 8) == hipSuccess &&
+                  hipMemcpy(c->d_twh, twh.data(), twh.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMalloc((void**)&c->d_twh32, twh32.size() * 4) == hipSuccess &&
+                  hipMemcpy(c->d_twh32, twh32.data(), twh32.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
+                  hipMalloc((void**)&c->d_twhf, twhf.size() * 8) == hipSuccess &&
+                  hipMemcpy(c->d_twhf, twhf.data(), twhf.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
                   hipMalloc((void**)&c->d_inv, inv.size() * 8) == hipSuccess &&
                   hipMemcpy(c->d_inv, inv.data(), inv.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
                   hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess &&
@@ -641,8 +680,11 @@ int he_ctx_destroy(he_ctx* c) {
   (void)hipFree(c->d_tw);
   (void)hipFree(c->d_tw32);
   (void)hipFree(c->d_twf);
+  (void)hipFree(c->d_twh);
+  (void)hipFree(c->d_twh32);
+  (void)hipFree(c->d_twhf);
   (void)hipFree(c->d_inv);
-  (void)hipFree(c->ws);
+  if (c->ws_owned) (void)hipFree(c->ws);
   if (c->side) (void)hipStreamDestroy(c->side);
   if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
   if (c->join_ev) (void)hipEventDestroy(c->join_ev);
@@ -660,12 +702,26 @@ int he_ctx_reserve(he_ctx* c, size_t bytes) {
   if (c->capturing) return fail(c, HE_EUNSUPPORTED, "he_ctx_reserve: not allowed during graph capture");
   ++c->epoch;
   (void)hipDeviceSynchronize();
-  (void)hipFree(c->ws);
+  if (c->ws_owned) (void)hipFree(c->ws);
   c->ws = nullptr;
   c->ws_bytes = 0;
+  c->ws_owned = true;
   if (hipMalloc((void**)&c->ws, bytes) != hipSuccess)
     return fail(c, HE_ENOMEM, "workspace allocation of %zu bytes failed", bytes);
   c->ws_bytes = bytes;
+  return HE_OK;
+}
+
+int he_ctx_set_workspace(he_ctx* c, void* d_ws, size_t bytes) {
+  if (!c || (!d_ws && bytes)) return fail(c, HE_EINVAL, "he_ctx_set_workspace: bad arguments");
+  if (((uintptr_t)d_ws & 255) != 0) return fail(c, HE_EINVAL, "he_ctx_set_workspace: buffer not 256-byte aligned");
+  if (c->capturing) return fail(c, HE_EUNSUPPORTED, "he_ctx_set_workspace: not allowed during graph capture");
+  ++c->epoch;
+  (void)hipDeviceSynchronize();
+  if (c->ws_owned) (void)hipFree(c->ws);
+  c->ws = (char*)d_ws;
+  c->ws_bytes = d_ws ? bytes : 0;
+  c->ws_owned = false;
   return HE_OK;
 }
 
@@ -721,18 +777,27 @@ int he_intt(he_ctx* c, uint64_t* d, int n_polys, int n_limbs, int first_mod, voi
   return check_launch(c, "he_intt");
 }
 
-int he_add(he_ctx* c, uint64_t* out, const uint64_t* a, const uint64_t* b, int count, int level, void* stream) {
+int he_add(he_ctx* c, uint64_t* out, const uint64_t* a, const uint64_t* b, int count, int level, double scale_a,
+           double scale_b, void* stream) {
   if (!c || !out || !a || !b || count < 1 || count > 65535 || !level_ok(c, level))
     return fail(c, HE_EINVAL, "he_add: bad arguments");
+  if (!scales_agree(scale_a, scale_b))
+    return fail(c, HE_ESCALE, "he_add: scales %.17g and %.17g differ", scale_a, scale_b);
   Prof pr(c, "add", S(stream));
   k_add<<<dim3(c->n / 256, level, count), 256, 0, S(stream)>>>(out, a, b, level, c->n, c->mods);
   return check_launch(c, "he_add");
 }
 
 int he_hma_plain(he_ctx* c, uint64_t* acc, const uint64_t* cts, int k, const uint64_t* pts, int pt_stride, int pt_limbs,
-                 const int32_t* h_galois, int level, int accumulate, void* stream) {
-  if (!c || !acc || !cts || !pts || k < 1 || pt_stride < 0 || pt_limbs < level || !level_ok(c, level))
+                 const int32_t* h_galois, int level, int accumulate, double ct_scale, double pt_scale,
+                 double* io_acc_scale, void* stream) {
+  if (!c || !acc || !cts || !pts || !io_acc_scale || k < 1 || pt_stride < 0 || pt_limbs < level || !level_ok(c, level))
     return fail(c, HE_EINVAL, "he_hma_plain: bad arguments");
+  const double prod_scale = ct_scale * pt_scale;
+  if (!scale_ok(ct_scale) || !scale_ok(pt_scale) || !scale_ok(prod_scale) ||
+      (accumulate && !scales_agree(*io_acc_scale, prod_scale)))
+    return fail(c, HE_ESCALE, "he_hma_plain: product scale %.17g does not match the accumulator's %.17g", prod_scale,
+                *io_acc_scale);
   Arena ar(c);
   const int32_t* d_gal = nullptr;
   if (h_galois) {
@@ -747,20 +812,35 @@ int he_hma_plain(he_ctx* c, uint64_t* acc, const uint64_t* cts, int k, const uin
   }
   dispatch_logn<LHmaPerm>(c->logn, c, acc, cts, k, pts, pt_stride, pt_limbs, d_gal, 1u, level, accumulate, 1,
                           S(stream));
-  return check_launch(c, "he_hma_plain");
+  const int e = check_launch(c, "he_hma_plain");
+  if (!e) *io_acc_scale = prod_scale;
+  return e;
 }
 
 int he_hma_scalar(he_ctx* c, uint64_t* acc, const uint64_t* cts, int k, const int64_t* h_w, int level, int accumulate,
-                  void* stream) {
-  if (!c || !acc || !cts || !h_w || k < 1 || !level_ok(c, level)) return fail(c, HE_EINVAL, "he_hma_scalar: bad arguments");
+                  double ct_scale, double w_scale, double* io_acc_scale, void* stream) {
+  if (!c || !acc || !cts || !h_w || !io_acc_scale || k < 1 || !level_ok(c, level))
+    return fail(c, HE_EINVAL, "he_hma_scalar: bad arguments");
+  const double prod_scale = ct_scale * w_scale;
+  if (!scale_ok(ct_scale) || !scale_ok(w_scale) || !scale_ok(prod_scale) ||
+      (accumulate && !scales_agree(*io_acc_scale, prod_scale)))
+    return fail(c, HE_ESCALE, "he_hma_scalar: product scale %.17g does not match the accumulator's %.17g", prod_scale,
+                *io_acc_scale);
+  for (int i = 0; i < k; ++i)
+    if (h_w[i] <= -(1ll << 62) || h_w[i] >= (1ll << 62)) return fail(c, HE_EINVAL, "he_hma_scalar: |w| >= 2^62");
   Arena ar(c);
   std::vector<int64_t> w(h_w, h_w + k);
-  if (!accumulate) return scalar_mac(c, acc, cts, k, w, 1, level, ar, S(stream));
-  u64* tmp = ar.take<u64>((size_t)2 * level * c->n);
-  if (!tmp) return fail(c, HE_ENOMEM, "workspace too small");
-  int e = scalar_mac(c, tmp, cts, k, w, 1, level, ar, S(stream));
-  if (e) return e;
-  return he_add(c, acc, acc, tmp, 1, level, stream);
+  int e;
+  if (!accumulate) {
+    e = scalar_mac(c, acc, cts, k, w, 1, level, ar, S(stream));
+  } else {
+    u64* tmp = ar.take<u64>((size_t)2 * level * c->n);
+    if (!tmp) return fail(c, HE_ENOMEM, "workspace too small");
+    e = scalar_mac(c, tmp, cts, k, w, 1, level, ar, S(stream));
+    if (!e) e = he_add(c, acc, acc, tmp, 1, level, prod_scale, prod_scale, stream);
+  }
+  if (!e) *io_acc_scale = prod_scale;
+  return e;
 }
 
 int he_rescale(he_ctx* c, uint64_t* out, const uint64_t* in, int count, int level, void* stream) {
@@ -771,8 +851,8 @@ int he_rescale(he_ctx* c, uint64_t* out, const uint64_t* in, int count, int leve
 }
 
 int he_keygen_switch(he_ctx* c, int32_t galois, const uint64_t* d_s, const uint64_t* d_a, const int64_t* d_e,
-                     void* stream) {
-  if (!c || !d_s || !d_a || !d_e) return fail(c, HE_EINVAL, "he_keygen_switch: null argument");
+                     uint64_t* d_key, void* stream) {
+  if (!c || !d_s || !d_a || !d_e || !d_key) return fail(c, HE_EINVAL, "he_keygen_switch: null argument");
   if (c->capturing) return fail(c, HE_EUNSUPPORTED, "he_keygen_switch: not allowed during graph capture");
   if (galois != 0 && (galois < 1 || galois >= 2 * c->n || !(galois & 1)))
     return fail(c, HE_EINVAL, "he_keygen_switch: bad Galois element %d", galois);
@@ -786,40 +866,109 @@ int he_keygen_switch(he_ctx* c, int32_t galois, const uint64_t* d_s, const uint6
     k_from_signed<<<dim3(n / 256, L + 1), 256, 0, s>>>(ehat + (size_t)j * (L + 1) * n, d_e + (size_t)j * n, 0, (int)n,
                                                        c->mods);
   dispatch_logn<LNtt>(c->logn, c, ehat, L, L + 1, 0, true, s);
-  u64* key = nullptr;
-  auto it = c->keys.find(galois);
-  if (it != c->keys.end()) {
-    key = it->second;
-  } else if (hipMalloc((void**)&key, (size_t)L * 2 * (L + 1) * n * 8) != hipSuccess) {
-    (void)hipFree(ehat);
-    return fail(c, HE_ENOMEM, "key allocation failed");
-  }
   ConstTable pm{};
   for (int t = 0; t < L; ++t) {
     pm.v[t] = c->moduli[L] % c->moduli[t];
     pm.sh[t] = shoup_companion(pm.v[t], c->moduli[t]);
   }
-  dispatch_logn<LKeygen>(c->logn, c, key, d_s, d_a, (const u64*)ehat, (u32)galois, pm, s);
+  dispatch_logn<LKeygen>(c->logn, c, (u64*)d_key, d_s, d_a, (const u64*)ehat, (u32)galois, pm, s, 0);
   int e = check_launch(c, "keygen");
   (void)hipStreamSynchronize(s);
   (void)hipFree(ehat);
-  if (e) {
-    if (it == c->keys.end()) (void)hipFree(key);
-    return e;
+  return e;
+}
+
+int he_keys_upload(he_ctx* c, const int32_t* h_galois, int n_keys, const uint64_t* keys, int keys_on_device,
+                   void* stream) {
+  if (!c || !h_galois || !keys || n_keys < 1) return fail(c, HE_EINVAL, "he_keys_upload: bad arguments");
+  if (c->capturing) return fail(c, HE_EUNSUPPORTED, "he_keys_upload: not allowed during graph capture");
+  for (int i = 0; i < n_keys; ++i) {
+    const int32_t g = h_galois[i];
+    if (g != 0 && (g < 1 || g >= 2 * c->n || !(g & 1) || g == 1))
+      return fail(c, HE_EINVAL, "he_keys_upload: bad Galois element %d", g);
+    for (int k = 0; k < i; ++k)
+      if (h_galois[k] == g) return fail(c, HE_EINVAL, "he_keys_upload: Galois element %d listed twice", g);
   }
-  c->keys[galois] = key;
+  const int L = c->big_l;
+  const size_t key_elems = (size_t)L * 2 * (L + 1) * c->n;
+  hipStream_t s = S(stream);
+  std::vector<u64*> fresh(n_keys, nullptr);
+  u64* staging = nullptr;
+  int* bad = nullptr;
+  auto cleanup = [&](bool drop_fresh) {
+    (void)hipStreamSynchronize(s);
+    if (drop_fresh)
+      for (u64* k : fresh) (void)hipFree(k);
+    (void)hipFree(staging);
+    (void)hipFree(bad);
+  };
+  if (hipMalloc((void**)&bad, sizeof(int)) != hipSuccess ||
+      (!keys_on_device && hipMalloc((void**)&staging, key_elems * 8) != hipSuccess)) {
+    cleanup(true);
+    return fail(c, HE_ENOMEM, "he_keys_upload: staging allocation failed");
+  }
+  (void)hipMemsetAsync(bad, 0, sizeof(int), s);
+  for (int i = 0; i < n_keys; ++i) {
+    if (hipMalloc((void**)&fresh[i], key_elems * 8) != hipSuccess) {
+      fresh[i] = nullptr;
+      cleanup(true);
+      return fail(c, HE_ENOMEM, "he_keys_upload: key allocation failed");
+    }
+    const u64* src = keys + (size_t)i * key_elems;
+    if (!keys_on_device) {
+      // the staging buffer is reused by the next key only after this pack ran
+      if (hipMemcpyAsync(staging, src, key_elems * 8, hipMemcpyHostToDevice, s) != hipSuccess) {
+        cleanup(true);
+        return fail(c, HE_EDEVICE, "he_keys_upload: host copy failed");
+      }
+      src = staging;
+    }
+    k_key_pack<<<dim3(c->n / 256, L + 1, 2 * L), 256, 0, s>>>(fresh[i], src, L, c->n, c->mods, bad);
+    if (!keys_on_device) (void)hipStreamSynchronize(s);
+  }
+  int h_bad = 0;
+  if (hipMemcpyAsync(&h_bad, bad, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess || check_launch(c, "he_keys_upload") != HE_OK) {
+    cleanup(true);
+    return fail(c, HE_EDEVICE, "he_keys_upload: device failure");
+  }
+  if (h_bad) {
+    cleanup(true);
+    return fail(c, HE_EINVAL, "he_keys_upload: a key residue is not reduced modulo its prime");
+  }
+  bool replaced = false;
+  for (int i = 0; i < n_keys; ++i) {
+    auto it = c->keys.find(h_galois[i]);
+    if (it != c->keys.end()) {
+      replaced = true;
+      (void)hipFree(it->second);
+    }
+    c->keys[h_galois[i]] = fresh[i];
+  }
+  if (replaced) ++c->epoch;
+  cleanup(false);
   return HE_OK;
 }
 
 int he_has_key(const he_ctx* c, int32_t galois) { return c && c->keys.count(galois) ? 1 : 0; }
 
-int he_drop_keys(he_ctx* c) {
-  if (!c) return HE_EINVAL;
-  if (c->capturing) return fail(c, HE_EUNSUPPORTED, "he_drop_keys: not allowed during graph capture");
+int he_keys_free(he_ctx* c, const int32_t* h_galois, int n_keys) {
+  if (!c || n_keys < 0 || (n_keys > 0 && !h_galois)) return fail(c, HE_EINVAL, "he_keys_free: bad arguments");
+  if (c->capturing) return fail(c, HE_EUNSUPPORTED, "he_keys_free: not allowed during graph capture");
+  for (int i = 0; i < n_keys; ++i)
+    if (!c->keys.count(h_galois[i])) return fail(c, HE_ENOKEY, "he_keys_free: no key for Galois element %d", h_galois[i]);
   ++c->epoch;
   (void)hipDeviceSynchronize();
-  for (auto& kv : c->keys) (void)hipFree(kv.second);
-  c->keys.clear();
+  if (n_keys == 0) {
+    for (auto& kv : c->keys) (void)hipFree(kv.second);
+    c->keys.clear();
+    return HE_OK;
+  }
+  for (int i = 0; i < n_keys; ++i) {
+    auto it = c->keys.find(h_galois[i]);
+    (void)hipFree(it->second);
+    c->keys.erase(it);
+  }
   return HE_OK;
 }
 
@@ -1102,10 +1251,17 @@ int he_conv_densepack_batch(he_ctx* c, int n_layers, const uint64_t* d_in, size_
   return densepack_run(c, d_in, level, desc, d_filt, d_out, ar, S(stream), n_layers, in_stride, filt_stride);
 }
 
-int he_conv_convpack(he_ctx* c, const uint64_t* d_in, int k, int level, const double* h_w, int o_c, double w_scale,
-                     uint64_t* d_out, void* stream) {
-  if (!c || !d_in || !h_w || !d_out || k < 1 || o_c < 1 || o_c > 65535 || level < 2 || level > c->big_l)
+int he_conv_convpack(he_ctx* c, const uint64_t* d_in, int k, int level, const double* h_w, int o_c, double in_scale,
+                     double target_scale, uint64_t* d_out, double* out_scale, void* stream) {
+  if (!c || !d_in || !h_w || !d_out || !out_scale || k < 1 || o_c < 1 || o_c > 65535)
     return fail(c, HE_EINVAL, "he_conv_convpack: bad arguments");
+  if (level < 2 || level > c->big_l) return fail(c, HE_ELEVEL, "he_conv_convpack needs 2 <= level <= L (got %d)", level);
+  // weight scale that makes the rescale by q_{level-1} land on the target
+  const double q_last = (double)c->moduli[level - 1];
+  const double w_scale = q_last * target_scale / in_scale;
+  if (!scale_ok(in_scale) || !scale_ok(target_scale) || !std::isfinite(w_scale) || w_scale < 1.0)
+    return fail(c, HE_ESCALE, "he_conv_convpack: input scale %.17g cannot reach target %.17g at level %d", in_scale,
+                target_scale, level);
   c->counts = he_counts{};
   std::vector<int64_t> w((size_t)k * o_c);
   for (size_t i = 0; i < w.size(); ++i) {
@@ -1119,6 +1275,7 @@ int he_conv_convpack(he_ctx* c, const uint64_t* d_in, int k, int level, const do
   hipStream_t s = S(stream);
   int e = scalar_mac(c, z, d_in, k, w, o_c, level, ar, s);
   if (!e) e = rescale_batch(c, d_out, z, o_c, level, ar, s);
+  if (!e) *out_scale = in_scale * w_scale / q_last;
   c->counts.mulpc = (int64_t)k * o_c;
   c->counts.addcc = (int64_t)(k - 1) * o_c;
   c->counts.rescale = o_c;
@@ -1133,7 +1290,11 @@ int ffconv_layer(he_ctx* c, const uint64_t* d_in, int level, const he_conv_desc*
   if (o_c2 < 1 || k_bits < 0 || k_bits > 40 || desc->o_c < 1) return fail(c, HE_EINVAL, "ffconv_layer: bad W2 shape or k_bits");
   if (level < 3 || level > c->big_l) return fail(c, HE_ELEVEL, "ffconv_layer needs level >= 3 (got %d)", level);
   std::vector<int64_t> w((size_t)desc->o_c * o_c2);
-  for (size_t i = 0; i < w.size(); ++i) w[i] = round_half_away(std::ldexp(h_w2[i], k_bits));
+  for (size_t i = 0; i < w.size(); ++i) {
+    const double x = std::ldexp(h_w2[i], k_bits);
+    if (!(std::fabs(x) < 4.0e18)) return fail(c, HE_EINVAL, "ffconv_layer: W2 weight not finite or too large");
+    w[i] = round_half_away(x);
+  }
   std::vector<u64> tab = scalar_table(c, w, level - 1);
   Arena ar(c);
   u64* d_tab = ar.take<u64>(tab.size());

@@ -38,12 +38,18 @@ struct he_ctx {
   u64* d_tw = nullptr;    // [L+1][4][N] 64-bit twiddles + Shoup companions
   u32* d_tw32 = nullptr;  // 32-bit copies for the narrow moduli
   double* d_twf = nullptr;  // (w, w / q) as doubles for the f64 moduli
+  // forward twiddles of the two half-ring transforms that follow a transform's
+  // first stage, [L+1][2 halves][2 (w, companion)][N/2], in the three word types
+  u64* d_twh = nullptr;
+  u32* d_twh32 = nullptr;
+  double* d_twhf = nullptr;
   u64* d_inv = nullptr;   // [2][HE_MAXM][HE_MAXM]: m_div^-1 mod q_t and Shoup components
-  Tables tb() const { return Tables{d_tw, d_tw32, d_twf}; }
+  Tables tb() const { return Tables{d_tw, d_tw32, d_twf, d_twh, d_twh32, d_twhf}; }
   int pg_set[HE_MAXM + 1] = {};  // P groups per key-switch level (0 = cost model)
   int split_streams = 1;         // DensePack rotate-and-sum in two halves on two streams
   char* ws = nullptr;
   size_t ws_bytes = 0;
+  bool ws_owned = true;  // false: the caller's buffer (he_ctx_set_workspace)
   char* fixed_scratch = nullptr;  // this device's static scratch array (he_rotate_static)
   std::map<int, u64*> keys;  // Galois element (0 = relinearisation) -> [L][2][L+1][N]
   std::string err;
@@ -225,7 +231,7 @@ struct LHmaPerm {
 template <int LOGN>
 struct LKeygen {
   static void run(he_ctx* c, u64* key, const u64* sk, const u64* a, const u64* ehat, u32 g, ConstTable pm,
-                  hipStream_t s);
+                  hipStream_t s, int pack);
 };
 template <int LOGN>
 struct LHoistUp {

@@ -47,6 +47,10 @@ struct Tables {
   const u64* tw64;
   const u32* tw32;
   const double* twf;
+  // half-ring forward tables [n_mods][2 halves][2 (w, companion)][N/2]
+  const u64* twh64;
+  const u32* twh32;
+  const double* twhf;
 };
 
 template <int LOGN, int CLS>
@@ -56,6 +60,18 @@ __device__ __forceinline__ Tw<CLS> tw_of(const Tables& tb, int mi, int which) {
   if constexpr (CLS == CLS_N32) return {tb.tw32 + o, tb.tw32 + o + N};
   else if constexpr (CLS == CLS_F64) return {tb.twf + o, tb.twf + o + N};
   else return {tb.tw64 + o, tb.tw64 + o + N};
+}
+
+// Forward twiddles of half h of a ring of 2^LOGN points after its first stage:
+// the table of an N/2-point transform (index 2^s' + k' of its stage s', block
+// k') holding the full transform's twiddles of the blocks inside half h.
+template <int LOGN, int CLS>
+__device__ __forceinline__ Tw<CLS> tw_half_of(const Tables& tb, int mi, int h) {
+  constexpr size_t NH = (size_t)1 << (LOGN - 1);
+  const size_t o = ((size_t)mi * 2 + h) * 2 * NH;
+  if constexpr (CLS == CLS_N32) return {tb.twh32 + o, tb.twh32 + o + NH};
+  else if constexpr (CLS == CLS_F64) return {tb.twhf + o, tb.twhf + o + NH};
+  else return {tb.twh64 + o, tb.twh64 + o + NH};
 }
 
 // Transform kernels are templated on the width class CLS: the host launches
@@ -658,6 +674,204 @@ k_ks_modup_ip2(const KsJob* __restrict__ jobs, int count, const u64* __restrict_
   }
 }
 
+// ---------------------------------------------------------------------------
+// Half-ring ModUp for the largest rings.  A workgroup that holds a whole
+// N = 2^14 limb has N / 16 = 1024 threads and so at most 128 registers each,
+// too few for the two 16-entry accumulators beside a radix-16 pass (it
+// spills).  Here a target's work is split over two workgroups, one per half
+// of the NTT-domain output: the transform's first stage pairs entries i and
+// i + N/2 with the same twiddle, and after it each half is an independent
+// N/2-point transform whose output lands in that half (bit-reversed order
+// keeps blocks in place).  So the workgroup of half h reads both halves of
+// the coefficient-domain digit, forms its half of the first stage while it
+// lifts (x + w y for h = 0, x - w y for h = 1), runs the N/2-point transform
+// with the half's twiddles (tw_half_of) at 8 entries per thread, and keeps
+// 8 accumulators per output polynomial.  The cost: each digit is read twice
+// (the second read from L2) and each first-stage product computed twice.
+
+// Centred lift of one source residue v (mod qs, odd) into the word of the
+// target class (as lift_limb, per value).
+template <int CLS>
+__device__ __forceinline__ word_t<CLS> lift_word(u64 v, u64 qs, const ModConst& m) {
+  const u64 half = (qs - 1) / 2;
+  if constexpr (CLS == CLS_F64) {
+    if (qs < ((u64)1 << 43)) {
+      const double x = f64_from_u64(v);
+      return v > half ? x - f64_from_u64(qs) : x;
+    }
+    return f64_from_u64(lift_centered(v, qs, m));
+  } else if constexpr (CLS == CLS_N32) {
+    if (qs < 2 * m.q) return (u32)(v > half ? v + (m.q - qs) : v);
+    return (u32)lift_centered(v, qs, m);
+  } else {
+    return lift_centered(v, qs, m);
+  }
+}
+
+// Half h of the first forward stage of the lifted digit into LDS: local
+// entry k < N/2 gets x_k + w x_{k+N/2} (h = 0) or x_k - w x_{k+N/2} (h = 1),
+// x the centred lift of the source row (packed 32-bit words when qs is
+// narrow) and w = tw[1].  All loads are issued before any is used.
+template <int LOGN, int CLS, int E>
+__device__ __forceinline__ void lift_half(u64* lds, const u64* __restrict__ src, u64 qs, const ModConst& m, int h,
+                                          word_t<CLS> w1, word_t<CLS> w1sh, int tid) {
+  typedef word_t<CLS> W;
+  typedef Arith<CLS> A;
+  constexpr int NH = 1 << (LOGN - 1);
+  constexpr int T = NH / E;
+  const MV<CLS> q = mview<CLS>(m);
+  const int i0 = lds_idx(tid);
+  u64 x[E], y[E];
+  if (qs < NARROW_LIMIT) {
+    const u32* s32 = reinterpret_cast<const u32*>(src);
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      x[r] = s32[tid + r * T];
+      y[r] = s32[NH + tid + r * T];
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      x[r] = src[tid + r * T];
+      y[r] = src[NH + tid + r * T];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const W a = A::fwd_x(lift_word<CLS>(x[r], qs, m), q);
+    const W b = A::mulc(lift_word<CLS>(y[r], qs, m), w1, w1sh, q);
+    lds_putw_at<CLS>(lds, lds_step(i0, r, T), h ? A::sub(a, b, q) : A::add(a, b, q));
+  }
+}
+
+// NTT-domain limb src through the Galois permutation, half h into LDS:
+// lds[k] = src[galois_src(h N/2 + k, g)] for k < N/2.  The permutation maps a
+// half onto one half (the half of 2 brv(i) + 1 mod 4, which a factor g = 1
+// mod 4 keeps and g = 3 mod 4 swaps), so the workgroup reads that source
+// half coalesced and scatters it into LDS.
+template <int LOGN, int CLS, int E>
+__device__ __forceinline__ void load_half_perm(u64* lds, const u64* __restrict__ src, u32 ginv, bool packed, int h) {
+  constexpr int NH = 1 << (LOGN - 1);
+  constexpr int T = NH / E;
+  const int sh = h ^ (int)((ginv >> 1) & 1u);  // source half
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int idx = sh * NH + (int)threadIdx.x + r * T;
+    const u64 v = ld_res(src, idx, packed);
+    const int dst = ((ginv == 1u) ? idx : galois_src<LOGN>(idx, ginv)) - h * NH;
+    lds_put<CLS>(lds, dst, v);
+  }
+}
+
+// ModUp + inner product of half h of one target (as modup_ip_body, which it
+// mirrors entry for entry): output entries h N/2 + k, k < N/2, of u row `row`.
+template <int LOGN, int CLS>
+__device__ __forceinline__ void modup_ip_half_body(u64* lds, const u64* __restrict__ dcoef, const KsJob& jb, size_t b,
+                                                   u64* __restrict__ u, int lmax, int urows, int big_l, int t, int mi,
+                                                   int j0, int j1, int row, int h, const Mods& mods,
+                                                   const Tables& tb) {
+  typedef std::conditional_t<CLS == CLS_N32, u64, word_t<CLS>> A;
+  constexpr int E = 8;
+  constexpr int N = 1 << LOGN;
+  constexpr int NH = N / 2;
+  constexpr int T = NH / E;
+  const ModConst m = mods.m[mi];
+  const u64* key = jb.key;
+  const Tw<CLS> tw0 = tw_of<LOGN, CLS>(tb, mi, 0);
+  const word_t<CLS> w1 = tw0.w[1];
+  const word_t<CLS> w1sh = CLS == CLS_F64 ? word_t<CLS>(0) : tw0.sh[1];
+  const Tw<CLS> twh = tw_half_of<LOGN, CLS>(tb, mi, h);
+  const size_t hoff = (size_t)h * NH;
+  A acc0[E], acc1[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) acc0[r] = acc1[r] = 0;
+  for (int j = j0; j < j1; ++j) {
+    if (j == t) {
+      load_half_perm<LOGN, CLS, E>(lds, jb.d + (size_t)j * N, jb.ginv, (jb.flags & JOB_IN_PACKED) != 0, h);
+      __syncthreads();
+    } else {
+      lift_half<LOGN, CLS, E>(lds, dcoef + (b * lmax + j) * N, mods.m[j].q, m, h, w1, w1sh, opaque_tid());
+      ntt_fwd_lds<LOGN - 1, CLS, E>(lds, twh, mview<CLS>(m), opaque_tid());
+    }
+    const u64* kb = key + (((size_t)j * 2 + 0) * (big_l + 1) + mi) * N + hoff;
+    const u64* ka = key + (((size_t)j * 2 + 1) * (big_l + 1) + mi) * N + hoff;
+    const int tid = opaque_tid();
+    const int i0 = lds_idx(tid);
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int i = tid + r * T;
+      const int li = lds_step(i0, r, T);
+      if constexpr (CLS == CLS_N32) {
+        const u32 dv = (u32)to_canon<CLS>(lds_getw_at<CLS>(lds, li), m);
+        // narrow key rows are packed 32-bit residues (the half starts at word N/2)
+        acc0[r] += (u64)dv * reinterpret_cast<const u32*>(kb - hoff)[hoff + i];
+        acc1[r] += (u64)dv * reinterpret_cast<const u32*>(ka - hoff)[hoff + i];
+      } else if constexpr (CLS == CLS_F64) {
+        const double dv = lds_getw_at<CLS>(lds, li);
+        acc0[r] += f64_mulmod(dv, f64_from_u64(kb[i]), m.qd, m.qinv);
+        acc1[r] += f64_mulmod(dv, f64_from_u64(ka[i]), m.qd, m.qinv);
+      } else {
+        const u64 dv = lds_getw_at<CLS>(lds, li);
+        acc0[r] = add_mod(acc0[r], mul_mod_t<false>(dv, kb[i], m), m.q);
+        acc1[r] = add_mod(acc1[r], mul_mod_t<false>(dv, ka[i], m), m.q);
+      }
+    }
+    __syncthreads();
+  }
+  u64* u0 = u + ((b * 2 + 0) * urows + row) * N;
+  u64* u1 = u + ((b * 2 + 1) * urows + row) * N;
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int i = (int)hoff + (int)threadIdx.x + r * T;
+    if constexpr (CLS == CLS_N32) {  // packed row
+      reinterpret_cast<u32*>(u0)[i] = (u32)reduce64(acc0[r], m);
+      reinterpret_cast<u32*>(u1)[i] = (u32)reduce64(acc1[r], m);
+    } else if constexpr (CLS == CLS_F64) {
+      u0[i] = to_canon<CLS>(acc0[r], m);
+      u1[i] = to_canon<CLS>(acc1[r], m);
+    } else {
+      u0[i] = acc0[r];
+      u1[i] = acc1[r];
+    }
+  }
+}
+
+// Rings from 2^HALF_MODUP_MIN_LOGN up run ModUp in halves.
+constexpr int HALF_MODUP_MIN_LOGN = 14;
+template <int LOGN>
+constexpr int modup_half_threads() {
+  return (1 << (LOGN - 1)) / 8;
+}
+
+// grid xcd_grid(2 (Lmax + pg), count): workgroup (job b, 2 x + h): target x
+// as in k_ks_modup_ip2 (P groups first), half h.  Each workgroup runs the
+// body of its target's class (CA or CB; CA == CB for a one-class ring).  The
+// P limb's coefficient-domain copy is always left to k_intt_last.
+template <int LOGN, int CA, int CB>
+__global__ void __launch_bounds__(modup_half_threads<LOGN>())
+k_ks_modup_half(const KsJob* __restrict__ jobs, int count, const u64* __restrict__ dcoef, u64* __restrict__ u,
+                int lmax, int pg, int big_l, Mods mods, Tables tb) {
+  constexpr int LW = lds_words<LOGN - 1, CA>() > lds_words<LOGN - 1, CB>() ? lds_words<LOGN - 1, CA>()
+                                                                            : lds_words<LOGN - 1, CB>();
+  __shared__ u64 lds[LW];
+  const XcdSlot sl = xcd_slot(2 * (lmax + pg));
+  if (sl.job >= count) return;
+  const size_t b = sl.job;
+  const KsJob jb = jobs[b];
+  if (jb.key == nullptr) return;
+  ModupTarget o;
+  if (!modup_target(jb, sl.sub >> 1, lmax, pg, big_l, o)) return;
+  const int h = sl.sub & 1;
+  const int cls = (int)mods.m[o.mi].cls;
+  if (cls == CA)
+    modup_ip_half_body<LOGN, CA>(lds, dcoef, jb, b, u, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row, h, mods,
+                                 tb);
+  else if constexpr (CB != CA)
+    if (cls == CB)
+      modup_ip_half_body<LOGN, CB>(lds, dcoef, jb, b, u, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row, h,
+                                   mods, tb);
+}
+
 enum { MODE_P = 0, MODE_LAST = 1 };
 
 // Coefficient-domain copy of the P limb of u: the sum of its group partials
@@ -1162,9 +1376,11 @@ k_hma_perm(u64* __restrict__ acc, const u64* __restrict__ cts, int K, const u64*
 // Switching key rows: for digit j (blockIdx.z) and modulus t (blockIdx.y):
 // b = e_hat - a*s + [t == j] (P mod q_t) * s', with s' = sigma_g(s) (g odd)
 // or s^2 (g == 0).  ehat = NTT(e_j mod m_t) = [L][L+1][N] precomputed.
+// With `pack`, rows of narrow moduli are written in the library's stored
+// form (N 32-bit words), else every row as canonical 64-bit residues.
 template <int LOGN>
 __global__ void k_keygen(u64* key, const u64* s, const u64* a, const u64* ehat, u32 g, int big_l,
-                         ConstTable p_mod, Mods mods) {
+                         ConstTable p_mod, Mods mods, int pack) {
   constexpr int N = 1 << LOGN;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int t = blockIdx.y;
@@ -1182,7 +1398,7 @@ __global__ void k_keygen(u64* key, const u64* s, const u64* a, const u64* ehat, 
   }
   u64* kb = key + (((size_t)j * 2 + 0) * (big_l + 1) + t) * N;
   u64* ka = key + (((size_t)j * 2 + 1) * (big_l + 1) + t) * N;
-  if (m.narrow) {  // packed 32-bit residues
+  if (pack && m.narrow) {  // packed 32-bit residues
     reinterpret_cast<u32*>(kb)[i] = (u32)b;
     reinterpret_cast<u32*>(ka)[i] = (u32)av;
   } else {

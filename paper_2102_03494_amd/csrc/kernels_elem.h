@@ -47,6 +47,24 @@ __global__ void k_make_chain_jobs(KsJob* jobs, int count, u64* base, size_t stri
   jobs[(size_t)j * count + b] = jb;
 }
 
+// Switching keys made by a client, [L][2][L+1][N] canonical 64-bit residues
+// per key, into the library's stored form (rows of narrow moduli packed as N
+// 32-bit words at the start of the row); residues not below their modulus
+// set *bad.  grid (N / 256, L + 1, 2 L); src and dst do not overlap.
+__global__ void k_key_pack(u64* __restrict__ dst, const u64* __restrict__ src, int big_l, int n, Mods mods,
+                           int* bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = blockIdx.y;
+  const size_t row = ((size_t)blockIdx.z * (big_l + 1) + t) * n;
+  const ModConst m = mods.m[t];
+  const u64 v = src[row + i];
+  if (v >= m.q) atomicOr(bad, 1);
+  if (m.narrow)
+    reinterpret_cast<u32*>(dst + row)[i] = (u32)v;
+  else
+    dst[row + i] = v;
+}
+
 // CP -> DP combine, summing step: out[m] = sum_{o in block m} rot[o], block
 // m = [m B, min(O_c, (m+1) B)); grid (N / 256, level, n_dense).
 __global__ void k_block_sum(u64* __restrict__ out, const u64* __restrict__ rot, int o_c, int per_dense, int n_dense,

@@ -29,9 +29,12 @@ template <int LOGN>
 void LKsCore<LOGN>::run(he_ctx* c, const KsJob* jobs, int count, int lmax, int pg, u64* dcoef, u64* u, u64* rc,
                   hipStream_t s, int pk, bool digits_done) {
   constexpr int T = NttGeom<LOGN>::T;
+  const int n_cls = (int)c->has_cls[0] + (int)c->has_cls[1] + (int)c->has_cls[2];
+  // rings run in halves (HALF_MODUP_MIN_LOGN) leave the P limb to k_intt_last
+  const bool halves = LOGN >= HALF_MODUP_MIN_LOGN && n_cls <= 2;
   // with one P group, ModUp's P workgroups also write the coefficient-domain
   // P limb (rc), and no separate INTT launch is needed
-  u64* rc1 = pg == 1 ? rc : nullptr;
+  u64* rc1 = (pg == 1 && !halves) ? rc : nullptr;
   {
     Prof pr(c, "ks_digits", s);
     if (digits_done) {
@@ -46,8 +49,30 @@ void LKsCore<LOGN>::run(he_ctx* c, const KsJob* jobs, int count, int lmax, int p
   const unsigned grid = xcd_grid(lmax + pg, count);
   constexpr int TM = modup_threads<LOGN>();  // ModUp workgroup size
   static const char* names[3] = {"ks_modup_ip", "ks_modup_ip_f64", "ks_modup_ip_wide"};
-  const int n_cls = (int)c->has_cls[0] + (int)c->has_cls[1] + (int)c->has_cls[2];
-  if (n_cls == 2) {  // one launch, each workgroup in its target's class
+  if constexpr (LOGN >= HALF_MODUP_MIN_LOGN) {
+    if (halves) {  // one launch, two workgroups (halves) per target
+      Prof stage(c, "ks_modup_stage", s);
+      const unsigned hgrid = xcd_grid(2 * (lmax + pg), count);
+      constexpr int TH = modup_half_threads<LOGN>();
+#define HE_HALF(A, B) \
+  k_ks_modup_half<LOGN, A, B><<<hgrid, TH, 0, s>>>(jobs, count, dcoef, u, lmax, pg, c->big_l, c->mods, c->tb())
+      if (n_cls == 1) {
+        if (c->has_cls[CLS_N32]) HE_HALF(CLS_N32, CLS_N32);
+        else if (c->has_cls[CLS_F64]) HE_HALF(CLS_F64, CLS_F64);
+        else HE_HALF(CLS_U64, CLS_U64);
+      } else if (!c->has_cls[CLS_U64]) {
+        HE_HALF(CLS_N32, CLS_F64);
+      } else if (!c->has_cls[CLS_F64]) {
+        HE_HALF(CLS_N32, CLS_U64);
+      } else {
+        HE_HALF(CLS_F64, CLS_U64);
+      }
+#undef HE_HALF
+    }
+  }
+  if (halves) {
+    // ModUp done above
+  } else if (n_cls == 2) {  // one launch, each workgroup in its target's class
     Prof stage(c, "ks_modup_stage", s);
     if (!c->has_cls[CLS_U64])
       k_ks_modup_ip2<LOGN, CLS_N32, CLS_F64><<<grid, TM, 0, s>>>(jobs, count, dcoef, u, rc1, lmax, pg, c->big_l,
@@ -157,10 +182,10 @@ void LHmaPerm<LOGN>::run(he_ctx* c, u64* acc, const u64* cts, int K, const u64* 
 
 template <int LOGN>
 void LKeygen<LOGN>::run(he_ctx* c, u64* key, const u64* sk, const u64* a, const u64* ehat, u32 g, ConstTable pm,
-                  hipStream_t s) {
+                  hipStream_t s, int pack) {
   constexpr int N = 1 << LOGN;
   k_keygen<LOGN><<<dim3(N / 256, c->big_l + 1, c->big_l), 256, 0, s>>>(key, sk, a, ehat, g, c->big_l, pm,
-                                                                        c->mods);
+                                                                        c->mods, pack);
 }
 
 // Hoisted rotations: digits of c1 and the lifted digits, computed once ...

@@ -211,28 +211,39 @@ class HEContext:
         self._check(self.lib.he_intt(self.h, _ptr(polys), n_polys, n_limbs, first_mod, _stream()), "he_intt")
 
     # ---- elementwise -----------------------------------------------------------
-    def add(self, out: torch.Tensor, a: torch.Tensor, b: torch.Tensor):
-        level = a.shape[-2]
-        count = a.numel() // (2 * level * self.n)
-        self._check(self.lib.he_add(self.h, _ptr(out), _ptr(a), _ptr(b), count, level, _stream()), "he_add")
+    def add(self, out: torch.Tensor, a: Ct, b: Ct) -> Ct:
+        level = a.level
+        count = a.data.numel() // (2 * level * self.n)
+        self._check(self.lib.he_add(self.h, _ptr(out), _ptr(a.data), _ptr(b.data), count, level, float(a.scale),
+                                    float(b.scale), _stream()), "he_add")
+        return Ct(out, a.scale)
 
-    def hma_plain(self, acc: torch.Tensor, cts: torch.Tensor, pts: torch.Tensor, pt_stride: int,
-                  galois=None, accumulate: bool = False):
+    def hma_plain(self, acc: torch.Tensor, cts: Ct, pts: torch.Tensor, pt_stride: int, pt_scale: float,
+                  galois=None, acc_scale: float | None = None) -> Ct:
+        """acc (+)= sum_i cts[i] * sigma_{g_i}(pts[i * pt_stride]); accumulates when
+        acc_scale (the accumulator's scale) is given."""
         level = acc.shape[-2]
-        k = cts.numel() // (2 * level * self.n)
+        k = cts.data.numel() // (2 * level * self.n)
         pt_limbs = pts.shape[-2]
         gal = None
         if galois is not None:
             gal = (ctypes.c_int32 * k)(*[int(g) for g in galois])
-        self._check(self.lib.he_hma_plain(self.h, _ptr(acc), _ptr(cts), k, _ptr(pts), pt_stride, pt_limbs, gal,
-                                          level, int(accumulate), _stream()), "he_hma_plain")
+        io = ctypes.c_double(acc_scale if acc_scale is not None else 0.0)
+        self._check(self.lib.he_hma_plain(self.h, _ptr(acc), _ptr(cts.data), k, _ptr(pts), pt_stride, pt_limbs, gal,
+                                          level, int(acc_scale is not None), float(cts.scale), float(pt_scale),
+                                          ctypes.byref(io), _stream()), "he_hma_plain")
+        return Ct(acc, io.value)
 
-    def hma_scalar(self, acc: torch.Tensor, cts: torch.Tensor, weights, accumulate: bool = False):
+    def hma_scalar(self, acc: torch.Tensor, cts: Ct, weights, w_scale: float = 1.0,
+                   acc_scale: float | None = None) -> Ct:
         level = acc.shape[-2]
         k = len(weights)
         w = (ctypes.c_int64 * k)(*[int(x) for x in weights])
-        self._check(self.lib.he_hma_scalar(self.h, _ptr(acc), _ptr(cts), k, w, level, int(accumulate), _stream()),
-                    "he_hma_scalar")
+        io = ctypes.c_double(acc_scale if acc_scale is not None else 0.0)
+        self._check(self.lib.he_hma_scalar(self.h, _ptr(acc), _ptr(cts.data), k, w, level,
+                                           int(acc_scale is not None), float(cts.scale), float(w_scale),
+                                           ctypes.byref(io), _stream()), "he_hma_scalar")
+        return Ct(acc, io.value)
 
     def rescale(self, ct: Ct) -> Ct:
         level = ct.level
@@ -242,15 +253,50 @@ class HEContext:
         return Ct(out, ct.scale / self.q[level - 1])
 
     # ---- keys / client -----------------------------------------------------------
-    def keygen_switch(self, galois: int, s_ntt: torch.Tensor, a: torch.Tensor, e: torch.Tensor):
-        self._check(self.lib.he_keygen_switch(self.h, int(galois), _ptr(s_ntt), _ptr(a), _ptr(e), _stream()),
-                    "he_keygen_switch")
+    def keygen_switch(self, galois: int, s_ntt: torch.Tensor, a: torch.Tensor, e: torch.Tensor,
+                      out: torch.Tensor | None = None) -> torch.Tensor:
+        """Client side: the switching key of `galois` (0: relinearisation) in the
+        exchange layout [L][2][L+1][N]; nothing is stored in the context."""
+        if out is None:
+            out = torch.empty((self.L, 2, self.L + 1, self.n), dtype=torch.int64, device="cuda")
+        self._check(self.lib.he_keygen_switch(self.h, int(galois), _ptr(s_ntt), _ptr(a), _ptr(e), _ptr(out),
+                                              _stream()), "he_keygen_switch")
+        return out
+
+    def upload_keys(self, galois, keys):
+        """Server side: store client-made keys ([n][L][2][L+1][N], a device
+        tensor or a host uint64 array) for the Galois elements `galois`."""
+        galois = [int(g) for g in galois]
+        arr = (ctypes.c_int32 * len(galois))(*galois)
+        if isinstance(keys, torch.Tensor):
+            keys = keys.contiguous()
+            self._check(self.lib.he_keys_upload(self.h, arr, len(galois), _ptr(keys), 1, _stream()),
+                        "he_keys_upload")
+        else:
+            host = np.ascontiguousarray(keys, dtype=np.uint64)
+            self._check(self.lib.he_keys_upload(self.h, arr, len(galois), host.ctypes.data_as(ctypes.c_void_p), 0,
+                                                _stream()), "he_keys_upload")
 
     def has_key(self, galois: int) -> bool:
         return bool(self.lib.he_has_key(self.h, int(galois)))
 
-    def drop_keys(self):
-        self._check(self.lib.he_drop_keys(self.h), "he_drop_keys")
+    def drop_keys(self, galois=None):
+        """Free the keys of `galois` (None: all of them)."""
+        if galois is None:
+            self._check(self.lib.he_keys_free(self.h, None, 0), "he_keys_free")
+        else:
+            galois = [int(g) for g in galois]
+            arr = (ctypes.c_int32 * len(galois))(*galois)
+            self._check(self.lib.he_keys_free(self.h, arr, len(galois)), "he_keys_free")
+
+    def set_workspace(self, buf: torch.Tensor | None):
+        """Use a caller-owned device buffer as the workspace (None detaches it);
+        the caller keeps `buf` alive while the context uses it."""
+        if buf is None:
+            self._check(self.lib.he_ctx_set_workspace(self.h, None, 0), "he_ctx_set_workspace")
+        else:
+            self._check(self.lib.he_ctx_set_workspace(self.h, _ptr(buf), buf.numel() * buf.element_size()),
+                        "he_ctx_set_workspace")
 
     def from_signed(self, coeffs: torch.Tensor, n_limbs: int, first_mod: int = 0) -> torch.Tensor:
         out = torch.empty((n_limbs, self.n), dtype=torch.int64, device="cuda")
@@ -410,14 +456,16 @@ class HEContext:
                                               _stream()), "he_gather_onehot")
         return Ct(out, y.scale * mask_scale)
 
-    def conv_convpack(self, x: Ct, w: np.ndarray, w_scale: float) -> Ct:
+    def conv_convpack(self, x: Ct, w: np.ndarray, target_scale: float) -> Ct:
         level = x.level
         k, o_c = w.shape
         wf = np.ascontiguousarray(np.asarray(w, dtype=np.float64))
         out = torch.empty((o_c, 2, level - 1, self.n), dtype=torch.int64, device="cuda")
+        out_scale = ctypes.c_double(0.0)
         self._check(self.lib.he_conv_convpack(self.h, _ptr(x.data), k, level, wf.ctypes.data_as(_lib.DP), o_c,
-                                              float(w_scale), _ptr(out), _stream()), "he_conv_convpack")
-        return Ct(out, x.scale * w_scale / self.q[level - 1])
+                                              float(x.scale), float(target_scale), _ptr(out),
+                                              ctypes.byref(out_scale), _stream()), "he_conv_convpack")
+        return Ct(out, out_scale.value)
 
     def ffconv_layer(self, x: Ct, desc: HeConvDesc, w1_filt: torch.Tensor, w1_pt_scale: float,
                      mask: torch.Tensor, mask_scale: float, w2: np.ndarray, k_bits: int, square: bool,

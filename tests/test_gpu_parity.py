@@ -82,7 +82,18 @@ def test_ntt_intt_bit_exact(n, q_bits, p_bits):
     assert np.array_equal(_host(d), a)
 
 
-def _small_setup(rotations=(), relin=False, n=1024):
+# a second small chain in the f64 width class (40-bit ciphertext primes) with a
+# wide-class (60-bit) P, so the 64-bit branches of every kernel are compared
+# bit for bit too
+SMALL40 = dict(n=2048, q_bits=(40, 40, 40, 40), p_bits=60, scale=2.0**30)
+
+
+def _small_setup(rotations=(), relin=False, n=1024, chain=None):
+    if chain is not None:
+        p = P.Params(chain["n"], chain["q_bits"], chain["p_bits"], chain["scale"])
+        octx = Wk.make_context(p, W, rotations=rotations, relin=relin)
+        gctx = _ctx(p)
+        return p, octx, gctx, _client(gctx, rotations, relin)
     p = P.Params(n, SMALL["q_bits"], SMALL["p_bits"], 2.0**25)
     octx = Wk.make_context(p, W, rotations=rotations, relin=relin)
     gctx = _ctx(p)
@@ -126,6 +137,104 @@ def test_rotate_batch_bit_exact():
     d = _dev(low)
     gctx.rotate(he.Ct(d, p.scale), 3, out=d)
     assert np.array_equal(_host(d), S.rotate(p, octx, S.Ciphertext(low, p.scale), 3).c)
+
+
+@pytest.mark.parametrize("q_bits,p_bits", [
+    ((40,) * 6, 60),        # f64 primes + wide P: the two-class half-ring ModUp
+    ((40, 40, 40), 41),     # one class (f64)
+    ((30, 30, 30), 40),     # narrow primes + f64 P
+    ((30, 30), 60),         # narrow primes + wide P
+])
+def test_rotate_n16384_half_ring_modup(q_bits, p_bits):
+    """At N = 16384 ModUp runs as two half-ring workgroups per target (first
+    transform stage fused into the lift); every class pair and every P
+    grouping gives the oracle's bits."""
+    n = 16384
+    p = P.Params(n, q_bits, p_bits, 2.0**30)
+    steps = (1, -3)
+    octx = Wk.make_context(p, W, rotations=steps)
+    gctx = _ctx(p, ws=1 << 27)
+    _client(gctx, steps)
+    he = _he()
+    level = len(q_bits)
+    cts = np.stack([np.stack([np.stack([synth.rng(W, "test", 900 + i, c, t).integers(0, p.q[t], n, dtype=np.uint64)
+                                        for t in range(level)]) for c in range(2)]) for i in range(2)])
+    want = {k: S.rotate(p, octx, S.Ciphertext(cts, 1.0), k).c for k in steps}
+    for pg in range(1, min(level, 4) + 1):
+        gctx.set_tuning("p_groups", level, pg)
+        for k in steps:
+            got = _host(gctx.rotate(he.Ct(_dev(cts), 1.0), k).data)
+            assert np.array_equal(got, want[k]), (pg, k)
+    # a lower level of the same chain (ragged jobs share the launch geometry)
+    low = np.ascontiguousarray(cts[:, :, :level - 1])
+    got = _host(gctx.rotate(he.Ct(_dev(low), 1.0), 1).data)
+    assert np.array_equal(got, S.rotate(p, octx, S.Ciphertext(low, 1.0), 1).c)
+
+
+def test_uploaded_oracle_keys_rotate_bit_exact():
+    """The server context gets only keys: the oracle makes them on the CPU (the
+    client), they are uploaded from host memory in the exchange layout, and
+    rotations and the square then match the oracle bit for bit.  The GPU
+    client helper makes the same key bits, and bad uploads leave the store
+    unchanged."""
+    steps = (1, -3, 17)
+    p, octx, _, _ = _small_setup(rotations=steps, relin=True)
+    he = _he()
+    srv = _ctx(p)  # no secret ever enters this context
+    gal = [S.galois_for_rotation(k, p.n) for k in steps]
+    keys = np.stack([np.stack([octx.rot_keys[g].b, octx.rot_keys[g].a], axis=1) for g in gal])
+    srv.upload_keys(gal, keys)
+    rk = octx.relin_key
+    srv.upload_keys([0], np.stack([rk.b, rk.a], axis=1)[None])
+    batch = _enc_batch(octx, p, 3)
+    for k in steps:
+        got = _host(srv.rotate(he.Ct(_dev(batch), p.scale), k).data)
+        assert np.array_equal(got, S.rotate(p, octx, S.Ciphertext(batch, p.scale), k).c), k
+    got = _host(srv.square(he.Ct(_dev(batch[:, :, :3].copy()), p.scale)).data)
+    assert np.array_equal(got, S.square(p, octx, S.Ciphertext(batch[:, :, :3].copy(), p.scale)).c)
+    # the GPU client helper writes the same bits in the exchange layout
+    from paper_2102_03494_amd.client import Client
+    cl = Client(srv, W)
+    assert np.array_equal(_host(cl.switch_key(gal[1])), keys[1])
+    # a residue not below its modulus is refused and the store keeps the old key
+    bad = keys[:1].copy()
+    bad[0, 0, 0, 0, 5] = p.q[0]
+    with pytest.raises(he.HEError, match="code -1"):
+        srv.upload_keys(gal[:1], bad)
+    with pytest.raises(he.HEError, match="code -1"):
+        srv.upload_keys([gal[0], gal[0]], np.concatenate([keys[:1], keys[:1]]))
+    got = _host(srv.rotate(he.Ct(_dev(batch), p.scale), steps[0]).data)
+    assert np.array_equal(got, S.rotate(p, octx, S.Ciphertext(batch, p.scale), steps[0]).c)
+    # freeing: a missing key frees nothing; then the rotation reports the missing key
+    with pytest.raises(he.HEError, match="code -4"):
+        srv.drop_keys([gal[0], 12345 | 1])
+    assert srv.has_key(gal[0])
+    srv.drop_keys([gal[0]])
+    assert not srv.has_key(gal[0]) and srv.has_key(gal[1])
+    with pytest.raises(he.HEError, match="code -4"):
+        srv.rotate(he.Ct(_dev(batch), p.scale), steps[0])
+
+
+def test_caller_owned_workspace():
+    """A context given the caller's device buffer as its workspace computes the
+    same bits; too small a buffer gives HE_ENOMEM, not an allocation."""
+    steps = (1, 2)
+    p, octx, gctx, cl = _small_setup(rotations=steps)
+    he = _he()
+    srv = he.HEContext(p.n, p.q_bits, p.p_bits)
+    cl.gen_rotation_keys(steps, server=srv)
+    batch = _enc_batch(octx, p, 4)
+    want = _host(gctx.rotate(he.Ct(_dev(batch), p.scale), 2).data)
+    tiny = torch.empty(16, dtype=torch.int64, device="cuda")
+    srv.set_workspace(tiny)
+    with pytest.raises(he.HEError, match="code -5"):
+        srv.rotate(he.Ct(_dev(batch), p.scale), 2)
+    buf = torch.empty((8 << 20) // 8, dtype=torch.int64, device="cuda")
+    srv.set_workspace(buf)
+    assert np.array_equal(_host(srv.rotate(he.Ct(_dev(batch), p.scale), 2).data), want)
+    srv.set_workspace(None)
+    srv.reserve(8 << 20)
+    assert np.array_equal(_host(srv.rotate(he.Ct(_dev(batch), p.scale), 2).data), want)
 
 
 def test_p_groups_do_not_change_bits():
@@ -192,8 +301,13 @@ def test_rotsum_rescale_add_bit_exact():
     r = gctx.rescale(he.Ct(d, p.scale))
     assert np.array_equal(_host(r.data), S.rescale(p, want).c)
     out = torch.empty_like(d)
-    gctx.add(out, d, _dev(batch))
+    gctx.add(out, he.Ct(d, p.scale), he.Ct(_dev(batch), p.scale))
     assert np.array_equal(_host(out), S.add(p, want, S.Ciphertext(batch, p.scale)).c)
+    # operands at different scales are refused before any launch, output untouched
+    before = out.clone()
+    with pytest.raises(he.HEError, match="code -3"):
+        gctx.add(out, he.Ct(d, p.scale), he.Ct(_dev(batch), p.scale * 2))
+    assert torch.equal(out, before)
 
 
 def test_square_bit_exact():
@@ -203,26 +317,39 @@ def test_square_bit_exact():
     assert np.array_equal(got, S.square(p, octx, S.Ciphertext(batch, p.scale)).c)
 
 
-def test_hma_plain_and_scalar_bit_exact():
-    p, octx, gctx, cl = _small_setup()
+@pytest.mark.parametrize("chain", [None, SMALL40], ids=["30bit", "40bit"])
+def test_hma_plain_and_scalar_bit_exact(chain):
+    p, octx, gctx, cl = _small_setup(chain=chain)
     batch = _enc_batch(octx, p, 4, level=3)
     pts = np.stack([E.encode(synth.message(W, p.slots, index=40 + i), p, 4, 2.0**20) for i in range(4)])
     gal = [1, 5, 25, 2 * p.n - 5]
     acc = torch.empty((2, 3, p.n), dtype=torch.int64, device="cuda")
-    gctx.hma_plain(acc, _dev(batch), _dev(pts), 1, galois=gal)
+    he = _he()
+    cts = he.Ct(_dev(batch), p.scale)
+    got = gctx.hma_plain(acc, cts, _dev(pts), 1, 2.0**20, galois=gal)
+    assert got.scale == p.scale * 2.0**20
     want = None
     from oracle.ring import automorph_ntt
     for i in range(4):
-        prod = S.mul_plain(p, S.Ciphertext(batch[i], 1.0), automorph_ntt(pts[i], gal[i]), 1.0)
+        prod = S.mul_plain(p, S.Ciphertext(batch[i], p.scale), automorph_ntt(pts[i], gal[i]), 2.0**20)
         want = prod if want is None else S.add(p, want, prod)
     assert np.array_equal(_host(acc), want.c)
+    # accumulating into it: a second MulPC of the same scale adds, another scale is refused
+    got2 = gctx.hma_plain(acc, he.Ct(cts.data[:1].contiguous(), p.scale), _dev(pts[:1]), 0, 2.0**20,
+                          acc_scale=got.scale)
+    want = S.add(p, want, S.mul_plain(p, S.Ciphertext(batch[0], p.scale), pts[0], 2.0**20))
+    assert np.array_equal(_host(acc), want.c) and got2.scale == want.scale
+    with pytest.raises(he.HEError, match="code -3"):
+        gctx.hma_plain(acc, cts, _dev(pts), 1, 2.0**21, acc_scale=got.scale)
     w = [3, -7, 1 << 40, -(1 << 35) + 11]
-    gctx.hma_scalar(acc, _dev(batch), w)
+    got = gctx.hma_scalar(acc, cts, w, w_scale=1.0)
     want = None
     for i in range(4):
-        prod = S.mul_int(p, S.Ciphertext(batch[i], 1.0), w[i])
+        prod = S.mul_int(p, S.Ciphertext(batch[i], p.scale), w[i])
         want = prod if want is None else S.add(p, want, prod)
-    assert np.array_equal(_host(acc), want.c)
+    assert np.array_equal(_host(acc), want.c) and got.scale == p.scale
+    with pytest.raises(he.HEError, match="code -3"):
+        gctx.hma_scalar(acc, cts, w, w_scale=4.0, acc_scale=p.scale)
 
 
 def _densepack_case(p, octx, gctx, geom, o_c, level, outputs=None, std=0.1, wid=7):
@@ -267,15 +394,24 @@ def test_convpack_bit_exact():
     batch = _enc_batch(octx, p, 3, level=3)
     wts = synth.weights(W, 11, (3, 4), 0.2)
     want, _ = C.convpack(p, S.Ciphertext(batch, p.scale), wts, p.scale)
-    dw = p.q[2] * p.scale / p.scale
-    got = gctx.conv_convpack(_he().Ct(_dev(batch), p.scale), wts, dw)
+    got = gctx.conv_convpack(_he().Ct(_dev(batch), p.scale), wts, p.scale)
     assert np.array_equal(_host(got.data), want.c)
     assert got.scale == want.scale
+    cnt = gctx.last_counts()
+    assert cnt["mulpc"] == 3 * 4 and cnt["addcc"] == 4 * 2  # Table II: O_c K MulPC, O_c (K-1) AddCC
+    # an input scale that cannot reach the target at this level is refused
+    with pytest.raises(_he().HEError, match="code -3"):
+        gctx.conv_convpack(_he().Ct(_dev(batch), p.q[2] * p.scale * 4), wts, p.scale)
 
 
-def test_ffconv_layer_bit_exact_small():
-    """Whole FFConv layer (W1 DensePack, gather, 1x1 ConvPack, x^2) on a small ring."""
-    p, octx, gctx, cl = _small_setup(rotations=[1 << j for j in range(9)], relin=True)
+@pytest.mark.parametrize("chain", [None, SMALL40], ids=["30bit", "40bit"])
+def test_ffconv_layer_bit_exact_small(chain):
+    """Whole FFConv layer (W1 DensePack, gather, 1x1 ConvPack, x^2) on a small
+    ring: 30-bit primes (narrow class) and 40-bit primes with a 60-bit P (f64
+    and wide classes: the 64-bit branches of the gather, the scalar MAC, the
+    tensor square, relinearisation and ModDown)."""
+    r_steps = 9 if chain is None else int(math.log2(chain["n"] // 2))
+    p, octx, gctx, cl = _small_setup(rotations=[1 << j for j in range(r_steps)], relin=True, chain=chain)
     geom = C.ConvGeom(7, 7, 2, 3, 2, 1)
     x = synth.image(W, (7, 7, 2))
     w1 = synth.weights(W, 21, (3, 3, 2, 2), 0.3)
@@ -291,7 +427,7 @@ def test_ffconv_layer_bit_exact_small():
     z, _ = C.gather_convpack(p, y, geom.spatial, w2, 12, mask, ms)
     want, _ = C.square_rescale(p, octx, z)
     he = _he()
-    desc = he.HEContext.conv_desc(7, 7, 2, 3, 2, 1, 2, 9)
+    desc = he.HEContext.conv_desc(7, 7, 2, 3, 2, 1, 2, r_steps)
     got = gctx.ffconv_layer(he.Ct(_dev(ct.c[None]), p.scale), desc, _dev(bf), pts, _dev(mask), ms, w2, 12, True)
     assert np.array_equal(_host(got.data), want.c)
     assert abs(got.scale - want.scale) <= 1e-12 * want.scale
