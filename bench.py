@@ -362,6 +362,136 @@ def ragged_section(torch, reps: int):
     return res
 
 
+def cifar_section(torch, steps: int, plain: bool, digests_path: str):
+    """The CIFAR-shaped layer: a 32x32x3 image (U[0,1)) under DensePack in one
+    ciphertext at N = 16384 (6 x 40-bit primes + 60-bit P, scale 2^30).
+      * FFConv: 3x3 pad 1 conv 3 -> r = 8 under DensePack (8192 dot products,
+        13 rotate-and-add steps each: 106,496 rotations), the DP->CP gather and
+        a 1x1 conv 8 -> 64 under ConvPack (12-bit integer weights), rescale;
+      * plain comparator: the 3x3 pad 1 conv 3 -> 64 with W = W1 W2 under
+        DensePack (65,536 dot products: 851,968 rotations), rescale.
+    Weights N(0, 0.05^2).  Reports latency, rotations/s, HMA/s, decrypted max
+    error against FP64, the ModUp stage's ALU roofline, and a bit-for-bit
+    check of 72 W1 outputs (every channel x border class) against digests the
+    oracle wrote offline for the same seeded inputs."""
+    import hashlib
+
+    import numpy as np
+
+    import synth
+    from paper_2102_03494_amd import layers as Ly
+    from paper_2102_03494_amd.client import Client
+    from paper_2102_03494_amd.he import HEContext
+
+    wl = "cifar_n16384"
+    n, level, scale = 16384, 6, 2.0**30
+    ctx = HEContext(n, (40,) * level, 60)
+    cl = Client(ctx, wl)
+    r_steps = int(math.log2(n // 2))
+    cl.gen_rotation_keys([1 << j for j in range(r_steps)])
+    geom = Ly.Geometry(32, 32, 3, 3, 1, 1)
+    x = synth.image(wl, (32, 32, 3))
+    w1 = synth.weights(wl, 1, (3, 3, 3, 8), 0.05)
+    w2 = synth.weights(wl, 2, (8, 64), 0.05)
+    ct = cl.encrypt(Ly.densepack_layout(x, geom, n // 2)[0], level, scale, index=0)
+    desc = ctx.conv_desc(32, 32, 3, 3, 1, 1, 8, r_steps)
+    pts = Ly.pt_scale_for(ctx, level, scale, scale)
+    f1 = Ly.encode_filters(cl, w1, geom, level, pts)
+    y_scale = scale * pts / ctx.q[level - 1]
+    ms = Ly.mask_scale_for(ctx, level - 1, y_scale, scale, K_BITS)
+    mask = Ly.onehot_mask(cl, level - 1, ms)
+    ctx.reserve(ctx.ffconv_workspace_need(1, level, desc, 64, False))
+    out = torch.empty((64, 2, level - 2, n), dtype=torch.int64, device="cuda")
+
+    def ffconv():
+        return ctx.ffconv_layer(ct, desc, f1, pts, mask, ms, w2, K_BITS, False, out=out)
+
+    ffconv()
+    torch.cuda.synchronize()
+    ctx.prof_select(DOMINANT)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        z = ffconv()
+    torch.cuda.synchronize()
+    t_ff = (time.perf_counter() - t0) / steps
+    dom_ms, dom_busy_ms, dom_launches = ctx.prof_read_busy()
+    ctx.prof_select(None)
+    counts_ff = ctx.last_counts()
+    print(f"# cifar ffconv: {t_ff * 1e3:.1f} ms/layer", file=sys.stderr, flush=True)
+    ref = Ly.reference_conv2d(x, w1, 1, 1) @ w2
+    err_ff = 0.0
+    for o in range(64):
+        v = cl.decrypt(z.data[o], z.scale, geom.spatial, limbs=1)
+        err_ff = max(err_ff, float(np.abs(v - ref[:, :, o].ravel()).max()))
+    pg = ctx.get_tuning("p_groups", level)
+    n_dp = 8 * geom.spatial
+    ops = r_steps * modup_ip_ops(n_dp, level, n, ctx.moduli, pg)
+    roof = {"kernel": "k_ks_modup_half<14, f64, wide>: ModUp NTTs + key inner product into the six 40-bit primes "
+                      "(f64 class) and P (wide), two half-ring workgroups per target, one launch per rotate-and-add "
+                      "step of the 8192 W1 outputs (two concurrent halves of the outputs when split_streams)",
+            "bound": "alu", "achieved": ops * steps / (dom_busy_ms * 1e-3) / 1e12 if dom_busy_ms else None,
+            "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s (VALU lane ops)",
+            "avg_launch_ms": dom_ms / max(1, dom_launches), "launches": dom_launches, "busy_ms": dom_busy_ms,
+            "algorithmic_ops_per_layer": ops, "p_groups": pg}
+    if roof["achieved"] is not None:
+        roof["frac"] = roof["achieved"] / roof["peak"]
+    # 72 W1 dot products bit for bit against the oracle's digests
+    bit = None
+    if os.path.exists(digests_path):
+        with open(digests_path) as f:
+            gold = json.load(f).get(wl)
+        if gold:
+            y = ctx.conv_densepack(ct, desc, f1, pts)
+            torch.cuda.synchronize()
+            got = [hashlib.sha256(np.ascontiguousarray(y.data[i].cpu().numpy().view(np.uint64), dtype="<u8")
+                                  .tobytes()).hexdigest() for i in gold["w1_sample"]]
+            bit = {"sampled_w1_outputs": len(got),
+                   "identical": sum(g == w for g, w in zip(got, gold["w1_sample_sha256"]))}
+            del y
+    res = {
+        "workload": "CIFAR-shaped layer 32x32x3, N=16384 (6x40-bit + 60-bit P, scale 2^30): FFConv 3x3 pad 1 "
+                    "3->8 DensePack + 1x1 8->64 ConvPack vs plain 3x3 pad 1 3->64 DensePack (W = W1 W2)",
+        "ffconv_layer_ms": t_ff * 1e3, "ffconv_rotations_per_s": counts_ff["rot"] / t_ff,
+        "ffconv_hma_per_s": (counts_ff["mulpc"] + counts_ff["scalar_mul"]) / t_ff,
+        "counts_ffconv": counts_ff, "ffconv_decrypted_max_abs_err": err_ff, "roofline": roof,
+        "w1_bit_exact_vs_oracle": bit,
+    }
+    if plain:
+        del out, z
+        torch.cuda.empty_cache()
+        wp = Ly.compose_factors(w1, w2)
+        pts_pl = Ly.pt_scale_for(ctx, level, scale, scale)
+        fp = Ly.encode_filters(cl, wp, geom, level, pts_pl)
+        descp = ctx.conv_desc(32, 32, 3, 3, 1, 1, 64, r_steps)
+        # outputs (65,536 replicated ciphertexts at level 5: 80 GiB) plus a
+        # workspace that runs the layer in chunks of about 8000 dot products
+        yp = torch.empty((64 * geom.spatial, 2, level - 1, n), dtype=torch.int64, device="cuda")
+        ctx.reserve(ctx.workspace_need(8000, level))
+        print("# cifar plain comparator: 65,536 dot products", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        zp = ctx.conv_densepack(ct, descp, fp, pts_pl, out=yp)
+        torch.cuda.synchronize()
+        t_pl = time.perf_counter() - t0
+        counts_pl = ctx.last_counts()
+        refp = Ly.reference_conv2d(x, wp, 1, 1)
+        err_pl = 0.0
+        rng = np.random.default_rng(7)
+        for idx in rng.choice(yp.shape[0], 256, replace=False):
+            o, rem = divmod(int(idx), geom.spatial)
+            i, j = divmod(rem, geom.out_w)
+            v = cl.decrypt(yp[idx], zp.scale, 1, limbs=1)
+            err_pl = max(err_pl, abs(float(v[0]) - refp[i, j, o]))
+        res.update(plain_layer_ms=t_pl * 1e3, plain_rotations_per_s=counts_pl["rot"] / t_pl,
+                   plain_hma_per_s=counts_pl["mulpc"] / t_pl, counts_plain=counts_pl,
+                   plain_decrypted_max_abs_err_256_sampled=err_pl, speedup_vs_plain=t_pl / t_ff)
+        print(f"# cifar plain: {t_pl * 1e3:.1f} ms/layer", file=sys.stderr, flush=True)
+        del yp, zp
+    del ctx, cl
+    torch.cuda.empty_cache()
+    return res
+
+
 def serving_section(window: float, cap: float):
     """The MNIST-shaped share of the serving stream (Poisson, 200 requests/s,
     70% MNIST-shaped) over a short window, served by the FFConv net and by the
@@ -419,6 +549,9 @@ def main():
     ap.add_argument("--batched-layers", type=int, default=128,
                     help="independent layers in the batched/graph section (0 = skip)")
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged 64-ciphertext batch section")
+    ap.add_argument("--no-cifar", action="store_true", help="skip the N=16384 CIFAR-shaped layer section")
+    ap.add_argument("--no-cifar-plain", action="store_true",
+                    help="skip the CIFAR-shaped plain comparator (65,536 dot products, about 80 GiB of outputs)")
     ap.add_argument("--serve-window", type=float, default=1.0,
                     help="arrival window (s) of the serving section (0 = skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -551,6 +684,13 @@ def main():
         print("# hoisted rotations at N=16384", file=sys.stderr, flush=True)
         hoisted = hoisted_section(torch, max(1, min(args.steps, 5)))
 
+    cifar = None
+    if not args.no_cifar:
+        torch.cuda.empty_cache()
+        print("# CIFAR-shaped layer at N=16384", file=sys.stderr, flush=True)
+        cifar = cifar_section(torch, max(1, min(args.steps, 3)), not args.no_cifar_plain,
+                              os.path.join(ROOT, "tests", "golden", "fullsize_digests.json"))
+
     ragged = None
     if not args.no_ragged:
         torch.cuda.empty_cache()
@@ -598,6 +738,7 @@ def main():
         "ragged_batch": ragged,
         "serving_mnist": serving,
         "hoisted_rotations": hoisted,
+        "cifar_layer": cifar,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
