@@ -342,6 +342,48 @@ def pre_square_target(params, level_after_rescale: int, scale: float) -> float:
     return math.sqrt(params.q[level_after_rescale - 1] * scale)
 
 
+def im2col_slots(x: np.ndarray, geom: ConvGeom, slots: int) -> list[np.ndarray]:
+    """Client-side plaintext Im2Col for a ConvPack input (Sec. 3.3, Eq. 1):
+    K = d^2 I_c slot vectors, vector k holding column k of the S x K matrix I
+    (the S = O_w O_h patch values at tap k = (kh d + kw) I_c + c, zero for
+    taps outside the image) in slots 0..S-1 and zeros elsewhere."""
+    from .reference import im2col
+    cols = im2col(x, geom.d, geom.stride, geom.pad)
+    s_out, k = cols.shape
+    if s_out > slots:
+        raise ValueError("S exceeds the slot count")
+    out = []
+    for j in range(k):
+        v = np.zeros(slots)
+        v[:s_out] = cols[:, j]
+        out.append(v)
+    return out
+
+
+def convpack_convpack(params, keys, cts: scheme.Ciphertext, w1: np.ndarray, w2: np.ndarray, target_scale: float,
+                      square: bool = False, counts: Counts | None = None):
+    """FFConv with both factors under ConvPack (Sec. 4.2.2 "ConvPack for W1",
+    Fig. 5; CP-HI2C-CP with d = 1 in Table III).
+
+    cts: the K Im2Col ciphertexts of the input (im2col_slots).  W1 (K x O'_c,
+    the d x d low-rank filters flattened as Eq. 1) under ConvPack gives O'_c
+    channel ciphertexts, each holding its S outputs in slots 0..S-1; for the
+    1 x 1 W2 these already are the per-channel ConvPack inputs (HGrouping with
+    d = 1 moves no slot: no MulPC, no rotation), so W2 (O'_c x O_c) under
+    ConvPack follows directly.  Each ConvPack rescales once; with `square`,
+    W2 lands on the pre-square scale and x^2 (relinearised, rescaled) returns
+    to target_scale.
+    """
+    counts = counts if counts is not None else Counts()
+    level = cts.level
+    t2 = pre_square_target(params, level - 2, target_scale) if square else target_scale
+    y, _ = convpack(params, cts, w1, target_scale, counts)
+    z, _ = convpack(params, y, w2, t2, counts)
+    if square:
+        z, _ = square_rescale(params, keys, z, counts)
+    return z, counts
+
+
 def combine_cp_to_dp(params, keys, z: scheme.Ciphertext, spatial: int, per_dense: int,
                      counts: Counts | None = None):
     """CP->DP: dense_m = sum_{o in block m} Rot(Z_o, -(o mod B)*S)."""

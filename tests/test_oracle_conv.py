@@ -265,3 +265,51 @@ def test_convpack_identity_and_linearity():
         db = ctx.decrypt(S.Ciphertext(zb.c[o], zb.scale))
         ds = ctx.decrypt(S.Ciphertext(zs.c[o], zs.scale))
         assert np.abs(ds - (da + db)).max() < 1e-4
+
+
+def test_im2col_slots_are_patch_columns():
+    """Client-side Im2Col: vector k holds, for every output p = i O_w + j, the
+    input pixel under tap k = (kh d + kw) I_c + c (zero outside the image),
+    written out here by direct indexing, in slots 0..S-1."""
+    geom = C.ConvGeom(7, 6, 2, 3, 2, 1)
+    x = synth.image(W, (7, 6, 2))
+    vecs = C.im2col_slots(x, geom, 64)
+    assert len(vecs) == 3 * 3 * 2
+    for kh in range(3):
+        for kw in range(3):
+            for c in range(2):
+                v = vecs[(kh * 3 + kw) * 2 + c]
+                for i in range(geom.out_h):
+                    for j in range(geom.out_w):
+                        y, xx = 2 * i - 1 + kh, 2 * j - 1 + kw
+                        want = x[y, xx, c] if 0 <= y < 7 and 0 <= xx < 6 else 0.0
+                        assert v[i * geom.out_w + j] == want
+                assert not v[geom.spatial:].any()
+
+
+@pytest.mark.parametrize("square", [False, True])
+def test_convpack_convpack_ffconv_matches_fp64_and_counts(square):
+    """FFConv with both factors under ConvPack (CP-HI2C-CP, d = 1): decrypts to
+    the FP64 W1-then-W2 reference (with x^2) within 1e-3; executes Table II's
+    FFConv counts (derived AddCC form) and Table III's zero HGrouping cost
+    (no rotation at all); lands on the target scale."""
+    p = P.Params(512, (30, 30, 30, 30), 36, 2.0**25)
+    ctx = Wk.make_context(p, W, relin=square)
+    geom = C.ConvGeom(8, 8, 2, 3, 1, 1)
+    x = synth.image(W, (8, 8, 2))
+    w1 = synth.weights(W, 61, (3, 3, 2, 3), 0.3)
+    w2 = synth.weights(W, 62, (3, 4), 0.5)
+    cts = [Wk.encrypt_slots(ctx, v, 4, p.scale, W, 300 + k).c for k, v in enumerate(C.im2col_slots(x, geom, p.slots))]
+    z, cnt = C.convpack_convpack(p, ctx, S.Ciphertext(np.stack(cts), p.scale), R.filters_as_matrix(w1), w2, p.scale,
+                                 square=square)
+    k = 3 * 3 * 2
+    want = counts.convpack_ffconv_derived(4, 3, k)
+    hg = counts.him2col("CP-CP", 1)
+    assert (cnt.mulpc, cnt.addcc, cnt.rot) == (want["mulpc"] + hg["mulpc"], want["addcc"] + hg["addcc"], 0)
+    assert cnt.square == (4 if square else 0)
+    assert z.level == (1 if square else 2) and abs(z.scale / p.scale - 1) < 1e-9
+    ref = R.ffconv_reference(x, w1, w2, 1, 1, square=square)
+    for o in range(4):
+        got = ctx.decrypt(S.Ciphertext(z.c[o], z.scale))
+        assert np.abs(got[: geom.spatial] - ref[:, :, o].reshape(-1)).max() < 1e-3
+        assert np.abs(got[geom.spatial:]).max() < 1e-3
