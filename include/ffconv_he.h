@@ -359,6 +359,30 @@ int he_conv_convpack(he_ctx *ctx, const uint64_t *d_in, int k, int level, const 
                      int o_c, double in_scale, double target_scale, uint64_t *d_out, double *out_scale,
                      void *stream);
 
+/* ffconv_layer_convpack (Section 4.2.2 "ConvPack for W1", Fig. 5; CP-HI2C-CP
+ * with d = 1 in Tables III and IX): FFConv with both factors under ConvPack,
+ * no rotation at all.
+ *   d_in: the K = d^2 I_c Im2Col ciphertexts of the input, [K][2][level][N]
+ *         at in_scale (the client packs column k of Eq. 1's matrix I -- the
+ *         S = O_w O_h pixels under tap k = (kh d + kw) I_c + c, zero outside
+ *         the image -- into slots 0..S-1 of ciphertext k);
+ *   h_w1: W1 as the K x r matrix of Eq. 1 (row-major), h_w2: W2 as r x o_c.
+ *   1. W1 under ConvPack (he_conv_convpack, landing on target_scale): r
+ *      channel ciphertexts at level-1, channel c's S outputs in slots 0..S-1;
+ *   2. these are already the per-channel inputs of the 1 x 1 W2 (HGrouping
+ *      with d = 1 moves no slot);
+ *   3. W2 under ConvPack, landing on target_scale, or with `square` on
+ *      sqrt(q_{level-3} target_scale); 4. if square: x^2 (relinearised,
+ *      rescaled) back at target_scale.
+ * d_out: [o_c][2][level-2 (-1 more if square)][N]; *out_scale its scale.
+ * Counts: MulPC r (K + o_c) (integer-scalar products), AddCC r (K - 1) +
+ * o_c (r - 1), no Rot.  HE_ELEVEL unless level >= 3 (4 with square);
+ * HE_ESCALE / HE_EINVAL as he_conv_convpack for either factor; HE_ENOKEY
+ * without the relinearisation key when square. */
+int ffconv_layer_convpack(he_ctx *ctx, const uint64_t *d_in, int k, int level, const double *h_w1, int r,
+                          const double *h_w2, int o_c, double in_scale, double target_scale, int square,
+                          uint64_t *d_out, double *out_scale, void *stream);
+
 /* ffconv_layer (Section 4, DP-HI2C-CP of Table IX):
  *   1. W1 under DensePack exactly as he_conv_densepack (desc->o_c = rank r),
  *      giving r*S replicated ciphertexts at level-1;

@@ -80,6 +80,7 @@ SIGNATURES = {
     "he_conv_densepack": (I, [P, P, I, ctypes.POINTER(HeConvDesc), P, P, P]),
     "he_conv_convpack": (I, [P, P, I, I, DP, I, ctypes.c_double, ctypes.c_double, P, DP, P]),
     "ffconv_layer": (I, [P, P, I, ctypes.POINTER(HeConvDesc), P, P, DP, I, I, I, P, P]),
+    "ffconv_layer_convpack": (I, [P, P, I, I, DP, I, DP, I, ctypes.c_double, ctypes.c_double, I, P, DP, P]),
     "he_int_weight_table": (I, [P, DP, I, I, I, P, P]),
     "ffconv_layer_batch": (I, [P, I, P, ctypes.c_size_t, I, ctypes.POINTER(HeConvDesc), P, ctypes.c_size_t, P, P,
                                I, I, P, P]),

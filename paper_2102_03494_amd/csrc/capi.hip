@@ -1251,34 +1251,96 @@ int he_conv_densepack_batch(he_ctx* c, int n_layers, const uint64_t* d_in, size_
   return densepack_run(c, d_in, level, desc, d_filt, d_out, ar, S(stream), n_layers, in_stride, filt_stride);
 }
 
+// Integer weights of a ConvPack layer whose rescale by q_{level-1} lands on
+// target: round-half-away(w * (q_{level-1} target / in_scale)).  Checks the
+// scales and the weights' range before anything is launched.
+int convpack_weights(he_ctx* c, const char* who, const double* h_w, size_t count, int level, double in_scale,
+                     double target_scale, std::vector<int64_t>& w, double& w_scale) {
+  const double q_last = (double)c->moduli[level - 1];
+  w_scale = q_last * target_scale / in_scale;
+  if (!scale_ok(in_scale) || !scale_ok(target_scale) || !std::isfinite(w_scale) || w_scale < 1.0)
+    return fail(c, HE_ESCALE, "%s: input scale %.17g cannot reach target %.17g at level %d", who, in_scale,
+                target_scale, level);
+  w.resize(count);
+  for (size_t i = 0; i < count; ++i) {
+    const double x = h_w[i] * w_scale;
+    if (!(std::fabs(x) < 4.0e18)) return fail(c, HE_EINVAL, "%s: weight too large for the scale", who);
+    w[i] = round_half_away(x);
+  }
+  return HE_OK;
+}
+
+// One ConvPack layer (Table II): out[o] = rescale(sum_k w[k][o] in[k]); adds
+// its counts.  z: o_c ciphertexts of workspace at `level`.
+int convpack_run(he_ctx* c, const u64* in, int k, int level, const std::vector<int64_t>& w, int o_c, u64* out,
+                 Arena& ar, hipStream_t s) {
+  u64* z = ar.take<u64>((size_t)o_c * 2 * level * c->n);
+  if (!z) return fail(c, HE_ENOMEM, "workspace too small for ConvPack");
+  int e = scalar_mac(c, z, in, k, w, o_c, level, ar, s);
+  if (!e) e = rescale_batch(c, out, z, o_c, level, ar, s);
+  c->counts.mulpc += (int64_t)k * o_c;
+  c->counts.addcc += (int64_t)(k - 1) * o_c;
+  c->counts.rescale += o_c;
+  return e;
+}
+
 int he_conv_convpack(he_ctx* c, const uint64_t* d_in, int k, int level, const double* h_w, int o_c, double in_scale,
                      double target_scale, uint64_t* d_out, double* out_scale, void* stream) {
   if (!c || !d_in || !h_w || !d_out || !out_scale || k < 1 || o_c < 1 || o_c > 65535)
     return fail(c, HE_EINVAL, "he_conv_convpack: bad arguments");
   if (level < 2 || level > c->big_l) return fail(c, HE_ELEVEL, "he_conv_convpack needs 2 <= level <= L (got %d)", level);
-  // weight scale that makes the rescale by q_{level-1} land on the target
-  const double q_last = (double)c->moduli[level - 1];
-  const double w_scale = q_last * target_scale / in_scale;
-  if (!scale_ok(in_scale) || !scale_ok(target_scale) || !std::isfinite(w_scale) || w_scale < 1.0)
-    return fail(c, HE_ESCALE, "he_conv_convpack: input scale %.17g cannot reach target %.17g at level %d", in_scale,
-                target_scale, level);
+  std::vector<int64_t> w;
+  double w_scale = 0;
+  int e = convpack_weights(c, "he_conv_convpack", h_w, (size_t)k * o_c, level, in_scale, target_scale, w, w_scale);
+  if (e) return e;
   c->counts = he_counts{};
-  std::vector<int64_t> w((size_t)k * o_c);
-  for (size_t i = 0; i < w.size(); ++i) {
-    const double x = h_w[i] * w_scale;
-    if (!(std::fabs(x) < 4.0e18)) return fail(c, HE_EINVAL, "he_conv_convpack: weight too large for the scale");
-    w[i] = round_half_away(x);
-  }
   Arena ar(c);
-  u64* z = ar.take<u64>((size_t)o_c * 2 * level * c->n);
-  if (!z) return fail(c, HE_ENOMEM, "workspace too small");
+  e = convpack_run(c, d_in, k, level, w, o_c, d_out, ar, S(stream));
+  if (!e) *out_scale = in_scale * w_scale / (double)c->moduli[level - 1];
+  return e;
+}
+
+int ffconv_layer_convpack(he_ctx* c, const uint64_t* d_in, int k, int level, const double* h_w1, int r,
+                          const double* h_w2, int o_c, double in_scale, double target_scale, int square,
+                          uint64_t* d_out, double* out_scale, void* stream) {
+  if (!c || !d_in || !h_w1 || !h_w2 || !d_out || !out_scale || k < 1 || r < 1 || o_c < 1 || r > 65535 ||
+      o_c > 65535)
+    return fail(c, HE_EINVAL, "ffconv_layer_convpack: bad arguments");
+  const int need = square ? 4 : 3;
+  if (level < need || level > c->big_l)
+    return fail(c, HE_ELEVEL, "ffconv_layer_convpack needs %d <= level <= L (got %d)", need, level);
+  if (square && !c->keys.count(0)) return fail(c, HE_ENOKEY, "ffconv_layer_convpack: no relinearisation key");
+  // W1 lands on target_scale; W2 on target_scale, or with x^2 on the scale
+  // whose square, rescaled by q_{level-3}, is target_scale
+  const double t2 = square ? std::sqrt((double)c->moduli[level - 3] * target_scale) : target_scale;
+  std::vector<int64_t> w1, w2;
+  double s1 = 0, s2 = 0;
+  int e = convpack_weights(c, "ffconv_layer_convpack (W1)", h_w1, (size_t)k * r, level, in_scale, target_scale, w1, s1);
+  if (e) return e;
+  const double y_scale = in_scale * s1 / (double)c->moduli[level - 1];
+  e = convpack_weights(c, "ffconv_layer_convpack (W2)", h_w2, (size_t)r * o_c, level - 1, y_scale, t2, w2, s2);
+  if (e) return e;
+  double z_scale = y_scale * s2 / (double)c->moduli[level - 2];
+  const int n = c->n;
+  c->counts = he_counts{};
+  Arena ar(c);
   hipStream_t s = S(stream);
-  int e = scalar_mac(c, z, d_in, k, w, o_c, level, ar, s);
-  if (!e) e = rescale_batch(c, d_out, z, o_c, level, ar, s);
-  if (!e) *out_scale = in_scale * w_scale / q_last;
-  c->counts.mulpc = (int64_t)k * o_c;
-  c->counts.addcc = (int64_t)(k - 1) * o_c;
-  c->counts.rescale = o_c;
+  u64* y = ar.take<u64>((size_t)r * 2 * (level - 1) * n);
+  u64* z = square ? ar.take<u64>((size_t)o_c * 2 * (level - 2) * n) : d_out;
+  u64* sq = square ? ar.take<u64>((size_t)o_c * 2 * (level - 2) * n) : nullptr;
+  if (!y || !z || (square && !sq)) return fail(c, HE_ENOMEM, "workspace too small for ffconv_layer_convpack");
+  // W1 under ConvPack; its r channel ciphertexts are W2's ConvPack inputs as
+  // they stand (HGrouping with d = 1: no slot moves, no rotation)
+  e = convpack_run(c, d_in, k, level, w1, r, y, ar, s);
+  if (!e) e = convpack_run(c, y, r, level - 1, w2, o_c, z, ar, s);
+  if (!e && square) {
+    e = square_batch(c, sq, z, o_c, level - 2, ar, s);
+    if (!e) e = rescale_batch(c, d_out, sq, o_c, level - 2, ar, s);
+    c->counts.square += o_c;
+    c->counts.rescale += o_c;
+    z_scale = z_scale * z_scale / (double)c->moduli[level - 3];
+  }
+  if (!e) *out_scale = z_scale;
   return e;
 }
 

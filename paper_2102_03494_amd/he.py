@@ -467,6 +467,24 @@ class HEContext:
                                               ctypes.byref(out_scale), _stream()), "he_conv_convpack")
         return Ct(out, out_scale.value)
 
+    def ffconv_layer_convpack(self, x: Ct, w1: np.ndarray, w2: np.ndarray, target_scale: float,
+                              square: bool = False) -> Ct:
+        """FFConv with both factors under ConvPack on the K Im2Col ciphertexts
+        x ([K][2][level][N]); w1: K x r (Eq. 1 rows), w2: r x o_c."""
+        level = x.level
+        k, r = w1.shape
+        o_c = w2.shape[1]
+        w1f = np.ascontiguousarray(np.asarray(w1, dtype=np.float64))
+        w2f = np.ascontiguousarray(np.asarray(w2, dtype=np.float64))
+        lvl_out = level - 2 - (1 if square else 0)
+        out = torch.empty((o_c, 2, lvl_out, self.n), dtype=torch.int64, device="cuda")
+        out_scale = ctypes.c_double(0.0)
+        self._check(self.lib.ffconv_layer_convpack(self.h, _ptr(x.data), k, level, w1f.ctypes.data_as(_lib.DP), r,
+                                                   w2f.ctypes.data_as(_lib.DP), o_c, float(x.scale),
+                                                   float(target_scale), int(square), _ptr(out),
+                                                   ctypes.byref(out_scale), _stream()), "ffconv_layer_convpack")
+        return Ct(out, out_scale.value)
+
     def ffconv_layer(self, x: Ct, desc: HeConvDesc, w1_filt: torch.Tensor, w1_pt_scale: float,
                      mask: torch.Tensor, mask_scale: float, w2: np.ndarray, k_bits: int, square: bool,
                      out: torch.Tensor | None = None) -> Ct:

@@ -80,6 +80,27 @@ def densepack_layout(x: np.ndarray, g: Geometry, slots: int) -> list[np.ndarray]
     return vecs
 
 
+def im2col_layout(x: np.ndarray, g: Geometry, slots: int) -> list[np.ndarray]:
+    """Client-side plaintext Im2Col for a ConvPack input (Eq. 1): K = d^2 I_c
+    slot vectors; vector (kh d + kw) I_c + c holds, at slot i O_w + j, the
+    pixel X[s i - pad + kh][s j - pad + kw][c] (zero outside the image)."""
+    h, w, c_in = x.shape
+    s_out = g.out_h * g.out_w
+    if s_out > slots:
+        raise ValueError("more outputs than slots")
+    xp = np.zeros((h + 2 * g.pad, w + 2 * g.pad, c_in))
+    xp[g.pad:g.pad + h, g.pad:g.pad + w] = x
+    out = []
+    for kh in range(g.d):
+        for kw in range(g.d):
+            win = xp[kh:kh + g.stride * (g.out_h - 1) + 1:g.stride, kw:kw + g.stride * (g.out_w - 1) + 1:g.stride]
+            for c in range(c_in):
+                v = np.zeros(slots)
+                v[:s_out] = win[:, :, c].reshape(-1)
+                out.append(v)
+    return out
+
+
 def filter_layout(weights: np.ndarray, g: Geometry, slots: int, o: int, cls: int, m: int) -> np.ndarray:
     rows, cols = g.classes()
     kh0, kh1 = rows[cls // len(cols)]

@@ -437,6 +437,70 @@ def test_ffconv_layer_bit_exact_small(chain):
         assert np.abs(v - ref[:, :, o].reshape(-1)).max() < 1e-3
 
 
+def test_factorized_layer_bit_exact():
+    """Eq. 2 end to end: W factorised by the product's truncated SVD at rank
+    2, then the FFConv layer on the GPU equals the oracle's layer on the same
+    factors bit for bit, and decrypts to the FP64 rank-2 conv within 1e-3;
+    at full rank the factors reproduce W's conv."""
+    from paper_2102_03494_amd import factorize as F
+    p, octx, gctx, cl = _small_setup(rotations=[1 << j for j in range(9)])
+    geom = C.ConvGeom(6, 6, 2, 3, 1, 1)
+    x = synth.image(W, (6, 6, 2))
+    w = synth.weights(W, 23, (3, 3, 2, 4), 0.2)
+    level = 3
+    ct = Wk.encrypt_slots(octx, C.densepack_slots(x, geom, p.slots)[0], level, p.scale, W, 0)
+    he = _he()
+    for r in (2, 4):
+        w1, w2 = F.factorize(w, r)
+        pts = C.densepack_pt_scale(p, level, p.scale, p.scale)
+        bf = C.densepack_base_filters(p, w1, geom, level, pts)
+        y, _ = C.conv_densepack(p, octx, ct, geom, bf, pts)
+        ms = C.gather_mask_scale(p, y.level, y.scale, p.scale, 12)
+        mask = C.encode_onehot(p, y.level, ms)
+        want, _ = C.gather_convpack(p, y, geom.spatial, w2, 12, mask, ms)
+        desc = he.HEContext.conv_desc(6, 6, 2, 3, 1, 1, r, 9)
+        got = gctx.ffconv_layer(he.Ct(_dev(ct.c[None]), p.scale), desc, _dev(bf), pts, _dev(mask), ms, w2, 12, False)
+        assert np.array_equal(_host(got.data), want.c), r
+        ref = R.ffconv_reference(x, w1, w2, 1, 1)
+        ref_w = R.conv2d(x, w, 1, 1)
+        for o in range(4):
+            v = cl.decrypt(got.data[o], got.scale, geom.spatial)
+            assert np.abs(v - ref[:, :, o].reshape(-1)).max() < 1e-3
+            if r == 4:  # full rank: the factorisation is exact
+                assert np.abs(v - ref_w[:, :, o].reshape(-1)).max() < 1e-3
+
+
+@pytest.mark.parametrize("chain,square", [(None, True), (None, False), (SMALL40, True)],
+                         ids=["30bit-sq", "30bit", "40bit-sq"])
+def test_ffconv_convpack_convpack_bit_exact(chain, square):
+    """FFConv with both factors under ConvPack (CP-HI2C-CP, d = 1): the GPU
+    layer on the client's Im2Col ciphertexts equals the oracle's bit for bit,
+    executes no rotation, and decrypts to the FP64 reference within 1e-3."""
+    p, octx, gctx, cl = _small_setup(relin=square, chain=chain)
+    geom = C.ConvGeom(7, 7, 2, 3, 2, 1)
+    x = synth.image(W, (7, 7, 2))
+    w1 = synth.weights(W, 71, (3, 3, 2, 3), 0.3)
+    w2 = synth.weights(W, 72, (3, 4), 0.4)
+    level = 4
+    vecs = C.im2col_slots(x, geom, p.slots)
+    from paper_2102_03494_amd import layers as Ly
+    gvecs = Ly.im2col_layout(x, Ly.Geometry(7, 7, 2, 3, 2, 1), p.slots)
+    assert all(np.array_equal(a, b) for a, b in zip(vecs, gvecs))  # the product's layout is the oracle's
+    cts = np.stack([Wk.encrypt_slots(octx, v, level, p.scale, W, 400 + k).c for k, v in enumerate(vecs)])
+    w1m = R.filters_as_matrix(w1)
+    want, cnt = C.convpack_convpack(p, octx, S.Ciphertext(cts, p.scale), w1m, w2, p.scale, square=square)
+    he = _he()
+    got = gctx.ffconv_layer_convpack(he.Ct(_dev(cts), p.scale), w1m, w2, p.scale, square=square)
+    assert np.array_equal(_host(got.data), want.c)
+    assert got.scale == want.scale
+    gc = gctx.last_counts()
+    assert (gc["mulpc"], gc["addcc"], gc["rot"], gc["square"]) == (cnt.mulpc, cnt.addcc, 0, cnt.square)
+    ref = R.ffconv_reference(x, w1, w2, 2, 1, square=square)
+    for o in range(4):
+        v = cl.decrypt(got.data[o], got.scale, geom.spatial)
+        assert np.abs(v - ref[:, :, o].reshape(-1)).max() < 1e-3
+
+
 def test_batch_rotate_ragged_levels():
     """One launch set over items at levels 4, 2, 3, 4, 1 with different steps (0 copies)."""
     steps = [1, 3, -7, 0, 100]
