@@ -156,6 +156,26 @@ def setup(ctx, client, x, w1, w2):
     return geom, ct, ffconv_step, plain_step, w_plain
 
 
+def paper_counts_dp_hi2c_cp(spatial: int, r: int, o_c: int, r_steps: int) -> dict:
+    """The paper's formula counts of an FFConv layer packed DP-HI2C-CP with
+    d = 1 (Table I for W1 with O' = S r, Table III DP-HI2C-CP d = 1: O^1_c
+    MulPC and O^1_c Rot, Table II for W2 with K = r)."""
+    o1 = spatial * r
+    w1 = {"mulpc": o1, "addcc": o1 * r_steps, "rot": o1 * r_steps}
+    hi2c = {"mulpc": r, "addcc": 0, "rot": r}
+    w2 = {"mulpc": o_c * r, "addcc": o_c * (r - 1), "rot": 0}
+    tot = {k: w1[k] + hi2c[k] + w2[k] for k in w1}
+    return {"W1_densepack_table_I": w1, "HI2C_table_III_dp_cp_d1": hi2c, "W2_convpack_table_II": w2, "total": tot,
+            "note": "executed: the DP->CP step is S r one-hot mask products and no rotation (CKKS replicated "
+                    "DensePack outputs), plus x^2 with its relinearisation where configured"}
+
+
+def paper_counts_dp(spatial: int, o_c: int, r_steps: int) -> dict:
+    """Table I counts of a plain DensePack layer (O = S O_c dot products)."""
+    o = spatial * o_c
+    return {"mulpc": o, "addcc": o * r_steps, "rot": o * r_steps}
+
+
 def timed(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -362,6 +382,91 @@ def ragged_section(torch, reps: int):
     return res
 
 
+def convpack_ffconv(torch, ctx, cl, x, w1, w2, stride, pad, level, scale, square, reps: int, index0: int):
+    """FFConv with both factors under ConvPack (CP-HI2C-CP, d = 1; Sec. 4.2.2,
+    Fig. 5): the client encrypts the K = d^2 I_c columns of the plaintext
+    Im2Col, W1 and W2 run as two ConvPack layers with no rotation.  Reports
+    latency, executed and paper-formula counts and the decrypted error."""
+    import numpy as np
+
+    from paper_2102_03494_amd import layers as Ly
+    from paper_2102_03494_amd.he import Ct
+
+    h, w_, c_in = x.shape
+    d, r, o_c = w1.shape[0], w1.shape[3], w2.shape[1]
+    geom = Ly.Geometry(h, w_, c_in, d, stride, pad)
+    vecs = Ly.im2col_layout(x, geom, ctx.n // 2)
+    cts = torch.stack([cl.encrypt(v, level, scale, index=index0 + k).data[0] for k, v in enumerate(vecs)])
+    xin = Ct(cts.contiguous(), scale)
+    w1m = w1.reshape(-1, r)
+    ctx.reserve(ctx.workspace_need(max(r, o_c) * 3, level) + (64 << 20))
+    t, z = timed(lambda: ctx.ffconv_layer_convpack(xin, w1m, w2, scale, square=square), reps, 1, torch)
+    cnt = ctx.last_counts()
+    ref = Ly.reference_conv2d(x, w1, stride, pad) @ w2
+    if square:
+        ref = ref * ref
+    err = 0.0
+    for o in range(o_c):
+        v = cl.decrypt(z.data[o], z.scale, geom.spatial, limbs=1)
+        err = max(err, float(np.abs(v - ref[:, :, o].ravel()).max()))
+    k = len(vecs)
+    return {"layer_ms": t * 1e3, "input_ciphertexts": k, "counts": cnt,
+            "paper_counts": {"mulpc": r * (k + o_c), "addcc": r * (k - 1) + o_c * (r - 1), "rot": 0,
+                             "source": "Table II (FFConv, both factors ConvPack; AddCC derived form) + Table III "
+                                       "CP-HI2C-CP d = 1 (0, 0, 0)"},
+            "decrypted_max_abs_err": err}
+
+
+def rank_sweep(torch, ctx, cl, shape, stride, pad, level, scale, ranks, wl, reps: int):
+    """Eq. 2 / Table X: a synthetic W (d x d x I_c x O_c) whose K x O_c matrix
+    has singular values 0.3 * 0.7^i is factorised at each rank r (truncated
+    SVD, factorize.py) and evaluated as an FFConv layer (W1 under DensePack,
+    gather, W2 under ConvPack, rescale; no x^2).  Per rank: layer latency,
+    executed rotations, the relative Frobenius error of W1 W2, the max
+    decrypted error against the FP64 rank-r conv (HE error) and against the
+    FP64 conv with W (factorisation + HE error)."""
+    import numpy as np
+
+    import synth
+    from paper_2102_03494_amd import factorize as F
+    from paper_2102_03494_amd import layers as Ly
+
+    h, w_, c_in, d, o_c = shape[0], shape[1], shape[2], shape[3], shape[4]
+    geom = Ly.Geometry(h, w_, c_in, d, stride, pad)
+    k = d * d * c_in
+    m = min(k, o_c)
+    sigma = 0.3 * 0.7 ** np.arange(m)
+    rng = synth.rng(wl, "weight", 900)
+    w = F.with_spectrum(rng.normal(size=(k, m)), rng.normal(size=(o_c, m)), sigma, (d, d, c_in, o_c))
+    x = synth.image(wl, (h, w_, c_in))
+    ct = cl.encrypt(Ly.densepack_layout(x, geom, ctx.n // 2)[0], level, scale, index=0)
+    ref_full = Ly.reference_conv2d(x, w, stride, pad)
+    r_steps = int(math.log2(ctx.n // 2))
+    rows = []
+    for r in ranks:
+        w1, w2 = F.factorize(w, r)
+        desc = ctx.conv_desc(h, w_, c_in, d, stride, pad, r, r_steps)
+        pts = Ly.pt_scale_for(ctx, level, scale, scale)
+        f1 = Ly.encode_filters(cl, w1, geom, level, pts)
+        ms = Ly.mask_scale_for(ctx, level - 1, scale * pts / ctx.q[level - 1], scale, K_BITS)
+        mask = Ly.onehot_mask(cl, level - 1, ms)
+        ctx.reserve(ctx.ffconv_workspace_need(1, level, desc, o_c, False))
+        t, z = timed(lambda: ctx.ffconv_layer(ct, desc, f1, pts, mask, ms, w2, K_BITS, False), reps, 1, torch)
+        rot = ctx.last_counts()["rot"]
+        ref_r = Ly.reference_conv2d(x, w1, stride, pad) @ w2
+        e_he = e_full = 0.0
+        for o in range(o_c):
+            v = cl.decrypt(z.data[o], z.scale, geom.spatial, limbs=1)
+            e_he = max(e_he, float(np.abs(v - ref_r[:, :, o].ravel()).max()))
+            e_full = max(e_full, float(np.abs(v - ref_full[:, :, o].ravel()).max()))
+        rows.append({"rank": r, "layer_ms": t * 1e3, "rotations": rot, "w_rel_frobenius_error": F.relative_error(w, w1, w2),
+                     "decrypted_max_abs_err_vs_rank_r_fp64": e_he, "decrypted_max_abs_err_vs_full_w_fp64": e_full})
+        del z, f1
+    return {"workload": f"{h}x{w_}x{c_in} input, {d}x{d} stride {stride} pad {pad} conv {c_in}->{o_c}, synthetic W "
+                        f"with singular values 0.3*0.7^i, N={ctx.n}; FFConv at each rank (no x^2)",
+            "ranks": rows}
+
+
 def cifar_section(torch, steps: int, plain: bool, digests_path: str):
     """The CIFAR-shaped layer: a 32x32x3 image (U[0,1)) under DensePack in one
     ciphertext at N = 16384 (6 x 40-bit primes + 60-bit P, scale 2^30).
@@ -448,17 +553,25 @@ def cifar_section(torch, steps: int, plain: bool, digests_path: str):
             bit = {"sampled_w1_outputs": len(got),
                    "identical": sum(g == w for g, w in zip(got, gold["w1_sample_sha256"]))}
             del y
+    print("# cifar ConvPack-ConvPack FFConv", file=sys.stderr, flush=True)
+    cpcp = convpack_ffconv(torch, ctx, cl, x, w1, w2, 1, 1, level, scale, False, max(1, steps), 500)
+    cpcp["speedup_vs_dp_hi2c_cp"] = t_ff * 1e3 / cpcp["layer_ms"]
+    print("# cifar rank sweep", file=sys.stderr, flush=True)
+    del out, z
+    torch.cuda.empty_cache()
+    sweep = rank_sweep(torch, ctx, cl, (32, 32, 3, 3, 64), 1, 1, level, scale, (1, 2, 4, 8, 16), wl, 1)
     res = {
+        "rank_sweep": sweep,
+        "ffconv_convpack_convpack": cpcp,
         "workload": "CIFAR-shaped layer 32x32x3, N=16384 (6x40-bit + 60-bit P, scale 2^30): FFConv 3x3 pad 1 "
                     "3->8 DensePack + 1x1 8->64 ConvPack vs plain 3x3 pad 1 3->64 DensePack (W = W1 W2)",
         "ffconv_layer_ms": t_ff * 1e3, "ffconv_rotations_per_s": counts_ff["rot"] / t_ff,
         "ffconv_hma_per_s": (counts_ff["mulpc"] + counts_ff["scalar_mul"]) / t_ff,
-        "counts_ffconv": counts_ff, "ffconv_decrypted_max_abs_err": err_ff, "roofline": roof,
+        "counts_ffconv": counts_ff, "paper_counts_ffconv": paper_counts_dp_hi2c_cp(geom.spatial, 8, 64, r_steps),
+        "ffconv_decrypted_max_abs_err": err_ff, "roofline": roof,
         "w1_bit_exact_vs_oracle": bit,
     }
     if plain:
-        del out, z
-        torch.cuda.empty_cache()
         wp = Ly.compose_factors(w1, w2)
         pts_pl = Ly.pt_scale_for(ctx, level, scale, scale)
         fp = Ly.encode_filters(cl, wp, geom, level, pts_pl)
@@ -484,6 +597,7 @@ def cifar_section(torch, steps: int, plain: bool, digests_path: str):
             err_pl = max(err_pl, abs(float(v[0]) - refp[i, j, o]))
         res.update(plain_layer_ms=t_pl * 1e3, plain_rotations_per_s=counts_pl["rot"] / t_pl,
                    plain_hma_per_s=counts_pl["mulpc"] / t_pl, counts_plain=counts_pl,
+                   paper_counts_plain=paper_counts_dp(geom.spatial, 64, r_steps),
                    plain_decrypted_max_abs_err_256_sampled=err_pl, speedup_vs_plain=t_pl / t_ff)
         print(f"# cifar plain: {t_pl * 1e3:.1f} ms/layer", file=sys.stderr, flush=True)
         del yp, zp
@@ -550,6 +664,7 @@ def main():
                     help="independent layers in the batched/graph section (0 = skip)")
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged 64-ciphertext batch section")
     ap.add_argument("--no-cifar", action="store_true", help="skip the N=16384 CIFAR-shaped layer section")
+    ap.add_argument("--no-rank-sweep", action="store_true", help="skip the low-rank factorisation sweep (N=8192)")
     ap.add_argument("--no-cifar-plain", action="store_true",
                     help="skip the CIFAR-shaped plain comparator (65,536 dot products, about 80 GiB of outputs)")
     ap.add_argument("--serve-window", type=float, default=1.0,
@@ -677,6 +792,19 @@ def main():
         print("# batched layers and graph", file=sys.stderr, flush=True)
         batched = batched_layers_section(torch, ctx, client, args.batched_layers, max(1, min(args.steps, 3)))
 
+    print("# ConvPack-ConvPack FFConv at N=8192", file=sys.stderr, flush=True)
+    cpcp = convpack_ffconv(torch, ctx, client, x, w1, w2, 2, 0, len(Q_BITS), SCALE, True, max(1, min(args.steps, 10)),
+                           500)
+    cpcp["speedup_vs_dp_hi2c_cp"] = t_ff * 1e3 / cpcp["layer_ms"]
+    cpcp["workload"] = ("the same 28x28x1 layer with both factors under ConvPack: 25 Im2Col ciphertexts, W1 25->2, "
+                        "W2 2->5, x^2 (CP-HI2C-CP, d = 1)")
+
+    sweep = None
+    if not args.no_rank_sweep:
+        print("# rank sweep at N=8192", file=sys.stderr, flush=True)
+        sweep = rank_sweep(torch, ctx, client, (28, 28, 1, 5, 5), 2, 0, len(Q_BITS), SCALE, (1, 2, 3, 4, 5), WORKLOAD,
+                           max(1, min(args.steps, 5)))
+
     hoisted = None
     if not args.no_hoisted:
         del ctx, client
@@ -731,10 +859,14 @@ def main():
         "hma_per_s": hma_ff / t_ff,
         "counts_ffconv": counts_ff,
         "counts_plain_conv": counts_pl,
+        "paper_counts_ffconv": paper_counts_dp_hi2c_cp(geom.spatial, w1.shape[3], w2.shape[1], 12),
+        "paper_counts_plain_conv": paper_counts_dp(geom.spatial, w2.shape[1], 12),
         "decrypted_max_abs_err": {"ffconv": err_ff, "plain": err_pl},
         "roofline": roofline,
         "tuning": tuning,
         "batched_layers_graph": batched,
+        "rank_sweep": sweep,
+        "ffconv_convpack_convpack": cpcp,
         "ragged_batch": ragged,
         "serving_mnist": serving,
         "hoisted_rotations": hoisted,
