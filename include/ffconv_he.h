@@ -423,6 +423,42 @@ int ffconv_layer_batch(he_ctx *ctx, int n_layers, const uint64_t *d_in, size_t i
                        const uint64_t *d_mask, const uint64_t *d_w2_tab, int o_c2, int square, uint64_t *d_out,
                        void *stream);
 
+/* ---- pieces of a layer for iteration-level (continuous) batching -----------
+ * A serving engine that merges the work of requests at different points of
+ * their nets into shared launches runs a DensePack layer as its three parts:
+ * he_densepack_hma: the MulPC of he_conv_densepack_batch only (Table I's
+ *          O MulPC): d_acc [n_layers * o_c * S][2][level][N] gets the
+ *          unsummed products at `level` (no rotation, no rescale).
+ * he_rotsum_groups: one rotate-and-add step for several groups of such
+ *          accumulators at once: for every group g and i < count_g,
+ *          acc_g[i] <- acc_g[i] + Rot(acc_g[i], 2^step_g) in place (each
+ *          group its own level and step, so chains that started at
+ *          different times share the launch; R steps j = 0..R-1 complete
+ *          the DensePack sum of Fig. 1b).  Needs the keys of 2^step_g;
+ *          2^step a multiple of N/2 is refused (identity).
+ * ffconv_tail_batch: the rest of ffconv_layer_batch after the rotate-and-
+ *          sum: rescale of the n_layers * r * S summed accumulators d_acc
+ *          (r = desc->o_c, at `level`), DP->CP gather with d_mask, 1x1
+ *          ConvPack with the W2 tables d_w2_tab (he_int_weight_table, layer l
+ *          at d_w2_tab + l * 2 * r * o_c2 * (level - 1)), rescale, and with
+ *          `square` x^2 + relinearisation + rescale.  d_out as
+ *          ffconv_layer_batch's.
+ * Results are bit-identical to the one-call layers (each ciphertext's
+ * arithmetic is independent of what else shares a launch). */
+typedef struct {
+  uint64_t *acc;   /* [count][2][level][N], device */
+  int32_t count;
+  int32_t level;
+  int32_t step;    /* this group's rotation is by 2^step */
+} he_rotsum_group;
+int he_densepack_hma(he_ctx *ctx, int n_layers, const uint64_t *d_in, size_t in_stride, int level,
+                     const he_conv_desc *desc, const uint64_t *d_filt, size_t filt_stride, uint64_t *d_acc,
+                     void *stream);
+int he_rotsum_groups(he_ctx *ctx, const he_rotsum_group *h_groups, int n_groups, void *stream);
+int ffconv_tail_batch(he_ctx *ctx, int n_layers, const uint64_t *d_acc, int level, const he_conv_desc *desc,
+                      const uint64_t *d_mask, const uint64_t *d_w2_tab, int o_c2, int square, uint64_t *d_out,
+                      void *stream);
+
 /* Workspace bytes ffconv_layer / ffconv_layer_batch need for n_layers layers
  * (0 on bad arguments); the batch runs in a smaller workspace too, in more
  * chunks, down to one ciphertext's temporaries. */

@@ -30,6 +30,11 @@ class HeConvDesc(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int32) for k in ("h", "w", "c_in", "d", "stride", "pad", "o_c", "r_steps")]
 
 
+class HeRotsumGroup(ctypes.Structure):
+    _fields_ = [("acc", ctypes.c_void_p), ("count", ctypes.c_int32), ("level", ctypes.c_int32),
+                ("step", ctypes.c_int32)]
+
+
 class HeCounts(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("mulpc", "addcc", "rot", "rescale", "square", "scalar_mul")]
 
@@ -85,6 +90,9 @@ SIGNATURES = {
     "ffconv_layer_batch": (I, [P, I, P, ctypes.c_size_t, I, ctypes.POINTER(HeConvDesc), P, ctypes.c_size_t, P, P,
                                I, I, P, P]),
     "he_ffconv_workspace_need": (ctypes.c_size_t, [P, I, I, ctypes.POINTER(HeConvDesc), I, I]),
+    "he_densepack_hma": (I, [P, I, P, ctypes.c_size_t, I, ctypes.POINTER(HeConvDesc), P, ctypes.c_size_t, P, P]),
+    "he_rotsum_groups": (I, [P, ctypes.POINTER(HeRotsumGroup), I, P]),
+    "ffconv_tail_batch": (I, [P, I, P, I, ctypes.POINTER(HeConvDesc), P, P, I, I, P, P]),
     "he_combine_cp_dp_batch": (I, [P, I, P, I, I, I, I, P, P]),
     "he_gather_onehot": (I, [P, I, P, I, P, I, P, P]),
     "he_conv_densepack_batch": (I, [P, I, P, ctypes.c_size_t, I, ctypes.POINTER(HeConvDesc), P, ctypes.c_size_t, P,

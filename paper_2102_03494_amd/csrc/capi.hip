@@ -503,6 +503,9 @@ size_t ffconv_need(const he_ctx* c, int n_layers, int level, int spatial, int r,
   return need + ((size_t)64 << 20);
 }
 
+int ffconv_tail(he_ctx* c, int n_layers, const u64* y, int l1, int spatial, int r, const u64* d_mask,
+                const u64* d_w2tab, int o_c2, int square, u64* d_out, Arena& ar, hipStream_t s);
+
 // FFConv over n_layers independent layers of one geometry (layer l: input at
 // d_in + l in_stride, W1 base filters at d_w1 + l f_stride, W2 integer table
 // at d_w2tab + l 2 r o_c2 (level - 1)): W1 DensePack, DP->CP gather with the
@@ -520,19 +523,32 @@ int ffconv_run(he_ctx* c, int n_layers, const u64* d_in, size_t in_stride, int l
   const int n = c->n;
   const int r = desc->o_c;
   const int spatial = geo.out_h * geo.out_w;
-  const int l1 = level - 1, l2 = level - 2;
+  const int l1 = level - 1;
   if ((long long)n_layers * r > 65535 || (long long)n_layers * o_c2 > 65535)
     return fail(c, HE_EINVAL, "too many layers for one call");
   const size_t B = (size_t)n_layers;
   u64* y = ar.take<u64>(B * r * spatial * 2 * l1 * n);
+  if (!y) return fail(c, HE_ENOMEM, "workspace too small for the FFConv layer");
+  // 1. W1 under DensePack (HMA, rotate-and-sum, rescale), all layers in one batch
+  int e = densepack_run(c, d_in, level, desc, d_w1, y, ar, s, n_layers, in_stride, f_stride);
+  if (e) return e;
+  return ffconv_tail(c, n_layers, y, l1, spatial, r, d_mask, d_w2tab, o_c2, square, d_out, ar, s);
+}
+
+// Steps 2-5 of ffconv_run from the rescaled W1 DensePack outputs y
+// ([n_layers][r][S][2][l1][N]): gather, 1x1 ConvPack, rescale, optional
+// square + relinearise + rescale.
+int ffconv_tail(he_ctx* c, int n_layers, const u64* y, int l1, int spatial, int r, const u64* d_mask,
+                const u64* d_w2tab, int o_c2, int square, u64* d_out, Arena& ar, hipStream_t s) {
+  const int n = c->n;
+  const int l2 = l1 - 1;
+  const size_t B = (size_t)n_layers;
   u64* g = ar.take<u64>(B * r * 2 * l1 * n);
   u64* z = ar.take<u64>(B * o_c2 * 2 * l1 * n);
   u64* zr = square ? ar.take<u64>(B * o_c2 * 2 * l2 * n) : nullptr;
   u64* sq = square ? ar.take<u64>(B * o_c2 * 2 * l2 * n) : nullptr;
-  if (!y || !g || !z || (square && (!zr || !sq))) return fail(c, HE_ENOMEM, "workspace too small for the FFConv layer");
-  // 1. W1 under DensePack (HMA, rotate-and-sum, rescale), all layers in one batch
-  int e = densepack_run(c, d_in, level, desc, d_w1, y, ar, s, n_layers, in_stride, f_stride);
-  if (e) return e;
+  if (!g || !z || (square && (!zr || !sq))) return fail(c, HE_ENOMEM, "workspace too small for the FFConv layer");
+  int e = HE_OK;
   // 2. DP->CP gather: G_c = sum_p y_{c,p} * sigma_{5^-p}(E), one accumulator per (layer, c)
   const u32 g5inv = galois_of(-1, n);  // 5^-1 in the group of odd residues mod 2N
   dispatch_logn<LHmaPerm>(c->logn, c, g, (const u64*)y, spatial, d_mask, 0, l1, (const int32_t*)nullptr, g5inv, l1, 0,
@@ -1391,6 +1407,89 @@ int ffconv_layer_batch(he_ctx* c, int n_layers, const uint64_t* d_in, size_t in_
   Arena ar(c);
   return ffconv_run(c, n_layers, d_in, in_stride, level, desc, d_w1_filt, filt_stride, d_mask, d_w2_tab, o_c2, square,
                     d_out, ar, S(stream));
+}
+
+int he_densepack_hma(he_ctx* c, int n_layers, const uint64_t* d_in, size_t in_stride, int level,
+                     const he_conv_desc* desc, const uint64_t* d_filt, size_t filt_stride, uint64_t* d_acc,
+                     void* stream) {
+  if (!c || !d_in || !desc || !d_filt || !d_acc || n_layers < 1)
+    return fail(c, HE_EINVAL, "he_densepack_hma: bad arguments");
+  DPGeom geo;
+  int n_cls = 0;
+  if (!build_geom(c, desc, geo, n_cls)) return fail(c, HE_EINVAL, "he_densepack_hma: bad convolution geometry");
+  if (!level_ok(c, level)) return fail(c, HE_ELEVEL, "he_densepack_hma: level %d out of range", level);
+  if ((long long)n_layers * geo.per_layer > (1ll << 30)) return fail(c, HE_EINVAL, "he_densepack_hma: too many outputs");
+  geo.x_stride = in_stride;
+  geo.f_stride = filt_stride;
+  const int total = n_layers * geo.per_layer;
+  hipStream_t s = S(stream);
+  for (int o0 = 0; o0 < total; o0 += 65535) {
+    const int cn = std::min(65535, total - o0);
+    dispatch_logn<LDpHma>(c->logn, c, d_in, d_filt, d_acc + (size_t)o0 * 2 * level * c->n, level, o0, cn, geo, s);
+  }
+  c->counts = he_counts{};
+  c->counts.mulpc = (int64_t)total * geo.m_cts;
+  c->counts.addcc = (int64_t)total * (geo.m_cts - 1);
+  return check_launch(c, "he_densepack_hma");
+}
+
+int he_rotsum_groups(he_ctx* c, const he_rotsum_group* h_groups, int n_groups, void* stream) {
+  if (!c || !h_groups || n_groups < 1) return fail(c, HE_EINVAL, "he_rotsum_groups: bad arguments");
+  const int n = c->n;
+  size_t total = 0;
+  for (int g = 0; g < n_groups; ++g) {
+    const he_rotsum_group& gr = h_groups[g];
+    if (!gr.acc || gr.count < 0 || !level_ok(c, gr.level) || gr.step < 0 || gr.step > 30)
+      return fail(c, HE_EINVAL, "he_rotsum_groups: bad group %d", g);
+    if ((1ll << gr.step) % (n / 2) == 0) return fail(c, HE_EINVAL, "he_rotsum_groups: step 2^%d is the identity", gr.step);
+    total += (size_t)gr.count;
+  }
+  if (total == 0) return HE_OK;
+  std::vector<KsJob> jobs;
+  jobs.reserve(total);
+  for (int g = 0; g < n_groups; ++g) {
+    const he_rotsum_group& gr = h_groups[g];
+    const int k = 1 << gr.step;
+    const u32 gal = galois_of(k, n);
+    auto it = c->keys.find((int)gal);
+    if (it == c->keys.end()) return fail(c, HE_ENOKEY, "he_rotsum_groups: no rotation key for step %d", k);
+    const u32 ginv = galois_of(-k, n);
+    const size_t cstride = (size_t)2 * gr.level * n;
+    for (int i = 0; i < gr.count; ++i) {
+      u64* ct = gr.acc + (size_t)i * cstride;
+      jobs.push_back(KsJob{ct + (size_t)gr.level * n, ct, ct, it->second, gal, ginv, gr.level, 0});
+    }
+  }
+  Arena ar(c);
+  return rotate_jobs(c, jobs, EPI_ROTSUM, ar, S(stream));
+}
+
+int ffconv_tail_batch(he_ctx* c, int n_layers, const uint64_t* d_acc, int level, const he_conv_desc* desc,
+                      const uint64_t* d_mask, const uint64_t* d_w2_tab, int o_c2, int square, uint64_t* d_out,
+                      void* stream) {
+  if (!c || !d_acc || !desc || !d_mask || !d_w2_tab || !d_out || n_layers < 1 || o_c2 < 1 || desc->o_c < 1)
+    return fail(c, HE_EINVAL, "ffconv_tail_batch: bad arguments");
+  const int need = square ? 4 : 3;
+  if (level < need || level > c->big_l) return fail(c, HE_ELEVEL, "ffconv_tail_batch needs level >= %d (got %d)", need, level);
+  DPGeom geo;
+  int n_cls = 0;
+  if (!build_geom(c, desc, geo, n_cls)) return fail(c, HE_EINVAL, "ffconv_tail_batch: bad convolution geometry");
+  const int r = desc->o_c;
+  if ((long long)n_layers * r > 65535 || (long long)n_layers * o_c2 > 65535)
+    return fail(c, HE_EINVAL, "ffconv_tail_batch: too many layers for one call");
+  if (square && !c->keys.count(0)) return fail(c, HE_ENOKEY, "ffconv_tail_batch: no relinearisation key");
+  const int spatial = geo.out_h * geo.out_w;
+  const int n = c->n;
+  c->counts = he_counts{};
+  Arena ar(c);
+  hipStream_t s = S(stream);
+  const size_t cnt = (size_t)n_layers * r * spatial;
+  u64* y = ar.take<u64>(cnt * 2 * (level - 1) * n);
+  if (!y) return fail(c, HE_ENOMEM, "workspace too small for ffconv_tail_batch");
+  int e = rescale_batch(c, y, d_acc, (int)cnt, level, ar, s);
+  c->counts.rescale += (int64_t)cnt;
+  if (e) return e;
+  return ffconv_tail(c, n_layers, y, level - 1, spatial, r, d_mask, d_w2_tab, o_c2, square, d_out, ar, s);
 }
 
 size_t he_ffconv_workspace_need(const he_ctx* c, int n_layers, int level, const he_conv_desc* desc, int o_c2,

@@ -467,6 +467,48 @@ class HEContext:
                                               ctypes.byref(out_scale), _stream()), "he_conv_convpack")
         return Ct(out, out_scale.value)
 
+    # ---- layer pieces for iteration-level batching ------------------------------
+    def densepack_hma(self, xs: torch.Tensor, desc: HeConvDesc, filt: torch.Tensor, shared_filters: bool = True,
+                      out: torch.Tensor | None = None) -> torch.Tensor:
+        """MulPC part of a DensePack layer on xs[l] ([B][M][2][level][N]):
+        returns the unsummed accumulators [B * o_c * S][2][level][N]."""
+        n_layers = xs.shape[0]
+        level = xs.shape[-2]
+        oh = (desc.h + 2 * desc.pad - desc.d) // desc.stride + 1
+        ow = (desc.w + 2 * desc.pad - desc.d) // desc.stride + 1
+        total = n_layers * oh * ow * desc.o_c
+        if out is None:
+            out = torch.empty((total, 2, level, self.n), dtype=torch.int64, device="cuda")
+        f_stride = 0 if shared_filters else filt[0].numel()
+        self._check(self.lib.he_densepack_hma(self.h, n_layers, _ptr(xs), xs[0].numel(), level, ctypes.byref(desc),
+                                              _ptr(filt), f_stride, _ptr(out), _stream()), "he_densepack_hma")
+        return out
+
+    def rotsum_groups(self, groups):
+        """One rotate-and-add step for each (acc tensor [count][2][level][N], step)."""
+        arr = (_lib.HeRotsumGroup * len(groups))()
+        for i, (acc, step) in enumerate(groups):
+            if not (acc.is_cuda and acc.is_contiguous()):
+                raise HEError("rotsum_groups takes contiguous device tensors")
+            arr[i].acc = acc.data_ptr()
+            arr[i].level = acc.shape[-2]
+            arr[i].count = acc.numel() // (2 * acc.shape[-2] * self.n)
+            arr[i].step = int(step)
+        self._check(self.lib.he_rotsum_groups(self.h, arr, len(groups), _stream()), "he_rotsum_groups")
+
+    def ffconv_tail_batch(self, acc: torch.Tensor, n_layers: int, desc: HeConvDesc, mask: torch.Tensor,
+                          w2_tabs: torch.Tensor, o_c2: int, square: bool, out: torch.Tensor | None = None):
+        """Rescale + gather + 1x1 ConvPack (+ x^2) of summed W1 accumulators
+        acc [n_layers * r * S][2][level][N]; returns [n_layers][o_c2][2][..][N]."""
+        level = acc.shape[-2]
+        lvl_out = level - 2 - (1 if square else 0)
+        if out is None:
+            out = torch.empty((n_layers, o_c2, 2, lvl_out, self.n), dtype=torch.int64, device="cuda")
+        self._check(self.lib.ffconv_tail_batch(self.h, n_layers, _ptr(acc), level, ctypes.byref(desc), _ptr(mask),
+                                               _ptr(w2_tabs), o_c2, int(square), _ptr(out), _stream()),
+                    "ffconv_tail_batch")
+        return out
+
     def ffconv_layer_convpack(self, x: Ct, w1: np.ndarray, w2: np.ndarray, target_scale: float,
                               square: bool = False) -> Ct:
         """FFConv with both factors under ConvPack on the K Im2Col ciphertexts

@@ -142,3 +142,80 @@ def test_serial_mode_runs_one_batch_at_a_time():
     _sched({"dear": dear, "cheap": cheap}, "sjf", clk).run(reqs, 10.0, 100.0)
     assert reqs[0].t_done == pytest.approx(5.0, abs=2 * POLL)
     assert reqs[1].t_done == pytest.approx(5.01, abs=3 * POLL)  # waited for the long batch
+
+
+# ---- continuous batching (ContinuousServer) ------------------------------------
+from paper_2102_03494_amd.serve import ContinuousServer  # noqa: E402
+
+
+class FakeEngine:
+    """An engine whose requests each need `steps` ticks; a tick advances every
+    in-flight request by one step (up to `slots` in flight) and takes
+    `tick_s` of device time after the previous tick of any engine."""
+
+    def __init__(self, dev, steps, slots, tick_s):
+        self.dev, self.steps, self.slots, self.tick_s = dev, steps, slots, tick_s
+        self.waiting, self.flight = [], {}
+        self.ticks = []
+
+    def submit(self, r):
+        self.waiting.append(r)
+
+    def has_work(self):
+        return bool(self.waiting or self.flight)
+
+    def backlog(self):
+        return len(self.waiting) + len(self.flight)
+
+    def tick(self):
+        while self.waiting and len(self.flight) < self.slots:
+            r = self.waiting.pop(0)
+            self.flight[r.rid] = [r, 0]
+        if not self.flight:
+            return None
+        done = []
+        for rid in list(self.flight):
+            self.flight[rid][1] += 1
+            if self.flight[rid][1] == self.steps:
+                done.append(self.flight.pop(rid)[0])
+        self.ticks.append(sorted(self.flight) + [x.rid for x in done])
+        self.dev["busy_until"] = max(self.dev["busy_until"], self.dev["clock"].t) + self.tick_s
+        return done
+
+
+def _server(engines, clk, dev, ahead=1, order=None):
+    return ContinuousServer(engines, lambda cls: dev["busy_until"], lambda tok: clk.t >= tok - 1e-12,
+                            clk.now, clk.sleep, poll_s=POLL, ahead=ahead, order=order)
+
+
+def test_continuous_admits_arrivals_into_running_work():
+    """A request arriving while another is in flight joins at the next tick:
+    both advance together, and the later one finishes `steps` ticks after it
+    joined instead of after the first request's whole run."""
+    clk = Clock()
+    dev = {"busy_until": 0.0, "clock": clk}
+    eng = FakeEngine(dev, steps=10, slots=8, tick_s=0.01)
+    reqs = [Request(0, "a", 0.0), Request(1, "a", 0.035)]
+    rep = _server({"a": eng}, clk, dev).run(reqs, window_s=1.0, cap_s=5.0)
+    c = rep["classes"]["a"]
+    assert c["completed"] == 2 and rep["backlog_at_end"] == 0
+    # request 1 appears in a tick while request 0 is still in flight
+    assert any(0 in t and 1 in t for t in eng.ticks)
+    lat0, lat1 = reqs[0].t_done - reqs[0].t_arrival, reqs[1].t_done - reqs[1].t_arrival
+    assert lat0 == pytest.approx(0.10, abs=3 * POLL)
+    assert lat1 == pytest.approx(0.10, abs=0.01 + 3 * POLL)
+
+
+def test_continuous_interleaves_classes_and_respects_slots():
+    """Two classes alternate ticks (neither waits for the other's requests to
+    finish), and at most `slots` requests of a class are in flight."""
+    clk = Clock()
+    dev = {"busy_until": 0.0, "clock": clk}
+    short = FakeEngine(dev, steps=3, slots=2, tick_s=0.001)
+    long_ = FakeEngine(dev, steps=50, slots=1, tick_s=0.004)
+    reqs = [Request(i, "s", 0.002 * i) for i in range(5)] + [Request(100, "l", 0.0)]
+    rep = _server({"s": short, "l": long_}, clk, dev, order=["s", "l"]).run(reqs, window_s=1.0, cap_s=5.0)
+    assert rep["classes"]["s"]["completed"] == 5 and rep["classes"]["l"]["completed"] == 1
+    assert max(len(t) for t in short.ticks) <= 2
+    # every short request finishes before the long one
+    assert max(r.t_done for r in reqs[:5]) < reqs[5].t_done
