@@ -801,9 +801,8 @@ def main():
         "p_groups": pg, "split_streams": split,
         "hbm_gbs_algorithmic": bytes_layer * layers / (dom_busy_ms * 1e-3) / 1e9,
     }
-    tuning = {"source": ctx.tuning_source,
-              "p_groups": {lv: ctx.get_tuning("p_groups", lv) for lv in range(1, len(Q_BITS) + 1)},
-              "split_streams": split}
+    from paper_2102_03494_amd import tune as _tune
+    tuning = {"source": ctx.tuning_source, **_tune.chosen(ctx)}
 
     batched = None
     if args.batched_layers > 0:

@@ -118,9 +118,13 @@ const char *he_last_error(const he_ctx *ctx);
  * product into the special prime P at key-switch level `level` (1..L);
  * value 0 restores the built-in cost model.  knob "split_streams" (level
  * ignored; 1 by default, 0 or 1): run the rotate-and-sum of a DensePack
- * layer's outputs as two halves on two streams.  he_ctx_set_tuning returns
+ * layer's outputs as two halves on two streams.  knob "modup_halves" at
+ * key-switch level `level` (0: every level; -1 restores the default, which is
+ * 1 for N >= 16384, else 0): 1 runs ModUp as two half-ring workgroups per
+ * target (N >= 2048; a launch follows its largest level), 0 as one workgroup
+ * per target.  he_ctx_set_tuning returns
  * HE_EINVAL for an unknown knob or out-of-range level/value;
- * he_ctx_get_tuning returns the value in effect (>= 1) or a negative code. */
+ * he_ctx_get_tuning returns the value in effect (>= 0) or a negative code. */
 int he_ctx_set_tuning(he_ctx *ctx, const char *knob, int level, int value);
 int he_ctx_get_tuning(const he_ctx *ctx, const char *knob, int level);
 

@@ -765,6 +765,14 @@ int he_ctx_set_tuning(he_ctx* c, const char* knob, int level, int value) {
     c->split_streams = value;
     return HE_OK;
   }
+  if (std::strcmp(knob, "modup_halves") == 0) {
+    if (value < -1 || value > 1) return fail(c, HE_EINVAL, "he_ctx_set_tuning: modup_halves is -1, 0 or 1");
+    if (level < 0 || level > c->big_l) return fail(c, HE_EINVAL, "he_ctx_set_tuning: level %d out of range", level);
+    if (value == 1 && c->logn < HALF_MODUP_ANY_LOGN)
+      return fail(c, HE_EINVAL, "he_ctx_set_tuning: modup_halves needs N >= %d", 1 << HALF_MODUP_ANY_LOGN);
+    for (int lv = (level ? level : 1); lv <= (level ? level : c->big_l); ++lv) c->halves_set[lv] = value;
+    return HE_OK;
+  }
   if (std::strcmp(knob, "p_groups") != 0) return fail(c, HE_EINVAL, "he_ctx_set_tuning: unknown knob '%s'", knob);
   if (level < 1 || level > c->big_l || value < 0 || value > std::min(level, PG_MAX))
     return fail(c, HE_EINVAL, "he_ctx_set_tuning: p_groups %d out of range at level %d", value, level);
@@ -775,6 +783,11 @@ int he_ctx_set_tuning(he_ctx* c, const char* knob, int level, int value) {
 int he_ctx_get_tuning(const he_ctx* c, const char* knob, int level) {
   if (!c || !knob) return HE_EINVAL;
   if (std::strcmp(knob, "split_streams") == 0) return c->split_streams;
+  if (std::strcmp(knob, "modup_halves") == 0) {
+    const int lv = level ? level : c->big_l;
+    if (lv < 1 || lv > c->big_l) return HE_EINVAL;
+    return c->halves_set[lv] < 0 ? (c->logn >= HALF_MODUP_MIN_LOGN ? 1 : 0) : c->halves_set[lv];
+  }
   if (std::strcmp(knob, "p_groups") != 0 || level < 1 || level > c->big_l) return HE_EINVAL;
   return p_groups(c, level);
 }

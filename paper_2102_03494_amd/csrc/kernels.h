@@ -836,8 +836,96 @@ __device__ __forceinline__ void modup_ip_half_body(u64* lds, const u64* __restri
   }
 }
 
-// Rings from 2^HALF_MODUP_MIN_LOGN up run ModUp in halves.
+// Narrow targets of the half-ring ModUp (as modup_ip_half_body), with the key
+// half-rows of digit j (both components, packed 32-bit) copied
+// asynchronously into the staging array S = [key b | key a] before the
+// digit is loaded, as modup_ip_narrow_staged does for a whole limb: both
+// loads are in flight together and the products read the key from LDS.
+template <int LOGN>
+__device__ __forceinline__ void modup_ip_half_narrow_staged(u64* lds, u32* S, const u64* __restrict__ dcoef,
+                                                            const KsJob& jb, size_t b, u64* __restrict__ u,
+                                                            int lmax, int urows, int big_l, int t, int mi, int j0,
+                                                            int j1, int row, int h, const Mods& mods,
+                                                            const Tables& tb) {
+  constexpr int CLS = CLS_N32;
+  constexpr int E = 8;
+  constexpr int N = 1 << LOGN;
+  constexpr int NH = N / 2;
+  constexpr int T = NH / E;
+  const ModConst m = mods.m[mi];
+  const u64* key = jb.key;
+  const Tw<CLS> tw0 = tw_of<LOGN, CLS>(tb, mi, 0);
+  const u32 w1 = tw0.w[1];
+  const u32 w1sh = tw0.sh[1];
+  const Tw<CLS> twh = tw_half_of<LOGN, CLS>(tb, mi, h);
+  const int hoff = h * NH;
+  const int tid = opaque_tid();
+  const int wave0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x) & ~63;
+  const int i0 = lds_idx(tid);
+  u64 acc0[E], acc1[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) acc0[r] = acc1[r] = 0;
+  for (int j = j0; j < j1; ++j) {
+    const u32* kb = reinterpret_cast<const u32*>(key + (((size_t)j * 2 + 0) * (big_l + 1) + mi) * N) + hoff;
+    const u32* ka = reinterpret_cast<const u32*>(key + (((size_t)j * 2 + 1) * (big_l + 1) + mi) * N) + hoff;
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      copy_to_lds(kb + tid + r * T, S + r * T + wave0);
+      copy_to_lds(ka + tid + r * T, S + NH + r * T + wave0);
+    }
+    __builtin_amdgcn_sched_barrier(0);  // the copies are issued before the digit's loads
+    if (j == t) {
+      load_half_perm<LOGN, CLS, E>(lds, jb.d + (size_t)j * N, jb.ginv, (jb.flags & JOB_IN_PACKED) != 0, h);
+      lds_barrier();
+    } else {
+      lift_half<LOGN, CLS, E>(lds, dcoef + (b * lmax + j) * N, mods.m[j].q, m, h, w1, w1sh, tid);
+      ntt_fwd_lds<LOGN - 1, CLS, E>(lds, twh, mview<CLS>(m), opaque_tid());
+    }
+    wait_vm();
+    if (j1 - j0 <= 8) {
+      // transform outputs (< 4q) brought below 2q only: each product is below
+      // 2^61, so the 64-bit sums of up to 8 digits cannot overflow
+      const u32 q2 = 2u * (u32)m.q;
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        const u32 v = lds_getw_at<CLS>(lds, lds_step(i0, r, T));
+        const u32 dv = min(v, v - q2);
+        acc0[r] += (u64)dv * S[r * T + tid];
+        acc1[r] += (u64)dv * S[NH + r * T + tid];
+      }
+    } else {
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        const u32 dv = (u32)to_canon<CLS>(lds_getw_at<CLS>(lds, lds_step(i0, r, T)), m);
+        acc0[r] += (u64)dv * S[r * T + tid];
+        acc1[r] += (u64)dv * S[NH + r * T + tid];
+      }
+    }
+    lds_barrier();  // the copies of the next digit overwrite S
+  }
+  u64* u0 = u + ((b * 2 + 0) * urows + row) * N;
+  u64* u1 = u + ((b * 2 + 1) * urows + row) * N;
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int i = hoff + (int)threadIdx.x + r * T;
+    reinterpret_cast<u32*>(u0)[i] = (u32)reduce64(acc0[r], m);
+    reinterpret_cast<u32*>(u1)[i] = (u32)reduce64(acc1[r], m);
+  }
+}
+
+// Staging array of the half-ring ModUp in 32-bit words: the key half-rows of
+// one digit (2 N/2), or the half-ring transform buffer of the other class.
+template <int LOGN>
+constexpr int stage_words_half() {
+  return (2 << (LOGN - 1)) > 2 * lds_words<LOGN - 1, CLS_U64>() ? (2 << (LOGN - 1))
+                                                                   : 2 * lds_words<LOGN - 1, CLS_U64>();
+}
+
+// Rings from 2^HALF_MODUP_MIN_LOGN up run ModUp in halves unless the
+// context's "modup_halves" knob says otherwise; smaller rings (from 2^11)
+// run it in halves when the knob asks for it.
 constexpr int HALF_MODUP_MIN_LOGN = 14;
+constexpr int HALF_MODUP_ANY_LOGN = 11;
 template <int LOGN>
 constexpr int modup_half_threads() {
   return (1 << (LOGN - 1)) / 8;
@@ -851,9 +939,6 @@ template <int LOGN, int CA, int CB>
 __global__ void __launch_bounds__(modup_half_threads<LOGN>())
 k_ks_modup_half(const KsJob* __restrict__ jobs, int count, const u64* __restrict__ dcoef, u64* __restrict__ u,
                 int lmax, int pg, int big_l, Mods mods, Tables tb) {
-  constexpr int LW = lds_words<LOGN - 1, CA>() > lds_words<LOGN - 1, CB>() ? lds_words<LOGN - 1, CA>()
-                                                                            : lds_words<LOGN - 1, CB>();
-  __shared__ u64 lds[LW];
   const XcdSlot sl = xcd_slot(2 * (lmax + pg));
   if (sl.job >= count) return;
   const size_t b = sl.job;
@@ -863,13 +948,30 @@ k_ks_modup_half(const KsJob* __restrict__ jobs, int count, const u64* __restrict
   if (!modup_target(jb, sl.sub >> 1, lmax, pg, big_l, o)) return;
   const int h = sl.sub & 1;
   const int cls = (int)mods.m[o.mi].cls;
-  if (cls == CA)
-    modup_ip_half_body<LOGN, CA>(lds, dcoef, jb, b, u, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row, h, mods,
-                                 tb);
-  else if constexpr (CB != CA)
-    if (cls == CB)
-      modup_ip_half_body<LOGN, CB>(lds, dcoef, jb, b, u, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row, h,
+  if constexpr (CA == CLS_N32) {
+    // narrow targets: transform buffer lds + key staging S; targets of the
+    // other class use S as their transform buffer
+    __shared__ u64 lds[lds_words<LOGN - 1, CLS_N32>()];
+    __shared__ __align__(16) u32 S[stage_words_half<LOGN>()];
+    if (cls == CA)
+      modup_ip_half_narrow_staged<LOGN>(lds, S, dcoef, jb, b, u, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1,
+                                        o.row, h, mods, tb);
+    else if constexpr (CB != CA)
+      if (cls == CB)
+        modup_ip_half_body<LOGN, CB>(reinterpret_cast<u64*>(S), dcoef, jb, b, u, lmax, lmax + pg, big_l, o.t, o.mi,
+                                     o.j0, o.j1, o.row, h, mods, tb);
+  } else {
+    constexpr int LW = lds_words<LOGN - 1, CA>() > lds_words<LOGN - 1, CB>() ? lds_words<LOGN - 1, CA>()
+                                                                              : lds_words<LOGN - 1, CB>();
+    __shared__ u64 lds[LW];
+    if (cls == CA)
+      modup_ip_half_body<LOGN, CA>(lds, dcoef, jb, b, u, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row, h,
                                    mods, tb);
+    else if constexpr (CB != CA)
+      if (cls == CB)
+        modup_ip_half_body<LOGN, CB>(lds, dcoef, jb, b, u, lmax, lmax + pg, big_l, o.t, o.mi, o.j0, o.j1, o.row, h,
+                                     mods, tb);
+  }
 }
 
 enum { MODE_P = 0, MODE_LAST = 1 };

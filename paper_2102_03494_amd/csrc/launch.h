@@ -30,8 +30,10 @@ void LKsCore<LOGN>::run(he_ctx* c, const KsJob* jobs, int count, int lmax, int p
                   hipStream_t s, int pk, bool digits_done) {
   constexpr int T = NttGeom<LOGN>::T;
   const int n_cls = (int)c->has_cls[0] + (int)c->has_cls[1] + (int)c->has_cls[2];
-  // rings run in halves (HALF_MODUP_MIN_LOGN) leave the P limb to k_intt_last
-  const bool halves = LOGN >= HALF_MODUP_MIN_LOGN && n_cls <= 2;
+  // rings run in halves leave the P limb to k_intt_last
+  const int hs = c->halves_set[lmax];
+  const bool want_halves = hs < 0 ? LOGN >= HALF_MODUP_MIN_LOGN : hs != 0;
+  const bool halves = LOGN >= HALF_MODUP_ANY_LOGN && want_halves && n_cls <= 2;
   // with one P group, ModUp's P workgroups also write the coefficient-domain
   // P limb (rc), and no separate INTT launch is needed
   u64* rc1 = (pg == 1 && !halves) ? rc : nullptr;
@@ -49,7 +51,7 @@ void LKsCore<LOGN>::run(he_ctx* c, const KsJob* jobs, int count, int lmax, int p
   const unsigned grid = xcd_grid(lmax + pg, count);
   constexpr int TM = modup_threads<LOGN>();  // ModUp workgroup size
   static const char* names[3] = {"ks_modup_ip", "ks_modup_ip_f64", "ks_modup_ip_wide"};
-  if constexpr (LOGN >= HALF_MODUP_MIN_LOGN) {
+  if constexpr (LOGN >= HALF_MODUP_ANY_LOGN) {
     if (halves) {  // one launch, two workgroups (halves) per target
       Prof stage(c, "ks_modup_stage", s);
       const unsigned hgrid = xcd_grid(2 * (lmax + pg), count);

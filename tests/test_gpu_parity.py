@@ -171,6 +171,27 @@ def test_rotate_n16384_half_ring_modup(q_bits, p_bits):
     assert np.array_equal(got, S.rotate(p, octx, S.Ciphertext(low, 1.0), 1).c)
 
 
+@pytest.mark.parametrize("n,q_bits,p_bits", [(2048, (30,) * 4, 40), (8192, (30,) * 4, 40), (4096, (40,) * 3, 60)])
+def test_modup_halves_knob_bit_exact(n, q_bits, p_bits):
+    """ModUp as one workgroup per target or as two half-ring workgroups gives
+    the oracle's bits on smaller rings too (the knob the autotuner sets)."""
+    p = P.Params(n, q_bits, p_bits, 2.0**25)
+    octx = Wk.make_context(p, W, rotations=(3,))
+    gctx = _ctx(p, ws=1 << 27)
+    _client(gctx, (3,))
+    he = _he()
+    level = len(q_bits)
+    cts = np.stack([np.stack([np.stack([synth.rng(W, "test", 950 + i, c, t).integers(0, p.q[t], n, dtype=np.uint64)
+                                        for t in range(level)]) for c in range(2)]) for i in range(3)])
+    want = S.rotate(p, octx, S.Ciphertext(cts, 1.0), 3).c
+    for halves in (0, 1):
+        gctx.set_tuning("modup_halves", 0, halves)
+        assert gctx.get_tuning("modup_halves", 0) == halves
+        for pg in (1, 2):
+            gctx.set_tuning("p_groups", level, pg)
+            assert np.array_equal(_host(gctx.rotate(he.Ct(_dev(cts), 1.0), 3).data), want), (halves, pg)
+
+
 def test_uploaded_oracle_keys_rotate_bit_exact():
     """The server context gets only keys: the oracle makes them on the CPU (the
     client), they are uploaded from host memory in the exchange layout, and
