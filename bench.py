@@ -81,13 +81,16 @@ def width_class(q: int) -> str:
     return "n32" if q < (1 << 30) else ("f64" if q < (1 << 42) else "u64")
 
 
-def modup_ip_ops(count: int, level: int, n: int, moduli, pg: int) -> float:
+def modup_ip_ops(count: int, level: int, n: int, moduli, pg: int, halves: bool = False) -> float:
     """Algorithmic VALU ops of the ModUp + inner-product stage (every target
     prime of every width class, P split over pg digit groups) over `count`
     ciphertexts at `level`: per target, a lift and an NTT of each digit but
     its own, one key product per digit and output polynomial, one final
-    reduction per output coefficient; with one P group, the INTT of the P
-    limb (which then runs in the same launch)."""
+    reduction per output coefficient; with one P group and whole-limb
+    workgroups, the INTT of the P limb (which then runs in the same launch).
+    With half-ring workgroups the work is the same (the duplicated
+    first-stage products are not counted) and the P INTT runs in its own
+    kernel."""
     bfly = (n // 2) * int(math.log2(n))
     ops = 0.0
     for t in range(level):
@@ -98,7 +101,7 @@ def modup_ip_ops(count: int, level: int, n: int, moduli, pg: int) -> float:
     groups = -(-level // -(-level // pg))
     ops += level * (bfly * COST["bfly"][c] + n * COST["lift"][c] + 2 * n * COST["mac"][c])
     ops += groups * 2 * n * COST["fin"][c]
-    if groups == 1:  # the P workgroup also takes its limb back to the coefficient domain
+    if groups == 1 and not halves:  # the P workgroup also takes its limb back to the coefficient domain
         ops += 2 * (bfly * COST["bfly"][c] + n * COST["fin"][c])
     return ops * count
 
@@ -214,6 +217,10 @@ def hoisted_section(torch, steps: int):
     t_h = (time.perf_counter() - t0) / steps
     ip_ms, ip_launches = ctx.prof_read()
     ctx.prof_select(None)
+    # the variant with the inner product fused into ModDown (no u round trip)
+    ctx.set_tuning("hoist_fused", 0, 1)
+    t_fused, _ = timed(lambda: ctx.rotate_hoisted(ct, amounts), steps, 1, torch)
+    ctx.set_tuning("hoist_fused", 0, 0)
     out = torch.empty_like(ct.data)
     t0 = time.perf_counter()
     for k in amounts:
@@ -222,17 +229,28 @@ def hoisted_section(torch, steps: int):
     t_u = time.perf_counter() - t0
     limb = 8 * n
     m = len(amounts)
+    # the whole call: the input ciphertext once, then per rotation its key
+    # (2 L (L + 1) limbs) and its output (2 L limbs)
+    call_bytes = 2 * level * limb + m * (2 * level * limb + 2 * level * (level + 1) * limb)
+    # the inner-product kernel: per rotation its key and its 2 (L + 1) output
+    # rows, and the shared lifted digits once
     ip_bytes = m * (2 * level * (level + 1) * limb + 2 * (level + 1) * limb) + level * (level + 1) * limb
     avg = ip_ms / max(1, ip_launches)
     ach = ip_bytes / (avg * 1e-3) / 1e9
+    ach_call = call_bytes / t_h / 1e9
     return {
         "workload": "one ciphertext, N=16384, level 6 (6x40-bit + 60-bit P), 256 seeded rotation amounts",
         "hoisted_ms": t_h * 1e3, "unhoisted_ms": t_u * 1e3, "speedup": t_u / t_h,
+        "hoisted_fused_moddown_ms": t_fused * 1e3,
         "rotations_per_s": m / t_h,
-        "roofline": {"kernel": "k_ip_perm (key inner product of all 256 rotations, one launch)",
-                     "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic("ip_perm"), "avg_launch_ms": avg,
-                     "algorithmic_bytes_per_launch": ip_bytes},
+        "roofline": {"kernel": "he_rotate_hoisted end to end (one ModUp; the inner products of all 256 rotations "
+                               "in one launch; P INTT; ModDown)",
+                     "bound": "hbm", "achieved": ach_call, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach_call / HBM_PEAK_GBS, "traffic": None, "algorithmic_bytes_per_call": call_bytes},
+        "roofline_ip_kernel": {"kernel": "k_ip_perm (key inner product of all 256 rotations, one launch)",
+                               "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic("ip_perm"),
+                               "avg_launch_ms": avg, "algorithmic_bytes_per_launch": ip_bytes},
     }
 
 
@@ -530,7 +548,7 @@ def cifar_section(torch, steps: int, plain: bool, digests_path: str):
         err_ff = max(err_ff, float(np.abs(v - ref[:, :, o].ravel()).max()))
     pg = ctx.get_tuning("p_groups", level)
     n_dp = 8 * geom.spatial
-    ops = r_steps * modup_ip_ops(n_dp, level, n, ctx.moduli, pg)
+    ops = r_steps * modup_ip_ops(n_dp, level, n, ctx.moduli, pg, ctx.get_tuning("modup_halves", level) == 1)
     roof = {"kernel": "k_ks_modup_half<14, f64, wide>: ModUp NTTs + key inner product into the six 40-bit primes "
                       "(f64 class) and P (wide), two half-ring workgroups per target, one launch per rotate-and-add "
                       "step of the 8192 W1 outputs (two concurrent halves of the outputs when split_streams)",
@@ -772,8 +790,10 @@ def main():
     # the timed region holds, per layer, 12 rotate-and-add steps of the 288 W1
     # outputs (as two launches of 144 on two streams when split) and the 5
     # relinearisations of x^2 (level 2)
-    ops_layer = 12 * modup_ip_ops(288, level, N, ctx.moduli, pg) + \
-        modup_ip_ops(5, 2, N, ctx.moduli[:2] + ctx.moduli[-1:], ctx.get_tuning("p_groups", 2))
+    hv = ctx.get_tuning("modup_halves", level) == 1
+    ops_layer = 12 * modup_ip_ops(288, level, N, ctx.moduli, pg, hv) + \
+        modup_ip_ops(5, 2, N, ctx.moduli[:2] + ctx.moduli[-1:], ctx.get_tuning("p_groups", 2),
+                     ctx.get_tuning("modup_halves", 2) == 1)
     # the chain's accumulator is packed after its first step (all primes narrow)
     packed = all(q < (1 << 30) for q in ctx.moduli[:level])
     bytes_layer = modup_ip_bytes(288, level, N, ctx.moduli, pg) + \
@@ -788,9 +808,12 @@ def main():
     achieved_ops = ops_layer * layers / (dom_busy_ms * 1e-3)
     per_launch_ops = ops_per_launch / (avg_ms * 1e-3)
     roofline = {
-        "kernel": "k_ks_modup_ip2<13, narrow, f64>: ModUp NTTs + key inner product into the four 30-bit primes and "
-                  "P (f64, p_groups digit groups), one launch per rotate-and-add step of the 288 W1 outputs at level 4 "
-                  "(two concurrent launches of 144 when split_streams), plus one relinearisation launch per layer",
+        "kernel": ("k_ks_modup_half<13, narrow, f64>: ModUp NTTs + key inner product into the four 30-bit primes "
+                   "and P (f64), two half-ring workgroups per target" if hv else
+                   "k_ks_modup_ip2<13, narrow, f64>: ModUp NTTs + key inner product into the four 30-bit primes and "
+                   "P (f64), one workgroup per target") +
+                  ", one launch per rotate-and-add step of the 288 W1 outputs at level 4 (two concurrent launches "
+                  "of 144 when split_streams), plus one relinearisation launch per layer",
         "bound": "alu", "achieved": achieved_ops / 1e12, "peak": VALU_PEAK_OPS / 1e12,
         "unit": "Tops/s (VALU lane ops)", "frac": achieved_ops / VALU_PEAK_OPS,
         "traffic": measured_traffic("ks_modup_stage"),

@@ -120,9 +120,11 @@ const char *he_last_error(const he_ctx *ctx);
  * ignored; 1 by default, 0 or 1): run the rotate-and-sum of a DensePack
  * layer's outputs as two halves on two streams.  knob "modup_halves" at
  * key-switch level `level` (0: every level; -1 restores the default, which is
- * 1 for N >= 16384, else 0): 1 runs ModUp as two half-ring workgroups per
+ * 1 for N >= 8192, else 0): 1 runs ModUp as two half-ring workgroups per
  * target (N >= 2048; a launch follows its largest level), 0 as one workgroup
- * per target.  he_ctx_set_tuning returns
+ * per target.  knob "hoist_fused" (level ignored; 0 by default, 0 or 1): in
+ * he_rotate_hoisted, compute each rotation's inner-product rows inside its
+ * ModDown (1) or write them to the workspace first (0).  he_ctx_set_tuning returns
  * HE_EINVAL for an unknown knob or out-of-range level/value;
  * he_ctx_get_tuning returns the value in effect (>= 0) or a negative code. */
 int he_ctx_set_tuning(he_ctx *ctx, const char *knob, int level, int value);

@@ -765,6 +765,11 @@ int he_ctx_set_tuning(he_ctx* c, const char* knob, int level, int value) {
     c->split_streams = value;
     return HE_OK;
   }
+  if (std::strcmp(knob, "hoist_fused") == 0) {
+    if (value < 0 || value > 1) return fail(c, HE_EINVAL, "he_ctx_set_tuning: hoist_fused is 0 or 1");
+    c->hoist_fused = value;
+    return HE_OK;
+  }
   if (std::strcmp(knob, "modup_halves") == 0) {
     if (value < -1 || value > 1) return fail(c, HE_EINVAL, "he_ctx_set_tuning: modup_halves is -1, 0 or 1");
     if (level < 0 || level > c->big_l) return fail(c, HE_EINVAL, "he_ctx_set_tuning: level %d out of range", level);
@@ -783,6 +788,7 @@ int he_ctx_set_tuning(he_ctx* c, const char* knob, int level, int value) {
 int he_ctx_get_tuning(const he_ctx* c, const char* knob, int level) {
   if (!c || !knob) return HE_EINVAL;
   if (std::strcmp(knob, "split_streams") == 0) return c->split_streams;
+  if (std::strcmp(knob, "hoist_fused") == 0) return c->hoist_fused;
   if (std::strcmp(knob, "modup_halves") == 0) {
     const int lv = level ? level : c->big_l;
     if (lv < 1 || lv > c->big_l) return HE_EINVAL;
@@ -1236,11 +1242,14 @@ int he_rotate_hoisted(he_ctx* c, const uint64_t* d_in, int level, const int32_t*
   u64* dcoef = ar.take<u64>((size_t)level * n);
   u64* dhat = ar.take<u64>((size_t)level * (level + 1) * n);
   KsJob* d_jobs = ar.take<KsJob>(m);
-  const size_t per = (size_t)2 * (level + 1) * n + 2 * (size_t)n;
+  // fused: per rotation only the coefficient-domain P limb (2 N); else also
+  // the 2 (level + 1) inner-product rows
+  const bool fused = c->hoist_fused != 0;
+  const size_t per = (fused ? 0 : (size_t)2 * (level + 1) * n) + 2 * (size_t)n;
   const int chunk = (int)std::min<size_t>((size_t)m, ar.left() / 8 / (per + 64));
   if (!job1 || !dcoef || !dhat || !d_jobs || chunk < 1)
     return fail(c, HE_ENOMEM, "workspace too small for hoisted rotation");
-  u64* u = ar.take<u64>((size_t)chunk * 2 * (level + 1) * n);
+  u64* u = fused ? nullptr : ar.take<u64>((size_t)chunk * 2 * (level + 1) * n);
   u64* rc = ar.take<u64>((size_t)chunk * 2 * n);
   // the digits of c1 itself: a job with no permutation
   KsJob j1 = jobs[0];

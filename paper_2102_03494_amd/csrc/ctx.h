@@ -47,6 +47,7 @@ struct he_ctx {
   Tables tb() const { return Tables{d_tw, d_tw32, d_twf, d_twh, d_twh32, d_twhf}; }
   int pg_set[HE_MAXM + 1] = {};  // P groups per key-switch level (0 = cost model)
   int split_streams = 1;         // DensePack rotate-and-sum in two halves on two streams
+  int hoist_fused = 0;           // hoisted rotations: ModDown fused with the inner product (measured slower)
   // ModUp as two half-ring workgroups per target, per key-switch level
   // (-1: by ring size)
   int halves_set[HE_MAXM + 1] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};

@@ -924,7 +924,7 @@ constexpr int stage_words_half() {
 // Rings from 2^HALF_MODUP_MIN_LOGN up run ModUp in halves unless the
 // context's "modup_halves" knob says otherwise; smaller rings (from 2^11)
 // run it in halves when the knob asks for it.
-constexpr int HALF_MODUP_MIN_LOGN = 14;
+constexpr int HALF_MODUP_MIN_LOGN = 13;
 constexpr int HALF_MODUP_ANY_LOGN = 11;
 template <int LOGN>
 constexpr int modup_half_threads() {
@@ -1070,6 +1070,7 @@ constexpr int drop_threads() {
 }
 
 enum { EPI_STORE = 0, EPI_ROT = 1, EPI_ROTSUM = 2, EPI_RELIN = 3 };
+
 
 // Drop the last limb, for polynomial p = 2 b + comp (blockIdx.y) and kept
 // prime t (blockIdx.x):  val = (src_t - NTT(lift(rc_p))) * div^-1 mod q_t,
@@ -1302,6 +1303,167 @@ __global__ void k_ip_perm(const u64* __restrict__ dhat, const KsJob* __restrict_
   } else {
     u0[i] = s0;
     u1[i] = s1;
+  }
+}
+
+// Hoisted rotations with ModDown fused into the inner product, so the
+// 2 (level + 1) inner-product rows of a rotation never go to memory.  The
+// permutation sigma_g of the shared lifted digits is applied through LDS: a
+// workgroup loads a digit row coalesced into LDS and each thread reads its
+// entries at the permuted positions, instead of gathering them from memory.
+//
+// Lazy sums of products per width class: narrow 64-bit sums of products of
+// canonical residues (< 2^60 each, at most 15 digits), f64 unreduced sums of
+// centred products (below 8.2 q for at most 15 digits), wide residues.
+template <int CLS>
+struct IpAcc {
+  typedef std::conditional_t<CLS == CLS_N32, u64, word_t<CLS>> A;
+  static __device__ __forceinline__ void mac(A& acc, u64 dv, u64 k, const ModConst& m) {
+    if constexpr (CLS == CLS_N32) acc += (u64)(u32)dv * (u32)k;
+    else if constexpr (CLS == CLS_F64) acc += f64_mulmod(f64_from_u64(dv), f64_from_u64(k), m.qd, m.qinv);
+    else acc = add_mod(acc, mul_mod_t<false>(dv, k, m), m.q);
+  }
+  static __device__ __forceinline__ u64 canon(A acc, const ModConst& m) {
+    if constexpr (CLS == CLS_N32) return reduce64(acc, m);
+    else if constexpr (CLS == CLS_F64) return to_canon<CLS>(acc, m);
+    else return acc;
+  }
+};
+
+// Key residue i of row (digit j, component comp, modulus mi): narrow rows are
+// packed 32-bit words.
+__device__ __forceinline__ u64 key_at(const u64* key, int big_l, int j, int comp, int mi, int i, int n, bool narrow) {
+  const u64* row = key + (((size_t)j * 2 + comp) * (big_l + 1) + mi) * n;
+  return narrow ? (u64) reinterpret_cast<const u32*>(row)[i] : row[i];
+}
+
+// The rotation's P row of the inner product, for one polynomial comp, into
+// the coefficient domain: for each digit the P row of dhat is loaded into
+// LDS and read through sigma_g; the sum goes back to LDS, INTT, N^-1,
+// stored (packed when narrow) at rcoef.  grid xcd_grid(2, m): workgroup
+// (rotation r, polynomial comp).
+template <int LOGN, int CLS>
+__global__ void __launch_bounds__(NttGeom<LOGN>::T)
+k_hoist_p_intt(const u64* __restrict__ dhat, const KsJob* __restrict__ jobs, int m_rot, int level, int big_l,
+               u64* __restrict__ rcoef, Mods mods, Tables tb) {
+  constexpr int N = 1 << LOGN;
+  constexpr int T = NttGeom<LOGN>::T;
+  constexpr int E = 16;
+  __shared__ u64 lds[NttGeom<LOGN>::LDS];  // 64-bit residues of the digit rows, then the transform
+  const XcdSlot sl = xcd_slot(2);
+  if (sl.job >= m_rot) return;
+  const size_t r = sl.job;
+  const int comp = sl.sub;
+  const KsJob jb = jobs[r];
+  const ModConst m = mods.m[big_l];
+  if ((int)m.cls != CLS) return;
+  typedef IpAcc<CLS> IP;
+  typename IP::A acc[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) acc[e] = 0;
+  for (int j = 0; j < level; ++j) {
+    const u64* row = dhat + ((size_t)j * (level + 1) + level) * N;
+#pragma unroll
+    for (int e = 0; e < E; ++e) lds_putw<CLS_U64>(lds, (int)threadIdx.x + e * T, row[(int)threadIdx.x + e * T]);
+    __syncthreads();
+#pragma unroll 4
+    for (int e = 0; e < E; ++e) {
+      const int i = (int)threadIdx.x + e * T;
+      const u64 dv = lds_getw<CLS_U64>(lds, galois_src<LOGN>(i, jb.g));
+      IP::mac(acc[e], dv, key_at(jb.key, big_l, j, comp, big_l, i, N, m.narrow), m);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) lds_put<CLS>(lds, (int)threadIdx.x + e * T, IP::canon(acc[e], m));
+  inv_lds<LOGN, CLS>(lds, tb, big_l, m);
+  store_limb<LOGN, CLS, true>(rcoef + (r * 2 + comp) * N, lds, m, true);
+}
+
+// ModDown of the hoisted rotation into ciphertext prime t, half h of the
+// NTT-domain output, polynomial comp: the inner product of the t rows with
+// key component comp (digit half-rows through LDS and sigma_g, the key read
+// coalesced) is kept in registers; then the P limb's coefficients (rcoef)
+// are lifted to q_t with the transform's first stage fused (lift_half), the
+// N/2-point transform runs, and out = (ip - that) P^-1 (+ sigma_g(c0) for
+// c0).  grid xcd_grid(4 level, m): workgroup (rotation r, (comp level + t)
+// 2 + h).
+template <int LOGN, int CLS>
+__global__ void __launch_bounds__(modup_half_threads<LOGN>())
+k_hoist_drop(const u64* __restrict__ dhat, const KsJob* __restrict__ jobs, int m_rot, int level, int big_l,
+             const u64* __restrict__ rcoef, const u64* __restrict__ inv_tab, Mods mods, Tables tb) {
+  constexpr int N = 1 << LOGN;
+  constexpr int NH = N / 2;
+  constexpr int E = 8;
+  constexpr int T = NH / E;
+  constexpr bool NW = CLS == CLS_N32;
+  __shared__ u64 lds[NttGeom<LOGN - 1, E>::LDS];
+  const XcdSlot sl = xcd_slot(4 * level);
+  if (sl.job >= m_rot) return;
+  const size_t b = sl.job;
+  const int h = sl.sub & 1;
+  const int comp = (sl.sub >> 1) / level;
+  const int t = (sl.sub >> 1) - comp * level;
+  const KsJob jb = jobs[b];
+  const ModConst m = mods.m[t];
+  if ((int)m.cls != CLS) return;
+  typedef IpAcc<CLS> IP;
+  const int hoff = h * NH;
+  const int sh = h ^ (int)((jb.g >> 1) & 1u);  // the source half of sigma_g's output half h
+  typename IP::A acc[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) acc[e] = 0;
+  for (int j = 0; j < level; ++j) {
+    const u64* row = dhat + ((size_t)j * (level + 1) + t) * N + (size_t)sh * NH;
+    // the key entries of this digit are loaded together with the digit row
+    // (both in flight before the barrier)
+    u64 kv[E], dv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) kv[e] = key_at(jb.key, big_l, j, comp, t, hoff + (int)threadIdx.x + e * T, N, m.narrow);
+#pragma unroll
+    for (int e = 0; e < E; ++e) dv[e] = row[(int)threadIdx.x + e * T];
+#pragma unroll
+    for (int e = 0; e < E; ++e) lds_putw<CLS_U64>(lds, (int)threadIdx.x + e * T, dv[e]);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int i = hoff + (int)threadIdx.x + e * T;
+      IP::mac(acc[e], lds_getw<CLS_U64>(lds, galois_src<LOGN>(i, jb.g) - sh * NH), kv[e], m);
+    }
+    __syncthreads();
+  }
+  const Tw<CLS> tw0 = tw_of<LOGN, CLS>(tb, t, 0);
+  const word_t<CLS> w1 = tw0.w[1];
+  const word_t<CLS> w1sh = CLS == CLS_F64 ? word_t<CLS>(0) : tw0.sh[1];
+  lift_half<LOGN, CLS, E>(lds, rcoef + (b * 2 + comp) * N, mods.m[big_l].q, m, h, w1, w1sh, (int)threadIdx.x);
+  ntt_fwd_lds<LOGN - 1, CLS, E>(lds, tw_half_of<LOGN, CLS>(tb, t, h), mview<CLS>(m), opaque_tid());
+  const u64 iv = inv_tab[big_l * HE_MAXM + t];
+  const u64 ivs = inv_tab[HE_MAXM * HE_MAXM + big_l * HE_MAXM + t];
+  const int i0 = lds_idx((int)threadIdx.x);
+  u64 val[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int li = lds_step(i0, e, T);
+    const u64 ipv = IP::canon(acc[e], m);
+    if constexpr (CLS == CLS_F64) {
+      const double dlt = f64_from_u64(ipv) - lds_getw_at<CLS>(lds, li);
+      val[e] = to_canon<CLS>(f64_mulmod(dlt, f64_from_u64(iv), m.qd, m.qinv), m);
+    } else {
+      val[e] = shoupm<NW>(subm<NW>(ipv, to_canon<CLS>(lds_getw_at<CLS>(lds, li), m), m.q), iv, ivs, m.q);
+    }
+  }
+  u64* o = jb.out + ((size_t)comp * level + t) * N;
+  if (comp == 0) {
+    // sigma_g(c0) of this half through LDS (64-bit canonical words)
+    __syncthreads();
+    load_half_perm<LOGN, CLS_U64, E>(lds, jb.c + (size_t)t * N, jb.ginv, false, h);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      o[hoff + (int)threadIdx.x + e * T] = addm<NW>(lds_getw_at<CLS_U64>(lds, lds_step(i0, e, T)), val[e], m.q);
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) o[hoff + (int)threadIdx.x + e * T] = val[e];
   }
 }
 

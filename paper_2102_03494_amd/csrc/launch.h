@@ -207,6 +207,19 @@ template <int LOGN>
 void LHoisted<LOGN>::run(he_ctx* c, const KsJob* jobs, int m, int level, const u64* dhat, u64* u, u64* rc, hipStream_t s) {
   constexpr int T = NttGeom<LOGN>::T;
   constexpr int N = 1 << LOGN;
+  if (u == nullptr) {
+    // fused: the P row of each rotation's inner product to the coefficient
+    // domain, then ModDown with the other rows computed where they are used
+    {
+      Prof pr(c, "hoist_p_intt", s);
+      HE_FOR_CLASSES(1u << c->p_cls, (k_hoist_p_intt<LOGN, CLS><<<xcd_grid(2, m), T, 0, s>>>(
+                                         dhat, jobs, m, level, c->big_l, rc, c->mods, c->tb())));
+    }
+    Prof pr(c, "hoist_drop", s);
+    HE_FOR_CLASSES(c->q_mask, (k_hoist_drop<LOGN, CLS><<<xcd_grid(4 * level, m), modup_half_threads<LOGN>(), 0, s>>>(
+                                  dhat, jobs, m, level, c->big_l, rc, c->d_inv, c->mods, c->tb())));
+    return;
+  }
   {
     Prof pr(c, "ip_perm", s);
     k_ip_perm<LOGN><<<dim3(N / 256, level + 1, m), 256, 0, s>>>(dhat, jobs, u, level, c->big_l, c->mods);

@@ -302,9 +302,15 @@ def test_split_streams_do_not_change_bits():
         assert np.array_equal(outs[1][i], want.c[k]), i
 
 
-def test_rotate_hoisted_bit_exact():
+@pytest.mark.parametrize("chain", [None, SMALL40], ids=["30bit", "40bit"])
+@pytest.mark.parametrize("fused", [1, 0])
+def test_rotate_hoisted_bit_exact(chain, fused):
+    """Hoisted rotations with ModDown fused into the inner product (1) or
+    after it (0) give the bits of one-at-a-time rotations (the oracle's)."""
     steps = [1, 2, 5, 17, 255, -3]
-    p, octx, gctx, cl = _small_setup(rotations=steps)
+    p, octx, gctx, cl = _small_setup(rotations=steps, chain=chain)
+    gctx.set_tuning("hoist_fused", 0, fused)
+    assert gctx.get_tuning("hoist_fused", 0) == fused
     ct = _enc_batch(octx, p, 1)[0]
     got = _host(gctx.rotate_hoisted(_he().Ct(_dev(ct), p.scale), steps).data)
     for r, k in enumerate(steps):
