@@ -384,6 +384,163 @@ def convpack_convpack(params, keys, cts: scheme.Ciphertext, w1: np.ndarray, w2: 
     return z, counts
 
 
+# ---- Tap-style DensePack (hoisted rotations) ----------------------------------
+# A variant of the DensePack conv beyond the paper's own designs (Table I
+# counts R rotations per output; Sec. 3.2): instead of one rotate-and-sum
+# chain per output, each input ciphertext is rotated once per filter tap,
+# all those rotations share one digit decomposition, and plaintexts that
+# hold the tap's weights at the output slots do the rest.  Layout: input as
+# C10 (channel c of ciphertext m in block b = c - m B at slots b H W + h W +
+# w); output o's value for (i, j) at slot (s i) W + s j.
+
+def tap_shifts(geom: ConvGeom) -> list[int]:
+    """Left rotation of tap t = kh d + kw: it moves the input pixel
+    (s i - pad + kh, s j - pad + kw) of every block onto the output slot
+    (s i) W + s j of that block."""
+    return [(kh - geom.pad) * geom.w + (kw - geom.pad) for kh in range(geom.d) for kw in range(geom.d)]
+
+
+def tap_output_slots(geom: ConvGeom) -> np.ndarray:
+    """Slot of output (i, j), in output order (row-major)."""
+    return np.array([geom.stride * i * geom.w + geom.stride * j
+                     for i in range(geom.out_h) for j in range(geom.out_w)], dtype=np.int64)
+
+
+def tap_filter_slots(weights: np.ndarray, geom: ConvGeom, slots: int, o: int, m: int, t: int) -> np.ndarray:
+    """Masked weight plaintext of (output channel o, input ciphertext m, tap
+    t): in block b (channel c = m B + b) the weight W[kh][kw][c][o] at the
+    slot of every output whose tap t falls inside the image (zero padding
+    elsewhere), zero in all other slots."""
+    per = geom.channels_per_ct(slots)
+    kh, kw = divmod(t, geom.d)
+    hw = geom.h * geom.w
+    v = np.zeros(slots)
+    for c in range(m * per, min((m + 1) * per, geom.c_in)):
+        b = c - m * per
+        for i in range(geom.out_h):
+            y = geom.stride * i - geom.pad + kh
+            if not 0 <= y < geom.h:
+                continue
+            for j in range(geom.out_w):
+                x = geom.stride * j - geom.pad + kw
+                if 0 <= x < geom.w:
+                    v[b * hw + geom.stride * i * geom.w + geom.stride * j] = weights[kh, kw, c, o]
+    return v
+
+
+def tap_filters(params, weights: np.ndarray, geom: ConvGeom, level: int, pt_scale: float) -> np.ndarray:
+    """All tap plaintexts, NTT domain: (O, M, d^2, level, N)."""
+    slots = params.slots
+    o_c = weights.shape[3]
+    m_cts = geom.n_cts(slots)
+    out = np.empty((o_c, m_cts, geom.d * geom.d, level, params.n), dtype=np.uint64)
+    for o in range(o_c):
+        for m in range(m_cts):
+            for t in range(geom.d * geom.d):
+                out[o, m, t] = encode(tap_filter_slots(weights, geom, slots, o, m, t), params, level, pt_scale)
+    return out
+
+
+def tap_block_schedule(blocks: int, hw: int) -> list[tuple[str, int]]:
+    """Steps that sum the first `blocks` blocks of H W slots into block 0,
+    sum_{b < blocks} Rot(t, b H W), by the binary method over the bits of
+    `blocks` below the leading one: ("double", k H W) takes a k-block sum S
+    to S + Rot(S, k H W) (2k blocks), ("inc", H W) takes it to
+    t + Rot(S, H W) (k + 1 blocks).  No slot wraps past the last block."""
+    steps = []
+    k = 1
+    for bit in bin(blocks)[3:]:
+        steps.append(("double", k * hw))
+        k *= 2
+        if bit == "1":
+            steps.append(("inc", hw))
+            k += 1
+    return steps
+
+
+def tap_rotation_steps(geom: ConvGeom, slots: int) -> list[int]:
+    """Every rotation amount (mod slots, nonzero) a tap-style layer uses."""
+    amounts = {s % slots for s in tap_shifts(geom)}
+    amounts |= {a for _, a in tap_block_schedule(geom.channels_per_ct(slots), geom.h * geom.w)}
+    return sorted(amounts - {0})
+
+
+def tap_conv(params, keys, xs: scheme.Ciphertext, geom: ConvGeom, filters: np.ndarray, pt_scale: float,
+             counts: Counts | None = None) -> tuple[scheme.Ciphertext, Counts]:
+    """Tap-style DensePack conv of one input (xs.c: M ciphertexts).
+
+    1. Each input ciphertext x_m is rotated by every nonzero tap shift, the
+       rotations of one x_m hoisted over one digit decomposition
+       (scheme.rotate_hoisted); the zero shift is x_m itself.
+    2. t_o = sum_m sum_t F[o][m][t] * Rot(x_m, shift_t) (MulPC, AddCC):
+       block b of t_o holds, at each output slot, channel m B + b's part of
+       the dot product.
+    3. The blocks are summed into block 0 (tap_block_schedule), then one
+       rescale.  The rescale comes after all rotations, as for the
+       rotate-and-sum of C10.
+    Output (O cts at level - 1): output (i, j) of channel o at slot
+    (s i) W + s j; other slots hold partial sums and noise."""
+    counts = counts if counts is not None else Counts()
+    slots = params.slots
+    shifts = [s % slots for s in tap_shifts(geom)]
+    moved = []
+    for m in range(xs.c.shape[0]):
+        x = scheme.Ciphertext(xs.c[m], xs.scale)
+        nonzero = [s for s in shifts if s != 0]
+        rot = dict(zip(nonzero, scheme.rotate_hoisted(params, keys, x, nonzero)))
+        counts.rot += len(nonzero)
+        moved.append([x if s == 0 else rot[s] for s in shifts])
+    o_c = filters.shape[0]
+    blocks = geom.channels_per_ct(slots)
+    outs = []
+    for o in range(o_c):
+        t_o = None
+        for m, row in enumerate(moved):
+            for t, y in enumerate(row):
+                term = scheme.mul_plain(params, y, filters[o, m, t], pt_scale)
+                counts.mulpc += 1
+                if t_o is None:
+                    t_o = term
+                else:
+                    t_o = scheme.add(params, t_o, term)
+                    counts.addcc += 1
+        first = t_o
+        for kind, amount in tap_block_schedule(blocks, geom.h * geom.w):
+            r = scheme.rotate(params, keys, t_o, amount)
+            t_o = scheme.add(params, t_o if kind == "double" else first, r)
+            counts.rot += 1
+            counts.addcc += 1
+        outs.append(t_o.c)
+    z = scheme.rescale(params, scheme.Ciphertext(np.stack(outs), xs.scale * pt_scale))
+    counts.rescale += o_c
+    return z, counts
+
+
+def tap_output_mask_slots(geom: ConvGeom, slots: int) -> np.ndarray:
+    """E of the tap-style FFConv: 1 at every output slot (s i) W + s j."""
+    v = np.zeros(slots)
+    v[tap_output_slots(geom)] = 1.0
+    return v
+
+
+def tap_ffconv(params, keys, xs: scheme.Ciphertext, geom: ConvGeom, w1_filters: np.ndarray, w1_scale: float,
+               w2: np.ndarray, k_bits: int, mask_pt: np.ndarray, mask_scale: float, square: bool = False,
+               counts: Counts | None = None) -> tuple[scheme.Ciphertext, Counts]:
+    """FFConv with W1 as a tap-style DensePack conv (tap_conv, r outputs),
+    then C12's second half with one ciphertext per channel: G_c = y_c * E
+    (E = tap_output_mask_slots at mask_scale; it clears the partial sums
+    and leaves the outputs at their slots), Z_o = sum_c round(W2[c][o] 2^k)
+    G_c, rescale, and with `square` x^2 relinearised and rescaled.
+    Output: O_c ciphertexts, output (i, j) at slot (s i) W + s j, zero
+    elsewhere."""
+    counts = counts if counts is not None else Counts()
+    y, _ = tap_conv(params, keys, xs, geom, w1_filters, w1_scale, counts)
+    z, _ = gather_convpack(params, y, 1, w2, k_bits, mask_pt, mask_scale, counts)
+    if square:
+        z, _ = square_rescale(params, keys, z, counts)
+    return z, counts
+
+
 def combine_cp_to_dp(params, keys, z: scheme.Ciphertext, spatial: int, per_dense: int,
                      counts: Counts | None = None):
     """CP->DP: dense_m = sum_{o in block m} Rot(Z_o, -(o mod B)*S)."""

@@ -14,6 +14,11 @@
 * The standalone ConvPack layer (Table II) decrypts to the FP64 per-pixel
   matrix product, counts O_c K MulPC and O_c (K - 1) AddCC, lands on its
   target scale, returns its inputs for W = I and is linear in W.
+* Tap-style DensePack (hoisted tap rotations, masked weight plaintexts, a
+  block sum): the binary block schedule sums blocks without wrapping; the
+  dataflow run on plain slot vectors equals Eq. 1 exactly; encrypted, the
+  conv and the FFConv built on it decrypt to the FP64 reference with the
+  stated rotation and MulPC counts.
 """
 import math
 
@@ -313,3 +318,121 @@ def test_convpack_convpack_ffconv_matches_fp64_and_counts(square):
         got = ctx.decrypt(S.Ciphertext(z.c[o], z.scale))
         assert np.abs(got[: geom.spatial] - ref[:, :, o].reshape(-1)).max() < 1e-3
         assert np.abs(got[geom.spatial:]).max() < 1e-3
+
+
+@pytest.mark.parametrize("blocks", list(range(1, 21)))
+def test_tap_block_schedule_sums_blocks_without_wrap(blocks):
+    """The binary block-sum schedule, run on a plain slot vector (rotation =
+    np.roll), leaves sum_{b < blocks} block b in block 0, reads no slot at or
+    beyond blocks * H W, and uses floor(log2 B) doublings plus popcount(B) - 1
+    increments."""
+    hw = 7
+    slots = blocks * hw + 5
+    rng = np.random.default_rng(blocks)
+    t = np.zeros(slots)
+    t[: blocks * hw] = rng.normal(size=blocks * hw)
+    # poison the tail: any read of it shows up in block 0
+    t[blocks * hw:] = 1e6
+    s = t.copy()
+    sched = C.tap_block_schedule(blocks, hw)
+    for kind, amount in sched:
+        s = (s if kind == "double" else t) + np.roll(s, -amount)
+    want = t[: blocks * hw].reshape(blocks, hw).sum(axis=0)
+    assert np.allclose(s[:hw], want, rtol=0, atol=1e-9)
+    assert sum(k == "double" for k, _ in sched) == blocks.bit_length() - 1
+    assert sum(k == "inc" for k, _ in sched) == bin(blocks).count("1") - 1
+
+
+TAP_GEOMS = [((6, 6, 3), 3, 1, 1), ((9, 9, 1), 5, 2, 0), ((5, 5, 12), 3, 1, 1), ((8, 8, 1), 5, 2, 1),
+             ((7, 5, 2), 3, 2, 1)]
+
+
+@pytest.mark.parametrize("shape,d,stride,pad", TAP_GEOMS)
+def test_tap_layout_in_the_clear(shape, d, stride, pad):
+    """The tap-style dataflow on plain slot vectors (np.roll for Rot, float
+    products for MulPC): sum over ciphertexts and taps of
+    filter * roll(x_m, -shift), then the block schedule, equals Eq. 1's
+    convolution at every output slot.  Pins the shifts, the masked filter
+    layout and the output slots without any encryption."""
+    slots = 256
+    geom = C.ConvGeom(shape[0], shape[1], shape[2], d, stride, pad)
+    x = synth.image(W, shape)
+    w = synth.weights(W, 91, (d, d, shape[2], 3), 0.3)
+    xs = C.densepack_slots(x, geom, slots)
+    shifts = C.tap_shifts(geom)
+    ref = R.conv2d(x, w, stride, pad)
+    where = C.tap_output_slots(geom)
+    for o in range(3):
+        t = np.zeros(slots)
+        for m, xm in enumerate(xs):
+            for k, sh in enumerate(shifts):
+                t += C.tap_filter_slots(w, geom, slots, o, m, k) * np.roll(xm, -sh)
+        s = t.copy()
+        for kind, amount in C.tap_block_schedule(geom.channels_per_ct(slots), geom.h * geom.w):
+            s = (s if kind == "double" else t) + np.roll(s, -amount)
+        assert np.allclose(s[where], ref[:, :, o].reshape(-1), rtol=0, atol=1e-12)
+
+
+def _tap_setup(shape, d, stride, pad, relin=False, q=(30, 30, 30), level=3):
+    p = P.Params(512, q, 36, 2.0**25)
+    geom = C.ConvGeom(shape[0], shape[1], shape[2], d, stride, pad)
+    ctx = Wk.make_context(p, W, rotations=C.tap_rotation_steps(geom, p.slots), relin=relin)
+    x = synth.image(W, shape)
+    xs = S.Ciphertext(np.stack([Wk.encrypt_slots(ctx, v, level, p.scale, W, 600 + m).c
+                                for m, v in enumerate(C.densepack_slots(x, geom, p.slots))]), p.scale)
+    return p, geom, ctx, x, xs
+
+
+@pytest.mark.parametrize("shape,d,stride,pad", TAP_GEOMS)
+def test_tap_conv_matches_fp64_and_counts(shape, d, stride, pad):
+    """Tap-style DensePack decrypts to Eq. 1's conv within 1e-3 at the output
+    slots, lands on its target scale, and executes M (d^2 - 1) hoisted
+    rotations (d odd, pad = (d - 1) / 2: the centre tap needs none; else d^2
+    when no tap has shift 0), O len(schedule) block-sum rotations, O M d^2
+    MulPC and O rescales."""
+    o_c = 3
+    p, geom, ctx, x, xs = _tap_setup(shape, d, stride, pad)
+    w = synth.weights(W, 81, (d, d, shape[2], o_c), 0.2)
+    target = p.scale
+    pt_scale = p.q[2] * target / xs.scale
+    filt = C.tap_filters(p, w, geom, 3, pt_scale)
+    z, cnt = C.tap_conv(p, ctx, xs, geom, filt, pt_scale)
+    assert z.level == 2 and abs(z.scale / target - 1) < 1e-12
+    ref = R.conv2d(x, w, stride, pad)
+    where = C.tap_output_slots(geom)
+    for o in range(o_c):
+        got = ctx.decrypt(S.Ciphertext(z.c[o], z.scale))
+        assert np.abs(got[where] - ref[:, :, o].reshape(-1)).max() < 1e-3
+    m_cts = geom.n_cts(p.slots)
+    zero_tap = 1 if 0 in C.tap_shifts(geom) else 0
+    sched = C.tap_block_schedule(geom.channels_per_ct(p.slots), geom.h * geom.w)
+    assert cnt.rot == m_cts * (d * d - zero_tap) + o_c * len(sched)
+    assert cnt.mulpc == o_c * m_cts * d * d and cnt.rescale == o_c
+
+
+@pytest.mark.parametrize("square", [False, True])
+def test_tap_ffconv_matches_fp64(square):
+    """Tap-style FFConv (W1 tap-style DensePack, masked gather, 1x1 ConvPack
+    with 2^12-scaled integers, optional x^2) decrypts to the FP64 W1-then-W2
+    reference within 1e-3 at the output slots and to 0 elsewhere, on the
+    target scale."""
+    p, geom, ctx, x, xs = _tap_setup((6, 6, 3), 3, 1, 1, relin=square, q=(30,) * 5, level=5)
+    w1 = synth.weights(W, 71, (3, 3, 3, 2), 0.3)
+    w2 = synth.weights(W, 72, (2, 4), 0.5)
+    target = p.scale
+    w1_scale = p.q[4] * target / xs.scale
+    filt = C.tap_filters(p, w1, geom, 5, w1_scale)
+    t2 = C.pre_square_target(p, 3, target) if square else target
+    mask_scale = C.gather_mask_scale(p, 4, target, t2, 12)
+    mask = E.encode(C.tap_output_mask_slots(geom, p.slots), p, 4, mask_scale)
+    z, cnt = C.tap_ffconv(p, ctx, xs, geom, filt, w1_scale, w2, 12, mask, mask_scale, square=square)
+    assert z.level == (2 if square else 3) and abs(z.scale / target - 1) < 1e-9
+    ref = R.ffconv_reference(x, w1, w2, 1, 1, square=square)
+    where = C.tap_output_slots(geom)
+    rest = np.ones(p.slots, bool)
+    rest[where] = False
+    for o in range(4):
+        got = ctx.decrypt(S.Ciphertext(z.c[o], z.scale))
+        assert np.abs(got[where] - ref[:, :, o].reshape(-1)).max() < 1e-3
+        assert np.abs(got[rest]).max() < 1e-3
+    assert cnt.square == (4 if square else 0)
