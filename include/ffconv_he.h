@@ -239,11 +239,20 @@ int he_decode_coeffs(int n, const double *h_m, int n_values, double *h_z);
  *          sharing one digit decomposition (the Galois permutation is applied
  *          to the lifted digits); d_outs = [m][2][level][N].  Results are
  *          bit-identical to he_rotate.
+ * he_rotate_hoisted_batch: the same for `count` ciphertexts d_in
+ *          ([count][2][level][N]) and 1 <= m <= 64 steps: d_outs[i][r] =
+ *          Rot(d_in[i], h_steps[r]), [count][m][2][level][N]; one
+ *          decomposition per input ciphertext, all of them in a few shared
+ *          launches.  Bit-identical to he_rotate.  HE_EINVAL for a step
+ *          that is 0 mod N/2, HE_ENOKEY for a missing key (before any
+ *          launch); d_outs must not overlap d_in.
  * he_rotsum: in place, for j < r_steps: t <- t + Rot(t, 2^j), for `count`
  *          ciphertexts (the DensePack dot-product sum, Fig. 1b). */
 int he_rotate(he_ctx *ctx, uint64_t *d_out, const uint64_t *d_in, int count, int level, int k, void *stream);
 int he_rotate_hoisted(he_ctx *ctx, const uint64_t *d_in, int level, const int32_t *h_steps, int m,
                       uint64_t *d_outs, void *stream);
+int he_rotate_hoisted_batch(he_ctx *ctx, const uint64_t *d_in, int count, int level, const int32_t *h_steps, int m,
+                            uint64_t *d_outs, void *stream);
 int he_rotsum(he_ctx *ctx, uint64_t *d_cts, int count, int level, int r_steps, void *stream);
 
 /* ---- allocation-free rotation ----------------------------------------------
@@ -364,6 +373,63 @@ int he_conv_densepack_batch(he_ctx *ctx, int n_layers, const uint64_t *d_in, siz
 int he_conv_convpack(he_ctx *ctx, const uint64_t *d_in, int k, int level, const double *h_w,
                      int o_c, double in_scale, double target_scale, uint64_t *d_out, double *out_scale,
                      void *stream);
+
+/* ---- tap-style DensePack (hoisted rotations) ---------------------------------
+ * A variant of the DensePack conv of Table I / Sec. 3.2 that is not in the
+ * paper: instead of one rotate-and-sum chain of R rotations per output, each
+ * input ciphertext is rotated once per filter tap, all its rotations sharing
+ * one digit decomposition (hoisting), and plaintexts holding each tap's
+ * weights at the output slots combine them.
+ *   desc:   geometry (h, w, c_in, d, stride, pad; o_c outputs; r_steps
+ *           unused).  Needs d <= h, d <= w, d^2 <= 64, 2 pad <= d - 1,
+ *           h w <= N/2 (else HE_EINVAL).
+ *   d_in:   [n_batch][M][2][level][N], the DensePack layout of each input
+ *           (B = min(floor(N / (2 h w)), c_in) channels per ciphertext,
+ *           channel c = m B + b in block b at slots b h w + y w + x;
+ *           M = ceil(c_in / B)), all at in_scale.
+ *   d_filt: [o_c][M][d^2][pt_limbs][N] NTT-domain plaintexts (first `level`
+ *           limbs used) at pt_scale: plaintext (o, m, t = kh d + kw) holds
+ *           W[kh][kw][m B + b][o] in block b at the slot (s i) w + s j of
+ *           every output (i, j) whose tap (kh, kw) lies inside the image,
+ *           zero elsewhere.
+ *   1. x_m rotated left by every nonzero tap shift (kh - pad) w + (kw - pad)
+ *      (mod N/2), hoisted per input ciphertext (the zero shift is x_m);
+ *   2. t_o = sum_m sum_t d_filt[o][m][t] * Rot(x_m, shift_t);
+ *   3. blocks summed into block 0 by the binary method over the bits of B
+ *      below the leading one: "double" S <- S + Rot(S, k h w) (k -> 2k),
+ *      "inc" S <- t_o + Rot(S, h w) (k -> k + 1); no slot wraps;
+ *   4. one rescale.
+ * he_conv_tap: d_out [n_batch][o_c][2][level-1][N], output (i, j) of channel
+ *          o at slot (s i) w + s j (other slots hold partial sums);
+ *          *out_scale = in_scale * pt_scale / q_{level-1}.  Needs rotation
+ *          keys for the nonzero tap shifts and for the block steps.  Counts
+ *          per input: Rot M (#nonzero shifts) + o_c (#block steps), MulPC
+ *          o_c M d^2, AddCC o_c (M d^2 - 1 + #block steps), o_c rescales.
+ *          HE_ELEVEL unless 2 <= level <= L; HE_ESCALE for a scale that is
+ *          not finite and positive; HE_EINVAL when pt_limbs < level or a
+ *          batch needs more than 65535 outputs.
+ * ffconv_layer_tap: FFConv with W1 (desc->o_c = r) as he_conv_tap with
+ *          plaintexts d_w1 at w1_scale, then the second half of the FFConv
+ *          layer with one ciphertext per channel: G_c = y_c * E (d_mask: E,
+ *          one at every output slot, NTT domain, >= level-1 limbs, at
+ *          mask_scale; it clears the partial sums), Z_o = sum_c
+ *          round-half-away(h_w2[c*o_c2 + o] 2^k_bits) G_c, rescale, and with
+ *          `square` x^2 relinearised and rescaled.  d_out: [n_batch][o_c2][2]
+ *          [level-2 (-1 more if square)][N], output (i, j) at slot
+ *          (s i) w + s j, zero elsewhere; *out_scale = ((in_scale w1_scale /
+ *          q_{level-1}) mask_scale 2^k / q_{level-2}) (squared and divided by
+ *          q_{level-3} with square).  HE_ELEVEL unless level >= 3 (4 with
+ *          square); HE_ENOKEY without the relinearisation key when square.
+ * he_tap_workspace_need: workspace bytes for either call (o_c2 = 0: the
+ *          conv alone); 0 for a bad geometry or level. */
+size_t he_tap_workspace_need(he_ctx *ctx, int n_batch, int level, const he_conv_desc *desc, int o_c2, int square);
+int he_conv_tap(he_ctx *ctx, int n_batch, const uint64_t *d_in, int level, const he_conv_desc *desc,
+                const uint64_t *d_filt, int pt_limbs, double in_scale, double pt_scale, uint64_t *d_out,
+                double *out_scale, void *stream);
+int ffconv_layer_tap(he_ctx *ctx, int n_batch, const uint64_t *d_in, int level, const he_conv_desc *desc,
+                     const uint64_t *d_w1, int w1_limbs, double in_scale, double w1_scale, const uint64_t *d_mask,
+                     double mask_scale, const double *h_w2, int o_c2, int k_bits, int square, uint64_t *d_out,
+                     double *out_scale, void *stream);
 
 /* ffconv_layer_convpack (Section 4.2.2 "ConvPack for W1", Fig. 5; CP-HI2C-CP
  * with d = 1 in Tables III and IX): FFConv with both factors under ConvPack,

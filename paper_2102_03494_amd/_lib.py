@@ -74,6 +74,7 @@ SIGNATURES = {
     "he_decode_coeffs": (I, [I, DP, I, DP]),
     "he_rotate": (I, [P, P, P, I, I, I, P]),
     "he_rotate_hoisted": (I, [P, P, I, I32P, I, P, P]),
+    "he_rotate_hoisted_batch": (I, [P, P, I, I, I32P, I, P, P]),
     "he_rotsum": (I, [P, P, I, I, I, P]),
     "he_rotate_static": (I, [P, P, P, I, I, I, P]),
     "he_rotate_static_max_batch": (I, [P, I]),
@@ -87,6 +88,10 @@ SIGNATURES = {
     "ffconv_layer": (I, [P, P, I, ctypes.POINTER(HeConvDesc), P, P, DP, I, I, I, P, P]),
     "ffconv_layer_convpack": (I, [P, P, I, I, DP, I, DP, I, ctypes.c_double, ctypes.c_double, I, P, DP, P]),
     "he_int_weight_table": (I, [P, DP, I, I, I, P, P]),
+    "he_tap_workspace_need": (ctypes.c_size_t, [P, I, I, ctypes.POINTER(HeConvDesc), I, I]),
+    "he_conv_tap": (I, [P, I, P, I, ctypes.POINTER(HeConvDesc), P, I, ctypes.c_double, ctypes.c_double, P, DP, P]),
+    "ffconv_layer_tap": (I, [P, I, P, I, ctypes.POINTER(HeConvDesc), P, I, ctypes.c_double, ctypes.c_double, P,
+                             ctypes.c_double, DP, I, I, I, P, DP, P]),
     "ffconv_layer_batch": (I, [P, I, P, ctypes.c_size_t, I, ctypes.POINTER(HeConvDesc), P, ctypes.c_size_t, P, P,
                                I, I, P, P]),
     "he_ffconv_workspace_need": (ctypes.c_size_t, [P, I, I, ctypes.POINTER(HeConvDesc), I, I]),

@@ -441,12 +441,13 @@ int64_t round_half_away(double x) {
 // and its device table (scalar_table layout, 2 K o_c level u64) at
 // d_tab + l 2 K o_c level.
 int scalar_mac_dev(he_ctx* c, u64* out, const u64* in, int k, const u64* d_tab, int o_c, int level, int n_layers,
-                   size_t in_stride, hipStream_t s) {
+                   size_t in_stride, hipStream_t s, bool shared_tab = false) {
   if ((long long)n_layers * o_c > 65535) return fail(c, HE_EINVAL, "too many output ciphertexts for one launch");
   const size_t tab = (size_t)k * o_c * level;
   Prof pr(c, "scalar_mac", s);
   k_scalar_mac<<<dim3(c->n / 256, level, n_layers * o_c), 256, 0, s>>>(out, in, k, o_c, d_tab, d_tab + tab, level,
-                                                                       c->n, in_stride, 2 * tab, c->mods);
+                                                                       c->n, in_stride, shared_tab ? 0 : 2 * tab,
+                                                                       c->mods);
   return check_launch(c, "scalar_mac");
 }
 
@@ -504,7 +505,8 @@ size_t ffconv_need(const he_ctx* c, int n_layers, int level, int spatial, int r,
 }
 
 int ffconv_tail(he_ctx* c, int n_layers, const u64* y, int l1, int spatial, int r, const u64* d_mask,
-                const u64* d_w2tab, int o_c2, int square, u64* d_out, Arena& ar, hipStream_t s);
+                const u64* d_w2tab, int o_c2, int square, u64* d_out, Arena& ar, hipStream_t s,
+                bool shared_w2 = false);
 
 // FFConv over n_layers independent layers of one geometry (layer l: input at
 // d_in + l in_stride, W1 base filters at d_w1 + l f_stride, W2 integer table
@@ -537,9 +539,10 @@ int ffconv_run(he_ctx* c, int n_layers, const u64* d_in, size_t in_stride, int l
 
 // Steps 2-5 of ffconv_run from the rescaled W1 DensePack outputs y
 // ([n_layers][r][S][2][l1][N]): gather, 1x1 ConvPack, rescale, optional
-// square + relinearise + rescale.
+// square + relinearise + rescale.  shared_w2: every layer uses the one
+// table at d_w2tab.
 int ffconv_tail(he_ctx* c, int n_layers, const u64* y, int l1, int spatial, int r, const u64* d_mask,
-                const u64* d_w2tab, int o_c2, int square, u64* d_out, Arena& ar, hipStream_t s) {
+                const u64* d_w2tab, int o_c2, int square, u64* d_out, Arena& ar, hipStream_t s, bool shared_w2) {
   const int n = c->n;
   const int l2 = l1 - 1;
   const size_t B = (size_t)n_layers;
@@ -555,7 +558,7 @@ int ffconv_tail(he_ctx* c, int n_layers, const u64* y, int l1, int spatial, int 
                           n_layers * r, s);
   if ((e = check_launch(c, "gather"))) return e;
   // 3. 1x1 ConvPack with exact integer weights round(W2 * 2^k)
-  if ((e = scalar_mac_dev(c, z, g, r, d_w2tab, o_c2, l1, n_layers, (size_t)r * 2 * l1 * n, s))) return e;
+  if ((e = scalar_mac_dev(c, z, g, r, d_w2tab, o_c2, l1, n_layers, (size_t)r * 2 * l1 * n, s, shared_w2))) return e;
   // 4. rescale; 5. optional square + relinearise + rescale
   const int nz = n_layers * o_c2;
   if (!square) {
@@ -571,6 +574,171 @@ int ffconv_tail(he_ctx* c, int n_layers, const u64* y, int l1, int spatial, int 
   c->counts.rescale += (int64_t)nz * (square ? 2 : 1);
   c->counts.square += square ? nz : 0;
   return e;
+}
+
+// Rotations of n_in ciphertexts (ciphertext i at in + i in_stride,
+// [2][level][N]) by the m rotations of hk; the rotations of one ciphertext
+// share its digit decomposition and ModUp.  out = [n_in][m][2][level][N].
+// Ciphertexts go in passes that fit the workspace (a single ciphertext's
+// rotations in chunks when even one does not fit whole).
+int hoisted_batch(he_ctx* c, const u64* in, size_t in_stride, int n_in, int level, const HoistKeys& hk, int m,
+                  u64* out, Arena& ar, hipStream_t s) {
+  const int n = c->n;
+  const size_t per_ct = (size_t)level * n + (size_t)level * (level + 1) * n + 128;  // digits, lifted digits
+  const size_t per_rot = (size_t)2 * (level + 2) * n + 64;                         // u rows, ModDown input, job
+  const size_t left = ar.left() / 8;
+  size_t cc = std::min<size_t>({(size_t)n_in, (size_t)(32000 / m), left / (per_ct + (size_t)m * per_rot)});
+  size_t rch = cc * m;
+  if (cc < 1) {
+    cc = 1;
+    if (left < per_ct + (size_t)m * 8 + per_rot + 256)
+      return fail(c, HE_ENOMEM, "workspace too small for hoisted rotations at level %d", level);
+    rch = std::min<size_t>(m, (left - per_ct - (size_t)m * 8 - 256) / per_rot);
+  }
+  Arena sub = ar;
+  KsJob* jobs1 = sub.take<KsJob>(cc);
+  KsJob* jobs = sub.take<KsJob>(cc * m);
+  u64* dcoef = sub.take<u64>(cc * level * n);
+  u64* dhat = sub.take<u64>(cc * level * (level + 1) * n);
+  u64* u = sub.take<u64>(rch * 2 * (level + 1) * n);
+  u64* rc = sub.take<u64>(rch * 2 * n);
+  if (!jobs1 || !jobs || !dcoef || !dhat || !u || !rc)
+    return fail(c, HE_ENOMEM, "workspace too small for hoisted rotations at level %d", level);
+  const size_t ostride = (size_t)2 * level * n;
+  for (int i0 = 0; i0 < n_in; i0 += (int)cc) {
+    const int cn = std::min((int)cc, n_in - i0);
+    const u64* cin = in + (size_t)i0 * in_stride;
+    u64* cout = out + (size_t)i0 * m * ostride;
+    k_make_hoist_jobs<<<dim3((cn + 255) / 256, 1), 256, 0, s>>>(jobs1, cn, 1, cin, in_stride, cout, level, n, hk, 1);
+    k_make_hoist_jobs<<<dim3((cn + 255) / 256, m), 256, 0, s>>>(jobs, cn, m, cin, in_stride, cout, level, n, hk, 0);
+    dispatch_logn<LHoistUp>(c->logn, c, (const KsJob*)jobs1, cn, level, dcoef, dhat, s);
+    const int total = cn * m;
+    for (int r0 = 0; r0 < total; r0 += (int)rch) {
+      const int cm = std::min((int)rch, total - r0);
+      dispatch_logn<LHoisted>(c->logn, c, (const KsJob*)(jobs + r0), cm, level, (const u64*)dhat, u, rc, s, r0, m,
+                              (size_t)level * (level + 1) * n);
+    }
+  }
+  return check_launch(c, "hoisted rotations");
+}
+
+// ---- Tap-style DensePack ------------------------------------------------------
+// Input in the DensePack layout (channel c of ciphertext m in block
+// b = c - m B at slots b H W + h W + w); each ciphertext is rotated by the
+// d^2 tap shifts (kh - pad) W + (kw - pad), hoisted; the masked weight
+// plaintexts F[o][m][t] multiply and sum them; the blocks are summed into
+// block 0 by the binary schedule; one rescale.  Output (i, j) of channel o
+// at slot (s i) W + s j.
+
+struct TapPlan {
+  int per = 0, m_cts = 0, hw = 0, nrot = 0;
+  TapMap map{};
+  HoistKeys hk{};
+  std::vector<std::pair<int, int>> sched;  // (0: S + Rot(S, a), 1: t + Rot(S, a); a = rotation)
+  bool has_inc = false;
+};
+
+// need_keys false: the geometry only (for workspace sizes).
+int tap_plan(he_ctx* c, const char* who, const he_conv_desc* g, TapPlan& tp, bool need_keys = true) {
+  const int slots = c->n / 2;
+  if (g->h < 1 || g->w < 1 || g->c_in < 1 || g->d < 1 || g->stride < 1 || g->pad < 0 || 2 * g->pad > g->d - 1 ||
+      g->d > g->h || g->d > g->w || g->d * g->d > 64 || g->o_c < 1 || g->o_c > 65535 ||
+      (long long)g->h * g->w > slots)
+    return fail(c, HE_EINVAL, "%s: unsupported geometry (%dx%dx%d, d %d, stride %d, pad %d)", who, g->h, g->w, g->c_in,
+                g->d, g->stride, g->pad);
+  const int n = c->n;
+  tp.hw = g->h * g->w;
+  tp.per = std::min(slots / tp.hw, g->c_in);
+  tp.m_cts = (g->c_in + tp.per - 1) / tp.per;
+  const int d2 = g->d * g->d;
+  tp.nrot = 0;
+  for (int t = 0; t < d2; ++t) {
+    const int kh = t / g->d, kw = t % g->d;
+    int sh = ((kh - g->pad) * g->w + (kw - g->pad)) % slots;
+    if (sh < 0) sh += slots;
+    if (sh == 0) {
+      tp.map.idx[t] = -1;
+      continue;
+    }
+    const u32 gal = galois_of(sh, n);
+    auto it = c->keys.find((int)gal);
+    if (need_keys && it == c->keys.end()) return fail(c, HE_ENOKEY, "%s: no rotation key for tap shift %d", who, sh);
+    tp.hk.key[tp.nrot] = it == c->keys.end() ? nullptr : it->second;
+    tp.hk.g[tp.nrot] = gal;
+    tp.hk.ginv[tp.nrot] = galois_of(-sh, n);
+    tp.map.idx[t] = (signed char)tp.nrot;
+    ++tp.nrot;
+  }
+  tp.map.d2 = d2;
+  tp.map.m_cts = tp.m_cts;
+  tp.map.o_c = g->o_c;
+  tp.map.nrot = tp.nrot;
+  tp.sched.clear();
+  tp.has_inc = false;
+  int k = 1, top = 0;
+  while ((tp.per >> (top + 1)) != 0) ++top;
+  for (int bit = top - 1; bit >= 0; --bit) {
+    tp.sched.push_back({0, k * tp.hw});
+    k *= 2;
+    if ((tp.per >> bit) & 1) {
+      tp.sched.push_back({1, tp.hw});
+      tp.has_inc = true;
+      k += 1;
+    }
+  }
+  for (auto& st : tp.sched)
+    if (need_keys && !c->keys.count((int)galois_of(st.second, n)))
+      return fail(c, HE_ENOKEY, "%s: no rotation key for block step %d", who, st.second);
+  return HE_OK;
+}
+
+size_t tap_need(const he_ctx* c, const TapPlan& tp, int nb, int level) {
+  auto al = [](size_t elems) { return ((elems * 8 + 255) & ~(size_t)255); };
+  const size_t n = c->n, cs = 2 * (size_t)level * n;
+  const size_t o = (size_t)nb * tp.map.o_c;
+  size_t need = al((size_t)nb * tp.m_cts * tp.nrot * cs) + al(o * cs) * (tp.has_inc ? 2 : 1);
+  // one ciphertext's hoisting with all its rotations, and a key-switch chunk of the block sum
+  const size_t hoist = ((size_t)level * n + (size_t)level * (level + 1) * n + 128 +
+                        (size_t)tp.nrot * (2 * (level + 2) * n + 64)) * 8 + 4096;
+  const size_t ks = std::min<size_t>(o, 4096) * 8 *
+                    (ks_elems_per_job(level, p_groups(const_cast<he_ctx*>(c), level), (int)n) + 128);
+  return need + std::max(hoist, ks) + ((size_t)16 << 20);
+}
+
+// out = [nb][O][2][level - 1][N] from in = [nb][M][2][level][N]; filt =
+// [O][M][d^2][pt_limbs][N]; adds its counts.
+int tap_run(he_ctx* c, const TapPlan& tp, int nb, const u64* in, int level, const u64* filt, int pt_limbs, u64* out,
+            Arena& ar, hipStream_t s) {
+  const int n = c->n;
+  const int o_c = tp.map.o_c;
+  const size_t cs = (size_t)2 * level * n;
+  const int n_in = nb * tp.m_cts;
+  const int n_out = nb * o_c;
+  u64* rot = tp.nrot ? ar.take<u64>((size_t)n_in * tp.nrot * cs) : nullptr;
+  u64* t = ar.take<u64>((size_t)n_out * cs);
+  u64* t0 = tp.has_inc ? ar.take<u64>((size_t)n_out * cs) : nullptr;
+  if ((tp.nrot && !rot) || !t || (tp.has_inc && !t0)) return fail(c, HE_ENOMEM, "workspace too small for the tap-style layer");
+  int e = HE_OK;
+  if (tp.nrot && (e = hoisted_batch(c, in, cs, n_in, level, tp.hk, tp.nrot, rot, ar, s))) return e;
+  dispatch_logn<LTapHma>(c->logn, c, in, (const u64*)rot, filt, t, level, pt_limbs, tp.map, nb, s);
+  if ((e = check_launch(c, "tap_hma"))) return e;
+  if (tp.has_inc && hipMemcpyAsync(t0, t, (size_t)n_out * cs * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return fail(c, HE_EDEVICE, "tap-style layer: device copy failed");
+  for (auto& st : tp.sched) {
+    e = rotate_batch(c, t, t, n_out, level, st.second, st.first == 0 ? EPI_ROTSUM : EPI_ROT, ar, s);
+    if (!e && st.first == 1) {
+      k_add<<<dim3(n / 256, level, n_out), 256, 0, s>>>(t, t0, t, level, n, c->mods);
+      e = check_launch(c, "tap-style block sum");
+    }
+    if (e) return e;
+  }
+  if ((e = rescale_batch(c, out, t, n_out, level, ar, s))) return e;
+  const int64_t d2 = tp.map.d2, steps = (int64_t)tp.sched.size();
+  c->counts.rot += (int64_t)n_in * tp.nrot + (int64_t)n_out * steps;
+  c->counts.mulpc += (int64_t)n_out * tp.m_cts * d2;
+  c->counts.addcc += (int64_t)n_out * (tp.m_cts * d2 - 1 + steps);
+  c->counts.rescale += n_out;
+  return HE_OK;
 }
 
 }  // namespace
@@ -1257,12 +1425,112 @@ int he_rotate_hoisted(he_ctx* c, const uint64_t* d_in, int level, const int32_t*
   int e = upload(c, job1, &j1, sizeof(KsJob), s);
   if (!e) e = upload(c, d_jobs, jobs.data(), (size_t)m * sizeof(KsJob), s);
   if (e) return e;
-  dispatch_logn<LHoistUp>(c->logn, c, (const KsJob*)job1, d_in + (size_t)level * n, level, dcoef, dhat, s);
+  dispatch_logn<LHoistUp>(c->logn, c, (const KsJob*)job1, 1, level, dcoef, dhat, s);
   for (int r0 = 0; r0 < m; r0 += chunk) {
     const int cm = std::min(chunk, m - r0);
     dispatch_logn<LHoisted>(c->logn, c, (const KsJob*)(d_jobs + r0), cm, level, (const u64*)dhat, u, rc, s);
   }
   return check_launch(c, "he_rotate_hoisted");
+}
+
+int he_rotate_hoisted_batch(he_ctx* c, const uint64_t* d_in, int count, int level, const int32_t* h_steps, int m,
+                            uint64_t* d_outs, void* stream) {
+  if (!c || !d_in || !h_steps || !d_outs || count < 1 || m < 1 || m > MAX_HOIST || !level_ok(c, level))
+    return fail(c, HE_EINVAL, "he_rotate_hoisted_batch: bad arguments");
+  if ((long long)count * m > ((long long)1 << 31) / (2 * level * (long long)c->n))
+    return fail(c, HE_EINVAL, "he_rotate_hoisted_batch: too many outputs");
+  const int n = c->n;
+  HoistKeys hk{};
+  for (int r = 0; r < m; ++r) {
+    const u32 g = galois_of(h_steps[r], n);
+    auto it = c->keys.find((int)g);
+    if (g == 1 || it == c->keys.end())
+      return fail(c, g == 1 ? HE_EINVAL : HE_ENOKEY, "he_rotate_hoisted_batch: no key for step %d", h_steps[r]);
+    hk.key[r] = it->second;
+    hk.g[r] = g;
+    hk.ginv[r] = galois_of(-h_steps[r], n);
+  }
+  Arena ar(c);
+  return hoisted_batch(c, d_in, (size_t)2 * level * n, count, level, hk, m, d_outs, ar, S(stream));
+}
+
+size_t he_tap_workspace_need(he_ctx* c, int n_batch, int level, const he_conv_desc* desc, int o_c2, int square) {
+  if (!c || !desc || n_batch < 1 || level < 2 || level > c->big_l) return 0;
+  TapPlan tp;
+  if (tap_plan(c, "he_tap_workspace_need", desc, tp, false)) return 0;
+  size_t need = tap_need(c, tp, n_batch, level);
+  if (o_c2 > 0) {  // the FFConv tail after the r W1 outputs at level - 1
+    auto al = [](size_t elems) { return ((elems * 8 + 255) & ~(size_t)255); };
+    const size_t n = c->n, l1 = level - 1, l2 = level - 2, nb = n_batch;
+    need += al(nb * desc->o_c * 2 * l1 * n) * 2 + al(nb * o_c2 * 2 * l1 * n) +
+            (square ? 2 * al(nb * o_c2 * 2 * l2 * n) : 0) + al(2 * (size_t)desc->o_c * o_c2 * l1);
+  }
+  return need;
+}
+
+int he_conv_tap(he_ctx* c, int n_batch, const uint64_t* d_in, int level, const he_conv_desc* desc,
+                const uint64_t* d_filt, int pt_limbs, double in_scale, double pt_scale, uint64_t* d_out,
+                double* out_scale, void* stream) {
+  if (!c || !d_in || !desc || !d_filt || !d_out || !out_scale || n_batch < 1 || pt_limbs < 1)
+    return fail(c, HE_EINVAL, "he_conv_tap: bad arguments");
+  if (level < 2 || level > c->big_l) return fail(c, HE_ELEVEL, "he_conv_tap needs 2 <= level <= L (got %d)", level);
+  if (pt_limbs < level) return fail(c, HE_EINVAL, "he_conv_tap: plaintexts have %d limbs, level is %d", pt_limbs, level);
+  if (!scale_ok(in_scale) || !scale_ok(pt_scale))
+    return fail(c, HE_ESCALE, "he_conv_tap: scales %.17g, %.17g", in_scale, pt_scale);
+  TapPlan tp;
+  int e = tap_plan(c, "he_conv_tap", desc, tp);
+  if (e) return e;
+  if ((long long)n_batch * desc->o_c > 65535 || (long long)n_batch * tp.m_cts > 65535)
+    return fail(c, HE_EINVAL, "he_conv_tap: batch too large for one call");
+  c->counts = he_counts{};
+  Arena ar(c);
+  e = tap_run(c, tp, n_batch, d_in, level, d_filt, pt_limbs, d_out, ar, S(stream));
+  if (!e) *out_scale = in_scale * pt_scale / (double)c->moduli[level - 1];
+  return e;
+}
+
+int ffconv_layer_tap(he_ctx* c, int n_batch, const uint64_t* d_in, int level, const he_conv_desc* desc,
+                     const uint64_t* d_w1, int w1_limbs, double in_scale, double w1_scale, const uint64_t* d_mask,
+                     double mask_scale, const double* h_w2, int o_c2, int k_bits, int square, uint64_t* d_out,
+                     double* out_scale, void* stream) {
+  if (!c || !d_in || !desc || !d_w1 || !d_mask || !h_w2 || !d_out || !out_scale || n_batch < 1 || o_c2 < 1 ||
+      k_bits < 0 || k_bits > 40 || w1_limbs < 1)
+    return fail(c, HE_EINVAL, "ffconv_layer_tap: bad arguments");
+  const int need = square ? 4 : 3;
+  if (level < need || level > c->big_l)
+    return fail(c, HE_ELEVEL, "ffconv_layer_tap needs %d <= level <= L (got %d)", need, level);
+  if (w1_limbs < level) return fail(c, HE_EINVAL, "ffconv_layer_tap: W1 plaintexts have %d limbs, level is %d", w1_limbs, level);
+  if (square && !c->keys.count(0)) return fail(c, HE_ENOKEY, "ffconv_layer_tap: no relinearisation key");
+  if (!scale_ok(in_scale) || !scale_ok(w1_scale) || !scale_ok(mask_scale))
+    return fail(c, HE_ESCALE, "ffconv_layer_tap: scales %.17g, %.17g, %.17g", in_scale, w1_scale, mask_scale);
+  TapPlan tp;
+  int e = tap_plan(c, "ffconv_layer_tap", desc, tp);
+  if (e) return e;
+  const int r = desc->o_c;
+  if ((long long)n_batch * r > 65535 || (long long)n_batch * o_c2 > 65535 || (long long)n_batch * tp.m_cts > 65535)
+    return fail(c, HE_EINVAL, "ffconv_layer_tap: batch too large for one call");
+  std::vector<int64_t> w((size_t)r * o_c2);
+  for (size_t i = 0; i < w.size(); ++i) {
+    const double x = std::ldexp(h_w2[i], k_bits);
+    if (!(std::fabs(x) < 4.0e18)) return fail(c, HE_EINVAL, "ffconv_layer_tap: W2 weight not finite or too large");
+    w[i] = round_half_away(x);
+  }
+  const int n = c->n;
+  hipStream_t s = S(stream);
+  c->counts = he_counts{};
+  Arena ar(c);
+  std::vector<u64> tab = scalar_table(c, w, level - 1);
+  u64* d_tab = ar.take<u64>(tab.size());
+  u64* y = ar.take<u64>((size_t)n_batch * r * 2 * (level - 1) * n);
+  if (!d_tab || !y) return fail(c, HE_ENOMEM, "workspace too small for ffconv_layer_tap");
+  if ((e = upload(c, d_tab, tab.data(), tab.size() * 8, s))) return e;
+  if ((e = tap_run(c, tp, n_batch, d_in, level, d_w1, w1_limbs, y, ar, s))) return e;
+  if ((e = ffconv_tail(c, n_batch, y, level - 1, 1, r, d_mask, d_tab, o_c2, square, d_out, ar, s, true))) return e;
+  const double y_scale = in_scale * w1_scale / (double)c->moduli[level - 1];
+  double z_scale = y_scale * mask_scale * std::ldexp(1.0, k_bits) / (double)c->moduli[level - 2];
+  if (square) z_scale = z_scale * z_scale / (double)c->moduli[level - 3];
+  *out_scale = z_scale;
+  return HE_OK;
 }
 
 int he_square(he_ctx* c, uint64_t* d_out, const uint64_t* d_in, int count, int level, void* stream) {

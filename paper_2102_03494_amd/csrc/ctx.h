@@ -239,11 +239,18 @@ struct LKeygen {
 };
 template <int LOGN>
 struct LHoistUp {
-  static void run(he_ctx* c, const KsJob* job1, const u64* c1, int level, u64* dcoef, u64* dhat, hipStream_t s);
+  static void run(he_ctx* c, const KsJob* jobs1, int count, int level, u64* dcoef, u64* dhat, hipStream_t s);
 };
 template <int LOGN>
 struct LHoisted {
-  static void run(he_ctx* c, const KsJob* jobs, int m, int level, const u64* dhat, u64* u, u64* rc, hipStream_t s);
+  static void run(he_ctx* c, const KsJob* jobs, int m, int level, const u64* dhat, u64* u, u64* rc, hipStream_t s,
+                  int job_base = 0, int per_ct = 1 << 30, size_t dstride = 0);
+};
+struct TapMap;
+template <int LOGN>
+struct LTapHma {
+  static void run(he_ctx* c, const u64* x, const u64* rot, const u64* filt, u64* out, int level, int pt_limbs,
+                  const TapMap& tm, int n_b, hipStream_t s);
 };
 
 }  // namespace he

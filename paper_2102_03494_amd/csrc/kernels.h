@@ -1248,28 +1248,37 @@ __device__ __forceinline__ void modup_store_body(u64* lds, const u64* __restrict
   store_limb<LOGN, CLS>(out, lds, m, false);
 }
 
+// grid dim3(level + 1, level, count): ciphertext z = blockIdx.z of a batch,
+// its c1 at jobs[z].d, its digits at dcoef + z level N (k_ks_digits' layout)
+// and its lifted digits stored at dhat + z level (level + 1) N.
 template <int LOGN, int CLS>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
-k_modup_store(const u64* __restrict__ dcoef, const u64* __restrict__ c1, u64* __restrict__ dhat, int level, int big_l,
-              Mods mods, Tables tb) {
+k_modup_store(const u64* __restrict__ dcoef, const KsJob* __restrict__ jobs, u64* __restrict__ dhat, int level,
+              int big_l, Mods mods, Tables tb) {
+  constexpr int N = 1 << LOGN;
   __shared__ u64 lds[lds_words<LOGN, CLS>()];
   const int mi = ((int)blockIdx.x < level) ? (int)blockIdx.x : big_l;
   if ((int)mods.m[mi].cls != CLS) return;
-  modup_store_body<LOGN, CLS>(lds, dcoef, c1, dhat, level, big_l, mods, tb);
+  const size_t z = blockIdx.z;
+  modup_store_body<LOGN, CLS>(lds, dcoef + z * level * N, jobs[z].d, dhat + z * level * (level + 1) * N, level, big_l,
+                              mods, tb);
 }
 
 // Inner product of the shared lifted digits, permuted per rotation, with
 // that rotation's key: u[r][c][t][i] = sum_j dhat[j][t][src_{g_r}(i)] *
 // key_r[j][c][m_t][i], with (key_r, g_r) from jobs[r].  The products are
 // summed at full width (64-bit for narrow primes, 128-bit otherwise) and
-// reduced once.  grid (N / 256, level + 1, m).
+// reduced once.  grid (N / 256, level + 1, m).  Batches of ciphertexts:
+// job r belongs to ciphertext (job_base + r) / per_ct, whose lifted digits
+// start dstride words after the previous one's.
 template <int LOGN>
 __global__ void k_ip_perm(const u64* __restrict__ dhat, const KsJob* __restrict__ jobs, u64* __restrict__ u,
-                          int level, int big_l, Mods mods) {
+                          int level, int big_l, Mods mods, int job_base, int per_ct, size_t dstride) {
   constexpr int N = 1 << LOGN;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int t = blockIdx.y;
   const size_t r = blockIdx.z;
+  dhat += (size_t)((job_base + (int)r) / per_ct) * dstride;
   const int mi = (t < level) ? t : big_l;
   const ModConst m = mods.m[mi];
   const KsJob jb = jobs[r];
@@ -1474,6 +1483,13 @@ struct ChainKeys {
   u32 g[MAX_CHAIN], ginv[MAX_CHAIN];
 };
 
+// Keys and Galois elements of the rotations hoisted over one decomposition.
+constexpr int MAX_HOIST = 64;
+struct HoistKeys {
+  const u64* key[MAX_HOIST];
+  u32 g[MAX_HOIST], ginv[MAX_HOIST];
+};
+
 // ---------------------------------------------------------------------------
 // Elementwise kernels: blockIdx.x * blockDim.x + threadIdx.x = coefficient,
 // blockIdx.y = limb, blockIdx.z = item.
@@ -1632,6 +1648,100 @@ k_hma_perm(u64* __restrict__ acc, const u64* __restrict__ cts, int K, const u64*
 #pragma unroll
   for (int e = 0; e < HMA_SLICES; ++e) v = add_mod(v, part[c][e][lane], m.q);
   a[i] = v;
+}
+
+// Tap-style DensePack MulPC: out[b][o] = sum_{m < M} sum_{k < d^2}
+// F[o][m][k] * X(b, m, k), where X(b, m, k) is the input x[b][m] for the tap
+// with shift 0 (idx[k] < 0) and its hoisted rotation
+// rot[(b M + m) nrot + idx[k]] otherwise.  F: [O][M][d^2][pt_limbs][N];
+// x, rot, out: ciphertexts [2][level][N].  grid (N / 256, level,
+// n_b ceil(O / TAP_OT)), 256 threads: a thread holds one coefficient of up to
+// TAP_OT outputs, so each product term reads 2 ciphertext words and one
+// plaintext word per output.  Narrow primes sum 15 products (< 2^60 each)
+// before one reduction.
+constexpr int TAP_OT = 8;
+struct TapMap {
+  int d2, m_cts, o_c, nrot;
+  signed char idx[64];
+};
+template <int LOGN>
+__global__ void __launch_bounds__(256)
+k_tap_hma(const u64* __restrict__ x, const u64* __restrict__ rot, const u64* __restrict__ filt, u64* __restrict__ out,
+          int level, int pt_limbs, TapMap tm, Mods mods) {
+  constexpr int N = 1 << LOGN;
+  const int i = blockIdx.x * 256 + (int)threadIdx.x;
+  const int t = blockIdx.y;
+  const int n_ot = (tm.o_c + TAP_OT - 1) / TAP_OT;
+  const size_t b = blockIdx.z / n_ot;
+  const int o0 = (int)(blockIdx.z % n_ot) * TAP_OT;
+  const int no = min(TAP_OT, tm.o_c - o0);
+  const ModConst m = mods.m[t];
+  const size_t cstride = (size_t)2 * level * N;
+  const size_t fo = (size_t)tm.m_cts * tm.d2 * pt_limbs * N;  // from one output's plaintexts to the next
+  const u64* fbase = filt + (size_t)o0 * fo + (size_t)t * N + i;
+  u64 s0[TAP_OT], s1[TAP_OT];
+#pragma unroll
+  for (int r = 0; r < TAP_OT; ++r) s0[r] = s1[r] = 0;
+  if (m.narrow) {
+    u64 l0[TAP_OT], l1[TAP_OT];
+#pragma unroll
+    for (int r = 0; r < TAP_OT; ++r) l0[r] = l1[r] = 0;
+    int n_lazy = 0;
+    for (int mc = 0; mc < tm.m_cts; ++mc) {
+      const size_t ct = b * tm.m_cts + mc;
+      for (int k = 0; k < tm.d2; ++k) {
+        const int id = tm.idx[k];
+        const u64* src = (id < 0 ? x + ct * cstride : rot + (ct * tm.nrot + id) * cstride) + (size_t)t * N + i;
+        const u64 a0 = (u32)src[0], a1 = (u32)src[(size_t)level * N];
+        const u64* f = fbase + ((size_t)mc * tm.d2 + k) * pt_limbs * N;
+#pragma unroll
+        for (int r = 0; r < TAP_OT; ++r)
+          if (r < no) {
+            const u64 fv = (u32)f[r * fo];
+            l0[r] += a0 * fv;
+            l1[r] += a1 * fv;
+          }
+        if (++n_lazy == 15) {
+#pragma unroll
+          for (int r = 0; r < TAP_OT; ++r) {
+            s0[r] = add_mod(s0[r], reduce64(l0[r], m), m.q);
+            s1[r] = add_mod(s1[r], reduce64(l1[r], m), m.q);
+            l0[r] = l1[r] = 0;
+          }
+          n_lazy = 0;
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < TAP_OT; ++r) {
+      s0[r] = add_mod(s0[r], reduce64(l0[r], m), m.q);
+      s1[r] = add_mod(s1[r], reduce64(l1[r], m), m.q);
+    }
+  } else {
+    for (int mc = 0; mc < tm.m_cts; ++mc) {
+      const size_t ct = b * tm.m_cts + mc;
+      for (int k = 0; k < tm.d2; ++k) {
+        const int id = tm.idx[k];
+        const u64* src = (id < 0 ? x + ct * cstride : rot + (ct * tm.nrot + id) * cstride) + (size_t)t * N + i;
+        const u64 a0 = src[0], a1 = src[(size_t)level * N];
+        const u64* f = fbase + ((size_t)mc * tm.d2 + k) * pt_limbs * N;
+#pragma unroll
+        for (int r = 0; r < TAP_OT; ++r)
+          if (r < no) {
+            const u64 fv = f[r * fo];
+            s0[r] = add_mod(s0[r], mul_mod(a0, fv, m), m.q);
+            s1[r] = add_mod(s1[r], mul_mod(a1, fv, m), m.q);
+          }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < TAP_OT; ++r)
+    if (r < no) {
+      u64* o = out + ((b * tm.o_c + o0 + r) * 2 * level + t) * N + i;
+      o[0] = s0[r];
+      o[(size_t)level * N] = s1[r];
+    }
 }
 
 // ---------------------------------------------------------------------------

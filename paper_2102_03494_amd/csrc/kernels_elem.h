@@ -47,6 +47,36 @@ __global__ void k_make_chain_jobs(KsJob* jobs, int count, u64* base, size_t stri
   jobs[(size_t)j * count + b] = jb;
 }
 
+// Jobs of hoisted rotations of n_in ciphertexts (ciphertext i at
+// in + i in_stride): jobs[i m + r] rotates ciphertext i by rotation r of hk
+// into out + (i m + r) 2 level n.  With digits_only, jobs[i] is ciphertext
+// i's decomposition job (no permutation; key hk.key[0] marks it as
+// switching).  grid (ceil(n_in / 256), m).
+__global__ void k_make_hoist_jobs(KsJob* jobs, int n_in, int m, const u64* in, size_t in_stride, u64* out, int level,
+                                  int n, HoistKeys hk, int digits_only) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (i >= n_in) return;
+  const u64* x = in + (size_t)i * in_stride;
+  KsJob jb;
+  jb.d = x + (size_t)level * n;
+  jb.c = x;
+  jb.level = level;
+  jb.flags = 0;
+  if (digits_only) {
+    jb.out = nullptr;
+    jb.key = hk.key[0];
+    jb.g = jb.ginv = 1u;
+    jobs[i] = jb;
+    return;
+  }
+  jb.out = out + ((size_t)i * m + r) * 2 * level * n;
+  jb.key = hk.key[r];
+  jb.g = hk.g[r];
+  jb.ginv = hk.ginv[r];
+  jobs[(size_t)i * m + r] = jb;
+}
+
 // Switching keys made by a client, [L][2][L+1][N] canonical 64-bit residues
 // per key, into the library's stored form (rows of narrow moduli packed as N
 // 32-bit words at the start of the row); residues not below their modulus

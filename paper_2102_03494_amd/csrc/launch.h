@@ -190,21 +190,26 @@ void LKeygen<LOGN>::run(he_ctx* c, u64* key, const u64* sk, const u64* a, const 
                                                                         c->mods, pack);
 }
 
-// Hoisted rotations: digits of c1 and the lifted digits, computed once ...
+// Hoisted rotations: digits of c1 and the lifted digits, computed once per
+// ciphertext (jobs1: one decomposition job per ciphertext) ...
 template <int LOGN>
-void LHoistUp<LOGN>::run(he_ctx* c, const KsJob* job1, const u64* c1, int level, u64* dcoef, u64* dhat, hipStream_t s) {
+void LHoistUp<LOGN>::run(he_ctx* c, const KsJob* jobs1, int count, int level, u64* dcoef, u64* dhat, hipStream_t s) {
   constexpr int T = NttGeom<LOGN>::T;
-  HE_FOR_CLASSES(c->q_mask, (k_ks_digits<LOGN, CLS><<<xcd_grid(level, 1), T, 0, s>>>(job1, 1, dcoef, level,
-                                                                                       c->mods, c->tb())));
+  HE_FOR_CLASSES(c->q_mask, (k_ks_digits<LOGN, CLS><<<xcd_grid(level, count), T, 0, s>>>(jobs1, count, dcoef, level,
+                                                                                           c->mods, c->tb())));
   Prof pr(c, "modup_store", s);
   HE_FOR_CLASSES(c->q_mask | (1u << c->p_cls),
-                 (k_modup_store<LOGN, CLS><<<dim3(level + 1, level), T, 0, s>>>(dcoef, c1, dhat, level, c->big_l,
-                                                                                c->mods, c->tb())));
+                 (k_modup_store<LOGN, CLS><<<dim3(level + 1, level, count), T, 0, s>>>(dcoef, jobs1, dhat, level,
+                                                                                       c->big_l, c->mods, c->tb())));
 }
 
 // ... then, per chunk of rotations: inner product with each key, ModDown.
+// Rotation r of the chunk uses the lifted digits of ciphertext
+// (job_base + r) / per_ct, dstride words apart; the fused form (u null)
+// serves one ciphertext.
 template <int LOGN>
-void LHoisted<LOGN>::run(he_ctx* c, const KsJob* jobs, int m, int level, const u64* dhat, u64* u, u64* rc, hipStream_t s) {
+void LHoisted<LOGN>::run(he_ctx* c, const KsJob* jobs, int m, int level, const u64* dhat, u64* u, u64* rc, hipStream_t s,
+                         int job_base, int per_ct, size_t dstride) {
   constexpr int T = NttGeom<LOGN>::T;
   constexpr int N = 1 << LOGN;
   if (u == nullptr) {
@@ -222,7 +227,8 @@ void LHoisted<LOGN>::run(he_ctx* c, const KsJob* jobs, int m, int level, const u
   }
   {
     Prof pr(c, "ip_perm", s);
-    k_ip_perm<LOGN><<<dim3(N / 256, level + 1, m), 256, 0, s>>>(dhat, jobs, u, level, c->big_l, c->mods);
+    k_ip_perm<LOGN><<<dim3(N / 256, level + 1, m), 256, 0, s>>>(dhat, jobs, u, level, c->big_l, c->mods, job_base,
+                                                                 per_ct, dstride);
   }
   {  // u rows per polynomial: level + 1, P at row level (one P group)
     Prof pr(c, "intt_last", s);
@@ -230,6 +236,15 @@ void LHoisted<LOGN>::run(he_ctx* c, const KsJob* jobs, int m, int level, const u
                                        jobs, m, u, level, 1, c->big_l, rc, c->mods, c->tb())));
   }
   LDrop<LOGN>::run(c, MODE_P, EPI_ROT, jobs, m, level, level + 1, u, rc, s);
+}
+
+template <int LOGN>
+void LTapHma<LOGN>::run(he_ctx* c, const u64* x, const u64* rot, const u64* filt, u64* out, int level, int pt_limbs,
+                        const TapMap& tm, int n_b, hipStream_t s) {
+  constexpr int N = 1 << LOGN;
+  Prof pr(c, "tap_hma", s);
+  const int n_ot = (tm.o_c + TAP_OT - 1) / TAP_OT;
+  k_tap_hma<LOGN><<<dim3(N / 256, level, n_b * n_ot), 256, 0, s>>>(x, rot, filt, out, level, pt_limbs, tm, c->mods);
 }
 
 }  // namespace he
@@ -245,4 +260,5 @@ void LHoisted<LOGN>::run(he_ctx* c, const KsJob* jobs, int m, int level, const u
   template struct LKeygen<LOGN>;          \
   template struct LHoistUp<LOGN>;         \
   template struct LHoisted<LOGN>;         \
+  template struct LTapHma<LOGN>;          \
   }

@@ -352,6 +352,19 @@ class HEContext:
                     "he_rotate_hoisted")
         return Ct(out, ct.scale)
 
+    def rotate_hoisted_batch(self, cts: torch.Tensor, steps, out: torch.Tensor | None = None) -> torch.Tensor:
+        """cts [count][2][level][N] -> [count][len(steps)][2][level][N]: each
+        ciphertext rotated by every step, one decomposition per ciphertext."""
+        level = cts.shape[-2]
+        count = cts.numel() // (2 * level * self.n)
+        m = len(steps)
+        arr = (ctypes.c_int32 * m)(*[int(k) for k in steps])
+        if out is None:
+            out = torch.empty((count, m, 2, level, self.n), dtype=torch.int64, device="cuda")
+        self._check(self.lib.he_rotate_hoisted_batch(self.h, _ptr(cts), count, level, arr, m, _ptr(out), _stream()),
+                    "he_rotate_hoisted_batch")
+        return out
+
     def rotsum(self, ct: Ct, r_steps: int):
         level = ct.level
         count = ct.data.numel() // (2 * level * self.n)
@@ -465,6 +478,47 @@ class HEContext:
         self._check(self.lib.he_conv_convpack(self.h, _ptr(x.data), k, level, wf.ctypes.data_as(_lib.DP), o_c,
                                               float(x.scale), float(target_scale), _ptr(out),
                                               ctypes.byref(out_scale), _stream()), "he_conv_convpack")
+        return Ct(out, out_scale.value)
+
+    # ---- tap-style DensePack (hoisted tap rotations) ---------------------------
+    def tap_workspace_need(self, n_batch: int, level: int, desc: HeConvDesc, o_c2: int = 0,
+                           square: bool = False) -> int:
+        need = self.lib.he_tap_workspace_need(self.h, n_batch, level, ctypes.byref(desc), o_c2, int(square))
+        if need == 0:
+            raise HEError("he_tap_workspace_need: bad geometry or level")
+        return need
+
+    def conv_tap(self, xs: torch.Tensor, scale: float, desc: HeConvDesc, filt: torch.Tensor, pt_scale: float,
+                 out: torch.Tensor | None = None) -> Ct:
+        """Tap-style DensePack conv of xs [B][M][2][level][N] with plaintexts
+        filt [O][M][d^2][limbs][N]; returns [B][O][2][level-1][N]."""
+        nb, level = xs.shape[0], xs.shape[-2]
+        if out is None:
+            out = torch.empty((nb, desc.o_c, 2, level - 1, self.n), dtype=torch.int64, device="cuda")
+        out_scale = ctypes.c_double(0.0)
+        self._check(self.lib.he_conv_tap(self.h, nb, _ptr(xs), level, ctypes.byref(desc), _ptr(filt), filt.shape[-2],
+                                         float(scale), float(pt_scale), _ptr(out), ctypes.byref(out_scale),
+                                         _stream()), "he_conv_tap")
+        return Ct(out, out_scale.value)
+
+    def ffconv_layer_tap(self, xs: torch.Tensor, scale: float, desc: HeConvDesc, w1_filt: torch.Tensor,
+                         w1_scale: float, mask: torch.Tensor, mask_scale: float, w2: np.ndarray, k_bits: int,
+                         square: bool = False, out: torch.Tensor | None = None) -> Ct:
+        """Tap-style FFConv of xs [B][M][2][level][N]: W1 plaintexts
+        [r][M][d^2][limbs][N] (desc.o_c = r), output mask E, W2 (r x o_c2);
+        returns [B][o_c2][2][level-2 (-1 with square)][N]."""
+        nb, level = xs.shape[0], xs.shape[-2]
+        w2f = np.ascontiguousarray(np.asarray(w2, dtype=np.float64))
+        o_c2 = w2f.shape[1]
+        lvl_out = level - 2 - (1 if square else 0)
+        if out is None:
+            out = torch.empty((nb, o_c2, 2, lvl_out, self.n), dtype=torch.int64, device="cuda")
+        out_scale = ctypes.c_double(0.0)
+        self._check(self.lib.ffconv_layer_tap(self.h, nb, _ptr(xs), level, ctypes.byref(desc), _ptr(w1_filt),
+                                              w1_filt.shape[-2], float(scale), float(w1_scale), _ptr(mask),
+                                              float(mask_scale), w2f.ctypes.data_as(_lib.DP), o_c2, int(k_bits),
+                                              int(square), _ptr(out), ctypes.byref(out_scale), _stream()),
+                    "ffconv_layer_tap")
         return Ct(out, out_scale.value)
 
     # ---- layer pieces for iteration-level batching ------------------------------

@@ -117,6 +117,64 @@ def filter_layout(weights: np.ndarray, g: Geometry, slots: int, o: int, cls: int
     return v
 
 
+# ---- tap-style DensePack (hoisted tap rotations; not one of the paper's designs) ----
+
+def tap_shifts(g: Geometry) -> list[int]:
+    """Left rotation of tap t = kh d + kw: (kh - pad) W + (kw - pad)."""
+    return [(kh - g.pad) * g.w + (kw - g.pad) for kh in range(g.d) for kw in range(g.d)]
+
+
+def tap_block_steps(blocks: int, hw: int) -> list[tuple[int, int]]:
+    """The library's block-sum schedule: (0, k H W) doubles a k-block sum,
+    (1, H W) adds one block, over the bits of `blocks` below the leading one."""
+    steps, k = [], 1
+    for bit in bin(blocks)[3:]:
+        steps.append((0, k * hw))
+        k *= 2
+        if bit == "1":
+            steps.append((1, hw))
+            k += 1
+    return steps
+
+
+def tap_rotation_steps(g: Geometry, slots: int) -> list[int]:
+    """Rotation keys a tap-style layer of this geometry needs."""
+    amounts = {s % slots for s in tap_shifts(g)} | {a for _, a in tap_block_steps(g.per_ct(slots), g.h * g.w)}
+    return sorted(amounts - {0})
+
+
+def tap_output_slots(g: Geometry) -> np.ndarray:
+    """Slot (s i) W + s j of output (i, j), row-major over outputs."""
+    i = np.arange(g.out_h)[:, None]
+    j = np.arange(g.out_w)[None, :]
+    return (g.stride * i * g.w + g.stride * j).reshape(-1)
+
+
+def tap_filter_layout(weights: np.ndarray, g: Geometry, slots: int, o: int, m: int, t: int) -> np.ndarray:
+    """Plaintext (o, m, t): W[kh][kw][m B + b][o] in block b at the slot of
+    every output whose tap (kh, kw) is inside the image; zero elsewhere."""
+    kh, kw = divmod(t, g.d)
+    per = g.per_ct(slots)
+    hw = g.h * g.w
+    ys = g.stride * np.arange(g.out_h) - g.pad + kh
+    xs = g.stride * np.arange(g.out_w) - g.pad + kw
+    valid = ((ys >= 0) & (ys < g.h))[:, None] & ((xs >= 0) & (xs < g.w))[None, :]
+    where = tap_output_slots(g)[valid.reshape(-1)]
+    v = np.zeros(slots)
+    for b in range(per):
+        c = m * per + b
+        if c >= g.c_in:
+            break
+        v[b * hw + where] = weights[kh, kw, c, o]
+    return v
+
+
+def tap_output_mask_layout(g: Geometry, slots: int) -> np.ndarray:
+    v = np.zeros(slots)
+    v[tap_output_slots(g)] = 1.0
+    return v
+
+
 class PlainEncoder:
     """Keyless encoder for the server's plaintext weights: slot values to an
     NTT-domain plaintext [level][N] on the device (the client's encoding:
@@ -144,6 +202,32 @@ def encode_filters(client, weights: np.ndarray, g: Geometry, level: int, pt_scal
         for b in range(n_cls):
             for m in range(m_cts):
                 out[o, b, m] = client.encode(filter_layout(weights, g, ctx.n // 2, o, b, m), level, pt_scale)
+    return out
+
+
+def encode_tap_filters(client, weights: np.ndarray, g: Geometry, level: int, pt_scale: float,
+                       threads: int = 16) -> torch.Tensor:
+    """Tap plaintexts [O][M][d^2][level][N] on the device.  The host encodes
+    run in a thread pool (the library's encoder releases the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    ctx = client.ctx
+    slots = ctx.n // 2
+    o_c = weights.shape[3]
+    m_cts = g.n_cts(slots)
+    d2 = g.d * g.d
+    out = torch.empty((o_c, m_cts, d2, level, ctx.n), dtype=torch.int64, device="cuda")
+    idx = [(o, m, t) for o in range(o_c) for m in range(m_cts) for t in range(d2)]
+
+    def coeffs(key):
+        o, m, t = key
+        return ctx.encode_coeffs(tap_filter_layout(weights, g, slots, o, m, t), pt_scale)
+
+    with ThreadPoolExecutor(max_workers=threads) as pool:
+        for (o, m, t), co in zip(idx, pool.map(coeffs, idx)):
+            pt = ctx.from_signed(torch.from_numpy(co).cuda(), level, 0)
+            ctx.ntt(pt.view(1, level, ctx.n))
+            out[o, m, t] = pt
     return out
 
 

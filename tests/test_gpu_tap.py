@@ -1,0 +1,165 @@
+"""Tap-style DensePack (hoisted tap rotations, masked weight plaintexts,
+binary block sum) and the batched hoisted rotation on the GPU, against the
+oracle bit for bit.
+
+The product's layouts (tap plaintexts, output mask, rotation steps) are
+compared with the oracle's first; then each layer's output ciphertexts, for
+several inputs in one call, must equal the oracle's for each input, with the
+same scale and counts, and decrypt to the FP64 convolution within 1e-3.
+Geometries cover stride 1 and 2, padding 0 and 1, a non-square image, one
+and two input ciphertexts, block counts with and without "inc" steps, and
+more outputs than one workgroup's tile (8).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import synth  # noqa: E402
+from oracle import conv as C  # noqa: E402
+from oracle import encoding as E  # noqa: E402
+from oracle import reference as R  # noqa: E402
+from oracle import scheme as S  # noqa: E402
+from oracle import workloads as Wk  # noqa: E402
+from test_gpu_parity import SMALL40, W, _dev, _enc_batch, _he, _host, _small_setup  # noqa: E402
+
+
+def _layers():
+    from paper_2102_03494_amd import layers as Ly
+    return Ly
+
+
+@pytest.mark.parametrize("chain", [None, SMALL40], ids=["30bit", "40bit"])
+def test_rotate_hoisted_batch_bit_exact(chain):
+    steps = [1, -5, 31, 200]
+    p, octx, gctx, cl = _small_setup(rotations=steps, chain=chain)
+    cts = _enc_batch(octx, p, 3, level=3)
+    got = _host(gctx.rotate_hoisted_batch(_dev(cts), steps))
+    assert got.shape == (3, 4, 2, 3, p.n)
+    for i in range(3):
+        for r, k in enumerate(steps):
+            assert np.array_equal(got[i, r], S.rotate(p, octx, S.Ciphertext(cts[i], p.scale), k).c), (i, k)
+
+
+TAP_CASES = [((6, 6, 3), 3, 1, 1, 3), ((9, 9, 1), 5, 2, 0, 3), ((5, 5, 24), 3, 1, 1, 10), ((8, 8, 1), 5, 2, 1, 2),
+             ((7, 5, 2), 3, 2, 1, 9)]
+
+
+def _tap_inputs(p, octx, geom, shape, level, nb, seed0):
+    xs, cts = [], []
+    for b in range(nb):
+        x = synth.image(W, shape, index=seed0 + b)
+        xs.append(x)
+        cts.append(np.stack([Wk.encrypt_slots(octx, v, level, p.scale, W, 700 + 10 * b + m).c
+                             for m, v in enumerate(C.densepack_slots(x, geom, p.slots))]))
+    return xs, np.stack(cts)
+
+
+def _same_layouts(p, geom, g):
+    Ly = _layers()
+    assert Ly.tap_rotation_steps(g, p.slots) == C.tap_rotation_steps(geom, p.slots)
+    assert np.array_equal(Ly.tap_output_slots(g), C.tap_output_slots(geom))
+
+
+@pytest.mark.parametrize("shape,d,stride,pad,o_c", TAP_CASES)
+def test_tap_conv_bit_exact(shape, d, stride, pad, o_c):
+    Ly = _layers()
+    geom = C.ConvGeom(shape[0], shape[1], shape[2], d, stride, pad)
+    g = Ly.Geometry(shape[0], shape[1], shape[2], d, stride, pad)
+    n = 1024
+    rots = C.tap_rotation_steps(geom, n // 2)
+    p, octx, gctx, cl = _small_setup(rotations=rots)
+    _same_layouts(p, geom, g)
+    level, nb = 3, 2
+    w = synth.weights(W, 83, (d, d, shape[2], o_c), 0.2)
+    pt_scale = p.q[level - 1] * p.scale / p.scale
+    want_f = C.tap_filters(p, w, geom, level, pt_scale)
+    filt = Ly.encode_tap_filters(Ly.PlainEncoder(gctx), w, g, level, pt_scale)
+    assert np.array_equal(_host(filt), want_f)
+    xs, cts = _tap_inputs(p, octx, geom, shape, level, nb, 40)
+    desc = gctx.conv_desc(*shape, d, stride, pad, o_c, 0)
+    gctx.reserve(gctx.tap_workspace_need(nb, level, desc))
+    got = gctx.conv_tap(_dev(cts), p.scale, desc, filt, pt_scale)
+    out = _host(got.data)
+    gc = gctx.last_counts()
+    ref_all = []
+    for b in range(nb):
+        want, cnt = C.tap_conv(p, octx, S.Ciphertext(cts[b], p.scale), geom, want_f, pt_scale)
+        assert np.array_equal(out[b], want.c), b
+        assert got.scale == want.scale
+        ref_all.append(cnt)
+    assert (gc["rot"], gc["mulpc"], gc["addcc"], gc["rescale"]) == (
+        nb * ref_all[0].rot, nb * ref_all[0].mulpc, nb * ref_all[0].addcc, nb * ref_all[0].rescale)
+    where = C.tap_output_slots(geom)
+    for b in range(nb):
+        ref = R.conv2d(xs[b], w, stride, pad)
+        for o in range(o_c):
+            v = cl.decrypt(got.data[b, o], got.scale)
+            assert np.abs(v[where] - ref[:, :, o].reshape(-1)).max() < 1e-3, (b, o)
+
+
+@pytest.mark.parametrize("chain,square,o_c2", [(None, True, 4), (None, False, 9), (SMALL40, True, 4)],
+                         ids=["30bit-sq", "30bit", "40bit-sq"])
+def test_ffconv_tap_bit_exact(chain, square, o_c2):
+    Ly = _layers()
+    shape, d, stride, pad, r = (6, 6, 3), 3, 1, 1, 2
+    geom = C.ConvGeom(*shape, d, stride, pad)
+    g = Ly.Geometry(*shape, d, stride, pad)
+    n = chain["n"] if chain else 1024
+    p, octx, gctx, cl = _small_setup(rotations=C.tap_rotation_steps(geom, n // 2), relin=square, chain=chain)
+    level, nb = 4, 3
+    w1 = synth.weights(W, 73, (d, d, shape[2], r), 0.3)
+    w2 = synth.weights(W, 74, (r, o_c2), 0.5)
+    w1_scale = p.q[level - 1] * p.scale / p.scale
+    t2 = C.pre_square_target(p, level - 2, p.scale) if square else p.scale
+    mask_scale = C.gather_mask_scale(p, level - 1, p.scale, t2, 12)
+    want_f = C.tap_filters(p, w1, geom, level, w1_scale)
+    want_m = E.encode(C.tap_output_mask_slots(geom, p.slots), p, level - 1, mask_scale)
+    filt = Ly.encode_tap_filters(Ly.PlainEncoder(gctx), w1, g, level, w1_scale)
+    mask = Ly.PlainEncoder(gctx).encode(Ly.tap_output_mask_layout(g, p.slots), level - 1, mask_scale)
+    assert np.array_equal(_host(filt), want_f) and np.array_equal(_host(mask), want_m)
+    xs, cts = _tap_inputs(p, octx, geom, shape, level, nb, 50)
+    desc = gctx.conv_desc(*shape, d, stride, pad, r, 0)
+    gctx.reserve(gctx.tap_workspace_need(nb, level, desc, o_c2, square))
+    got = gctx.ffconv_layer_tap(_dev(cts), p.scale, desc, filt, w1_scale, mask, mask_scale, w2, 12, square=square)
+    out = _host(got.data)
+    where = C.tap_output_slots(geom)
+    rest = np.ones(p.slots, bool)
+    rest[where] = False
+    for b in range(nb):
+        want, _ = C.tap_ffconv(p, octx, S.Ciphertext(cts[b], p.scale), geom, want_f, w1_scale, w2, 12, want_m,
+                               mask_scale, square=square)
+        assert np.array_equal(out[b], want.c), b
+        assert abs(got.scale / want.scale - 1) < 1e-15
+        ref = R.ffconv_reference(xs[b], w1, w2, stride, pad, square=square)
+        for o in range(o_c2):
+            v = cl.decrypt(got.data[b, o], got.scale)
+            assert np.abs(v[where] - ref[:, :, o].reshape(-1)).max() < 1e-3, (b, o)
+            assert np.abs(v[rest]).max() < 1e-3
+
+
+def test_tap_errors_before_launch():
+    """Missing keys, a bad geometry, short plaintexts and bad scales are
+    reported before anything runs; the output stays untouched."""
+    he = _he()
+    Ly = _layers()
+    shape = (6, 6, 3)
+    geom = C.ConvGeom(*shape, 3, 1, 1)
+    steps = C.tap_rotation_steps(geom, 512)
+    p, octx, gctx, cl = _small_setup(rotations=steps[:-1])  # the last step's key is missing
+    g = Ly.Geometry(*shape, 3, 1, 1)
+    filt = Ly.encode_tap_filters(Ly.PlainEncoder(gctx), np.ones((3, 3, 3, 2)), g, 3, 2.0**20)
+    x = _dev(_tap_inputs(p, octx, geom, shape, 3, 1, 60)[1])
+    out = torch.full((1, 2, 2, 2, p.n), 7, dtype=torch.int64, device="cuda")
+    desc = gctx.conv_desc(*shape, 3, 1, 1, 2, 0)
+    with pytest.raises(he.HEError, match="no rotation key"):
+        gctx.conv_tap(x, p.scale, desc, filt, 2.0**20, out=out)
+    with pytest.raises(he.HEError, match="unsupported geometry"):
+        gctx.conv_tap(x, p.scale, gctx.conv_desc(*shape, 3, 1, 2, 2, 0), filt, 2.0**20, out=out)
+    with pytest.raises(he.HEError, match="limbs"):
+        gctx.conv_tap(x, p.scale, desc, filt[:, :, :, :2].contiguous(), 2.0**20, out=out)
+    with pytest.raises(he.HEError, match="scales"):
+        gctx.conv_tap(x, float("nan"), desc, filt, 2.0**20, out=out)
+    torch.cuda.synchronize()
+    assert bool((out == 7).all())
