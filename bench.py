@@ -624,6 +624,130 @@ def cifar_section(torch, steps: int, plain: bool, digests_path: str):
     return res
 
 
+TAP_KERNELS = ("ip_perm", "modup_store", "ks_digits", "intt_last", "drop_last", "tap_hma", "ks_modup_stage",
+               "hma_perm", "scalar_mac", "tensor_sq")
+
+
+def tap_case(torch, name, ring, shape, d, stride, pad, level, r, o_c, square, batch, reps, plain=True):
+    """One tap-style layer shape: FFConv (W1 d x d -> r under tap-style
+    DensePack, masked gather, 1x1 r -> o_c ConvPack, optional x^2) and the
+    plain conv (W1 W2 under tap-style DensePack, optional x^2), on `batch`
+    seeded inputs in one call.  Latency, executed counts, rotations/s,
+    per-kernel busy time, decrypted error against FP64."""
+    import numpy as np
+
+    import synth
+    from paper_2102_03494_amd import layers as Ly
+    from paper_2102_03494_amd.client import Client
+    from paper_2102_03494_amd.he import Ct, HEContext
+
+    n, q_bits, p_bits, scale = ring
+    wl = f"tap_{name}"
+    ctx = HEContext(n, q_bits, p_bits)
+    cl = Client(ctx, wl)
+    g = Ly.Geometry(*shape, d, stride, pad)
+    slots = n // 2
+    cl.gen_rotation_keys(Ly.tap_rotation_steps(g, slots))
+    if square:
+        cl.gen_relin_key()
+    xs = [synth.image(wl, shape, index=b) for b in range(batch)]
+    cts = torch.stack([torch.stack([cl.encrypt(v, level, scale, index=100 * b + m).data[0]
+                                    for m, v in enumerate(Ly.densepack_layout(x, g, slots))]) for b, x in enumerate(xs)])
+    w1 = synth.weights(wl, 1, (d, d, shape[2], r), 0.05)
+    w2 = synth.weights(wl, 2, (r, o_c), 0.05)
+    enc = Ly.PlainEncoder(ctx)
+    w1_scale = Ly.pt_scale_for(ctx, level, scale, scale)
+    t0 = time.perf_counter()
+    f1 = Ly.encode_tap_filters(enc, w1, g, level, w1_scale)
+    t_enc = time.perf_counter() - t0
+    t2 = Ly.pre_square_target(ctx, level - 2, scale) if square else scale
+    ms = Ly.mask_scale_for(ctx, level - 1, scale, t2, K_BITS)
+    mask = enc.encode(Ly.tap_output_mask_layout(g, slots), level - 1, ms)
+    desc = ctx.conv_desc(*shape, d, stride, pad, r, 0)
+    ctx.reserve(ctx.tap_workspace_need(batch, level, desc, o_c, square))
+    where = Ly.tap_output_slots(g)
+
+    def ff():
+        return ctx.ffconv_layer_tap(cts, scale, desc, f1, w1_scale, mask, ms, w2, K_BITS, square=square)
+
+    t_ff, z = timed(ff, reps, 1, torch)
+    counts_ff = ctx.last_counts()
+    busy = {}
+    for k in TAP_KERNELS:
+        ctx.prof_select(k)
+        ff()
+        b_ms, _, launches = ctx.prof_read_busy()
+        if launches:
+            busy[k] = round(b_ms, 4)
+    ctx.prof_select(None)
+    err = 0.0
+    for b in range(batch if batch <= 2 else 2):
+        ref = Ly.reference_conv2d(xs[b], w1, stride, pad) @ w2
+        ref = ref * ref if square else ref
+        for o in range(o_c):
+            v = cl.decrypt(z.data[b, o], z.scale)
+            err = max(err, float(np.abs(v[where] - ref[:, :, o].ravel()).max()))
+    out = {"batch": batch, "ffconv_ms": t_ff * 1e3, "ffconv_ms_per_input": t_ff * 1e3 / batch,
+           "ffconv_counts_per_input": {k: v // batch for k, v in counts_ff.items()},
+           "ffconv_rotations_per_s": counts_ff["rot"] / t_ff, "ffconv_decrypted_max_abs_err": err,
+           "ffconv_kernel_ms": busy, "w1_plaintexts": int(f1.shape[0] * f1.shape[1] * f1.shape[2]),
+           "w1_encode_s": t_enc}
+    del f1
+    if plain:
+        wp = Ly.compose_factors(w1, w2)
+        tp = Ly.pre_square_target(ctx, level - 1, scale) if square else scale
+        ps = Ly.pt_scale_for(ctx, level, scale, tp)
+        t0 = time.perf_counter()
+        fp = Ly.encode_tap_filters(enc, wp, g, level, ps)
+        t_enc = time.perf_counter() - t0
+        desc_p = ctx.conv_desc(*shape, d, stride, pad, o_c, 0)
+        ctx.reserve(ctx.tap_workspace_need(batch, level, desc_p) + (batch * o_c * 4 * level * n * 8 if square else 0))
+
+        def pl():
+            y = ctx.conv_tap(cts, scale, desc_p, fp, ps)
+            if not square:
+                return y
+            sq = ctx.square(Ct(y.data.view(-1, 2, level - 1, n), y.scale))
+            return ctx.rescale(sq)
+
+        t_pl, zp = timed(pl, reps, 1, torch)
+        err_p = 0.0
+        zd = zp.data.view(batch, o_c, 2, -1, n)
+        for b in range(batch if batch <= 2 else 2):
+            ref = Ly.reference_conv2d(xs[b], wp, stride, pad)
+            ref = ref * ref if square else ref
+            for o in range(o_c):
+                v = cl.decrypt(zd[b, o], zp.scale)
+                err_p = max(err_p, float(np.abs(v[where] - ref[:, :, o].ravel()).max()))
+        out.update(plain_ms=t_pl * 1e3, plain_ms_per_input=t_pl * 1e3 / batch, plain_decrypted_max_abs_err=err_p,
+                   plain_plaintexts=int(fp.shape[0] * fp.shape[1] * fp.shape[2]), plain_encode_s=t_enc)
+        del fp
+    print(f"# tap {name} b{batch}: ffconv {t_ff * 1e3:.2f} ms" +
+          (f", plain {out['plain_ms']:.2f} ms" if plain else ""), file=sys.stderr, flush=True)
+    ctx.close()
+    return out
+
+
+def tap_section(torch, reps: int) -> dict:
+    """Tap-style DensePack (hoisted tap rotations; a variant that is not one
+    of the paper's designs) on the MNIST-shaped layer of the timed workload
+    and on the two conv stages of the CIFAR-shaped serving net."""
+    ring8 = (N, Q_BITS, P_BITS, SCALE)
+    ring16 = (16384, (40,) * 6, 60, 2.0**30)
+    out = {"note": "tap-style DensePack: per input ciphertext one hoisted rotation per nonzero tap shift, masked "
+                   "weight plaintexts per (output, ciphertext, tap), a block sum of ceil-log rotations per output; "
+                   "outputs at slot (s i) W + s j"}
+    out["mnist_28x28x1_d5s2_b1"] = tap_case(torch, "mnist", ring8, (28, 28, 1), 5, 2, 0, len(Q_BITS), 2, 5, True, 1,
+                                            reps)
+    out["mnist_28x28x1_d5s2_b32"] = tap_case(torch, "mnist", ring8, (28, 28, 1), 5, 2, 0, len(Q_BITS), 2, 5, True,
+                                             32, reps)
+    out["cifar_stage1_32x32x3_r8_o64"] = tap_case(torch, "cifar1", ring16, (32, 32, 3), 3, 1, 1, 6, 8, 64, False, 1,
+                                                  reps)
+    out["cifar_stage2_32x32x64_r8_o64_level3"] = tap_case(torch, "cifar2", ring16, (32, 32, 64), 3, 1, 1, 3, 8, 64,
+                                                          False, 1, reps)
+    return out
+
+
 def serving_section(window: float, cap: float, mix_cap: float):
     """Serving (Poisson arrivals at 200 requests/s, 70% MNIST-shaped):
     * the 70/30 mix of MNIST- and CIFAR-shaped requests served by FFConv nets
@@ -697,6 +821,7 @@ def main():
     ap.add_argument("--batched-layers", type=int, default=128,
                     help="independent layers in the batched/graph section (0 = skip)")
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged 64-ciphertext batch section")
+    ap.add_argument("--no-tap", action="store_true", help="skip the tap-style DensePack section")
     ap.add_argument("--no-cifar", action="store_true", help="skip the N=16384 CIFAR-shaped layer section")
     ap.add_argument("--no-rank-sweep", action="store_true", help="skip the low-rank factorisation sweep (N=8192)")
     ap.add_argument("--no-cifar-plain", action="store_true",
@@ -865,6 +990,12 @@ def main():
         print("# ragged batch at N=16384", file=sys.stderr, flush=True)
         ragged = ragged_section(torch, max(1, min(args.steps, 3)))
 
+    tap = None
+    if not args.no_tap:
+        torch.cuda.empty_cache()
+        print("# tap-style DensePack section", file=sys.stderr, flush=True)
+        tap = tap_section(torch, max(1, min(args.steps, 5)))
+
     serving = None
     if args.serve_window > 0:
         torch.cuda.empty_cache()
@@ -911,6 +1042,7 @@ def main():
         "serving": serving,
         "hoisted_rotations": hoisted,
         "cifar_layer": cifar,
+        "tap_style_densepack": tap,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -48,6 +48,9 @@ WORKLOADS = {
     "cifar_n16384": 3,     # 32x32x3 layer, N=16384
     "batched_n16384": 4,   # mixed-level batch, hoisted rotations, many layers
     "serving": 5,          # request loop
+    "tap_mnist": 6,        # tap-style DensePack, 28x28x1 5x5 s2 layer, N=8192
+    "tap_cifar1": 7,       # tap-style DensePack, 32x32x3 3x3 layer, N=16384
+    "tap_cifar2": 8,       # tap-style DensePack, 32x32x64 3x3 layer, N=16384
     "unit": 99,            # small unit-test rings
 }
 
