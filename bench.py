@@ -754,6 +754,8 @@ def serving_section(window: float, cap: float, mix_cap: float):
       with continuous (iteration-level) batching: per class p50/p99 latency,
       completed requests per second and backlog (the CIFAR-shaped load is far
       beyond one GPU, so the run is capped and the backlog reported);
+    * the same mix served by tap-style FFConv nets (hoisted tap rotations)
+      in whole-request batches;
     * the MNIST-shaped share alone, served by FFConv nets and by the plain
       comparator nets in whole-request batches (sequential plain-conv
       evaluation), for reference."""
@@ -770,6 +772,18 @@ def serving_section(window: float, cap: float, mix_cap: float):
                     "+ x^2, combine, FC 845->10 at N=8192) and 30% CIFAR-shaped (FFConv 3x3 3->8->64 + x^2, "
                     "combine, FFConv 64->8->64 at N=16384); continuous batching, drain capped at "
                     f"{mix_cap:g} s"}
+    # the same mix with tap-style FFConv nets (whole-request batches, shortest class first)
+    args = serve.parse_args(["--window", str(window), "--cap", str(mix_cap), "--classes", "mnist,cifar",
+                             "--variant", "tap", "--mode", "queue", "--max-batch-cifar", "8"])
+    rep = serve.run(args)
+    out["tap_mix"] = {
+        "classes": rep["classes"], "makespan_s": rep["makespan_s"], "completed_per_s": rep["completed_per_s"],
+        "peak_backlog": rep["peak_backlog"], "backlog_at_end": rep["backlog_at_end"],
+        "decrypted_max_abs_err": rep["decrypted_max_abs_err"], "max_batch": rep["max_batch"],
+        "ms_per_request": {c: 1e3 * v for c, v in rep["cost_per_request_s"].items()},
+        "workload": "the same arrivals; every FFConv stage tap-style (hoisted tap rotations, masked W1 "
+                    "plaintexts), whole-request batches of up to 32 (MNIST-shaped) / 8 (CIFAR-shaped), "
+                    "shortest class first"}
     for variant in ("ffconv", "plain"):
         args = serve.parse_args(["--window", str(window), "--cap", str(cap), "--classes", "mnist",
                                  "--variant", variant, "--mode", "queue"])

@@ -35,8 +35,9 @@ import torch
 import synth
 
 from .he import Ct, HEContext
-from .layers import (Geometry, PlainEncoder, compose_factors, densepack_layout, encode_filters, onehot_mask,
-                     pre_square_target, pt_scale_for, reference_conv2d, rot_steps)
+from .layers import (Geometry, PlainEncoder, compose_factors, densepack_layout, encode_filters, encode_tap_filters,
+                     onehot_mask, pre_square_target, pt_scale_for, reference_conv2d, rot_steps, tap_output_mask_layout,
+                     tap_rotation_steps)
 
 K_BITS = 12
 
@@ -281,3 +282,127 @@ class EncryptedNet:
         vals = [client.decrypt(out.data[b, m], out.scale, per * s, limbs=1) for m in range(out.data.shape[1])]
         flat = np.concatenate(vals)[: last.o_c * s]
         return flat.reshape(last.o_c, s).T
+
+
+class TapNet:
+    """The same nets with every FFConv stage as a tap-style FFConv
+    (ffconv_layer_tap: hoisted tap rotations and masked W1 plaintexts
+    instead of one rotate-and-sum chain per DensePack output; not one of the
+    paper's designs).  A stage's output channel o holds output (i, j) at slot
+    (s i) W + s j of its input plane (W: input width), zero elsewhere; the
+    CP->DP combine packs B = floor(N / (2 H W)) channels per ciphertext with
+    blocks of H W slots, so for stride 1 the next stage reads the usual
+    DensePack layout.  The MNIST-shaped net's FC layer is a DensePack layer
+    over that plane whose weights sit at the strided output positions (zero
+    elsewhere): the same 845 -> 10 map.  Same interface as EncryptedNet
+    (forward, decode, keys, sizes)."""
+
+    plain = False
+
+    def __init__(self, ctx: HEContext, spec: NetSpec, weights: dict, encoder=None):
+        self.ctx, self.spec = ctx, spec
+        enc = encoder if encoder is not None else PlainEncoder(ctx)
+        slots = ctx.n // 2
+        self.r_steps = int(math.log2(slots))
+        scale = spec.scale
+        level = spec.level
+        cur_scale = scale
+        self.stages = []
+        steps = set()
+        for k, st in enumerate(spec.stages):
+            g = st.geom
+            steps |= set(tap_rotation_steps(g, slots))
+            desc = ctx.conv_desc(g.h, g.w, g.c_in, g.d, g.stride, g.pad, st.r, 0)
+            w1s = pt_scale_for(ctx, level, cur_scale, scale)
+            y_scale = cur_scale * w1s / ctx.q[level - 1]
+            tgt = pre_square_target(ctx, level - 2, scale) if st.square else scale
+            ms = ctx.q[level - 2] * tgt / (y_scale * 2.0**K_BITS)
+            rec = dict(spec=st, level=level, in_scale=cur_scale, desc=desc, w1s=w1s, ms=ms,
+                       filt=encode_tap_filters(enc, weights[f"w1_{k}"], g, level, w1s),
+                       mask=enc.encode(tap_output_mask_layout(g, slots), level - 1, ms), w2=weights[f"w2_{k}"])
+            out_level = level - 2 - (1 if st.square else 0)
+            z_scale = y_scale * ms * 2.0**K_BITS / ctx.q[level - 2]
+            if st.square:
+                z_scale = z_scale * z_scale / ctx.q[level - 3]
+            rec.update(out_level=out_level, out_scale=z_scale)
+            if k + 1 < len(spec.stages) or spec.fc is not None:
+                block = g.h * g.w
+                per = min(st.o_c, slots // block)
+                rec.update(block=block, per_dense=per)
+                steps |= {(-(o % per) * block) % slots for o in range(st.o_c) if o % per}
+            self.stages.append(rec)
+            level, cur_scale = out_level, z_scale
+        self.fc = None
+        if spec.fc is not None:
+            o, _, _ = spec.fc
+            last = spec.stages[-1]
+            gl = last.geom
+            if gl.h != gl.w:
+                raise ValueError("the FC layer over a stage's plane needs a square plane")
+            wd = np.zeros((gl.h, gl.w, last.o_c, o))
+            s_ = gl.stride
+            wd[0:s_ * gl.out_h:s_, 0:s_ * gl.out_w:s_] = weights["fc"]
+            gf = Geometry(gl.h, gl.w, last.o_c, gl.h, 1, 0)
+            desc = ctx.conv_desc(gf.h, gf.w, gf.c_in, gf.d, 1, 0, o, self.r_steps)
+            pts = pt_scale_for(ctx, level, cur_scale, scale)
+            self.fc = dict(desc=desc, pts=pts, level=level, filt=encode_filters(enc, wd, gf, level, pts),
+                           out_scale=cur_scale * pts / ctx.q[level - 1])
+            steps |= set(rot_steps(ctx))
+        self.steps = sorted(steps - {0})
+
+    def rotation_steps(self) -> list[int]:
+        return list(self.steps)
+
+    def needs_relin(self) -> bool:
+        return any(st.square for st in self.spec.stages)
+
+    def input_layout(self, x: np.ndarray) -> list[np.ndarray]:
+        return densepack_layout(x, self.spec.stages[0].geom, self.ctx.n // 2)
+
+    def workspace_need(self, batch: int) -> int:
+        ctx = self.ctx
+        need = 0
+        for rec in self.stages:
+            st = rec["spec"]
+            need = max(need, ctx.tap_workspace_need(batch, rec["level"], rec["desc"], st.o_c, st.square))
+            need = max(need, ctx.workspace_need(batch * st.o_c, rec["out_level"]))
+        if self.fc is not None:
+            need = max(need, ctx.workspace_need(batch * self.fc["desc"].o_c, self.fc["level"]))
+        return need
+
+    def activation_bytes(self, batch: int) -> int:
+        n = self.ctx.n
+        most = max(batch * rec["spec"].o_c * 2 * (rec["level"] - 1) * n * 8 for rec in self.stages)
+        return 2 * most
+
+    def forward(self, xs: torch.Tensor) -> Ct:
+        """xs: [B][M][2][level][N] (or [B][2][level][N]) requests; returns
+        [B][10][2][1][N] replicated FC outputs (MNIST-shaped) or the last
+        stage's [B][o_c][2][level][N] channels (CIFAR-shaped)."""
+        ctx = self.ctx
+        batch = xs.shape[0]
+        data = xs.contiguous() if xs.dim() == 5 else xs.contiguous().unsqueeze(1)
+        cur = Ct(data, self.spec.scale)
+        for rec in self.stages:
+            st = rec["spec"]
+            z = ctx.ffconv_layer_tap(cur.data, cur.scale, rec["desc"], rec["filt"], rec["w1s"], rec["mask"],
+                                     rec["ms"], rec["w2"], K_BITS, square=st.square)
+            cur = ctx.combine_cp_dp_batch(z, rec["block"], rec["per_dense"]) if "per_dense" in rec else z
+        if self.fc is not None:
+            fc = self.fc
+            out = ctx.conv_densepack_batch(cur.data.contiguous(), cur.scale, fc["desc"], fc["filt"], fc["pts"])
+            return Ct(out.data.view(batch, fc["desc"].o_c, 2, 1, ctx.n), out.scale)
+        return cur
+
+    def decode(self, client, out: Ct, b: int) -> np.ndarray:
+        """Decrypted prediction of request b (FC values, or the last stage's
+        channels as [S][o_c])."""
+        if self.fc is not None:
+            return np.array([client.decrypt(out.data[b, o], out.scale, 1, limbs=1)[0]
+                             for o in range(out.data.shape[1])])
+        last = self.spec.stages[-1]
+        g = last.geom
+        i = np.arange(g.out_h)[:, None]
+        j = np.arange(g.out_w)[None, :]
+        where = (g.stride * i * g.w + g.stride * j).reshape(-1)
+        return np.stack([client.decrypt(out.data[b, o], out.scale, limbs=1)[where] for o in range(last.o_c)], 1)

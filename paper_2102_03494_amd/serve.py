@@ -360,7 +360,10 @@ def build_class(name: str, variant: str, budget_gb: float, max_batch: int, small
     spec = nets.mnist_spec() if name == "mnist" else nets.cifar_spec()
     ctx = HEContext(spec.n, spec.q_bits, spec.p_bits)
     weights = nets.net_weights(spec)
-    net = nets.EncryptedNet(ctx, spec, weights, plain=(variant == "plain"))
+    if variant == "tap":
+        net = nets.TapNet(ctx, spec, weights)
+    else:
+        net = nets.EncryptedNet(ctx, spec, weights, plain=(variant == "plain"))
     client = Client(ctx, spec.workload)
     client.gen_rotation_keys(net.rotation_steps())
     if net.needs_relin():
@@ -404,7 +407,9 @@ def parse_args(argv=None):
     ap.add_argument("--rate", type=float, default=200.0, help="mean arrivals per second")
     ap.add_argument("--p-mnist", type=float, default=0.7, help="probability that a request is MNIST-shaped")
     ap.add_argument("--cap", type=float, default=120.0, help="stop draining after this many seconds")
-    ap.add_argument("--variant", choices=("ffconv", "plain"), default="ffconv")
+    ap.add_argument("--variant", choices=("ffconv", "plain", "tap"), default="ffconv",
+                    help="ffconv: FFConv nets (DensePack W1); plain: composed-weight DensePack convs; tap: FFConv "
+                         "nets with tap-style W1 (hoisted tap rotations), served in whole-request batches")
     ap.add_argument("--policy", choices=("sjf", "fifo"), default="sjf")
     ap.add_argument("--budget-gb", type=float, default=120.0, help="HBM workspace budget per class")
     ap.add_argument("--max-batch-mnist", type=int, default=32)
@@ -412,7 +417,8 @@ def parse_args(argv=None):
     ap.add_argument("--classes", default="mnist,cifar")
     ap.add_argument("--concurrent", action="store_true", help="overlap the classes' batches on their streams")
     ap.add_argument("--mode", choices=("continuous", "queue"), default="continuous",
-                    help="continuous: iteration-level batching (FFConv nets); queue: batches of whole requests")
+                    help="continuous: iteration-level batching (the ffconv variant; the others always run as "
+                         "queue); queue: batches of whole requests")
     ap.add_argument("--out", default=None)
     return ap.parse_args(argv)
 

@@ -163,3 +163,41 @@ def test_tap_errors_before_launch():
         gctx.conv_tap(x, float("nan"), desc, filt, 2.0**20, out=out)
     torch.cuda.synchronize()
     assert bool((out == 7).all())
+
+
+@pytest.mark.parametrize("name", ["mnist", "cifar"])
+def test_tap_net_batch_bits_and_fp64(name):
+    """The serving nets with tap-style FFConv stages (small-ring analogs of
+    the MNIST- and CIFAR-shaped nets): each request's output bits are the
+    same in a batch of three as alone, and decrypt to the FP64 forward pass
+    within 1e-3."""
+    from paper_2102_03494_amd import nets
+    from paper_2102_03494_amd.client import Client
+    from paper_2102_03494_amd.he import HEContext
+    if name == "mnist":
+        spec = nets.mnist_spec(n=1024, q_bits=(30,) * 5, p_bits=40, image=8, d=3, stride=2, pad=1, r=2, o_c=3,
+                               fc_out=4)
+    else:
+        spec = nets.cifar_spec(n=1024, q_bits=(30,) * 6, p_bits=40, image=8, c_in=3, r1=2, o1=16, r2=2, o2=16)
+    ctx = HEContext(spec.n, spec.q_bits, spec.p_bits)
+    weights = nets.net_weights(spec)
+    net = nets.TapNet(ctx, spec, weights)
+    cl = Client(ctx, spec.workload)
+    cl.gen_rotation_keys(net.rotation_steps())
+    cl.gen_relin_key()
+    ctx.reserve(net.workspace_need(3) + (64 << 20))
+    g = spec.stages[0].geom
+    xs = [synth.image("serving", (g.h, g.w, g.c_in), index=900 + b) for b in range(3)]
+    payload = torch.stack([torch.stack([cl.encrypt(v, spec.level, spec.scale, index=20_000 + 10 * b + m).data[0]
+                                        for m, v in enumerate(net.input_layout(x))]) for b, x in enumerate(xs)])
+    out = net.forward(payload)
+    torch.cuda.synchronize()
+    for b in range(3):
+        alone = net.forward(payload[b:b + 1])
+        torch.cuda.synchronize()
+        assert torch.equal(alone.data[0], out.data[b]), b
+        ref = nets.reference_forward(spec, weights, xs[b])
+        if spec.fc is None:
+            ref = ref.reshape(-1, ref.shape[-1])
+        got = net.decode(cl, out, b)
+        assert np.abs(got - ref.reshape(got.shape)).max() < 1e-3, b
