@@ -541,6 +541,79 @@ def tap_ffconv(params, keys, xs: scheme.Ciphertext, geom: ConvGeom, w1_filters: 
     return z, counts
 
 
+# ---- Homomorphic Im2Col for d > 1 (Table III, CP-HI2C-*) ------------------------
+# From a DensePack input to the K = d^2 I_c ConvPack input ciphertexts of
+# Eq. 1.  The paper gives only the counts; this is one concrete algorithm
+# with hoisted rotations, and its executed counts are reported beside
+# Table III's.  Layout of Im2Col ciphertext k = (kh d + kw) I_c + c: the
+# pixel under tap (kh, kw) of channel c for output (i, j) at slot
+# (s i) W + s j, zero elsewhere.
+
+def him2col_block_shifts(geom: ConvGeom, slots: int) -> list[int]:
+    """Left rotations b H W, 0 < b < B, that bring block b to block 0."""
+    per = geom.channels_per_ct(slots)
+    return [b * geom.h * geom.w for b in range(1, per)]
+
+
+def him2col_rotation_steps(geom: ConvGeom, slots: int) -> list[int]:
+    amounts = {s % slots for s in tap_shifts(geom)} | set(him2col_block_shifts(geom, slots))
+    return sorted(amounts - {0})
+
+
+def him2col_mask_slots(geom: ConvGeom, slots: int, t: int) -> np.ndarray:
+    """Mask of tap t: 1 at the slot of every output whose tap t lies inside
+    the image."""
+    kh, kw = divmod(t, geom.d)
+    v = np.zeros(slots)
+    for i in range(geom.out_h):
+        y = geom.stride * i - geom.pad + kh
+        if not 0 <= y < geom.h:
+            continue
+        for j in range(geom.out_w):
+            x = geom.stride * j - geom.pad + kw
+            if 0 <= x < geom.w:
+                v[geom.stride * i * geom.w + geom.stride * j] = 1.0
+    return v
+
+
+def him2col(params, keys, xs: scheme.Ciphertext, geom: ConvGeom, masks: np.ndarray, mask_scale: float,
+            counts: Counts | None = None) -> tuple[scheme.Ciphertext, Counts]:
+    """Im2Col ciphertexts of a DensePack input xs (M ciphertexts).
+
+    1. Per input ciphertext x_m, z_b = Rot(x_m, b H W) for 0 < b < B_m
+       (B_m channels in x_m), hoisted over x_m's decomposition; z_0 = x_m.
+    2. Per z_b, Rot(z_b, shift_t) for every nonzero tap shift, hoisted over
+       z_b's decomposition (the zero shift is z_b).
+    3. Ciphertext k = (kh d + kw) I_c + c (c = m B + b, t = kh d + kw) is
+       mask_t * Rot(z_b, shift_t) (masks[t]: him2col_mask_slots at
+       mask_scale, NTT domain), then all K are rescaled.
+    Counts: Rot sum_m (B_m - 1 + B_m #nonzero shifts), MulPC K, K rescales."""
+    counts = counts if counts is not None else Counts()
+    slots = params.slots
+    per = geom.channels_per_ct(slots)
+    hw = geom.h * geom.w
+    shifts = [s % slots for s in tap_shifts(geom)]
+    nonzero = [s for s in shifts if s != 0]
+    d2 = geom.d * geom.d
+    out = [None] * (d2 * geom.c_in)
+    for m in range(xs.c.shape[0]):
+        x = scheme.Ciphertext(xs.c[m], xs.scale)
+        b_m = min(per, geom.c_in - m * per)
+        blocks = [x] + (scheme.rotate_hoisted(params, keys, x, [b * hw for b in range(1, b_m)]) if b_m > 1 else [])
+        counts.rot += b_m - 1
+        for b, z in enumerate(blocks):
+            rot = dict(zip(nonzero, scheme.rotate_hoisted(params, keys, z, nonzero))) if nonzero else {}
+            counts.rot += len(nonzero)
+            c = m * per + b
+            for t, s in enumerate(shifts):
+                y = z if s == 0 else rot[s]
+                out[t * geom.c_in + c] = scheme.mul_plain(params, y, masks[t], mask_scale).c
+                counts.mulpc += 1
+    y = scheme.rescale(params, scheme.Ciphertext(np.stack(out), xs.scale * mask_scale))
+    counts.rescale += len(out)
+    return y, counts
+
+
 def combine_cp_to_dp(params, keys, z: scheme.Ciphertext, spatial: int, per_dense: int,
                      counts: Counts | None = None):
     """CP->DP: dense_m = sum_{o in block m} Rot(Z_o, -(o mod B)*S)."""

@@ -436,3 +436,43 @@ def test_tap_ffconv_matches_fp64(square):
         assert np.abs(got[where] - ref[:, :, o].reshape(-1)).max() < 1e-3
         assert np.abs(got[rest]).max() < 1e-3
     assert cnt.square == (4 if square else 0)
+
+
+@pytest.mark.parametrize("shape,d,stride,pad", [((6, 6, 3), 3, 1, 1), ((9, 9, 2), 4, 2, 0), ((5, 5, 12), 3, 1, 1),
+                                                ((7, 5, 2), 3, 2, 1)])
+def test_him2col_columns_and_counts(shape, d, stride, pad):
+    """Homomorphic Im2Col from a DensePack input: ciphertext k decrypts to
+    column k of Eq. 1's matrix I (conv2d's im2col, an independent numpy
+    routine) at the output slots and to 0 elsewhere; ConvPack of the
+    columns decrypts to the FP64 conv; executed counts are K MulPC and
+    sum_m (B_m - 1 + B_m #nonzero shifts) rotations (K - #zero-shift columns
+    when every ciphertext is full and pad = 0 keeps one zero shift)."""
+    p = P.Params(512, (30, 30, 30, 30), 36, 2.0**25)
+    geom = C.ConvGeom(shape[0], shape[1], shape[2], d, stride, pad)
+    ctx = Wk.make_context(p, W, rotations=C.him2col_rotation_steps(geom, p.slots))
+    x = synth.image(W, shape)
+    xs = S.Ciphertext(np.stack([Wk.encrypt_slots(ctx, v, 4, p.scale, W, 800 + m).c
+                                for m, v in enumerate(C.densepack_slots(x, geom, p.slots))]), p.scale)
+    ms = float(p.q[3])
+    masks = [E.encode(C.him2col_mask_slots(geom, p.slots, t), p, 4, ms) for t in range(d * d)]
+    y, cnt = C.him2col(p, ctx, xs, geom, masks, ms)
+    assert y.level == 3 and abs(y.scale / p.scale - 1) < 1e-12
+    cols = R.im2col(x, d, stride, pad)
+    where = C.tap_output_slots(geom)
+    rest = np.ones(p.slots, bool)
+    rest[where] = False
+    assert y.c.shape[0] == cols.shape[1] == d * d * shape[2]
+    for k in range(cols.shape[1]):
+        got = ctx.decrypt(S.Ciphertext(y.c[k], y.scale))
+        assert np.abs(got[where] - cols[:, k]).max() < 1e-3, k
+        assert np.abs(got[rest]).max() < 1e-3, k
+    per = geom.channels_per_ct(p.slots)
+    nz = sum(1 for s in C.tap_shifts(geom) if s % p.slots)
+    want = sum((min(per, shape[2] - m * per) - 1) + min(per, shape[2] - m * per) * nz for m in range(xs.c.shape[0]))
+    assert cnt.rot == want and cnt.mulpc == d * d * shape[2] and cnt.rescale == d * d * shape[2]
+    w = synth.weights(W, 85, (d, d, shape[2], 2), 0.2)
+    z, _ = C.convpack(p, y, R.filters_as_matrix(w), p.scale)
+    ref = R.conv2d(x, w, stride, pad)
+    for o in range(2):
+        got = ctx.decrypt(S.Ciphertext(z.c[o], z.scale))
+        assert np.abs(got[where] - ref[:, :, o].reshape(-1)).max() < 1e-3
