@@ -624,6 +624,183 @@ def cifar_section(torch, steps: int, plain: bool, digests_path: str):
     return res
 
 
+def packing_ablation_section(torch, reps: int) -> dict:
+    """The four packings of FFConv's two factors (Table IX) at the shapes of
+    WideNet's second conv (Sec. 5: 14x14x83 input, W1 6x6 stride 2 to 20
+    channels, W2 1x1 20 -> 163), synthetic input and weights, one input
+    ciphertext set at N = 16384 (6 x 40-bit + 60-bit P, scale 2^30):
+      DP-HI2C-CP  W1 DensePack, gather (HI2C, d = 1), W2 ConvPack (ffconv_layer)
+      DP-DP       W1 DensePack, one-hot arrangement into a DensePack input, W2 DensePack
+      CP-HI2C-CP  homomorphic Im2Col (d = 6), W1 ConvPack, W2 ConvPack (HGrouping: nothing)
+      CP-HI2C-DP  homomorphic Im2Col, W1 ConvPack, combine (I_c - 1 rotations), W2 DensePack
+    Per variant: time of each part, executed counts, and the paper's
+    formula counts (Tables I-III, log2 N rotations per DensePack dot
+    product).  Timing and counts only; the DensePack W2 after the
+    Im2Col-based W1 runs on a 9 x 14 plane (the W1 outputs keep their
+    stride-2 slots), so it computes 5 x 7 positions per channel, 10 of them
+    outside the 5 x 5 output."""
+    import numpy as np
+
+    import synth
+    from paper_2102_03494_amd import layers as Ly
+    from paper_2102_03494_amd.client import Client
+    from paper_2102_03494_amd.he import Ct, HEContext
+
+    wl = "widenet_n16384"
+    n, level, scale = 16384, 6, 2.0**30
+    slots = n // 2
+    ctx = HEContext(n, (40,) * level, 60)
+    cl = Client(ctx, wl)
+    g1 = Ly.Geometry(14, 14, 83, 6, 2, 0)
+    r, o_c = 20, 163
+    r_steps = int(math.log2(slots))
+    g2p = Ly.Geometry(9, 14, r, 1, 2, 0)  # W2 DensePack over the W1 outputs' stride-2 slots
+    steps = set(Ly.rot_steps(ctx)) | set(Ly.him2col_rotation_steps(g1, slots))
+    steps |= {(-(c * g2p.h * g2p.w)) % slots for c in range(1, r)}
+    cl.gen_rotation_keys(sorted(steps))
+    x = synth.image(wl, (14, 14, 83))
+    cts = torch.stack([cl.encrypt(v, level, scale, index=m).data[0] for m, v in enumerate(Ly.densepack_layout(x, g1, slots))])
+    xct = Ct(cts, scale)
+    w1 = synth.weights(wl, 1, (6, 6, 83, r), 0.02)
+    w2 = synth.weights(wl, 2, (r, o_c), 0.05)
+    w1m = w1.reshape(-1, r)
+    enc = Ly.PlainEncoder(ctx)
+    s_out = g1.spatial  # 25
+    k_cols = 6 * 6 * 83
+    lg = math.log2(n)
+    out = {"workload": "WideNet conv2 shapes (14x14x83, W1 6x6 s2 -> 20, W2 1x1 -> 163), synthetic U[0,1) input "
+                       "and N(0, 0.02^2) / N(0, 0.05^2) weights, N=16384 (6x40-bit + 60-bit P), scale 2^30",
+           "paper_table_ix_s": {"CP-HI2C-DP": 3269.65, "CP-HI2C-CP": 2560.49, "DP-DP": 784.45, "DP-HI2C-CP": 75.27}}
+
+    def run(parts):
+        """parts: [(name, fn)]; time each part (median of reps) and collect counts."""
+        res, counts = {}, {}
+        for name, fn in parts:
+            ts = []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            res[name + "_s"] = sorted(ts)[len(ts) // 2]
+            counts[name] = ctx.last_counts()
+        res["total_s"] = sum(v for k, v in res.items() if k.endswith("_s"))
+        return res, counts
+
+    state = {}
+    # ---- DP-HI2C-CP (ours)
+    desc1 = ctx.conv_desc(14, 14, 83, 6, 2, 0, r, r_steps)
+    pts1 = Ly.pt_scale_for(ctx, level, scale, scale)
+    f1 = Ly.encode_filters(enc, w1, g1, level, pts1)
+    ms = Ly.mask_scale_for(ctx, level - 1, scale, scale, K_BITS)
+    onehot = Ly.onehot_mask(enc, level - 1, ms)
+    ctx.reserve(ctx.ffconv_workspace_need(1, level, desc1, o_c, False))
+    res, cnt = run([("W1+HI2C+W2", lambda: ctx.ffconv_layer(xct, desc1, f1, pts1, onehot, ms, w2, K_BITS, False))])
+    out["DP-HI2C-CP"] = {"time": res, "executed": cnt,
+                         "paper": {"W1 DP": {"mulpc": r * s_out, "rot": r * s_out * lg, "addcc": r * s_out * lg},
+                                   "HI2C d=1": {"mulpc": r, "rot": r, "addcc": 0},
+                                   "W2 CP": {"mulpc": o_c * r, "rot": 0, "addcc": o_c * (r - 1)}}}
+    print(f"# ablation DP-HI2C-CP {res['total_s'] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    # ---- DP-DP
+    ms_arr = float(ctx.q[level - 2])
+    arr_mask = Ly.onehot_mask(enc, level - 1, ms_arr)
+    g2 = Ly.Geometry(5, 5, r, 1, 1, 0)
+    desc2 = ctx.conv_desc(5, 5, r, 1, 1, 0, o_c, r_steps)
+    f2 = Ly.encode_filters(enc, w2.reshape(1, 1, r, o_c), g2, level - 2, float(ctx.q[level - 3]))
+    ctx.reserve(ctx.workspace_need(min(o_c * s_out, 16000), level - 2) + ctx.workspace_need(r * s_out, level))
+
+    def dp_w1():
+        state["y"] = ctx.conv_densepack(xct, desc1, f1, pts1)
+
+    def dp_arrange():
+        dense = ctx.gather_onehot(Ct(state["y"].data, state["y"].scale), r * s_out, arr_mask, ms_arr)
+        state["dense"] = ctx.rescale(dense)
+
+    def dp_w2():
+        state["z"] = ctx.conv_densepack(Ct(state["dense"].data, state["dense"].scale), desc2, f2,
+                                        float(ctx.q[level - 3]))
+
+    res, cnt = run([("W1", dp_w1), ("arrange", dp_arrange), ("W2", dp_w2)])
+    out["DP-DP"] = {"time": res, "executed": cnt,
+                    "paper": {"W1 DP": {"mulpc": r * s_out, "rot": r * s_out * lg, "addcc": r * s_out * lg},
+                              "W2 DP": {"mulpc": o_c * s_out, "rot": o_c * s_out * lg, "addcc": o_c * s_out * lg}}}
+    print(f"# ablation DP-DP {res['total_s'] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    state.clear()
+    del f1, f2
+    torch.cuda.empty_cache()
+    # ---- CP-HI2C-CP and CP-HI2C-DP share the homomorphic Im2Col and the W1 ConvPack
+    descm = ctx.conv_desc(14, 14, 83, 6, 2, 0, 1, 0)
+    ms_i = float(ctx.q[level - 1])
+    masks = Ly.encode_him2col_masks(enc, g1, level, ms_i)
+    ctx.reserve(ctx.him2col_workspace_need(1, level, descm))
+
+    def hi2c():
+        state["cols"] = ctx.him2col(cts[None], scale, descm, masks, ms_i)
+
+    def cp_w1():
+        c_ = state["cols"]
+        state["y"] = ctx.conv_convpack(Ct(c_.data[0], c_.scale), w1m, scale)
+
+    def cp_w2():
+        state["z"] = ctx.conv_convpack(state["y"], w2, scale)
+
+    res, cnt = run([("HI2C", hi2c), ("W1", cp_w1), ("W2", cp_w2)])
+    paper_hi2c = {"mulpc": 14 * 14 * 83, "rot": s_out * k_cols, "addcc": s_out * k_cols}
+    # per-rotation time of a batched (not hoisted) rotation of the K Im2Col
+    # ciphertexts at level 6, to price Table III's HI2C count
+    ctx.reserve(max(ctx.him2col_workspace_need(1, level, descm), ctx.workspace_need(k_cols, level)))
+    big = Ct(state["cols"].data[0].new_zeros((k_cols, 2, level, n)), scale)
+    big.data[:, :, :, :] = cts[0][None]
+    ctx.rotate(big, 1, out=big.data)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.rotate(big, 1, out=big.data)
+    torch.cuda.synchronize()
+    t_rot = (time.perf_counter() - t0) / k_cols
+    del big
+    out["batched_rotation_ms_level6"] = t_rot * 1e3
+    out["table_iii_hi2c_projected_s"] = paper_hi2c["rot"] * t_rot
+    out["CP-HI2C-CP"] = {"time": res, "executed": cnt,
+                         "paper": {"HI2C d=6": paper_hi2c,
+                                   "W1 CP": {"mulpc": r * k_cols, "rot": 0, "addcc": r * (k_cols - 1)},
+                                   "HGrouping d=1": {"mulpc": 0, "rot": 0, "addcc": 0},
+                                   "W2 CP": {"mulpc": o_c * r, "rot": 0, "addcc": o_c * (r - 1)}}}
+    print(f"# ablation CP-HI2C-CP {res['total_s'] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    block = g2p.h * g2p.w
+    desc2p = ctx.conv_desc(9, 14, r, 1, 2, 0, o_c, r_steps)
+    f2p = Ly.encode_filters(enc, w2.reshape(1, 1, r, o_c), g2p, level - 2, float(ctx.q[level - 3]))
+    ctx.reserve(ctx.workspace_need(min(o_c * g2p.spatial, 16000), level - 2))
+
+    def combine():
+        y = state["y"]
+        state["dense"] = ctx.combine_cp_dp(Ct(y.data, y.scale), block, r)
+
+    def dp_w2p():
+        d_ = state["dense"]
+        state["z"] = ctx.conv_densepack(Ct(d_.data, d_.scale), desc2p, f2p, float(ctx.q[level - 3]))
+
+    res, cnt = run([("HI2C", hi2c), ("W1", cp_w1), ("combine", combine), ("W2", dp_w2p)])
+    out["CP-HI2C-DP"] = {"time": res, "executed": cnt,
+                         "paper": {"HI2C d=6": paper_hi2c,
+                                   "W1 CP": {"mulpc": r * k_cols, "rot": 0, "addcc": r * (k_cols - 1)},
+                                   "combine": {"mulpc": 0, "rot": r - 1, "addcc": r - 1},
+                                   "W2 DP": {"mulpc": o_c * s_out, "rot": o_c * s_out * lg,
+                                             "addcc": o_c * s_out * lg}}}
+    print(f"# ablation CP-HI2C-DP {res['total_s'] * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    state.clear()
+    ctx.close()
+    order = sorted(["DP-HI2C-CP", "DP-DP", "CP-HI2C-CP", "CP-HI2C-DP"], key=lambda k: out[k]["time"]["total_s"])
+    out["fastest_first"] = order
+    # the same ranking with the HI2C priced at Table III's rotation count
+    proj = {k: out[k]["time"]["total_s"] for k in ("DP-HI2C-CP", "DP-DP")}
+    for k in ("CP-HI2C-CP", "CP-HI2C-DP"):
+        proj[k] = out[k]["time"]["total_s"] - out[k]["time"]["HI2C_s"] + out["table_iii_hi2c_projected_s"]
+    out["total_s_with_table_iii_hi2c"] = proj
+    out["fastest_first_with_table_iii_hi2c"] = sorted(proj, key=proj.get)
+    return out
+
+
 TAP_KERNELS = ("ip_perm", "modup_store", "ks_digits", "intt_last", "drop_last", "tap_hma", "ks_modup_stage",
                "hma_perm", "scalar_mac", "tensor_sq")
 
@@ -836,6 +1013,7 @@ def main():
                     help="independent layers in the batched/graph section (0 = skip)")
     ap.add_argument("--no-ragged", action="store_true", help="skip the ragged 64-ciphertext batch section")
     ap.add_argument("--no-tap", action="store_true", help="skip the tap-style DensePack section")
+    ap.add_argument("--no-ablation", action="store_true", help="skip the packing-variant ablation (WideNet shapes)")
     ap.add_argument("--no-cifar", action="store_true", help="skip the N=16384 CIFAR-shaped layer section")
     ap.add_argument("--no-rank-sweep", action="store_true", help="skip the low-rank factorisation sweep (N=8192)")
     ap.add_argument("--no-cifar-plain", action="store_true",
@@ -1010,6 +1188,12 @@ def main():
         print("# tap-style DensePack section", file=sys.stderr, flush=True)
         tap = tap_section(torch, max(1, min(args.steps, 5)))
 
+    ablation = None
+    if not args.no_ablation:
+        torch.cuda.empty_cache()
+        print("# packing-variant ablation", file=sys.stderr, flush=True)
+        ablation = packing_ablation_section(torch, max(1, min(args.steps, 2)))
+
     serving = None
     if args.serve_window > 0:
         torch.cuda.empty_cache()
@@ -1057,6 +1241,7 @@ def main():
         "hoisted_rotations": hoisted,
         "cifar_layer": cifar,
         "tap_style_densepack": tap,
+        "packing_ablation": ablation,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

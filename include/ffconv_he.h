@@ -431,6 +431,34 @@ int ffconv_layer_tap(he_ctx *ctx, int n_batch, const uint64_t *d_in, int level, 
                      double mask_scale, const double *h_w2, int o_c2, int k_bits, int square, uint64_t *d_out,
                      double *out_scale, void *stream);
 
+/* ---- homomorphic Im2Col for d > 1 (Table III, CP-HI2C-CP / CP-HI2C-DP) -----
+ * he_him2col: the K = d^2 I_c ConvPack input ciphertexts of Eq. 1 from a
+ *          DensePack input (layout as for he_conv_tap; same geometry limits,
+ *          and at most 65 channels per ciphertext).  The paper gives only
+ *          the counts; this algorithm:
+ *   1. z[m][b] = Rot(x_m, b h w), 0 < b < B_m (B_m channels in x_m), hoisted
+ *      per input ciphertext; z[m][0] = x_m;
+ *   2. each z[m][b] rotated by every nonzero tap shift (kh - pad) w +
+ *      (kw - pad), hoisted per z[m][b];
+ *   3. ciphertext k = (kh d + kw) c_in + c (c = m B + b, tap t = kh d + kw)
+ *      = mask_t * Rot(z[m][b], shift_t), d_masks [d^2][mask_limbs][N]
+ *      (first `level` limbs used, NTT domain, at mask_scale): mask t is one
+ *      at the slot (s i) w + s j of every output (i, j) whose tap t lies
+ *      inside the image, zero elsewhere;
+ *   4. one rescale of each.
+ *   d_in [n_batch][M][2][level][N] at in_scale; d_out
+ *   [n_batch][K][2][level-1][N], output (i, j)'s pixel under the tap at slot
+ *   (s i) w + s j, zero elsewhere; *out_scale = in_scale mask_scale /
+ *   q_{level-1}.  Needs rotation keys for the block shifts and the nonzero
+ *   tap shifts.  Counts per input: Rot sum_m (B_m - 1 + B_m #nonzero
+ *   shifts), MulPC K, K rescales.  HE_ELEVEL unless 2 <= level <= L;
+ *   HE_EINVAL for mask_limbs < level or more than 65535 outputs per call.
+ * he_him2col_workspace_need: its workspace bytes (0: bad geometry or level). */
+size_t he_him2col_workspace_need(he_ctx *ctx, int n_batch, int level, const he_conv_desc *desc);
+int he_him2col(he_ctx *ctx, int n_batch, const uint64_t *d_in, int level, const he_conv_desc *desc,
+               const uint64_t *d_masks, int mask_limbs, double in_scale, double mask_scale, uint64_t *d_out,
+               double *out_scale, void *stream);
+
 /* ffconv_layer_convpack (Section 4.2.2 "ConvPack for W1", Fig. 5; CP-HI2C-CP
  * with d = 1 in Tables III and IX): FFConv with both factors under ConvPack,
  * no rotation at all.

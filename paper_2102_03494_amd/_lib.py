@@ -88,6 +88,8 @@ SIGNATURES = {
     "ffconv_layer": (I, [P, P, I, ctypes.POINTER(HeConvDesc), P, P, DP, I, I, I, P, P]),
     "ffconv_layer_convpack": (I, [P, P, I, I, DP, I, DP, I, ctypes.c_double, ctypes.c_double, I, P, DP, P]),
     "he_int_weight_table": (I, [P, DP, I, I, I, P, P]),
+    "he_him2col_workspace_need": (ctypes.c_size_t, [P, I, I, ctypes.POINTER(HeConvDesc)]),
+    "he_him2col": (I, [P, I, P, I, ctypes.POINTER(HeConvDesc), P, I, ctypes.c_double, ctypes.c_double, P, DP, P]),
     "he_tap_workspace_need": (ctypes.c_size_t, [P, I, I, ctypes.POINTER(HeConvDesc), I, I]),
     "he_conv_tap": (I, [P, I, P, I, ctypes.POINTER(HeConvDesc), P, I, ctypes.c_double, ctypes.c_double, P, DP, P]),
     "ffconv_layer_tap": (I, [P, I, P, I, ctypes.POINTER(HeConvDesc), P, I, ctypes.c_double, ctypes.c_double, P,

@@ -578,11 +578,13 @@ int ffconv_tail(he_ctx* c, int n_layers, const u64* y, int l1, int spatial, int 
 
 // Rotations of n_in ciphertexts (ciphertext i at in + i in_stride,
 // [2][level][N]) by the m rotations of hk; the rotations of one ciphertext
-// share its digit decomposition and ModUp.  out = [n_in][m][2][level][N].
+// share its digit decomposition and ModUp.  out = [n_in][m][2][level][N]
+// (with out_stride: rotation r of ciphertext i at out + i out_stride +
+// r 2 level N).
 // Ciphertexts go in passes that fit the workspace (a single ciphertext's
 // rotations in chunks when even one does not fit whole).
 int hoisted_batch(he_ctx* c, const u64* in, size_t in_stride, int n_in, int level, const HoistKeys& hk, int m,
-                  u64* out, Arena& ar, hipStream_t s) {
+                  u64* out, Arena& ar, hipStream_t s, size_t out_stride = 0) {
   const int n = c->n;
   const size_t per_ct = (size_t)level * n + (size_t)level * (level + 1) * n + 128;  // digits, lifted digits
   const size_t per_rot = (size_t)2 * (level + 2) * n + 64;                         // u rows, ModDown input, job
@@ -604,13 +606,15 @@ int hoisted_batch(he_ctx* c, const u64* in, size_t in_stride, int n_in, int leve
   u64* rc = sub.take<u64>(rch * 2 * n);
   if (!jobs1 || !jobs || !dcoef || !dhat || !u || !rc)
     return fail(c, HE_ENOMEM, "workspace too small for hoisted rotations at level %d", level);
-  const size_t ostride = (size_t)2 * level * n;
+  const size_t ostride = out_stride ? out_stride : (size_t)m * 2 * level * n;  // between input ciphertexts
   for (int i0 = 0; i0 < n_in; i0 += (int)cc) {
     const int cn = std::min((int)cc, n_in - i0);
     const u64* cin = in + (size_t)i0 * in_stride;
-    u64* cout = out + (size_t)i0 * m * ostride;
-    k_make_hoist_jobs<<<dim3((cn + 255) / 256, 1), 256, 0, s>>>(jobs1, cn, 1, cin, in_stride, cout, level, n, hk, 1);
-    k_make_hoist_jobs<<<dim3((cn + 255) / 256, m), 256, 0, s>>>(jobs, cn, m, cin, in_stride, cout, level, n, hk, 0);
+    u64* cout = out + (size_t)i0 * ostride;
+    k_make_hoist_jobs<<<dim3((cn + 255) / 256, 1), 256, 0, s>>>(jobs1, cn, 1, cin, in_stride, cout, ostride, level, n,
+                                                                 hk, 1);
+    k_make_hoist_jobs<<<dim3((cn + 255) / 256, m), 256, 0, s>>>(jobs, cn, m, cin, in_stride, cout, ostride, level, n,
+                                                                 hk, 0);
     dispatch_logn<LHoistUp>(c->logn, c, (const KsJob*)jobs1, cn, level, dcoef, dhat, s);
     const int total = cn * m;
     for (int r0 = 0; r0 < total; r0 += (int)rch) {
@@ -739,6 +743,63 @@ int tap_run(he_ctx* c, const TapPlan& tp, int nb, const u64* in, int level, cons
   c->counts.addcc += (int64_t)n_out * (tp.m_cts * d2 - 1 + steps);
   c->counts.rescale += n_out;
   return HE_OK;
+}
+
+// ---- Homomorphic Im2Col (d > 1) ---------------------------------------------
+struct Him2colPlan {
+  int per = 0, m_cts = 0, hw = 0, nrot = 0, last = 0;  // last: channels in the last input ciphertext
+  Him2colMap map{};
+  HoistKeys tap{}, blk{};
+  int nblk = 0;
+};
+
+int him2col_plan(he_ctx* c, const he_conv_desc* g, Him2colPlan& hp, bool need_keys = true) {
+  TapPlan tp;
+  he_conv_desc d1 = *g;
+  d1.o_c = 1;
+  int e = tap_plan(c, "he_him2col", &d1, tp, false);
+  if (e) return e;
+  const int n = c->n;
+  hp.per = tp.per;
+  hp.m_cts = tp.m_cts;
+  hp.hw = tp.hw;
+  hp.nrot = tp.nrot;
+  hp.tap = tp.hk;
+  hp.last = g->c_in - (tp.m_cts - 1) * tp.per;
+  hp.nblk = tp.per - 1;
+  if (hp.nblk > MAX_HOIST) return fail(c, HE_EINVAL, "he_him2col: %d channels per ciphertext (at most %d)", tp.per,
+                                       MAX_HOIST + 1);
+  for (int r = 0; r < tp.nrot; ++r)
+    if (need_keys && !tp.hk.key[r]) return fail(c, HE_ENOKEY, "he_him2col: no rotation key for a tap shift");
+  for (int b = 1; b < tp.per; ++b) {
+    const u32 gal = galois_of(b * tp.hw, n);
+    auto it = c->keys.find((int)gal);
+    if (need_keys && it == c->keys.end()) return fail(c, HE_ENOKEY, "he_him2col: no rotation key for block shift %d",
+                                                      b * tp.hw);
+    hp.blk.key[b - 1] = it == c->keys.end() ? nullptr : it->second;
+    hp.blk.g[b - 1] = gal;
+    hp.blk.ginv[b - 1] = galois_of(-b * tp.hw, n);
+  }
+  hp.map.d2 = g->d * g->d;
+  hp.map.c_in = g->c_in;
+  hp.map.per = tp.per;
+  hp.map.m_cts = tp.m_cts;
+  hp.map.nrot = tp.nrot;
+  hp.map.nvalid = g->c_in;  // (M - 1) B + last
+  for (int t = 0; t < hp.map.d2; ++t) hp.map.idx[t] = tp.map.idx[t];
+  return HE_OK;
+}
+
+size_t him2col_need(const he_ctx* c, const Him2colPlan& hp, int nb, int level) {
+  auto al = [](size_t elems) { return ((elems * 8 + 255) & ~(size_t)255); };
+  const size_t n = c->n, cs = 2 * (size_t)level * n;
+  const size_t k = (size_t)hp.map.d2 * hp.map.c_in;
+  size_t need = al((size_t)nb * hp.m_cts * hp.per * cs) + al((size_t)nb * hp.map.nvalid * hp.nrot * cs) +
+                al((size_t)nb * k * cs);
+  const int m = std::max(1, std::max(hp.nrot, hp.nblk));
+  need += ((size_t)level * n + (size_t)level * (level + 1) * n + 128 + (size_t)m * (2 * (level + 2) * n + 64)) * 8 +
+          std::min<size_t>((size_t)nb * k, 32000) * (2 * n + 64) * 8;
+  return need + ((size_t)16 << 20);
 }
 
 }  // namespace
@@ -1530,6 +1591,65 @@ int ffconv_layer_tap(he_ctx* c, int n_batch, const uint64_t* d_in, int level, co
   double z_scale = y_scale * mask_scale * std::ldexp(1.0, k_bits) / (double)c->moduli[level - 2];
   if (square) z_scale = z_scale * z_scale / (double)c->moduli[level - 3];
   *out_scale = z_scale;
+  return HE_OK;
+}
+
+size_t he_him2col_workspace_need(he_ctx* c, int n_batch, int level, const he_conv_desc* desc) {
+  if (!c || !desc || n_batch < 1 || level < 2 || level > c->big_l) return 0;
+  Him2colPlan hp;
+  if (him2col_plan(c, desc, hp, false)) return 0;
+  return him2col_need(c, hp, n_batch, level);
+}
+
+int he_him2col(he_ctx* c, int n_batch, const uint64_t* d_in, int level, const he_conv_desc* desc,
+               const uint64_t* d_masks, int mask_limbs, double in_scale, double mask_scale, uint64_t* d_out,
+               double* out_scale, void* stream) {
+  if (!c || !d_in || !desc || !d_masks || !d_out || !out_scale || n_batch < 1 || mask_limbs < 1)
+    return fail(c, HE_EINVAL, "he_him2col: bad arguments");
+  if (level < 2 || level > c->big_l) return fail(c, HE_ELEVEL, "he_him2col needs 2 <= level <= L (got %d)", level);
+  if (mask_limbs < level) return fail(c, HE_EINVAL, "he_him2col: masks have %d limbs, level is %d", mask_limbs, level);
+  if (!scale_ok(in_scale) || !scale_ok(mask_scale))
+    return fail(c, HE_ESCALE, "he_him2col: scales %.17g, %.17g", in_scale, mask_scale);
+  Him2colPlan hp;
+  int e = him2col_plan(c, desc, hp);
+  if (e) return e;
+  const int kk = hp.map.d2 * desc->c_in;
+  if ((long long)n_batch * kk > 65535) return fail(c, HE_EINVAL, "he_him2col: more than 65535 outputs in one call");
+  const int n = c->n;
+  const size_t cs = (size_t)2 * level * n;
+  hipStream_t s = S(stream);
+  c->counts = he_counts{};
+  Arena ar(c);
+  u64* z = ar.take<u64>((size_t)n_batch * hp.m_cts * hp.per * cs);
+  u64* rot = hp.nrot ? ar.take<u64>((size_t)n_batch * hp.map.nvalid * hp.nrot * cs) : nullptr;
+  u64* tmp = ar.take<u64>((size_t)n_batch * kk * cs);
+  if (!z || (hp.nrot && !rot) || !tmp) return fail(c, HE_ENOMEM, "workspace too small for he_him2col");
+  for (int b = 0; b < n_batch; ++b) {
+    const u64* xb = d_in + (size_t)b * hp.m_cts * cs;
+    u64* zb = z + (size_t)b * hp.m_cts * hp.per * cs;
+    // z[b][m][0] = x_m; z[b][m][blk] = Rot(x_m, blk H W), hoisted per x_m
+    if (hipMemcpy2DAsync(zb, hp.per * cs * 8, xb, cs * 8, cs * 8, hp.m_cts, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return fail(c, HE_EDEVICE, "he_him2col: device copy failed");
+    if (hp.m_cts > 1 && hp.nblk > 0 &&
+        (e = hoisted_batch(c, xb, cs, hp.m_cts - 1, level, hp.blk, hp.nblk, zb + cs, ar, s, hp.per * cs)))
+      return e;
+    if (hp.last > 1 && (e = hoisted_batch(c, xb + (size_t)(hp.m_cts - 1) * cs, cs, 1, level, hp.blk, hp.last - 1,
+                                          zb + ((size_t)(hp.m_cts - 1) * hp.per + 1) * cs, ar, s, hp.per * cs)))
+      return e;
+    // every valid block-shifted ciphertext rotated by the nonzero tap shifts, hoisted per ciphertext
+    if (hp.nrot && (e = hoisted_batch(c, zb, cs, hp.map.nvalid, level, hp.tap, hp.nrot,
+                                      rot + (size_t)b * hp.map.nvalid * hp.nrot * cs, ar, s)))
+      return e;
+  }
+  k_him2col_mask<<<dim3(n / 256, level, n_batch * kk), 256, 0, s>>>(z, rot, d_masks, mask_limbs, tmp, level, n,
+                                                                     hp.map, c->mods);
+  if ((e = check_launch(c, "he_him2col masks"))) return e;
+  if ((e = rescale_batch(c, d_out, tmp, n_batch * kk, level, ar, s))) return e;
+  c->counts.rot += (int64_t)n_batch * ((int64_t)(hp.m_cts - 1) * hp.nblk + (hp.last - 1) +
+                                       (int64_t)hp.map.nvalid * hp.nrot);
+  c->counts.mulpc += (int64_t)n_batch * kk;
+  c->counts.rescale += (int64_t)n_batch * kk;
+  *out_scale = in_scale * mask_scale / (double)c->moduli[level - 1];
   return HE_OK;
 }
 

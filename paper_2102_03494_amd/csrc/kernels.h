@@ -1654,12 +1654,15 @@ k_hma_perm(u64* __restrict__ acc, const u64* __restrict__ cts, int K, const u64*
 // F[o][m][k] * X(b, m, k), where X(b, m, k) is the input x[b][m] for the tap
 // with shift 0 (idx[k] < 0) and its hoisted rotation
 // rot[(b M + m) nrot + idx[k]] otherwise.  F: [O][M][d^2][pt_limbs][N];
-// x, rot, out: ciphertexts [2][level][N].  grid (N / 256, level,
-// n_b ceil(O / TAP_OT)), 256 threads: a thread holds one coefficient of up to
-// TAP_OT outputs, so each product term reads 2 ciphertext words and one
-// plaintext word per output.  Narrow primes sum 15 products (< 2^60 each)
+// x, rot, out: ciphertexts [2][level][N].  grid (N / 64, level,
+// n_b ceil(O / TAP_OT)), 256 threads: 64 coefficients x TAP_SLICES slices
+// of the (m, k) sum (slice s takes terms s, s + TAP_SLICES, ...), each
+// thread holding up to TAP_OT outputs of its coefficient (per term 2
+// ciphertext words and one plaintext word per output are read); the slices'
+// partial sums meet in LDS.  Narrow primes sum 15 products (< 2^60 each)
 // before one reduction.
 constexpr int TAP_OT = 8;
+constexpr int TAP_SLICES = 4;
 struct TapMap {
   int d2, m_cts, o_c, nrot;
   signed char idx[64];
@@ -1669,7 +1672,10 @@ __global__ void __launch_bounds__(256)
 k_tap_hma(const u64* __restrict__ x, const u64* __restrict__ rot, const u64* __restrict__ filt, u64* __restrict__ out,
           int level, int pt_limbs, TapMap tm, Mods mods) {
   constexpr int N = 1 << LOGN;
-  const int i = blockIdx.x * 256 + (int)threadIdx.x;
+  __shared__ u64 part[TAP_SLICES][2 * TAP_OT][64];
+  const int lane = (int)threadIdx.x & 63;
+  const int sl = (int)threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
   const int t = blockIdx.y;
   const int n_ot = (tm.o_c + TAP_OT - 1) / TAP_OT;
   const size_t b = blockIdx.z / n_ot;
@@ -1679,6 +1685,7 @@ k_tap_hma(const u64* __restrict__ x, const u64* __restrict__ rot, const u64* __r
   const size_t cstride = (size_t)2 * level * N;
   const size_t fo = (size_t)tm.m_cts * tm.d2 * pt_limbs * N;  // from one output's plaintexts to the next
   const u64* fbase = filt + (size_t)o0 * fo + (size_t)t * N + i;
+  const int terms = tm.m_cts * tm.d2;
   u64 s0[TAP_OT], s1[TAP_OT];
 #pragma unroll
   for (int r = 0; r < TAP_OT; ++r) s0[r] = s1[r] = 0;
@@ -1687,29 +1694,28 @@ k_tap_hma(const u64* __restrict__ x, const u64* __restrict__ rot, const u64* __r
 #pragma unroll
     for (int r = 0; r < TAP_OT; ++r) l0[r] = l1[r] = 0;
     int n_lazy = 0;
-    for (int mc = 0; mc < tm.m_cts; ++mc) {
+    for (int e = sl; e < terms; e += TAP_SLICES) {
+      const int mc = e / tm.d2, k = e - mc * tm.d2;
       const size_t ct = b * tm.m_cts + mc;
-      for (int k = 0; k < tm.d2; ++k) {
-        const int id = tm.idx[k];
-        const u64* src = (id < 0 ? x + ct * cstride : rot + (ct * tm.nrot + id) * cstride) + (size_t)t * N + i;
-        const u64 a0 = (u32)src[0], a1 = (u32)src[(size_t)level * N];
-        const u64* f = fbase + ((size_t)mc * tm.d2 + k) * pt_limbs * N;
+      const int id = tm.idx[k];
+      const u64* src = (id < 0 ? x + ct * cstride : rot + (ct * tm.nrot + id) * cstride) + (size_t)t * N + i;
+      const u64 a0 = (u32)src[0], a1 = (u32)src[(size_t)level * N];
+      const u64* f = fbase + (size_t)e * pt_limbs * N;
 #pragma unroll
-        for (int r = 0; r < TAP_OT; ++r)
-          if (r < no) {
-            const u64 fv = (u32)f[r * fo];
-            l0[r] += a0 * fv;
-            l1[r] += a1 * fv;
-          }
-        if (++n_lazy == 15) {
-#pragma unroll
-          for (int r = 0; r < TAP_OT; ++r) {
-            s0[r] = add_mod(s0[r], reduce64(l0[r], m), m.q);
-            s1[r] = add_mod(s1[r], reduce64(l1[r], m), m.q);
-            l0[r] = l1[r] = 0;
-          }
-          n_lazy = 0;
+      for (int r = 0; r < TAP_OT; ++r)
+        if (r < no) {
+          const u64 fv = (u32)f[r * fo];
+          l0[r] += a0 * fv;
+          l1[r] += a1 * fv;
         }
+      if (++n_lazy == 15) {
+#pragma unroll
+        for (int r = 0; r < TAP_OT; ++r) {
+          s0[r] = add_mod(s0[r], reduce64(l0[r], m), m.q);
+          s1[r] = add_mod(s1[r], reduce64(l1[r], m), m.q);
+          l0[r] = l1[r] = 0;
+        }
+        n_lazy = 0;
       }
     }
 #pragma unroll
@@ -1718,32 +1724,50 @@ k_tap_hma(const u64* __restrict__ x, const u64* __restrict__ rot, const u64* __r
       s1[r] = add_mod(s1[r], reduce64(l1[r], m), m.q);
     }
   } else {
-    for (int mc = 0; mc < tm.m_cts; ++mc) {
+    for (int e = sl; e < terms; e += TAP_SLICES) {
+      const int mc = e / tm.d2, k = e - mc * tm.d2;
       const size_t ct = b * tm.m_cts + mc;
-      for (int k = 0; k < tm.d2; ++k) {
-        const int id = tm.idx[k];
-        const u64* src = (id < 0 ? x + ct * cstride : rot + (ct * tm.nrot + id) * cstride) + (size_t)t * N + i;
-        const u64 a0 = src[0], a1 = src[(size_t)level * N];
-        const u64* f = fbase + ((size_t)mc * tm.d2 + k) * pt_limbs * N;
+      const int id = tm.idx[k];
+      const u64* src = (id < 0 ? x + ct * cstride : rot + (ct * tm.nrot + id) * cstride) + (size_t)t * N + i;
+      const u64 a0 = src[0], a1 = src[(size_t)level * N];
+      const u64* f = fbase + (size_t)e * pt_limbs * N;
 #pragma unroll
-        for (int r = 0; r < TAP_OT; ++r)
-          if (r < no) {
-            const u64 fv = f[r * fo];
-            s0[r] = add_mod(s0[r], mul_mod(a0, fv, m), m.q);
-            s1[r] = add_mod(s1[r], mul_mod(a1, fv, m), m.q);
-          }
-      }
+      for (int r = 0; r < TAP_OT; ++r)
+        if (r < no) {
+          const u64 fv = f[r * fo];
+          s0[r] = add_mod(s0[r], mul_mod(a0, fv, m), m.q);
+          s1[r] = add_mod(s1[r], mul_mod(a1, fv, m), m.q);
+        }
     }
   }
 #pragma unroll
-  for (int r = 0; r < TAP_OT; ++r)
-    if (r < no) {
-      u64* o = out + ((b * tm.o_c + o0 + r) * 2 * level + t) * N + i;
-      o[0] = s0[r];
-      o[(size_t)level * N] = s1[r];
-    }
+  for (int r = 0; r < TAP_OT; ++r) {
+    part[sl][r][lane] = s0[r];
+    part[sl][TAP_OT + r][lane] = s1[r];
+  }
+  __syncthreads();
+  // 2 TAP_OT x 64 sums of TAP_SLICES partials; consecutive threads take consecutive coefficients
+  for (int e = (int)threadIdx.x; e < 2 * TAP_OT * 64; e += 256) {
+    const int l = e & 63, v = e >> 6;
+    const int c = v / TAP_OT, r = v - c * TAP_OT;
+    if (r >= no) continue;
+    u64 acc = part[0][v][l];
+#pragma unroll
+    for (int q = 1; q < TAP_SLICES; ++q) acc = add_mod(acc, part[q][v][l], m.q);
+    out[(((b * tm.o_c + o0 + r) * 2 + c) * level + t) * N + blockIdx.x * 64 + l] = acc;
+  }
 }
 
+// Homomorphic Im2Col, the masking step: out[b][k] (k = tap I_c + c,
+// c = m B + blk) = mask_tap * X, X the block-shifted ciphertext
+// z[b][m][blk] for the zero-shift tap (idx < 0) and its tap rotation
+// rot[b][(m B + blk) nrot + idx[tap]] otherwise (nvalid block-shifted
+// ciphertexts per input).  masks: [d^2][mask_limbs][N].  grid (N / 256,
+// level, n_b K).
+struct Him2colMap {
+  int d2, c_in, per, m_cts, nrot, nvalid;
+  signed char idx[64];
+};
 // ---------------------------------------------------------------------------
 // Client-side helpers (key generation, encryption, decryption).
 

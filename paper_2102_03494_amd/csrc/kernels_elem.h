@@ -49,11 +49,11 @@ __global__ void k_make_chain_jobs(KsJob* jobs, int count, u64* base, size_t stri
 
 // Jobs of hoisted rotations of n_in ciphertexts (ciphertext i at
 // in + i in_stride): jobs[i m + r] rotates ciphertext i by rotation r of hk
-// into out + (i m + r) 2 level n.  With digits_only, jobs[i] is ciphertext
+// into out + i out_stride + r 2 level n.  With digits_only, jobs[i] is ciphertext
 // i's decomposition job (no permutation; key hk.key[0] marks it as
 // switching).  grid (ceil(n_in / 256), m).
-__global__ void k_make_hoist_jobs(KsJob* jobs, int n_in, int m, const u64* in, size_t in_stride, u64* out, int level,
-                                  int n, HoistKeys hk, int digits_only) {
+__global__ void k_make_hoist_jobs(KsJob* jobs, int n_in, int m, const u64* in, size_t in_stride, u64* out,
+                                  size_t out_stride, int level, int n, HoistKeys hk, int digits_only) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   if (i >= n_in) return;
@@ -70,11 +70,34 @@ __global__ void k_make_hoist_jobs(KsJob* jobs, int n_in, int m, const u64* in, s
     jobs[i] = jb;
     return;
   }
-  jb.out = out + ((size_t)i * m + r) * 2 * level * n;
+  jb.out = out + (size_t)i * out_stride + (size_t)r * 2 * level * n;
   jb.key = hk.key[r];
   jb.g = hk.g[r];
   jb.ginv = hk.ginv[r];
   jobs[(size_t)i * m + r] = jb;
+}
+
+// The masking step of the homomorphic Im2Col (Him2colMap).
+__global__ void __launch_bounds__(256)
+k_him2col_mask(const u64* __restrict__ z, const u64* __restrict__ rot, const u64* __restrict__ masks, int mask_limbs,
+               u64* __restrict__ out, int level, int n, Him2colMap hm, Mods mods) {
+  const int i = blockIdx.x * 256 + (int)threadIdx.x;
+  const int t = blockIdx.y;
+  const size_t bk = blockIdx.z;
+  const int kk = hm.d2 * hm.c_in;
+  const size_t b = bk / kk;
+  const int k = (int)(bk % kk);
+  const int tap = k / hm.c_in, c = k % hm.c_in;
+  const int m = c / hm.per, blk = c % hm.per;
+  const size_t cs = (size_t)2 * level * n;
+  const int id = hm.idx[tap];
+  const u64* src = id < 0 ? z + ((b * hm.m_cts + m) * hm.per + blk) * cs
+                          : rot + ((b * hm.nvalid + (size_t)m * hm.per + blk) * hm.nrot + id) * cs;
+  const ModConst mc = mods.m[t];
+  const u64 mv = masks[((size_t)tap * mask_limbs + t) * n + i];
+  u64* o = out + (bk * 2 * level + t) * n + i;
+  o[0] = mul_mod(src[(size_t)t * n + i], mv, mc);
+  o[(size_t)level * n] = mul_mod(src[((size_t)level + t) * n + i], mv, mc);
 }
 
 // Switching keys made by a client, [L][2][L+1][N] canonical 64-bit residues

@@ -244,7 +244,7 @@ void LTapHma<LOGN>::run(he_ctx* c, const u64* x, const u64* rot, const u64* filt
   constexpr int N = 1 << LOGN;
   Prof pr(c, "tap_hma", s);
   const int n_ot = (tm.o_c + TAP_OT - 1) / TAP_OT;
-  k_tap_hma<LOGN><<<dim3(N / 256, level, n_b * n_ot), 256, 0, s>>>(x, rot, filt, out, level, pt_limbs, tm, c->mods);
+  k_tap_hma<LOGN><<<dim3(N / 64, level, n_b * n_ot), 256, 0, s>>>(x, rot, filt, out, level, pt_limbs, tm, c->mods);
 }
 
 }  // namespace he

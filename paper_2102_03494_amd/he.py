@@ -521,6 +521,26 @@ class HEContext:
                     "ffconv_layer_tap")
         return Ct(out, out_scale.value)
 
+    def him2col_workspace_need(self, n_batch: int, level: int, desc: HeConvDesc) -> int:
+        need = self.lib.he_him2col_workspace_need(self.h, n_batch, level, ctypes.byref(desc))
+        if need == 0:
+            raise HEError("he_him2col_workspace_need: bad geometry or level")
+        return need
+
+    def him2col(self, xs: torch.Tensor, scale: float, desc: HeConvDesc, masks: torch.Tensor, mask_scale: float,
+                out: torch.Tensor | None = None) -> Ct:
+        """Homomorphic Im2Col of DensePack inputs xs [B][M][2][level][N]
+        with the tap masks [d^2][limbs][N]; returns [B][K][2][level-1][N]."""
+        nb, level = xs.shape[0], xs.shape[-2]
+        k = desc.d * desc.d * desc.c_in
+        if out is None:
+            out = torch.empty((nb, k, 2, level - 1, self.n), dtype=torch.int64, device="cuda")
+        out_scale = ctypes.c_double(0.0)
+        self._check(self.lib.he_him2col(self.h, nb, _ptr(xs), level, ctypes.byref(desc), _ptr(masks),
+                                        masks.shape[-2], float(scale), float(mask_scale), _ptr(out),
+                                        ctypes.byref(out_scale), _stream()), "he_him2col")
+        return Ct(out, out_scale.value)
+
     # ---- layer pieces for iteration-level batching ------------------------------
     def densepack_hma(self, xs: torch.Tensor, desc: HeConvDesc, filt: torch.Tensor, shared_filters: bool = True,
                       out: torch.Tensor | None = None) -> torch.Tensor:

@@ -169,6 +169,25 @@ def tap_filter_layout(weights: np.ndarray, g: Geometry, slots: int, o: int, m: i
     return v
 
 
+def him2col_rotation_steps(g: Geometry, slots: int) -> list[int]:
+    """Rotation keys of he_him2col: the nonzero tap shifts and the block
+    shifts b H W, 0 < b < B."""
+    amounts = {s % slots for s in tap_shifts(g)} | {b * g.h * g.w for b in range(1, g.per_ct(slots))}
+    return sorted(amounts - {0})
+
+
+def him2col_mask_layout(g: Geometry, slots: int, t: int) -> np.ndarray:
+    """Mask of tap t: one at the slot of every output whose tap t is inside
+    the image."""
+    ones = np.ones((g.d, g.d, 1, 1))
+    return tap_filter_layout(ones, Geometry(g.h, g.w, 1, g.d, g.stride, g.pad), slots, 0, 0, t)
+
+
+def encode_him2col_masks(enc, g: Geometry, level: int, scale: float) -> torch.Tensor:
+    slots = enc.ctx.n // 2
+    return torch.stack([enc.encode(him2col_mask_layout(g, slots, t), level, scale) for t in range(g.d * g.d)])
+
+
 def tap_output_mask_layout(g: Geometry, slots: int) -> np.ndarray:
     v = np.zeros(slots)
     v[tap_output_slots(g)] = 1.0

@@ -51,6 +51,7 @@ WORKLOADS = {
     "tap_mnist": 6,        # tap-style DensePack, 28x28x1 5x5 s2 layer, N=8192
     "tap_cifar1": 7,       # tap-style DensePack, 32x32x3 3x3 layer, N=16384
     "tap_cifar2": 8,       # tap-style DensePack, 32x32x64 3x3 layer, N=16384
+    "widenet_n16384": 9,   # packing-variant ablation at WideNet conv2 shapes
     "unit": 99,            # small unit-test rings
 }
 

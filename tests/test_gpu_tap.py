@@ -201,3 +201,38 @@ def test_tap_net_batch_bits_and_fp64(name):
             ref = ref.reshape(-1, ref.shape[-1])
         got = net.decode(cl, out, b)
         assert np.abs(got - ref.reshape(got.shape)).max() < 1e-3, b
+
+
+@pytest.mark.parametrize("shape,d,stride,pad", [((6, 6, 3), 3, 1, 1), ((9, 9, 2), 4, 2, 0), ((5, 5, 24), 3, 1, 1),
+                                                ((7, 5, 2), 3, 2, 1)])
+def test_him2col_bit_exact(shape, d, stride, pad):
+    """Homomorphic Im2Col (block shifts, then tap shifts, both hoisted; tap
+    masks; rescale) for two inputs in one call equals the oracle's for each,
+    with its scale and counts."""
+    Ly = _layers()
+    geom = C.ConvGeom(*shape, d, stride, pad)
+    g = Ly.Geometry(*shape, d, stride, pad)
+    rots = C.him2col_rotation_steps(geom, 512)
+    assert Ly.him2col_rotation_steps(g, 512) == rots
+    p, octx, gctx, cl = _small_setup(rotations=rots)
+    level, nb = 4, 2
+    ms = float(p.q[level - 1])
+    want_m = np.stack([E.encode(C.him2col_mask_slots(geom, p.slots, t), p, level, ms) for t in range(d * d)])
+    masks = Ly.encode_him2col_masks(Ly.PlainEncoder(gctx), g, level, ms)
+    assert np.array_equal(_host(masks), want_m)
+    xs, cts = _tap_inputs(p, octx, geom, shape, level, nb, 70)
+    desc = gctx.conv_desc(*shape, d, stride, pad, 1, 0)
+    gctx.reserve(gctx.him2col_workspace_need(nb, level, desc))
+    got = gctx.him2col(_dev(cts), p.scale, desc, masks, ms)
+    out = _host(got.data)
+    gc = gctx.last_counts()
+    for b in range(nb):
+        want, cnt = C.him2col(p, octx, S.Ciphertext(cts[b], p.scale), geom, want_m, ms)
+        assert np.array_equal(out[b], want.c), b
+        assert got.scale == want.scale
+    assert (gc["rot"], gc["mulpc"], gc["rescale"]) == (nb * cnt.rot, nb * cnt.mulpc, nb * cnt.rescale)
+    cols = R.im2col(xs[1], d, stride, pad)
+    where = C.tap_output_slots(geom)
+    for k in (0, cols.shape[1] // 2, cols.shape[1] - 1):
+        v = cl.decrypt(got.data[1, k], got.scale)
+        assert np.abs(v[where] - cols[:, k]).max() < 1e-3, k
