@@ -124,7 +124,12 @@ const char *he_last_error(const he_ctx *ctx);
  * target (N >= 2048; a launch follows its largest level), 0 as one workgroup
  * per target.  knob "hoist_fused" (level ignored; 0 by default, 0 or 1): in
  * he_rotate_hoisted, compute each rotation's inner-product rows inside its
- * ModDown (1) or write them to the workspace first (0).  he_ctx_set_tuning returns
+ * ModDown (1) or write them to the workspace first (0).  knob
+ * "hoist_pipeline" (level ignored; 1 by default, 0 or 1): hoisted rotations
+ * (he_rotate_hoisted(_batch) and the layers built on them) with 64 or more
+ * rotations whose temporaries all fit run as up to four chunks, the inner
+ * products of one chunk on the call's stream while the previous chunk's
+ * P INTT and ModDown run on a second stream.  he_ctx_set_tuning returns
  * HE_EINVAL for an unknown knob or out-of-range level/value;
  * he_ctx_get_tuning returns the value in effect (>= 0) or a negative code. */
 int he_ctx_set_tuning(he_ctx *ctx, const char *knob, int level, int value);

@@ -576,6 +576,34 @@ int ffconv_tail(he_ctx* c, int n_layers, const u64* y, int l1, int spatial, int 
   return e;
 }
 
+// Inner products, P INTT and ModDown of m hoisted rotations whose
+// inner-product rows (u) and P-limb coefficients (rc) all fit: the rows of
+// chunk k are computed on s while chunk k - 1 is taken down on the side
+// stream (the first stage streams keys from HBM, the second is transform
+// arithmetic), then s waits for the side stream.  Without a side stream or
+// with few rotations, one stream.
+void hoisted_rest(he_ctx* c, const KsJob* jobs, int m, int level, const u64* dhat, u64* u, u64* rc, hipStream_t s,
+                  int per_ct, size_t dstride) {
+  const int n = c->n;
+  const int sub = m >= 64 ? (m + 3) / 4 : m;  // at most 4 chunks: one event each
+  if (!c->side || !c->hoist_pipeline || sub == m) {
+    dispatch_logn<LHoisted>(c->logn, c, jobs, m, level, dhat, u, rc, s, 0, per_ct, dstride);
+    return;
+  }
+  for (int r0 = 0, k = 0; r0 < m; r0 += sub, ++k) {
+    const int cm = std::min(sub, m - r0);
+    u64* ur = u + (size_t)r0 * 2 * (level + 1) * n;
+    u64* rr = rc + (size_t)r0 * 2 * n;
+    dispatch_logn<LHoisted>(c->logn, c, jobs + r0, cm, level, dhat, ur, rr, s, r0, per_ct, dstride, 1);
+    // the side stream sees everything s did up to this chunk's inner products
+    (void)hipEventRecord(c->pipe_ev[k], s);
+    (void)hipStreamWaitEvent(c->side, c->pipe_ev[k], 0);
+    dispatch_logn<LHoisted>(c->logn, c, jobs + r0, cm, level, dhat, ur, rr, c->side, r0, per_ct, dstride, 2);
+  }
+  (void)hipEventRecord(c->join_ev, c->side);
+  (void)hipStreamWaitEvent(s, c->join_ev, 0);
+}
+
 // Rotations of n_in ciphertexts (ciphertext i at in + i in_stride,
 // [2][level][N]) by the m rotations of hk; the rotations of one ciphertext
 // share its digit decomposition and ModUp.  out = [n_in][m][2][level][N]
@@ -617,6 +645,10 @@ int hoisted_batch(he_ctx* c, const u64* in, size_t in_stride, int n_in, int leve
                                                                  hk, 0);
     dispatch_logn<LHoistUp>(c->logn, c, (const KsJob*)jobs1, cn, level, dcoef, dhat, s);
     const int total = cn * m;
+    if ((int)rch >= total) {
+      hoisted_rest(c, jobs, total, level, dhat, u, rc, s, m, (size_t)level * (level + 1) * n);
+      continue;
+    }
     for (int r0 = 0; r0 < total; r0 += (int)rch) {
       const int cm = std::min((int)rch, total - r0);
       dispatch_logn<LHoisted>(c->logn, c, (const KsJob*)(jobs + r0), cm, level, (const u64*)dhat, u, rc, s, r0, m,
@@ -907,7 +939,11 @@ int he_ctx_create(const he_params* p, he_ctx** out) {
                   hipMemcpy(c->d_inv, inv.data(), inv.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
                   hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess &&
                   hipEventCreateWithFlags(&c->fork_ev, hipEventDisableTiming) == hipSuccess &&
-                  hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) == hipSuccess;
+                  hipEventCreateWithFlags(&c->join_ev, hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&c->pipe_ev[0], hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&c->pipe_ev[1], hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&c->pipe_ev[2], hipEventDisableTiming) == hipSuccess &&
+                  hipEventCreateWithFlags(&c->pipe_ev[3], hipEventDisableTiming) == hipSuccess;
   if (!ok || scratch_setup(c) != HE_OK) {
     he_ctx_destroy(c);
     return HE_EDEVICE;
@@ -931,6 +967,8 @@ int he_ctx_destroy(he_ctx* c) {
   (void)hipFree(c->d_inv);
   if (c->ws_owned) (void)hipFree(c->ws);
   if (c->side) (void)hipStreamDestroy(c->side);
+  for (hipEvent_t e : c->pipe_ev)
+    if (e) (void)hipEventDestroy(e);
   if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
   if (c->join_ev) (void)hipEventDestroy(c->join_ev);
   for (auto& st : c->stage) {
@@ -994,6 +1032,11 @@ int he_ctx_set_tuning(he_ctx* c, const char* knob, int level, int value) {
     c->split_streams = value;
     return HE_OK;
   }
+  if (std::strcmp(knob, "hoist_pipeline") == 0) {
+    if (value < 0 || value > 1) return fail(c, HE_EINVAL, "he_ctx_set_tuning: hoist_pipeline is 0 or 1");
+    c->hoist_pipeline = value;
+    return HE_OK;
+  }
   if (std::strcmp(knob, "hoist_fused") == 0) {
     if (value < 0 || value > 1) return fail(c, HE_EINVAL, "he_ctx_set_tuning: hoist_fused is 0 or 1");
     c->hoist_fused = value;
@@ -1018,6 +1061,7 @@ int he_ctx_get_tuning(const he_ctx* c, const char* knob, int level) {
   if (!c || !knob) return HE_EINVAL;
   if (std::strcmp(knob, "split_streams") == 0) return c->split_streams;
   if (std::strcmp(knob, "hoist_fused") == 0) return c->hoist_fused;
+  if (std::strcmp(knob, "hoist_pipeline") == 0) return c->hoist_pipeline;
   if (std::strcmp(knob, "modup_halves") == 0) {
     const int lv = level ? level : c->big_l;
     if (lv < 1 || lv > c->big_l) return HE_EINVAL;
@@ -1487,6 +1531,10 @@ int he_rotate_hoisted(he_ctx* c, const uint64_t* d_in, int level, const int32_t*
   if (!e) e = upload(c, d_jobs, jobs.data(), (size_t)m * sizeof(KsJob), s);
   if (e) return e;
   dispatch_logn<LHoistUp>(c->logn, c, (const KsJob*)job1, 1, level, dcoef, dhat, s);
+  if (!fused && chunk == m) {
+    hoisted_rest(c, d_jobs, m, level, dhat, u, rc, s, 1 << 30, 0);
+    return check_launch(c, "he_rotate_hoisted");
+  }
   for (int r0 = 0; r0 < m; r0 += chunk) {
     const int cm = std::min(chunk, m - r0);
     dispatch_logn<LHoisted>(c->logn, c, (const KsJob*)(d_jobs + r0), cm, level, (const u64*)dhat, u, rc, s);

@@ -48,6 +48,7 @@ struct he_ctx {
   int pg_set[HE_MAXM + 1] = {};  // P groups per key-switch level (0 = cost model)
   int split_streams = 1;         // DensePack rotate-and-sum in two halves on two streams
   int hoist_fused = 0;           // hoisted rotations: ModDown fused with the inner product (measured slower)
+  int hoist_pipeline = 1;        // hoisted rotations: inner products and ModDown of chunks on two streams
   // ModUp as two half-ring workgroups per target, per key-switch level
   // (-1: by ring size)
   int halves_set[HE_MAXM + 1] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
@@ -66,6 +67,7 @@ struct he_ctx {
   // second stream (default priority) for the other width classes of a launch
   hipStream_t side = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  hipEvent_t pipe_ev[4] = {};  // one per chunk of a hoisted-rotation pipeline
   StageSlot stage[STAGE_SLOTS];
   int stage_next = 0;
   // graph capture: set between he_graph_begin and he_graph_end; epoch counts
@@ -243,8 +245,9 @@ struct LHoistUp {
 };
 template <int LOGN>
 struct LHoisted {
+  // part: 0 all, 1 the inner products only, 2 the P INTT and ModDown only
   static void run(he_ctx* c, const KsJob* jobs, int m, int level, const u64* dhat, u64* u, u64* rc, hipStream_t s,
-                  int job_base = 0, int per_ct = 1 << 30, size_t dstride = 0);
+                  int job_base = 0, int per_ct = 1 << 30, size_t dstride = 0, int part = 0);
 };
 struct TapMap;
 template <int LOGN>

@@ -209,7 +209,7 @@ void LHoistUp<LOGN>::run(he_ctx* c, const KsJob* jobs1, int count, int level, u6
 // serves one ciphertext.
 template <int LOGN>
 void LHoisted<LOGN>::run(he_ctx* c, const KsJob* jobs, int m, int level, const u64* dhat, u64* u, u64* rc, hipStream_t s,
-                         int job_base, int per_ct, size_t dstride) {
+                         int job_base, int per_ct, size_t dstride, int part) {
   constexpr int T = NttGeom<LOGN>::T;
   constexpr int N = 1 << LOGN;
   if (u == nullptr) {
@@ -225,11 +225,12 @@ void LHoisted<LOGN>::run(he_ctx* c, const KsJob* jobs, int m, int level, const u
                                   dhat, jobs, m, level, c->big_l, rc, c->d_inv, c->mods, c->tb())));
     return;
   }
-  {
+  if (part != 2) {
     Prof pr(c, "ip_perm", s);
     k_ip_perm<LOGN><<<dim3(N / 256, level + 1, m), 256, 0, s>>>(dhat, jobs, u, level, c->big_l, c->mods, job_base,
                                                                  per_ct, dstride);
   }
+  if (part == 1) return;
   {  // u rows per polynomial: level + 1, P at row level (one P group)
     Prof pr(c, "intt_last", s);
     HE_FOR_CLASSES(1u << c->p_cls, (k_intt_last<LOGN, MODE_P, CLS><<<xcd_grid(2, m), T, 0, s>>>(

@@ -18,6 +18,9 @@ tests make them):
 * ``cifar_n16384``: the CIFAR-shaped FFConv W1 (3x3 pad 1, 3->8 under
   DensePack) at N = 16384, 6 x 40-bit + 60-bit P: per-output digests of 72
   sampled dot products, one per (output channel, border class) pair.
+* ``tap``: the tap-style FFConv layers of bench.py's section (MNIST-shaped
+  at N = 8192 with x^2; the CIFAR-shaped net's two stages at N = 16384):
+  digests of the W1 output and of the layer output.
 
 A digest is the SHA-256 of the little-endian uint64 residues of the
 ciphertext array [count][2][level][N] in C order.  Each DensePack output is
@@ -167,10 +170,49 @@ def config3(pool_size: int) -> dict:
     return {"w1_sample": sample, "w1_sample_sha256": digests}
 
 
+# ---- tap-style DensePack FFConv at the bench's shapes ------------------------------
+# (workload, ring, image shape, d, stride, pad, level, r, o_c, square)
+TAP_CASES = {
+    "tap_mnist": ("ffconv_n8192", (28, 28, 1), 5, 2, 0, 4, 2, 5, True),
+    "tap_cifar1": ("cifar_n16384", (32, 32, 3), 3, 1, 1, 6, 8, 64, False),
+    "tap_cifar2": ("cifar_n16384", (32, 32, 64), 3, 1, 1, 3, 8, 64, False),
+}
+
+
+def tap_case(name: str) -> dict:
+    """The tap-style FFConv of bench.py's section for one workload: input
+    image synth.image(name, shape), DensePack input ciphertext m encrypted
+    with draw index m, W1 = synth.weights(name, 1, (d, d, c, r), 0.05),
+    W2 = synth.weights(name, 2, (r, o_c), 0.05), W1 plaintexts at
+    q_{level-1} (target = input scale), mask E at the gather scale for the
+    (pre-square) target, 12-bit W2 integers.  Digests of the W1 output
+    (r ciphertexts after the rescale) and of the layer output."""
+    ring, shape, d, stride, pad, level, r, o_c, square = TAP_CASES[name]
+    p = P.ffconv_n8192() if ring == "ffconv_n8192" else P.cifar_n16384()
+    geom = C.ConvGeom(*shape, d, stride, pad)
+    octx = Wk.make_context(p, name, rotations=C.tap_rotation_steps(geom, p.slots), relin=square)
+    x = synth.image(name, shape)
+    xs = S.Ciphertext(np.stack([Wk.encrypt_slots(octx, v, level, p.scale, name, m).c
+                                for m, v in enumerate(C.densepack_slots(x, geom, p.slots))]), p.scale)
+    w1 = synth.weights(name, 1, (d, d, shape[2], r), 0.05)
+    w2 = synth.weights(name, 2, (r, o_c), 0.05)
+    w1_scale = p.q[level - 1] * p.scale / p.scale
+    filt = C.tap_filters(p, w1, geom, level, w1_scale)
+    y, _ = C.tap_conv(p, octx, xs, geom, filt, w1_scale)
+    t2 = C.pre_square_target(p, level - 2, p.scale) if square else p.scale
+    ms = C.gather_mask_scale(p, level - 1, y.scale, t2, 12)
+    mask = C.encode(C.tap_output_mask_slots(geom, p.slots), p, level - 1, ms)
+    z, _ = C.gather_convpack(p, y, 1, w2, 12, mask, ms)
+    if square:
+        z, _ = C.square_rescale(p, octx, z)
+    return {"w1_tap": {"shape": list(y.c.shape), "scale": y.scale, "sha256": digest(y.c)},
+            "ffconv_tap": {"shape": list(z.c.shape), "scale": z.scale, "sha256": digest(z.c)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("-j", type=int, default=min(8, os.cpu_count() or 1))
-    ap.add_argument("--only", choices=["ffconv_n8192", "cifar_n16384"], default=None)
+    ap.add_argument("--only", choices=["ffconv_n8192", "cifar_n16384", "tap"], default=None)
     a = ap.parse_args()
     os.environ.setdefault("OMP_NUM_THREADS", "1")
     res = json.load(open(OUT)) if os.path.exists(OUT) else {}
@@ -181,6 +223,11 @@ def main():
     if a.only in (None, "cifar_n16384"):
         res["cifar_n16384"] = config3(a.j)
         print("cifar_n16384 done", flush=True)
+    if a.only in (None, "tap"):
+        with mp.get_context("fork").Pool(min(a.j, len(TAP_CASES))) as pool:
+            got = pool.map(tap_case, list(TAP_CASES))
+        res["tap"] = dict(zip(TAP_CASES, got))
+        print("tap done", flush=True)
     with open(OUT, "w") as f:
         json.dump(res, f, indent=1)
 

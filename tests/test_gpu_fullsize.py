@@ -241,3 +241,71 @@ def test_hoisted_256_rotations_n16384():
     for r in (3, 200):
         v = cl.decrypt(outs.data[r], outs.scale, 64, limbs=1)
         assert np.abs(v - np.roll(z, -amounts[r])[:64]).max() < 1e-4
+
+
+# tap-style FFConv at the bench's shapes: (ring, image shape, d, stride, pad, level, r, o_c, square)
+TAP_CASES = {
+    "tap_mnist": ("ffconv_n8192", (28, 28, 1), 5, 2, 0, 4, 2, 5, True),
+    "tap_cifar1": ("cifar_n16384", (32, 32, 3), 3, 1, 1, 6, 8, 64, False),
+    "tap_cifar2": ("cifar_n16384", (32, 32, 64), 3, 1, 1, 3, 8, 64, False),
+}
+
+
+@pytest.mark.parametrize("name", list(TAP_CASES))
+def test_tap_ffconv_fullsize_digests(name):
+    """The tap-style FFConv layers of bench.py's section at their full sizes
+    (N = 8192 with x^2; N = 16384 stage 1 at level 6 and stage 2 over 8 input
+    ciphertexts at level 3), on the oracle's ciphertexts and plaintexts: the
+    W1 output and the layer output equal the oracle's bit for bit (digests
+    written by make_fullsize_digests.py from the oracle alone), and the
+    output decrypts to the FP64 layer within 1e-3."""
+    he = _he()
+    from paper_2102_03494_amd import layers as Ly
+    from paper_2102_03494_amd.client import Client
+    ring, shape, d, stride, pad, level, r, o_c, square = TAP_CASES[name]
+    gold = _golden("tap")[name]
+    p = P.ffconv_n8192() if ring == "ffconv_n8192" else P.cifar_n16384()
+    geom = C.ConvGeom(*shape, d, stride, pad)
+    g = Ly.Geometry(*shape, d, stride, pad)
+    octx = Wk.make_context(p, name)  # the secret and encryption draws only
+    x = synth.image(name, shape)
+    cts = np.stack([Wk.encrypt_slots(octx, v, level, p.scale, name, m).c
+                    for m, v in enumerate(C.densepack_slots(x, geom, p.slots))])
+    gctx = he.HEContext(p.n, p.q_bits, p.p_bits)
+    cl = Client(gctx, name)
+    cl.gen_rotation_keys(Ly.tap_rotation_steps(g, p.slots))
+    if square:
+        cl.gen_relin_key()
+    w1 = synth.weights(name, 1, (d, d, shape[2], r), 0.05)
+    w2 = synth.weights(name, 2, (r, o_c), 0.05)
+    enc = Ly.PlainEncoder(gctx)
+    w1_scale = p.q[level - 1] * p.scale / p.scale
+    # the oracle's plaintexts drive the layer; the library's own encoder
+    # (a different FP64 FFT) may round a coefficient of a tap plaintext the
+    # other way (measured on the CPU: one coefficient, by 1, in one of the
+    # 576 plaintexts of the second CIFAR-shaped stage), within its error
+    # bound; at most two plaintexts may differ
+    want_f = C.tap_filters(p, w1, geom, level, w1_scale)
+    mine = he.to_host(Ly.encode_tap_filters(enc, w1, g, level, w1_scale))
+    differ = (mine != want_f).any(axis=(-2, -1))  # plaintexts whose NTT residues differ
+    assert differ.sum() <= 2, int(differ.sum())
+    filt = he.to_device(want_f)
+    del mine
+    t2 = C.pre_square_target(p, level - 2, p.scale) if square else p.scale
+    ms = C.gather_mask_scale(p, level - 1, p.scale, t2, 12)
+    mask = he.to_device(C.encode(C.tap_output_mask_slots(geom, p.slots), p, level - 1, ms))
+    desc = gctx.conv_desc(*shape, d, stride, pad, r, 0)
+    gctx.reserve(gctx.tap_workspace_need(1, level, desc, o_c, square))
+    xs = he.to_device(cts[None])
+    y = gctx.conv_tap(xs, p.scale, desc, filt, w1_scale)
+    assert list(y.data.shape[1:]) == gold["w1_tap"]["shape"] and y.scale == gold["w1_tap"]["scale"]
+    assert _digest(y.data[0]) == gold["w1_tap"]["sha256"]
+    z = gctx.ffconv_layer_tap(xs, p.scale, desc, filt, w1_scale, mask, ms, w2, 12, square=square)
+    assert list(z.data.shape[1:]) == gold["ffconv_tap"]["shape"]
+    assert abs(z.scale / gold["ffconv_tap"]["scale"] - 1) < 1e-15
+    assert _digest(z.data[0]) == gold["ffconv_tap"]["sha256"]
+    ref = R.ffconv_reference(x, w1, w2, stride, pad, square=square)
+    where = C.tap_output_slots(geom)
+    for o in range(o_c):
+        v = cl.decrypt(z.data[0, o], z.scale)
+        assert np.abs(v[where] - ref[:, :, o].reshape(-1)).max() < 1e-3, o

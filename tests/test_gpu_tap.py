@@ -236,3 +236,19 @@ def test_him2col_bit_exact(shape, d, stride, pad):
     for k in (0, cols.shape[1] // 2, cols.shape[1] - 1):
         v = cl.decrypt(got.data[1, k], got.scale)
         assert np.abs(v[where] - cols[:, k]).max() < 1e-3, k
+
+
+@pytest.mark.parametrize("pipeline", [1, 0])
+def test_rotate_hoisted_batch_pipeline_bit_exact(pipeline):
+    """64 hoisted rotations (8 ciphertexts x 8 steps): with hoist_pipeline
+    the inner products of one chunk and the ModDown of the previous one run
+    on two streams; either way every rotation equals the oracle's."""
+    steps = [1, 2, 3, -4, 9, 33, -100, 200]
+    p, octx, gctx, cl = _small_setup(rotations=steps)
+    gctx.set_tuning("hoist_pipeline", 0, pipeline)
+    assert gctx.get_tuning("hoist_pipeline", 0) == pipeline
+    cts = _enc_batch(octx, p, 8, level=3, index0=30)
+    got = _host(gctx.rotate_hoisted_batch(_dev(cts), steps))
+    for i in range(8):
+        for r, k in enumerate(steps):
+            assert np.array_equal(got[i, r], S.rotate(p, octx, S.Ciphertext(cts[i], p.scale), k).c), (i, k)
