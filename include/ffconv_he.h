@@ -125,7 +125,7 @@ const char *he_last_error(const he_ctx *ctx);
  * per target.  knob "hoist_fused" (level ignored; 0 by default, 0 or 1): in
  * he_rotate_hoisted, compute each rotation's inner-product rows inside its
  * ModDown (1) or write them to the workspace first (0).  knob
- * "hoist_pipeline" (level ignored; 1 by default, 0 or 1): hoisted rotations
+ * "hoist_pipeline" (level ignored; 0 by default, 0 or 1): hoisted rotations
  * (he_rotate_hoisted(_batch) and the layers built on them) with 64 or more
  * rotations whose temporaries all fit run as up to four chunks, the inner
  * products of one chunk on the call's stream while the previous chunk's

@@ -48,7 +48,7 @@ struct he_ctx {
   int pg_set[HE_MAXM + 1] = {};  // P groups per key-switch level (0 = cost model)
   int split_streams = 1;         // DensePack rotate-and-sum in two halves on two streams
   int hoist_fused = 0;           // hoisted rotations: ModDown fused with the inner product (measured slower)
-  int hoist_pipeline = 1;        // hoisted rotations: inner products and ModDown of chunks on two streams
+  int hoist_pipeline = 0;        // hoisted rotations: inner products and ModDown of chunks on two streams (slower)
   // ModUp as two half-ring workgroups per target, per key-switch level
   // (-1: by ring size)
   int halves_set[HE_MAXM + 1] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};

@@ -241,8 +241,9 @@ def test_him2col_bit_exact(shape, d, stride, pad):
 @pytest.mark.parametrize("pipeline", [1, 0])
 def test_rotate_hoisted_batch_pipeline_bit_exact(pipeline):
     """64 hoisted rotations (8 ciphertexts x 8 steps): with hoist_pipeline
-    the inner products of one chunk and the ModDown of the previous one run
-    on two streams; either way every rotation equals the oracle's."""
+    (off by default) the inner products of one chunk and the ModDown of the
+    previous one run on two streams; either way every rotation equals the
+    oracle's."""
     steps = [1, 2, 3, -4, 9, 33, -100, 200]
     p, octx, gctx, cl = _small_setup(rotations=steps)
     gctx.set_tuning("hoist_pipeline", 0, pipeline)
