@@ -37,8 +37,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import scheme
-from .encoding import encode, round_half_away
+from . import modq, scheme
+from .encoding import encode, encode_int, round_half_away, to_rns_ntt
 from .ring import automorph_ntt, galois_for_rotation
 
 
@@ -510,6 +510,83 @@ def tap_conv(params, keys, xs: scheme.Ciphertext, geom: ConvGeom, filters: np.nd
             t_o = scheme.add(params, t_o if kind == "double" else first, r)
             counts.rot += 1
             counts.addcc += 1
+        outs.append(t_o.c)
+    z = scheme.rescale(params, scheme.Ciphertext(np.stack(outs), xs.scale * pt_scale))
+    counts.rescale += o_c
+    return z, counts
+
+
+def tap_filters_p(params, weights: np.ndarray, geom: ConvGeom, pt_scale: float) -> np.ndarray:
+    """The tap plaintexts' residues modulo the special prime P, NTT domain:
+    (O, M, d^2, N), for tap_conv_lazy."""
+    slots = params.slots
+    o_c = weights.shape[3]
+    m_cts = geom.n_cts(slots)
+    out = np.empty((o_c, m_cts, geom.d * geom.d, params.n), dtype=np.uint64)
+    for o in range(o_c):
+        for m in range(m_cts):
+            for t in range(geom.d * geom.d):
+                z = tap_filter_slots(weights, geom, slots, o, m, t)
+                out[o, m, t] = to_rns_ntt(encode_int(z, params.n, pt_scale), [params.p], params.psi)[0]
+    return out
+
+
+def tap_conv_lazy(params, keys, xs: scheme.Ciphertext, geom: ConvGeom, filters: np.ndarray, filters_p: np.ndarray,
+                  pt_scale: float, counts: Counts | None = None) -> tuple[scheme.Ciphertext, Counts]:
+    """tap_conv with the ModDown of the hoisted rotations deferred past the
+    plaintext products: one ModDown per output instead of one per rotation.
+    A rotation by g is (sigma_g(c0) + ModDown(u_0), ModDown(u_1)) with
+    u = the key inner product over (Q, P); since ModDown(P a + b) =
+    a + ModDown(b) exactly, the products and sums run over (Q, P) on
+    U_o = sum_m [ sum_{t: shift != 0} F[o][m][t] * (u_{m,t} + (P sigma_t(c0_m), 0))
+                  + F[o][m][t0] * P x_m ]
+    (F's residues mod P from filters_p, the P terms on the Q limbs only),
+    and t_o = ModDown(U_o).  The block sum and the rescale follow as in
+    tap_conv.  Different rounding from tap_conv (one ModDown instead of one
+    per rotation), same value within noise."""
+    counts = counts if counts is not None else Counts()
+    slots = params.slots
+    level = xs.level
+    n = params.n
+    shifts = [s % slots for s in tap_shifts(geom)]
+    o_c = filters.shape[0]
+    u_acc = np.zeros((o_c, 2, level + 1, n), dtype=np.uint64)
+    moduli = params.q[:level] + [params.p]
+    p_mod = [np.uint64(params.p % q) for q in params.q[:level]]
+    for m in range(xs.c.shape[0]):
+        c = xs.c[m]
+        lifted = scheme.lift_digits(params, scheme.decompose(params, c[1]))
+        for t, s in enumerate(shifts):
+            if s == 0:
+                term = np.zeros((2, level + 1, n), dtype=np.uint64)
+                for i in range(level):
+                    term[:, i] = modq.mul(c[:, i], p_mod[i], params.q[i])
+            else:
+                g = galois_for_rotation(s, n)
+                moved = [[automorph_ntt(v, g) for v in row] for row in lifted]
+                term = scheme.inner_product(params, moved, keys.rot_keys[g])
+                c0 = automorph_ntt(c[0], g)
+                for i in range(level):
+                    term[0, i] = modq.add(term[0, i], modq.mul(c0[i], p_mod[i], params.q[i]), params.q[i])
+                counts.rot += 1
+            for o in range(o_c):
+                for i, q in enumerate(moduli):
+                    f = filters[o, m, t, i] if i < level else filters_p[o, m, t]
+                    u_acc[o, :, i] = modq.add(u_acc[o, :, i], modq.mul(term[:, i], f, q), q)
+                counts.mulpc += 1
+    t_all = scheme.mod_down(params, u_acc)
+    counts.extra["moddown"] = counts.extra.get("moddown", 0) + o_c
+    blocks = geom.channels_per_ct(slots)
+    outs = []
+    for o in range(o_c):
+        t_o = scheme.Ciphertext(t_all[o], xs.scale * pt_scale)
+        first = t_o
+        for kind, amount in tap_block_schedule(blocks, geom.h * geom.w):
+            r = scheme.rotate(params, keys, t_o, amount)
+            t_o = scheme.add(params, t_o if kind == "double" else first, r)
+            counts.rot += 1
+            counts.addcc += 1
+        counts.addcc += xs.c.shape[0] * geom.d * geom.d - 1
         outs.append(t_o.c)
     z = scheme.rescale(params, scheme.Ciphertext(np.stack(outs), xs.scale * pt_scale))
     counts.rescale += o_c

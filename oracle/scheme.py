@@ -196,8 +196,8 @@ def lift_digits(params, digits) -> list[list[np.ndarray]]:
     return [[ntt(modq.from_signed(dj, m), m, params.psi[m]) for m in moduli] for dj in digits]
 
 
-def inner_product_moddown(params, lifted, key: SwitchKey):
-    """(u0, u1) = ModDown(sum_j lifted_j * (b_j, a_j)), each (..., level, N)."""
+def inner_product(params, lifted, key: SwitchKey) -> np.ndarray:
+    """u = sum_j lifted_j * (b_j, a_j) over (q_0..q_{l-1}, P): (..., 2, level + 1, N)."""
     level = len(lifted)
     moduli = params.q[:level] + [params.p]
     key_index = list(range(level)) + [params.max_level]
@@ -208,7 +208,18 @@ def inner_product_moddown(params, lifted, key: SwitchKey):
             kt = key_index[t]
             u[..., 0, t, :] = modq.add(u[..., 0, t, :], modq.mul(lifted[j][t], key.b[j, kt], m), m)
             u[..., 1, t, :] = modq.add(u[..., 1, t, :], modq.mul(lifted[j][t], key.a[j, kt], m), m)
-    out = _drop_last_limb(params, u, params.p, level)
+    return u
+
+
+def mod_down(params, u: np.ndarray) -> np.ndarray:
+    """ModDown: (..., level + 1, N) over (q_0..q_{l-1}, P) to
+    round(u / P) over (q_0..q_{l-1})."""
+    return _drop_last_limb(params, u, params.p, u.shape[-2] - 1)
+
+
+def inner_product_moddown(params, lifted, key: SwitchKey):
+    """(u0, u1) = ModDown(sum_j lifted_j * (b_j, a_j)), each (..., level, N)."""
+    out = mod_down(params, inner_product(params, lifted, key))
     return out[..., 0, :, :], out[..., 1, :, :]
 
 

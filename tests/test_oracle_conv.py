@@ -476,3 +476,68 @@ def test_him2col_columns_and_counts(shape, d, stride, pad):
     for o in range(2):
         got = ctx.decrypt(S.Ciphertext(z.c[o], z.scale))
         assert np.abs(got[where] - ref[:, :, o].reshape(-1)).max() < 1e-3
+
+
+def test_moddown_absorbs_multiples_of_p():
+    """ModDown(P a + b) = a + ModDown(b) exactly (the identity that lets the
+    lazy tap conv fold the rotations' c0 terms into one ModDown)."""
+    from oracle import modq
+    p = P.Params(512, (30, 30, 30), 36, 2.0**25)
+    rng = np.random.default_rng(5)
+    level = 3
+    moduli = p.q[:level] + [p.p]
+    a = np.stack([rng.integers(0, q, p.n, dtype=np.uint64) for q in p.q[:level]])
+    b = np.stack([rng.integers(0, q, p.n, dtype=np.uint64) for q in moduli])
+    pa_b = b.copy()
+    for i, q in enumerate(p.q[:level]):
+        pa_b[i] = modq.add(modq.mul(a[i], np.uint64(p.p % q), q), b[i], q)
+    lhs = S.mod_down(p, pa_b)
+    rhs = S.mod_down(p, b)
+    for i, q in enumerate(p.q[:level]):
+        rhs[i] = modq.add(rhs[i], a[i], q)
+    assert np.array_equal(lhs, rhs)
+
+
+def test_tap_conv_lazy_single_unit_tap_is_a_rotation():
+    """With the constant plaintext 1 on one tap and 0 on the others, the
+    lazy tap conv's output is rescale(Rot(x, shift)) bit for bit: the one
+    ModDown after the products equals the rotation's own."""
+    p = P.Params(512, (30, 30, 30), 36, 2.0**25)
+    geom = C.ConvGeom(6, 6, 1, 3, 1, 1)
+    ctx = Wk.make_context(p, W, rotations=C.tap_rotation_steps(geom, p.slots))
+    x = Wk.encrypt_slots(ctx, synth.message(W, p.slots), 3, p.scale, W, 5)
+    shifts = C.tap_shifts(geom)
+    for t in (0, 5, 8):
+        filt = np.zeros((1, 1, 9, 3, p.n), dtype=np.uint64)
+        filt_p = np.zeros((1, 1, 9, p.n), dtype=np.uint64)
+        filt[0, 0, t] = 1
+        filt_p[0, 0, t] = 1
+        z, cnt = C.tap_conv_lazy(p, ctx, S.Ciphertext(x.c[None], x.scale), geom, filt, filt_p, 1.0)
+        want = S.rescale(p, S.rotate(p, ctx, x, shifts[t] % p.slots))
+        assert np.array_equal(z.c[0], want.c), t
+        assert cnt.rot == 8 and cnt.extra["moddown"] == 1
+
+
+@pytest.mark.parametrize("shape,d,stride,pad", TAP_GEOMS[:4])
+def test_tap_conv_lazy_matches_fp64(shape, d, stride, pad):
+    """The lazy tap conv decrypts to Eq. 1's conv within 1e-3 and to the
+    per-rotation tap conv within 1e-4, with the same rotation and MulPC
+    counts and one ModDown per output."""
+    o_c = 3
+    p, geom, ctx, x, xs = _tap_setup(shape, d, stride, pad)
+    w = synth.weights(W, 81, (d, d, shape[2], o_c), 0.2)
+    pt_scale = p.q[2] * p.scale / xs.scale
+    filt = C.tap_filters(p, w, geom, 3, pt_scale)
+    filt_p = C.tap_filters_p(p, w, geom, pt_scale)
+    z, cnt = C.tap_conv_lazy(p, ctx, xs, geom, filt, filt_p, pt_scale)
+    z1, cnt1 = C.tap_conv(p, ctx, xs, geom, filt, pt_scale)
+    assert z.level == 2 and z.scale == z1.scale
+    assert (cnt.rot, cnt.mulpc, cnt.rescale) == (cnt1.rot, cnt1.mulpc, cnt1.rescale)
+    assert cnt.extra["moddown"] == o_c
+    ref = R.conv2d(x, w, stride, pad)
+    where = C.tap_output_slots(geom)
+    for o in range(o_c):
+        got = ctx.decrypt(S.Ciphertext(z.c[o], z.scale))
+        per_rot = ctx.decrypt(S.Ciphertext(z1.c[o], z1.scale))
+        assert np.abs(got[where] - ref[:, :, o].reshape(-1)).max() < 1e-3
+        assert np.abs(got[where] - per_rot[where]).max() < 1e-4
