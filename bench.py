@@ -843,7 +843,7 @@ def tap_case(torch, name, ring, shape, d, stride, pad, level, r, o_c, square, ba
     enc = Ly.PlainEncoder(ctx)
     w1_scale = Ly.pt_scale_for(ctx, level, scale, scale)
     t0 = time.perf_counter()
-    f1 = Ly.encode_tap_filters(enc, w1, g, level, w1_scale)
+    f1, f1p = Ly.encode_tap_filters(enc, w1, g, level, w1_scale, with_p=True)
     t_enc = time.perf_counter() - t0
     t2 = Ly.pre_square_target(ctx, level - 2, scale) if square else scale
     ms = Ly.mask_scale_for(ctx, level - 1, scale, t2, K_BITS)
@@ -852,32 +852,45 @@ def tap_case(torch, name, ring, shape, d, stride, pad, level, r, o_c, square, ba
     ctx.reserve(ctx.tap_workspace_need(batch, level, desc, o_c, square))
     where = Ly.tap_output_slots(g)
 
-    def ff():
-        return ctx.ffconv_layer_tap(cts, scale, desc, f1, w1_scale, mask, ms, w2, K_BITS, square=square)
+    def ff(lazy=False):
+        return ctx.ffconv_layer_tap(cts, scale, desc, f1, w1_scale, mask, ms, w2, K_BITS, square=square,
+                                    w1_p=f1p if lazy else None)
+
+    def kernel_ms(fn):
+        busy = {}
+        for k in TAP_KERNELS:
+            ctx.prof_select(k)
+            fn()
+            b_ms, _, launches = ctx.prof_read_busy()
+            if launches:
+                busy[k] = round(b_ms, 4)
+        ctx.prof_select(None)
+        return busy
 
     t_ff, z = timed(ff, reps, 1, torch)
     counts_ff = ctx.last_counts()
-    busy = {}
-    for k in TAP_KERNELS:
-        ctx.prof_select(k)
-        ff()
-        b_ms, _, launches = ctx.prof_read_busy()
-        if launches:
-            busy[k] = round(b_ms, 4)
-    ctx.prof_select(None)
-    err = 0.0
+    busy = kernel_ms(ff)
+    # one ModDown per W1 output instead of one per hoisted rotation
+    t_lazy, zl = timed(lambda: ff(True), reps, 1, torch)
+    busy_lazy = kernel_ms(lambda: ff(True))
+    err = err_l = 0.0
     for b in range(batch if batch <= 2 else 2):
         ref = Ly.reference_conv2d(xs[b], w1, stride, pad) @ w2
         ref = ref * ref if square else ref
         for o in range(o_c):
             v = cl.decrypt(z.data[b, o], z.scale)
             err = max(err, float(np.abs(v[where] - ref[:, :, o].ravel()).max()))
+            v = cl.decrypt(zl.data[b, o], zl.scale)
+            err_l = max(err_l, float(np.abs(v[where] - ref[:, :, o].ravel()).max()))
     out = {"batch": batch, "ffconv_ms": t_ff * 1e3, "ffconv_ms_per_input": t_ff * 1e3 / batch,
            "ffconv_counts_per_input": {k: v // batch for k, v in counts_ff.items()},
            "ffconv_rotations_per_s": counts_ff["rot"] / t_ff, "ffconv_decrypted_max_abs_err": err,
            "ffconv_kernel_ms": busy, "w1_plaintexts": int(f1.shape[0] * f1.shape[1] * f1.shape[2]),
-           "w1_encode_s": t_enc}
-    del f1
+           "w1_encode_s": t_enc,
+           "ffconv_moddown_per_output_ms": t_lazy * 1e3, "ffconv_moddown_per_output_ms_per_input": t_lazy * 1e3 / batch,
+           "ffconv_moddown_per_output_kernel_ms": busy_lazy,
+           "ffconv_moddown_per_output_decrypted_max_abs_err": err_l}
+    del f1, f1p
     if plain:
         wp = Ly.compose_factors(w1, w2)
         tp = Ly.pre_square_target(ctx, level - 1, scale) if square else scale
@@ -907,7 +920,7 @@ def tap_case(torch, name, ring, shape, d, stride, pad, level, r, o_c, square, ba
         out.update(plain_ms=t_pl * 1e3, plain_ms_per_input=t_pl * 1e3 / batch, plain_decrypted_max_abs_err=err_p,
                    plain_plaintexts=int(fp.shape[0] * fp.shape[1] * fp.shape[2]), plain_encode_s=t_enc)
         del fp
-    print(f"# tap {name} b{batch}: ffconv {t_ff * 1e3:.2f} ms" +
+    print(f"# tap {name} b{batch}: ffconv {t_ff * 1e3:.2f} ms (one ModDown per output: {t_lazy * 1e3:.2f} ms)" +
           (f", plain {out['plain_ms']:.2f} ms" if plain else ""), file=sys.stderr, flush=True)
     ctx.close()
     return out

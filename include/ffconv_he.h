@@ -397,8 +397,18 @@ int he_conv_convpack(he_ctx *ctx, const uint64_t *d_in, int k, int level, const 
  *           W[kh][kw][m B + b][o] in block b at the slot (s i) w + s j of
  *           every output (i, j) whose tap (kh, kw) lies inside the image,
  *           zero elsewhere.
+ *   d_filt_p: NULL, or the same plaintexts' residues modulo the special
+ *           prime P ([o_c][M][d^2][N], NTT domain): then the ModDown of the
+ *           hoisted rotations is deferred past the products (double
+ *           hoisting): the key inner products over (Q, P), with
+ *           P sigma_t(c0) added, and P x for the zero shift, are multiplied
+ *           and summed over (Q, P), and each output takes one ModDown
+ *           (exact because ModDown(P a + b) = a + ModDown(b)); with NULL
+ *           every rotation takes its own ModDown first.  The two give
+ *           different rounding, the same value within noise.
  *   1. x_m rotated left by every nonzero tap shift (kh - pad) w + (kw - pad)
- *      (mod N/2), hoisted per input ciphertext (the zero shift is x_m);
+ *      (mod N/2), hoisted per input ciphertext (the zero shift is x_m; see
+ *      d_filt_p for where the ModDown goes);
  *   2. t_o = sum_m sum_t d_filt[o][m][t] * Rot(x_m, shift_t);
  *   3. blocks summed into block 0 by the binary method over the bits of B
  *      below the leading one: "double" S <- S + Rot(S, k h w) (k -> 2k),
@@ -414,7 +424,8 @@ int he_conv_convpack(he_ctx *ctx, const uint64_t *d_in, int k, int level, const 
  *          not finite and positive; HE_EINVAL when pt_limbs < level or a
  *          batch needs more than 65535 outputs.
  * ffconv_layer_tap: FFConv with W1 (desc->o_c = r) as he_conv_tap with
- *          plaintexts d_w1 at w1_scale, then the second half of the FFConv
+ *          plaintexts d_w1 (and d_w1_p, as d_filt_p) at w1_scale, then the
+ *          second half of the FFConv
  *          layer with one ciphertext per channel: G_c = y_c * E (d_mask: E,
  *          one at every output slot, NTT domain, >= level-1 limbs, at
  *          mask_scale; it clears the partial sums), Z_o = sum_c
@@ -429,12 +440,12 @@ int he_conv_convpack(he_ctx *ctx, const uint64_t *d_in, int k, int level, const 
  *          conv alone); 0 for a bad geometry or level. */
 size_t he_tap_workspace_need(he_ctx *ctx, int n_batch, int level, const he_conv_desc *desc, int o_c2, int square);
 int he_conv_tap(he_ctx *ctx, int n_batch, const uint64_t *d_in, int level, const he_conv_desc *desc,
-                const uint64_t *d_filt, int pt_limbs, double in_scale, double pt_scale, uint64_t *d_out,
-                double *out_scale, void *stream);
+                const uint64_t *d_filt, int pt_limbs, const uint64_t *d_filt_p, double in_scale, double pt_scale,
+                uint64_t *d_out, double *out_scale, void *stream);
 int ffconv_layer_tap(he_ctx *ctx, int n_batch, const uint64_t *d_in, int level, const he_conv_desc *desc,
-                     const uint64_t *d_w1, int w1_limbs, double in_scale, double w1_scale, const uint64_t *d_mask,
-                     double mask_scale, const double *h_w2, int o_c2, int k_bits, int square, uint64_t *d_out,
-                     double *out_scale, void *stream);
+                     const uint64_t *d_w1, int w1_limbs, const uint64_t *d_w1_p, double in_scale, double w1_scale,
+                     const uint64_t *d_mask, double mask_scale, const double *h_w2, int o_c2, int k_bits, int square,
+                     uint64_t *d_out, double *out_scale, void *stream);
 
 /* ---- homomorphic Im2Col for d > 1 (Table III, CP-HI2C-CP / CP-HI2C-DP) -----
  * he_him2col: the K = d^2 I_c ConvPack input ciphertexts of Eq. 1 from a

@@ -602,16 +602,21 @@ def tap_output_mask_slots(geom: ConvGeom, slots: int) -> np.ndarray:
 
 def tap_ffconv(params, keys, xs: scheme.Ciphertext, geom: ConvGeom, w1_filters: np.ndarray, w1_scale: float,
                w2: np.ndarray, k_bits: int, mask_pt: np.ndarray, mask_scale: float, square: bool = False,
-               counts: Counts | None = None) -> tuple[scheme.Ciphertext, Counts]:
+               counts: Counts | None = None, w1_filters_p: np.ndarray | None = None
+               ) -> tuple[scheme.Ciphertext, Counts]:
     """FFConv with W1 as a tap-style DensePack conv (tap_conv, r outputs),
     then C12's second half with one ciphertext per channel: G_c = y_c * E
     (E = tap_output_mask_slots at mask_scale; it clears the partial sums
     and leaves the outputs at their slots), Z_o = sum_c round(W2[c][o] 2^k)
     G_c, rescale, and with `square` x^2 relinearised and rescaled.
     Output: O_c ciphertexts, output (i, j) at slot (s i) W + s j, zero
-    elsewhere."""
+    elsewhere.  With w1_filters_p (W1's residues mod P) W1 runs as
+    tap_conv_lazy."""
     counts = counts if counts is not None else Counts()
-    y, _ = tap_conv(params, keys, xs, geom, w1_filters, w1_scale, counts)
+    if w1_filters_p is None:
+        y, _ = tap_conv(params, keys, xs, geom, w1_filters, w1_scale, counts)
+    else:
+        y, _ = tap_conv_lazy(params, keys, xs, geom, w1_filters, w1_filters_p, w1_scale, counts)
     z, _ = gather_convpack(params, y, 1, w2, k_bits, mask_pt, mask_scale, counts)
     if square:
         z, _ = square_rescale(params, keys, z, counts)

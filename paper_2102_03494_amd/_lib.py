@@ -91,8 +91,9 @@ SIGNATURES = {
     "he_him2col_workspace_need": (ctypes.c_size_t, [P, I, I, ctypes.POINTER(HeConvDesc)]),
     "he_him2col": (I, [P, I, P, I, ctypes.POINTER(HeConvDesc), P, I, ctypes.c_double, ctypes.c_double, P, DP, P]),
     "he_tap_workspace_need": (ctypes.c_size_t, [P, I, I, ctypes.POINTER(HeConvDesc), I, I]),
-    "he_conv_tap": (I, [P, I, P, I, ctypes.POINTER(HeConvDesc), P, I, ctypes.c_double, ctypes.c_double, P, DP, P]),
-    "ffconv_layer_tap": (I, [P, I, P, I, ctypes.POINTER(HeConvDesc), P, I, ctypes.c_double, ctypes.c_double, P,
+    "he_conv_tap": (I, [P, I, P, I, ctypes.POINTER(HeConvDesc), P, I, P, ctypes.c_double, ctypes.c_double, P, DP,
+                        P]),
+    "ffconv_layer_tap": (I, [P, I, P, I, ctypes.POINTER(HeConvDesc), P, I, P, ctypes.c_double, ctypes.c_double, P,
                              ctypes.c_double, DP, I, I, I, P, DP, P]),
     "ffconv_layer_batch": (I, [P, I, P, ctypes.c_size_t, I, ctypes.POINTER(HeConvDesc), P, ctypes.c_size_t, P, P,
                                I, I, P, P]),

@@ -658,6 +658,37 @@ int hoisted_batch(he_ctx* c, const u64* in, size_t in_stride, int n_in, int leve
   return check_launch(c, "hoisted rotations");
 }
 
+// Key inner products (over Q and P, with P sigma_g(c0) added to u_0) of n_in
+// ciphertexts' hoisted rotations, no ModDown: u = [n_in][m][2][level + 1][N]
+// in the key-switch row layout (narrow rows packed), all of it the caller's.
+int hoisted_ip(he_ctx* c, const u64* in, size_t in_stride, int n_in, int level, const HoistKeys& hk, int m, u64* u,
+               Arena& ar, hipStream_t s) {
+  const int n = c->n;
+  const size_t per_ct = (size_t)level * n + (size_t)level * (level + 1) * n + 128 + (size_t)m * 8;
+  const size_t cc = std::min<size_t>({(size_t)n_in, (size_t)(32000 / m), ar.left() / 8 / per_ct});
+  if (cc < 1) return fail(c, HE_ENOMEM, "workspace too small for hoisted inner products at level %d", level);
+  Arena sub = ar;
+  KsJob* jobs1 = sub.take<KsJob>(cc);
+  KsJob* jobs = sub.take<KsJob>(cc * m);
+  u64* dcoef = sub.take<u64>(cc * level * n);
+  u64* dhat = sub.take<u64>(cc * level * (level + 1) * n);
+  if (!jobs1 || !jobs || !dcoef || !dhat) return fail(c, HE_ENOMEM, "workspace too small for hoisted inner products");
+  const size_t ustride = (size_t)m * 2 * (level + 1) * n;  // per input ciphertext
+  for (int i0 = 0; i0 < n_in; i0 += (int)cc) {
+    const int cn = std::min((int)cc, n_in - i0);
+    const u64* cin = in + (size_t)i0 * in_stride;
+    u64* ui = u + (size_t)i0 * ustride;
+    k_make_hoist_jobs<<<dim3((cn + 255) / 256, 1), 256, 0, s>>>(jobs1, cn, 1, cin, in_stride, ui, ustride, level, n,
+                                                                 hk, 1);
+    k_make_hoist_jobs<<<dim3((cn + 255) / 256, m), 256, 0, s>>>(jobs, cn, m, cin, in_stride, ui, ustride, level, n,
+                                                                 hk, 0);
+    dispatch_logn<LHoistUp>(c->logn, c, (const KsJob*)jobs1, cn, level, dcoef, dhat, s);
+    dispatch_logn<LHoisted>(c->logn, c, (const KsJob*)jobs, cn * m, level, (const u64*)dhat, ui, (u64*)nullptr, s, 0,
+                            m, (size_t)level * (level + 1) * n, 1, 1);
+  }
+  return check_launch(c, "hoisted inner products");
+}
+
 // ---- Tap-style DensePack ------------------------------------------------------
 // Input in the DensePack layout (channel c of ciphertext m in block
 // b = c - m B at slots b H W + h W + w); each ciphertext is rotated by the
@@ -730,9 +761,12 @@ int tap_plan(he_ctx* c, const char* who, const he_conv_desc* g, TapPlan& tp, boo
 
 size_t tap_need(const he_ctx* c, const TapPlan& tp, int nb, int level) {
   auto al = [](size_t elems) { return ((elems * 8 + 255) & ~(size_t)255); };
-  const size_t n = c->n, cs = 2 * (size_t)level * n;
+  const size_t n = c->n, cs = 2 * (size_t)level * n, us = 2 * (size_t)(level + 1) * n;
   const size_t o = (size_t)nb * tp.map.o_c;
-  size_t need = al((size_t)nb * tp.m_cts * tp.nrot * cs) + al(o * cs) * (tp.has_inc ? 2 : 1);
+  // rotated ciphertexts, or with a deferred ModDown their inner-product rows and the outputs' rows
+  size_t need = std::max(al((size_t)nb * tp.m_cts * tp.nrot * cs),
+                         al((size_t)nb * tp.m_cts * tp.nrot * us) + al(o * us) + al(o * 2 * n) + al(o * 8)) +
+                al(o * cs) * (tp.has_inc ? 2 : 1);
   // one ciphertext's hoisting with all its rotations, and a key-switch chunk of the block sum
   const size_t hoist = ((size_t)level * n + (size_t)level * (level + 1) * n + 128 +
                         (size_t)tp.nrot * (2 * (level + 2) * n + 64)) * 8 + 4096;
@@ -742,22 +776,41 @@ size_t tap_need(const he_ctx* c, const TapPlan& tp, int nb, int level) {
 }
 
 // out = [nb][O][2][level - 1][N] from in = [nb][M][2][level][N]; filt =
-// [O][M][d^2][pt_limbs][N]; adds its counts.
-int tap_run(he_ctx* c, const TapPlan& tp, int nb, const u64* in, int level, const u64* filt, int pt_limbs, u64* out,
-            Arena& ar, hipStream_t s) {
+// [O][M][d^2][pt_limbs][N]; filt_p (or null) the same plaintexts mod P,
+// [O][M][d^2][N]: with it one ModDown per output after the products over
+// (Q, P), else one per rotation before them.  Adds its counts.
+int tap_run(he_ctx* c, const TapPlan& tp, int nb, const u64* in, int level, const u64* filt, int pt_limbs,
+            const u64* filt_p, u64* out, Arena& ar, hipStream_t s) {
   const int n = c->n;
   const int o_c = tp.map.o_c;
   const size_t cs = (size_t)2 * level * n;
   const int n_in = nb * tp.m_cts;
   const int n_out = nb * o_c;
-  u64* rot = tp.nrot ? ar.take<u64>((size_t)n_in * tp.nrot * cs) : nullptr;
+  const bool lazy = filt_p != nullptr && tp.nrot > 0;
+  const size_t us = (size_t)2 * (level + 1) * n;
   u64* t = ar.take<u64>((size_t)n_out * cs);
   u64* t0 = tp.has_inc ? ar.take<u64>((size_t)n_out * cs) : nullptr;
-  if ((tp.nrot && !rot) || !t || (tp.has_inc && !t0)) return fail(c, HE_ENOMEM, "workspace too small for the tap-style layer");
+  if (!t || (tp.has_inc && !t0)) return fail(c, HE_ENOMEM, "workspace too small for the tap-style layer");
   int e = HE_OK;
-  if (tp.nrot && (e = hoisted_batch(c, in, cs, n_in, level, tp.hk, tp.nrot, rot, ar, s))) return e;
-  dispatch_logn<LTapHma>(c->logn, c, in, (const u64*)rot, filt, t, level, pt_limbs, tp.map, nb, s);
-  if ((e = check_launch(c, "tap_hma"))) return e;
+  if (lazy) {
+    Arena la = ar;  // the rows below are free once the ModDown has run
+    u64* uq = la.take<u64>((size_t)n_in * tp.nrot * us);
+    u64* uo = la.take<u64>((size_t)n_out * us);
+    u64* rc = la.take<u64>((size_t)n_out * 2 * n);
+    KsJob* dj = la.take<KsJob>(n_out);
+    if (!uq || !uo || !rc || !dj) return fail(c, HE_ENOMEM, "workspace too small for the tap-style layer");
+    if ((e = hoisted_ip(c, in, cs, n_in, level, tp.hk, tp.nrot, uq, la, s))) return e;
+    dispatch_logn<LTapHmaQp>(c->logn, c, in, (const u64*)uq, filt, filt_p, uo, level, pt_limbs, tp.map, nb, s);
+    make_jobs(c, dj, n_out, t, cs, t, cs, t, cs, tp.hk.key[0], 1u, 1u, level, s);
+    dispatch_logn<LModDown>(c->logn, c, (const KsJob*)dj, n_out, level, (const u64*)uo, rc, s);
+    if ((e = check_launch(c, "tap_hma_qp"))) return e;
+  } else {
+    u64* rot = tp.nrot ? ar.take<u64>((size_t)n_in * tp.nrot * cs) : nullptr;
+    if (tp.nrot && !rot) return fail(c, HE_ENOMEM, "workspace too small for the tap-style layer");
+    if (tp.nrot && (e = hoisted_batch(c, in, cs, n_in, level, tp.hk, tp.nrot, rot, ar, s))) return e;
+    dispatch_logn<LTapHma>(c->logn, c, in, (const u64*)rot, filt, t, level, pt_limbs, tp.map, nb, s);
+    if ((e = check_launch(c, "tap_hma"))) return e;
+  }
   if (tp.has_inc && hipMemcpyAsync(t0, t, (size_t)n_out * cs * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
     return fail(c, HE_EDEVICE, "tap-style layer: device copy failed");
   for (auto& st : tp.sched) {
@@ -1578,8 +1631,8 @@ size_t he_tap_workspace_need(he_ctx* c, int n_batch, int level, const he_conv_de
 }
 
 int he_conv_tap(he_ctx* c, int n_batch, const uint64_t* d_in, int level, const he_conv_desc* desc,
-                const uint64_t* d_filt, int pt_limbs, double in_scale, double pt_scale, uint64_t* d_out,
-                double* out_scale, void* stream) {
+                const uint64_t* d_filt, int pt_limbs, const uint64_t* d_filt_p, double in_scale, double pt_scale,
+                uint64_t* d_out, double* out_scale, void* stream) {
   if (!c || !d_in || !desc || !d_filt || !d_out || !out_scale || n_batch < 1 || pt_limbs < 1)
     return fail(c, HE_EINVAL, "he_conv_tap: bad arguments");
   if (level < 2 || level > c->big_l) return fail(c, HE_ELEVEL, "he_conv_tap needs 2 <= level <= L (got %d)", level);
@@ -1593,13 +1646,14 @@ int he_conv_tap(he_ctx* c, int n_batch, const uint64_t* d_in, int level, const h
     return fail(c, HE_EINVAL, "he_conv_tap: batch too large for one call");
   c->counts = he_counts{};
   Arena ar(c);
-  e = tap_run(c, tp, n_batch, d_in, level, d_filt, pt_limbs, d_out, ar, S(stream));
+  e = tap_run(c, tp, n_batch, d_in, level, d_filt, pt_limbs, d_filt_p, d_out, ar, S(stream));
   if (!e) *out_scale = in_scale * pt_scale / (double)c->moduli[level - 1];
   return e;
 }
 
 int ffconv_layer_tap(he_ctx* c, int n_batch, const uint64_t* d_in, int level, const he_conv_desc* desc,
-                     const uint64_t* d_w1, int w1_limbs, double in_scale, double w1_scale, const uint64_t* d_mask,
+                     const uint64_t* d_w1, int w1_limbs, const uint64_t* d_w1_p, double in_scale, double w1_scale,
+                     const uint64_t* d_mask,
                      double mask_scale, const double* h_w2, int o_c2, int k_bits, int square, uint64_t* d_out,
                      double* out_scale, void* stream) {
   if (!c || !d_in || !desc || !d_w1 || !d_mask || !h_w2 || !d_out || !out_scale || n_batch < 1 || o_c2 < 1 ||
@@ -1633,7 +1687,7 @@ int ffconv_layer_tap(he_ctx* c, int n_batch, const uint64_t* d_in, int level, co
   u64* y = ar.take<u64>((size_t)n_batch * r * 2 * (level - 1) * n);
   if (!d_tab || !y) return fail(c, HE_ENOMEM, "workspace too small for ffconv_layer_tap");
   if ((e = upload(c, d_tab, tab.data(), tab.size() * 8, s))) return e;
-  if ((e = tap_run(c, tp, n_batch, d_in, level, d_w1, w1_limbs, y, ar, s))) return e;
+  if ((e = tap_run(c, tp, n_batch, d_in, level, d_w1, w1_limbs, d_w1_p, y, ar, s))) return e;
   if ((e = ffconv_tail(c, n_batch, y, level - 1, 1, r, d_mask, d_tab, o_c2, square, d_out, ar, s, true))) return e;
   const double y_scale = in_scale * w1_scale / (double)c->moduli[level - 1];
   double z_scale = y_scale * mask_scale * std::ldexp(1.0, k_bits) / (double)c->moduli[level - 2];

@@ -245,11 +245,21 @@ struct LHoistUp {
 };
 template <int LOGN>
 struct LHoisted {
-  // part: 0 all, 1 the inner products only, 2 the P INTT and ModDown only
+  // part: 0 all, 1 the inner products only, 2 the P INTT and ModDown only;
+  // add_c0 (with part 1): the inner products also get P sigma_g(c0)
   static void run(he_ctx* c, const KsJob* jobs, int m, int level, const u64* dhat, u64* u, u64* rc, hipStream_t s,
-                  int job_base = 0, int per_ct = 1 << 30, size_t dstride = 0, int part = 0);
+                  int job_base = 0, int per_ct = 1 << 30, size_t dstride = 0, int part = 0, int add_c0 = 0);
 };
 struct TapMap;
+template <int LOGN>
+struct LModDown {  // P INTT + ModDown (store) of count key-switch row sets u [2][level + 1][N]
+  static void run(he_ctx* c, const KsJob* jobs, int count, int level, const u64* u, u64* rc, hipStream_t s);
+};
+template <int LOGN>
+struct LTapHmaQp {
+  static void run(he_ctx* c, const u64* x, const u64* u, const u64* filt, const u64* fp, u64* out, int level,
+                  int pt_limbs, const TapMap& tm, int n_b, hipStream_t s);
+};
 template <int LOGN>
 struct LTapHma {
   static void run(he_ctx* c, const u64* x, const u64* rot, const u64* filt, u64* out, int level, int pt_limbs,

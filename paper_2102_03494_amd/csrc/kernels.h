@@ -1266,14 +1266,16 @@ k_modup_store(const u64* __restrict__ dcoef, const KsJob* __restrict__ jobs, u64
 
 // Inner product of the shared lifted digits, permuted per rotation, with
 // that rotation's key: u[r][c][t][i] = sum_j dhat[j][t][src_{g_r}(i)] *
-// key_r[j][c][m_t][i], with (key_r, g_r) from jobs[r].  The products are
+// key_r[j][c][m_t][i], with (key_r, g_r) from jobs[r]; with add_c0, row t <
+// level of u_0 also gets P sigma_{g_r}(c0) (c0 from jobs[r].c).  The products are
 // summed at full width (64-bit for narrow primes, 128-bit otherwise) and
 // reduced once.  grid (N / 256, level + 1, m).  Batches of ciphertexts:
 // job r belongs to ciphertext (job_base + r) / per_ct, whose lifted digits
 // start dstride words after the previous one's.
 template <int LOGN>
 __global__ void k_ip_perm(const u64* __restrict__ dhat, const KsJob* __restrict__ jobs, u64* __restrict__ u,
-                          int level, int big_l, Mods mods, int job_base, int per_ct, size_t dstride) {
+                          int level, int big_l, Mods mods, int job_base, int per_ct, size_t dstride,
+                          int add_c0) {
   constexpr int N = 1 << LOGN;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int t = blockIdx.y;
@@ -1304,6 +1306,8 @@ __global__ void k_ip_perm(const u64* __restrict__ dhat, const KsJob* __restrict_
     s0 = reduce128(a0, m);
     s1 = reduce128(a1, m);
   }
+  if (add_c0 && t < level)  // + P sigma_g(c0): the rotation's c0 term, ahead of a deferred ModDown
+    s0 = add_mod(s0, mul_mod(jb.c[(size_t)t * N + src], reduce64(mods.m[big_l].q, m), m), m.q);
   u64* u0 = u + ((r * 2 + 0) * (level + 1) + t) * N;
   u64* u1 = u + ((r * 2 + 1) * (level + 1) + t) * N;
   if (m.narrow) {  // packed rows
@@ -1755,6 +1759,131 @@ k_tap_hma(const u64* __restrict__ x, const u64* __restrict__ rot, const u64* __r
 #pragma unroll
     for (int q = 1; q < TAP_SLICES; ++q) acc = add_mod(acc, part[q][v][l], m.q);
     out[(((b * tm.o_c + o0 + r) * 2 + c) * level + t) * N + blockIdx.x * 64 + l] = acc;
+  }
+}
+
+// Tap-style DensePack MulPC over (Q, P) ahead of one ModDown per output:
+// U[b][o] = sum_{m < M} [ sum_{k: idx[k] >= 0} F[o][m][k] * u[(b M + m) nrot
+// + idx[k]] + F[o][m][k0] * P x[b][m] ], u the hoisted key inner products
+// with P sigma(c0) already in (k_ip_perm with add_c0), P x on the Q limbs
+// only.  Limb t < level reads F's limb t (F: [O][M][d^2][pt_limbs][N]); limb
+// level is P and reads fp ([O][M][d^2][N]).  u and U rows in the key-switch
+// layout: [2][level + 1][N] per ciphertext, narrow rows packed.  grid
+// (N / 64, level + 1, n_b ceil(O / TAP_OT)), 256 threads as k_tap_hma.
+template <int LOGN>
+__global__ void __launch_bounds__(256)
+k_tap_hma_qp(const u64* __restrict__ x, const u64* __restrict__ u, const u64* __restrict__ filt,
+             const u64* __restrict__ fp, u64* __restrict__ out, int level, int pt_limbs, int big_l, TapMap tm,
+             Mods mods) {
+  constexpr int N = 1 << LOGN;
+  __shared__ u64 part[TAP_SLICES][2 * TAP_OT][64];
+  const int lane = (int)threadIdx.x & 63;
+  const int sl = (int)threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + lane;
+  const int t = blockIdx.y;
+  const bool is_p = t == level;
+  const int n_ot = (tm.o_c + TAP_OT - 1) / TAP_OT;
+  const size_t b = blockIdx.z / n_ot;
+  const int o0 = (int)(blockIdx.z % n_ot) * TAP_OT;
+  const int no = min(TAP_OT, tm.o_c - o0);
+  const ModConst m = mods.m[is_p ? big_l : t];
+  const u64 pm = is_p ? 0 : reduce64(mods.m[big_l].q, m);  // P mod q_t
+  const size_t cstride = (size_t)2 * level * N;
+  const size_t ustride = (size_t)2 * (level + 1) * N;
+  const int fl = is_p ? 1 : pt_limbs;  // limbs per plaintext in the array read
+  const size_t fo = (size_t)tm.m_cts * tm.d2 * fl * N;
+  const u64* fbase = (is_p ? fp : filt + (size_t)t * N) + (size_t)o0 * fo + i;
+  const int terms = tm.m_cts * tm.d2;
+  u64 s0[TAP_OT], s1[TAP_OT];
+#pragma unroll
+  for (int r = 0; r < TAP_OT; ++r) s0[r] = s1[r] = 0;
+  if (m.narrow) {
+    u64 l0[TAP_OT], l1[TAP_OT];
+#pragma unroll
+    for (int r = 0; r < TAP_OT; ++r) l0[r] = l1[r] = 0;
+    int n_lazy = 0;
+    for (int e = sl; e < terms; e += TAP_SLICES) {
+      const int mc = e / tm.d2, k = e - mc * tm.d2;
+      const size_t ct = b * tm.m_cts + mc;
+      const int id = tm.idx[k];
+      u64 a0, a1;
+      if (id >= 0) {  // packed rows: N 32-bit residues at the start of each 64-bit row
+        const u64* row0 = u + (ct * tm.nrot + id) * ustride + (size_t)t * N;
+        a0 = reinterpret_cast<const u32*>(row0)[i];
+        a1 = reinterpret_cast<const u32*>(row0 + (size_t)(level + 1) * N)[i];
+      } else {
+        if (is_p) continue;
+        const u64* src = x + ct * cstride + (size_t)t * N + i;
+        a0 = mul_mod(src[0], pm, m);
+        a1 = mul_mod(src[(size_t)level * N], pm, m);
+      }
+      const u64* f = fbase + (size_t)e * fl * N;
+#pragma unroll
+      for (int r = 0; r < TAP_OT; ++r)
+        if (r < no) {
+          const u64 fv = (u32)f[r * fo];
+          l0[r] += a0 * fv;
+          l1[r] += a1 * fv;
+        }
+      if (++n_lazy == 15) {
+#pragma unroll
+        for (int r = 0; r < TAP_OT; ++r) {
+          s0[r] = add_mod(s0[r], reduce64(l0[r], m), m.q);
+          s1[r] = add_mod(s1[r], reduce64(l1[r], m), m.q);
+          l0[r] = l1[r] = 0;
+        }
+        n_lazy = 0;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < TAP_OT; ++r) {
+      s0[r] = add_mod(s0[r], reduce64(l0[r], m), m.q);
+      s1[r] = add_mod(s1[r], reduce64(l1[r], m), m.q);
+    }
+  } else {
+    for (int e = sl; e < terms; e += TAP_SLICES) {
+      const int mc = e / tm.d2, k = e - mc * tm.d2;
+      const size_t ct = b * tm.m_cts + mc;
+      const int id = tm.idx[k];
+      u64 a0, a1;
+      if (id >= 0) {
+        const u64* ur = u + (ct * tm.nrot + id) * ustride + (size_t)t * N + i;
+        a0 = ur[0];
+        a1 = ur[(size_t)(level + 1) * N];
+      } else {
+        if (is_p) continue;
+        const u64* src = x + ct * cstride + (size_t)t * N + i;
+        a0 = mul_mod(src[0], pm, m);
+        a1 = mul_mod(src[(size_t)level * N], pm, m);
+      }
+      const u64* f = fbase + (size_t)e * fl * N;
+#pragma unroll
+      for (int r = 0; r < TAP_OT; ++r)
+        if (r < no) {
+          const u64 fv = f[r * fo];
+          s0[r] = add_mod(s0[r], mul_mod(a0, fv, m), m.q);
+          s1[r] = add_mod(s1[r], mul_mod(a1, fv, m), m.q);
+        }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < TAP_OT; ++r) {
+    part[sl][r][lane] = s0[r];
+    part[sl][TAP_OT + r][lane] = s1[r];
+  }
+  __syncthreads();
+  for (int e = (int)threadIdx.x; e < 2 * TAP_OT * 64; e += 256) {
+    const int l = e & 63, v = e >> 6;
+    const int c = v / TAP_OT, r = v - c * TAP_OT;
+    if (r >= no) continue;
+    u64 acc = part[0][v][l];
+#pragma unroll
+    for (int q = 1; q < TAP_SLICES; ++q) acc = add_mod(acc, part[q][v][l], m.q);
+    u64* row = out + ((b * tm.o_c + o0 + r) * 2 + c) * (level + 1) * N + (size_t)t * N;
+    if (m.narrow)
+      reinterpret_cast<u32*>(row)[blockIdx.x * 64 + l] = (u32)acc;
+    else
+      row[blockIdx.x * 64 + l] = acc;
   }
 }
 

@@ -209,7 +209,7 @@ void LHoistUp<LOGN>::run(he_ctx* c, const KsJob* jobs1, int count, int level, u6
 // serves one ciphertext.
 template <int LOGN>
 void LHoisted<LOGN>::run(he_ctx* c, const KsJob* jobs, int m, int level, const u64* dhat, u64* u, u64* rc, hipStream_t s,
-                         int job_base, int per_ct, size_t dstride, int part) {
+                         int job_base, int per_ct, size_t dstride, int part, int add_c0) {
   constexpr int T = NttGeom<LOGN>::T;
   constexpr int N = 1 << LOGN;
   if (u == nullptr) {
@@ -228,7 +228,7 @@ void LHoisted<LOGN>::run(he_ctx* c, const KsJob* jobs, int m, int level, const u
   if (part != 2) {
     Prof pr(c, "ip_perm", s);
     k_ip_perm<LOGN><<<dim3(N / 256, level + 1, m), 256, 0, s>>>(dhat, jobs, u, level, c->big_l, c->mods, job_base,
-                                                                 per_ct, dstride);
+                                                                 per_ct, dstride, add_c0);
   }
   if (part == 1) return;
   {  // u rows per polynomial: level + 1, P at row level (one P group)
@@ -237,6 +237,27 @@ void LHoisted<LOGN>::run(he_ctx* c, const KsJob* jobs, int m, int level, const u
                                        jobs, m, u, level, 1, c->big_l, rc, c->mods, c->tb())));
   }
   LDrop<LOGN>::run(c, MODE_P, EPI_ROT, jobs, m, level, level + 1, u, rc, s);
+}
+
+template <int LOGN>
+void LModDown<LOGN>::run(he_ctx* c, const KsJob* jobs, int count, int level, const u64* u, u64* rc, hipStream_t s) {
+  constexpr int T = NttGeom<LOGN>::T;
+  {
+    Prof pr(c, "intt_last", s);
+    HE_FOR_CLASSES(1u << c->p_cls, (k_intt_last<LOGN, MODE_P, CLS><<<xcd_grid(2, count), T, 0, s>>>(
+                                       jobs, count, u, level, 1, c->big_l, rc, c->mods, c->tb())));
+  }
+  LDrop<LOGN>::run(c, MODE_P, EPI_STORE, jobs, count, level, level + 1, u, rc, s);
+}
+
+template <int LOGN>
+void LTapHmaQp<LOGN>::run(he_ctx* c, const u64* x, const u64* u, const u64* filt, const u64* fp, u64* out, int level,
+                          int pt_limbs, const TapMap& tm, int n_b, hipStream_t s) {
+  constexpr int N = 1 << LOGN;
+  Prof pr(c, "tap_hma", s);
+  const int n_ot = (tm.o_c + TAP_OT - 1) / TAP_OT;
+  k_tap_hma_qp<LOGN><<<dim3(N / 64, level + 1, n_b * n_ot), 256, 0, s>>>(x, u, filt, fp, out, level, pt_limbs,
+                                                                        c->big_l, tm, c->mods);
 }
 
 template <int LOGN>
@@ -262,4 +283,6 @@ void LTapHma<LOGN>::run(he_ctx* c, const u64* x, const u64* rot, const u64* filt
   template struct LHoistUp<LOGN>;         \
   template struct LHoisted<LOGN>;         \
   template struct LTapHma<LOGN>;          \
+  template struct LTapHmaQp<LOGN>;        \
+  template struct LModDown<LOGN>;         \
   }

@@ -489,24 +489,29 @@ class HEContext:
         return need
 
     def conv_tap(self, xs: torch.Tensor, scale: float, desc: HeConvDesc, filt: torch.Tensor, pt_scale: float,
-                 out: torch.Tensor | None = None) -> Ct:
+                 filt_p: torch.Tensor | None = None, out: torch.Tensor | None = None) -> Ct:
         """Tap-style DensePack conv of xs [B][M][2][level][N] with plaintexts
-        filt [O][M][d^2][limbs][N]; returns [B][O][2][level-1][N]."""
+        filt [O][M][d^2][limbs][N] (and their residues mod P, filt_p
+        [O][M][d^2][N], for one ModDown per output); returns
+        [B][O][2][level-1][N]."""
         nb, level = xs.shape[0], xs.shape[-2]
         if out is None:
             out = torch.empty((nb, desc.o_c, 2, level - 1, self.n), dtype=torch.int64, device="cuda")
         out_scale = ctypes.c_double(0.0)
+        fp = None if filt_p is None else _ptr(filt_p)
         self._check(self.lib.he_conv_tap(self.h, nb, _ptr(xs), level, ctypes.byref(desc), _ptr(filt), filt.shape[-2],
-                                         float(scale), float(pt_scale), _ptr(out), ctypes.byref(out_scale),
+                                         fp, float(scale), float(pt_scale), _ptr(out), ctypes.byref(out_scale),
                                          _stream()), "he_conv_tap")
         return Ct(out, out_scale.value)
 
     def ffconv_layer_tap(self, xs: torch.Tensor, scale: float, desc: HeConvDesc, w1_filt: torch.Tensor,
                          w1_scale: float, mask: torch.Tensor, mask_scale: float, w2: np.ndarray, k_bits: int,
-                         square: bool = False, out: torch.Tensor | None = None) -> Ct:
+                         square: bool = False, w1_p: torch.Tensor | None = None,
+                         out: torch.Tensor | None = None) -> Ct:
         """Tap-style FFConv of xs [B][M][2][level][N]: W1 plaintexts
-        [r][M][d^2][limbs][N] (desc.o_c = r), output mask E, W2 (r x o_c2);
-        returns [B][o_c2][2][level-2 (-1 with square)][N]."""
+        [r][M][d^2][limbs][N] (desc.o_c = r; w1_p their residues mod P for
+        one ModDown per output), output mask E, W2 (r x o_c2); returns
+        [B][o_c2][2][level-2 (-1 with square)][N]."""
         nb, level = xs.shape[0], xs.shape[-2]
         w2f = np.ascontiguousarray(np.asarray(w2, dtype=np.float64))
         o_c2 = w2f.shape[1]
@@ -515,7 +520,8 @@ class HEContext:
             out = torch.empty((nb, o_c2, 2, lvl_out, self.n), dtype=torch.int64, device="cuda")
         out_scale = ctypes.c_double(0.0)
         self._check(self.lib.ffconv_layer_tap(self.h, nb, _ptr(xs), level, ctypes.byref(desc), _ptr(w1_filt),
-                                              w1_filt.shape[-2], float(scale), float(w1_scale), _ptr(mask),
+                                              w1_filt.shape[-2], None if w1_p is None else _ptr(w1_p),
+                                              float(scale), float(w1_scale), _ptr(mask),
                                               float(mask_scale), w2f.ctypes.data_as(_lib.DP), o_c2, int(k_bits),
                                               int(square), _ptr(out), ctypes.byref(out_scale), _stream()),
                     "ffconv_layer_tap")

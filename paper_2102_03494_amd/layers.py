@@ -225,9 +225,11 @@ def encode_filters(client, weights: np.ndarray, g: Geometry, level: int, pt_scal
 
 
 def encode_tap_filters(client, weights: np.ndarray, g: Geometry, level: int, pt_scale: float,
-                       threads: int = 16) -> torch.Tensor:
-    """Tap plaintexts [O][M][d^2][level][N] on the device.  The host encodes
-    run in a thread pool (the library's encoder releases the GIL)."""
+                       threads: int = 16, with_p: bool = False):
+    """Tap plaintexts [O][M][d^2][level][N] on the device (with_p: also their
+    residues mod the special prime P, [O][M][d^2][N], returned as a pair).
+    The host encodes run in a thread pool (the library's encoder releases
+    the GIL)."""
     from concurrent.futures import ThreadPoolExecutor
 
     ctx = client.ctx
@@ -236,6 +238,8 @@ def encode_tap_filters(client, weights: np.ndarray, g: Geometry, level: int, pt_
     m_cts = g.n_cts(slots)
     d2 = g.d * g.d
     out = torch.empty((o_c, m_cts, d2, level, ctx.n), dtype=torch.int64, device="cuda")
+    outp = torch.empty((o_c, m_cts, d2, ctx.n), dtype=torch.int64, device="cuda") if with_p else None
+    big_l = len(ctx.q)
     idx = [(o, m, t) for o in range(o_c) for m in range(m_cts) for t in range(d2)]
 
     def coeffs(key):
@@ -244,10 +248,15 @@ def encode_tap_filters(client, weights: np.ndarray, g: Geometry, level: int, pt_
 
     with ThreadPoolExecutor(max_workers=threads) as pool:
         for (o, m, t), co in zip(idx, pool.map(coeffs, idx)):
-            pt = ctx.from_signed(torch.from_numpy(co).cuda(), level, 0)
+            dco = torch.from_numpy(co).cuda()
+            pt = ctx.from_signed(dco, level, 0)
             ctx.ntt(pt.view(1, level, ctx.n))
             out[o, m, t] = pt
-    return out
+            if with_p:
+                pp = ctx.from_signed(dco, 1, big_l)
+                ctx.ntt(pp.view(1, 1, ctx.n), big_l)
+                outp[o, m, t] = pp[0]
+    return (out, outp) if with_p else out
 
 
 def pt_scale_for(ctx: HEContext, level: int, in_scale: float, target: float) -> float:

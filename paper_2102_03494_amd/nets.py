@@ -287,8 +287,8 @@ class EncryptedNet:
 class TapNet:
     """The same nets with every FFConv stage as a tap-style FFConv
     (ffconv_layer_tap: hoisted tap rotations and masked W1 plaintexts
-    instead of one rotate-and-sum chain per DensePack output; not one of the
-    paper's designs).  A stage's output channel o holds output (i, j) at slot
+    instead of one rotate-and-sum chain per DensePack output, the rotations'
+    ModDown deferred to one per W1 output; not one of the paper's designs).  A stage's output channel o holds output (i, j) at slot
     (s i) W + s j of its input plane (W: input width), zero elsewhere; the
     CP->DP combine packs B = floor(N / (2 H W)) channels per ciphertext with
     blocks of H W slots, so for stride 1 the next stage reads the usual
@@ -317,8 +317,8 @@ class TapNet:
             y_scale = cur_scale * w1s / ctx.q[level - 1]
             tgt = pre_square_target(ctx, level - 2, scale) if st.square else scale
             ms = ctx.q[level - 2] * tgt / (y_scale * 2.0**K_BITS)
-            rec = dict(spec=st, level=level, in_scale=cur_scale, desc=desc, w1s=w1s, ms=ms,
-                       filt=encode_tap_filters(enc, weights[f"w1_{k}"], g, level, w1s),
+            filt, filt_p = encode_tap_filters(enc, weights[f"w1_{k}"], g, level, w1s, with_p=True)
+            rec = dict(spec=st, level=level, in_scale=cur_scale, desc=desc, w1s=w1s, ms=ms, filt=filt, filt_p=filt_p,
                        mask=enc.encode(tap_output_mask_layout(g, slots), level - 1, ms), w2=weights[f"w2_{k}"])
             out_level = level - 2 - (1 if st.square else 0)
             z_scale = y_scale * ms * 2.0**K_BITS / ctx.q[level - 2]
@@ -386,7 +386,7 @@ class TapNet:
         for rec in self.stages:
             st = rec["spec"]
             z = ctx.ffconv_layer_tap(cur.data, cur.scale, rec["desc"], rec["filt"], rec["w1s"], rec["mask"],
-                                     rec["ms"], rec["w2"], K_BITS, square=st.square)
+                                     rec["ms"], rec["w2"], K_BITS, square=st.square, w1_p=rec["filt_p"])
             cur = ctx.combine_cp_dp_batch(z, rec["block"], rec["per_dense"]) if "per_dense" in rec else z
         if self.fc is not None:
             fc = self.fc

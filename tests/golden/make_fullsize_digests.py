@@ -20,7 +20,8 @@ tests make them):
   sampled dot products, one per (output channel, border class) pair.
 * ``tap``: the tap-style FFConv layers of bench.py's section (MNIST-shaped
   at N = 8192 with x^2; the CIFAR-shaped net's two stages at N = 16384):
-  digests of the W1 output and of the layer output.
+  digests of the W1 output and of the layer output, with the hoisted
+  rotations' ModDown per rotation and deferred to one per output.
 
 A digest is the SHA-256 of the little-endian uint64 residues of the
 ciphertext array [count][2][level][N] in C order.  Each DensePack output is
@@ -205,8 +206,14 @@ def tap_case(name: str) -> dict:
     z, _ = C.gather_convpack(p, y, 1, w2, 12, mask, ms)
     if square:
         z, _ = C.square_rescale(p, octx, z)
+    # the same with one ModDown per W1 output (tap_conv_lazy)
+    filt_p = C.tap_filters_p(p, w1, geom, w1_scale)
+    yl, _ = C.tap_conv_lazy(p, octx, xs, geom, filt, filt_p, w1_scale)
+    zl, _ = C.tap_ffconv(p, octx, xs, geom, filt, w1_scale, w2, 12, mask, ms, square=square, w1_filters_p=filt_p)
     return {"w1_tap": {"shape": list(y.c.shape), "scale": y.scale, "sha256": digest(y.c)},
-            "ffconv_tap": {"shape": list(z.c.shape), "scale": z.scale, "sha256": digest(z.c)}}
+            "ffconv_tap": {"shape": list(z.c.shape), "scale": z.scale, "sha256": digest(z.c)},
+            "w1_tap_lazy": {"shape": list(yl.c.shape), "scale": yl.scale, "sha256": digest(yl.c)},
+            "ffconv_tap_lazy": {"shape": list(zl.c.shape), "scale": zl.scale, "sha256": digest(zl.c)}}
 
 
 def main():

@@ -251,14 +251,16 @@ TAP_CASES = {
 }
 
 
+@pytest.mark.parametrize("lazy", [0, 1], ids=["moddown-per-rotation", "moddown-per-output"])
 @pytest.mark.parametrize("name", list(TAP_CASES))
-def test_tap_ffconv_fullsize_digests(name):
+def test_tap_ffconv_fullsize_digests(name, lazy):
     """The tap-style FFConv layers of bench.py's section at their full sizes
     (N = 8192 with x^2; N = 16384 stage 1 at level 6 and stage 2 over 8 input
     ciphertexts at level 3), on the oracle's ciphertexts and plaintexts: the
     W1 output and the layer output equal the oracle's bit for bit (digests
-    written by make_fullsize_digests.py from the oracle alone), and the
-    output decrypts to the FP64 layer within 1e-3."""
+    written by make_fullsize_digests.py from the oracle alone), with the
+    hoisted rotations' ModDown per rotation or deferred to one per output,
+    and the output decrypts to the FP64 layer within 1e-3."""
     he = _he()
     from paper_2102_03494_amd import layers as Ly
     from paper_2102_03494_amd.client import Client
@@ -290,6 +292,8 @@ def test_tap_ffconv_fullsize_digests(name):
     differ = (mine != want_f).any(axis=(-2, -1))  # plaintexts whose NTT residues differ
     assert differ.sum() <= 2, int(differ.sum())
     filt = he.to_device(want_f)
+    filt_p = he.to_device(C.tap_filters_p(p, w1, geom, w1_scale)) if lazy else None
+    sfx = "_lazy" if lazy else ""
     del mine
     t2 = C.pre_square_target(p, level - 2, p.scale) if square else p.scale
     ms = C.gather_mask_scale(p, level - 1, p.scale, t2, 12)
@@ -297,13 +301,14 @@ def test_tap_ffconv_fullsize_digests(name):
     desc = gctx.conv_desc(*shape, d, stride, pad, r, 0)
     gctx.reserve(gctx.tap_workspace_need(1, level, desc, o_c, square))
     xs = he.to_device(cts[None])
-    y = gctx.conv_tap(xs, p.scale, desc, filt, w1_scale)
-    assert list(y.data.shape[1:]) == gold["w1_tap"]["shape"] and y.scale == gold["w1_tap"]["scale"]
-    assert _digest(y.data[0]) == gold["w1_tap"]["sha256"]
-    z = gctx.ffconv_layer_tap(xs, p.scale, desc, filt, w1_scale, mask, ms, w2, 12, square=square)
-    assert list(z.data.shape[1:]) == gold["ffconv_tap"]["shape"]
-    assert abs(z.scale / gold["ffconv_tap"]["scale"] - 1) < 1e-15
-    assert _digest(z.data[0]) == gold["ffconv_tap"]["sha256"]
+    y = gctx.conv_tap(xs, p.scale, desc, filt, w1_scale, filt_p=filt_p)
+    gw, gz = gold["w1_tap" + sfx], gold["ffconv_tap" + sfx]
+    assert list(y.data.shape[1:]) == gw["shape"] and y.scale == gw["scale"]
+    assert _digest(y.data[0]) == gw["sha256"]
+    z = gctx.ffconv_layer_tap(xs, p.scale, desc, filt, w1_scale, mask, ms, w2, 12, square=square, w1_p=filt_p)
+    assert list(z.data.shape[1:]) == gz["shape"]
+    assert abs(z.scale / gz["scale"] - 1) < 1e-15
+    assert _digest(z.data[0]) == gz["sha256"]
     ref = R.ffconv_reference(x, w1, w2, stride, pad, square=square)
     where = C.tap_output_slots(geom)
     for o in range(o_c):

@@ -62,8 +62,9 @@ def _same_layouts(p, geom, g):
     assert np.array_equal(Ly.tap_output_slots(g), C.tap_output_slots(geom))
 
 
+@pytest.mark.parametrize("lazy", [0, 1], ids=["moddown-per-rotation", "moddown-per-output"])
 @pytest.mark.parametrize("shape,d,stride,pad,o_c", TAP_CASES)
-def test_tap_conv_bit_exact(shape, d, stride, pad, o_c):
+def test_tap_conv_bit_exact(shape, d, stride, pad, o_c, lazy):
     Ly = _layers()
     geom = C.ConvGeom(shape[0], shape[1], shape[2], d, stride, pad)
     g = Ly.Geometry(shape[0], shape[1], shape[2], d, stride, pad)
@@ -75,17 +76,21 @@ def test_tap_conv_bit_exact(shape, d, stride, pad, o_c):
     w = synth.weights(W, 83, (d, d, shape[2], o_c), 0.2)
     pt_scale = p.q[level - 1] * p.scale / p.scale
     want_f = C.tap_filters(p, w, geom, level, pt_scale)
-    filt = Ly.encode_tap_filters(Ly.PlainEncoder(gctx), w, g, level, pt_scale)
-    assert np.array_equal(_host(filt), want_f)
+    want_p = C.tap_filters_p(p, w, geom, pt_scale)
+    filt, filt_p = Ly.encode_tap_filters(Ly.PlainEncoder(gctx), w, g, level, pt_scale, with_p=True)
+    assert np.array_equal(_host(filt), want_f) and np.array_equal(_host(filt_p), want_p)
     xs, cts = _tap_inputs(p, octx, geom, shape, level, nb, 40)
     desc = gctx.conv_desc(*shape, d, stride, pad, o_c, 0)
     gctx.reserve(gctx.tap_workspace_need(nb, level, desc))
-    got = gctx.conv_tap(_dev(cts), p.scale, desc, filt, pt_scale)
+    got = gctx.conv_tap(_dev(cts), p.scale, desc, filt, pt_scale, filt_p=filt_p if lazy else None)
     out = _host(got.data)
     gc = gctx.last_counts()
     ref_all = []
     for b in range(nb):
-        want, cnt = C.tap_conv(p, octx, S.Ciphertext(cts[b], p.scale), geom, want_f, pt_scale)
+        if lazy:
+            want, cnt = C.tap_conv_lazy(p, octx, S.Ciphertext(cts[b], p.scale), geom, want_f, want_p, pt_scale)
+        else:
+            want, cnt = C.tap_conv(p, octx, S.Ciphertext(cts[b], p.scale), geom, want_f, pt_scale)
         assert np.array_equal(out[b], want.c), b
         assert got.scale == want.scale
         ref_all.append(cnt)
@@ -99,9 +104,10 @@ def test_tap_conv_bit_exact(shape, d, stride, pad, o_c):
             assert np.abs(v[where] - ref[:, :, o].reshape(-1)).max() < 1e-3, (b, o)
 
 
+@pytest.mark.parametrize("lazy", [0, 1], ids=["moddown-per-rotation", "moddown-per-output"])
 @pytest.mark.parametrize("chain,square,o_c2", [(None, True, 4), (None, False, 9), (SMALL40, True, 4)],
                          ids=["30bit-sq", "30bit", "40bit-sq"])
-def test_ffconv_tap_bit_exact(chain, square, o_c2):
+def test_ffconv_tap_bit_exact(chain, square, o_c2, lazy):
     Ly = _layers()
     shape, d, stride, pad, r = (6, 6, 3), 3, 1, 1, 2
     geom = C.ConvGeom(*shape, d, stride, pad)
@@ -115,21 +121,23 @@ def test_ffconv_tap_bit_exact(chain, square, o_c2):
     t2 = C.pre_square_target(p, level - 2, p.scale) if square else p.scale
     mask_scale = C.gather_mask_scale(p, level - 1, p.scale, t2, 12)
     want_f = C.tap_filters(p, w1, geom, level, w1_scale)
+    want_p = C.tap_filters_p(p, w1, geom, w1_scale) if lazy else None
     want_m = E.encode(C.tap_output_mask_slots(geom, p.slots), p, level - 1, mask_scale)
-    filt = Ly.encode_tap_filters(Ly.PlainEncoder(gctx), w1, g, level, w1_scale)
+    filt, filt_p = Ly.encode_tap_filters(Ly.PlainEncoder(gctx), w1, g, level, w1_scale, with_p=True)
     mask = Ly.PlainEncoder(gctx).encode(Ly.tap_output_mask_layout(g, p.slots), level - 1, mask_scale)
     assert np.array_equal(_host(filt), want_f) and np.array_equal(_host(mask), want_m)
     xs, cts = _tap_inputs(p, octx, geom, shape, level, nb, 50)
     desc = gctx.conv_desc(*shape, d, stride, pad, r, 0)
     gctx.reserve(gctx.tap_workspace_need(nb, level, desc, o_c2, square))
-    got = gctx.ffconv_layer_tap(_dev(cts), p.scale, desc, filt, w1_scale, mask, mask_scale, w2, 12, square=square)
+    got = gctx.ffconv_layer_tap(_dev(cts), p.scale, desc, filt, w1_scale, mask, mask_scale, w2, 12, square=square,
+                                w1_p=filt_p if lazy else None)
     out = _host(got.data)
     where = C.tap_output_slots(geom)
     rest = np.ones(p.slots, bool)
     rest[where] = False
     for b in range(nb):
         want, _ = C.tap_ffconv(p, octx, S.Ciphertext(cts[b], p.scale), geom, want_f, w1_scale, w2, 12, want_m,
-                               mask_scale, square=square)
+                               mask_scale, square=square, w1_filters_p=want_p)
         assert np.array_equal(out[b], want.c), b
         assert abs(got.scale / want.scale - 1) < 1e-15
         ref = R.ffconv_reference(xs[b], w1, w2, stride, pad, square=square)
