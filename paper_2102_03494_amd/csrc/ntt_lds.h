@@ -19,7 +19,9 @@
 // into passes of up to 4; in a pass every thread loads 16 entries (one or
 // more radix-2^k groups) into registers, runs the k stages there and writes
 // them back, with one barrier per pass: 3-4 LDS round trips per transform
-// instead of log2 N.  Callers stage data into LDS (coalesced, with any fused
+// instead of log2 N.  A forward transform whose last 1 or 2 stages do not
+// fill a pass runs them on the last full pass's registers with lane
+// exchanges inside a quad (DPP) instead of one more LDS pass.  Callers stage data into LDS (coalesced, with any fused
 // pre-processing such as a Galois permutation or a centred lift) and read the
 // result back out of LDS in a coalesced pattern.
 //
@@ -231,8 +233,33 @@ struct Tw {
   const word_t<CLS>* sh;
 };
 
-// One forward pass: stages s0 .. s0+K-1.
-template <int LOGN, int K, int CLS, int E = 16>
+// Lane exchange inside a quad through DPP (xor 1: quad_perm [1,0,3,2];
+// xor 2: [2,3,0,1]); every lane of the wave must be active.
+template <int X>
+__device__ __forceinline__ u32 quad_xor32(u32 v) {
+  static_assert(X == 1 || X == 2, "quad lanes only");
+  return (u32)__builtin_amdgcn_update_dpp(0, (int)v, X == 1 ? 0xB1 : 0x4E, 0xF, 0xF, false);
+}
+template <int X, typename W>
+__device__ __forceinline__ W quad_xor(W v) {
+  if constexpr (sizeof(W) == 4) {
+    return (W)quad_xor32<X>((u32)v);
+  } else {
+    const u64 b = __builtin_bit_cast(u64, v);
+    const u64 r = ((u64)quad_xor32<X>((u32)(b >> 32)) << 32) | quad_xor32<X>((u32)b);
+    return __builtin_bit_cast(W, r);
+  }
+}
+
+// One forward pass: stages s0 .. s0+K-1.  With TAIL (1 or 2, the pass that
+// ends K stages before the last), the last TAIL stages follow in registers:
+// after the pass a thread's entries are j = blk B0 + off + 2^TAIL r with
+// off = lane mod 2^TAIL, so each remaining butterfly pairs the same r of
+// lanes off and off ^ t (t = 1, 2), exchanged within the quad through DPP
+// instead of another LDS round trip and barrier.  The lane of the lower
+// entry sends fwd_x(x), the upper lane w y; both form the usual x + w y /
+// x - w y, so the results are those of the LDS pass.
+template <int LOGN, int K, int CLS, int E = 16, int TAIL = 0>
 __device__ __forceinline__ void fwd_pass(u64* lds_raw, int s0, Tw<CLS> tw, MV<CLS> q, int tid) {
   typedef word_t<CLS> W;
   typedef Arith<CLS> A;
@@ -266,6 +293,25 @@ __device__ __forceinline__ void fwd_pass(u64* lds_raw, int s0, Tw<CLS> tw, MV<CL
         const W y = A::mulc(v[r + half], tw.w[ti], CLS == CLS_F64 ? W(0) : tw.sh[ti], q);
         v[r] = A::add(x, y, q);
         v[r + half] = A::sub(x, y, q);
+      }
+    }
+    if constexpr (TAIL > 0) {
+      static_assert(TAIL <= 2 && G == 1, "a tail follows a full pass with one group per thread");
+#pragma unroll
+      for (int u = 0; u < TAIL; ++u) {
+        const int t = 1 << (TAIL - 1 - u);  // lane (and entry) distance of this stage's pairs
+        const int m = 1 << (s0 + K + u);
+        const bool upper = (off & t) != 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int j = base + Wd * r;
+          const int ti = m + (j >> (TAIL - u));
+          const W x = A::fwd_x(v[r], q);
+          const W y = A::mulc(v[r], tw.w[ti], CLS == CLS_F64 ? W(0) : tw.sh[ti], q);
+          const W send = upper ? y : x;
+          const W recv = (TAIL - 1 - u) == 0 ? quad_xor<1>(send) : quad_xor<2>(send);
+          v[r] = upper ? A::sub(recv, y, q) : A::add(x, recv, q);
+        }
       }
     }
 #pragma unroll
@@ -334,14 +380,25 @@ __device__ __forceinline__ void ntt_fwd_lds(u64* lds, Tw<CLS> tw, MV<CLS> q, int
   constexpr int FULL = LOGN / KM;
   constexpr int REM = LOGN % KM;
   lds_barrier();
+  if constexpr (REM > 0 && REM <= 2 && FULL > 0) {
+    // the last REM stages ride on the last full pass (lane exchanges, no LDS pass)
 #pragma unroll
-  for (int p = 0; p < FULL; ++p) {
-    fwd_pass<LOGN, KM, CLS, E>(lds, KM * p, tw, q, tid);
+    for (int p = 0; p < FULL - 1; ++p) {
+      fwd_pass<LOGN, KM, CLS, E>(lds, KM * p, tw, q, tid);
+      lds_barrier();
+    }
+    fwd_pass<LOGN, KM, CLS, E, REM>(lds, KM * (FULL - 1), tw, q, tid);
     lds_barrier();
-  }
-  if constexpr (REM > 0) {
-    fwd_pass<LOGN, REM, CLS, E>(lds, KM * FULL, tw, q, tid);
-    lds_barrier();
+  } else {
+#pragma unroll
+    for (int p = 0; p < FULL; ++p) {
+      fwd_pass<LOGN, KM, CLS, E>(lds, KM * p, tw, q, tid);
+      lds_barrier();
+    }
+    if constexpr (REM > 0) {
+      fwd_pass<LOGN, REM, CLS, E>(lds, KM * FULL, tw, q, tid);
+      lds_barrier();
+    }
   }
 }
 
