@@ -926,6 +926,74 @@ def tap_case(torch, name, ring, shape, d, stride, pad, level, r, o_c, square, ba
     return out
 
 
+def tap_graph_section(torch, n_inputs: int = 128) -> dict:
+    """Launch-bound layers: the MNIST-shaped tap-style FFConv (one ModDown per
+    output, W2 from a device table, so the call copies nothing from the
+    host) on n_inputs encrypted images three ways: one call per image, one
+    captured call replayed per image (the next image copied into its input
+    buffer first), and one batched call over all images."""
+    import synth
+    from paper_2102_03494_amd import layers as Ly
+    from paper_2102_03494_amd.client import Client
+    from paper_2102_03494_amd.he import HEContext
+
+    wl = "tap_mnist"
+    ctx = HEContext(N, Q_BITS, P_BITS)
+    cl = Client(ctx, wl)
+    g = Ly.Geometry(28, 28, 1, 5, 2, 0)
+    slots = N // 2
+    level = len(Q_BITS)
+    cl.gen_rotation_keys(Ly.tap_rotation_steps(g, slots))
+    cl.gen_relin_key()
+    imgs = [synth.image(wl, (28, 28, 1), index=b) for b in range(n_inputs)]
+    cts = torch.stack([cl.encrypt(Ly.densepack_layout(x, g, slots)[0], level, SCALE, index=b).data
+                       for b, x in enumerate(imgs)])  # [B][1][2][level][N]
+    w1 = synth.weights(wl, 1, (5, 5, 1, 2), 0.05)
+    w2 = synth.weights(wl, 2, (2, 5), 0.05)
+    enc = Ly.PlainEncoder(ctx)
+    w1s = Ly.pt_scale_for(ctx, level, SCALE, SCALE)
+    f1, f1p = Ly.encode_tap_filters(enc, w1, g, level, w1s, with_p=True)
+    t2 = Ly.pre_square_target(ctx, level - 2, SCALE)
+    ms = Ly.mask_scale_for(ctx, level - 1, SCALE, t2, K_BITS)
+    mask = enc.encode(Ly.tap_output_mask_layout(g, slots), level - 1, ms)
+    tab = ctx.int_weight_table(w2, K_BITS, level - 1)
+    desc = ctx.conv_desc(28, 28, 1, 5, 2, 0, 2, 0)
+    ctx.reserve(ctx.tap_workspace_need(n_inputs, level, desc, 5, True))
+    x1 = cts[0:1].clone()
+    out1 = torch.empty((1, 5, 2, level - 3, N), dtype=torch.int64, device="cuda")
+
+    def one(xs, out=None):
+        return ctx.ffconv_layer_tap(xs, SCALE, desc, f1, w1s, mask, ms, w2, K_BITS, square=True, w1_p=f1p,
+                                    w2_tab=tab, out=out)
+
+    def eager_all():
+        for b in range(n_inputs):
+            one(cts[b:b + 1])
+
+    graph, _ = ctx.capture(lambda: one(x1, out1))
+
+    def graph_all():
+        for b in range(n_inputs):
+            x1.copy_(cts[b:b + 1])
+            graph.launch()
+
+    t_eager, _ = timed(eager_all, 2, 1, torch)
+    t_graph, _ = timed(graph_all, 2, 1, torch)
+    t_batch, zb = timed(lambda: one(cts), 3, 1, torch)
+    x1.copy_(cts[n_inputs - 1:n_inputs])
+    graph.launch()
+    torch.cuda.synchronize()
+    same = bool(torch.equal(out1[0], zb.data[n_inputs - 1]))
+    graph.close()
+    ctx.close()
+    print(f"# tap graph: eager {t_eager * 1e3 / n_inputs:.3f}, graph {t_graph * 1e3 / n_inputs:.3f}, "
+          f"batched {t_batch * 1e3 / n_inputs:.3f} ms per image", file=sys.stderr, flush=True)
+    return {"workload": f"{n_inputs} MNIST-shaped images (28x28x1), tap-style FFConv 5x5 s2 1->2->5 + x^2 at N=8192",
+            "eager_ms_per_image": t_eager * 1e3 / n_inputs, "graph_ms_per_image": t_graph * 1e3 / n_inputs,
+            "batched_ms_per_image": t_batch * 1e3 / n_inputs, "graph_speedup": t_eager / t_graph,
+            "batched_speedup": t_eager / t_batch, "graph_bits_equal_batched": same}
+
+
 def tap_section(torch, reps: int) -> dict:
     """Tap-style DensePack (hoisted tap rotations; a variant that is not one
     of the paper's designs) on the MNIST-shaped layer of the timed workload
@@ -943,6 +1011,8 @@ def tap_section(torch, reps: int) -> dict:
                                                   reps)
     out["cifar_stage2_32x32x64_r8_o64_level3"] = tap_case(torch, "cifar2", ring16, (32, 32, 64), 3, 1, 1, 3, 8, 64,
                                                           False, 1, reps)
+    torch.cuda.empty_cache()
+    out["launch_bound_graph_vs_batch"] = tap_graph_section(torch)
     return out
 
 

@@ -429,7 +429,10 @@ int he_conv_convpack(he_ctx *ctx, const uint64_t *d_in, int k, int level, const 
  *          layer with one ciphertext per channel: G_c = y_c * E (d_mask: E,
  *          one at every output slot, NTT domain, >= level-1 limbs, at
  *          mask_scale; it clears the partial sums), Z_o = sum_c
- *          round-half-away(h_w2[c*o_c2 + o] 2^k_bits) G_c, rescale, and with
+ *          round-half-away(h_w2[c*o_c2 + o] 2^k_bits) G_c (or the same
+ *          integers from d_w2_tab, he_int_weight_table's table of the r x o_c2
+ *          W2 at level - 1, when d_w2_tab is not NULL: then the call copies
+ *          nothing from the host and can be captured in a graph), rescale, and with
  *          `square` x^2 relinearised and rescaled.  d_out: [n_batch][o_c2][2]
  *          [level-2 (-1 more if square)][N], output (i, j) at slot
  *          (s i) w + s j, zero elsewhere; *out_scale = ((in_scale w1_scale /
@@ -444,8 +447,8 @@ int he_conv_tap(he_ctx *ctx, int n_batch, const uint64_t *d_in, int level, const
                 uint64_t *d_out, double *out_scale, void *stream);
 int ffconv_layer_tap(he_ctx *ctx, int n_batch, const uint64_t *d_in, int level, const he_conv_desc *desc,
                      const uint64_t *d_w1, int w1_limbs, const uint64_t *d_w1_p, double in_scale, double w1_scale,
-                     const uint64_t *d_mask, double mask_scale, const double *h_w2, int o_c2, int k_bits, int square,
-                     uint64_t *d_out, double *out_scale, void *stream);
+                     const uint64_t *d_mask, double mask_scale, const double *h_w2, const uint64_t *d_w2_tab,
+                     int o_c2, int k_bits, int square, uint64_t *d_out, double *out_scale, void *stream);
 
 /* ---- homomorphic Im2Col for d > 1 (Table III, CP-HI2C-CP / CP-HI2C-DP) -----
  * he_him2col: the K = d^2 I_c ConvPack input ciphertexts of Eq. 1 from a

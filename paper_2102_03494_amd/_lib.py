@@ -94,7 +94,7 @@ SIGNATURES = {
     "he_conv_tap": (I, [P, I, P, I, ctypes.POINTER(HeConvDesc), P, I, P, ctypes.c_double, ctypes.c_double, P, DP,
                         P]),
     "ffconv_layer_tap": (I, [P, I, P, I, ctypes.POINTER(HeConvDesc), P, I, P, ctypes.c_double, ctypes.c_double, P,
-                             ctypes.c_double, DP, I, I, I, P, DP, P]),
+                             ctypes.c_double, DP, P, I, I, I, P, DP, P]),
     "ffconv_layer_batch": (I, [P, I, P, ctypes.c_size_t, I, ctypes.POINTER(HeConvDesc), P, ctypes.c_size_t, P, P,
                                I, I, P, P]),
     "he_ffconv_workspace_need": (ctypes.c_size_t, [P, I, I, ctypes.POINTER(HeConvDesc), I, I]),

@@ -1654,10 +1654,10 @@ int he_conv_tap(he_ctx* c, int n_batch, const uint64_t* d_in, int level, const h
 int ffconv_layer_tap(he_ctx* c, int n_batch, const uint64_t* d_in, int level, const he_conv_desc* desc,
                      const uint64_t* d_w1, int w1_limbs, const uint64_t* d_w1_p, double in_scale, double w1_scale,
                      const uint64_t* d_mask,
-                     double mask_scale, const double* h_w2, int o_c2, int k_bits, int square, uint64_t* d_out,
-                     double* out_scale, void* stream) {
-  if (!c || !d_in || !desc || !d_w1 || !d_mask || !h_w2 || !d_out || !out_scale || n_batch < 1 || o_c2 < 1 ||
-      k_bits < 0 || k_bits > 40 || w1_limbs < 1)
+                     double mask_scale, const double* h_w2, const uint64_t* d_w2_tab, int o_c2, int k_bits,
+                     int square, uint64_t* d_out, double* out_scale, void* stream) {
+  if (!c || !d_in || !desc || !d_w1 || !d_mask || (!h_w2 && !d_w2_tab) || !d_out || !out_scale || n_batch < 1 ||
+      o_c2 < 1 || k_bits < 0 || k_bits > 40 || w1_limbs < 1)
     return fail(c, HE_EINVAL, "ffconv_layer_tap: bad arguments");
   const int need = square ? 4 : 3;
   if (level < need || level > c->big_l)
@@ -1672,21 +1672,26 @@ int ffconv_layer_tap(he_ctx* c, int n_batch, const uint64_t* d_in, int level, co
   const int r = desc->o_c;
   if ((long long)n_batch * r > 65535 || (long long)n_batch * o_c2 > 65535 || (long long)n_batch * tp.m_cts > 65535)
     return fail(c, HE_EINVAL, "ffconv_layer_tap: batch too large for one call");
-  std::vector<int64_t> w((size_t)r * o_c2);
-  for (size_t i = 0; i < w.size(); ++i) {
-    const double x = std::ldexp(h_w2[i], k_bits);
-    if (!(std::fabs(x) < 4.0e18)) return fail(c, HE_EINVAL, "ffconv_layer_tap: W2 weight not finite or too large");
-    w[i] = round_half_away(x);
-  }
   const int n = c->n;
   hipStream_t s = S(stream);
   c->counts = he_counts{};
   Arena ar(c);
-  std::vector<u64> tab = scalar_table(c, w, level - 1);
-  u64* d_tab = ar.take<u64>(tab.size());
+  const u64* d_tab = d_w2_tab;
+  if (!d_w2_tab) {  // from host weights: one copy to the device, so not capturable
+    std::vector<int64_t> w((size_t)r * o_c2);
+    for (size_t i = 0; i < w.size(); ++i) {
+      const double x = std::ldexp(h_w2[i], k_bits);
+      if (!(std::fabs(x) < 4.0e18)) return fail(c, HE_EINVAL, "ffconv_layer_tap: W2 weight not finite or too large");
+      w[i] = round_half_away(x);
+    }
+    std::vector<u64> tab = scalar_table(c, w, level - 1);
+    u64* t = ar.take<u64>(tab.size());
+    if (!t) return fail(c, HE_ENOMEM, "workspace too small for ffconv_layer_tap");
+    if ((e = upload(c, t, tab.data(), tab.size() * 8, s))) return e;
+    d_tab = t;
+  }
   u64* y = ar.take<u64>((size_t)n_batch * r * 2 * (level - 1) * n);
-  if (!d_tab || !y) return fail(c, HE_ENOMEM, "workspace too small for ffconv_layer_tap");
-  if ((e = upload(c, d_tab, tab.data(), tab.size() * 8, s))) return e;
+  if (!y) return fail(c, HE_ENOMEM, "workspace too small for ffconv_layer_tap");
   if ((e = tap_run(c, tp, n_batch, d_in, level, d_w1, w1_limbs, d_w1_p, y, ar, s))) return e;
   if ((e = ffconv_tail(c, n_batch, y, level - 1, 1, r, d_mask, d_tab, o_c2, square, d_out, ar, s, true))) return e;
   const double y_scale = in_scale * w1_scale / (double)c->moduli[level - 1];

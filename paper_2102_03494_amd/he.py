@@ -507,14 +507,17 @@ class HEContext:
     def ffconv_layer_tap(self, xs: torch.Tensor, scale: float, desc: HeConvDesc, w1_filt: torch.Tensor,
                          w1_scale: float, mask: torch.Tensor, mask_scale: float, w2: np.ndarray, k_bits: int,
                          square: bool = False, w1_p: torch.Tensor | None = None,
-                         out: torch.Tensor | None = None) -> Ct:
+                         out: torch.Tensor | None = None, w2_tab: torch.Tensor | None = None) -> Ct:
         """Tap-style FFConv of xs [B][M][2][level][N]: W1 plaintexts
         [r][M][d^2][limbs][N] (desc.o_c = r; w1_p their residues mod P for
-        one ModDown per output), output mask E, W2 (r x o_c2); returns
+        one ModDown per output), output mask E, W2 (r x o_c2; with w2_tab,
+        its int_weight_table at level - 1, the call copies nothing from the
+        host and can be captured); returns
         [B][o_c2][2][level-2 (-1 with square)][N]."""
         nb, level = xs.shape[0], xs.shape[-2]
         w2f = np.ascontiguousarray(np.asarray(w2, dtype=np.float64))
         o_c2 = w2f.shape[1]
+        h_w2 = None if w2_tab is not None else w2f.ctypes.data_as(_lib.DP)
         lvl_out = level - 2 - (1 if square else 0)
         if out is None:
             out = torch.empty((nb, o_c2, 2, lvl_out, self.n), dtype=torch.int64, device="cuda")
@@ -522,7 +525,8 @@ class HEContext:
         self._check(self.lib.ffconv_layer_tap(self.h, nb, _ptr(xs), level, ctypes.byref(desc), _ptr(w1_filt),
                                               w1_filt.shape[-2], None if w1_p is None else _ptr(w1_p),
                                               float(scale), float(w1_scale), _ptr(mask),
-                                              float(mask_scale), w2f.ctypes.data_as(_lib.DP), o_c2, int(k_bits),
+                                              float(mask_scale), h_w2, None if w2_tab is None else _ptr(w2_tab),
+                                              o_c2, int(k_bits),
                                               int(square), _ptr(out), ctypes.byref(out_scale), _stream()),
                     "ffconv_layer_tap")
         return Ct(out, out_scale.value)

@@ -319,7 +319,8 @@ class TapNet:
             ms = ctx.q[level - 2] * tgt / (y_scale * 2.0**K_BITS)
             filt, filt_p = encode_tap_filters(enc, weights[f"w1_{k}"], g, level, w1s, with_p=True)
             rec = dict(spec=st, level=level, in_scale=cur_scale, desc=desc, w1s=w1s, ms=ms, filt=filt, filt_p=filt_p,
-                       mask=enc.encode(tap_output_mask_layout(g, slots), level - 1, ms), w2=weights[f"w2_{k}"])
+                       mask=enc.encode(tap_output_mask_layout(g, slots), level - 1, ms), w2=weights[f"w2_{k}"],
+                       w2_tab=ctx.int_weight_table(weights[f"w2_{k}"], K_BITS, level - 1))
             out_level = level - 2 - (1 if st.square else 0)
             z_scale = y_scale * ms * 2.0**K_BITS / ctx.q[level - 2]
             if st.square:
@@ -386,7 +387,8 @@ class TapNet:
         for rec in self.stages:
             st = rec["spec"]
             z = ctx.ffconv_layer_tap(cur.data, cur.scale, rec["desc"], rec["filt"], rec["w1s"], rec["mask"],
-                                     rec["ms"], rec["w2"], K_BITS, square=st.square, w1_p=rec["filt_p"])
+                                     rec["ms"], rec["w2"], K_BITS, square=st.square, w1_p=rec["filt_p"],
+                                     w2_tab=rec["w2_tab"])
             cur = ctx.combine_cp_dp_batch(z, rec["block"], rec["per_dense"]) if "per_dense" in rec else z
         if self.fc is not None:
             fc = self.fc

@@ -261,3 +261,48 @@ def test_rotate_hoisted_batch_pipeline_bit_exact(pipeline):
     for i in range(8):
         for r, k in enumerate(steps):
             assert np.array_equal(got[i, r], S.rotate(p, octx, S.Ciphertext(cts[i], p.scale), k).c), (i, k)
+
+
+def test_ffconv_tap_graph_replays_equal_eager():
+    """The tap-style FFConv with its W2 as a device table copies nothing from
+    the host: its output equals the host-weights call, and the call captured
+    in a HIP graph gives the eager bits on every replay, with eager work and
+    new inputs between the replays."""
+    Ly = _layers()
+    shape, d, stride, pad, r, o_c2 = (6, 6, 3), 3, 1, 1, 2, 4
+    geom = C.ConvGeom(*shape, d, stride, pad)
+    g = Ly.Geometry(*shape, d, stride, pad)
+    p, octx, gctx, cl = _small_setup(rotations=C.tap_rotation_steps(geom, 512), relin=True)
+    level, nb = 4, 2
+    w1 = synth.weights(W, 75, (d, d, shape[2], r), 0.3)
+    w2 = synth.weights(W, 76, (r, o_c2), 0.5)
+    w1_scale = p.q[level - 1] * p.scale / p.scale
+    t2 = C.pre_square_target(p, level - 2, p.scale)
+    ms = C.gather_mask_scale(p, level - 1, p.scale, t2, 12)
+    enc = Ly.PlainEncoder(gctx)
+    filt, filt_p = Ly.encode_tap_filters(enc, w1, g, level, w1_scale, with_p=True)
+    mask = enc.encode(Ly.tap_output_mask_layout(g, p.slots), level - 1, ms)
+    tab = gctx.int_weight_table(w2, 12, level - 1)
+    desc = gctx.conv_desc(*shape, d, stride, pad, r, 0)
+    gctx.reserve(gctx.tap_workspace_need(nb, level, desc, o_c2, True))
+    _, cts_a = _tap_inputs(p, octx, geom, shape, level, nb, 80)
+    _, cts_b = _tap_inputs(p, octx, geom, shape, level, nb, 90)
+    xs = _dev(cts_a)
+
+    def call(out=None, table=True):
+        return gctx.ffconv_layer_tap(xs, p.scale, desc, filt, w1_scale, mask, ms, w2, 12, square=True, w1_p=filt_p,
+                                     out=out, w2_tab=tab if table else None)
+
+    eager_a = _host(call(table=False).data)
+    assert np.array_equal(_host(call().data), eager_a)
+    out = torch.empty((nb, o_c2, 2, level - 3, p.n), dtype=torch.int64, device="cuda")
+    graph, _ = gctx.capture(lambda: call(out=out))
+    xs.copy_(_dev(cts_b))
+    eager_b = _host(call().data)
+    for k in range(3):
+        xs.copy_(_dev(cts_a if k % 2 == 0 else cts_b))
+        graph.launch()
+        torch.cuda.synchronize()
+        assert np.array_equal(_host(out), eager_a if k % 2 == 0 else eager_b), k
+        call()  # eager work between replays
+    graph.close()
