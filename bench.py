@@ -45,11 +45,11 @@ DOMINANT = "ks_modup_stage"
 # valid only for the kernel sources they were measured on: bench.py reports
 # them when these sources hash to KERNEL_SHA256, else null.
 KERNEL_SOURCES = ("modarith.h", "ntt_lds.h", "kernels.h", "capi.hip")
-KERNEL_SHA256 = "5be7c7b31d1f17959fed0538de38bcfa35a25ca8ca13bbe33766f1a4433ddc3e"
+KERNEL_SHA256 = "19ddcaa58fbc3da508bbd909c2e6171855cc1611274c9ba2cab9ee1a0a73cfa9"
 # ks_modup_stage: mean over one layer's 25 launches (24 of 144 jobs at
-# 147.7 MB, one relinearisation launch of 5 jobs at 6.6 MB); ip_perm: one
+# 124.9 MB, one relinearisation launch of 5 jobs at 6.3 MB); ip_perm: one
 # launch over all 256 rotations
-TRAFFIC_BYTES = {"ks_modup_stage": 142070579, "ip_perm": 4455740330}
+TRAFFIC_BYTES = {"ks_modup_stage": 120195144, "ip_perm": 4454178755}
 
 
 def kernel_sha256() -> str:
