@@ -176,11 +176,15 @@ struct Chain {
   KsScratch ks;
   int count = 0, level = 0, pg = 1, steps = 0;
   bool packed = false;  // the accumulator leaves the chain packed
+  bool in_packed0 = false;  // the first step reads packed input too
 };
 
 // False (nothing launched) when the chain does not fit the arena in one
 // chunk or has too many steps; the caller then rotates step by step.
-bool chain_prepare(he_ctx* c, u64* acc, int count, int level, int steps, Arena ar, hipStream_t s, Chain& ch) {
+// With in_packed0 (honoured only where the accumulator is kept packed), the
+// chain starts from a packed accumulator; ch.in_packed0 says whether it does.
+bool chain_prepare(he_ctx* c, u64* acc, int count, int level, int steps, Arena ar, hipStream_t s, Chain& ch,
+                   bool in_packed0 = false) {
   const int n = c->n;
   if (steps < 1 || steps > MAX_CHAIN || count < 1) return false;
   const int pg = p_groups(c, level);
@@ -202,8 +206,10 @@ bool chain_prepare(he_ctx* c, u64* acc, int count, int level, int steps, Arena a
   ch.steps = steps;
   // between steps the accumulator is kept packed when every ciphertext prime is narrow
   ch.packed = c->q_mask == (1u << CLS_N32);
+  ch.in_packed0 = ch.packed && in_packed0;
   k_make_chain_jobs<<<dim3((count + 255) / 256, steps), 256, 0, s>>>(ch.jobs, count, acc, (size_t)2 * level * n,
-                                                                    (size_t)level * n, level, ck, (int)ch.packed);
+                                                                    (size_t)level * n, level, ck, (int)ch.packed,
+                                                                    (int)ch.in_packed0);
   return true;
 }
 
@@ -215,7 +221,8 @@ void chain_step(he_ctx* c, const Chain& ch, int j, hipStream_t s) {
   auto switches = [&](int k) { return k < ch.steps && galois_of(1 << k, c->n) != 1; };
   // ModDown writes the next step's digits only where the kernel has them
   auto fused = [&](int k) { return c->logn <= NEXT_DIGITS_MAX_LOGN && switches(k) && switches(k + 1); };
-  const int pk = ch.packed ? (JOB_OUT_PACKED | (j > 0 ? JOB_IN_PACKED : 0)) : 0;  // as k_make_chain_jobs sets
+  // as k_make_chain_jobs sets
+  const int pk = ch.packed ? (JOB_OUT_PACKED | ((j > 0 || ch.in_packed0) ? JOB_IN_PACKED : 0)) : 0;
   if (switches(j))
     dispatch_logn<LKsCore>(c->logn, c, jobs, ch.count, ch.level, ch.pg, ch.ks.dcoef, ch.ks.u, ch.ks.rc, s, pk,
                            j > 0 && fused(j - 1));
@@ -348,9 +355,10 @@ int densepack_run(he_ctx* c, const u64* d_in, int level, const he_conv_desc* des
     Arena sub = ar;
     u64* acc = sub.take<u64>((size_t)cn * 2 * level * n);
     if (!acc) return fail(c, HE_ENOMEM, "workspace too small");
-    dispatch_logn<LDpHma>(c->logn, c, d_in, d_filt, acc, level, o0, cn, geo, s);
     u64* out = d_out + (size_t)o0 * 2 * (level - 1) * n;
     const int n_cls = (int)c->has_cls[0] + (int)c->has_cls[1] + (int)c->has_cls[2];
+    // The chains' job tables come first, so that the HMA can leave the
+    // products packed where the chains keep their accumulators packed.
     if (c->split_streams && cn >= 64 && n_cls <= 2) {
       // The outputs are independent chains through the rotate-and-add steps:
       // two halves on two streams fill each other's kernel tails; one fork
@@ -360,13 +368,15 @@ int densepack_run(he_ctx* c, const u64* d_in, int level, const he_conv_desc* des
       u64* out1 = out + (size_t)h0 * 2 * (level - 1) * n;
       Arena a0 = sub, a1 = sub;
       sub.halves(a0, a1);
+      Chain ch0, ch1;
+      const bool chained = chain_prepare(c, acc, h0, level, desc->r_steps, a0, s, ch0, true) &&
+                           chain_prepare(c, acc1, h1, level, desc->r_steps, a1, s, ch1, true);
+      dispatch_logn<LDpHma>(c->logn, c, d_in, d_filt, acc, level, o0, cn, geo, s, chained && ch0.in_packed0);
       (void)hipEventRecord(c->fork_ev, s);
       (void)hipStreamWaitEvent(c->side, c->fork_ev, 0);
       int e = HE_OK;
-      Chain ch0, ch1;
       bool packed0 = false, packed1 = false;
-      if (chain_prepare(c, acc, h0, level, desc->r_steps, a0, s, ch0) &&
-          chain_prepare(c, acc1, h1, level, desc->r_steps, a1, c->side, ch1)) {
+      if (chained) {
         for (int j = 0; j < desc->r_steps; ++j) {
           chain_step(c, ch0, j, s);
           chain_step(c, ch1, j, c->side);
@@ -386,8 +396,10 @@ int densepack_run(he_ctx* c, const u64* d_in, int level, const he_conv_desc* des
       if (e) return e;
     } else {
       Chain ch;
+      const bool chained = chain_prepare(c, acc, cn, level, desc->r_steps, sub, s, ch, true);
+      dispatch_logn<LDpHma>(c->logn, c, d_in, d_filt, acc, level, o0, cn, geo, s, chained && ch.in_packed0);
       bool packed = false;
-      if (chain_prepare(c, acc, cn, level, desc->r_steps, sub, s, ch)) {
+      if (chained) {
         for (int j = 0; j < desc->r_steps; ++j) chain_step(c, ch, j, s);
         packed = ch.packed;
       } else {

@@ -227,7 +227,7 @@ struct LIntt1 {
 template <int LOGN>
 struct LDpHma {
   static void run(he_ctx* c, const u64* x, const u64* filt, u64* out, int level, int out_base, int n_out,
-                  const DPGeom& geo, hipStream_t s);
+                  const DPGeom& geo, hipStream_t s, bool out_packed = false);
 };
 template <int LOGN>
 struct LHmaPerm {

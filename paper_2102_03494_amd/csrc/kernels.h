@@ -1509,7 +1509,8 @@ __device__ __forceinline__ u32 pow_mod_2n(u32 base, u32 e, u32 mask2n) {
 }
 
 // DensePack MulPC (Table I): output out_base + blockIdx.y (index o*S + p),
-// limb blockIdx.x; out[blockIdx.y] = sum_m x_m * sigma_{g_p}(F[o][class][m]).
+// limb blockIdx.x; out[blockIdx.y] = sum_m x_m * sigma_{g_p}(F[o][class][m]),
+// narrow limbs packed as 32-bit words when out_packed (KsJob's packed rows).
 struct DPGeom {
   int h, w, c_in, d, stride, pad, o_c;
   int out_h, out_w, n_row_cls, n_col_cls, m_cts;
@@ -1524,7 +1525,7 @@ struct DPGeom {
 template <int LOGN, bool NARROW>
 __device__ __forceinline__ void dp_hma_body(const u64* __restrict__ x, const u64* __restrict__ filt,
                                             u64* __restrict__ out, int level, int out_base, const DPGeom& geo,
-                                            const ModConst& m, u64* lds) {
+                                            const ModConst& m, u64* lds, int out_packed) {
   typedef std::conditional_t<NARROW, u32, u64> W;
   constexpr int N = 1 << LOGN;
   constexpr int T = NttGeom<LOGN>::T;
@@ -1567,6 +1568,15 @@ __device__ __forceinline__ void dp_hma_body(const u64* __restrict__ x, const u64
   }
   u64* o0 = out + (((size_t)blockIdx.y * 2 + 0) * level + t) * N;  // chunk-relative
   u64* o1 = out + (((size_t)blockIdx.y * 2 + 1) * level + t) * N;
+  if (NARROW && out_packed) {  // packed row (as a rotate-and-sum chain keeps its accumulator)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int k = (int)threadIdx.x + r * T;
+      reinterpret_cast<u32*>(o0)[k] = (u32)acc0[r];
+      reinterpret_cast<u32*>(o1)[k] = (u32)acc1[r];
+    }
+    return;
+  }
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int k = (int)threadIdx.x + r * T;
@@ -1578,11 +1588,11 @@ __device__ __forceinline__ void dp_hma_body(const u64* __restrict__ x, const u64
 template <int LOGN>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
 k_dp_hma(const u64* __restrict__ x, const u64* __restrict__ filt, u64* __restrict__ out, int level, int out_base,
-         DPGeom geo, Mods mods) {
+         DPGeom geo, Mods mods, int out_packed) {
   __shared__ u64 lds[NttGeom<LOGN>::LDS];
   const ModConst m = mods.m[blockIdx.x];
-  if (m.narrow) dp_hma_body<LOGN, true>(x, filt, out, level, out_base, geo, m, lds);
-  else dp_hma_body<LOGN, false>(x, filt, out, level, out_base, geo, m, lds);
+  if (m.narrow) dp_hma_body<LOGN, true>(x, filt, out, level, out_base, geo, m, lds, out_packed);
+  else dp_hma_body<LOGN, false>(x, filt, out, level, out_base, geo, m, lds, out_packed);
 }
 
 // Sum of permuted-plaintext products into one accumulator per blockIdx.z:

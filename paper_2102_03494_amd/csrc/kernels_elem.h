@@ -27,10 +27,10 @@ __global__ void k_make_jobs(KsJob* jobs, int count, const u64* d_base, size_t d_
 // Job tables of all steps of a rotate-and-sum chain over `count` ciphertexts
 // updated in place (ciphertext b at base + b * stride): step j's table at
 // jobs + j * count.  With `packed`, every step writes its output packed and
-// every step but the first reads packed input.  grid (ceil(count / 256),
-// steps).
+// every step but the first reads packed input (the first too with
+// in_packed0).  grid (ceil(count / 256), steps).
 __global__ void k_make_chain_jobs(KsJob* jobs, int count, u64* base, size_t stride, size_t c1_off, int level,
-                                  ChainKeys ck, int packed) {
+                                  ChainKeys ck, int packed, int in_packed0) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y;
   if (b >= count) return;
@@ -43,7 +43,7 @@ __global__ void k_make_chain_jobs(KsJob* jobs, int count, u64* base, size_t stri
   jb.g = ck.g[j];
   jb.ginv = ck.ginv[j];
   jb.level = level;
-  jb.flags = packed ? (JOB_OUT_PACKED | (j > 0 ? JOB_IN_PACKED : 0)) : 0;
+  jb.flags = packed ? (JOB_OUT_PACKED | ((j > 0 || in_packed0) ? JOB_IN_PACKED : 0)) : 0;
   jobs[(size_t)j * count + b] = jb;
 }
 

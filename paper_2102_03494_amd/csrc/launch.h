@@ -168,9 +168,10 @@ void LIntt1<LOGN>::run(he_ctx* c, const KsJob* jobs, int count, int lmax, u64* r
 
 template <int LOGN>
 void LDpHma<LOGN>::run(he_ctx* c, const u64* x, const u64* filt, u64* out, int level, int out_base, int n_out,
-                  const DPGeom& geo, hipStream_t s) {
+                  const DPGeom& geo, hipStream_t s, bool out_packed) {
   Prof pr(c, "dp_hma", s);
-  k_dp_hma<LOGN><<<dim3(level, n_out), NttGeom<LOGN>::T, 0, s>>>(x, filt, out, level, out_base, geo, c->mods);
+  k_dp_hma<LOGN><<<dim3(level, n_out), NttGeom<LOGN>::T, 0, s>>>(x, filt, out, level, out_base, geo, c->mods,
+                                                                (int)out_packed);
 }
 
 template <int LOGN>
