@@ -127,6 +127,20 @@ def modup_ip_bytes(count: int, level: int, n: int, moduli, pg: int, packed_in: b
     return count * per + key
 
 
+def dp_hma_bytes(n_out: int, m_cts: int, n_filters: int, level: int, n: int, moduli,
+                 packed_out: bool = True) -> float:
+    """Algorithmic HBM bytes of one DensePack MulPC launch (k_dp_hma) over
+    n_out outputs: the m_cts input ciphertexts and the n_filters base filter
+    plaintexts (one per output channel, border class and input ciphertext)
+    read once, as 64-bit words, and the n_out products (two polynomials of
+    `level` limbs) written once, narrow residues as packed 32-bit words when
+    packed_out (the products then go straight into packed rotate-and-sum
+    chains)."""
+    qs = moduli[:level]
+    out_row = sum(4 if (packed_out and q < (1 << 30)) else 8 for q in qs) * n
+    return (2 * m_cts + n_filters) * level * 8 * n + n_out * 2 * out_row
+
+
 def setup(ctx, client, x, w1, w2):
     from paper_2102_03494_amd import layers as Ly
     from paper_2102_03494_amd.he import Ct
@@ -1166,6 +1180,14 @@ def main():
     ctx.prof_select(None)
     counts_ff = ctx.last_counts()
     print(f"# ffconv: {t_ff * 1e3:.3f} ms/layer", file=sys.stderr, flush=True)
+    # the DensePack MulPC kernel, bracketed by HIP events in a few more layers
+    hma_steps = max(2, min(args.steps, 10))
+    ctx.prof_select("dp_hma")
+    for _ in range(hma_steps):
+        ffconv_step()
+    torch.cuda.synchronize()
+    hma_ms, _hma_busy, hma_launches = ctx.prof_read_busy()
+    ctx.prof_select(None)
 
     # ---- plain comparator -------------------------------------------------------
     t_pl, zp, counts_pl = float("nan"), None, None
@@ -1202,10 +1224,10 @@ def main():
     ops_layer = 12 * modup_ip_ops(288, level, N, ctx.moduli, pg, hv) + \
         modup_ip_ops(5, 2, N, ctx.moduli[:2] + ctx.moduli[-1:], ctx.get_tuning("p_groups", 2),
                      ctx.get_tuning("modup_halves", 2) == 1)
-    # the chain's accumulator is packed after its first step (all primes narrow)
+    # the chain's accumulator is packed from its first step on (all primes
+    # narrow: the MulPC kernel leaves its products packed)
     packed = all(q < (1 << 30) for q in ctx.moduli[:level])
-    bytes_layer = modup_ip_bytes(288, level, N, ctx.moduli, pg) + \
-        11 * modup_ip_bytes(288, level, N, ctx.moduli, pg, packed_in=packed) + \
+    bytes_layer = 12 * modup_ip_bytes(288, level, N, ctx.moduli, pg, packed_in=packed) + \
         modup_ip_bytes(5, 2, N, ctx.moduli[:2] + ctx.moduli[-1:], ctx.get_tuning("p_groups", 2))
     launches_layer = 12 * (2 if split else 1) + 1
     avg_ms = dom_ms / max(1, dom_launches)
@@ -1231,6 +1253,18 @@ def main():
         "per_launch_achieved": per_launch_ops / 1e12,
         "p_groups": pg, "split_streams": split,
         "hbm_gbs_algorithmic": bytes_layer * layers / (dom_busy_ms * 1e-3) / 1e9,
+    }
+    rows, cols = geom.classes()
+    n_out_ff = geom.spatial * w1.shape[3]
+    hma_bytes = dp_hma_bytes(n_out_ff, 1, w1.shape[3] * len(rows) * len(cols), level, N, ctx.moduli, packed)
+    hma_avg_ms = hma_ms / max(1, hma_launches)
+    hma_roofline = {
+        "kernel": "k_dp_hma<13>: DensePack MulPC of the 288 W1 outputs (input times Galois-permuted base filter, "
+                  "four 30-bit limbs), one launch per layer",
+        "bound": "hbm", "achieved": hma_bytes / (hma_avg_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": hma_bytes / (hma_avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": measured_traffic("dp_hma"),
+        "avg_launch_ms": hma_avg_ms, "launches": hma_launches, "algorithmic_bytes_per_launch": hma_bytes,
+        "hma_per_s_in_kernel": n_out_ff / (hma_avg_ms * 1e-3),
     }
     from paper_2102_03494_amd import tune as _tune
     tuning = {"source": ctx.tuning_source, **_tune.chosen(ctx)}
@@ -1323,6 +1357,7 @@ def main():
         "paper_counts_plain_conv": paper_counts_dp(geom.spatial, w2.shape[1], 12),
         "decrypted_max_abs_err": {"ffconv": err_ff, "plain": err_pl},
         "roofline": roofline,
+        "hma_roofline": hma_roofline,
         "tuning": tuning,
         "batched_layers_graph": batched,
         "rank_sweep": sweep,

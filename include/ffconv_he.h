@@ -118,7 +118,10 @@ const char *he_last_error(const he_ctx *ctx);
  * product into the special prime P at key-switch level `level` (1..L);
  * value 0 restores the built-in cost model.  knob "split_streams" (level
  * ignored; 1 by default, 0 or 1): run the rotate-and-sum of a DensePack
- * layer's outputs as two halves on two streams.  knob "modup_halves" at
+ * layer's outputs as independent chains on as many streams (each with its
+ * own workspace share).  knob "split_parts" (level ignored; 2 by default,
+ * 2..4): the number of those chains (fewer when a chunk has under 32 outputs
+ * per chain).  knob "modup_halves" at
  * key-switch level `level` (0: every level; -1 restores the default, which is
  * 1 for N >= 8192, else 0): 1 runs ModUp as two half-ring workgroups per
  * target (N >= 2048; a launch follows its largest level), 0 as one workgroup

@@ -359,40 +359,46 @@ int densepack_run(he_ctx* c, const u64* d_in, int level, const he_conv_desc* des
     const int n_cls = (int)c->has_cls[0] + (int)c->has_cls[1] + (int)c->has_cls[2];
     // The chains' job tables come first, so that the HMA can leave the
     // products packed where the chains keep their accumulators packed.
-    if (c->split_streams && cn >= 64 && n_cls <= 2) {
+    const int parts = (c->split_streams && cn >= 64 && n_cls <= 2) ? std::min(c->split_parts, cn / 32) : 1;
+    if (parts > 1) {
       // The outputs are independent chains through the rotate-and-add steps:
-      // two halves on two streams fill each other's kernel tails; one fork
-      // and one join per chunk, each half with its own scratch.
-      const int h0 = cn / 2, h1 = cn - h0;
-      u64* acc1 = acc + (size_t)h0 * 2 * level * n;
-      u64* out1 = out + (size_t)h0 * 2 * (level - 1) * n;
-      Arena a0 = sub, a1 = sub;
-      sub.halves(a0, a1);
-      Chain ch0, ch1;
-      const bool chained = chain_prepare(c, acc, h0, level, desc->r_steps, a0, s, ch0, true) &&
-                           chain_prepare(c, acc1, h1, level, desc->r_steps, a1, s, ch1, true);
-      dispatch_logn<LDpHma>(c->logn, c, d_in, d_filt, acc, level, o0, cn, geo, s, chained && ch0.in_packed0);
-      (void)hipEventRecord(c->fork_ev, s);
-      (void)hipStreamWaitEvent(c->side, c->fork_ev, 0);
-      int e = HE_OK;
-      bool packed0 = false, packed1 = false;
-      if (chained) {
-        for (int j = 0; j < desc->r_steps; ++j) {
-          chain_step(c, ch0, j, s);
-          chain_step(c, ch1, j, c->side);
-        }
-        packed0 = ch0.packed;
-        packed1 = ch1.packed;
-      } else {
-        for (int j = 0; j < desc->r_steps && !e; ++j) {
-          e = rotate_batch(c, acc, acc, h0, level, 1 << j, EPI_ROTSUM, a0, s);
-          if (!e) e = rotate_batch(c, acc1, acc1, h1, level, 1 << j, EPI_ROTSUM, a1, c->side);
-        }
+      // `parts` chains on as many streams fill each other's kernel tails; one
+      // fork and one join per chunk, each chain with its own scratch.
+      hipStream_t st[MAX_SPLIT] = {s, c->side, c->side_x[0], c->side_x[1]};
+      hipEvent_t jn[MAX_SPLIT] = {nullptr, c->join_ev, c->join_x[0], c->join_x[1]};
+      int cnt[MAX_SPLIT], first[MAX_SPLIT];
+      for (int p = 0; p < parts; ++p) {
+        first[p] = (int)((long long)cn * p / parts);
+        cnt[p] = (int)((long long)cn * (p + 1) / parts) - first[p];
       }
-      if (!e) e = rescale_batch(c, out, acc, h0, level, a0, s, packed0);
-      if (!e) e = rescale_batch(c, out1, acc1, h1, level, a1, c->side, packed1);
-      (void)hipEventRecord(c->join_ev, c->side);
-      (void)hipStreamWaitEvent(s, c->join_ev, 0);
+      Arena ap[MAX_SPLIT] = {sub, sub, sub, sub};
+      sub.split(parts, ap);
+      Chain ch[MAX_SPLIT];
+      bool chained = true;
+      for (int p = 0; p < parts && chained; ++p)
+        chained = chain_prepare(c, acc + (size_t)first[p] * 2 * level * n, cnt[p], level, desc->r_steps, ap[p], s,
+                                ch[p], true);
+      dispatch_logn<LDpHma>(c->logn, c, d_in, d_filt, acc, level, o0, cn, geo, s, chained && ch[0].in_packed0);
+      (void)hipEventRecord(c->fork_ev, s);
+      for (int p = 1; p < parts; ++p) (void)hipStreamWaitEvent(st[p], c->fork_ev, 0);
+      int e = HE_OK;
+      if (chained) {
+        for (int j = 0; j < desc->r_steps; ++j)
+          for (int p = 0; p < parts; ++p) chain_step(c, ch[p], j, st[p]);
+      } else {
+        for (int j = 0; j < desc->r_steps && !e; ++j)
+          for (int p = 0; p < parts && !e; ++p) {
+            u64* a = acc + (size_t)first[p] * 2 * level * n;
+            e = rotate_batch(c, a, a, cnt[p], level, 1 << j, EPI_ROTSUM, ap[p], st[p]);
+          }
+      }
+      for (int p = 0; p < parts && !e; ++p)
+        e = rescale_batch(c, out + (size_t)first[p] * 2 * (level - 1) * n, acc + (size_t)first[p] * 2 * level * n,
+                          cnt[p], level, ap[p], st[p], chained && ch[p].packed);
+      for (int p = 1; p < parts; ++p) {
+        (void)hipEventRecord(jn[p], st[p]);
+        (void)hipStreamWaitEvent(s, jn[p], 0);
+      }
       if (e) return e;
     } else {
       Chain ch;
@@ -988,7 +994,7 @@ int he_ctx_create(const he_params* p, he_ctx** out) {
       inv[dv * HE_MAXM + t] = v;
       inv[HE_MAXM * HE_MAXM + dv * HE_MAXM + t] = shoup_companion(v, mods[t]);
     }
-  const bool ok = hipMalloc((void**)&c->d_tw, tw.size() * 8) == hipSuccess &&
+  bool ok = hipMalloc((void**)&c->d_tw, tw.size() * 8) == hipSuccess &&
                   hipMemcpy(c->d_tw, tw.data(), tw.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
                   hipMalloc((void**)&c->d_tw32, tw32.size() * 4) == hipSuccess &&
                   hipMemcpy(c->d_tw32, tw32.data(), tw32.size() * 4, hipMemcpyHostToDevice) == hipSuccess &&
@@ -1009,6 +1015,9 @@ int he_ctx_create(const he_params* p, he_ctx** out) {
                   hipEventCreateWithFlags(&c->pipe_ev[1], hipEventDisableTiming) == hipSuccess &&
                   hipEventCreateWithFlags(&c->pipe_ev[2], hipEventDisableTiming) == hipSuccess &&
                   hipEventCreateWithFlags(&c->pipe_ev[3], hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; ok && i < MAX_SPLIT - 2; ++i)
+    ok = hipStreamCreateWithFlags(&c->side_x[i], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&c->join_x[i], hipEventDisableTiming) == hipSuccess;
   if (!ok || scratch_setup(c) != HE_OK) {
     he_ctx_destroy(c);
     return HE_EDEVICE;
@@ -1032,6 +1041,10 @@ int he_ctx_destroy(he_ctx* c) {
   (void)hipFree(c->d_inv);
   if (c->ws_owned) (void)hipFree(c->ws);
   if (c->side) (void)hipStreamDestroy(c->side);
+  for (int i = 0; i < MAX_SPLIT - 2; ++i) {
+    if (c->side_x[i]) (void)hipStreamDestroy(c->side_x[i]);
+    if (c->join_x[i]) (void)hipEventDestroy(c->join_x[i]);
+  }
   for (hipEvent_t e : c->pipe_ev)
     if (e) (void)hipEventDestroy(e);
   if (c->fork_ev) (void)hipEventDestroy(c->fork_ev);
@@ -1097,6 +1110,12 @@ int he_ctx_set_tuning(he_ctx* c, const char* knob, int level, int value) {
     c->split_streams = value;
     return HE_OK;
   }
+  if (std::strcmp(knob, "split_parts") == 0) {
+    if (value < 2 || value > MAX_SPLIT)
+      return fail(c, HE_EINVAL, "he_ctx_set_tuning: split_parts is 2..%d", MAX_SPLIT);
+    c->split_parts = value;
+    return HE_OK;
+  }
   if (std::strcmp(knob, "hoist_pipeline") == 0) {
     if (value < 0 || value > 1) return fail(c, HE_EINVAL, "he_ctx_set_tuning: hoist_pipeline is 0 or 1");
     c->hoist_pipeline = value;
@@ -1125,6 +1144,7 @@ int he_ctx_set_tuning(he_ctx* c, const char* knob, int level, int value) {
 int he_ctx_get_tuning(const he_ctx* c, const char* knob, int level) {
   if (!c || !knob) return HE_EINVAL;
   if (std::strcmp(knob, "split_streams") == 0) return c->split_streams;
+  if (std::strcmp(knob, "split_parts") == 0) return c->split_parts;
   if (std::strcmp(knob, "hoist_fused") == 0) return c->hoist_fused;
   if (std::strcmp(knob, "hoist_pipeline") == 0) return c->hoist_pipeline;
   if (std::strcmp(knob, "modup_halves") == 0) {

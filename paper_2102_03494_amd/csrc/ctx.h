@@ -28,6 +28,9 @@ constexpr int STAGE_SLOTS = 64;
 
 using namespace he;
 
+// Most chains (one stream each) a DensePack rotate-and-sum is split into.
+constexpr int MAX_SPLIT = 4;
+
 struct he_ctx {
   int n = 0, logn = 0, big_l = 0;
   std::vector<u64> moduli;  // q_0..q_{L-1}, P
@@ -46,7 +49,8 @@ struct he_ctx {
   u64* d_inv = nullptr;   // [2][HE_MAXM][HE_MAXM]: m_div^-1 mod q_t and Shoup components
   Tables tb() const { return Tables{d_tw, d_tw32, d_twf, d_twh, d_twh32, d_twhf}; }
   int pg_set[HE_MAXM + 1] = {};  // P groups per key-switch level (0 = cost model)
-  int split_streams = 1;         // DensePack rotate-and-sum in two halves on two streams
+  int split_streams = 1;         // DensePack rotate-and-sum split over several streams
+  int split_parts = 2;           // ... into this many chains (2..MAX_SPLIT), one stream each
   int hoist_fused = 0;           // hoisted rotations: ModDown fused with the inner product (measured slower)
   int hoist_pipeline = 0;        // hoisted rotations: inner products and ModDown of chunks on two streams (slower)
   // ModUp as two half-ring workgroups per target, per key-switch level
@@ -67,6 +71,10 @@ struct he_ctx {
   // second stream (default priority) for the other width classes of a launch
   hipStream_t side = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  // further streams (default priority) and their join events for a DensePack
+  // rotate-and-sum split into up to MAX_SPLIT chains
+  hipStream_t side_x[MAX_SPLIT - 2] = {};
+  hipEvent_t join_x[MAX_SPLIT - 2] = {};
   hipEvent_t pipe_ev[4] = {};  // one per chunk of a hoisted-rotation pipeline
   StageSlot stage[STAGE_SLOTS];
   int stage_next = 0;
@@ -151,6 +159,15 @@ struct Arena {
     return p;
   }
   size_t left() const { return cap - used; }
+  // The remaining space split into k disjoint arenas of about 1/k each.
+  void split(int k, Arena* out) const {
+    const size_t part = (left() / (size_t)k) & ~(size_t)255;
+    for (int i = 0; i < k; ++i) {
+      out[i] = *this;
+      out[i].used = used + (size_t)i * part;
+      out[i].cap = (i == k - 1) ? cap : used + (size_t)(i + 1) * part;
+    }
+  }
   // The remaining space split into two disjoint arenas of about half each.
   void halves(Arena& lo, Arena& hi) const {
     const size_t mid = used + ((left() / 2) & ~(size_t)255);

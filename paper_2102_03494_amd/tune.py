@@ -8,13 +8,14 @@ Knobs (none changes a result bit; all are GPU-tested for that):
   lift) and the number of workgroups sharing the P target ("p_groups", the
   limb grouping: with P in a costlier width class, one P workgroup per
   ciphertext would finish long after the others);
-* per ring, whether a DensePack layer runs its rotate-and-sum as two halves
-  on two streams ("split_streams").
+* per ring, whether a DensePack layer runs its rotate-and-sum as several
+  chains on as many streams ("split_streams"), and into how many (2 to 4,
+  "split_parts").
 
 `tune()` times one batched rotate-and-add step over `batch` ciphertexts at
 every level for every (modup_halves, p_groups) pair, then a DensePack layer
-of `layer_outputs` dot products with split_streams 0 and 1, and keeps the
-fastest.  `apply()` loads the cached choice for a context's ring into the
+of `layer_outputs` dot products unsplit and split into 2, 3 and 4 chains,
+and keeps the fastest.  `apply()` loads the cached choice for a context's ring into the
 library (he_ctx_set_tuning); HEContext does that at creation.  The cache is
 `tuning_cache.json` beside this file, keyed by ring dimension and prime
 sizes; every entry records the hash of the kernel sources it was measured
@@ -94,6 +95,8 @@ def apply(ctx, path: str = CACHE) -> str:
             ctx.set_tuning("modup_halves", int(level), int(hv))
     if "split_streams" in entry:
         ctx.set_tuning("split_streams", 0, int(entry["split_streams"]))
+    if "split_parts" in entry:
+        ctx.set_tuning("split_parts", 0, int(entry["split_parts"]))
     return "cache"
 
 
@@ -101,7 +104,8 @@ def chosen(ctx) -> dict:
     """The knob values in effect on ctx, per level."""
     return {"p_groups": {lv: ctx.get_tuning("p_groups", lv) for lv in range(1, ctx.L + 1)},
             "modup_halves": {lv: ctx.get_tuning("modup_halves", lv) for lv in range(1, ctx.L + 1)},
-            "split_streams": ctx.get_tuning("split_streams", 0)}
+            "split_streams": ctx.get_tuning("split_streams", 0),
+            "split_parts": ctx.get_tuning("split_parts", 0)}
 
 
 def _time(fn, reps, torch):
@@ -116,9 +120,9 @@ def _time(fn, reps, torch):
 
 def tune(ctx, batch: int = 288, reps: int = 8, levels=None, layer_outputs: int = 288) -> dict:
     """Fastest (modup_halves, p_groups) per level for one rotate-and-add step
-    over `batch` ciphertexts, then split_streams for a DensePack layer of
-    `layer_outputs` dot products (uniform random residues: timing does not
-    depend on them)."""
+    over `batch` ciphertexts, then (split_streams, split_parts) for a
+    DensePack layer of `layer_outputs` dot products (uniform random residues:
+    timing does not depend on them)."""
     import math
 
     import numpy as np
@@ -163,13 +167,16 @@ def tune(ctx, batch: int = 288, reps: int = 8, levels=None, layer_outputs: int =
     total = side * side * desc.o_c
     ctx.reserve(ctx.workspace_need(total, level))
     split_t = {}
-    for sp in (0, 1):
+    for sp, parts in ((0, 2), (1, 2), (1, 3), (1, 4)):
         ctx.set_tuning("split_streams", 0, sp)
-        split_t[sp] = _time(lambda: ctx.conv_densepack(x, desc, filt, 1.0), max(2, reps // 2), torch)
-    best_sp = min(split_t, key=split_t.get)
-    ctx.set_tuning("split_streams", 0, best_sp)
-    out["split_streams"] = {"best": best_sp, "ms": split_t, "outputs": total}
-    print(f"# split_streams: {split_t} -> {best_sp}", file=sys.stderr, flush=True)
+        ctx.set_tuning("split_parts", 0, parts)
+        split_t[(sp, parts)] = _time(lambda: ctx.conv_densepack(x, desc, filt, 1.0), max(2, reps // 2), torch)
+    best = min(split_t, key=split_t.get)
+    ctx.set_tuning("split_streams", 0, best[0])
+    ctx.set_tuning("split_parts", 0, best[1])
+    out["split_streams"] = {"best": best[0], "parts": best[1], "outputs": total,
+                            "ms": {("1" if sp == 0 else str(parts)): t for (sp, parts), t in split_t.items()}}
+    print(f"# split (chains: ms): {out['split_streams']['ms']} -> {best}", file=sys.stderr, flush=True)
     return out
 
 
@@ -178,8 +185,9 @@ def entry_of(res: dict, batch: int) -> dict:
     return {"p_groups": {str(k): v["p_groups"] for k, v in lv.items()},
             "modup_halves": {str(k): v["modup_halves"] for k, v in lv.items()},
             "split_streams": res["split_streams"]["best"],
+            "split_parts": res["split_streams"]["parts"],
             "ms_per_step": {str(k): {kk: round(t, 4) for kk, t in v["ms"].items()} for k, v in lv.items()},
-            "split_ms_per_layer": {str(k): round(t, 4) for k, t in res["split_streams"]["ms"].items()},
+            "split_ms_per_layer": {k: round(t, 4) for k, t in res["split_streams"]["ms"].items()},
             "batch": batch, "device": _device_name(), "kernel_sha256": kernel_sha256()}
 
 

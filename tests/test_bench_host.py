@@ -50,3 +50,18 @@ def test_modup_ops_scale_with_jobs_and_grouping(pg):
         expect = base - 2 * (bfly * bench.COST["bfly"][c] + N * bench.COST["fin"][c]) \
             + (groups - 1) * 2 * N * bench.COST["fin"][c]
         assert one == pytest.approx(expect)
+
+
+def test_dp_hma_bytes_count_rows():
+    level, n = 4, N
+    row32, row64 = 4 * n, 8 * n
+    # one input ciphertext and two base filters read as 64-bit rows; 288
+    # products of two polynomials written as packed narrow rows
+    packed = bench.dp_hma_bytes(288, 1, 2, level, n, MODULI)
+    assert packed == (2 + 2) * level * row64 + 288 * 2 * level * row32
+    # unpacked products take 64-bit words
+    assert bench.dp_hma_bytes(288, 1, 2, level, n, MODULI, packed_out=False) - packed == \
+        288 * 2 * level * (row64 - row32)
+    # a 40-bit limb is never packed
+    wide = [(1 << 40) - 87] * 2 + MODULI[-1:]
+    assert bench.dp_hma_bytes(1, 1, 1, 2, n, wide) == 3 * 2 * row64 + 2 * 2 * row64

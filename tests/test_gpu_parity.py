@@ -279,7 +279,8 @@ def test_p_groups_do_not_change_bits():
 
 
 def test_split_streams_do_not_change_bits():
-    """DensePack with its outputs in two halves on two streams gives the one-stream bits."""
+    """DensePack with its outputs split into 2, 3 or 4 chains on as many
+    streams gives the one-stream bits."""
     p, octx, gctx, cl = _small_setup(rotations=[1 << j for j in range(9)])
     geom = C.ConvGeom(9, 9, 2, 3, 1, 1)
     x = synth.image(W, (9, 9, 2), index=3)
@@ -290,16 +291,22 @@ def test_split_streams_do_not_change_bits():
     he = _he()
     desc = he.HEContext.conv_desc(9, 9, 2, 3, 1, 1, 2, 9)
     outs = {}
-    for split in (0, 1):
+    for split, parts in ((0, 2), (1, 2), (1, 3), (1, 4)):
         gctx.set_tuning("split_streams", 0, split)
-        assert gctx.get_tuning("split_streams", 0) == split
-        outs[split] = _host(gctx.conv_densepack(he.Ct(_dev(ct.c[None]), p.scale), desc, _dev(bf), pts).data)
-    assert outs[0].shape[0] == 162  # 81 outputs x 2 channels: split into halves of 81
-    assert np.array_equal(outs[0], outs[1])
-    sample = [0, 80, 81, 161]
+        gctx.set_tuning("split_parts", 0, parts)
+        assert gctx.get_tuning("split_streams", 0) == split and gctx.get_tuning("split_parts", 0) == parts
+        outs[split, parts] = _host(gctx.conv_densepack(he.Ct(_dev(ct.c[None]), p.scale), desc, _dev(bf), pts).data)
+    gctx.set_tuning("split_parts", 0, 2)
+    for bad in (1, 5):
+        with pytest.raises(he.HEError):
+            gctx.set_tuning("split_parts", 0, bad)
+    assert outs[0, 2].shape[0] == 162  # 81 outputs x 2 channels: chains of 81, 54 or 40-41
+    for key in ((1, 2), (1, 3), (1, 4)):
+        assert np.array_equal(outs[0, 2], outs[key]), key
+    sample = [0, 40, 41, 80, 81, 108, 161]
     want, _ = C.conv_densepack(p, octx, ct, geom, bf, pts, outputs=[C.output_list(geom, 2)[i] for i in sample])
     for k, i in enumerate(sample):
-        assert np.array_equal(outs[1][i], want.c[k]), i
+        assert np.array_equal(outs[1, 4][i], want.c[k]), i
 
 
 @pytest.mark.parametrize("chain", [None, SMALL40], ids=["30bit", "40bit"])

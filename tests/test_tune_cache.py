@@ -40,6 +40,7 @@ def test_committed_cache_entries_are_legal():
         assert key.startswith("n") and "_q" in key and "_p" in key
         assert len(entry["kernel_sha256"]) == 64
         assert entry["split_streams"] in (0, 1)
+        assert entry.get("split_parts", 2) in (2, 3, 4)
         for level, pg in entry["p_groups"].items():
             hv = entry["modup_halves"][level]
             assert 1 <= pg <= min(int(level), 4) and hv in (0, 1)
