@@ -1585,14 +1585,17 @@ __device__ __forceinline__ void dp_hma_body(const u64* __restrict__ x, const u64
   }
 }
 
-template <int LOGN>
+// One instance per width class (limbs of other classes exit at once): the
+// narrow one declares half the LDS, so twice the workgroups fit a CU.
+template <int LOGN, int CLS>
 __global__ void __launch_bounds__(NttGeom<LOGN>::T)
 k_dp_hma(const u64* __restrict__ x, const u64* __restrict__ filt, u64* __restrict__ out, int level, int out_base,
          DPGeom geo, Mods mods, int out_packed) {
-  __shared__ u64 lds[NttGeom<LOGN>::LDS];
+  constexpr bool NARROW = CLS == CLS_N32;
+  __shared__ u64 lds[lds_words<LOGN, NARROW ? CLS_N32 : CLS_U64>()];
   const ModConst m = mods.m[blockIdx.x];
-  if (m.narrow) dp_hma_body<LOGN, true>(x, filt, out, level, out_base, geo, m, lds, out_packed);
-  else dp_hma_body<LOGN, false>(x, filt, out, level, out_base, geo, m, lds, out_packed);
+  if ((int)m.cls != CLS) return;
+  dp_hma_body<LOGN, NARROW>(x, filt, out, level, out_base, geo, m, lds, out_packed);
 }
 
 // Sum of permuted-plaintext products into one accumulator per blockIdx.z:

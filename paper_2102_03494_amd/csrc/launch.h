@@ -170,8 +170,8 @@ template <int LOGN>
 void LDpHma<LOGN>::run(he_ctx* c, const u64* x, const u64* filt, u64* out, int level, int out_base, int n_out,
                   const DPGeom& geo, hipStream_t s, bool out_packed) {
   Prof pr(c, "dp_hma", s);
-  k_dp_hma<LOGN><<<dim3(level, n_out), NttGeom<LOGN>::T, 0, s>>>(x, filt, out, level, out_base, geo, c->mods,
-                                                                (int)out_packed);
+  HE_FOR_CLASSES(c->q_mask, (k_dp_hma<LOGN, CLS><<<dim3(level, n_out), NttGeom<LOGN>::T, 0, s>>>(
+                                 x, filt, out, level, out_base, geo, c->mods, (int)out_packed)));
 }
 
 template <int LOGN>
