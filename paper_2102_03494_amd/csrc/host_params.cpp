@@ -123,7 +123,7 @@ ModConst make_modconst(u64 q, int n) {
   m.r64 = (u64)(((u128)1 << 64) % q);
   m.r64_sh = shoup_companion(m.r64, q);
   m.cls = (u32)width_class(q);
-  m.pad_ = 0;
+  m.r32_sh = is_narrow(q) ? (u32)shoup_companion(((u64)1 << 32) % q, q) : 0u;
   m.qd = (double)q;
   m.qinv = 1.0 / (double)q;
   m.n_inv_q = (double)m.n_inv / (double)q;

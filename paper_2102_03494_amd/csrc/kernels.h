@@ -456,14 +456,15 @@ __device__ __forceinline__ void modup_ip_body(u64* lds, const u64* __restrict__ 
     p_limb_to_coeffs<LOGN, CLS, E>(lds, acc1, rc_p + N, mi, m, tb);
     return;
   }
+  const bool lazy = mi != big_l;  // ciphertext-prime rows in [0, 2q) (reduce64_lazy32)
   u64* u0 = u + ((b * 2 + 0) * urows + row) * N;
   u64* u1 = u + ((b * 2 + 1) * urows + row) * N;
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int i = (int)threadIdx.x + r * T;
     if constexpr (CLS == CLS_N32) {  // packed row
-      reinterpret_cast<u32*>(u0)[i] = (u32)reduce64(acc0[r], m);
-      reinterpret_cast<u32*>(u1)[i] = (u32)reduce64(acc1[r], m);
+      reinterpret_cast<u32*>(u0)[i] = lazy ? reduce64_lazy32(acc0[r], m) : (u32)reduce64(acc0[r], m);
+      reinterpret_cast<u32*>(u1)[i] = lazy ? reduce64_lazy32(acc1[r], m) : (u32)reduce64(acc1[r], m);
     } else if constexpr (CLS == CLS_F64) {
       u0[i] = to_canon<CLS>(acc0[r], m);
       u1[i] = to_canon<CLS>(acc1[r], m);
@@ -563,13 +564,14 @@ __device__ __forceinline__ void modup_ip_narrow_staged(u64* lds, u32* S, const u
     p_limb_to_coeffs<LOGN, CLS, E>(lds, acc1, rc_p + N, mi, m, tb);
     return;
   }
+  const bool lazy = mi != big_l;  // ciphertext-prime rows in [0, 2q) (reduce64_lazy32)
   u64* u0 = u + ((b * 2 + 0) * urows + row) * N;
   u64* u1 = u + ((b * 2 + 1) * urows + row) * N;
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int i = (int)threadIdx.x + r * T;
-    reinterpret_cast<u32*>(u0)[i] = (u32)reduce64(acc0[r], m);
-    reinterpret_cast<u32*>(u1)[i] = (u32)reduce64(acc1[r], m);
+    reinterpret_cast<u32*>(u0)[i] = lazy ? reduce64_lazy32(acc0[r], m) : (u32)reduce64(acc0[r], m);
+    reinterpret_cast<u32*>(u1)[i] = lazy ? reduce64_lazy32(acc1[r], m) : (u32)reduce64(acc1[r], m);
   }
 }
 
@@ -818,14 +820,15 @@ __device__ __forceinline__ void modup_ip_half_body(u64* lds, const u64* __restri
     }
     __syncthreads();
   }
+  const bool lazy = mi != big_l;  // ciphertext-prime rows in [0, 2q) (reduce64_lazy32)
   u64* u0 = u + ((b * 2 + 0) * urows + row) * N;
   u64* u1 = u + ((b * 2 + 1) * urows + row) * N;
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int i = (int)hoff + (int)threadIdx.x + r * T;
     if constexpr (CLS == CLS_N32) {  // packed row
-      reinterpret_cast<u32*>(u0)[i] = (u32)reduce64(acc0[r], m);
-      reinterpret_cast<u32*>(u1)[i] = (u32)reduce64(acc1[r], m);
+      reinterpret_cast<u32*>(u0)[i] = lazy ? reduce64_lazy32(acc0[r], m) : (u32)reduce64(acc0[r], m);
+      reinterpret_cast<u32*>(u1)[i] = lazy ? reduce64_lazy32(acc1[r], m) : (u32)reduce64(acc1[r], m);
     } else if constexpr (CLS == CLS_F64) {
       u0[i] = to_canon<CLS>(acc0[r], m);
       u1[i] = to_canon<CLS>(acc1[r], m);
@@ -903,13 +906,14 @@ __device__ __forceinline__ void modup_ip_half_narrow_staged(u64* lds, u32* S, co
     }
     lds_barrier();  // the copies of the next digit overwrite S
   }
+  const bool lazy = mi != big_l;  // ciphertext-prime rows in [0, 2q) (reduce64_lazy32)
   u64* u0 = u + ((b * 2 + 0) * urows + row) * N;
   u64* u1 = u + ((b * 2 + 1) * urows + row) * N;
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int i = hoff + (int)threadIdx.x + r * T;
-    reinterpret_cast<u32*>(u0)[i] = (u32)reduce64(acc0[r], m);
-    reinterpret_cast<u32*>(u1)[i] = (u32)reduce64(acc1[r], m);
+    reinterpret_cast<u32*>(u0)[i] = lazy ? reduce64_lazy32(acc0[r], m) : (u32)reduce64(acc0[r], m);
+    reinterpret_cast<u32*>(u1)[i] = lazy ? reduce64_lazy32(acc1[r], m) : (u32)reduce64(acc1[r], m);
   }
 }
 

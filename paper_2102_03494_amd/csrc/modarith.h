@@ -36,7 +36,7 @@ struct ModConst {
   u64 r64;     // 2^64 mod q (folds the high word of a 128-bit sum)
   u64 r64_sh;
   u32 cls;     // width class (CLS_*)
-  u32 pad_;
+  u32 r32_sh;  // narrow: Shoup companion of 2^32 mod q (else 0)
   double qd;       // q as a double (exact for q < 2^53)
   double qinv;     // 1 / q rounded to double
   double n_inv_q;  // n_inv / q rounded to double (f64 Shoup-style companion)
@@ -150,6 +150,24 @@ __host__ __device__ inline u64 reduce64(u64 v, const ModConst& m) {
   u64 qh = mulhi64(v, m.mu64);
   u64 r = v - qh * m.q;
   return r >= m.q ? r - m.q : r;
+}
+
+// A 64-bit sum of products of narrow residues reduced to [0, 2q) in 32-bit
+// arithmetic (q < 2^30): the high word through r = 2^32 mod q by a Shoup
+// product (companion m.r32_sh), the low word by Barrett with floor(2^32 / q)
+// (the high word of m.mu64); each part lands in [0, 2q), their sum below 4q.
+// ModDown reads the ciphertext-prime rows of u in this form (its subtraction
+// and Shoup product take inputs below 2q); the P row stays canonical.
+__host__ __device__ inline u32 reduce64_lazy32(u64 a, const ModConst& m) {
+  const u32 q = (u32)m.q;
+  const u32 mu32 = (u32)(m.mu64 >> 32);
+  const u32 r32 = 0u - mu32 * q;  // 2^32 - floor(2^32 / q) q
+  const u32 hi = (u32)(a >> 32), lo = (u32)a;
+  const u32 x = hi * r32 - (u32)(((u64)hi * m.r32_sh) >> 32) * q;
+  const u32 y = lo - (u32)(((u64)lo * mu32) >> 32) * q;
+  const u32 s = x + y;
+  const u32 t = s - 2 * q;
+  return t < s ? t : s;
 }
 
 // Centred representative of v (a residue mod qs, qs odd) reduced mod m.

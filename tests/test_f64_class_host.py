@@ -29,3 +29,16 @@ def test_f64_class_exact(tmp_path):
     assert res.returncode == 0, res.stderr
     run = subprocess.run([exe], capture_output=True, text=True, timeout=300)
     assert run.returncode == 0 and run.stdout.startswith("OK"), run.stdout + run.stderr
+
+
+@pytest.mark.skipif(not os.path.exists(HIPCC) and shutil.which("hipcc") is None, reason="hipcc not available")
+def test_narrow_lazy_reduction(tmp_path):
+    """reduce64_lazy32 (ModUp's store of narrow inner-product rows) lands
+    below 2q and congruent to its 64-bit input, against exact remainders."""
+    exe = str(tmp_path / "narrow_reduce_check")
+    cmd = [HIPCC if os.path.exists(HIPCC) else "hipcc", "-O2", "-std=c++17", "-x", "c++", "-D__HIP_PLATFORM_AMD__",
+           "-I/opt/rocm/include", os.path.join(HERE, "host", "narrow_reduce_check.cpp"), "-o", exe]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    assert res.returncode == 0, res.stderr
+    run = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+    assert run.returncode == 0 and run.stdout.startswith("OK"), run.stdout + run.stderr
