@@ -45,11 +45,11 @@ DOMINANT = "ks_modup_stage"
 # valid only for the kernel sources they were measured on: bench.py reports
 # them when these sources hash to KERNEL_SHA256, else null.
 KERNEL_SOURCES = ("modarith.h", "ntt_lds.h", "kernels.h", "capi.hip")
-KERNEL_SHA256 = "19ddcaa58fbc3da508bbd909c2e6171855cc1611274c9ba2cab9ee1a0a73cfa9"
+KERNEL_SHA256 = "a9abb2ea8d140e7fed2fab373033b63ea25640a925666d7d23a5e0de1714f9e6"
 # ks_modup_stage: mean over one layer's 25 launches (24 of 144 jobs at
-# 124.9 MB, one relinearisation launch of 5 jobs at 6.3 MB); ip_perm: one
-# launch over all 256 rotations
-TRAFFIC_BYTES = {"ks_modup_stage": 120195144, "ip_perm": 4454178755}
+# 123.1 MB, one relinearisation launch of 5 jobs at 6.3 MB); ip_perm: one
+# launch over all 256 rotations; dp_hma: the one MulPC launch of a layer
+TRAFFIC_BYTES = {"ks_modup_stage": 118423921, "ip_perm": 4454978538, "dp_hma": 77746600}
 
 
 def kernel_sha256() -> str:
