@@ -125,7 +125,11 @@ const char *he_last_error(const he_ctx *ctx);
  * key-switch level `level` (0: every level; -1 restores the default, which is
  * 1 for N >= 8192, else 0): 1 runs ModUp as two half-ring workgroups per
  * target (N >= 2048; a launch follows its largest level), 0 as one workgroup
- * per target.  knob "hoist_fused" (level ignored; 0 by default, 0 or 1): in
+ * per target.  knob "moddown_halves" (level ignored; -1 restores the default,
+ * which is 1 for N >= 16384, else 0): 1 runs a key switch's ModDown as two
+ * half-ring workgroups per output limb (N >= 2048; not inside rotate-and-sum
+ * chains that keep packed accumulators or write the next step's digits),
+ * 0 as one.  knob "hoist_fused" (level ignored; 0 by default, 0 or 1): in
  * he_rotate_hoisted, compute each rotation's inner-product rows inside its
  * ModDown (1) or write them to the workspace first (0).  knob
  * "hoist_pipeline" (level ignored; 0 by default, 0 or 1): hoisted rotations

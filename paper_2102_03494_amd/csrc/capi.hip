@@ -1110,6 +1110,13 @@ int he_ctx_set_tuning(he_ctx* c, const char* knob, int level, int value) {
     c->split_streams = value;
     return HE_OK;
   }
+  if (std::strcmp(knob, "moddown_halves") == 0) {
+    if (value < -1 || value > 1) return fail(c, HE_EINVAL, "he_ctx_set_tuning: moddown_halves is -1, 0 or 1");
+    if (value == 1 && c->logn < HALF_MODUP_ANY_LOGN)
+      return fail(c, HE_EINVAL, "he_ctx_set_tuning: moddown_halves needs N >= %d", 1 << HALF_MODUP_ANY_LOGN);
+    c->moddown_halves = value;
+    return HE_OK;
+  }
   if (std::strcmp(knob, "split_parts") == 0) {
     if (value < 2 || value > MAX_SPLIT)
       return fail(c, HE_EINVAL, "he_ctx_set_tuning: split_parts is 2..%d", MAX_SPLIT);
@@ -1145,6 +1152,8 @@ int he_ctx_get_tuning(const he_ctx* c, const char* knob, int level) {
   if (!c || !knob) return HE_EINVAL;
   if (std::strcmp(knob, "split_streams") == 0) return c->split_streams;
   if (std::strcmp(knob, "split_parts") == 0) return c->split_parts;
+  if (std::strcmp(knob, "moddown_halves") == 0)
+    return c->moddown_halves < 0 ? (c->logn >= HALF_MODDOWN_MIN_LOGN ? 1 : 0) : c->moddown_halves;
   if (std::strcmp(knob, "hoist_fused") == 0) return c->hoist_fused;
   if (std::strcmp(knob, "hoist_pipeline") == 0) return c->hoist_pipeline;
   if (std::strcmp(knob, "modup_halves") == 0) {

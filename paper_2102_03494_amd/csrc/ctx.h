@@ -51,6 +51,7 @@ struct he_ctx {
   int pg_set[HE_MAXM + 1] = {};  // P groups per key-switch level (0 = cost model)
   int split_streams = 1;         // DensePack rotate-and-sum split over several streams
   int split_parts = 2;           // ... into this many chains (2..MAX_SPLIT), one stream each
+  int moddown_halves = -1;       // ModDown as two half-ring workgroups per limb (-1: from N = 16384)
   int hoist_fused = 0;           // hoisted rotations: ModDown fused with the inner product (measured slower)
   int hoist_pipeline = 0;        // hoisted rotations: inner products and ModDown of chunks on two streams (slower)
   // ModUp as two half-ring workgroups per target, per key-switch level

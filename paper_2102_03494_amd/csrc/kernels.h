@@ -1226,6 +1226,114 @@ k_drop_last(const KsJob* __restrict__ jobs, int count, int kmax, const u64* __re
                                                           mods, tb, nd);
 }
 
+// ModDown (MODE_P) in halves: workgroup (job b, polynomial comp, kept prime
+// t, half h) computes the entries h N/2 .. (h + 1) N/2 - 1 of the output
+// limb exactly as drop_last_body does for the whole limb.  The lifted P
+// limb's first forward stage is fused into the lift (lift_half) and the rest
+// is an N/2-point transform with the half's twiddles, as in
+// k_ks_modup_half; a rotation's sigma_g(c0) comes from one source half
+// (load_half_perm).  Every Galois element here is a power of 5 (1 mod 4),
+// which maps each half onto itself, so an in-place rotate-and-add reads and
+// writes only its own half.  Unpacked ciphertexts, no next-step digits.  With
+// 8 entries per thread a 16384-point ring gets 1024-thread workgroups with
+// half the LDS of the whole-limb kernel: two per CU, twice its waves.
+// grid xcd_grid(4 Kmax, count).
+constexpr int HALF_MODDOWN_MIN_LOGN = 14;  // default: halves from N = 16384
+template <int LOGN>
+constexpr int drop_half_threads() {
+  return (1 << (LOGN - 1)) / 8;
+}
+template <int LOGN, int EPI, int CLS>
+__global__ void __launch_bounds__(drop_half_threads<LOGN>())
+k_drop_half(const KsJob* __restrict__ jobs, int count, int kmax, const u64* __restrict__ u, int urows, int big_l,
+            const u64* __restrict__ rcoef, const u64* __restrict__ inv_tab, Mods mods, Tables tb) {
+  constexpr int E = 8;
+  constexpr bool NW = CLS == CLS_N32;
+  typedef std::conditional_t<NW, u32, u64> V;
+  constexpr int N = 1 << LOGN;
+  constexpr int NH = N / 2;
+  constexpr int T = NH / E;
+  constexpr int PC = NW ? CLS_N32 : CLS_U64;  // word of sigma_g(c0) in LDS
+  __shared__ u64 lds[lds_words<LOGN - 1, CLS>()];
+  const XcdSlot sl = xcd_slot(4 * kmax);
+  if (sl.job >= count) return;
+  const size_t b = sl.job;
+  const int h = sl.sub & 1;
+  const int comp = (sl.sub >> 1) / kmax;
+  const int t = (sl.sub >> 1) - comp * kmax;
+  const KsJob jb = jobs[b];
+  const int level = jb.level;
+  if (t >= level) return;
+  const ModConst m = mods.m[t];
+  if ((int)m.cls != CLS) return;
+  const int hoff = h * NH;
+  u64* o = jb.out + ((size_t)comp * level + t) * N;
+  const u64* cs = jb.c + ((size_t)comp * level + t) * N;
+  if (jb.key == nullptr) {  // identity job
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int i = hoff + (int)threadIdx.x + r * T;
+      u64 x = cs[i];
+      if constexpr (EPI == EPI_ROTSUM) x = addm<NW>(x, x, m.q);
+      o[i] = x;
+    }
+    return;
+  }
+  const Tw<CLS> tw0 = tw_of<LOGN, CLS>(tb, t, 0);
+  lift_half<LOGN, CLS, E>(lds, rcoef + (b * 2 + comp) * N, mods.m[big_l].q, m, h, tw0.w[1],
+                          CLS == CLS_F64 ? word_t<CLS>(0) : tw0.sh[1], opaque_tid());
+  ntt_fwd_lds<LOGN - 1, CLS, E>(lds, tw_half_of<LOGN, CLS>(tb, t, h), mview<CLS>(m), opaque_tid());
+  const u64* s = u + ((b * 2 + comp) * urows + t) * N;
+  const u64 iv = inv_tab[big_l * HE_MAXM + t];
+  const u64 ivs = inv_tab[HE_MAXM * HE_MAXM + big_l * HE_MAXM + t];
+  const int tid = opaque_tid();
+  const int i0 = lds_idx(tid);
+  V val[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int i = hoff + tid + r * T;
+    const int li = lds_step(i0, r, T);
+    const u64 sv = NW ? (u64)reinterpret_cast<const u32*>(s)[i] : s[i];  // narrow u rows are packed
+    if constexpr (CLS == CLS_F64) {
+      const double dlt = f64_from_u64(sv) - lds_getw_at<CLS>(lds, li);
+      val[r] = to_canon<CLS>(f64_mulmod(dlt, f64_from_u64(iv), m.qd, m.qinv), m);
+    } else {
+      val[r] = (V)shoupm<NW>(subm<NW>(sv, to_canon<CLS>(lds_getw_at<CLS>(lds, li), m), m.q), iv, ivs, m.q);
+    }
+  }
+  if constexpr (EPI == EPI_STORE) {
+#pragma unroll
+    for (int r = 0; r < E; ++r) o[hoff + tid + r * T] = val[r];
+  } else if constexpr (EPI == EPI_RELIN) {
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int i = hoff + tid + r * T;
+      o[i] = addm<NW>(cs[i], val[r], m.q);
+    }
+  } else if (comp == 0) {  // EPI_ROT / EPI_ROTSUM: sigma_g(c0) through LDS
+    V own[E];
+    if constexpr (EPI == EPI_ROTSUM) {
+#pragma unroll
+      for (int r = 0; r < E; ++r) own[r] = (V)cs[hoff + tid + r * T];
+    }
+    __syncthreads();  // everyone is done reading the transform
+    load_half_perm<LOGN, PC, E>(lds, cs, jb.ginv, false, h);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      u64 x = addm<NW>((u64)lds_getw_at<PC>(lds, lds_step(i0, r, T)), val[r], m.q);  // sigma_g(c0) + u0
+      if constexpr (EPI == EPI_ROTSUM) x = addm<NW>(x, own[r], m.q);
+      o[hoff + tid + r * T] = x;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int i = hoff + tid + r * T;
+      o[i] = (EPI == EPI_ROTSUM) ? addm<NW>(cs[i], val[r], m.q) : (u64)val[r];
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Hoisted rotations of one ciphertext.
 // ModUp once: dhat[j][t] = NTT(lift(digit_j) mod m_t) for j < level,

@@ -130,6 +130,23 @@ void LDrop<LOGN>::run(he_ctx* c, int mode, int epi, const KsJob* jobs, int count
   const int keep = mode == MODE_P ? lmax : lmax - 1;
   const unsigned grid = xcd_grid(2 * keep, count);
   Prof pr(c, "drop_last", s);
+  if constexpr (LOGN >= HALF_MODUP_ANY_LOGN) {
+    // ModDown in halves (k_drop_half): unpacked ciphertexts, no next-step digits
+    const bool halves = c->moddown_halves < 0 ? LOGN >= HALF_MODDOWN_MIN_LOGN : c->moddown_halves != 0;
+    if (halves && mode == MODE_P && pk == 0 && nd.dcoef == nullptr) {
+      const unsigned hgrid = xcd_grid(4 * keep, count);
+      constexpr int TH = drop_half_threads<LOGN>();
+#define HE_DROP_HALF(EP)                                                                                        \
+  HE_FOR_CLASSES(c->q_mask, (k_drop_half<LOGN, EP, CLS><<<hgrid, TH, 0, s>>>(jobs, count, keep, u, urows, c->big_l, \
+                                                                             rc, c->d_inv, c->mods, c->tb())))
+      if (epi == EPI_ROT) HE_DROP_HALF(EPI_ROT);
+      else if (epi == EPI_ROTSUM) HE_DROP_HALF(EPI_ROTSUM);
+      else if (epi == EPI_RELIN) HE_DROP_HALF(EPI_RELIN);
+      else HE_DROP_HALF(EPI_STORE);
+#undef HE_DROP_HALF
+      return;
+    }
+  }
 #define HE_DROP(MD, EP, PK)                                                                                    \
 HE_FOR_CLASSES(c->q_mask, (k_drop_last<LOGN, MD, EP, CLS, PK><<<grid, T, 0, s>>>(jobs, count, keep, u, urows,  \
                                                                                  c->big_l, rc, c->d_inv, c->mods, \

@@ -192,6 +192,41 @@ def test_modup_halves_knob_bit_exact(n, q_bits, p_bits):
             assert np.array_equal(_host(gctx.rotate(he.Ct(_dev(cts), 1.0), 3).data), want), (halves, pg)
 
 
+@pytest.mark.parametrize("n,q_bits,p_bits", [(2048, (30,) * 4, 40), (4096, (40,) * 3, 60)])
+def test_moddown_halves_knob_bit_exact(n, q_bits, p_bits):
+    """ModDown as one workgroup per limb or as two half-ring workgroups gives
+    the oracle's bits: rotations, an in-place rotate-and-sum (packed chains
+    keep the whole-limb kernel, so the narrow chain checks that path), hoisted
+    rotations and x^2 with relinearisation."""
+    p = P.Params(n, q_bits, p_bits, 2.0**25)
+    steps = [1 << j for j in range(5)]
+    octx = Wk.make_context(p, W, rotations=steps + [3], relin=True)
+    gctx = _ctx(p, ws=1 << 27)
+    _client(gctx, steps + [3], True)
+    he = _he()
+    level = len(q_bits)
+    cts = np.stack([np.stack([np.stack([synth.rng(W, "test", 970 + i, c, t).integers(0, p.q[t], n, dtype=np.uint64)
+                                        for t in range(level)]) for c in range(2)]) for i in range(3)])
+    ct = S.Ciphertext(cts, p.scale)
+    want_rot = S.rotate(p, octx, ct, 3).c
+    want_sum = C.rotate_and_sum(p, octx, ct, 5, C.Counts()).c
+    want_hoist = [S.rotate(p, octx, S.Ciphertext(cts[:1], p.scale), k).c for k in (1, 3)]
+    want_sq = S.square(p, octx, ct).c
+    for halves in (0, 1, -1):
+        gctx.set_tuning("moddown_halves", 0, halves)
+        assert gctx.get_tuning("moddown_halves", 0) == (halves if halves >= 0 else 0)
+        assert np.array_equal(_host(gctx.rotate(he.Ct(_dev(cts), p.scale), 3).data), want_rot), halves
+        d = _dev(cts)
+        gctx.rotsum(he.Ct(d, p.scale), 5)
+        assert np.array_equal(_host(d), want_sum), halves
+        hoisted = _host(gctx.rotate_hoisted(he.Ct(_dev(cts[:1]), p.scale), [1, 3]).data)
+        for k in range(2):
+            assert np.array_equal(hoisted[k], want_hoist[k][0]), (halves, k)
+        assert np.array_equal(_host(gctx.square(he.Ct(_dev(cts), p.scale)).data), want_sq), halves
+    with pytest.raises(he.HEError):
+        gctx.set_tuning("moddown_halves", 0, 2)
+
+
 def test_uploaded_oracle_keys_rotate_bit_exact():
     """The server context gets only keys: the oracle makes them on the CPU (the
     client), they are uploaded from host memory in the exchange layout, and
