@@ -982,13 +982,13 @@ enum { MODE_P = 0, MODE_LAST = 1 };
 
 // Coefficient-domain copy of the P limb of u: the sum of its group partials
 // (rows lmax .. lmax + groups - 1, each canonical mod P), INTT, N^-1.
-template <int LOGN, int CLS>
+template <int LOGN, int CLS, int E = 16>
 __device__ __forceinline__ void intt_p_body(u64* lds, const u64* __restrict__ urow, int groups, u64* out, int mi,
                                             const ModConst& m, const Tables& tb) {
   constexpr int N = 1 << LOGN;
-  constexpr int T = NttGeom<LOGN>::T;
+  constexpr int T = NttGeom<LOGN, E>::T;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
+  for (int r = 0; r < E; ++r) {
     const int i = (int)threadIdx.x + r * T;
     u64 v;
     if constexpr (CLS == CLS_N32) {  // packed rows
@@ -1000,8 +1000,34 @@ __device__ __forceinline__ void intt_p_body(u64* lds, const u64* __restrict__ ur
     }
     lds_put<CLS>(lds, i, v);
   }
-  inv_lds<LOGN, CLS>(lds, tb, mi, m);
-  store_limb<LOGN, CLS, true>(out, lds, m, true);
+  inv_lds<LOGN, CLS, E>(lds, tb, mi, m);
+  store_limb<LOGN, CLS, true, E>(out, lds, m, true);
+}
+
+// The P INTT of k_intt_last (MODE_P) with 8 entries per thread: at N <= 8192
+// an f64 or wide P limb takes 64-bit LDS words, two workgroups per CU, so
+// twice the threads per workgroup double the waves that hide the passes'
+// latency.  grid xcd_grid(2, count), N / 8 threads.
+template <int LOGN>
+constexpr int p8_threads() {
+  return NttGeom<LOGN, 8>::T;
+}
+template <int LOGN, int CLS>
+__global__ void __launch_bounds__(p8_threads<LOGN>())
+k_intt_p8(const KsJob* __restrict__ jobs, int count, const u64* __restrict__ u, int lmax, int pg, int big_l,
+          u64* __restrict__ rcoef, Mods mods, Tables tb) {
+  constexpr int N = 1 << LOGN;
+  __shared__ u64 lds[lds_words<LOGN, CLS>()];
+  const XcdSlot sl = xcd_slot(2);
+  if (sl.job >= count) return;
+  const size_t b = sl.job;
+  const int comp = sl.sub;
+  const KsJob jb = jobs[b];
+  if (jb.key == nullptr) return;
+  const ModConst m = mods.m[big_l];
+  if ((int)m.cls != CLS) return;
+  intt_p_body<LOGN, CLS, 8>(lds, u + ((b * 2 + comp) * (lmax + pg) + lmax) * N, pgroup_count(jb.level, pg),
+                            rcoef + (2 * b + comp) * N, big_l, m, tb);
 }
 
 // INTT of the limb that is divided out: for polynomial p = 2 b + comp,

@@ -117,6 +117,13 @@ void LKsCore<LOGN>::run(he_ctx* c, const KsJob* jobs, int count, int lmax, int p
   }
   if (rc1) return;
   Prof pr(c, "intt_last", s);
+  if constexpr (LOGN <= 13) {
+    if (c->p_cls != CLS_N32) {  // 64-bit LDS words: 8 entries per thread, twice the waves
+      HE_FOR_CLASSES(1u << c->p_cls, (k_intt_p8<LOGN, CLS><<<xcd_grid(2, count), p8_threads<LOGN>(), 0, s>>>(
+                                         jobs, count, u, lmax, pg, c->big_l, rc, c->mods, c->tb())));
+      return;
+    }
+  }
   HE_FOR_CLASSES(1u << c->p_cls, (k_intt_last<LOGN, MODE_P, CLS><<<xcd_grid(2, count), T, 0, s>>>(
                                      jobs, count, u, lmax, pg, c->big_l, rc, c->mods, c->tb())));
 }
