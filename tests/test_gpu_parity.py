@@ -620,3 +620,63 @@ def test_combine_cp_dp_bit_exact():
     assert gctx.last_counts()["rot"] == cnt.rot == 4
     dense = cl.decrypt(got.data[0], p.scale, 80)
     assert np.abs(dense - vals).max() < 1e-4
+
+
+def test_empty_and_out_of_range_inputs_are_refused():
+    """Empty batches and levels outside 1..L are refused with an error code
+    before any launch (the output buffers keep their contents)."""
+    import ctypes
+    p, octx, gctx, cl = _small_setup(rotations=(1,))
+    he = _he()
+    lib = gctx.lib
+    L = len(p.q_bits)
+    buf = torch.full((2, L, p.n), 7, dtype=torch.int64, device="cuda")
+    out = torch.full_like(buf, 9)
+    ptr = he._ptr
+    # count 0
+    assert lib.he_rotate(gctx.h, ptr(out), ptr(buf), 0, L, 1, None) == -1
+    assert lib.he_square(gctx.h, ptr(out), ptr(buf), 0, L, None) == -1
+    assert lib.he_rotsum(gctx.h, ptr(buf), 0, L, 1, None) == -1
+    steps = (ctypes.c_int32 * 1)(1)
+    assert lib.he_rotate_hoisted(gctx.h, ptr(buf), L, steps, 0, ptr(out), None) == -1
+    # levels outside 1..L
+    assert lib.he_rotate(gctx.h, ptr(out), ptr(buf), 1, L + 1, 1, None) == -1
+    assert lib.he_rotate(gctx.h, ptr(out), ptr(buf), 1, 0, 1, None) == -1
+    assert lib.he_rescale(gctx.h, ptr(out), ptr(buf), 1, 1, None) in (-1, -2)
+    torch.cuda.synchronize()
+    assert bool((buf == 7).all()) and bool((out == 9).all())
+    # the context still works afterwards
+    ct = _enc_batch(octx, p, 1)
+    got = _host(gctx.rotate(he.Ct(_dev(ct), p.scale), 1).data)
+    assert np.array_equal(got, S.rotate(p, octx, S.Ciphertext(ct, p.scale), 1).c)
+
+
+@pytest.mark.parametrize("parts", [2, 3])
+def test_densepack_chunked_workspace_same_bits(parts):
+    """A workspace that holds only part of a layer's outputs makes the layer
+    run in chunks (the last one ragged, each split over `parts` chains where
+    it is large enough); the bits equal the one-chunk run and the oracle's."""
+    p, octx, gctx, cl = _small_setup(rotations=[1 << j for j in range(9)])
+    geom = C.ConvGeom(9, 9, 2, 3, 1, 1)
+    x = synth.image(W, (9, 9, 2), index=5)
+    w = synth.weights(W, 33, (3, 3, 2, 2), 0.3)
+    ct = Wk.encrypt_slots(octx, C.densepack_slots(x, geom, p.slots)[0], 3, p.scale, W, 11)
+    pts = C.densepack_pt_scale(p, 3, p.scale, p.scale)
+    bf = C.densepack_base_filters(p, w, geom, 3, pts)
+    he = _he()
+    desc = he.HEContext.conv_desc(9, 9, 2, 3, 1, 1, 2, 9)
+    gctx.set_tuning("split_parts", 0, parts)
+    whole = _host(gctx.conv_densepack(he.Ct(_dev(ct.c[None]), p.scale), desc, _dev(bf), pts).data)
+    # about 100 outputs' key-switch temporaries: chunks of ~100 and ~62 of the 162
+    per_output = ((3 * 3 + 2 + 2) * p.n + 2 * 3 * p.n + 2 * p.n + 128) * 8
+    small = torch.empty((100 * per_output + (1 << 20)) // 8, dtype=torch.int64, device="cuda")
+    gctx.set_workspace(small)
+    chunked = _host(gctx.conv_densepack(he.Ct(_dev(ct.c[None]), p.scale), desc, _dev(bf), pts).data)
+    gctx.set_workspace(None)
+    gctx.set_tuning("split_parts", 0, 2)
+    assert chunked.shape[0] == 162
+    assert np.array_equal(whole, chunked)
+    sample = [0, 99, 100, 161]
+    want, _ = C.conv_densepack(p, octx, ct, geom, bf, pts, outputs=[C.output_list(geom, 2)[i] for i in sample])
+    for k, i in enumerate(sample):
+        assert np.array_equal(chunked[i], want.c[k]), i
