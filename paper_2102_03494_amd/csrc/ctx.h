@@ -169,14 +169,6 @@ struct Arena {
       out[i].cap = (i == k - 1) ? cap : used + (size_t)(i + 1) * part;
     }
   }
-  // The remaining space split into two disjoint arenas of about half each.
-  void halves(Arena& lo, Arena& hi) const {
-    const size_t mid = used + ((left() / 2) & ~(size_t)255);
-    lo = *this;
-    lo.cap = mid;
-    hi = *this;
-    hi.used = mid;
-  }
 };
 
 inline u32 galois_of(int k, int n) {
