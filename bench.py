@@ -1099,6 +1099,8 @@ def serving_section(window: float, cap: float, mix_cap: float):
 def cpu_baseline(x, w1, n_outputs: int):
     """The oracle's DensePack dot products (HMA + 12 rotate-and-add + rescale)
     on a sample of W1 outputs of the same workload, single process."""
+    from threadpoolctl import threadpool_limits
+
     import synth  # noqa: F401
     from oracle import conv as C
     from oracle import params as P
@@ -1112,10 +1114,12 @@ def cpu_baseline(x, w1, n_outputs: int):
     bf = C.densepack_base_filters(p, w1, geom, p.max_level, pts)
     outs = C.output_list(geom, w1.shape[3])
     sample = [outs[i] for i in range(0, len(outs), max(1, len(outs) // n_outputs))][:n_outputs]
-    t0 = time.perf_counter()
-    _, cnt = C.conv_densepack(p, ctx, ct, geom, bf, pts, outputs=sample)
-    dt = time.perf_counter() - t0
+    with threadpool_limits(limits=1):  # BLAS/OpenMP pools held to one thread
+        t0 = time.perf_counter()
+        _, cnt = C.conv_densepack(p, ctx, ct, geom, bf, pts, outputs=sample)
+        dt = time.perf_counter() - t0
     return {"value": cnt.rot / dt, "unit": "rotations/s", "cores": 1, "kind": "oracle",
+            "cores_available": len(os.sched_getaffinity(0)),
             "sample": f"{len(sample)} of the {len(outs)} W1 DensePack dot products (HMA, 12 rotate-and-add, "
                       f"rescale) at N=8192, {dt:.1f} s single-threaded numpy"}
 
@@ -1202,6 +1206,18 @@ def main():
     torch.cuda.synchronize()
     hma_ms, _hma_busy, hma_launches = ctx.prof_read_busy()
     ctx.prof_select(None)
+    # spread of single layers: a HIP event pair on the library's stream (the
+    # side streams join it before a call returns) around each of 20 layers
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+    for a, b in ev:
+        a.record()
+        ffconv_step()
+        b.record()
+    torch.cuda.synchronize()
+    lay_ms = np.array([a.elapsed_time(b) for a, b in ev])
+    layer_spread = {"layers": len(lay_ms), "median_ms": float(np.median(lay_ms)),
+                    "p10_ms": float(np.percentile(lay_ms, 10)), "p90_ms": float(np.percentile(lay_ms, 90)),
+                    "note": "HIP events around each layer, after the timed steps"}
 
     # ---- plain comparator -------------------------------------------------------
     t_pl, zp, counts_pl = float("nan"), None, None
@@ -1367,6 +1383,7 @@ def main():
                                "N=8192, 4x30-bit + 40-bit P, scale 2^25",
                    "global_batch": 1, "parallelism": "none (1 GPU)"},
         "ffconv_layer_ms": t_ff * 1e3,
+        "ffconv_layer_spread": layer_spread,
         "plain_layer_ms": None if zp is None else t_pl * 1e3,
         "speedup_vs_plain": None if zp is None else t_pl / t_ff,
         "plain_rotations_per_s": None if zp is None else rot_pl / t_pl,
