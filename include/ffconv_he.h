@@ -627,7 +627,9 @@ int he_last_counts(const he_ctx *ctx, he_counts *out);
  * kernels of the three-class case), "intt_last", "drop_last",
  * "dp_hma", "hma_perm", "scalar_mac", "tensor_sq", "modup_store", "ip_perm",
  * "add") is bracketed by two HIP events recorded on the stream it is launched
- * on; NULL or "" stops recording.  he_prof_read waits for the recorded events and
+ * on (timing-only events without the system-scope fence, so they add no
+ * cache write-back between the kernels they bracket); NULL or "" stops
+ * recording.  he_prof_read waits for the recorded events and
  * returns the summed kernel time (ms) and the number of launches since the
  * last select or read, then clears them. */
 int he_prof_select(he_ctx *ctx, const char *kernel);

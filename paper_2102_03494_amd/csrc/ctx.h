@@ -120,8 +120,11 @@ inline hipEvent_t prof_event(he_ctx* c) {
     c->prof_pool.pop_back();
     return e;
   }
+  // timing only: these events order no data (their pairs are read after the
+  // stream has been synchronised), so they skip the system-scope fence and
+  // its cache write-back between the kernels they bracket
   hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
   return e;
 }
 
