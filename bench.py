@@ -203,6 +203,15 @@ def paper_counts_dp(spatial: int, o_c: int, r_steps: int) -> dict:
     return {"mulpc": o, "addcc": o * r_steps, "rot": o * r_steps}
 
 
+def chain_parts(n_out: int, split_streams: int, split_parts: int) -> int:
+    """Chains (one stream each) the library splits a DensePack rotate-and-sum
+    of n_out outputs into: split_parts when splitting is on and there are at
+    least 64 outputs, at most one chain per 32 outputs; else one."""
+    if not split_streams or n_out < 64:
+        return 1
+    return max(1, min(split_parts, n_out // 32))
+
+
 def timed(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -584,7 +593,7 @@ def cifar_section(torch, steps: int, plain: bool, digests_path: str):
     ops = r_steps * modup_ip_ops(n_dp, level, n, ctx.moduli, pg, ctx.get_tuning("modup_halves", level) == 1)
     roof = {"kernel": "k_ks_modup_half<14, f64, wide>: ModUp NTTs + key inner product into the six 40-bit primes "
                       "(f64 class) and P (wide), two half-ring workgroups per target, one launch per rotate-and-add "
-                      "step of the 8192 W1 outputs (two concurrent halves of the outputs when split_streams)",
+                      "step of the 8192 W1 outputs (split into concurrent chains when split_streams)",
             "bound": "alu", "achieved": ops * steps / (dom_busy_ms * 1e-3) / 1e12 if dom_busy_ms else None,
             "peak": VALU_PEAK_OPS / 1e12, "unit": "Tops/s (VALU lane ops)",
             "avg_launch_ms": dom_ms / max(1, dom_launches), "launches": dom_launches, "busy_ms": dom_busy_ms,
@@ -1253,9 +1262,10 @@ def main():
     level = len(Q_BITS)
     pg = ctx.get_tuning("p_groups", level)
     split = ctx.get_tuning("split_streams", 0)
+    parts = chain_parts(288, split, ctx.get_tuning("split_parts", 0))
     # the timed region holds, per layer, 12 rotate-and-add steps of the 288 W1
-    # outputs (as two launches of 144 on two streams when split) and the 5
-    # relinearisations of x^2 (level 2)
+    # outputs (one launch per chain and step) and the 5 relinearisations of
+    # x^2 (level 2)
     hv = ctx.get_tuning("modup_halves", level) == 1
     ops_layer = 12 * modup_ip_ops(288, level, N, ctx.moduli, pg, hv) + \
         modup_ip_ops(5, 2, N, ctx.moduli[:2] + ctx.moduli[-1:], ctx.get_tuning("p_groups", 2),
@@ -1265,7 +1275,7 @@ def main():
     packed = all(q < (1 << 30) for q in ctx.moduli[:level])
     bytes_layer = 12 * modup_ip_bytes(288, level, N, ctx.moduli, pg, packed_in=packed) + \
         modup_ip_bytes(5, 2, N, ctx.moduli[:2] + ctx.moduli[-1:], ctx.get_tuning("p_groups", 2))
-    launches_layer = 12 * (2 if split else 1) + 1
+    launches_layer = 12 * parts + 1
     avg_ms = dom_ms / max(1, dom_launches)
     layers = dom_launches / launches_layer
     ops_per_launch = ops_layer / launches_layer
@@ -1278,8 +1288,8 @@ def main():
                    "and P (f64), two half-ring workgroups per target" if hv else
                    "k_ks_modup_ip2<13, narrow, f64>: ModUp NTTs + key inner product into the four 30-bit primes and "
                    "P (f64), one workgroup per target") +
-                  ", one launch per rotate-and-add step of the 288 W1 outputs at level 4 (two concurrent launches "
-                  "of 144 when split_streams), plus one relinearisation launch per layer",
+                  ", one launch per rotate-and-add step of each chain of W1 outputs at level 4 (the 288 outputs "
+                  "split into concurrent chains on their own streams), plus one relinearisation launch per layer",
         "bound": "alu", "achieved": achieved_ops / 1e12, "peak": VALU_PEAK_OPS / 1e12,
         "unit": "Tops/s (VALU lane ops)", "frac": achieved_ops / VALU_PEAK_OPS,
         "traffic": measured_traffic("ks_modup_stage"),
@@ -1287,7 +1297,7 @@ def main():
         "concurrency": dom_ms / dom_busy_ms if dom_busy_ms > 0 else None,
         "algorithmic_ops_per_launch": ops_per_launch,
         "per_launch_achieved": per_launch_ops / 1e12,
-        "p_groups": pg, "split_streams": split,
+        "p_groups": pg, "split_streams": split, "split_parts": parts,
         "hbm_gbs_algorithmic": bytes_layer * layers / (dom_busy_ms * 1e-3) / 1e9,
     }
     rows, cols = geom.classes()

@@ -65,3 +65,13 @@ def test_dp_hma_bytes_count_rows():
     # a 40-bit limb is never packed
     wide = [(1 << 40) - 87] * 2 + MODULI[-1:]
     assert bench.dp_hma_bytes(1, 1, 1, 2, n, wide) == 3 * 2 * row64 + 2 * 2 * row64
+
+
+def test_chain_parts_follow_the_library_split():
+    # the library splits a rotate-and-sum of cn outputs into
+    # min(split_parts, cn / 32) chains when split_streams is on and cn >= 64
+    assert bench.chain_parts(288, 1, 2) == 2
+    assert bench.chain_parts(288, 1, 4) == 4
+    assert bench.chain_parts(288, 0, 4) == 1
+    assert bench.chain_parts(96, 1, 4) == 3
+    assert bench.chain_parts(63, 1, 4) == 1
