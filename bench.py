@@ -1139,6 +1139,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--plain-steps", type=int, default=4)
+    ap.add_argument("--spread-layers", type=int, default=20,
+                    help="layers timed one by one with HIP events after the timed steps (0: none)")
     ap.add_argument("--cpu-sample", type=int, default=12, help="oracle dot products timed (0 = skip)")
     ap.add_argument("--no-hoisted", action="store_true", help="skip the N=16384 hoisted-rotation section")
     ap.add_argument("--batched-layers", type=int, default=128,
@@ -1217,16 +1219,19 @@ def main():
     ctx.prof_select(None)
     # spread of single layers: a HIP event pair on the library's stream (the
     # side streams join it before a call returns) around each of 20 layers
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
-    for a, b in ev:
-        a.record()
-        ffconv_step()
-        b.record()
-    torch.cuda.synchronize()
-    lay_ms = np.array([a.elapsed_time(b) for a, b in ev])
-    layer_spread = {"layers": len(lay_ms), "median_ms": float(np.median(lay_ms)),
-                    "p10_ms": float(np.percentile(lay_ms, 10)), "p90_ms": float(np.percentile(lay_ms, 90)),
-                    "note": "HIP events around each layer, after the timed steps"}
+    layer_spread = None
+    if args.spread_layers > 0:
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.spread_layers)]
+        for a, b in ev:
+            a.record()
+            ffconv_step()
+            b.record()
+        torch.cuda.synchronize()
+        lay_ms = np.array([a.elapsed_time(b) for a, b in ev])
+        layer_spread = {"layers": len(lay_ms), "median_ms": float(np.median(lay_ms)),
+                        "p10_ms": float(np.percentile(lay_ms, 10)), "p90_ms": float(np.percentile(lay_ms, 90)),
+                        "note": "HIP events around each layer, after the timed steps"}
 
     # ---- plain comparator -------------------------------------------------------
     t_pl, zp, counts_pl = float("nan"), None, None
