@@ -139,12 +139,16 @@ __device__ __forceinline__ u64 shoupm(u64 a, u64 w, u64 wsh, u64 q) {
 // Coalesced limb load into LDS, optionally through the Galois permutation
 // sigma_g: afterwards lds[i] = src[galois_src(i, g)].  ginv = g^-1 mod 2N
 // (the scatter position of source entry idx is galois_src(idx, ginv)).
-template <int LOGN, int CLS, int E = 16>
+// IN_LOOP: the call sits in a loop whose trips share ginv; the permuted
+// indices are then formed at each call instead of being hoisted out of the
+// loop and held in registers (or spilled) across it.
+template <int LOGN, int CLS, int E = 16, bool IN_LOOP = false>
 __device__ __forceinline__ void load_limb_perm(u64* lds, const u64* __restrict__ src, u32 ginv, bool packed = false) {
   constexpr int T = NttGeom<LOGN, E>::T;
+  const int tid = IN_LOOP ? opaque_tid() : (int)threadIdx.x;
 #pragma unroll
   for (int r = 0; r < E; ++r) {
-    const int idx = (int)threadIdx.x + r * T;
+    const int idx = tid + r * T;
     const u64 v = ld_res(src, idx, packed);
     const int dst = (ginv == 1u) ? idx : galois_src<LOGN>(idx, ginv);
     lds_put<CLS>(lds, dst, v);
@@ -418,7 +422,7 @@ __device__ __forceinline__ void modup_ip_body(u64* lds, const u64* __restrict__ 
   for (int j = j0; j < j1; ++j) {
     if (j == t) {
       // the digit reduced mod its own prime is the (permuted) input limb itself
-      load_limb_perm<LOGN, CLS, E>(lds, jb.d + (size_t)j * N, jb.ginv, (jb.flags & JOB_IN_PACKED) != 0);
+      load_limb_perm<LOGN, CLS, E, true>(lds, jb.d + (size_t)j * N, jb.ginv, (jb.flags & JOB_IN_PACKED) != 0);
       __syncthreads();
     } else {
       lift_limb<LOGN, CLS, E>(lds, dcoef + (b * lmax + j) * N, mods.m[j].q, m, opaque_tid());
@@ -531,7 +535,7 @@ __device__ __forceinline__ void modup_ip_narrow_staged(u64* lds, u32* S, const u
     __builtin_amdgcn_sched_barrier(0);  // the copies are issued before the digit's loads
     if (j == t) {
       // the digit reduced mod its own prime is the (permuted) input limb itself
-      load_limb_perm<LOGN, CLS, E>(lds, jb.d + (size_t)j * N, jb.ginv, (jb.flags & JOB_IN_PACKED) != 0);
+      load_limb_perm<LOGN, CLS, E, true>(lds, jb.d + (size_t)j * N, jb.ginv, (jb.flags & JOB_IN_PACKED) != 0);
       lds_barrier();
     } else {
       lift_limb<LOGN, CLS, E>(lds, dcoef + (b * lmax + j) * N, mods.m[j].q, m, tid);
@@ -756,9 +760,10 @@ __device__ __forceinline__ void load_half_perm(u64* lds, const u64* __restrict__
   constexpr int NH = 1 << (LOGN - 1);
   constexpr int T = NH / E;
   const int sh = h ^ (int)((ginv >> 1) & 1u);  // source half
+  const int tid = opaque_tid();  // indices formed at each call, not held across the caller's digit loop
 #pragma unroll
   for (int r = 0; r < E; ++r) {
-    const int idx = sh * NH + (int)threadIdx.x + r * T;
+    const int idx = sh * NH + tid + r * T;
     const u64 v = ld_res(src, idx, packed);
     const int dst = ((ginv == 1u) ? idx : galois_src<LOGN>(idx, ginv)) - h * NH;
     lds_put<CLS>(lds, dst, v);
@@ -1691,13 +1696,14 @@ __device__ __forceinline__ void dp_hma_body(const u64* __restrict__ x, const u64
   const int n_cls = geo.n_row_cls * geo.n_col_cls;
   for (int mc = 0; mc < geo.m_cts; ++mc) {
     const u64* f = filt + ((((size_t)o * n_cls + cls) * geo.m_cts + mc) * level + t) * N;
-    load_limb_perm<LOGN, NARROW ? CLS_N32 : CLS_U64>(lds, f, ginv);
+    load_limb_perm<LOGN, NARROW ? CLS_N32 : CLS_U64, 16, true>(lds, f, ginv);
     __syncthreads();
     const u64* x0 = x + (((size_t)mc * 2 + 0) * level + t) * N;
     const u64* x1 = x + (((size_t)mc * 2 + 1) * level + t) * N;
+    const int tid = opaque_tid();
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int k = (int)threadIdx.x + r * T;
+      const int k = tid + r * T;
       const u64 fv = lds_get<NARROW ? CLS_N32 : CLS_U64>(lds, k, m);
       acc0[r] = (W)addm<NARROW>(acc0[r], mul_mod_t<NARROW>(x0[k], fv, m), m.q);
       acc1[r] = (W)addm<NARROW>(acc1[r], mul_mod_t<NARROW>(x1[k], fv, m), m.q);
